@@ -1,0 +1,157 @@
+"""Measurement operator Phi and its real adjoint (FP64, CPU).
+
+The paper discretises the interferometric measurement as y = Phi x + n with
+y in C^M, x in R^N (measurement-model paragraph); the image is real and
+non-negative (problem (1)), so the adjoint used by every solver step is the
+real-linear one, Phi^dagger v = Re(Phi^H v).
+
+Conventions (the paper fixes none):
+* x is n x n, indexed x[r, c]; pixel offsets are n1 = r - n/2, n2 = c - n/2.
+* u, v are in radians per pixel, in [-pi, pi); u pairs with rows, v with columns.
+* (Phi x)_m = sum_{r,c} x[r, c] exp(-i (u_m n1 + v_m n2))  (natural weighting, no w-term).
+
+Two realisations:
+* :class:`DFT` is that definition written out (exact, O(M N)).
+* :class:`NUFFT` is the operator the GPU computes: Phi = G F Z S with an
+  alpha-times oversampled grid of side K = alpha n, S dividing by the KB
+  transform, Z zero-padding with pixel offset n placed at grid index n mod K,
+  F the unnormalised forward DFT, and G the J x J Kaiser-Bessel interpolation at
+  kappa = u K / (2 pi) over taps j = floor(kappa) - J/2 + 1 + t, t = 0..J-1,
+  with grid indices taken mod K.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import kb
+
+
+def pixel_offsets(n: int) -> np.ndarray:
+    """Signed pixel offsets n1 = r - n/2 for r = 0..n-1."""
+    return np.arange(n, dtype=np.float64) - n // 2
+
+
+class DFT:
+    """Direct evaluation of the discretised measurement equation."""
+
+    def __init__(self, uv: np.ndarray, n: int):
+        self.uv = np.asarray(uv, dtype=np.float64)
+        self.n = n
+        self.M = len(self.uv)
+        off = pixel_offsets(n)
+        self.E1 = np.exp(-1j * np.outer(self.uv[:, 0], off))  # (M, n) row factor
+        self.E2 = np.exp(-1j * np.outer(self.uv[:, 1], off))  # (M, n) column factor
+
+    def fwd_complex(self, x: np.ndarray) -> np.ndarray:
+        """Phi x for a complex image x (n, n)."""
+        return np.sum((self.E1 @ x) * self.E2, axis=1)
+
+    def adj_complex(self, v: np.ndarray) -> np.ndarray:
+        """Phi^H v as a complex image (n, n)."""
+        return self.E1.conj().T @ (v[:, None] * self.E2.conj())
+
+    def fwd(self, x: np.ndarray) -> np.ndarray:
+        return self.fwd_complex(np.asarray(x, dtype=np.float64))
+
+    def adj(self, v: np.ndarray) -> np.ndarray:
+        """Real adjoint Re(Phi^H v)."""
+        return self.adj_complex(np.asarray(v, dtype=np.complex128)).real
+
+
+class NUFFT:
+    """FP64 non-uniform FFT with the KB kernel, as computed on the GPU."""
+
+    def __init__(self, uv: np.ndarray, n: int, J: int, alpha: int = 2, chunk: int = 1 << 20):
+        if J % 2:
+            raise ValueError("kernel width J must be even")
+        self.uv = np.asarray(uv, dtype=np.float64)
+        self.n, self.J, self.alpha = n, J, alpha
+        self.K = K = alpha * n
+        self.M = len(self.uv)
+        self.beta = kb.beta(J, alpha)
+        self.chunk = chunk
+        off = pixel_offsets(n)
+        ph = kb.psi_hat(off / K, J, self.beta)
+        self.deapod = 1.0 / np.outer(ph, ph)                 # S, (n, n)
+        self.grid_idx = np.mod(off.astype(np.int64), K)      # Z, pixel offset -> grid index
+
+    def _taps(self, lo: int, hi: int):
+        """Grid indices (mod K) and 1D KB weights for visibilities lo..hi-1, per axis."""
+        K, J = self.K, self.J
+        kappa = self.uv[lo:hi] * (K / (2.0 * np.pi))       # (m, 2)
+        base = np.floor(kappa)
+        t = np.arange(J, dtype=np.float64)
+        j = base[:, :, None] - J / 2 + 1 + t[None, None, :]  # (m, 2, J)
+        w = kb.psi(kappa[:, :, None] - j, J, self.beta)
+        return np.mod(j.astype(np.int64), K), w
+
+    def fwd(self, x: np.ndarray) -> np.ndarray:
+        K, n = self.K, self.n
+        grid = np.zeros((K, K), dtype=np.complex128)
+        grid[np.ix_(self.grid_idx, self.grid_idx)] = np.asarray(x, dtype=np.float64) * self.deapod
+        X = np.fft.fft2(grid)                                # F, unnormalised, exp(-2 pi i k n / K)
+        out = np.zeros(self.M, dtype=np.complex128)
+        for lo in range(0, self.M, self.chunk):
+            hi = min(self.M, lo + self.chunk)
+            j, w = self._taps(lo, hi)
+            acc = np.zeros(hi - lo, dtype=np.complex128)
+            for t1 in range(self.J):
+                for t2 in range(self.J):
+                    acc += w[:, 0, t1] * w[:, 1, t2] * X[j[:, 0, t1], j[:, 1, t2]]
+            out[lo:hi] = acc
+        return out
+
+    def adj(self, v: np.ndarray) -> np.ndarray:
+        """Real adjoint Re(S Z^T F^H G^H v)."""
+        K = self.K
+        v = np.asarray(v, dtype=np.complex128)
+        gre = np.zeros(K * K)
+        gim = np.zeros(K * K)
+        for lo in range(0, self.M, self.chunk):
+            hi = min(self.M, lo + self.chunk)
+            j, w = self._taps(lo, hi)
+            vv = v[lo:hi]
+            for t1 in range(self.J):
+                for t2 in range(self.J):
+                    idx = j[:, 0, t1] * K + j[:, 1, t2]
+                    ww = w[:, 0, t1] * w[:, 1, t2]
+                    gre += np.bincount(idx, weights=ww * vv.real, minlength=K * K)
+                    gim += np.bincount(idx, weights=ww * vv.imag, minlength=K * K)
+        G = (gre + 1j * gim).reshape(K, K)
+        Y = np.fft.ifft2(G) * (K * K)                        # F^H: exp(+2 pi i k n / K), unnormalised
+        crop = Y[np.ix_(self.grid_idx, self.grid_idx)]
+        return crop.real * self.deapod
+
+
+class Identity:
+    """Phi = I on R^N viewed in C^N (used to pin the solver against a closed form)."""
+
+    def __init__(self, n: int):
+        self.n = n
+        self.M = n * n
+
+    def fwd(self, x):
+        return np.asarray(x, dtype=np.float64).ravel().astype(np.complex128)
+
+    def adj(self, v):
+        return np.asarray(v).real.reshape(self.n, self.n).astype(np.float64)
+
+
+def op_norm(op, x0: np.ndarray, max_iter: int = 200, tol: float = 1e-12) -> float:
+    """||Phi||_2 of the real-linear map R^N -> C^N: power iteration on Re(Phi^H Phi).
+
+    Starts from x0 (a seeded Gaussian image), stops after max_iter steps or when
+    the eigenvalue estimate changes by at most tol relative.
+    """
+    x = np.asarray(x0, dtype=np.float64)
+    x = x / np.linalg.norm(x)
+    lam = 0.0
+    for _ in range(max_iter):
+        y = op.adj(op.fwd(x))
+        lam_new = float(np.vdot(x, y).real)
+        x = y / np.linalg.norm(y)
+        if lam > 0 and abs(lam_new - lam) <= tol * lam_new:
+            lam = lam_new
+            break
+        lam = lam_new
+    return float(np.sqrt(lam))

@@ -1,0 +1,220 @@
+"""Pins for the oracle's SDMM / SARA solver.
+
+* CG against a dense solve.
+* Closed form: Psi = I, Phi = I, W = I, R = 1 gives x = max(y - lambda, 0) with
+  ||y - x|| = eps (bisection on lambda).
+* Trivial case eps >= ||y||: x = 0, even from a warm start.
+* Brute force: a tiny problem (3) solved as a smooth constrained program by
+  scipy's trust-constr; SDMM must reach the same objective and be feasible.
+* KKT residuals of SDMM's own state vanish at convergence.
+* Reweighting invariants.
+"""
+import numpy as np
+import pytest
+import scipy.optimize
+import scipy.sparse
+
+from oracle import measurement, problem, sdmm, wavelets
+from paper_1502_05037_amd import synth
+
+
+def test_cg_matches_dense_solve():
+    g = synth.rng(96, 0, 0)
+    B = g.normal(size=(40, 40))
+    A = 2 * np.eye(40) + B @ B.T / 40
+    b = g.normal(size=40)
+    x = sdmm.cg(lambda v: A @ v, b, np.zeros(40))
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-10)
+    # fixed steps: n steps of CG are exact for an n x n SPD matrix (up to rounding)
+    A3 = np.diag([2.0, 2.5, 3.0])
+    x3 = sdmm.cg(lambda v: A3 @ v, np.ones(3), np.zeros(3), iters=3)
+    np.testing.assert_allclose(x3, 1 / np.diag(A3), rtol=1e-12)
+
+
+def _closed_form_identity(y, eps):
+    """min ||x||_1 s.t. ||y - x|| <= eps, x >= 0, y real: x = max(y - lam, 0)."""
+    lo, hi = 0.0, float(np.max(np.abs(y)))
+    for _ in range(200):
+        lam = 0.5 * (lo + hi)
+        r = np.linalg.norm(y - np.maximum(y - lam, 0))
+        lo, hi = (lam, hi) if r < eps else (lo, lam)
+    return np.maximum(y - 0.5 * (lo + hi), 0)
+
+
+def test_identity_special_case_closed_form():
+    n = 8
+    g = synth.rng(96, 1, 0)
+    y = synth.sky(n, 4, 2.0, synth.rng(96, 1, synth.SKY)).ravel() + 0.05 * g.normal(size=n * n)
+    eps = 0.3 * np.linalg.norm(y)
+    op = measurement.Identity(n)
+    psi = wavelets.SARA(n, 3, mask=1)
+    p = sdmm.Params(gamma=0.05, nu=1.0, max_iter=4000, tol_rel=1e-12, eps_slack=1e-10)
+    x, _, infos, st = sdmm.sara(op, psi, y.astype(complex), [0, n * n], [eps], p)
+    expect = _closed_form_identity(y, eps).reshape(n, n)
+    np.testing.assert_allclose(x, expect, atol=1e-7 * np.abs(expect).max())
+    assert infos[0].block_resid[0] <= eps * (1 + 1e-8)
+
+
+def test_trivial_case_zero_solution():
+    n, m = 8, 64
+    uv = synth.uv_gaussian(m, synth.rng(96, 2, synth.UV))
+    op = measurement.DFT(uv, n)
+    psi = wavelets.SARA(n, 3)
+    x_true = synth.sky(n, 4, 2.0, synth.rng(96, 2, synth.SKY))
+    y = op.fwd(x_true)
+    eps = 1.01 * np.linalg.norm(y)
+    nu = measurement.op_norm(op, np.ones((n, n)))
+    p = sdmm.Params(gamma=1e-2, nu=nu, max_iter=3000, tol_rel=0.0)
+    x, *_ = sdmm.sara(op, psi, y, [0, m], [eps], p, x0=x_true)
+    assert np.linalg.norm(x) <= 1e-6 * np.linalg.norm(x_true)
+
+
+def _tiny_problem(R=2, n=8, m=128, seed=3):
+    uv = synth.sort_by_radius(synth.uv_gaussian(m, synth.rng(96, seed, synth.UV)))
+    op = measurement.DFT(uv, n)
+    psi = wavelets.SARA(n, 3)
+    x_true = synth.sky(n, 4, 2.0, synth.rng(96, seed, synth.SKY))
+    clean = op.fwd(x_true)
+    sigma = problem.noise_sigma(clean, 30.0)
+    y = problem.add_noise(clean, sigma, synth.complex_normal(m, synth.rng(96, seed, synth.NOISE)))
+    sizes = synth.block_sizes(m, R, synth.rng(96, seed, synth.BLOCKS))
+    off = synth.offsets(sizes)
+    eps = problem.eps_blocks(sigma, sizes)
+    return op, psi, y, off, eps
+
+
+def _brute_force(op, psi, y, off, eps, W):
+    """Solve (3) as a smooth program in (x, t): min sum t, -t <= W Psi^dagger x <= t, x >= 0, balls."""
+    n = psi.n
+    N, D = n * n, psi.D
+    P = np.stack([psi.adj(e.reshape(n, n)).ravel() for e in np.eye(N)], axis=1)   # Psi^dagger, D x N
+    F = np.stack([op.fwd(e.reshape(n, n)) for e in np.eye(N)], axis=1)           # Phi, M x N
+    WP = W.ravel()[:, None] * P
+    I_D = np.eye(D)
+    A = np.block([[WP, -I_D], [-WP, -I_D]])
+    lin = scipy.optimize.LinearConstraint(A, -np.inf, 0.0)
+    cons = [lin]
+    for i in range(len(eps)):
+        Fi, yi = F[off[i]:off[i + 1]], y[off[i]:off[i + 1]]
+
+        def fun(z, Fi=Fi, yi=yi):
+            r = yi - Fi @ z[:N]
+            return np.array([np.vdot(r, r).real])
+
+        def jac(z, Fi=Fi, yi=yi):
+            r = yi - Fi @ z[:N]
+            gx = -2 * (Fi.conj().T @ r).real
+            return np.concatenate([gx, np.zeros(D)])[None, :]
+
+        def hess(z, lam, Fi=Fi):
+            H = np.zeros((N + D, N + D))
+            H[:N, :N] = 2 * lam[0] * (Fi.conj().T @ Fi).real
+            return H
+
+        cons.append(scipy.optimize.NonlinearConstraint(fun, -np.inf, eps[i] ** 2, jac=jac, hess=hess))
+    bounds = scipy.optimize.Bounds(np.concatenate([np.zeros(N), np.full(D, -np.inf)]), np.inf)
+    c = np.concatenate([np.zeros(N), np.ones(D)])
+    z0 = np.concatenate([np.full(N, 0.1), np.abs(WP @ np.full(N, 0.1)) + 1.0])
+    res = scipy.optimize.minimize(lambda z: c @ z, z0, jac=lambda z: c, hess=lambda z: np.zeros((N + D, N + D)),
+                                  method="trust-constr", constraints=cons, bounds=bounds,
+                                  options={"maxiter": 20000, "gtol": 1e-10, "xtol": 1e-12})
+    x = res.x[:N].reshape(n, n)
+    return x, float(np.sum(np.abs(WP @ res.x[:N])))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("R", [1, 2])
+def test_sdmm_matches_brute_force(R):
+    op, psi, y, off, eps = _tiny_problem(R=R)
+    nu = measurement.op_norm(op, np.ones((psi.n, psi.n)), max_iter=5000, tol=0.0)
+    gamma = sdmm.default_gamma(op, psi, y, nu)
+    W = np.ones((9, psi.n, psi.n))
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=20000, tol_rel=1e-11, eps_slack=1e-9)
+    x, _, infos, st = sdmm.sara(op, psi, y, off, eps, p)
+    x_bf, obj_bf = _brute_force(op, psi, y, off, eps, W)
+    obj = np.sum(np.abs(psi.adj(x)))
+    assert obj == pytest.approx(obj_bf, rel=2e-5)
+    assert np.all(infos[0].block_resid <= eps * (1 + 1e-6))
+    assert np.min(x) >= -1e-6 * np.max(x)
+    # the minimiser is unique here in practice: compare images loosely as well
+    assert np.linalg.norm(x - x_bf) / np.linalg.norm(x_bf) <= 1e-3
+
+
+def test_kkt_residuals_vanish_at_convergence():
+    op, psi, y, off, eps = _tiny_problem(R=2, seed=4)
+    nu = measurement.op_norm(op, np.ones((psi.n, psi.n)), max_iter=5000, tol=0.0)
+    gamma = sdmm.default_gamma(op, psi, y, nu)
+    pb = sdmm.Problem(op, psi, y, off, eps, nu)
+    st = sdmm.init_state(pb)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=3000, tol_rel=0.0)
+    st, _ = sdmm.sdmm_pass(pb, None, p, st)
+    prim1, dual1 = sdmm.kkt(pb, st, None, gamma)
+    st, _ = sdmm.sdmm_pass(pb, None, p, st)
+    prim2, dual2 = sdmm.kkt(pb, st, None, gamma)
+    # SDMM converges linearly here: both residuals keep shrinking, and are small after 6000 steps
+    assert prim2 <= 1e-9 and dual2 <= 1e-6
+    assert prim2 <= prim1 / 10 and dual2 <= dual1 / 10
+    # early in the run the residuals are far from zero
+    st0, _ = sdmm.sdmm_pass(pb, None, sdmm.Params(gamma=gamma, nu=nu, max_iter=5), sdmm.init_state(pb))
+    assert max(sdmm.kkt(pb, st0, None, gamma)) > 1e-4
+
+
+def test_fixed_cg_close_to_exact_cg():
+    op, psi, y, off, eps = _tiny_problem(R=2, seed=5)
+    nu = measurement.op_norm(op, np.ones((psi.n, psi.n)))
+    gamma = sdmm.default_gamma(op, psi, y, nu)
+    pa = sdmm.Params(gamma=gamma, nu=nu, max_iter=50, cg_iters=8)
+    pb = sdmm.Params(gamma=gamma, nu=nu, max_iter=50)
+    xa, *_ = sdmm.sara(op, psi, y, off, eps, pa)
+    xb, *_ = sdmm.sara(op, psi, y, off, eps, pb)
+    assert np.linalg.norm(xa - xb) / np.linalg.norm(xb) <= 1e-6
+
+
+def test_reweight_invariants():
+    c = np.array([0.0, 1e-3, -2.0, 5.0])
+    w = sdmm.reweight(c, 0.5)
+    assert w[0] == 1.0
+    assert np.all((w > 0) & (w <= 1))
+    assert w[3] < w[2] < w[1] < w[0]
+
+
+def test_sara_passes_reweight_and_warm_start():
+    op, psi, y, off, eps = _tiny_problem(R=2, seed=6)
+    nu = measurement.op_norm(op, np.ones((psi.n, psi.n)))
+    gamma = sdmm.default_gamma(op, psi, y, nu)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=40, passes=3)
+    x, W, infos, st = sdmm.sara(op, psi, y, off, eps, p)
+    assert len(infos) == 3
+    # the last weights follow delta_3 = beta^1 * delta_2 with delta_2 = std after pass 1 ... check shape/range
+    assert W.shape == (9, psi.n, psi.n) and np.all((W > 0) & (W <= 1))
+    # running passes one at a time with explicit weights reproduces the multi-pass result
+    pb = sdmm.Problem(op, psi, y, off, eps, nu)
+    st1 = sdmm.init_state(pb)
+    p1 = sdmm.Params(gamma=gamma, nu=nu, max_iter=40)
+    st1, _ = sdmm.sdmm_pass(pb, None, p1, st1)
+    c = psi.adj(st1.x)
+    d1 = np.std(c)
+    st1, _ = sdmm.sdmm_pass(pb, sdmm.reweight(c, d1), p1, st1)
+    c = psi.adj(st1.x)
+    st1, _ = sdmm.sdmm_pass(pb, sdmm.reweight(c, 0.5 * d1), p1, st1)
+    np.testing.assert_allclose(st1.x, x, rtol=0, atol=0)
+
+
+def test_chi2_noise_bound_coverage():
+    import scipy.stats
+    g = synth.rng(96, 7, synth.NOISE)
+    m, trials, sigma = 50, 10000, 0.3
+    eps = problem.eps_blocks(sigma, [m])[0]
+    draws = g.normal(size=(trials, 2 * m))
+    norms = sigma / np.sqrt(2) * np.linalg.norm(draws, axis=1)
+    cover = np.mean(norms <= eps)
+    expect = scipy.stats.chi2.cdf(2 * (eps / sigma) ** 2, 2 * m)
+    assert abs(cover - expect) <= 4 * np.sqrt(expect * (1 - expect) / trials)
+    assert 0.96 < expect < 0.98
+
+
+def test_dirty_image_psf_peak_is_m_for_dft():
+    n, m = 8, 50
+    op = measurement.DFT(synth.uv_gaussian(m, synth.rng(96, 8, synth.UV)), n)
+    v = synth.complex_normal(m, synth.rng(96, 8, synth.NOISE))
+    np.testing.assert_allclose(problem.dirty_image(op, v), op.adj(v) / m, rtol=1e-12)
