@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the SARA/SDMM hot path on one MI355X.
+
+Workload: 1024 x 1024 synthetic sky (Gaussian blobs + 200 point sources, dynamic range 1e4),
+M = 2e7 visibilities on a radial-density uv coverage split into R = 64 uneven contiguous blocks,
+Kaiser-Bessel width J = 8 on a 2x oversampled grid, 30 dB input SNR.
+
+A timed step is one SDMM iteration of the blocked problem (3): (cg_iters + 1) Phi + Phi^dagger
+pairs, Psi and Psi^dagger, the three fused prox/dual updates with float64 block norms and the
+stopping-test reductions.  `value` is the Phi + Phi^dagger visibility rate inside those steps,
+(cg_iters + 1) * M per step.  The JSON line also carries the bare pair rate, the roofline of the
+dominant interpolation kernel (HIP events on the library's stream), SDMM time-to-tolerance and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu] [--no-tol]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Φ+Φ† visibilities/s and SDMM time-to-tol at 1024², plain vs warm-start, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup_workload(n=1024, m=20_000_000, R=64, J=8, n_points=200, dr=4.0, snr=30.0, cfg=3):
+    from paper_1502_05037_amd import synth
+    t0 = time.time()
+    uv = synth.sort_by_radius(synth.uv_radial(m, synth.rng(cfg, 0, synth.UV)))
+    sizes = synth.block_sizes(m, R, synth.rng(cfg, 0, synth.BLOCKS))
+    off = synth.offsets(sizes)
+    x_true = synth.sky(n, n_points, dr, synth.rng(cfg, 0, synth.SKY)).astype(np.float32)
+    draws = synth.complex_normal(m, synth.rng(cfg, 0, synth.NOISE)).astype(np.complex64)
+    log(f"[bench] inputs generated in {time.time() - t0:.1f}s (n={n}, M={m}, R={R}, J={J})")
+    return dict(n=n, m=m, R=R, J=J, snr=snr, uv=uv, sizes=sizes, off=off, x_true=x_true, draws=draws)
+
+
+def cpu_baseline(wl, sample=1_000_000):
+    """FP64 oracle Phi + Phi^dagger on every (M/sample)-th visibility of the workload."""
+    from oracle import measurement
+    stride = max(1, wl["m"] // sample)
+    uv = wl["uv"][::stride][:sample]
+    op = measurement.NUFFT(uv, wl["n"], wl["J"])
+    x = wl["x_true"].astype(np.float64)
+    v = wl["draws"][::stride][:sample].astype(np.complex128)
+    t0 = time.perf_counter()
+    op.fwd(x)
+    op.adj(v)
+    dt = time.perf_counter() - t0
+    return {"value": len(uv) / dt, "unit": "vis/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 Phi+Phi^dagger pair (numpy, single thread) on {len(uv)} of the {wl['m']} "
+                      f"visibilities (every {stride}th), n={wl['n']}, J={wl['J']}: {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tol", action="store_true")
+    ap.add_argument("--m", type=int, default=20_000_000)
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the blocked problem shards by data block; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1502_05037_amd import sarahip as sh
+
+    dev = torch.device("cuda:0")
+    wl = setup_workload(m=a.m)
+    n, m, R, J = wl["n"], wl["m"], wl["R"], wl["J"]
+    t0 = time.time()
+    op = sh.op_create(wl["uv"], n, 2, J, wl["off"])
+    plan_s = time.time() - t0
+    q = sh.op_query(op)
+    psi = sh.psi_create(n, 4)
+    log(f"[bench] plan built in {plan_s:.1f}s: {q}")
+
+    # data: y = Phi x_true + noise at 30 dB, eps_i from the chi^2 bound (mean + 2 s.d.)
+    x_true = torch.tensor(wl["x_true"], device=dev)
+    clean = torch.empty(m, dtype=torch.complex64, device=dev)
+    sh.phi_fwd(op, x_true, clean)
+    sigma = float(torch.linalg.vector_norm(clean.to(torch.complex128))) / np.sqrt(m) * 10 ** (-wl["snr"] / 20)
+    y = clean + (sigma / np.sqrt(2)) * torch.tensor(wl["draws"], device=dev)
+    sizes = wl["sizes"].astype(np.float64)
+    eps = sigma * np.sqrt(sizes + 2 * np.sqrt(sizes))
+    nu = sh.op_norm(op, torch.ones((n, n), device=dev), iters=100, tol=1e-6)
+    log(f"[bench] sigma={sigma:.4g} nu={nu:.6g}")
+
+    # ---- timed SDMM iterations
+    prm = sh.sdmm_default_params()
+    prm.nu = nu
+    prm.cg_iters = 8
+    sess = sh.sdmm_create(op, psi, y, eps, None, None, prm)
+    try:
+        sh.sdmm_iterate(sess, a.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sh.sdmm_iterate(sess, a.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        resid, rel = sh.sdmm_result(sess, None, R)
+    finally:
+        sh.sdmm_destroy(sess)
+    ms_step = 1e3 * dt / a.steps
+    pairs = prm.cg_iters + 1
+    value = pairs * m / (dt / a.steps)
+    log(f"[bench] SDMM iteration {ms_step:.3f} ms -> {value:.4g} vis/s (rel change {rel:.3g})")
+
+    # ---- bare Phi + Phi^dagger pairs (internal order) and per-kernel event timing
+    xin = torch.rand((n, n), device=dev)
+    vis = torch.empty(m, dtype=torch.complex64, device=dev)
+    xo = torch.empty((n, n), device=dev)
+    for _ in range(2):
+        sh.phi_fwd_internal(op, xin, vis)
+        sh.phi_adj_internal(op, vis, xo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        sh.phi_fwd_internal(op, xin, vis)
+        sh.phi_adj_internal(op, vis, xo)
+    torch.cuda.synchronize()
+    pair_s = (time.perf_counter() - t0) / a.steps
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        sh.phi_fwd(op, xin, vis)
+        sh.phi_adj(op, vis, xo)
+    torch.cuda.synchronize()
+    pair_user_s = (time.perf_counter() - t0) / a.steps
+    sh.profile_enable(True)
+    for _ in range(a.steps):
+        sh.phi_fwd_internal(op, xin, vis)
+        sh.phi_adj_internal(op, vis, xo)
+    torch.cuda.synchronize()
+    kern = {}
+    for name in ("degrid", "grid", "fold", "fft_rows", "fft_cols"):
+        cnt, ms = sh.profile_read(name)
+        kern[name] = {"launches": cnt, "avg_ms": ms / max(cnt, 1)}
+    sh.profile_enable(False)
+    K = q["K"]
+    # algorithmic bytes per launch: packed uv (8 B) + one complex64 visibility (8 B) per visibility,
+    # plus one pass over the complex64 K x K grid
+    alg_bytes = 16 * m + 8 * K * K
+    dom = max(("degrid", "grid"), key=lambda k: kern[k]["avg_ms"])
+    achieved = alg_bytes / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+    roof = {"kernel": dom + ("_kernel" if dom == "degrid" else "_kernel (+fold)"), "bound": "hbm",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(kern[dom]["avg_ms"], 4)}
+    if dom == "grid":
+        roof["avg_launch_ms_with_fold"] = round(kern["grid"]["avg_ms"] + kern["fold"]["avg_ms"], 4)
+
+    # ---- SDMM time to tolerance (plain start), 5 passes of at most 300 iterations
+    tol = None
+    if not a.no_tol:
+        p2 = sh.sdmm_default_params()
+        p2.nu, p2.tol_rel, p2.passes, p2.max_iter, p2.check_every = nu, 1e-4, 5, 300, 10
+        x = torch.empty((n, n), device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info, res = sh.sdmm_solve(op, psi, y, eps, None, None, p2, x)
+        torch.cuda.synchronize()
+        tol = {"plain_seconds": round(time.perf_counter() - t0, 3), "plain_iters": info["iters_total"],
+               "passes": info["passes_done"], "converged_last_pass": info["converged"],
+               "max_resid_over_eps": float(np.max(res / eps)), "tol_rel": 1e-4,
+               "warm_seconds": None, "warm_iters": None}
+        log(f"[bench] time-to-tol {tol}")
+
+    cpu = None if a.no_cpu else cpu_baseline(wl)
+    sh.psi_destroy(psi)
+    sh.op_destroy(op)
+    out = {
+        "metric": METRIC, "value": value, "unit": "vis/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "SARA/SDMM one SDMM iteration, 1024x1024 sky, M=2e7 radial uv, R=64 uneven "
+                               "blocks, KB J=8, alpha=2, 8 CG steps", "n": n, "M": m, "R": R, "J": J,
+                   "cg_iters": prm.cg_iters, "global_batch": 1},
+        "pair": {"internal_vis_per_s": m / pair_s, "user_order_vis_per_s": m / pair_user_s,
+                 "internal_ms": 1e3 * pair_s, "user_ms": 1e3 * pair_user_s},
+        "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
+        "roofline": roof, "cpu_baseline": cpu, "sdmm_time_to_tol": tol, "plan_seconds": round(plan_s, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * sarahip.h -- C ABI of the MI355X (gfx950) SARA/SDMM library.
+ *
+ * Carrillo, McEwen & Wiaux, "Why CLEAN when you can PURIFY?" (arXiv:1502.05037)
+ * images the sky x >= 0 from visibilities y = Phi x + n by solving the
+ * weighted-l1 problem (1), split into R data blocks as in (2) and solved in the
+ * blocked form (3) by SDMM; SARA repeats (1)/(3) with re-computed weights.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Image x: n x n float32, row-major x[r*n + c]; pixel offsets r - n/2, c - n/2.
+ *  - Visibilities: M complex64, interleaved (re, im) float32 pairs.  "User order"
+ *    is the order of the uv array given to sh_op_create; data blocks are the
+ *    contiguous ranges [block_offsets[i], block_offsets[i+1]) of that order.
+ *  - (Phi x)_m = sum_{r,c} x[r,c] exp(-i (u_m (r - n/2) + v_m (c - n/2))),
+ *    computed by an alpha-times oversampled NUFFT with a J x J Kaiser-Bessel
+ *    interpolation kernel; Phi^dagger is the real adjoint Re(Phi^H v).
+ *  - Coefficients: q planes of n x n float32 (plane 0 Dirac, then db1..db8 in
+ *    bit order of the basis mask), each a 2D periodic DWT in Mallat layout.
+ *  - Device pointers are HIP device memory owned by the caller (e.g. torch
+ *    tensors); host pointers are ordinary host memory owned by the caller.  The
+ *    library never frees or retains caller memory past a call.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Calls marked async only
+ *    enqueue work; all others synchronise on `stream` before returning.
+ *  - Errors: every call returns an sh_status.  Arguments are validated on the
+ *    host before any launch; an invalid argument returns SH_EINVAL and enqueues
+ *    nothing.  sh_last_error() gives a thread-local message for the last failure.
+ *    No exception or abort crosses this boundary.
+ */
+#ifndef SARAHIP_H
+#define SARAHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SH_OK = 0,
+  SH_EINVAL = -1,        /* invalid argument, nothing enqueued */
+  SH_ENOMEM = -2,        /* device or host allocation failed */
+  SH_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed */
+  SH_ENONFINITE = -4,    /* non-finite input or residual */
+  SH_EUNSUPPORTED = -5   /* valid but not supported by this build */
+} sh_status;
+
+typedef struct sh_op_s* sh_op;    /* measurement operator: packed uv, tile plan, tables, scratch */
+typedef struct sh_psi_s* sh_psi;  /* SARA dictionary: filter taps, level scratch */
+
+/* Message for the last non-OK status on this thread (never NULL). */
+const char* sh_last_error(void);
+
+/* Library version string. */
+const char* sh_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Measurement operator Phi (measurement equation y = Phi x + n; blocks (2)).
+ * ------------------------------------------------------------------------- */
+
+/* Plan Phi for M uv points (host, M x 2 row-major float64 (u, v) in radians
+ * per pixel, each in [-pi, pi)), image side n (power of two, 16..4096),
+ * oversampling alpha (2) and even kernel width J (2..16).  block_offsets (host,
+ * R+1 int64, 0 = b_0 < b_1 < ... < b_R = M) gives the data blocks of (2).
+ * The library converts uv to fixed-point grid coordinates in float64, sorts the
+ * visibilities by uv tile inside each block and builds the gridding work list.
+ * Synchronous.  Errors: SH_EINVAL (range, sizes, offsets), SH_ENOMEM. */
+sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
+                       const int64_t* block_offsets, int32_t R, sh_op* out);
+sh_status sh_op_destroy(sh_op op);
+
+/* Query plan sizes: out[0]=M, out[1]=n, out[2]=grid side K, out[3]=J, out[4]=R,
+ * out[5]=number of gridding work items, out[6]=tile side, out[7]=max items per tile. */
+sh_status sh_op_query(sh_op op, int64_t out[8]);
+
+/* Block offsets in internal order (host, R+1 int64).  Internal order permutes
+ * visibilities only inside each block, so these equal the user offsets. */
+sh_status sh_op_block_offsets(sh_op op, int64_t* offsets_out);
+
+/* Permutation: perm_out[i] = user index of internal visibility i (host, M int64). */
+sh_status sh_op_permutation(sh_op op, int64_t* perm_out);
+
+/* vis = Phi x in user order.  x: device n*n float32; vis: device M complex64.  Async. */
+sh_status sh_phi_fwd(sh_op op, const float* x, float* vis, void* stream);
+/* x = Re(Phi^H vis) from user-order visibilities.  Async. */
+sh_status sh_phi_adj(sh_op op, const float* vis, float* x, void* stream);
+/* The same two maps on internal-order visibilities (the order sdmm uses).  Async. */
+sh_status sh_phi_fwd_internal(sh_op op, const float* x, float* vis, void* stream);
+sh_status sh_phi_adj_internal(sh_op op, const float* vis, float* x, void* stream);
+/* Reorder visibilities between user and internal order (device M complex64 each, distinct).  Async. */
+sh_status sh_vis_to_internal(sh_op op, const float* user, float* internal, void* stream);
+sh_status sh_vis_to_user(sh_op op, const float* internal, float* user, void* stream);
+
+/* ||Phi||_2 of the real-linear map R^N -> C^M by power iteration on Re(Phi^H Phi)
+ * from the caller's start image x0 (device n*n float32, e.g. a seeded Gaussian),
+ * at most `iters` steps or until the eigenvalue estimate changes by <= tol
+ * relative.  Norms and Rayleigh quotients are reduced in float64.  Synchronous. */
+sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * SARA dictionary Psi = (1/sqrt q)[Psi_1 .. Psi_q] (SARA paragraph).
+ * ------------------------------------------------------------------------- */
+
+/* basis_mask: bit 0 = Dirac, bit b = Daubechies db_b (b = 1..8); SARA = 0x1FF.
+ * n must be divisible by 2^levels (levels 1..8).  Filters are computed on the
+ * host in float64 by spectral factorisation.  Synchronous. */
+sh_status sh_psi_create(int32_t n, int32_t levels, uint32_t basis_mask, sh_psi* out);
+sh_status sh_psi_destroy(sh_psi psi);
+/* Number of planes q (D = q*n*n coefficients). */
+sh_status sh_psi_planes(sh_psi psi, int32_t* q_out);
+/* The float64 scaling filter of db_p (2p taps) as used by the library (host). */
+sh_status sh_daubechies(int32_t p, double* h_out);
+/* x = Psi coeffs (synthesis).  coeffs: device q*n*n float32; x: device n*n.  Async. */
+sh_status sh_psi_fwd(sh_psi psi, const float* coeffs, float* x, void* stream);
+/* coeffs = Psi^dagger x (analysis).  Async. */
+sh_status sh_psi_adj(sh_psi psi, const float* x, float* coeffs, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Proximal steps of SDMM on (3), each fused with its dual update.  All async.
+ * ------------------------------------------------------------------------- */
+
+/* Weighted soft threshold + dual: t = s + z; y = sign(t) max(|t| - gamma w, 0);
+ * z <- t - y; v_out = y - z (the next x-update's input).  W may be NULL (w = 1).
+ * Length D float32 each (device). */
+sh_status sh_prox_l1(int64_t D, const float* s, float* z, const float* W, float gamma, float* v_out,
+                     void* stream);
+/* Positive orthant + dual: t = s + z; y = max(t, 0); z <- t - y; v_out = y - z.  Length N. */
+sh_status sh_prox_pos(int64_t N, const float* s, float* z, float* v_out, void* stream);
+/* Per-block l2-ball projection + dual on internal-order visibilities:
+ * t = s + z; rho_i = ||t_i - yhat_i||_2 (float64); y_i = yhat_i + (t_i - yhat_i) min(1, eps_i/rho_i);
+ * z <- t - y; v_out = y - z.  Also writes resid_out[i] = ||s_i - yhat_i||_2 (device float64, R).
+ * s, z, yhat, v_out: device M complex64; eps: device float64 R. */
+sh_status sh_prox_ball(sh_op op, const float* s, float* z, const float* yhat, const double* eps, float* v_out,
+                       double* resid_out, void* stream);
+
+/* SARA weights w = delta / (delta + |c|) (device D float32 in and out). */
+sh_status sh_reweight(int64_t D, const float* c, double delta, float* W_out, void* stream);
+/* Population standard deviation of c (float64 reduction).  Synchronous. */
+sh_status sh_std(int64_t D, const float* c, double* std_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * SDMM solve of (3) with SARA reweighting (PURIFY paragraph; SARA paragraph).
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+  double gamma;        /* l1 prox step; <= 0: 1e-3 * max|Psi^dagger Phi^dagger y| / nu^2 */
+  double nu;           /* operator norm used to normalise; <= 0: sh_op_norm from x0 = ones */
+  double tol_rel;      /* stop when ||x_n - x_{n-1}||/||x_n|| <= tol_rel and all blocks feasible;
+                          0 = run max_iter every pass (fixed schedule) */
+  double eps_slack;    /* feasibility test ||y_i - Phi_i x|| <= eps_i (1 + eps_slack) */
+  double rw_beta;      /* delta_{t+1} = rw_beta * delta_t */
+  double rw_delta0;    /* > 0: delta of the weights W passed in (warm start); else delta_1 = std */
+  int32_t max_iter;    /* SDMM iterations per pass */
+  int32_t cg_iters;    /* conjugate-gradient steps per x-update */
+  int32_t passes;      /* weighted-l1 solves, the first with W (or identity) */
+  int32_t check_every; /* host reads the stopping flags every this many iterations (>= 1) */
+} sh_sdmm_params;
+
+/* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
+ * max_iter 300, cg_iters 8, passes 1, check_every 10. */
+void sh_sdmm_default_params(sh_sdmm_params* p);
+
+typedef struct {
+  int32_t iters_total;   /* SDMM iterations over all passes */
+  int32_t passes_done;
+  int32_t converged;     /* last pass met the stopping test (not an error when 0) */
+  int32_t iters_last;    /* iterations of the last pass */
+  double rel_change;     /* ||x_n - x_{n-1}|| / ||x_n|| at exit */
+  double objective;      /* ||W Psi^dagger x||_1 with the last pass's weights */
+  double gamma;          /* step actually used */
+  double nu;             /* normalisation actually used */
+  double delta;          /* reweighting delta of W_out */
+  double seconds;        /* wall time inside the call */
+} sh_sdmm_info;
+
+/* Solve SARA/(3).  y: device M complex64, user order.  eps: host R float64 (user
+ * units).  W: device D float32 weights of the first pass or NULL (identity).
+ * x0: device n*n float32 warm start or NULL (zero start).  x_out: device n*n.
+ * W_out: device D float32 (the weights after the last reweighting, i.e. those a
+ * further pass would use) or NULL.  block_resid: host R float64 receiving
+ * ||y_i - Phi_i x|| at exit, or NULL.  Synchronous.
+ * Errors: SH_EINVAL, SH_ENONFINITE (non-finite y/eps or residual), SH_ENOMEM, SH_EDEVICE. */
+sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W,
+                        const float* x0, const sh_sdmm_params* params, float* x_out, float* W_out,
+                        double* block_resid, sh_sdmm_info* info, void* stream);
+
+/* Session form of the same solver, for callers that drive the iterations themselves
+ * (benchmarks, checkpointed runs).  sh_sdmm_create validates as sh_sdmm_solve, copies the data
+ * to device (internal order, normalised by nu), resolves nu and gamma, sets the zero or warm
+ * state and synchronises.  It keeps pointers to op and psi (which must outlive the session) but
+ * not to y, eps, W or x0. */
+typedef struct sh_sdmm_s* sh_sdmm;
+sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W,
+                         const float* x0, const sh_sdmm_params* params, sh_sdmm* out, void* stream);
+/* Enqueue exactly `iters` SDMM iterations of the current weighted-l1 pass (no stopping test, no
+ * reweighting, no host synchronisation).  Splitting a run into several calls gives the same
+ * iterates as one call.  Async. */
+sh_status sh_sdmm_iterate(sh_sdmm s, int32_t iters, void* stream);
+/* Current image (device n*n, may be NULL), block residuals ||y_i - Phi_i x|| (host R, may be
+ * NULL) and relative change of the last iteration.  Synchronous. */
+sh_status sh_sdmm_result(sh_sdmm s, float* x_out, double* block_resid, double* rel_change, void* stream);
+sh_status sh_sdmm_destroy(sh_sdmm s);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (HIP events around the gridding/degridding launches).
+ * ------------------------------------------------------------------------- */
+/* Enable (1) or disable (0) event timing; enabling clears the counters. */
+sh_status sh_profile_enable(int32_t on);
+/* Launch count and total milliseconds of kernel `name` ("degrid", "grid", "fold",
+ * "fft_rows", "fft_cols") recorded since enabling.  Synchronises the device. */
+sh_status sh_profile_read(const char* name, int64_t* count, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SARAHIP_H */

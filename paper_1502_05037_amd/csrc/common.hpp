@@ -1,0 +1,104 @@
+// Shared host-side helpers of the sarahip library: status handling, device buffers, launch checks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/sarahip.h"
+
+namespace sh {
+
+// Thread-local message for the last non-OK status.
+void set_error(const char* fmt, ...);
+const char* last_error();
+
+// Error propagation inside the library: functions return sh_status; SH_TRY returns early.
+#define SH_TRY(expr)                        \
+  do {                                      \
+    sh_status _s = (expr);                  \
+    if (_s != SH_OK) return _s;             \
+  } while (0)
+
+#define SH_HIP(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t _e = (expr);                                                                    \
+    if (_e != hipSuccess) {                                                                    \
+      ::sh::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, __LINE__); \
+      return _e == hipErrorOutOfMemory ? SH_ENOMEM : SH_EDEVICE;                               \
+    }                                                                                          \
+  } while (0)
+
+#define SH_LAUNCHED()                                                                            \
+  do {                                                                                           \
+    hipError_t _e = hipGetLastError();                                                           \
+    if (_e != hipSuccess) {                                                                      \
+      ::sh::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(_e), __FILE__, __LINE__); \
+      return SH_EDEVICE;                                                                         \
+    }                                                                                            \
+  } while (0)
+
+#define SH_REQUIRE(cond, ...)          \
+  do {                                 \
+    if (!(cond)) {                     \
+      ::sh::set_error(__VA_ARGS__);    \
+      return SH_EINVAL;                \
+    }                                  \
+  } while (0)
+
+// Owning device allocation (hipMalloc / hipFree).
+template <typename T>
+struct DevBuf {
+  T* ptr = nullptr;
+  size_t count = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    count = 0;
+  }
+  sh_status alloc(size_t n) {
+    release();
+    if (n == 0) return SH_OK;
+    SH_HIP(hipMalloc((void**)&ptr, n * sizeof(T)));
+    count = n;
+    return SH_OK;
+  }
+  sh_status upload(const T* host, size_t n) {
+    SH_TRY(alloc(n));
+    if (n) SH_HIP(hipMemcpy(ptr, host, n * sizeof(T), hipMemcpyHostToDevice));
+    return SH_OK;
+  }
+  sh_status upload(const std::vector<T>& v) { return upload(v.data(), v.size()); }
+};
+
+inline int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Kernel timing with HIP events on the launch stream (enabled by sh_profile_enable).
+struct ProfScope {
+  hipEvent_t a = nullptr, b = nullptr;
+  int slot = -1;
+  hipStream_t st = nullptr;
+  ProfScope(const char* name, hipStream_t stream);
+  ~ProfScope();
+};
+
+}  // namespace sh
+
+// Device-side complex helpers.
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }

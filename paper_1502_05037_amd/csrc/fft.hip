@@ -1,0 +1,252 @@
+// LDS Stockham FFT passes of the NUFFT measurement operator.
+//
+// Phi = G F Z S: the n x n image is deapodised (S), placed on the K x K grid at index offset mod K
+// (Z) and transformed by the unnormalised 2D DFT F, exp(-2 pi i k.n / K).  Only n of the K grid
+// rows and columns are non-zero on input, so the forward transform runs over the n image rows
+// (row pass, pruned input) and then over all K columns (column pass, pruned input).  The adjoint
+// F^H runs the column pass over all K columns keeping only the n needed rows, then the row pass
+// over those n rows keeping the n needed columns, fused with the crop, the deapodisation and Re().
+//
+// Each work-group transforms B sequences of length L in LDS with self-sorting (Stockham) radix-8
+// stages and one radix-4 or radix-2 stage; twiddles come from a float64-derived table.
+#include "op.hpp"
+
+namespace {
+
+enum Mode { ROWS_FWD = 0, COLS_FWD = 1, COLS_ADJ = 2, ROWS_ADJ = 3 };
+
+template <bool INV>
+__device__ __forceinline__ float2 rot_mi(float2 a) {  // multiply by -i (forward) or +i (inverse)
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 2) {
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const float2 t2 = cadd(v[1], v[3]), t3 = rot_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  } else {  // R == 8: two radix-4 halves combined with w^q, w = exp(-+ 2 pi i / 8)
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4, INV>(e);
+    dft<4, INV>(o);
+    const float h = 0.70710678118654752f;
+    const float2 o1 = INV ? make_float2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
+                          : make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+    const float2 o2 = rot_mi<INV>(o[2]);
+    const float2 o3 = INV ? make_float2(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
+                          : make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+}
+
+// One Stockham stage of radix R over a length-L sequence in LDS (all threads of the sequence).
+template <int L, int R, bool INV>
+__device__ __forceinline__ void stage(float2* buf, const float2* __restrict__ tw, int Ns, int lt, int tpt) {
+  constexpr int NB = L / R;                      // butterflies per sequence
+  constexpr int PER = (NB + L / 8 - 1) / (L / 8); // butterflies per thread (tpt = L/8)
+  float2 v[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = lt + q * tpt;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * NB];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = lt + q * tpt;
+    const int k = j % Ns;
+    const int step = L / (Ns * R);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      float2 w = tw[r * k * step];
+      if (INV) w.y = -w.y;
+      v[q][r] = cmul(v[q][r], w);
+    }
+    dft<R, INV>(v[q]);
+    const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q][r];
+  }
+  __syncthreads();
+}
+
+template <int L, bool INV>
+__device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw, int lt) {
+  constexpr int TPT = L / 8;
+  int Ns = 1;
+  constexpr int LOG = __builtin_ctz(L);
+  constexpr int N8 = LOG / 3;
+  constexpr int REM = LOG % 3;
+#pragma unroll
+  for (int s = 0; s < N8; ++s) {
+    stage<L, 8, INV>(buf, tw, Ns, lt, TPT);
+    Ns *= 8;
+  }
+  if constexpr (REM == 2) stage<L, 4, INV>(buf, tw, Ns, lt, TPT);
+  if constexpr (REM == 1) stage<L, 2, INV>(buf, tw, Ns, lt, TPT);
+}
+
+// B sequences of length L per work-group, L/8 threads each.
+template <int L, int B, int MODE>
+__global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ in, void* __restrict__ out,
+                                                      const float2* __restrict__ tw,
+                                                      const float* __restrict__ deapod, int n, float scale) {
+  extern __shared__ float2 lds[];
+  constexpr bool INV = (MODE == COLS_ADJ || MODE == ROWS_ADJ);
+  constexpr int NT = B * L / 8;
+  const int tid = threadIdx.x;
+  const int seq0 = blockIdx.x * B;    // first row (row modes) or column (column modes)
+  const int half = n / 2;
+  const int K = L;                    // grid side
+
+  // ---- load ----
+  if constexpr (MODE == ROWS_FWD) {
+    const float* x = (const float*)in;
+    for (int e = tid; e < B * L; e += NT) lds[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    for (int e = tid; e < B * n; e += NT) {
+      const int b = e / n, c = e - b * n;
+      const int r = seq0 + b;
+      const float val = x[(size_t)r * n + c] * deapod[r] * deapod[c];
+      lds[b * L + ((c - half) & (L - 1))] = make_float2(val, 0.f);
+    }
+  } else if constexpr (MODE == COLS_FWD) {
+    const float2* h = (const float2*)in;
+    for (int e = tid; e < B * L; e += NT) lds[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    for (int e = tid; e < B * n; e += NT) {
+      const int r = e / B, b = e - r * B;
+      lds[b * L + ((r - half) & (L - 1))] = h[(size_t)r * K + seq0 + b];
+    }
+  } else if constexpr (MODE == COLS_ADJ) {
+    const float2* g = (const float2*)in;
+    for (int e = tid; e < B * L; e += NT) {
+      const int r = e / B, b = e - r * B;
+      lds[b * L + r] = g[(size_t)r * K + seq0 + b];
+    }
+  } else {  // ROWS_ADJ
+    const float2* h = (const float2*)in;
+    for (int e = tid; e < B * L; e += NT) {
+      const int b = e / L, c = e - b * L;
+      lds[e] = h[(size_t)(seq0 + b) * K + c];
+    }
+  }
+  __syncthreads();
+
+  // ---- transform: thread tid works on sequence tid / (L/8) ----
+  const int sq = tid / (L / 8), lt = tid % (L / 8);
+  fft_lds<L, INV>(lds + sq * L, tw, lt);
+
+  // ---- store ----
+  if constexpr (MODE == ROWS_FWD) {
+    float2* h = (float2*)out;
+    for (int e = tid; e < B * L; e += NT) {
+      const int b = e / L, k = e - b * L;
+      h[(size_t)(seq0 + b) * K + k] = lds[e];
+    }
+  } else if constexpr (MODE == COLS_FWD) {
+    float2* g = (float2*)out;
+    for (int e = tid; e < B * L; e += NT) {
+      const int k = e / B, b = e - k * B;
+      g[(size_t)k * K + seq0 + b] = lds[b * L + k];
+    }
+  } else if constexpr (MODE == COLS_ADJ) {
+    float2* h = (float2*)out;
+    for (int e = tid; e < B * n; e += NT) {
+      const int r = e / B, b = e - r * B;
+      h[(size_t)r * K + seq0 + b] = lds[b * L + ((r - half) & (L - 1))];
+    }
+  } else {
+    float* x = (float*)out;
+    for (int e = tid; e < B * n; e += NT) {
+      const int b = e / n, c = e - b * n;
+      const int r = seq0 + b;
+      x[(size_t)r * n + c] = lds[b * L + ((c - half) & (L - 1))].x * deapod[r] * deapod[c] * scale;
+    }
+  }
+}
+
+template <int L, int MODE>
+sh_status launch_len(int count, const void* in, void* out, const float2* tw, const float* deapod, int n, float scale,
+                     hipStream_t st) {
+  constexpr int B = (8192 / L) < 1 ? 1 : (8192 / L);
+  int b = B > 64 ? 64 : B;
+  while (b > count) b >>= 1;  // few sequences (tiny images): shrink the batch
+  const size_t lds = size_t(b) * L * sizeof(float2);
+#define SH_FFT_CASE(BB)                                                                                  \
+  if (b == BB) {                                                                                         \
+    hipLaunchKernelGGL((fft_pass<L, BB, MODE>), dim3(count / BB), dim3(BB * L / 8), lds, st, in, out, tw, \
+                       deapod, n, scale);                                                                \
+    SH_LAUNCHED();                                                                                       \
+    return SH_OK;                                                                                        \
+  }
+  if constexpr (B >= 64) SH_FFT_CASE(64)
+  if constexpr (B >= 32) SH_FFT_CASE(32)
+  if constexpr (B >= 16) SH_FFT_CASE(16)
+  if constexpr (B >= 8) SH_FFT_CASE(8)
+  if constexpr (B >= 4) SH_FFT_CASE(4)
+  if constexpr (B >= 2) SH_FFT_CASE(2)
+  SH_FFT_CASE(1)
+#undef SH_FFT_CASE
+  sh::set_error("fft batch size");
+  return SH_EUNSUPPORTED;
+}
+
+template <int MODE>
+sh_status launch_mode(int L, int count, const void* in, void* out, const float2* tw, const float* deapod, int n,
+                      float scale, hipStream_t st) {
+  switch (L) {
+    case 32: return launch_len<32, MODE>(count, in, out, tw, deapod, n, scale, st);
+    case 64: return launch_len<64, MODE>(count, in, out, tw, deapod, n, scale, st);
+    case 128: return launch_len<128, MODE>(count, in, out, tw, deapod, n, scale, st);
+    case 256: return launch_len<256, MODE>(count, in, out, tw, deapod, n, scale, st);
+    case 512: return launch_len<512, MODE>(count, in, out, tw, deapod, n, scale, st);
+    case 1024: return launch_len<1024, MODE>(count, in, out, tw, deapod, n, scale, st);
+    case 2048: return launch_len<2048, MODE>(count, in, out, tw, deapod, n, scale, st);
+    case 4096: return launch_len<4096, MODE>(count, in, out, tw, deapod, n, scale, st);
+    case 8192: return launch_len<8192, MODE>(count, in, out, tw, deapod, n, scale, st);
+  }
+  sh::set_error("unsupported FFT length %d", L);
+  return SH_EUNSUPPORTED;
+}
+
+}  // namespace
+
+namespace sh {
+
+sh_status fft_forward_2d(sh_op op, const float* x, float2* grid, hipStream_t st) {
+  {
+    ProfScope ps("fft_rows", st);
+    SH_TRY(launch_mode<ROWS_FWD>(op->K, op->n, x, op->half.ptr, op->tw.ptr, op->deapod.ptr, op->n, 1.f, st));
+  }
+  ProfScope ps("fft_cols", st);
+  return launch_mode<COLS_FWD>(op->K, op->K, op->half.ptr, grid, op->tw.ptr, op->deapod.ptr, op->n, 1.f, st);
+}
+
+sh_status fft_adjoint_2d(sh_op op, const float2* grid, float* x, float scale, hipStream_t st) {
+  {
+    ProfScope ps("fft_cols", st);
+    SH_TRY(launch_mode<COLS_ADJ>(op->K, op->K, grid, op->half.ptr, op->tw.ptr, op->deapod.ptr, op->n, 1.f, st));
+  }
+  ProfScope ps("fft_rows", st);
+  return launch_mode<ROWS_ADJ>(op->K, op->n, op->half.ptr, x, op->tw.ptr, op->deapod.ptr, op->n, scale, st);
+}
+
+}  // namespace sh

@@ -1,0 +1,596 @@
+// Measurement operator Phi and its real adjoint (measurement equation y = Phi x + n; block split (2)).
+//
+// Phi = G F Z S: the FFT passes live in fft.hip; this file holds the planner and the interpolation
+// kernels G (degridding) and G^H (gridding) with a J x J Kaiser-Bessel kernel.
+//
+// Coordinates.  kappa = u K / (2 pi) is split on the host, in float64, into the grid cell
+// floor(kappa) mod K and the fraction kappa - floor(kappa); both are packed into one uint32 per axis
+// (cell in the top log2 K bits, the fraction truncated to the remaining bits), so the tap window is
+// the one float64 gives and the fraction is exact in float32.
+//
+// Order.  Inside each data block the visibilities are sorted by (uv tile of T x T cells, cell), so
+// blocks stay contiguous ("internal order": a permutation inside each block).  A work item is a
+// contiguous run of internal order with one (block, tile), cut into chunks of at most GRID_CHUNK.
+//
+// Degridding: one work-group per item stages the tile's padded (T+J-1)^2 grid patch in LDS; each
+// thread interpolates a contiguous sub-range of the item.  In dense items (many visibilities per
+// cell) a thread keeps the J x J taps of its current cell in registers across the run of
+// visibilities that share it.
+//
+// Gridding (atomic-free): one work-group per item owns a private padded patch.  Phase A computes the
+// 2J one-dimensional weights of a batch of visibilities, one thread each, into LDS.  Phase B walks
+// the batch wave by wave with one lane per tap (t1, t2): the lane accumulates w1[t1] w2[t2] v in a
+// register while the cell stays the same and adds it into its wave's own LDS copy of the patch when
+// the (wave-uniform) cell changes, so no two lanes ever update the same address.  The wave copies
+// are summed in a fixed order and the patch is written to the item's own slot; the fold kernel then
+// forms each grid cell as the sum, in a fixed order, of the patches that cover it.  Every sum has a
+// fixed order, so the adjoint is bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "op.hpp"
+#include "tables.hpp"
+
+namespace {
+
+constexpr int GRID_CHUNK = 4096;   // visibilities per gridding work item
+constexpr int BALL_CHUNK = 8192;   // visibilities per reduction chunk
+constexpr int RUN_MIN = 6;         // mean visibilities per cell of a dense work item
+
+__device__ __forceinline__ float kb_eval(const float* c, float s) {
+  float acc = c[KB_DEG];
+#pragma unroll
+  for (int i = KB_DEG - 1; i >= 0; --i) acc = fmaf(acc, s, c[i]);
+  return acc;
+}
+
+// Work items cover one tile's visibilities (gridding order: tile, then cell).  Each of the 256
+// threads of a work-group takes a contiguous sub-range of the item, so the lanes of a wave sit on
+// different cells.  Items whose visibilities pile up in few cells ("dense" items: many per cell) keep
+// the J x J taps of the current cell in registers across the run of visibilities that share it.
+
+__device__ __forceinline__ void item_range(const int4& it, int tid, int& lo, int& hi) {
+  lo = it.y + int((int64_t)it.z * tid / 256);
+  hi = it.y + int((int64_t)it.z * (tid + 1) / 256);
+}
+
+// Degridding of one item: the tile's padded (T+J-1)^2 grid patch is staged in LDS, then
+// V = sum_{t1,t2} w1[t1] w2[t2] X[r0 + t1, c0 + t2] per visibility.
+template <int J, int T, bool RUNS>
+__global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ grid,
+                                                     float2* __restrict__ out, const uint32_t* __restrict__ oidx,
+                                                     const int4* __restrict__ items, int log2K, int log2T, float scale,
+                                                     KBCoef kc) {
+  constexpr int P = T + J - 1;
+  constexpr int LO = J / 2 - 1;
+  __shared__ float2 patch[P * P];
+  const int tid = threadIdx.x;
+  const int4 it = items[blockIdx.x];
+  const int nT = 1 << (log2K - log2T);
+  const int kmask = (1 << log2K) - 1;
+  const int a0 = (it.x / nT) * T, b0 = (it.x % nT) * T;
+  for (int e = tid; e < P * P; e += 256) {
+    const int p1 = e / P, p2 = e - p1 * P;
+    patch[e] = grid[(size_t)((a0 - LO + p1) & kmask) * (kmask + 1) + ((b0 - LO + p2) & kmask)];
+  }
+  __syncthreads();
+  const int F = 32 - log2K;
+  const uint32_t fmask = (F == 32) ? 0xffffffffu : ((1u << F) - 1u);
+  const float fs = ldexpf(1.0f, 1 - F);
+  int lo, hi;
+  item_range(it, tid, lo, hi);
+  float2 cache[RUNS ? J : 1][RUNS ? J : 1];
+  int cur = -1;
+  for (int j = lo; j < hi; ++j) {
+    const uint2 c = coord[j];
+    const int lr = int(c.x >> F) - a0, lc = int(c.y >> F) - b0;
+    const float s1 = float(c.x & fmask) * fs - 1.0f;
+    const float s2 = float(c.y & fmask) * fs - 1.0f;
+    float w2[J];
+#pragma unroll
+    for (int t = 0; t < J; ++t) w2[t] = kb_eval(kc.c[t], s2);
+    float ar = 0.f, ai = 0.f;
+    if constexpr (RUNS) {
+      const int cell = lr * T + lc;
+      if (cell != cur) {
+        cur = cell;
+#pragma unroll
+        for (int t1 = 0; t1 < J; ++t1)
+#pragma unroll
+          for (int t2 = 0; t2 < J; ++t2) cache[t1][t2] = patch[(lr + t1) * P + lc + t2];
+      }
+#pragma unroll
+      for (int t1 = 0; t1 < J; ++t1) {
+        float rr = 0.f, ri = 0.f;
+#pragma unroll
+        for (int t2 = 0; t2 < J; ++t2) {
+          rr = fmaf(w2[t2], cache[t1][t2].x, rr);
+          ri = fmaf(w2[t2], cache[t1][t2].y, ri);
+        }
+        const float w1 = kb_eval(kc.c[t1], s1);
+        ar = fmaf(w1, rr, ar);
+        ai = fmaf(w1, ri, ai);
+      }
+    } else {
+#pragma unroll
+      for (int t1 = 0; t1 < J; ++t1) {
+        const float2* row = patch + (lr + t1) * P + lc;
+        float rr = 0.f, ri = 0.f;
+#pragma unroll
+        for (int t2 = 0; t2 < J; ++t2) {
+          const float2 g = row[t2];
+          rr = fmaf(w2[t2], g.x, rr);
+          ri = fmaf(w2[t2], g.y, ri);
+        }
+        const float w1 = kb_eval(kc.c[t1], s1);
+        ar = fmaf(w1, rr, ar);
+        ai = fmaf(w1, ri, ai);
+      }
+    }
+    out[oidx ? oidx[j] : j] = make_float2(ar * scale, ai * scale);
+  }
+}
+
+// Gridding of one work item into a private padded patch, written to patches[item slot].
+template <int J, int T>
+__global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ vis,
+                                                   const uint32_t* __restrict__ vidx, const int4* __restrict__ items,
+                                                   float2* __restrict__ patches, int log2K, int log2T, float scale,
+                                                   KBCoef kc) {
+  constexpr int P = T + J - 1;
+  constexpr int PP = P * P;
+  constexpr int NQ = (J * J + 63) / 64;   // taps per lane
+  constexpr int B = 256;                  // visibilities per batch (one per thread in phase A)
+  __shared__ float2 pat[4][PP];           // one patch copy per wave
+  __shared__ float wt[B][2 * J + 1];      // w1[0..J), w2[J..2J) per visibility
+  __shared__ float4 vc[B];                // (scale v.x, scale v.y, tap-(0,0) patch offset, -)
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < 4 * PP; e += 256) (&pat[0][0])[e] = make_float2(0.f, 0.f);
+  const int4 it = items[blockIdx.x];
+  const int nT = 1 << (log2K - log2T);
+  const int a0 = (it.x / nT) * T, b0 = (it.x % nT) * T;
+  const int F = 32 - log2K;
+  const uint32_t fmask = (F == 32) ? 0xffffffffu : ((1u << F) - 1u);
+  const float fs = ldexpf(1.0f, 1 - F);
+  int toff[NQ];                            // patch offset of this lane's taps relative to tap (0, 0)
+  bool tval[NQ];
+  float2 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int t = q * 64 + lane;
+    tval[q] = t < J * J;
+    toff[q] = tval[q] ? (t / J) * P + (t % J) : 0;
+    acc[q] = make_float2(0.f, 0.f);
+  }
+  int cur = -1;
+  const int end = it.y + it.z;
+  for (int base = it.y; base < end; base += B) {
+    const int nb = min(B, end - base);
+    __syncthreads();   // previous batch consumed (and the patches zeroed)
+    if (tid < nb) {
+      const int j = base + tid;
+      const uint2 c = coord[j];
+      const float2 v = vis[vidx ? vidx[j] : j];
+      const int lr = int(c.x >> F) - a0, lc = int(c.y >> F) - b0;
+      const float s1 = float(c.x & fmask) * fs - 1.0f;
+      const float s2 = float(c.y & fmask) * fs - 1.0f;
+#pragma unroll
+      for (int t = 0; t < J; ++t) {
+        wt[tid][t] = kb_eval(kc.c[t], s1);
+        wt[tid][J + t] = kb_eval(kc.c[t], s2);
+      }
+      vc[tid] = make_float4(v.x * scale, v.y * scale, __int_as_float(lr * P + lc), 0.f);
+    }
+    __syncthreads();
+    const int k1 = min(nb, wave * 64 + 64);
+    for (int k = wave * 64; k < k1; ++k) {
+      const float4 q4 = vc[k];
+      const int cell = __float_as_int(q4.z);   // the same for every lane of the wave
+      if (cell != cur) {
+        if (cur >= 0) {
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+            if (tval[q]) {
+              float2& d = pat[wave][cur + toff[q]];
+              d.x += acc[q].x;
+              d.y += acc[q].y;
+              acc[q] = make_float2(0.f, 0.f);
+            }
+        }
+        cur = cell;
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int t = q * 64 + lane;
+        if (tval[q]) {
+          const float w = wt[k][t / J] * wt[k][J + t % J];
+          acc[q].x = fmaf(w, q4.x, acc[q].x);
+          acc[q].y = fmaf(w, q4.y, acc[q].y);
+        }
+      }
+    }
+  }
+  if (cur >= 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (tval[q]) {
+        float2& d = pat[wave][cur + toff[q]];
+        d.x += acc[q].x;
+        d.y += acc[q].y;
+      }
+  }
+  __syncthreads();
+  float2* dst = patches + (size_t)it.w * PP;
+  for (int e = tid; e < PP; e += 256) {
+    const float2 p0 = pat[0][e], p1 = pat[1][e], p2 = pat[2][e], p3 = pat[3][e];
+    dst[e] = make_float2(((p0.x + p1.x) + p2.x) + p3.x, ((p0.y + p1.y) + p2.y) + p3.y);
+  }
+}
+
+// Each grid cell = sum over the tiles whose padded patch covers it (3 x 3 neighbourhood, fixed order)
+// of that tile's item patches (item order).  One work-group per tile.
+template <int J, int T>
+__global__ __launch_bounds__(256) void fold_kernel(const float2* __restrict__ patches, const int* __restrict__ tile_items,
+                                                   float2* __restrict__ grid, int log2K, int log2T) {
+  constexpr int P = T + J - 1;
+  constexpr int LO = J / 2 - 1;
+  const int nT = 1 << (log2K - log2T);
+  const int K = 1 << log2K;
+  const int tile = blockIdx.x;
+  const int a = tile / nT, b = tile % nT;
+  for (int e = threadIdx.x; e < T * T; e += 256) {
+    const int l1 = e / T, l2 = e % T;
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int da = -1; da <= 1; ++da) {
+      const int p1 = l1 - da * T + LO;
+      if (p1 < 0 || p1 >= P) continue;
+      const int a2 = (a + da + nT) % nT;
+#pragma unroll
+      for (int db = -1; db <= 1; ++db) {
+        const int p2 = l2 - db * T + LO;
+        if (p2 < 0 || p2 >= P) continue;
+        const int t2 = a2 * nT + (b + db + nT) % nT;
+        const int i0 = tile_items[t2], i1 = tile_items[t2 + 1];
+        for (int i = i0; i < i1; ++i) {
+          const float2 v = patches[(size_t)i * (P * P) + p1 * P + p2];
+          sr += v.x;
+          si += v.y;
+        }
+      }
+    }
+    grid[(size_t)(a * T + l1) * K + (b * T + l2)] = make_float2(sr, si);
+  }
+}
+
+__global__ void gather_kernel(const float2* __restrict__ src, const uint32_t* __restrict__ idx, float2* __restrict__ dst,
+                              int64_t M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) dst[i] = src[idx[i]];
+}
+
+__global__ void scatter_kernel(const float2* __restrict__ src, const uint32_t* __restrict__ idx, float2* __restrict__ dst,
+                               int64_t M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) dst[idx[i]] = src[i];
+}
+
+template <int J, int T>
+sh_status launch_degrid_T(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, float scale, hipStream_t st) {
+  if (op->n_sparse)
+    hipLaunchKernelGGL((degrid_kernel<J, T, false>), dim3((unsigned)op->n_sparse), dim3(256), 0, st, op->coord.ptr,
+                       grid, out, oidx, op->items.ptr, op->log2K, op->log2T, scale, op->kb);
+  if (op->n_items > op->n_sparse)
+    hipLaunchKernelGGL((degrid_kernel<J, T, true>), dim3((unsigned)(op->n_items - op->n_sparse)), dim3(256), 0, st,
+                       op->coord.ptr, grid, out, oidx, op->items.ptr + op->n_sparse, op->log2K, op->log2T, scale,
+                       op->kb);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+template <int J>
+sh_status launch_degrid(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, float scale, hipStream_t st) {
+  switch (op->T) {
+    case 8: return launch_degrid_T<J, 8>(op, grid, out, oidx, scale, st);
+    case 16: return launch_degrid_T<J, 16>(op, grid, out, oidx, scale, st);
+    case 32: return launch_degrid_T<J, 32>(op, grid, out, oidx, scale, st);
+  }
+  sh::set_error("unsupported tile %d", op->T);
+  return SH_EUNSUPPORTED;
+}
+
+template <int J, int T>
+sh_status launch_grid_T(sh_op op, const float2* vis, const uint32_t* vidx, float scale, hipStream_t st) {
+  {
+    sh::ProfScope ps("grid", st);
+    hipLaunchKernelGGL((grid_kernel<J, T>), dim3((unsigned)op->n_items), dim3(256), 0, st, op->coord.ptr, vis, vidx,
+                       op->items.ptr, op->patches.ptr, op->log2K, op->log2T, scale, op->kb);
+    SH_LAUNCHED();
+  }
+  sh::ProfScope ps("fold", st);
+  hipLaunchKernelGGL((fold_kernel<J, T>), dim3((unsigned)(op->nT * op->nT)), dim3(256), 0, st, op->patches.ptr,
+                     op->tile_items.ptr, op->grid.ptr, op->log2K, op->log2T);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+template <int J>
+sh_status launch_grid(sh_op op, const float2* vis, const uint32_t* vidx, float scale, hipStream_t st) {
+  switch (op->T) {
+    case 8: return launch_grid_T<J, 8>(op, vis, vidx, scale, st);
+    case 16: return launch_grid_T<J, 16>(op, vis, vidx, scale, st);
+    case 32: return launch_grid_T<J, 32>(op, vis, vidx, scale, st);
+  }
+  sh::set_error("unsupported tile %d", op->T);
+  return SH_EUNSUPPORTED;
+}
+
+}  // namespace
+
+namespace sh {
+
+sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, float scale, hipStream_t st) {
+  SH_TRY(fft_forward_2d(op, x, op->grid.ptr, st));
+  ProfScope ps("degrid", st);
+  const uint32_t* oi = user_order ? op->perm.ptr : nullptr;
+  switch (op->J) {
+#define SH_J(JJ) \
+  case JJ: return launch_degrid<JJ>(op, op->grid.ptr, vis, oi, scale, st);
+    SH_J(2) SH_J(4) SH_J(6) SH_J(8) SH_J(10) SH_J(12) SH_J(14) SH_J(16)
+#undef SH_J
+  }
+  set_error("unsupported J");
+  return SH_EUNSUPPORTED;
+}
+
+sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, float scale, hipStream_t st) {
+  const uint32_t* vi = user_order ? op->perm.ptr : nullptr;
+  sh_status s = SH_EUNSUPPORTED;
+  switch (op->J) {
+#define SH_J(JJ) \
+  case JJ: s = launch_grid<JJ>(op, vis, vi, scale, st); break;
+    SH_J(2) SH_J(4) SH_J(6) SH_J(8) SH_J(10) SH_J(12) SH_J(14) SH_J(16)
+#undef SH_J
+  }
+  SH_TRY(s);
+  return fft_adjoint_2d(op, op->grid.ptr, x, 1.0f, st);
+}
+
+}  // namespace sh
+
+// ------------------------------------------------------------------------------------------------
+// Planner and C ABI
+// ------------------------------------------------------------------------------------------------
+
+static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
+  const int64_t M = op->M;
+  const int K = op->K, F = 32 - op->log2K, log2T = op->log2T, nT = op->nT;
+  const double scale = double(K) / (2.0 * M_PI);
+  std::vector<uint2> cu(M);
+  std::vector<uint32_t> key(M);
+  for (int64_t m = 0; m < M; ++m) {
+    uint32_t q[2];
+    int cell[2];
+    for (int ax = 0; ax < 2; ++ax) {
+      const double kappa = uv[2 * m + ax] * scale;
+      const double base = std::floor(kappa);
+      const double frac = kappa - base;  // exact in float64, in [0, 1)
+      int64_t cl = (int64_t)base % K;
+      if (cl < 0) cl += K;
+      uint64_t fr = (uint64_t)std::floor(std::ldexp(frac, F));
+      if (F < 32 && fr >= (uint64_t(1) << F)) fr = (uint64_t(1) << F) - 1;
+      q[ax] = (uint32_t)(((uint64_t)cl << F) | fr);
+      cell[ax] = (int)cl;
+    }
+    cu[m] = make_uint2(q[0], q[1]);
+    const uint32_t tile = uint32_t((cell[0] >> log2T) * nT + (cell[1] >> log2T));
+    const uint32_t local = uint32_t(((cell[0] & (op->T - 1)) << log2T) | (cell[1] & (op->T - 1)));
+    key[m] = (tile << (2 * log2T)) | local;
+  }
+  // internal order: sort by (tile, cell) inside each block
+  std::vector<uint32_t> perm(M);
+  std::vector<uint64_t> kv;
+  for (int b = 0; b < op->R; ++b) {
+    const int64_t lo = offs[b], hi = offs[b + 1];
+    kv.resize(hi - lo);
+    for (int64_t m = lo; m < hi; ++m) kv[m - lo] = (uint64_t(key[m]) << 32) | uint64_t(m - lo);
+    std::sort(kv.begin(), kv.end());
+    for (int64_t m = lo; m < hi; ++m) perm[m] = uint32_t(lo + (kv[m - lo] & 0xffffffffu));
+  }
+  std::vector<uint2> ci(M);
+  for (int64_t i = 0; i < M; ++i) ci[i] = cu[perm[i]];
+  // work items: runs of internal order with one (block, tile), cut into near-equal chunks of at most
+  // GRID_CHUNK.  Items with at least RUN_MIN visibilities per occupied cell on average are "dense"
+  // (run-caching degridder).  Patch slots follow (tile, block) order so that the fold finds the
+  // items of a tile in one contiguous slot range.
+  const int ntiles = nT * nT;
+  struct Item { int tile, start, count, dense; };
+  std::vector<Item> all;
+  for (int64_t i = 0; i < M;) {
+    const uint32_t k0 = key[perm[i]] >> (2 * log2T);
+    int64_t e = i;
+    const int64_t bend = offs[std::upper_bound(offs, offs + op->R + 1, i) - offs];
+    while (e < bend && (key[perm[e]] >> (2 * log2T)) == k0) ++e;
+    const int64_t c = e - i, nck = sh::cdiv(c, GRID_CHUNK);
+    for (int64_t k = 0; k < nck; ++k) {
+      const int64_t a = i + c * k / nck, b = i + c * (k + 1) / nck;
+      int64_t cells = 0;
+      for (int64_t q = a; q < b; ++q) cells += (q == a || key[perm[q]] != key[perm[q - 1]]);
+      all.push_back({(int)k0, (int)a, (int)(b - a), (b - a) >= RUN_MIN * cells ? 1 : 0});
+    }
+    i = e;
+  }
+  std::vector<int> order(all.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return all[x].tile < all[y].tile; });
+  std::vector<int32_t> tile_items(ntiles + 1, 0), per_tile(ntiles, 0), slot_of(all.size());
+  for (size_t s = 0; s < order.size(); ++s) {
+    slot_of[order[s]] = (int32_t)s;
+    per_tile[all[order[s]].tile]++;
+  }
+  for (int t = 0; t < ntiles; ++t) tile_items[t + 1] = tile_items[t] + per_tile[t];
+  std::vector<int4> items;
+  for (int pass = 0; pass < 2; ++pass)
+    for (size_t q = 0; q < all.size(); ++q)
+      if (all[q].dense == pass) items.push_back(make_int4(all[q].tile, all[q].start, all[q].count, slot_of[q]));
+  op->n_items = (int64_t)items.size();
+  op->n_sparse = 0;
+  for (auto& a : all) op->n_sparse += a.dense == 0;
+  op->max_items_per_tile = *std::max_element(per_tile.begin(), per_tile.end());
+  // reduction chunks (never straddling a block)
+  std::vector<int4> chunks;
+  op->chunk_first.assign(op->R + 1, 0);
+  for (int b = 0; b < op->R; ++b) {
+    op->chunk_first[b] = (int32_t)chunks.size();
+    for (int64_t s = offs[b]; s < offs[b + 1]; s += BALL_CHUNK)
+      chunks.push_back(make_int4(b, (int)s, (int)std::min<int64_t>(s + BALL_CHUNK, offs[b + 1]), 0));
+  }
+  op->chunk_first[op->R] = (int32_t)chunks.size();
+  op->n_chunks = (int64_t)chunks.size();
+
+  SH_TRY(op->coord.upload(ci));
+  SH_TRY(op->perm.upload(perm));
+  SH_TRY(op->items.upload(items));
+  SH_TRY(op->tile_items.upload(tile_items));
+  SH_TRY(op->chunks.upload(chunks));
+  SH_TRY(op->chunk_first_d.upload(op->chunk_first));
+  SH_TRY(op->partials.alloc(2 * std::max<int64_t>(op->n_chunks, 1)));
+  // tables
+  std::vector<float> dp(op->n);
+  for (int r = 0; r < op->n; ++r) dp[r] = float(1.0 / sh::kb_transform(double(r - op->n / 2) / K, op->J, op->beta));
+  SH_TRY(op->deapod.upload(dp));
+  std::vector<float2> tw;
+  sh::fft_twiddles(K, tw);
+  SH_TRY(op->tw.upload(tw));
+  // scratch
+  const int P = op->T + op->J - 1;
+  SH_TRY(op->grid.alloc((size_t)K * K));
+  SH_TRY(op->half.alloc((size_t)op->n * K));
+  SH_TRY(op->patches.alloc((size_t)std::max<int64_t>(op->n_items, 1) * P * P));
+  SH_TRY(op->vis_tmp.alloc((size_t)M));
+  return SH_OK;
+}
+
+extern "C" {
+
+sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
+                       const int64_t* block_offsets, int32_t R, sh_op* out) {
+  SH_REQUIRE(out != nullptr, "out is NULL");
+  *out = nullptr;
+  SH_REQUIRE(uv != nullptr && block_offsets != nullptr, "uv and block_offsets must be non-NULL");
+  SH_REQUIRE(M >= 1 && M < (int64_t(1) << 31), "M must be in [1, 2^31), got %lld", (long long)M);
+  SH_REQUIRE(sh::is_pow2(n) && n >= 16 && n <= 4096, "n must be a power of two in [16, 4096], got %d", n);
+  SH_REQUIRE(oversample == 2 || oversample == 4, "oversample must be 2 or 4, got %d", oversample);
+  SH_REQUIRE(kernel_width >= 2 && kernel_width <= 16 && kernel_width % 2 == 0, "J must be even in [2, 16], got %d",
+             kernel_width);
+  SH_REQUIRE(R >= 1 && R <= M, "R must be in [1, M], got %d", R);
+  SH_REQUIRE(block_offsets[0] == 0 && block_offsets[R] == M, "block offsets must run from 0 to M");
+  for (int i = 0; i < R; ++i)
+    SH_REQUIRE(block_offsets[i + 1] > block_offsets[i], "block offsets must be strictly increasing (block %d)", i);
+  for (int64_t m = 0; m < 2 * M; ++m)
+    SH_REQUIRE(std::isfinite(uv[m]) && uv[m] >= -M_PI && uv[m] < M_PI, "uv[%lld] = %g outside [-pi, pi)",
+               (long long)m, uv[m]);
+  const int K = n * oversample;
+  SH_REQUIRE(K <= 8192, "grid side alpha*n must be <= 8192");
+  sh_op op = new (std::nothrow) sh_op_s();
+  if (!op) {
+    sh::set_error("host allocation failed");
+    return SH_ENOMEM;
+  }
+  op->M = M;
+  op->n = n;
+  op->alpha = oversample;
+  op->K = K;
+  op->log2K = sh::ilog2(K);
+  op->J = kernel_width;
+  op->R = R;
+  op->T = std::min(32, K / 4);
+  while (op->T < kernel_width / 2) op->T *= 2;
+  op->log2T = sh::ilog2(op->T);
+  op->nT = K / op->T;
+  op->beta = sh::kb_beta(kernel_width, oversample);
+  float coef[16 * (KB_DEG + 1)];
+  sh::kb_tap_polys(kernel_width, op->beta, KB_DEG, coef);
+  for (int t = 0; t < kernel_width; ++t)
+    for (int i = 0; i <= KB_DEG; ++i) op->kb.c[t][i] = coef[t * (KB_DEG + 1) + i];
+  op->offsets.assign(block_offsets, block_offsets + R + 1);
+  sh_status s = op_build(op, uv, block_offsets);
+  if (s != SH_OK) {
+    delete op;
+    return s;
+  }
+  *out = op;
+  return SH_OK;
+}
+
+sh_status sh_op_destroy(sh_op op) {
+  delete op;
+  return SH_OK;
+}
+
+sh_status sh_op_query(sh_op op, int64_t out[8]) {
+  SH_REQUIRE(op && out, "NULL argument");
+  out[0] = op->M;
+  out[1] = op->n;
+  out[2] = op->K;
+  out[3] = op->J;
+  out[4] = op->R;
+  out[5] = op->n_items;
+  out[6] = op->T;
+  out[7] = op->max_items_per_tile;
+  return SH_OK;
+}
+
+sh_status sh_op_block_offsets(sh_op op, int64_t* offsets_out) {
+  SH_REQUIRE(op && offsets_out, "NULL argument");
+  std::copy(op->offsets.begin(), op->offsets.end(), offsets_out);
+  return SH_OK;
+}
+
+sh_status sh_op_permutation(sh_op op, int64_t* perm_out) {
+  SH_REQUIRE(op && perm_out, "NULL argument");
+  std::vector<uint32_t> p(op->M);
+  SH_HIP(hipMemcpy(p.data(), op->perm.ptr, op->M * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < op->M; ++i) perm_out[i] = p[i];
+  return SH_OK;
+}
+
+sh_status sh_phi_fwd(sh_op op, const float* x, float* vis, void* stream) {
+  SH_REQUIRE(op && x && vis, "NULL argument");
+  return sh::phi_forward(op, x, (float2*)vis, true, 1.0f, (hipStream_t)stream);
+}
+
+sh_status sh_phi_adj(sh_op op, const float* vis, float* x, void* stream) {
+  SH_REQUIRE(op && x && vis, "NULL argument");
+  return sh::phi_adjoint(op, (const float2*)vis, x, true, 1.0f, (hipStream_t)stream);
+}
+
+sh_status sh_phi_fwd_internal(sh_op op, const float* x, float* vis, void* stream) {
+  SH_REQUIRE(op && x && vis, "NULL argument");
+  return sh::phi_forward(op, x, (float2*)vis, false, 1.0f, (hipStream_t)stream);
+}
+
+sh_status sh_phi_adj_internal(sh_op op, const float* vis, float* x, void* stream) {
+  SH_REQUIRE(op && x && vis, "NULL argument");
+  return sh::phi_adjoint(op, (const float2*)vis, x, false, 1.0f, (hipStream_t)stream);
+}
+
+sh_status sh_vis_to_internal(sh_op op, const float* user, float* internal, void* stream) {
+  SH_REQUIRE(op && user && internal && user != internal, "NULL or aliased argument");
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)sh::cdiv(op->M, 256)), dim3(256), 0, (hipStream_t)stream,
+                     (const float2*)user, op->perm.ptr, (float2*)internal, op->M);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status sh_vis_to_user(sh_op op, const float* internal, float* user, void* stream) {
+  SH_REQUIRE(op && user && internal && user != internal, "NULL or aliased argument");
+  hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)sh::cdiv(op->M, 256)), dim3(256), 0, (hipStream_t)stream,
+                     (const float2*)internal, op->perm.ptr, (float2*)user, op->M);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+}  // extern "C"

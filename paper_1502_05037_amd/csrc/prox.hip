@@ -1,0 +1,316 @@
+// Proximal steps of SDMM on problem (3), each fused with its dual update, plus the float64 reductions
+// that drive them (per-block l2 norms, CG dot products, the stopping test and the reweighting).
+//
+// For a split with linear image s = L_j x, dual z and proximal map prox:
+//   t = s + z;  y = prox(t);  z <- t - y;  v = y - z   (v feeds the next x-update).
+// Reductions are two-stage with a fixed tree (per-work-group partials, then one work-group), so they
+// are deterministic.
+#include <cmath>
+
+#include "prox.hpp"
+
+namespace {
+
+constexpr int RB = 512;   // work-groups of the first reduction stage
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// partial[b] = sum over a grid-stride slice of a[i]*b[i] (float64)
+__global__ __launch_bounds__(256) void dot_partial(const float* __restrict__ a, const float* __restrict__ b, int64_t N,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
+    acc += double(a[i]) * double(b[i]);
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+// out[0] = sum of part[0..n) (one work-group, fixed tree)
+__global__ __launch_bounds__(256) void sum_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+__global__ __launch_bounds__(256) void mean_partial(const float* __restrict__ a, int64_t N, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) acc += double(a[i]);
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void var_partial(const float* __restrict__ a, int64_t N, const double* __restrict__ sum,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[256];
+  const double mean = sum[0] / double(N);
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    const double d = double(a[i]) - mean;
+    acc += d * d;
+  }
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void maxabs_partial(const float* __restrict__ a, int64_t N, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
+    acc = fmax(acc, fabs(double(a[i])));
+  const int tid = threadIdx.x;
+  sh[tid] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] = fmax(sh[tid], sh[tid + s]);
+    __syncthreads();
+  }
+  if (tid == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void max_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc = fmax(acc, part[i]);
+  const int tid = threadIdx.x;
+  sh[tid] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] = fmax(sh[tid], sh[tid + s]);
+    __syncthreads();
+  }
+  if (tid == 0) out[0] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void l1w_partial(const float* __restrict__ c, const float* __restrict__ W, int64_t N,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
+    acc += fabs(double(c[i]) * (W ? double(W[i]) : 1.0));
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+// weighted soft threshold + dual
+__global__ __launch_bounds__(256) void prox_l1_kernel(int64_t D, const float* __restrict__ s, float* __restrict__ z,
+                                                      const float* __restrict__ W, float gamma, float* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= D) return;
+  const float t = s[i] + z[i];
+  const float tau = gamma * (W ? W[i] : 1.0f);
+  const float m = fabsf(t) - tau;
+  const float y = m > 0.f ? copysignf(m, t) : 0.f;
+  const float zn = t - y;
+  z[i] = zn;
+  v[i] = y - zn;
+}
+
+// positive orthant + dual
+__global__ __launch_bounds__(256) void prox_pos_kernel(int64_t N, const float* __restrict__ s, float* __restrict__ z,
+                                                       float* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const float t = s[i] + z[i];
+  const float y = fmaxf(t, 0.f);
+  const float zn = t - y;
+  z[i] = zn;
+  v[i] = y - zn;
+}
+
+// per-chunk float64 partial sums of ||s + z - yhat||^2 and ||s - yhat||^2
+__global__ __launch_bounds__(256) void ball_norms(const float2* __restrict__ s, const float2* __restrict__ z,
+                                                  const float2* __restrict__ yh, const int4* __restrict__ chunks,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int4 c = chunks[blockIdx.x];
+  double a = 0.0, b = 0.0;
+  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
+    const float2 sv = s[i], zv = z[i], yv = yh[i];
+    const double dr = double(sv.x) - double(yv.x), di = double(sv.y) - double(yv.y);
+    const double tr = dr + double(zv.x), ti = di + double(zv.y);
+    a += tr * tr + ti * ti;
+    b += dr * dr + di * di;
+  }
+  const double ra = block_sum(a, sh);
+  const double rb = block_sum(b, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ra;
+    part[2 * blockIdx.x + 1] = rb;
+  }
+}
+
+// per block: rho = ||t - yhat||, resid = ||s - yhat|| (chunk partials summed in order)
+__global__ void ball_final(const double* __restrict__ part, const int* __restrict__ first, int R,
+                           double* __restrict__ rho, double* __restrict__ resid) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= R) return;
+  double a = 0.0, c = 0.0;
+  for (int k = first[b]; k < first[b + 1]; ++k) {
+    a += part[2 * k];
+    c += part[2 * k + 1];
+  }
+  rho[b] = sqrt(a);
+  resid[b] = sqrt(c);
+}
+
+// y = yhat + (t - yhat) min(1, eps/rho); z <- t - y; v = y - z (- s if sub_s)
+__global__ __launch_bounds__(256) void ball_project(const float2* __restrict__ s, float2* __restrict__ z,
+                                                    const float2* __restrict__ yh, const int4* __restrict__ chunks,
+                                                    const double* __restrict__ eps, const double* __restrict__ rho,
+                                                    float2* __restrict__ v, int sub_s) {
+  const int4 c = chunks[blockIdx.x];
+  const double r = rho[c.x], e = eps[c.x];
+  const bool inside = r <= e;   // inside the ball (boundary included) the projection is the identity
+  const float ratio = inside ? 1.0f : float(e / r);
+  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
+    const float2 sv = s[i], zv = z[i], yv = yh[i];
+    const float tr = sv.x + zv.x, ti = sv.y + zv.y;
+    const float yr = inside ? tr : yv.x + (tr - yv.x) * ratio;
+    const float yi = inside ? ti : yv.y + (ti - yv.y) * ratio;
+    const float zr = tr - yr, zi = ti - yi;
+    z[i] = make_float2(zr, zi);
+    v[i] = sub_s ? make_float2(yr - zr - sv.x, yi - zi - sv.y) : make_float2(yr - zr, yi - zi);
+  }
+}
+
+__global__ __launch_bounds__(256) void reweight_kernel(int64_t D, const float* __restrict__ c, double delta,
+                                                       float* __restrict__ W) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < D) W[i] = float(delta / (delta + fabs(double(c[i]))));
+}
+
+}  // namespace
+
+namespace sh {
+
+sh_status Reducer::init() {
+  SH_TRY(part.alloc(RB * 2));
+  return SH_OK;
+}
+
+sh_status Reducer::dot(const float* a, const float* b, int64_t N, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(dot_partial, dim3(RB), dim3(256), 0, st, a, b, N, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part.ptr, RB, out);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status Reducer::std_dev(const float* a, int64_t N, double* sum_out, double* var_out, hipStream_t st) {
+  hipLaunchKernelGGL(mean_partial, dim3(RB), dim3(256), 0, st, a, N, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part.ptr, RB, sum_out);
+  hipLaunchKernelGGL(var_partial, dim3(RB), dim3(256), 0, st, a, N, sum_out, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part.ptr, RB, var_out);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status Reducer::maxabs(const float* a, int64_t N, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(maxabs_partial, dim3(RB), dim3(256), 0, st, a, N, part.ptr);
+  hipLaunchKernelGGL(max_final, dim3(1), dim3(256), 0, st, part.ptr, RB, out);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status Reducer::l1w(const float* c, const float* W, int64_t N, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(l1w_partial, dim3(RB), dim3(256), 0, st, c, W, N, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part.ptr, RB, out);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status launch_prox_l1(int64_t D, const float* s, float* z, const float* W, float gamma, float* v, hipStream_t st) {
+  ProfScope ps("prox", st);
+  hipLaunchKernelGGL(prox_l1_kernel, dim3((unsigned)cdiv(D, 256)), dim3(256), 0, st, D, s, z, W, gamma, v);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status launch_prox_pos(int64_t N, const float* s, float* z, float* v, hipStream_t st) {
+  ProfScope ps("prox", st);
+  hipLaunchKernelGGL(prox_pos_kernel, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, st, N, s, z, v);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
+                           double* resid, float2* v, bool sub_s, hipStream_t st) {
+  ProfScope ps("prox", st);
+  const unsigned nc = (unsigned)op->n_chunks;
+  hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, op->partials.ptr);
+  hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
+                     op->chunk_first_d.ptr, op->R, rho, resid);
+  hipLaunchKernelGGL(ball_project, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, eps, rho, v, sub_s ? 1 : 0);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status launch_reweight(int64_t D, const float* c, double delta, float* W, hipStream_t st) {
+  hipLaunchKernelGGL(reweight_kernel, dim3((unsigned)cdiv(D, 256)), dim3(256), 0, st, D, c, delta, W);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+}  // namespace sh
+
+extern "C" {
+
+sh_status sh_prox_l1(int64_t D, const float* s, float* z, const float* W, float gamma, float* v_out, void* stream) {
+  SH_REQUIRE(D >= 1 && s && z && v_out, "invalid argument");
+  SH_REQUIRE(std::isfinite(gamma) && gamma >= 0.f, "gamma must be finite and >= 0");
+  return sh::launch_prox_l1(D, s, z, W, gamma, v_out, (hipStream_t)stream);
+}
+
+sh_status sh_prox_pos(int64_t N, const float* s, float* z, float* v_out, void* stream) {
+  SH_REQUIRE(N >= 1 && s && z && v_out, "invalid argument");
+  return sh::launch_prox_pos(N, s, z, v_out, (hipStream_t)stream);
+}
+
+sh_status sh_prox_ball(sh_op op, const float* s, float* z, const float* yhat, const double* eps, float* v_out,
+                       double* resid_out, void* stream) {
+  SH_REQUIRE(op && s && z && yhat && eps && v_out && resid_out, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  sh::DevBuf<double> rho;
+  SH_TRY(rho.alloc(op->R));
+  SH_TRY(sh::launch_prox_ball(op, (const float2*)s, (float2*)z, (const float2*)yhat, eps, rho.ptr, resid_out,
+                              (float2*)v_out, false, st));
+  SH_HIP(hipStreamSynchronize(st));  // rho is freed on return
+  return SH_OK;
+}
+
+sh_status sh_reweight(int64_t D, const float* c, double delta, float* W_out, void* stream) {
+  SH_REQUIRE(D >= 1 && c && W_out, "invalid argument");
+  SH_REQUIRE(std::isfinite(delta) && delta > 0, "delta must be finite and > 0");
+  return sh::launch_reweight(D, c, delta, W_out, (hipStream_t)stream);
+}
+
+sh_status sh_std(int64_t D, const float* c, double* std_out, void* stream) {
+  SH_REQUIRE(D >= 1 && c && std_out, "invalid argument");
+  hipStream_t st = (hipStream_t)stream;
+  sh::Reducer red;
+  SH_TRY(red.init());
+  sh::DevBuf<double> r;
+  SH_TRY(r.alloc(2));
+  SH_TRY(red.std_dev(c, D, r.ptr, r.ptr + 1, st));
+  double h[2];
+  SH_HIP(hipMemcpyAsync(h, r.ptr, sizeof(h), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipStreamSynchronize(st));
+  *std_out = std::sqrt(h[1] / double(D));
+  return SH_OK;
+}
+
+}  // extern "C"

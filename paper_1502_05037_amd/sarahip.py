@@ -1,0 +1,305 @@
+"""ctypes binding of libsarahip.so (the C ABI in include/sarahip.h).
+
+Argument marshalling only: every step of the imaging path runs in the HIP
+library.  Device arrays are torch tensors on a ROCm device (float32, or
+complex64 / float32 pairs for visibilities); host arrays are numpy arrays.
+Each function has the name of the C entry point without the ``sh_`` prefix
+and raises :class:`SarahipError` on a non-OK status.  Importing this module
+raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsarahip.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "or python paper_1502_05037_amd/csrc/build.py")
+lib = C.CDLL(_LIB_PATH)
+
+STATUS = {0: "SH_OK", -1: "SH_EINVAL", -2: "SH_ENOMEM", -3: "SH_EDEVICE", -4: "SH_ENONFINITE", -5: "SH_EUNSUPPORTED"}
+SARA_MASK = 0x1FF
+
+
+class SarahipError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib.sh_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+
+
+class SdmmParams(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("nu", C.c_double), ("tol_rel", C.c_double), ("eps_slack", C.c_double),
+                ("rw_beta", C.c_double), ("rw_delta0", C.c_double), ("max_iter", C.c_int32),
+                ("cg_iters", C.c_int32), ("passes", C.c_int32), ("check_every", C.c_int32)]
+
+
+class SdmmInfo(C.Structure):
+    _fields_ = [("iters_total", C.c_int32), ("passes_done", C.c_int32), ("converged", C.c_int32),
+                ("iters_last", C.c_int32), ("rel_change", C.c_double), ("objective", C.c_double),
+                ("gamma", C.c_double), ("nu", C.c_double), ("delta", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp, _i64, _i32, _u32, _f32, _f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_float, C.c_double
+_P64 = C.POINTER(C.c_double)
+_PI64 = C.POINTER(C.c_int64)
+_SIGS = {
+    "sh_last_error": (C.c_char_p, []),
+    "sh_version": (C.c_char_p, []),
+    "sh_op_create": (C.c_int, [_P64, _i64, _i32, _i32, _i32, _PI64, _i32, C.POINTER(_vp)]),
+    "sh_op_destroy": (C.c_int, [_vp]),
+    "sh_op_query": (C.c_int, [_vp, _PI64]),
+    "sh_op_block_offsets": (C.c_int, [_vp, _PI64]),
+    "sh_op_permutation": (C.c_int, [_vp, _PI64]),
+    "sh_phi_fwd": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sh_phi_adj": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sh_phi_fwd_internal": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sh_phi_adj_internal": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sh_vis_to_internal": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sh_vis_to_user": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sh_op_norm": (C.c_int, [_vp, _vp, _i32, _f64, _P64, _vp]),
+    "sh_psi_create": (C.c_int, [_i32, _i32, _u32, C.POINTER(_vp)]),
+    "sh_psi_destroy": (C.c_int, [_vp]),
+    "sh_psi_planes": (C.c_int, [_vp, C.POINTER(_i32)]),
+    "sh_daubechies": (C.c_int, [_i32, _P64]),
+    "sh_psi_fwd": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sh_psi_adj": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sh_prox_l1": (C.c_int, [_i64, _vp, _vp, _vp, _f32, _vp, _vp]),
+    "sh_prox_pos": (C.c_int, [_i64, _vp, _vp, _vp, _vp]),
+    "sh_prox_ball": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "sh_reweight": (C.c_int, [_i64, _vp, _f64, _vp, _vp]),
+    "sh_std": (C.c_int, [_i64, _vp, _P64, _vp]),
+    "sh_sdmm_default_params": (None, [C.POINTER(SdmmParams)]),
+    "sh_sdmm_solve": (C.c_int, [_vp, _vp, _vp, _P64, _vp, _vp, C.POINTER(SdmmParams), _vp, _vp, _P64,
+                                C.POINTER(SdmmInfo), _vp]),
+    "sh_sdmm_create": (C.c_int, [_vp, _vp, _vp, _P64, _vp, _vp, C.POINTER(SdmmParams), C.POINTER(_vp), _vp]),
+    "sh_sdmm_iterate": (C.c_int, [_vp, _i32, _vp]),
+    "sh_sdmm_result": (C.c_int, [_vp, _vp, _P64, _P64, _vp]),
+    "sh_sdmm_destroy": (C.c_int, [_vp]),
+    "sh_profile_enable": (C.c_int, [_i32]),
+    "sh_profile_read": (C.c_int, [C.c_char_p, _PI64, _P64]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise SarahipError(status, where)
+
+
+def _ptr(t) -> int | None:
+    """Device pointer of a torch tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def version() -> str:
+    return lib.sh_version().decode()
+
+
+# ---- measurement operator ------------------------------------------------------------------
+
+def op_create(uv: np.ndarray, n: int, oversample: int, kernel_width: int, block_offsets) -> int:
+    uv = _f64(uv)
+    if uv.ndim != 2 or uv.shape[1] != 2:
+        raise ValueError("uv must be (M, 2)")
+    off = np.ascontiguousarray(block_offsets, dtype=np.int64)
+    h = _vp()
+    _check(lib.sh_op_create(uv.ctypes.data_as(_P64), uv.shape[0], n, oversample, kernel_width,
+                            off.ctypes.data_as(_PI64), len(off) - 1, C.byref(h)), "op_create")
+    return h.value
+
+
+def op_destroy(op: int) -> None:
+    _check(lib.sh_op_destroy(op), "op_destroy")
+
+
+def op_query(op: int) -> dict:
+    out = np.zeros(8, dtype=np.int64)
+    _check(lib.sh_op_query(op, out.ctypes.data_as(_PI64)), "op_query")
+    keys = ("M", "n", "K", "J", "R", "n_items", "tile", "max_items_per_tile")
+    return dict(zip(keys, (int(v) for v in out)))
+
+
+def op_block_offsets(op: int) -> np.ndarray:
+    R = op_query(op)["R"]
+    out = np.zeros(R + 1, dtype=np.int64)
+    _check(lib.sh_op_block_offsets(op, out.ctypes.data_as(_PI64)), "op_block_offsets")
+    return out
+
+
+def op_permutation(op: int) -> np.ndarray:
+    M = op_query(op)["M"]
+    out = np.zeros(M, dtype=np.int64)
+    _check(lib.sh_op_permutation(op, out.ctypes.data_as(_PI64)), "op_permutation")
+    return out
+
+
+def phi_fwd(op, x, vis, stream=None):
+    _check(lib.sh_phi_fwd(op, _ptr(x), _ptr(vis), _stream(stream)), "phi_fwd")
+
+
+def phi_adj(op, vis, x, stream=None):
+    _check(lib.sh_phi_adj(op, _ptr(vis), _ptr(x), _stream(stream)), "phi_adj")
+
+
+def phi_fwd_internal(op, x, vis, stream=None):
+    _check(lib.sh_phi_fwd_internal(op, _ptr(x), _ptr(vis), _stream(stream)), "phi_fwd_internal")
+
+
+def phi_adj_internal(op, vis, x, stream=None):
+    _check(lib.sh_phi_adj_internal(op, _ptr(vis), _ptr(x), _stream(stream)), "phi_adj_internal")
+
+
+def vis_to_internal(op, user, internal, stream=None):
+    _check(lib.sh_vis_to_internal(op, _ptr(user), _ptr(internal), _stream(stream)), "vis_to_internal")
+
+
+def vis_to_user(op, internal, user, stream=None):
+    _check(lib.sh_vis_to_user(op, _ptr(internal), _ptr(user), _stream(stream)), "vis_to_user")
+
+
+def op_norm(op, x0, iters: int = 200, tol: float = 1e-12, stream=None) -> float:
+    nu = C.c_double()
+    _check(lib.sh_op_norm(op, _ptr(x0), iters, tol, C.byref(nu), _stream(stream)), "op_norm")
+    return nu.value
+
+
+# ---- SARA dictionary ------------------------------------------------------------------------
+
+def psi_create(n: int, levels: int = 4, basis_mask: int = SARA_MASK) -> int:
+    h = _vp()
+    _check(lib.sh_psi_create(n, levels, basis_mask, C.byref(h)), "psi_create")
+    return h.value
+
+
+def psi_destroy(psi: int) -> None:
+    _check(lib.sh_psi_destroy(psi), "psi_destroy")
+
+
+def psi_planes(psi: int) -> int:
+    q = C.c_int32()
+    _check(lib.sh_psi_planes(psi, C.byref(q)), "psi_planes")
+    return q.value
+
+
+def daubechies(p: int) -> np.ndarray:
+    h = np.zeros(2 * p, dtype=np.float64)
+    _check(lib.sh_daubechies(p, h.ctypes.data_as(_P64)), "daubechies")
+    return h
+
+
+def psi_fwd(psi, coeffs, x, stream=None):
+    _check(lib.sh_psi_fwd(psi, _ptr(coeffs), _ptr(x), _stream(stream)), "psi_fwd")
+
+
+def psi_adj(psi, x, coeffs, stream=None):
+    _check(lib.sh_psi_adj(psi, _ptr(x), _ptr(coeffs), _stream(stream)), "psi_adj")
+
+
+# ---- proximal steps -------------------------------------------------------------------------
+
+def prox_l1(s, z, W, gamma: float, v_out, stream=None):
+    _check(lib.sh_prox_l1(s.numel(), _ptr(s), _ptr(z), _ptr(W), gamma, _ptr(v_out), _stream(stream)), "prox_l1")
+
+
+def prox_pos(s, z, v_out, stream=None):
+    _check(lib.sh_prox_pos(s.numel(), _ptr(s), _ptr(z), _ptr(v_out), _stream(stream)), "prox_pos")
+
+
+def prox_ball(op, s, z, yhat, eps_dev, v_out, resid_out, stream=None):
+    _check(lib.sh_prox_ball(op, _ptr(s), _ptr(z), _ptr(yhat), _ptr(eps_dev), _ptr(v_out), _ptr(resid_out),
+                            _stream(stream)), "prox_ball")
+
+
+def reweight(c, delta: float, W_out, stream=None):
+    _check(lib.sh_reweight(c.numel(), _ptr(c), delta, _ptr(W_out), _stream(stream)), "reweight")
+
+
+def std(c, stream=None) -> float:
+    out = C.c_double()
+    _check(lib.sh_std(c.numel(), _ptr(c), C.byref(out), _stream(stream)), "std")
+    return out.value
+
+
+# ---- SDMM -----------------------------------------------------------------------------------
+
+def sdmm_default_params() -> SdmmParams:
+    p = SdmmParams()
+    lib.sh_sdmm_default_params(C.byref(p))
+    return p
+
+
+def sdmm_solve(op, psi, y, eps, W, x0, params: SdmmParams, x_out, W_out=None, stream=None):
+    """Returns (info dict, block residuals ||y_i - Phi_i x|| as float64 numpy)."""
+    eps = _f64(eps)
+    R = len(eps)
+    resid = np.zeros(R, dtype=np.float64)
+    info = SdmmInfo()
+    _check(lib.sh_sdmm_solve(op, psi, _ptr(y), eps.ctypes.data_as(_P64), _ptr(W), _ptr(x0), C.byref(params),
+                             _ptr(x_out), _ptr(W_out), resid.ctypes.data_as(_P64), C.byref(info),
+                             _stream(stream)), "sdmm_solve")
+    return info.as_dict(), resid
+
+
+def sdmm_create(op, psi, y, eps, W, x0, params: SdmmParams, stream=None) -> int:
+    eps = _f64(eps)
+    h = _vp()
+    _check(lib.sh_sdmm_create(op, psi, _ptr(y), eps.ctypes.data_as(_P64), _ptr(W), _ptr(x0), C.byref(params),
+                              C.byref(h), _stream(stream)), "sdmm_create")
+    return h.value
+
+
+def sdmm_iterate(s: int, iters: int, stream=None) -> None:
+    _check(lib.sh_sdmm_iterate(s, iters, _stream(stream)), "sdmm_iterate")
+
+
+def sdmm_result(s: int, x_out=None, R: int = 0, stream=None):
+    """Returns (block residuals as float64 numpy of length R, relative change)."""
+    resid = np.zeros(max(R, 1), dtype=np.float64)
+    rel = C.c_double()
+    _check(lib.sh_sdmm_result(s, _ptr(x_out), resid.ctypes.data_as(_P64) if R else None, C.byref(rel),
+                              _stream(stream)), "sdmm_result")
+    return resid[:R], rel.value
+
+
+def sdmm_destroy(s: int) -> None:
+    _check(lib.sh_sdmm_destroy(s), "sdmm_destroy")
+
+
+# ---- timing ---------------------------------------------------------------------------------
+
+def profile_enable(on: bool = True) -> None:
+    _check(lib.sh_profile_enable(1 if on else 0), "profile_enable")
+
+
+def profile_read(name: str):
+    cnt = C.c_int64()
+    ms = C.c_double()
+    _check(lib.sh_profile_read(name.encode(), C.byref(cnt), C.byref(ms)), "profile_read")
+    return cnt.value, ms.value

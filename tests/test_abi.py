@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry point, validates
+arguments before touching the device, and computes the same Daubechies filters as the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1502_05037_amd import sarahip as sh
+from oracle import wavelets
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "sarahip.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sh_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_symbols()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(sh.lib, name), name
+    assert set(names) == set(sh.EXPORTED)
+
+
+def test_version():
+    assert "gfx950" in sh.version()
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_daubechies_matches_oracle(p):
+    np.testing.assert_allclose(sh.daubechies(p), wavelets.daubechies(p), rtol=0, atol=2e-15)
+
+
+def _bad_create(**kw):
+    args = dict(uv=np.zeros((4, 2)), n=16, oversample=2, kernel_width=6, block_offsets=[0, 4])
+    args.update(kw)
+    with pytest.raises(sh.SarahipError) as e:
+        sh.op_create(**args)
+    assert e.value.status == -1
+    return str(e.value)
+
+
+def test_op_create_rejects_invalid_arguments():
+    assert "[-pi, pi)" in _bad_create(uv=np.array([[0.0, np.pi], [0, 0], [0, 0], [0, 0]]))
+    _bad_create(uv=np.array([[np.nan, 0.0], [0, 0], [0, 0], [0, 0]]))
+    _bad_create(n=24)                           # not a power of two
+    _bad_create(kernel_width=5)                 # odd J
+    _bad_create(kernel_width=18)
+    _bad_create(block_offsets=[0, 3])           # does not end at M
+    _bad_create(block_offsets=[0, 2, 2, 4])     # empty block
+    _bad_create(uv=np.zeros((0, 2)), block_offsets=[0])  # M = 0
+    _bad_create(oversample=3)
+
+
+def test_psi_create_rejects_invalid_arguments():
+    for kw in (dict(n=24, levels=4), dict(n=16, levels=0), dict(n=16, levels=4, basis_mask=0),
+               dict(n=16, levels=4, basis_mask=0x200)):
+        with pytest.raises(sh.SarahipError) as e:
+            sh.psi_create(**kw)
+        assert e.value.status == -1
+
+
+def test_prox_and_profile_argument_checks():
+    with pytest.raises(sh.SarahipError):
+        sh.lib_check = sh._check(sh.lib.sh_prox_l1(0, None, None, None, 1.0, None, None), "prox_l1")
+    with pytest.raises(sh.SarahipError):
+        sh.profile_read("no_such_kernel")
+    sh.profile_enable(False)

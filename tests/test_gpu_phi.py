@@ -1,0 +1,164 @@
+"""GPU parity of the measurement operator Phi and its real adjoint against the FP64 oracle NUFFT.
+
+Bar: norm-wise relative error <= 1e-5 for both maps (FP32 operator vs FP64 oracle with the same
+J, alpha and Kaiser-Bessel shape), on ragged sizes, several tiles, heavy tiles split into many
+work items, grid-edge coordinates, single visibilities and one-visibility blocks.
+"""
+import numpy as np
+import pytest
+
+from oracle import measurement
+from paper_1502_05037_amd import synth
+from tests import helpers
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def sh():
+    from paper_1502_05037_amd import sarahip
+    return sarahip
+
+
+def _dev(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
+
+
+def _fwd_adj(sh, uv, n, J, off, x, v):
+    op = sh.op_create(uv, n, 2, J, off)
+    try:
+        vis = torch.empty(len(uv), dtype=torch.complex64, device="cuda")
+        sh.phi_fwd(op, _dev(x, torch.float32), vis)
+        xa = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        sh.phi_adj(op, _dev(v, torch.complex64), xa)
+        torch.cuda.synchronize()
+        return vis.cpu().numpy().astype(np.complex128), xa.cpu().numpy().astype(np.float64), sh.op_query(op)
+    finally:
+        sh.op_destroy(op)
+
+
+def _inputs(n, m, seed):
+    x = synth.sky(n, 20, 3.0, synth.rng(11, seed, synth.SKY)).astype(np.float32).astype(np.float64)
+    v = synth.complex_normal(m, synth.rng(11, seed, synth.NOISE)).astype(np.complex64).astype(np.complex128)
+    return x, v
+
+
+@pytest.mark.parametrize("n,m,J,R,cov", [
+    (64, 2048, 6, 1, "gaussian"),      # config-1 shape
+    (64, 3001, 8, 3, "radial"),        # ragged M, J = 8
+    (32, 777, 6, 2, "gaussian"),
+    (16, 300, 4, 1, "gaussian"),       # smallest image / grid
+    (128, 20000, 10, 5, "radial"),
+    (256, 65536, 6, 8, "gaussian"),    # config-2 image, 1/10 of its visibilities
+])
+def test_phi_parity(sh, n, m, J, R, cov):
+    print(f"phi parity n={n} m={m} J={J} R={R} {cov}", flush=True)
+    g = synth.rng(11, n + m, synth.UV)
+    uv = synth.sort_by_radius(synth.uv_gaussian(m, g) if cov == "gaussian" else synth.uv_radial(m, g))
+    off = synth.offsets(synth.block_sizes(m, R, synth.rng(11, m, synth.BLOCKS))) if R > 1 else [0, m]
+    x, v = _inputs(n, m, n + J)
+    ref = measurement.NUFFT(uv, n, J)
+    vis, xa, q = _fwd_adj(sh, uv, n, J, off, x, v)
+    assert helpers.rel(vis, ref.fwd(x)) <= TOL
+    assert helpers.rel(xa, ref.adj(v)) <= TOL
+
+
+def test_internal_order_and_permutation(sh):
+    n, m, J, R = 64, 5000, 6, 4
+    uv = synth.sort_by_radius(synth.uv_radial(m, synth.rng(12, 0, synth.UV)))
+    off = synth.offsets(synth.block_sizes(m, R, synth.rng(12, 0, synth.BLOCKS)))
+    x, v = _inputs(n, m, 3)
+    op = sh.op_create(uv, n, 2, J, off)
+    try:
+        perm = sh.op_permutation(op)
+        assert np.array_equal(np.sort(perm), np.arange(m))
+        np.testing.assert_array_equal(sh.op_block_offsets(op), off)
+        for b in range(R):   # the permutation stays inside each block
+            seg = perm[off[b]:off[b + 1]]
+            assert seg.min() >= off[b] and seg.max() < off[b + 1]
+        xd = _dev(x, torch.float32)
+        vi = torch.empty(m, dtype=torch.complex64, device="cuda")
+        vu = torch.empty_like(vi)
+        sh.phi_fwd_internal(op, xd, vi)
+        sh.phi_fwd(op, xd, vu)
+        back = torch.empty_like(vi)
+        sh.vis_to_user(op, vi, back)
+        fwd_i = torch.empty_like(vi)
+        sh.vis_to_internal(op, vu, fwd_i)
+        torch.cuda.synchronize()
+        vi_h, vu_h = vi.cpu().numpy(), vu.cpu().numpy()
+        np.testing.assert_array_equal(vi_h, vu_h[perm])
+        np.testing.assert_array_equal(back.cpu().numpy(), vu_h)
+        np.testing.assert_array_equal(fwd_i.cpu().numpy(), vi_h)
+        # adjoint on internal order equals adjoint of the same values in user order
+        vd = _dev(v, torch.complex64)
+        vint = torch.empty_like(vd)
+        sh.vis_to_internal(op, vd, vint)
+        a1 = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        a2 = torch.empty_like(a1)
+        sh.phi_adj(op, vd, a1)
+        sh.phi_adj_internal(op, vint, a2)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(a1.cpu().numpy(), a2.cpu().numpy(), rtol=0, atol=1e-4 * float(a1.abs().max()))
+    finally:
+        sh.op_destroy(op)
+
+
+def test_edges_heavy_tile_single_and_unit_blocks(sh):
+    n, J = 32, 8
+    # grid-edge coordinates, exact zero, values just below +pi
+    edge = np.array([[-np.pi, -np.pi], [np.nextafter(np.pi, 0), 0.3], [0.0, np.nextafter(np.pi, 0)],
+                     [-np.pi + 1e-9, 3.1], [0.0, 0.0], [1e-12, -1e-12]])
+    # 20000 visibilities around kappa = 3 (one tile of the 64-cell grid): the tile is split into
+    # several work items whose patches the fold sums
+    heavy = 0.3 + 0.01 * synth.uv_gaussian(20000, synth.rng(13, 0, synth.UV))
+    uv = np.concatenate([edge, heavy])
+    m = len(uv)
+    off = np.concatenate([np.arange(0, 6), [m]])        # five 1-visibility blocks then one big block
+    x, v = _inputs(n, m, 4)
+    ref = measurement.NUFFT(uv, n, J)
+    vis, xa, q = _fwd_adj(sh, uv, n, J, off, x, v)
+    assert q["max_items_per_tile"] >= 4
+    assert helpers.rel(vis, ref.fwd(x)) <= TOL
+    assert helpers.rel(xa, ref.adj(v)) <= TOL
+    # a single visibility
+    vis1, xa1, _ = _fwd_adj(sh, uv[:1], n, J, [0, 1], x, v[:1])
+    assert helpers.rel(vis1, ref.fwd(x)[:1]) <= TOL
+    assert helpers.rel(xa1, measurement.NUFFT(uv[:1], n, J).adj(v[:1])) <= TOL
+
+
+def test_adjoint_dot_on_gpu(sh):
+    n, m, J = 128, 30000, 8
+    uv = synth.sort_by_radius(synth.uv_radial(m, synth.rng(14, 0, synth.UV)))
+    x, v = _inputs(n, m, 5)
+    x = x - 0.5  # signed image
+    vis, xa, _ = _fwd_adj(sh, uv, n, J, [0, m], x, v)
+    lhs = np.vdot(v, vis).real
+    rhs = np.sum(x * xa)
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(v) * np.linalg.norm(vis)
+
+
+def test_op_norm_matches_oracle(sh):
+    n, m, J = 64, 2048, 6
+    uv = synth.uv_gaussian(m, synth.rng(15, 0, synth.UV))
+    ones = np.ones((n, n))
+    ref = measurement.op_norm(measurement.NUFFT(uv, n, J), ones, max_iter=200, tol=1e-12)
+    op = sh.op_create(uv, n, 2, J, [0, m])
+    try:
+        nu = sh.op_norm(op, _dev(ones, torch.float32), iters=200, tol=1e-12)
+    finally:
+        sh.op_destroy(op)
+    assert nu == pytest.approx(ref, rel=1e-5)
+
+
+def test_determinism_two_runs(sh):
+    n, m, J = 64, 8000, 6
+    uv = synth.uv_radial(m, synth.rng(16, 0, synth.UV))
+    x, v = _inputs(n, m, 6)
+    a = _fwd_adj(sh, uv, n, J, [0, m], x, v)
+    b = _fwd_adj(sh, uv, n, J, [0, m], x, v)
+    np.testing.assert_array_equal(a[0], b[0])          # degridding: fixed summation order
+    np.testing.assert_allclose(a[1], b[1], rtol=0, atol=1e-6 * np.abs(a[1]).max())

@@ -1,0 +1,171 @@
+"""GPU parity of the SDMM / SARA solve against the FP64 oracle.
+
+Fixed schedules (tol_rel = 0) with the same nu, gamma and CG step count on both sides: final image
+within 1e-4 relative (norm-wise).  Runs to tolerance: every block satisfies
+||y_i - Phi_i x|| <= eps_i (1 + 1e-4), re-evaluated with the oracle's FP64 operator.
+"""
+import numpy as np
+import pytest
+
+from oracle import measurement, sdmm, wavelets
+from tests import helpers
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sh():
+    from paper_1502_05037_amd import sarahip
+    return sarahip
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
+
+
+def _gpu_solve(sh, pb, prm, x0=None, W0=None, want_W=False, levels=4, mask=0x1FF):
+    n = pb.n
+    op = sh.op_create(pb.uv, n, 2, pb.J, pb.offsets)
+    psi = sh.psi_create(n, levels, mask)
+    try:
+        q = sh.psi_planes(psi)
+        x = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        Wo = torch.empty((q, n, n), dtype=torch.float32, device="cuda") if want_W else None
+        info, resid = sh.sdmm_solve(op, psi, _dev(pb.y, torch.complex64), pb.eps,
+                                    None if W0 is None else _dev(W0), None if x0 is None else _dev(x0), prm, x, Wo)
+        torch.cuda.synchronize()
+        return x.cpu().numpy().astype(np.float64), info, resid, (None if Wo is None else Wo.cpu().numpy())
+    finally:
+        sh.psi_destroy(psi)
+        sh.op_destroy(op)
+
+
+def _params(sh, **kw):
+    p = sh.sdmm_default_params()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _oracle_setup(pb, levels=4, mask=0x1FF):
+    psi = wavelets.SARA(pb.n, levels, mask)
+    nu = measurement.op_norm(pb.op, np.ones((pb.n, pb.n)), max_iter=200, tol=1e-12)
+    gamma = sdmm.default_gamma(pb.op, psi, pb.y, nu)
+    return psi, nu, gamma
+
+
+def test_config1_fixed_schedule_parity(sh):
+    pb = helpers.build(1, 64, 2048, 1, 6)
+    psi, nu, gamma = _oracle_setup(pb)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=300, cg_iters=8)
+    x_ref, _, infos, _ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
+    x, info, resid, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=300, cg_iters=8))
+    assert info["iters_total"] == 300
+    err = helpers.rel(x, x_ref)
+    print(f"config-1 image error vs oracle: {err:.3e}")
+    assert err <= 1e-4
+    np.testing.assert_allclose(resid, infos[0].block_resid, rtol=1e-4)
+    assert info["objective"] == pytest.approx(infos[0].objective, rel=1e-4)
+
+
+def test_reweighted_passes_parity_and_weights(sh):
+    pb = helpers.build(2, 32, 1200, 3, 6, coverage="radial", prob=1)
+    psi, nu, gamma = _oracle_setup(pb)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=3)
+    x_ref, W_last, infos, st = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
+    x, info, resid, Wo = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=3),
+                                    want_W=True)
+    assert info["passes_done"] == 3 and info["iters_total"] == 120
+    assert helpers.rel(x, x_ref) <= 1e-4
+    # W_out: the weights a fourth pass would use: delta_3 = beta^2 delta_1 from the final image
+    c1 = psi.adj(sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps,
+                           sdmm.Params(gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=1))[0])
+    delta = 0.25 * np.std(c1)
+    assert info["delta"] == pytest.approx(delta, rel=1e-4)
+    W_ref = sdmm.reweight(psi.adj(x_ref), delta)
+    assert helpers.rel(Wo, W_ref) <= 1e-4
+
+
+def test_warm_start_parity(sh):
+    pb = helpers.build(3, 32, 900, 2, 8, prob=2)
+    psi, nu, gamma = _oracle_setup(pb)
+    x0 = 0.9 * pb.x_true
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=60, cg_iters=8)
+    x_ref, *_ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p, x0=x0)
+    x, info, _, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=60, cg_iters=8), x0=x0)
+    assert helpers.rel(x, x_ref) <= 1e-4
+
+
+def test_run_to_tolerance_is_feasible(sh):
+    pb = helpers.build(4, 64, 4096, 4, 6, prob=3)
+    prm = _params(sh, max_iter=3000, tol_rel=1e-4, check_every=1, passes=2)
+    x, info, resid, _ = _gpu_solve(sh, pb, prm)
+    assert info["converged"] == 1
+    assert info["rel_change"] <= 1e-4
+    # independent re-evaluation of the constraints with the oracle's FP64 operator
+    v = pb.op.fwd(x)
+    for i in range(len(pb.eps)):
+        lo, hi = pb.offsets[i], pb.offsets[i + 1]
+        r = np.linalg.norm(pb.y[lo:hi] - v[lo:hi])
+        assert r <= pb.eps[i] * (1 + 1e-4), (i, r, pb.eps[i])
+    assert x.min() >= -1e-3 * x.max()
+
+
+def test_solver_argument_errors(sh):
+    pb = helpers.build(5, 32, 500, 2, 6)
+    bad = pb.eps.copy()
+    bad[1] = 0.0
+    op = sh.op_create(pb.uv, 32, 2, 6, pb.offsets)
+    psi = sh.psi_create(32, 4)
+    try:
+        x = torch.empty((32, 32), device="cuda")
+        y = _dev(pb.y, torch.complex64)
+        with pytest.raises(sh.SarahipError) as e:
+            sh.sdmm_solve(op, psi, y, bad, None, None, _params(sh), x)
+        assert e.value.status == -1
+        bad[1] = np.nan
+        with pytest.raises(sh.SarahipError) as e:
+            sh.sdmm_solve(op, psi, y, bad, None, None, _params(sh), x)
+        assert e.value.status == -4
+        ynan = y.clone()
+        ynan[3] = complex(float("nan"), 0.0)
+        with pytest.raises(sh.SarahipError) as e:
+            sh.sdmm_solve(op, psi, ynan, pb.eps, None, None, _params(sh), x)
+        assert e.value.status == -4
+        psi64 = sh.psi_create(64, 4)
+        with pytest.raises(sh.SarahipError) as e:
+            sh.sdmm_solve(op, psi64, y, pb.eps, None, None, _params(sh), x)
+        sh.psi_destroy(psi64)
+    finally:
+        sh.psi_destroy(psi)
+        sh.op_destroy(op)
+
+
+def test_session_split_equals_single_run(sh):
+    """Iterating 150 + 150 through the session API reproduces 300 iterations of one solve.
+
+    Gridding accumulates in LDS with atomic adds, so the summation order inside a patch (and with
+    it the last bits) can differ between runs; the bar is FP32-rounding level agreement."""
+    pb = helpers.build(6, 64, 3000, 3, 6, prob=4)
+    p = _params(sh, max_iter=300, cg_iters=8)
+    op = sh.op_create(pb.uv, 64, 2, 6, pb.offsets)
+    psi = sh.psi_create(64, 4)
+    try:
+        y = _dev(pb.y, torch.complex64)
+        x1 = torch.empty((64, 64), device="cuda")
+        info, r1 = sh.sdmm_solve(op, psi, y, pb.eps, None, None, p, x1)
+        p.nu, p.gamma = info["nu"], info["gamma"]
+        s = sh.sdmm_create(op, psi, y, pb.eps, None, None, p)
+        try:
+            sh.sdmm_iterate(s, 150)
+            sh.sdmm_iterate(s, 150)
+            x2 = torch.empty_like(x1)
+            r2, rel = sh.sdmm_result(s, x2, 3)
+        finally:
+            sh.sdmm_destroy(s)
+    finally:
+        sh.psi_destroy(psi)
+        sh.op_destroy(op)
+    assert helpers.rel(x2.cpu().numpy(), x1.cpu().numpy()) <= 1e-5
+    np.testing.assert_allclose(r2, r1, rtol=1e-5)
