@@ -68,6 +68,11 @@ const char* sh_version(void);
  * Synchronous.  Errors: SH_EINVAL (range, sizes, offsets), SH_ENOMEM. */
 sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
                        const int64_t* block_offsets, int32_t R, sh_op* out);
+/* Same plan with explicit tiling (the autotuner's knobs): tile side T in {8, 16, 32} cells
+ * (0 = automatic: 16, or alpha*n/4 when smaller) and the most visibilities per work item, 64..2^20 (0 = 4096).  The grid
+ * side alpha*n must hold at least 3 tiles.  Results agree with sh_op_create to rounding. */
+sh_status sh_op_create_tuned(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
+                             const int64_t* block_offsets, int32_t R, int32_t tile, int32_t chunk, sh_op* out);
 sh_status sh_op_destroy(sh_op op);
 
 /* Query plan sizes: out[0]=M, out[1]=n, out[2]=grid side K, out[3]=J, out[4]=R,

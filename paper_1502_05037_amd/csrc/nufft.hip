@@ -34,7 +34,7 @@
 
 namespace {
 
-constexpr int GRID_CHUNK = 4096;   // visibilities per gridding work item
+constexpr int GRID_CHUNK = 4096;   // default visibilities per work item
 constexpr int BALL_CHUNK = 8192;   // visibilities per reduction chunk
 constexpr int RUN_MIN = 6;         // mean visibilities per cell of a dense work item
 
@@ -43,6 +43,15 @@ __device__ __forceinline__ float kb_eval(const float* c, float s) {
 #pragma unroll
   for (int i = KB_DEG - 1; i >= 0; --i) acc = fmaf(acc, s, c[i]);
   return acc;
+}
+
+// Orders this lane's LDS accesses around a point where lanes of one wave hand data to each other
+// through LDS: the compiler reasons per lane and could otherwise move a read of one address above a
+// write that another lane makes to it.  One wave's LDS operations execute in program order, so a
+// compiler barrier is enough.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
 }
 
 // Work items cover one tile's visibilities (gridding order: tile, then cell).  Each of the 256
@@ -78,11 +87,20 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
   const int F = 32 - log2K;
   const uint32_t fmask = (F == 32) ? 0xffffffffu : ((1u << F) - 1u);
   const float fs = ldexpf(1.0f, 1 - F);
-  int lo, hi;
-  item_range(it, tid, lo, hi);
+  // dense items: a contiguous sub-range per thread (runs of one cell); sparse items: interleaved
+  // visibilities so that the coordinate loads and visibility stores coalesce
+  int lo, hi, step;
+  if constexpr (RUNS) {
+    item_range(it, tid, lo, hi);
+    step = 1;
+  } else {
+    lo = it.y + tid;
+    hi = it.y + it.z;
+    step = 256;
+  }
   float2 cache[RUNS ? J : 1][RUNS ? J : 1];
   int cur = -1;
-  for (int j = lo; j < hi; ++j) {
+  for (int j = lo; j < hi; j += step) {
     const uint2 c = coord[j];
     const int lr = int(c.x >> F) - a0, lc = int(c.y >> F) - b0;
     const float s1 = float(c.x & fmask) * fs - 1.0f;
@@ -133,6 +151,14 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
 }
 
 // Gridding of one work item into a private padded patch, written to patches[item slot].
+// Wave w owns the w-th quarter of the item and its own copy of the patch.  It walks its
+// visibilities in batches of 64: phase A (one lane per visibility) writes the 2J weights and
+// (scale v, cell) to the wave's LDS rows; phase B (one lane per tap) accumulates in registers
+// while the cell stays the same.  A finished run is added into the wave's patch copy with a plain
+// read-modify-write (64 lanes, 64 distinct addresses, no other wave on this copy) whose write is
+// deferred to the next cell change, so the read has landed by then; the wave's cells are
+// non-decreasing, so no later read needs a deferred value.  LDS float atomics would avoid the
+// read but measure several times slower here.  Every sum has a fixed order.
 template <int J, int T>
 __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ vis,
                                                    const uint32_t* __restrict__ vidx, const int4* __restrict__ items,
@@ -141,36 +167,40 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   constexpr int P = T + J - 1;
   constexpr int PP = P * P;
   constexpr int NQ = (J * J + 63) / 64;   // taps per lane
-  constexpr int B = 256;                  // visibilities per batch (one per thread in phase A)
+  constexpr int WS = 2 * J + 1;           // weight row stride (odd: fewer bank conflicts)
   __shared__ float2 pat[4][PP];           // one patch copy per wave
-  __shared__ float wt[B][2 * J + 1];      // w1[0..J), w2[J..2J) per visibility
-  __shared__ float4 vc[B];                // (scale v.x, scale v.y, tap-(0,0) patch offset, -)
+  __shared__ float wt[4][64][WS];         // per wave: w1[0..J), w2[J..2J) of its current 64 visibilities
+  __shared__ float4 vc[4][64];            // per wave: (scale v.x, scale v.y, tap-(0,0) patch offset, -)
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   for (int e = tid; e < 4 * PP; e += 256) (&pat[0][0])[e] = make_float2(0.f, 0.f);
+  __syncthreads();
   const int4 it = items[blockIdx.x];
   const int nT = 1 << (log2K - log2T);
   const int a0 = (it.x / nT) * T, b0 = (it.x % nT) * T;
   const int F = 32 - log2K;
   const uint32_t fmask = (F == 32) ? 0xffffffffu : ((1u << F) - 1u);
   const float fs = ldexpf(1.0f, 1 - F);
-  int toff[NQ];                            // patch offset of this lane's taps relative to tap (0, 0)
+  int toff[NQ], tr[NQ], tc[NQ];            // this lane's taps: patch offset from tap (0, 0), row, column
   bool tval[NQ];
-  float2 acc[NQ];
+  float2 acc[NQ], pend_val[NQ], pend_old[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int t = q * 64 + lane;
     tval[q] = t < J * J;
-    toff[q] = tval[q] ? (t / J) * P + (t % J) : 0;
-    acc[q] = make_float2(0.f, 0.f);
+    tr[q] = tval[q] ? t / J : 0;              // lanes past the last tap read tap (0, 0) and add zero
+    tc[q] = tval[q] ? t % J : 0;
+    toff[q] = tr[q] * P + tc[q];
+    acc[q] = pend_val[q] = pend_old[q] = make_float2(0.f, 0.f);
   }
-  int cur = -1;
-  const int end = it.y + it.z;
-  for (int base = it.y; base < end; base += B) {
-    const int nb = min(B, end - base);
-    __syncthreads();   // previous batch consumed (and the patches zeroed)
-    if (tid < nb) {
-      const int j = base + tid;
+  float2* mypat = pat[wave];
+  int cur = -1, pend = -1;                  // patch offset of tap (0, 0): current run, deferred run
+  const int w_lo = it.y + int((int64_t)it.z * wave / 4);
+  const int w_hi = it.y + int((int64_t)it.z * (wave + 1) / 4);
+  for (int base = w_lo; base < w_hi; base += 64) {
+    const int nb = min(64, w_hi - base);
+    if (lane < nb) {                        // phase A
+      const int j = base + lane;
       const uint2 c = coord[j];
       const float2 v = vis[vidx ? vidx[j] : j];
       const int lr = int(c.x >> F) - a0, lc = int(c.y >> F) - b0;
@@ -178,45 +208,69 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
       const float s2 = float(c.y & fmask) * fs - 1.0f;
 #pragma unroll
       for (int t = 0; t < J; ++t) {
-        wt[tid][t] = kb_eval(kc.c[t], s1);
-        wt[tid][J + t] = kb_eval(kc.c[t], s2);
+        wt[wave][lane][t] = kb_eval(kc.c[t], s1);
+        wt[wave][lane][J + t] = kb_eval(kc.c[t], s2);
       }
-      vc[tid] = make_float4(v.x * scale, v.y * scale, __int_as_float(lr * P + lc), 0.f);
+      vc[wave][lane] = make_float4(v.x * scale, v.y * scale, __int_as_float(lr * P + lc), 0.f);
     }
-    __syncthreads();
-    const int k1 = min(nb, wave * 64 + 64);
-    for (int k = wave * 64; k < k1; ++k) {
-      const float4 q4 = vc[k];
-      const int cell = __float_as_int(q4.z);   // the same for every lane of the wave
-      if (cell != cur) {
-        if (cur >= 0) {
+    wave_lds_order();                       // phase A rows visible to every lane
+    for (int k = 0; k < nb; k += 8) {       // phase B, eight visibilities per step
+      float4 q4[8];
+      float wa[NQ][8], wb[NQ][8];
 #pragma unroll
-          for (int q = 0; q < NQ; ++q)
-            if (tval[q]) {
-              float2& d = pat[wave][cur + toff[q]];
-              d.x += acc[q].x;
-              d.y += acc[q].y;
+      for (int u = 0; u < 8; ++u) {
+        q4[u] = vc[wave][k + u];            // k + u < 64: in bounds; rows past nb are never used
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          wa[q][u] = wt[wave][k + u][tr[q]];
+          wb[q][u] = wt[wave][k + u][J + tc[q]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (k + u >= nb) break;
+        const int cell = __builtin_amdgcn_readfirstlane(__float_as_int(q4[u].z));
+        if (cell != cur) {
+          if (pend >= 0) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+              if (tval[q])                  // lanes without a tap must not touch the patch
+                mypat[pend + toff[q]] = make_float2(pend_old[q].x + pend_val[q].x, pend_old[q].y + pend_val[q].y);
+            wave_lds_order();               // another lane's next read may hit an address just written
+          }
+          pend = cur;
+          if (cur >= 0) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              if (tval[q]) pend_old[q] = mypat[cur + toff[q]];
+              pend_val[q] = acc[q];
               acc[q] = make_float2(0.f, 0.f);
             }
+          }
+          cur = cell;
         }
-        cur = cell;
-      }
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int t = q * 64 + lane;
-        if (tval[q]) {
-          const float w = wt[k][t / J] * wt[k][J + t % J];
-          acc[q].x = fmaf(w, q4.x, acc[q].x);
-          acc[q].y = fmaf(w, q4.y, acc[q].y);
+        for (int q = 0; q < NQ; ++q) {
+          const float w = tval[q] ? wa[q][u] * wb[q][u] : 0.f;
+          acc[q].x = fmaf(w, q4[u].x, acc[q].x);
+          acc[q].y = fmaf(w, q4[u].y, acc[q].y);
         }
       }
     }
+    wave_lds_order();                       // rows of this batch consumed before the next phase A
+  }
+  if (pend >= 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (tval[q])
+        mypat[pend + toff[q]] = make_float2(pend_old[q].x + pend_val[q].x, pend_old[q].y + pend_val[q].y);
+    wave_lds_order();
   }
   if (cur >= 0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
       if (tval[q]) {
-        float2& d = pat[wave][cur + toff[q]];
+        float2& d = mypat[cur + toff[q]];
         d.x += acc[q].x;
         d.y += acc[q].y;
       }
@@ -230,39 +284,40 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
 }
 
 // Each grid cell = sum over the tiles whose padded patch covers it (3 x 3 neighbourhood, fixed order)
-// of that tile's item patches (item order).  One work-group per tile.
+// of that tile's item patches (slot order).  One work-group per group of 256 cells of a tile.
 template <int J, int T>
 __global__ __launch_bounds__(256) void fold_kernel(const float2* __restrict__ patches, const int* __restrict__ tile_items,
                                                    float2* __restrict__ grid, int log2K, int log2T) {
   constexpr int P = T + J - 1;
   constexpr int LO = J / 2 - 1;
+  constexpr int G = (T * T + 255) / 256;   // work-groups per tile
   const int nT = 1 << (log2K - log2T);
   const int K = 1 << log2K;
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x / G;
+  const int e = (blockIdx.x % G) * 256 + threadIdx.x;
+  if (e >= T * T) return;
   const int a = tile / nT, b = tile % nT;
-  for (int e = threadIdx.x; e < T * T; e += 256) {
-    const int l1 = e / T, l2 = e % T;
-    float sr = 0.f, si = 0.f;
+  const int l1 = e / T, l2 = e % T;
+  float sr = 0.f, si = 0.f;
 #pragma unroll
-    for (int da = -1; da <= 1; ++da) {
-      const int p1 = l1 - da * T + LO;
-      if (p1 < 0 || p1 >= P) continue;
-      const int a2 = (a + da + nT) % nT;
+  for (int da = -1; da <= 1; ++da) {
+    const int p1 = l1 - da * T + LO;
+    if (p1 < 0 || p1 >= P) continue;
+    const int a2 = (a + da + nT) % nT;
 #pragma unroll
-      for (int db = -1; db <= 1; ++db) {
-        const int p2 = l2 - db * T + LO;
-        if (p2 < 0 || p2 >= P) continue;
-        const int t2 = a2 * nT + (b + db + nT) % nT;
-        const int i0 = tile_items[t2], i1 = tile_items[t2 + 1];
-        for (int i = i0; i < i1; ++i) {
-          const float2 v = patches[(size_t)i * (P * P) + p1 * P + p2];
-          sr += v.x;
-          si += v.y;
-        }
+    for (int db = -1; db <= 1; ++db) {
+      const int p2 = l2 - db * T + LO;
+      if (p2 < 0 || p2 >= P) continue;
+      const int t2 = a2 * nT + (b + db + nT) % nT;
+      const int i0 = tile_items[t2], i1 = tile_items[t2 + 1];
+      for (int i = i0; i < i1; ++i) {
+        const float2 v = patches[(size_t)i * (P * P) + p1 * P + p2];
+        sr += v.x;
+        si += v.y;
       }
     }
-    grid[(size_t)(a * T + l1) * K + (b * T + l2)] = make_float2(sr, si);
   }
+  grid[(size_t)(a * T + l1) * K + (b * T + l2)] = make_float2(sr, si);
 }
 
 __global__ void gather_kernel(const float2* __restrict__ src, const uint32_t* __restrict__ idx, float2* __restrict__ dst,
@@ -310,7 +365,8 @@ sh_status launch_grid_T(sh_op op, const float2* vis, const uint32_t* vidx, float
     SH_LAUNCHED();
   }
   sh::ProfScope ps("fold", st);
-  hipLaunchKernelGGL((fold_kernel<J, T>), dim3((unsigned)(op->nT * op->nT)), dim3(256), 0, st, op->patches.ptr,
+  constexpr int G = (T * T + 255) / 256;
+  hipLaunchKernelGGL((fold_kernel<J, T>), dim3((unsigned)(op->nT * op->nT * G)), dim3(256), 0, st, op->patches.ptr,
                      op->tile_items.ptr, op->grid.ptr, op->log2K, op->log2T);
   SH_LAUNCHED();
   return SH_OK;
@@ -413,7 +469,7 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
     int64_t e = i;
     const int64_t bend = offs[std::upper_bound(offs, offs + op->R + 1, i) - offs];
     while (e < bend && (key[perm[e]] >> (2 * log2T)) == k0) ++e;
-    const int64_t c = e - i, nck = sh::cdiv(c, GRID_CHUNK);
+    const int64_t c = e - i, nck = sh::cdiv(c, op->chunk);
     for (int64_t k = 0; k < nck; ++k) {
       const int64_t a = i + c * k / nck, b = i + c * (k + 1) / nck;
       int64_t cells = 0;
@@ -475,8 +531,8 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
 
 extern "C" {
 
-sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
-                       const int64_t* block_offsets, int32_t R, sh_op* out) {
+sh_status sh_op_create_tuned(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
+                             const int64_t* block_offsets, int32_t R, int32_t tile, int32_t chunk, sh_op* out) {
   SH_REQUIRE(out != nullptr, "out is NULL");
   *out = nullptr;
   SH_REQUIRE(uv != nullptr && block_offsets != nullptr, "uv and block_offsets must be non-NULL");
@@ -494,6 +550,11 @@ sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversampl
                (long long)m, uv[m]);
   const int K = n * oversample;
   SH_REQUIRE(K <= 8192, "grid side alpha*n must be <= 8192");
+  SH_REQUIRE(tile == 0 || tile == 8 || tile == 16 || tile == 32, "tile must be 0 (auto), 8, 16 or 32");
+  SH_REQUIRE(chunk == 0 || (chunk >= 64 && chunk <= (1 << 20)), "chunk must be 0 (auto) or in [64, 2^20]");
+  int T = tile ? tile : std::min(16, K / 4);
+  while (T < kernel_width / 2) T *= 2;
+  SH_REQUIRE(K / T >= 3, "grid side %d needs at least 3 tiles of %d cells", K, T);
   sh_op op = new (std::nothrow) sh_op_s();
   if (!op) {
     sh::set_error("host allocation failed");
@@ -506,8 +567,8 @@ sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversampl
   op->log2K = sh::ilog2(K);
   op->J = kernel_width;
   op->R = R;
-  op->T = std::min(32, K / 4);
-  while (op->T < kernel_width / 2) op->T *= 2;
+  op->T = T;
+  op->chunk = chunk ? chunk : GRID_CHUNK;
   op->log2T = sh::ilog2(op->T);
   op->nT = K / op->T;
   op->beta = sh::kb_beta(kernel_width, oversample);
@@ -523,6 +584,11 @@ sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversampl
   }
   *out = op;
   return SH_OK;
+}
+
+sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
+                       const int64_t* block_offsets, int32_t R, sh_op* out) {
+  return sh_op_create_tuned(uv, M, n, oversample, kernel_width, block_offsets, R, 0, 0, out);
 }
 
 sh_status sh_op_destroy(sh_op op) {

@@ -14,6 +14,7 @@ struct sh_op_s {
   int64_t M = 0;
   int n = 0, K = 0, log2K = 0, J = 0, alpha = 0, R = 0;
   int T = 0, log2T = 0, nT = 0;   // gridding tile side, tiles per grid side
+  int chunk = 0;                   // most visibilities per work item
   double beta = 0;
   KBCoef kb{};
   std::vector<int64_t> offsets;    // block offsets (internal == user)

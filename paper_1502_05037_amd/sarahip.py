@@ -53,6 +53,7 @@ _SIGS = {
     "sh_last_error": (C.c_char_p, []),
     "sh_version": (C.c_char_p, []),
     "sh_op_create": (C.c_int, [_P64, _i64, _i32, _i32, _i32, _PI64, _i32, C.POINTER(_vp)]),
+    "sh_op_create_tuned": (C.c_int, [_P64, _i64, _i32, _i32, _i32, _PI64, _i32, _i32, _i32, C.POINTER(_vp)]),
     "sh_op_destroy": (C.c_int, [_vp]),
     "sh_op_query": (C.c_int, [_vp, _PI64]),
     "sh_op_block_offsets": (C.c_int, [_vp, _PI64]),
@@ -132,6 +133,18 @@ def op_create(uv: np.ndarray, n: int, oversample: int, kernel_width: int, block_
     h = _vp()
     _check(lib.sh_op_create(uv.ctypes.data_as(_P64), uv.shape[0], n, oversample, kernel_width,
                             off.ctypes.data_as(_PI64), len(off) - 1, C.byref(h)), "op_create")
+    return h.value
+
+
+def op_create_tuned(uv: np.ndarray, n: int, oversample: int, kernel_width: int, block_offsets, tile: int = 0,
+                    chunk: int = 0) -> int:
+    uv = _f64(uv)
+    if uv.ndim != 2 or uv.shape[1] != 2:
+        raise ValueError("uv must be (M, 2)")
+    off = np.ascontiguousarray(block_offsets, dtype=np.int64)
+    h = _vp()
+    _check(lib.sh_op_create_tuned(uv.ctypes.data_as(_P64), uv.shape[0], n, oversample, kernel_width,
+                                  off.ctypes.data_as(_PI64), len(off) - 1, tile, chunk, C.byref(h)), "op_create_tuned")
     return h.value
 
 

@@ -70,3 +70,11 @@ def test_prox_and_profile_argument_checks():
     with pytest.raises(sh.SarahipError):
         sh.profile_read("no_such_kernel")
     sh.profile_enable(False)
+
+
+def test_op_create_tuned_rejects_bad_tiling():
+    uv = np.zeros((4, 2))
+    for tile, chunk in ((12, 0), (0, 10), (32, 0)):   # bad tile; chunk too small; 3 tiles of 32 do not fit K = 32
+        with pytest.raises(sh.SarahipError) as e:
+            sh.op_create_tuned(uv, 16, 2, 6, [0, 4], tile=tile, chunk=chunk)
+        assert e.value.status == -1

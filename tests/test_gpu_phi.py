@@ -162,3 +162,25 @@ def test_determinism_two_runs(sh):
     b = _fwd_adj(sh, uv, n, J, [0, m], x, v)
     np.testing.assert_array_equal(a[0], b[0])          # degridding: fixed summation order
     np.testing.assert_allclose(a[1], b[1], rtol=0, atol=1e-6 * np.abs(a[1]).max())
+
+
+@pytest.mark.parametrize("tile,chunk", [(8, 64), (16, 300), (32, 0), (16, 0)])
+def test_phi_parity_tuned_tiling(sh, tile, chunk):
+    """Every tiling the autotuner may pick gives the same operator (small chunks force many items)."""
+    n, m, J, R = 64, 6000, 8, 3
+    uv = synth.sort_by_radius(synth.uv_radial(m, synth.rng(17, tile, synth.UV)))
+    off = synth.offsets(synth.block_sizes(m, R, synth.rng(17, tile, synth.BLOCKS)))
+    x, v = _inputs(n, m, tile)
+    ref = measurement.NUFFT(uv, n, J)
+    op = sh.op_create_tuned(uv, n, 2, J, off, tile=tile, chunk=chunk)
+    try:
+        vis = torch.empty(m, dtype=torch.complex64, device="cuda")
+        sh.phi_fwd(op, _dev(x, torch.float32), vis)
+        xa = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        sh.phi_adj(op, _dev(v, torch.complex64), xa)
+        torch.cuda.synchronize()
+        assert sh.op_query(op)["tile"] == tile
+    finally:
+        sh.op_destroy(op)
+    assert helpers.rel(vis.cpu().numpy(), ref.fwd(x)) <= TOL
+    assert helpers.rel(xa.cpu().numpy(), ref.adj(v)) <= TOL

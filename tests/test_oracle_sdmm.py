@@ -9,6 +9,8 @@
 * KKT residuals of SDMM's own state vanish at convergence.
 * Reweighting invariants.
 """
+import os
+
 import numpy as np
 import pytest
 import scipy.optimize
@@ -69,10 +71,10 @@ def test_trivial_case_zero_solution():
     assert np.linalg.norm(x) <= 1e-6 * np.linalg.norm(x_true)
 
 
-def _tiny_problem(R=2, n=8, m=128, seed=3):
+def _tiny_problem(R=2, n=8, m=128, seed=3, levels=3, mask=wavelets.SARA_MASK):
     uv = synth.sort_by_radius(synth.uv_gaussian(m, synth.rng(96, seed, synth.UV)))
     op = measurement.DFT(uv, n)
-    psi = wavelets.SARA(n, 3)
+    psi = wavelets.SARA(n, levels, mask)
     x_true = synth.sky(n, 4, 2.0, synth.rng(96, seed, synth.SKY))
     clean = op.fwd(x_true)
     sigma = problem.noise_sigma(clean, 30.0)
@@ -122,22 +124,57 @@ def _brute_force(op, psi, y, off, eps, W):
     return x, float(np.sum(np.abs(WP @ res.x[:N])))
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("R", [1, 2])
-def test_sdmm_matches_brute_force(R):
-    op, psi, y, off, eps = _tiny_problem(R=R)
+def _brute_force_slsqp(op, psi, y, off, eps, W):
+    """The same program as _brute_force, solved by SLSQP (fast for a few hundred unknowns)."""
+    n = psi.n
+    N, D = n * n, psi.D
+    P = W.ravel()[:, None] * np.stack([psi.adj(e.reshape(n, n)).ravel() for e in np.eye(N)], axis=1)
+    F = np.stack([op.fwd(e.reshape(n, n)) for e in np.eye(N)], axis=1)
+    I_D = np.eye(D)
+    cons = [{"type": "ineq", "fun": lambda z: np.concatenate([z[N:] - P @ z[:N], z[N:] + P @ z[:N]]),
+             "jac": lambda z: np.block([[-P, I_D], [P, I_D]])}]
+    for i in range(len(eps)):
+        Fi, yi = F[off[i]:off[i + 1]], y[off[i]:off[i + 1]]
+        cons.append({"type": "ineq",
+                     "fun": lambda z, Fi=Fi, yi=yi, e=eps[i]: np.array([e ** 2 - np.sum(np.abs(yi - Fi @ z[:N]) ** 2)]),
+                     "jac": lambda z, Fi=Fi, yi=yi: np.concatenate([2 * (Fi.conj().T @ (yi - Fi @ z[:N])).real,
+                                                                    np.zeros(D)])[None, :]})
+    c = np.concatenate([np.zeros(N), np.ones(D)])
+    z0 = np.concatenate([np.full(N, 0.1), np.abs(P @ np.full(N, 0.1)) + 1.0])
+    res = scipy.optimize.minimize(lambda z: c @ z, z0, jac=lambda z: c, method="SLSQP", constraints=cons,
+                                  bounds=[(0, None)] * N + [(None, None)] * D,
+                                  options={"maxiter": 2000, "ftol": 1e-14})
+    return res.x[:N].reshape(n, n), float(np.sum(np.abs(P @ res.x[:N])))
+
+
+def _check_against_brute_force(R, levels, mask, m, solver=None):
+    op, psi, y, off, eps = _tiny_problem(R=R, m=m, levels=levels, mask=mask)
     nu = measurement.op_norm(op, np.ones((psi.n, psi.n)), max_iter=5000, tol=0.0)
     gamma = sdmm.default_gamma(op, psi, y, nu)
-    W = np.ones((9, psi.n, psi.n))
+    W = np.ones((psi.q, psi.n, psi.n))
     p = sdmm.Params(gamma=gamma, nu=nu, max_iter=20000, tol_rel=1e-11, eps_slack=1e-9)
     x, _, infos, st = sdmm.sara(op, psi, y, off, eps, p)
-    x_bf, obj_bf = _brute_force(op, psi, y, off, eps, W)
+    x_bf, obj_bf = (solver or _brute_force)(op, psi, y, off, eps, W)
     obj = np.sum(np.abs(psi.adj(x)))
     assert obj == pytest.approx(obj_bf, rel=2e-5)
     assert np.all(infos[0].block_resid <= eps * (1 + 1e-6))
     assert np.min(x) >= -1e-6 * np.max(x)
     # the minimiser is unique here in practice: compare images loosely as well
     assert np.linalg.norm(x - x_bf) / np.linalg.norm(x_bf) <= 1e-3
+
+
+@pytest.mark.parametrize("R", [1, 2])
+def test_sdmm_matches_brute_force_small_dictionary(R):
+    # Dirac + db2 + db4, two levels: 256 unknowns for the constrained solver
+    _check_against_brute_force(R, 2, 0b10101, 96, solver=_brute_force_slsqp)
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(not os.environ.get("SARAHIP_SLOW"), reason="10 min per case; set SARAHIP_SLOW=1")
+@pytest.mark.parametrize("R", [1, 2])
+def test_sdmm_matches_brute_force(R):
+    # the full SARA dictionary (9 planes, three levels): 640 unknowns
+    _check_against_brute_force(R, 3, wavelets.SARA_MASK, 128)
 
 
 def test_kkt_residuals_vanish_at_convergence():
