@@ -49,6 +49,19 @@ def setup_workload(n=1024, m=20_000_000, R=64, J=8, n_points=200, dr=4.0, snr=30
     return dict(n=n, m=m, R=R, J=J, snr=snr, uv=uv, sizes=sizes, off=off, x_true=x_true, draws=draws)
 
 
+def measured_traffic(kernel_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if taken on this kernel source."""
+    import hashlib
+    try:
+        d = json.load(open(os.path.join(ROOT, "profiles", "grid_kernel_traffic.json")))
+        src = open(os.path.join(ROOT, d["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if d.get("kernel", "").split("<")[0] != kernel_name + "_kernel" or hashlib.sha256(src).hexdigest() != d["source_sha256"]:
+        return None
+    return d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
+
+
 def cpu_baseline(wl, sample=1_000_000):
     """FP64 oracle Phi + Phi^dagger on every (M/sample)-th visibility of the workload."""
     from oracle import measurement
@@ -74,6 +87,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tol", action="store_true")
     ap.add_argument("--m", type=int, default=20_000_000)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run three plain device copies of this many MiB (HBM counter calibration)")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -169,7 +184,7 @@ def main():
     t_dom = kern[dom]["avg_ms"] * 1e-3
     achieved = flop_per_vis * m / t_dom / 1e12
     roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom),
             "flop_per_launch": flop_per_vis * m, "avg_launch_ms": round(kern[dom]["avg_ms"], 4),
             "hbm_alg_bytes_per_launch": alg_bytes,
             "hbm_achieved_GBs": round(alg_bytes / t_dom / 1e9, 1), "hbm_peak_GBs": HBM_PEAK_GBS,
@@ -193,6 +208,14 @@ def main():
                "max_resid_over_eps": float(np.max(res / eps)), "tol_rel": 1e-4,
                "warm_seconds": None, "warm_iters": None}
         log(f"[bench] time-to-tol {tol}")
+
+    if a.copy_mb:
+        src = torch.ones(a.copy_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copies: 3 x {a.copy_mb} MiB")
 
     cpu = None if a.no_cpu else cpu_baseline(wl)
     sh.psi_destroy(psi)

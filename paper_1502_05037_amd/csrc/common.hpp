@@ -97,6 +97,29 @@ struct ProfScope {
 
 }  // namespace sh
 
+// Work-groups are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8), and each XCD has its own
+// L2.  This maps the hardware block index to a logical one so that every XCD works on one contiguous
+// range of logical blocks: neighbouring work (adjacent FFT columns, neighbouring tiles) then shares an
+// L2 instead of being fetched once per XCD.  A bijection on [0, nblocks).
+__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+  const int per = nblocks >> 3, rem = nblocks & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+// The same idea for uneven work (gridding items): consecutive runs of G logical blocks go to one XCD,
+// and the runs rotate over the XCDs, so neighbours share an L2 while heavy and light regions still
+// spread over all XCDs.  A bijection on [0, nblocks).
+__device__ __forceinline__ int xcd_block_runs(int bid, int nblocks, int G) {
+  const int span = 8 * G;
+  const int base = (bid / span) * span, b = bid - base;
+  const int r = nblocks - base < span ? nblocks - base : span;   // blocks in this group
+  const int x = b & 7, j = b >> 3;
+  int start = 0;
+  for (int y = 0; y < x; ++y) start += (r - y + 7) >> 3;          // blocks of XCDs 0..x-1 in the group
+  return base + start + j;
+}
+
 // Device-side complex helpers.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }

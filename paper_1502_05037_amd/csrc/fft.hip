@@ -112,7 +112,7 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
   constexpr bool INV = (MODE == COLS_ADJ || MODE == ROWS_ADJ);
   constexpr int NT = B * L / 8;
   const int tid = threadIdx.x;
-  const int seq0 = blockIdx.x * B;    // first row (row modes) or column (column modes)
+  const int seq0 = xcd_block(blockIdx.x, gridDim.x) * B;   // first row (row modes) or column (column modes)
   const int half = n / 2;
   const int K = L;                    // grid side
 

@@ -37,6 +37,7 @@ namespace {
 constexpr int GRID_CHUNK = 4096;   // default visibilities per work item
 constexpr int BALL_CHUNK = 8192;   // visibilities per reduction chunk
 constexpr int RUN_MIN = 6;         // mean visibilities per cell of a dense work item
+constexpr int DEGRID_STAGE = 4096; // outputs a dense degridding work-group stages in LDS (= default chunk)
 
 __device__ __forceinline__ float kb_eval(const float* c, float s) {
   float acc = c[KB_DEG];
@@ -48,11 +49,8 @@ __device__ __forceinline__ float kb_eval(const float* c, float s) {
 // Orders this lane's LDS accesses around a point where lanes of one wave hand data to each other
 // through LDS: the compiler reasons per lane and could otherwise move a read of one address above a
 // write that another lane makes to it.  One wave's LDS operations execute in program order, so a
-// compiler barrier is enough.
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_wave_barrier();
-  asm volatile("" ::: "memory");
-}
+// wavefront-scope fence (a compiler barrier that needs no wait instruction) is enough.
+__device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 // Work items cover one tile's visibilities (gridding order: tile, then cell).  Each of the 256
 // threads of a work-group takes a contiguous sub-range of the item, so the lanes of a wave sit on
@@ -75,7 +73,7 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
   constexpr int LO = J / 2 - 1;
   __shared__ float2 patch[P * P];
   const int tid = threadIdx.x;
-  const int4 it = items[blockIdx.x];
+  const int4 it = items[xcd_block_runs(blockIdx.x, gridDim.x, 16)];
   const int nT = 1 << (log2K - log2T);
   const int kmask = (1 << log2K) - 1;
   const int a0 = (it.x / nT) * T, b0 = (it.x % nT) * T;
@@ -99,6 +97,9 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
     step = 256;
   }
   float2 cache[RUNS ? J : 1][RUNS ? J : 1];
+  // dense items stage their results in LDS and store them coalesced at the end
+  __shared__ float2 staged[RUNS ? DEGRID_STAGE : 1];
+  const bool stage_out = RUNS && it.z <= DEGRID_STAGE;
   int cur = -1;
   for (int j = lo; j < hi; j += step) {
     const uint2 c = coord[j];
@@ -146,19 +147,28 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
         ai = fmaf(w1, ri, ai);
       }
     }
-    out[oidx ? oidx[j] : j] = make_float2(ar * scale, ai * scale);
+    const float2 r = make_float2(ar * scale, ai * scale);
+    if (stage_out)
+      staged[j - it.y] = r;
+    else
+      out[oidx ? oidx[j] : j] = r;
+  }
+  if (stage_out) {
+    __syncthreads();
+    for (int e = tid; e < it.z; e += 256) out[oidx ? oidx[it.y + e] : it.y + e] = staged[e];
   }
 }
 
 // Gridding of one work item into a private padded patch, written to patches[item slot].
 // Wave w owns the w-th quarter of the item and its own copy of the patch.  It walks its
-// visibilities in batches of 64: phase A (one lane per visibility) writes the 2J weights and
-// (scale v, cell) to the wave's LDS rows; phase B (one lane per tap) accumulates in registers
-// while the cell stays the same.  A finished run is added into the wave's patch copy with a plain
-// read-modify-write (64 lanes, 64 distinct addresses, no other wave on this copy) whose write is
-// deferred to the next cell change, so the read has landed by then; the wave's cells are
-// non-decreasing, so no later read needs a deferred value.  LDS float atomics would avoid the
-// read but measure several times slower here.  Every sum has a fixed order.
+// visibilities in batches of 64.  Phase A (one lane per visibility) writes a1[t1] = w1[t1] * scale * v
+// and w2[t2] to the wave's LDS rows and marks, in a 64-bit ballot, where the cell changes.  Phase B
+// (one lane per tap (t1, t2)) accumulates w2[t2] * a1[t1] in registers while the cell stays the same;
+// at a cell change the finished run is added into the wave's patch copy with a read-modify-write
+// (64 lanes, 64 distinct addresses, no other wave on this copy) whose write is deferred to the next
+// change so that the read has landed by then.  The wave's cells are non-decreasing, so no later
+// read needs a deferred value.  (LDS float atomics would avoid the read but measure several times
+// slower here.)  Every sum has a fixed order, so the result is reproducible.
 template <int J, int T>
 __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ vis,
                                                    const uint32_t* __restrict__ vidx, const int4* __restrict__ items,
@@ -167,15 +177,16 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   constexpr int P = T + J - 1;
   constexpr int PP = P * P;
   constexpr int NQ = (J * J + 63) / 64;   // taps per lane
-  constexpr int WS = 2 * J + 1;           // weight row stride (odd: fewer bank conflicts)
   __shared__ float2 pat[4][PP];           // one patch copy per wave
-  __shared__ float wt[4][64][WS];         // per wave: w1[0..J), w2[J..2J) of its current 64 visibilities
-  __shared__ float4 vc[4][64];            // per wave: (scale v.x, scale v.y, tap-(0,0) patch offset, -)
+  // per wave, tap-major with a 65-entry pitch: phase A (consecutive lanes) and phase B (8 rows at
+  // stride 65) both stay free of LDS bank conflicts
+  __shared__ float2 aw[4][J][65];         // w1[t1] * scale * v of the wave's current 64 visibilities
+  __shared__ float bw[4][J + 1][65];      // w2[t2]; row J stays 0
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   for (int e = tid; e < 4 * PP; e += 256) (&pat[0][0])[e] = make_float2(0.f, 0.f);
   __syncthreads();
-  const int4 it = items[blockIdx.x];
+  const int4 it = items[xcd_block_runs(blockIdx.x, gridDim.x, 16)];
   const int nT = 1 << (log2K - log2T);
   const int a0 = (it.x / nT) * T, b0 = (it.x % nT) * T;
   const int F = 32 - log2K;
@@ -188,49 +199,71 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   for (int q = 0; q < NQ; ++q) {
     const int t = q * 64 + lane;
     tval[q] = t < J * J;
-    tr[q] = tval[q] ? t / J : 0;              // lanes past the last tap read tap (0, 0) and add zero
-    tc[q] = tval[q] ? t % J : 0;
-    toff[q] = tr[q] * P + tc[q];
+    tr[q] = tval[q] ? t / J : 0;              // lanes past the last tap read tap (0, 0) with weight 0
+    tc[q] = tval[q] ? t % J : J;              // row J of bw is always 0
+    toff[q] = tval[q] ? (t / J) * P + t % J : 0;
     acc[q] = pend_val[q] = pend_old[q] = make_float2(0.f, 0.f);
   }
   float2* mypat = pat[wave];
+  bw[wave][J][lane] = 0.f;
   int cur = -1, pend = -1;                  // patch offset of tap (0, 0): current run, deferred run
   const int w_lo = it.y + int((int64_t)it.z * wave / 4);
   const int w_hi = it.y + int((int64_t)it.z * (wave + 1) / 4);
   for (int base = w_lo; base < w_hi; base += 64) {
     const int nb = min(64, w_hi - base);
-    if (lane < nb) {                        // phase A
+    int cell = -1;
+    if (lane >= nb) {                       // padding entries contribute exactly zero
+#pragma unroll
+      for (int t = 0; t < J; ++t) {
+        aw[wave][t][lane] = make_float2(0.f, 0.f);
+        bw[wave][t][lane] = 0.f;
+      }
+    } else {                                // phase A
       const int j = base + lane;
       const uint2 c = coord[j];
       const float2 v = vis[vidx ? vidx[j] : j];
       const int lr = int(c.x >> F) - a0, lc = int(c.y >> F) - b0;
       const float s1 = float(c.x & fmask) * fs - 1.0f;
       const float s2 = float(c.y & fmask) * fs - 1.0f;
+      const float vr = v.x * scale, vi = v.y * scale;
 #pragma unroll
       for (int t = 0; t < J; ++t) {
-        wt[wave][lane][t] = kb_eval(kc.c[t], s1);
-        wt[wave][lane][J + t] = kb_eval(kc.c[t], s2);
+        const float w1 = kb_eval(kc.c[t], s1);
+        aw[wave][t][lane] = make_float2(w1 * vr, w1 * vi);
+        bw[wave][t][lane] = kb_eval(kc.c[t], s2);
       }
-      vc[wave][lane] = make_float4(v.x * scale, v.y * scale, __int_as_float(lr * P + lc), 0.f);
+      cell = lr * P + lc;
     }
+    // run starts of this batch: lane i starts a run if its cell differs from lane i-1's
+    // (lane 0 compares with the run carried over from the previous batch)
+    const int prev = __shfl_up(cell, 1);
+    const uint64_t starts = __ballot(lane < nb && cell != (lane == 0 ? cur : prev));
     wave_lds_order();                       // phase A rows visible to every lane
-    for (int k = 0; k < nb; k += 8) {       // phase B, eight visibilities per step
-      float4 q4[8];
-      float wa[NQ][8], wb[NQ][8];
+    const int nb8 = (nb + 7) & ~7;          // entries up to nb8 exist (padding is zero)
+    for (int k = 0; k < nb8; k += 8) {      // phase B, eight visibilities per step
+      float2 av[NQ][8];
+      float bv[NQ][8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        q4[u] = vc[wave][k + u];            // k + u < 64: in bounds; rows past nb are never used
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          wa[q][u] = wt[wave][k + u][tr[q]];
-          wb[q][u] = wt[wave][k + u][J + tc[q]];
+          av[q][u] = aw[wave][tr[q]][k + u];
+          bv[q][u] = bw[wave][tc[q]][k + u];
         }
+      const uint32_t group = uint32_t(starts >> k) & 0xffu;
+      if (group == 0) {                     // no run starts here: straight-line accumulation
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            acc[q].x = fmaf(bv[q][u], av[q][u].x, acc[q].x);
+            acc[q].y = fmaf(bv[q][u], av[q][u].y, acc[q].y);
+          }
+        continue;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        if (k + u >= nb) break;
-        const int cell = __builtin_amdgcn_readfirstlane(__float_as_int(q4[u].z));
-        if (cell != cur) {
+        if ((group >> u) & 1) {
           if (pend >= 0) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
@@ -247,13 +280,12 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
               acc[q] = make_float2(0.f, 0.f);
             }
           }
-          cur = cell;
+          cur = __builtin_amdgcn_readlane(cell, k + u);
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          const float w = tval[q] ? wa[q][u] * wb[q][u] : 0.f;
-          acc[q].x = fmaf(w, q4[u].x, acc[q].x);
-          acc[q].y = fmaf(w, q4[u].y, acc[q].y);
+          acc[q].x = fmaf(bv[q][u], av[q][u].x, acc[q].x);
+          acc[q].y = fmaf(bv[q][u], av[q][u].y, acc[q].y);
         }
       }
     }
@@ -262,17 +294,15 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   if (pend >= 0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
-      if (tval[q])
-        mypat[pend + toff[q]] = make_float2(pend_old[q].x + pend_val[q].x, pend_old[q].y + pend_val[q].y);
+      if (tval[q]) mypat[pend + toff[q]] = make_float2(pend_old[q].x + pend_val[q].x, pend_old[q].y + pend_val[q].y);
     wave_lds_order();
   }
   if (cur >= 0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
       if (tval[q]) {
-        float2& d = mypat[cur + toff[q]];
-        d.x += acc[q].x;
-        d.y += acc[q].y;
+        const float2 o = mypat[cur + toff[q]];
+        mypat[cur + toff[q]] = make_float2(o.x + acc[q].x, o.y + acc[q].y);
       }
   }
   __syncthreads();
@@ -293,8 +323,9 @@ __global__ __launch_bounds__(256) void fold_kernel(const float2* __restrict__ pa
   constexpr int G = (T * T + 255) / 256;   // work-groups per tile
   const int nT = 1 << (log2K - log2T);
   const int K = 1 << log2K;
-  const int tile = blockIdx.x / G;
-  const int e = (blockIdx.x % G) * 256 + threadIdx.x;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = blk / G;
+  const int e = (blk % G) * 256 + threadIdx.x;
   if (e >= T * T) return;
   const int a = tile / nT, b = tile % nT;
   const int l1 = e / T, l2 = e % T;

@@ -14,6 +14,11 @@ import os
 
 import numpy as np
 
+# torch ships its own HIP runtime with the same soname (libamdhip64.so.7) as the ROCm one the library
+# is linked against; whichever is loaded first serves the whole process.  Importing torch first makes
+# that torch's runtime, so the library and torch share one runtime (device pointers and streams).
+import torch  # noqa: E402,F401
+
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsarahip.so")
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "

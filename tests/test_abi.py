@@ -78,3 +78,13 @@ def test_op_create_tuned_rejects_bad_tiling():
         with pytest.raises(sh.SarahipError) as e:
             sh.op_create_tuned(uv, 16, 2, 6, [0, 4], tile=tile, chunk=chunk)
         assert e.value.status == -1
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the binding leaves exactly one HIP runtime in the process (torch's)."""
+    import torch
+    maps = open("/proc/self/maps").read()
+    hips = {line.split()[-1] for line in maps.splitlines() if line.endswith(".so") or "libamdhip64" in line}
+    hips = {h for h in hips if "libamdhip64" in h}
+    assert len(hips) == 1, hips
+    assert os.path.dirname(torch.__file__) in next(iter(hips))
