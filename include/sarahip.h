@@ -75,9 +75,22 @@ sh_status sh_op_create_tuned(const double* uv, int64_t M, int32_t n, int32_t ove
                              const int64_t* block_offsets, int32_t R, int32_t tile, int32_t chunk, sh_op* out);
 sh_status sh_op_destroy(sh_op op);
 
+/* One plan for P independent problems of the same image side, oversampling and kernel width
+ * (many small fields imaged at once: the launches then cover all of them).  Problem p has M_p[p]
+ * visibilities and R_p[p] blocks; uv (host, M x 2, M = sum M_p) and block_offsets (host, R+1,
+ * R = sum R_p) concatenate the problems in order, so problem p's blocks are consecutive and cover
+ * exactly its visibilities.  Every map of the plan then acts on all problems at once: images are
+ * P x n x n (problem-major), visibilities M (problem-major), blocks R; problem p's visibilities
+ * are measured from problem p's image only.  Errors as sh_op_create_tuned, plus SH_EINVAL when a
+ * problem's blocks do not cover its visibilities exactly or P is outside [1, 4096]. */
+sh_status sh_op_create_batched(const double* uv, const int64_t* M_p, int32_t P, int32_t n, int32_t oversample,
+                               int32_t kernel_width, const int64_t* block_offsets, const int32_t* R_p,
+                               int32_t tile, int32_t chunk, sh_op* out);
+
 /* Query plan sizes: out[0]=M, out[1]=n, out[2]=grid side K, out[3]=J, out[4]=R,
- * out[5]=number of gridding work items, out[6]=tile side, out[7]=max items per tile. */
-sh_status sh_op_query(sh_op op, int64_t out[8]);
+ * out[5]=number of gridding work items, out[6]=tile side, out[7]=max items per tile,
+ * out[8]=number of problems P, out[9]=work items of the sparse (one thread per visibility) class. */
+sh_status sh_op_query(sh_op op, int64_t out[10]);
 
 /* Block offsets in internal order (host, R+1 int64).  Internal order permutes
  * visibilities only inside each block, so these equal the user offsets. */
@@ -86,7 +99,8 @@ sh_status sh_op_block_offsets(sh_op op, int64_t* offsets_out);
 /* Permutation: perm_out[i] = user index of internal visibility i (host, M int64). */
 sh_status sh_op_permutation(sh_op op, int64_t* perm_out);
 
-/* vis = Phi x in user order.  x: device n*n float32; vis: device M complex64.  Async. */
+/* vis = Phi x in user order.  x: device P*n*n float32 (P = 1 unless batched); vis: device M
+ * complex64.  Async. */
 sh_status sh_phi_fwd(sh_op op, const float* x, float* vis, void* stream);
 /* x = Re(Phi^H vis) from user-order visibilities.  Async. */
 sh_status sh_phi_adj(sh_op op, const float* vis, float* x, void* stream);
@@ -98,9 +112,10 @@ sh_status sh_vis_to_internal(sh_op op, const float* user, float* internal, void*
 sh_status sh_vis_to_user(sh_op op, const float* internal, float* user, void* stream);
 
 /* ||Phi||_2 of the real-linear map R^N -> C^M by power iteration on Re(Phi^H Phi)
- * from the caller's start image x0 (device n*n float32, e.g. a seeded Gaussian),
- * at most `iters` steps or until the eigenvalue estimate changes by <= tol
- * relative.  Norms and Rayleigh quotients are reduced in float64.  Synchronous. */
+ * from the caller's start image x0 (device P*n*n float32, e.g. a seeded Gaussian),
+ * at most `iters` steps or until every problem's eigenvalue estimate changes by <= tol
+ * relative.  Norms and Rayleigh quotients are reduced in float64.  nu_out: host, P values
+ * (one per problem of a batched plan).  Synchronous. */
 sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream);
 
 /* ---------------------------------------------------------------------------
@@ -111,6 +126,9 @@ sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, doubl
  * n must be divisible by 2^levels (levels 1..8).  Filters are computed on the
  * host in float64 by spectral factorisation.  Synchronous. */
 sh_status sh_psi_create(int32_t n, int32_t levels, uint32_t basis_mask, sh_psi* out);
+/* The same dictionary applied to `batch` images per call (1..4096): x is batch x n x n and the
+ * coefficients batch x q x n x n, image-major.  Pairs with a batched plan of P = batch problems. */
+sh_status sh_psi_create_batched(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch, sh_psi* out);
 sh_status sh_psi_destroy(sh_psi psi);
 /* Number of planes q (D = q*n*n coefficients). */
 sh_status sh_psi_planes(sh_psi psi, int32_t* q_out);
@@ -160,10 +178,13 @@ typedef struct {
   int32_t cg_iters;    /* conjugate-gradient steps per x-update */
   int32_t passes;      /* weighted-l1 solves, the first with W (or identity) */
   int32_t check_every; /* host reads the stopping flags every this many iterations (>= 1) */
+  int32_t graph;       /* 1: capture one iteration as a HIP graph and replay it; 0: plain launches.
+                          Same arithmetic either way; kernel timing (sh_profile_enable) forces 0 */
 } sh_sdmm_params;
 
 /* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
- * max_iter 300, cg_iters 8, passes 1, check_every 10. */
+ * max_iter 300, cg_iters 8, passes 1, check_every 10, graph 1.  With a batched plan, a given
+ * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 
 typedef struct {
@@ -184,7 +205,13 @@ typedef struct {
  * x0: device n*n float32 warm start or NULL (zero start).  x_out: device n*n.
  * W_out: device D float32 (the weights after the last reweighting, i.e. those a
  * further pass would use) or NULL.  block_resid: host R float64 receiving
- * ||y_i - Phi_i x|| at exit, or NULL.  Synchronous.
+ * ||y_i - Phi_i x|| at exit, or NULL.  info: host, one entry per problem, or NULL.
+ * Batched plans (P problems, psi with batch P) solve all problems together: images, weights and
+ * coefficients are P times larger (problem-major) and every problem keeps its own nu, gamma,
+ * CG scalars, reweighting delta and stopping test; the pass ends when every problem meets the
+ * test.  In the last pass each problem's image, residuals, relative change, objective and W_out
+ * are those of the iteration at which it first met the test (info[p].iters_last), as if it had
+ * been solved alone.  Synchronous.
  * Errors: SH_EINVAL, SH_ENONFINITE (non-finite y/eps or residual), SH_ENOMEM, SH_EDEVICE. */
 sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W,
                         const float* x0, const sh_sdmm_params* params, float* x_out, float* W_out,
@@ -202,8 +229,8 @@ sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps
  * reweighting, no host synchronisation).  Splitting a run into several calls gives the same
  * iterates as one call.  Async. */
 sh_status sh_sdmm_iterate(sh_sdmm s, int32_t iters, void* stream);
-/* Current image (device n*n, may be NULL), block residuals ||y_i - Phi_i x|| (host R, may be
- * NULL) and relative change of the last iteration.  Synchronous. */
+/* Current image (device P*n*n, may be NULL), block residuals ||y_i - Phi_i x|| (host R, may be
+ * NULL) and relative change of the last iteration (host, P values, may be NULL).  Synchronous. */
 sh_status sh_sdmm_result(sh_sdmm s, float* x_out, double* block_resid, double* rel_change, void* stream);
 sh_status sh_sdmm_destroy(sh_sdmm s);
 

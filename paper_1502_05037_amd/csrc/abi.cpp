@@ -52,6 +52,8 @@ void drain_locked() {
 }
 }  // namespace
 
+bool profiling_on() { return g_on; }
+
 ProfScope::ProfScope(const char* name, hipStream_t stream) : st(stream) {
   if (!g_on) return;
   slot = slot_of(name);

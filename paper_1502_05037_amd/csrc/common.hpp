@@ -87,6 +87,7 @@ inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Kernel timing with HIP events on the launch stream (enabled by sh_profile_enable).
+bool profiling_on();
 struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   int slot = -1;

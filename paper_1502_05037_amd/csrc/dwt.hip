@@ -4,7 +4,8 @@
 // Each Daubechies basis is a 2D periodic orthonormal DWT with `levels` levels in Mallat layout: one
 // level filters within rows into [a | d] and then within columns into [a ; d]; quadrants are LL
 // (top-left), row-high/column-low (top-right), row-low/column-high (bottom-left), HH (bottom-right).
-// Analysis runs one launch per level for all wavelet planes at once (blockIdx.z = plane): a
+// Analysis runs one launch per level for all wavelet planes of all images of a batch at once
+// (blockIdx.z = image * planes + plane): a
 // work-group stages a (2T + 2p - 2)^2 input window in LDS with coalesced row reads, filters along
 // rows, then along columns through LDS (the transpose), and writes T x T outputs of each subband.
 // Synthesis is the transpose, tile by tile; its last level sums all planes in registers so the
@@ -25,10 +26,11 @@ struct DwtPlanes {
 
 struct sh_psi_s {
   int n = 0, levels = 0, q = 0;
+  int batch = 1;                  // images transformed per call (image-major: x[img][n][n], c[img][q][n][n])
   uint32_t mask = 0;
   float scale = 1.f;
   DwtPlanes pl{};
-  sh::DevBuf<float> tmpA, tmpB;   // nplanes x (n/2)^2 LL ping-pong
+  sh::DevBuf<float> tmpA, tmpB;   // batch x nplanes x (n/2)^2 LL ping-pong
 };
 
 namespace {
@@ -38,16 +40,22 @@ constexpr int AIN = 2 * AT + 16 - 2;   // input window side for filters up to 16
 constexpr int ST = 32;                 // synthesis output tile
 constexpr int SK = ST / 2 + 8;         // subband window side
 
-// One analysis level.  Input: side L (ld in_ld, plane stride in_ps; 0 = shared input), scaled by
-// `s0`.  Details go to coefficient planes (ld n); LL goes to ll_out (ld ll_ld, stride ll_ps) or,
-// if ll_out is NULL, to the top-left of the coefficient plane.
-__global__ __launch_bounds__(256) void dwt_analysis(const float* __restrict__ in, int in_ld, int64_t in_ps, int L,
-                                                    float* __restrict__ coeffs, int n, float* __restrict__ ll_out,
-                                                    int ll_ld, int64_t ll_ps, float s0, DwtPlanes pl) {
+// One analysis level.  Input: side L (ld in_ld, plane stride in_ps, 0 = shared by the planes of an
+// image; image stride in_is), scaled by `s0`.  Details go to coefficient planes (ld n, image stride
+// c_is); LL goes to ll_out (ld ll_ld, plane stride ll_ps, image stride nplanes * ll_ps) or, if ll_out
+// is NULL, to the top-left of the coefficient plane.
+__global__ __launch_bounds__(256) void dwt_analysis(const float* __restrict__ in, int in_ld, int64_t in_ps,
+                                                    int64_t in_is, int L, float* __restrict__ coeffs, int n,
+                                                    int64_t c_is, float* __restrict__ ll_out, int ll_ld, int64_t ll_ps,
+                                                    float s0, DwtPlanes pl) {
   __shared__ float win[AIN][AIN + 1];
   __shared__ float ra[AIN][AT + 1];
   __shared__ float rd[AIN][AT + 1];
-  const int d = blockIdx.z;
+  const int img = blockIdx.z / pl.nplanes;
+  const int d = blockIdx.z - img * pl.nplanes;
+  in += img * in_is;
+  coeffs += img * c_is;
+  if (ll_out) ll_out += (int64_t)img * pl.nplanes * ll_ps;
   const int Lf = pl.flen[d];
   const int H = L / 2;
   const int te = H < AT ? H : AT;          // effective tile side
@@ -98,13 +106,14 @@ __global__ __launch_bounds__(256) void dwt_analysis(const float* __restrict__ in
 }
 
 // One synthesis level producing side L from subbands of side H = L/2.  LL comes from ll_in (ld
-// ll_ld, stride ll_ps) or, if NULL, from the coefficient plane.  If `sum_out` is set, the work-group
-// loops over all wavelet planes, adds the Dirac plane and writes s_out * sum to `out` (ld n);
-// otherwise plane blockIdx.z goes to out + z * out_ps (ld out_ld).
+// ll_ld, plane stride ll_ps, image stride nplanes * ll_ps) or, if NULL, from the coefficient plane
+// (image stride c_is).  If `sum_out` is set, work-group z (= image) loops over all wavelet planes,
+// adds the Dirac plane and writes s_out * sum to `out` (ld n, image stride n^2); otherwise
+// z = image * nplanes + plane goes to out + z * out_ps (ld out_ld).
 __global__ __launch_bounds__(256) void dwt_synthesis(const float* __restrict__ ll_in, int ll_ld, int64_t ll_ps, int L,
-                                                     const float* __restrict__ coeffs, int n, float* __restrict__ out,
-                                                     int out_ld, int64_t out_ps, int sum_out, float s_out,
-                                                     DwtPlanes pl) {
+                                                     const float* __restrict__ coeffs, int n, int64_t c_is,
+                                                     float* __restrict__ out, int out_ld, int64_t out_ps, int sum_out,
+                                                     float s_out, DwtPlanes pl) {
   __shared__ float sb[4][SK][SK + 1];    // LL, HL, LH, HH windows
   __shared__ float ylo[ST][SK + 1];      // column-synthesised, row-low half
   __shared__ float yhi[ST][SK + 1];      // column-synthesised, row-high half
@@ -115,8 +124,11 @@ __global__ __launch_bounds__(256) void dwt_synthesis(const float* __restrict__ l
   float acc[ST * ST / 256];
 #pragma unroll
   for (int q = 0; q < ST * ST / 256; ++q) acc[q] = 0.f;
-  const int d_begin = sum_out ? 0 : blockIdx.z;
-  const int d_end = sum_out ? pl.nplanes : blockIdx.z + 1;
+  const int img = sum_out ? (int)blockIdx.z : (int)blockIdx.z / pl.nplanes;
+  const int d_begin = sum_out ? 0 : blockIdx.z - img * pl.nplanes;
+  const int d_end = sum_out ? pl.nplanes : d_begin + 1;
+  coeffs += img * c_is;
+  if (ll_in) ll_in += (int64_t)img * pl.nplanes * ll_ps;
   for (int d = d_begin; d < d_end; ++d) {
     const int Lf = pl.flen[d];
     const int kw = te / 2 + Lf / 2 - 1;                  // window side in subband coordinates
@@ -176,17 +188,18 @@ __global__ __launch_bounds__(256) void dwt_synthesis(const float* __restrict__ l
     if (sum_out) {
       float v = acc[q];
       if (pl.dirac_plane >= 0) v += coeffs[(int64_t)pl.dirac_plane * n * n + (int64_t)gi * n + gj];
-      out[(int64_t)gi * n + gj] = v * s_out;
+      out[(int64_t)img * n * n + (int64_t)gi * n + gj] = v * s_out;
     } else {
       out[(int64_t)blockIdx.z * out_ps + (int64_t)gi * out_ld + gj] = acc[q];
     }
   }
 }
 
-// Dirac plane of the analysis: coeffs[plane] = s * x.
-__global__ void scale_copy(const float* __restrict__ x, float* __restrict__ y, int64_t N, float s) {
+// Dirac plane: y[img * ys + i] = s * x[img * xs + i], i < N, img = blockIdx.y.
+__global__ void scale_copy(const float* __restrict__ x, int64_t xs, float* __restrict__ y, int64_t ys, int64_t N,
+                           float s) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) y[i] = x[i] * s;
+  if (i < N) y[blockIdx.y * ys + i] = x[blockIdx.y * xs + i] * s;
 }
 
 }  // namespace
@@ -202,9 +215,10 @@ sh_status sh_daubechies(int32_t p, double* h_out) {
   return SH_OK;
 }
 
-sh_status sh_psi_create(int32_t n, int32_t levels, uint32_t basis_mask, sh_psi* out) {
+sh_status sh_psi_create_batched(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch, sh_psi* out) {
   SH_REQUIRE(out, "out is NULL");
   *out = nullptr;
+  SH_REQUIRE(batch >= 1 && batch <= 4096, "batch must be in [1, 4096]");
   SH_REQUIRE(levels >= 1 && levels <= 8, "levels must be in [1, 8]");
   SH_REQUIRE(n >= 2 && n <= 8192 && n % (1 << levels) == 0, "n = %d must be divisible by 2^levels", n);
   SH_REQUIRE(basis_mask != 0 && (basis_mask >> 9) == 0, "basis mask must be a non-empty subset of 0x1FF");
@@ -214,6 +228,7 @@ sh_status sh_psi_create(int32_t n, int32_t levels, uint32_t basis_mask, sh_psi* 
     return SH_ENOMEM;
   }
   psi->n = n;
+  psi->batch = batch;
   psi->levels = levels;
   psi->mask = basis_mask;
   int plane = 0;
@@ -237,7 +252,7 @@ sh_status sh_psi_create(int32_t n, int32_t levels, uint32_t basis_mask, sh_psi* 
   psi->q = plane;
   psi->scale = float(1.0 / std::sqrt(double(plane)));
   if (psi->pl.nplanes > 0) {
-    const size_t half = size_t(n / 2) * (n / 2) * psi->pl.nplanes;
+    const size_t half = size_t(n / 2) * (n / 2) * psi->pl.nplanes * batch;
     sh_status s = psi->tmpA.alloc(half);
     if (s == SH_OK) s = psi->tmpB.alloc(half);
     if (s != SH_OK) {
@@ -247,6 +262,10 @@ sh_status sh_psi_create(int32_t n, int32_t levels, uint32_t basis_mask, sh_psi* 
   }
   *out = psi;
   return SH_OK;
+}
+
+sh_status sh_psi_create(int32_t n, int32_t levels, uint32_t basis_mask, sh_psi* out) {
+  return sh_psi_create_batched(n, levels, basis_mask, 1, out);
 }
 
 sh_status sh_psi_destroy(sh_psi psi) {
@@ -263,19 +282,19 @@ sh_status sh_psi_planes(sh_psi psi, int32_t* q_out) {
 sh_status sh_psi_adj(sh_psi psi, const float* x, float* coeffs, void* stream) {
   SH_REQUIRE(psi && x && coeffs, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  const int n = psi->n;
+  const int n = psi->n, B = psi->batch;
+  const int64_t N = int64_t(n) * n, c_is = int64_t(psi->q) * N;
   sh::ProfScope ps("dwt", st);
   if (psi->pl.dirac_plane >= 0) {
-    const int64_t N = int64_t(n) * n;
-    hipLaunchKernelGGL(scale_copy, dim3((unsigned)sh::cdiv(N, 256)), dim3(256), 0, st, x,
-                       coeffs + (int64_t)psi->pl.dirac_plane * N, N, psi->scale);
+    hipLaunchKernelGGL(scale_copy, dim3((unsigned)sh::cdiv(N, 256), B), dim3(256), 0, st, x, N,
+                       coeffs + (int64_t)psi->pl.dirac_plane * N, c_is, N, psi->scale);
     SH_LAUNCHED();
   }
   const int np = psi->pl.nplanes;
   if (np == 0) return SH_OK;
   const float* in = x;
   int in_ld = n;
-  int64_t in_ps = 0;
+  int64_t in_ps = 0, in_is = N;
   float s0 = psi->scale;
   float* bufs[2] = {psi->tmpA.ptr, psi->tmpB.ptr};
   for (int lev = 0; lev < psi->levels; ++lev) {
@@ -284,13 +303,14 @@ sh_status sh_psi_adj(sh_psi psi, const float* x, float* coeffs, void* stream) {
     const bool last = lev == psi->levels - 1;
     float* llo = last ? nullptr : bufs[lev & 1];
     const unsigned nt = (unsigned)sh::cdiv(H, te);
-    dim3 grid(nt, nt, np);
-    hipLaunchKernelGGL(dwt_analysis, grid, dim3(256), 0, st, in, in_ld, in_ps, L, coeffs, n, llo, H, int64_t(H) * H,
-                       s0, psi->pl);
+    dim3 grid(nt, nt, np * B);
+    hipLaunchKernelGGL(dwt_analysis, grid, dim3(256), 0, st, in, in_ld, in_ps, in_is, L, coeffs, n, c_is, llo, H,
+                       int64_t(H) * H, s0, psi->pl);
     SH_LAUNCHED();
     in = llo;
     in_ld = H;
     in_ps = int64_t(H) * H;
+    in_is = in_ps * np;
     s0 = 1.f;
   }
   return SH_OK;
@@ -299,13 +319,13 @@ sh_status sh_psi_adj(sh_psi psi, const float* x, float* coeffs, void* stream) {
 sh_status sh_psi_fwd(sh_psi psi, const float* coeffs, float* x, void* stream) {
   SH_REQUIRE(psi && x && coeffs, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  const int n = psi->n;
+  const int n = psi->n, B = psi->batch;
+  const int64_t N = int64_t(n) * n, c_is = int64_t(psi->q) * N;
   sh::ProfScope ps("dwt", st);
   const int np = psi->pl.nplanes;
   if (np == 0) {  // Dirac only
-    const int64_t N = int64_t(n) * n;
-    hipLaunchKernelGGL(scale_copy, dim3((unsigned)sh::cdiv(N, 256)), dim3(256), 0, st,
-                       coeffs + (int64_t)psi->pl.dirac_plane * N, x, N, psi->scale);
+    hipLaunchKernelGGL(scale_copy, dim3((unsigned)sh::cdiv(N, 256), B), dim3(256), 0, st,
+                       coeffs + (int64_t)psi->pl.dirac_plane * N, c_is, x, N, N, psi->scale);
     SH_LAUNCHED();
     return SH_OK;
   }
@@ -316,20 +336,19 @@ sh_status sh_psi_fwd(sh_psi psi, const float* coeffs, float* x, void* stream) {
   for (int lev = psi->levels - 1; lev >= 0; --lev) {
     const int L = n >> lev;
     const int te = L < ST ? L : ST;
+    const unsigned nt = (unsigned)sh::cdiv(L, te);
     if (lev > 0) {
       float* o = bufs[lev & 1];
-      const unsigned nt = (unsigned)sh::cdiv(L, te);
-      dim3 grid(nt, nt, np);
-      hipLaunchKernelGGL(dwt_synthesis, grid, dim3(256), 0, st, ll, ll_ld, ll_ps, L, coeffs, n, o, L, int64_t(L) * L, 0,
-                         1.f, psi->pl);
+      dim3 grid(nt, nt, np * B);
+      hipLaunchKernelGGL(dwt_synthesis, grid, dim3(256), 0, st, ll, ll_ld, ll_ps, L, coeffs, n, c_is, o, L,
+                         int64_t(L) * L, 0, 1.f, psi->pl);
       SH_LAUNCHED();
       ll = o;
       ll_ld = L;
       ll_ps = int64_t(L) * L;
     } else {
-      const unsigned nt = (unsigned)sh::cdiv(L, te);
-      dim3 grid(nt, nt, 1);
-      hipLaunchKernelGGL(dwt_synthesis, grid, dim3(256), 0, st, ll, ll_ld, ll_ps, L, coeffs, n, x, n, 0, 1,
+      dim3 grid(nt, nt, B);
+      hipLaunchKernelGGL(dwt_synthesis, grid, dim3(256), 0, st, ll, ll_ld, ll_ps, L, coeffs, n, c_is, x, n, 0, 1,
                          psi->scale, psi->pl);
       SH_LAUNCHED();
     }
@@ -340,3 +359,4 @@ sh_status sh_psi_fwd(sh_psi psi, const float* coeffs, float* x, void* stream) {
 }  // extern "C"
 
 int psi_side(sh_psi psi) { return psi->n; }
+int psi_batch(sh_psi psi) { return psi->batch; }

@@ -107,14 +107,31 @@ __device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ 
 template <int L, int B, int MODE>
 __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ in, void* __restrict__ out,
                                                       const float2* __restrict__ tw,
-                                                      const float* __restrict__ deapod, int n, float scale) {
+                                                      const float* __restrict__ deapod, int n, int per) {
   extern __shared__ float2 lds[];
   constexpr bool INV = (MODE == COLS_ADJ || MODE == ROWS_ADJ);
   constexpr int NT = B * L / 8;
   const int tid = threadIdx.x;
-  const int seq0 = xcd_block(blockIdx.x, gridDim.x) * B;   // first row (row modes) or column (column modes)
-  const int half = n / 2;
   const int K = L;                    // grid side
+  // `per` sequences per problem (n rows or K columns); B divides per, so a block stays in one problem
+  const int gseq = xcd_block(blockIdx.x, gridDim.x) * B;
+  const int prob = gseq / per;
+  const int seq0 = gseq - prob * per;  // first row (row modes) or column (column modes) of the problem
+  const int half = n / 2;
+  const size_t img = (size_t)n * n, hk = (size_t)n * K, gk = (size_t)K * K;
+  if constexpr (MODE == ROWS_FWD) {
+    in = (const float*)in + prob * img;
+    out = (float2*)out + prob * hk;
+  } else if constexpr (MODE == COLS_FWD) {
+    in = (const float2*)in + prob * hk;
+    out = (float2*)out + prob * gk;
+  } else if constexpr (MODE == COLS_ADJ) {
+    in = (const float2*)in + prob * gk;
+    out = (float2*)out + prob * hk;
+  } else {
+    in = (const float2*)in + prob * hk;
+    out = (float*)out + prob * img;
+  }
 
   // ---- load ----
   if constexpr (MODE == ROWS_FWD) {
@@ -178,22 +195,22 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
     for (int e = tid; e < B * n; e += NT) {
       const int b = e / n, c = e - b * n;
       const int r = seq0 + b;
-      x[(size_t)r * n + c] = lds[b * L + ((c - half) & (L - 1))].x * deapod[r] * deapod[c] * scale;
+      x[(size_t)r * n + c] = lds[b * L + ((c - half) & (L - 1))].x * deapod[r] * deapod[c];
     }
   }
 }
 
 template <int L, int MODE>
-sh_status launch_len(int count, const void* in, void* out, const float2* tw, const float* deapod, int n, float scale,
+sh_status launch_len(int per, int P, const void* in, void* out, const float2* tw, const float* deapod, int n,
                      hipStream_t st) {
   constexpr int B = (8192 / L) < 1 ? 1 : (8192 / L);
   int b = B > 64 ? 64 : B;
-  while (b > count) b >>= 1;  // few sequences (tiny images): shrink the batch
+  while (b > per) b >>= 1;  // few sequences (tiny images): shrink the batch
   const size_t lds = size_t(b) * L * sizeof(float2);
 #define SH_FFT_CASE(BB)                                                                                  \
   if (b == BB) {                                                                                         \
-    hipLaunchKernelGGL((fft_pass<L, BB, MODE>), dim3(count / BB), dim3(BB * L / 8), lds, st, in, out, tw, \
-                       deapod, n, scale);                                                                \
+    hipLaunchKernelGGL((fft_pass<L, BB, MODE>), dim3(P * (per / BB)), dim3(BB * L / 8), lds, st, in, out, \
+                       tw, deapod, n, per);                                                              \
     SH_LAUNCHED();                                                                                       \
     return SH_OK;                                                                                        \
   }
@@ -210,18 +227,18 @@ sh_status launch_len(int count, const void* in, void* out, const float2* tw, con
 }
 
 template <int MODE>
-sh_status launch_mode(int L, int count, const void* in, void* out, const float2* tw, const float* deapod, int n,
-                      float scale, hipStream_t st) {
+sh_status launch_mode(int L, int per, int P, const void* in, void* out, const float2* tw, const float* deapod, int n,
+                      hipStream_t st) {
   switch (L) {
-    case 32: return launch_len<32, MODE>(count, in, out, tw, deapod, n, scale, st);
-    case 64: return launch_len<64, MODE>(count, in, out, tw, deapod, n, scale, st);
-    case 128: return launch_len<128, MODE>(count, in, out, tw, deapod, n, scale, st);
-    case 256: return launch_len<256, MODE>(count, in, out, tw, deapod, n, scale, st);
-    case 512: return launch_len<512, MODE>(count, in, out, tw, deapod, n, scale, st);
-    case 1024: return launch_len<1024, MODE>(count, in, out, tw, deapod, n, scale, st);
-    case 2048: return launch_len<2048, MODE>(count, in, out, tw, deapod, n, scale, st);
-    case 4096: return launch_len<4096, MODE>(count, in, out, tw, deapod, n, scale, st);
-    case 8192: return launch_len<8192, MODE>(count, in, out, tw, deapod, n, scale, st);
+    case 32: return launch_len<32, MODE>(per, P, in, out, tw, deapod, n, st);
+    case 64: return launch_len<64, MODE>(per, P, in, out, tw, deapod, n, st);
+    case 128: return launch_len<128, MODE>(per, P, in, out, tw, deapod, n, st);
+    case 256: return launch_len<256, MODE>(per, P, in, out, tw, deapod, n, st);
+    case 512: return launch_len<512, MODE>(per, P, in, out, tw, deapod, n, st);
+    case 1024: return launch_len<1024, MODE>(per, P, in, out, tw, deapod, n, st);
+    case 2048: return launch_len<2048, MODE>(per, P, in, out, tw, deapod, n, st);
+    case 4096: return launch_len<4096, MODE>(per, P, in, out, tw, deapod, n, st);
+    case 8192: return launch_len<8192, MODE>(per, P, in, out, tw, deapod, n, st);
   }
   sh::set_error("unsupported FFT length %d", L);
   return SH_EUNSUPPORTED;
@@ -234,19 +251,19 @@ namespace sh {
 sh_status fft_forward_2d(sh_op op, const float* x, float2* grid, hipStream_t st) {
   {
     ProfScope ps("fft_rows", st);
-    SH_TRY(launch_mode<ROWS_FWD>(op->K, op->n, x, op->half.ptr, op->tw.ptr, op->deapod.ptr, op->n, 1.f, st));
+    SH_TRY(launch_mode<ROWS_FWD>(op->K, op->n, op->P, x, op->half.ptr, op->tw.ptr, op->deapod.ptr, op->n, st));
   }
   ProfScope ps("fft_cols", st);
-  return launch_mode<COLS_FWD>(op->K, op->K, op->half.ptr, grid, op->tw.ptr, op->deapod.ptr, op->n, 1.f, st);
+  return launch_mode<COLS_FWD>(op->K, op->K, op->P, op->half.ptr, grid, op->tw.ptr, op->deapod.ptr, op->n, st);
 }
 
-sh_status fft_adjoint_2d(sh_op op, const float2* grid, float* x, float scale, hipStream_t st) {
+sh_status fft_adjoint_2d(sh_op op, const float2* grid, float* x, hipStream_t st) {
   {
     ProfScope ps("fft_cols", st);
-    SH_TRY(launch_mode<COLS_ADJ>(op->K, op->K, grid, op->half.ptr, op->tw.ptr, op->deapod.ptr, op->n, 1.f, st));
+    SH_TRY(launch_mode<COLS_ADJ>(op->K, op->K, op->P, grid, op->half.ptr, op->tw.ptr, op->deapod.ptr, op->n, st));
   }
   ProfScope ps("fft_rows", st);
-  return launch_mode<ROWS_ADJ>(op->K, op->n, op->half.ptr, x, op->tw.ptr, op->deapod.ptr, op->n, scale, st);
+  return launch_mode<ROWS_ADJ>(op->K, op->n, op->P, op->half.ptr, x, op->tw.ptr, op->deapod.ptr, op->n, st);
 }
 
 }  // namespace sh

@@ -67,8 +67,8 @@ __device__ __forceinline__ void item_range(const int4& it, int tid, int& lo, int
 template <int J, int T, bool RUNS>
 __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ grid,
                                                      float2* __restrict__ out, const uint32_t* __restrict__ oidx,
-                                                     const int4* __restrict__ items, int log2K, int log2T, float scale,
-                                                     KBCoef kc) {
+                                                     const int4* __restrict__ items, int log2K, int log2T,
+                                                     const float* __restrict__ scales, KBCoef kc) {
   constexpr int P = T + J - 1;
   constexpr int LO = J / 2 - 1;
   __shared__ float2 patch[P * P];
@@ -76,7 +76,10 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
   const int4 it = items[xcd_block_runs(blockIdx.x, gridDim.x, 16)];
   const int nT = 1 << (log2K - log2T);
   const int kmask = (1 << log2K) - 1;
-  const int a0 = (it.x / nT) * T, b0 = (it.x % nT) * T;
+  const int prob = it.x >> (2 * (log2K - log2T)), tloc = it.x & ((1 << (2 * (log2K - log2T))) - 1);
+  const int a0 = (tloc / nT) * T, b0 = (tloc % nT) * T;
+  grid += (size_t)prob << (2 * log2K);
+  const float scale = scales ? scales[prob] : 1.f;
   for (int e = tid; e < P * P; e += 256) {
     const int p1 = e / P, p2 = e - p1 * P;
     patch[e] = grid[(size_t)((a0 - LO + p1) & kmask) * (kmask + 1) + ((b0 - LO + p2) & kmask)];
@@ -172,8 +175,8 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
 template <int J, int T>
 __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ vis,
                                                    const uint32_t* __restrict__ vidx, const int4* __restrict__ items,
-                                                   float2* __restrict__ patches, int log2K, int log2T, float scale,
-                                                   KBCoef kc) {
+                                                   float2* __restrict__ patches, int log2K, int log2T,
+                                                   const float* __restrict__ scales, KBCoef kc) {
   constexpr int P = T + J - 1;
   constexpr int PP = P * P;
   constexpr int NQ = (J * J + 63) / 64;   // taps per lane
@@ -188,7 +191,9 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   __syncthreads();
   const int4 it = items[xcd_block_runs(blockIdx.x, gridDim.x, 16)];
   const int nT = 1 << (log2K - log2T);
-  const int a0 = (it.x / nT) * T, b0 = (it.x % nT) * T;
+  const int prob = it.x >> (2 * (log2K - log2T)), tloc = it.x & ((1 << (2 * (log2K - log2T))) - 1);
+  const int a0 = (tloc / nT) * T, b0 = (tloc % nT) * T;
+  const float scale = scales ? scales[prob] : 1.f;
   const int F = 32 - log2K;
   const uint32_t fmask = (F == 32) ? 0xffffffffu : ((1u << F) - 1u);
   const float fs = ldexpf(1.0f, 1 - F);
@@ -324,10 +329,13 @@ __global__ __launch_bounds__(256) void fold_kernel(const float2* __restrict__ pa
   const int nT = 1 << (log2K - log2T);
   const int K = 1 << log2K;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int tile = blk / G;
+  const int gtile = blk / G;                 // problem * nT^2 + tile
   const int e = (blk % G) * 256 + threadIdx.x;
   if (e >= T * T) return;
+  const int prob = gtile / (nT * nT), tile = gtile - prob * nT * nT;
   const int a = tile / nT, b = tile % nT;
+  tile_items += prob * nT * nT;
+  grid += (size_t)prob * K * K;
   const int l1 = e / T, l2 = e % T;
   float sr = 0.f, si = 0.f;
 #pragma unroll
@@ -364,51 +372,51 @@ __global__ void scatter_kernel(const float2* __restrict__ src, const uint32_t* _
 }
 
 template <int J, int T>
-sh_status launch_degrid_T(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, float scale, hipStream_t st) {
+sh_status launch_degrid_T(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, const float* scales, hipStream_t st) {
   if (op->n_sparse)
     hipLaunchKernelGGL((degrid_kernel<J, T, false>), dim3((unsigned)op->n_sparse), dim3(256), 0, st, op->coord.ptr,
-                       grid, out, oidx, op->items.ptr, op->log2K, op->log2T, scale, op->kb);
+                       grid, out, oidx, op->items.ptr, op->log2K, op->log2T, scales, op->kb);
   if (op->n_items > op->n_sparse)
     hipLaunchKernelGGL((degrid_kernel<J, T, true>), dim3((unsigned)(op->n_items - op->n_sparse)), dim3(256), 0, st,
-                       op->coord.ptr, grid, out, oidx, op->items.ptr + op->n_sparse, op->log2K, op->log2T, scale,
+                       op->coord.ptr, grid, out, oidx, op->items.ptr + op->n_sparse, op->log2K, op->log2T, scales,
                        op->kb);
   SH_LAUNCHED();
   return SH_OK;
 }
 
 template <int J>
-sh_status launch_degrid(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, float scale, hipStream_t st) {
+sh_status launch_degrid(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, const float* scales, hipStream_t st) {
   switch (op->T) {
-    case 8: return launch_degrid_T<J, 8>(op, grid, out, oidx, scale, st);
-    case 16: return launch_degrid_T<J, 16>(op, grid, out, oidx, scale, st);
-    case 32: return launch_degrid_T<J, 32>(op, grid, out, oidx, scale, st);
+    case 8: return launch_degrid_T<J, 8>(op, grid, out, oidx, scales, st);
+    case 16: return launch_degrid_T<J, 16>(op, grid, out, oidx, scales, st);
+    case 32: return launch_degrid_T<J, 32>(op, grid, out, oidx, scales, st);
   }
   sh::set_error("unsupported tile %d", op->T);
   return SH_EUNSUPPORTED;
 }
 
 template <int J, int T>
-sh_status launch_grid_T(sh_op op, const float2* vis, const uint32_t* vidx, float scale, hipStream_t st) {
+sh_status launch_grid_T(sh_op op, const float2* vis, const uint32_t* vidx, const float* scales, hipStream_t st) {
   {
     sh::ProfScope ps("grid", st);
     hipLaunchKernelGGL((grid_kernel<J, T>), dim3((unsigned)op->n_items), dim3(256), 0, st, op->coord.ptr, vis, vidx,
-                       op->items.ptr, op->patches.ptr, op->log2K, op->log2T, scale, op->kb);
+                       op->items.ptr, op->patches.ptr, op->log2K, op->log2T, scales, op->kb);
     SH_LAUNCHED();
   }
   sh::ProfScope ps("fold", st);
   constexpr int G = (T * T + 255) / 256;
-  hipLaunchKernelGGL((fold_kernel<J, T>), dim3((unsigned)(op->nT * op->nT * G)), dim3(256), 0, st, op->patches.ptr,
+  hipLaunchKernelGGL((fold_kernel<J, T>), dim3((unsigned)(op->P * op->nT * op->nT * G)), dim3(256), 0, st, op->patches.ptr,
                      op->tile_items.ptr, op->grid.ptr, op->log2K, op->log2T);
   SH_LAUNCHED();
   return SH_OK;
 }
 
 template <int J>
-sh_status launch_grid(sh_op op, const float2* vis, const uint32_t* vidx, float scale, hipStream_t st) {
+sh_status launch_grid(sh_op op, const float2* vis, const uint32_t* vidx, const float* scales, hipStream_t st) {
   switch (op->T) {
-    case 8: return launch_grid_T<J, 8>(op, vis, vidx, scale, st);
-    case 16: return launch_grid_T<J, 16>(op, vis, vidx, scale, st);
-    case 32: return launch_grid_T<J, 32>(op, vis, vidx, scale, st);
+    case 8: return launch_grid_T<J, 8>(op, vis, vidx, scales, st);
+    case 16: return launch_grid_T<J, 16>(op, vis, vidx, scales, st);
+    case 32: return launch_grid_T<J, 32>(op, vis, vidx, scales, st);
   }
   sh::set_error("unsupported tile %d", op->T);
   return SH_EUNSUPPORTED;
@@ -418,13 +426,13 @@ sh_status launch_grid(sh_op op, const float2* vis, const uint32_t* vidx, float s
 
 namespace sh {
 
-sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, float scale, hipStream_t st) {
+sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, const float* scales, hipStream_t st) {
   SH_TRY(fft_forward_2d(op, x, op->grid.ptr, st));
   ProfScope ps("degrid", st);
   const uint32_t* oi = user_order ? op->perm.ptr : nullptr;
   switch (op->J) {
 #define SH_J(JJ) \
-  case JJ: return launch_degrid<JJ>(op, op->grid.ptr, vis, oi, scale, st);
+  case JJ: return launch_degrid<JJ>(op, op->grid.ptr, vis, oi, scales, st);
     SH_J(2) SH_J(4) SH_J(6) SH_J(8) SH_J(10) SH_J(12) SH_J(14) SH_J(16)
 #undef SH_J
   }
@@ -432,17 +440,17 @@ sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, fl
   return SH_EUNSUPPORTED;
 }
 
-sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, float scale, hipStream_t st) {
+sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, const float* scales, hipStream_t st) {
   const uint32_t* vi = user_order ? op->perm.ptr : nullptr;
   sh_status s = SH_EUNSUPPORTED;
   switch (op->J) {
 #define SH_J(JJ) \
-  case JJ: s = launch_grid<JJ>(op, vis, vi, scale, st); break;
+  case JJ: s = launch_grid<JJ>(op, vis, vi, scales, st); break;
     SH_J(2) SH_J(4) SH_J(6) SH_J(8) SH_J(10) SH_J(12) SH_J(14) SH_J(16)
 #undef SH_J
   }
   SH_TRY(s);
-  return fft_adjoint_2d(op, op->grid.ptr, x, 1.0f, st);
+  return fft_adjoint_2d(op, op->grid.ptr, x, st);
 }
 
 }  // namespace sh
@@ -476,7 +484,7 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
     const uint32_t local = uint32_t(((cell[0] & (op->T - 1)) << log2T) | (cell[1] & (op->T - 1)));
     key[m] = (tile << (2 * log2T)) | local;
   }
-  // internal order: sort by (tile, cell) inside each block
+  // internal order: sort by (tile, cell) inside each block (blocks never straddle problems)
   std::vector<uint32_t> perm(M);
   std::vector<uint64_t> kv;
   for (int b = 0; b < op->R; ++b) {
@@ -489,35 +497,39 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   std::vector<uint2> ci(M);
   for (int64_t i = 0; i < M; ++i) ci[i] = cu[perm[i]];
   // work items: runs of internal order with one (block, tile), cut into near-equal chunks of at most
-  // GRID_CHUNK.  Items with at least RUN_MIN visibilities per occupied cell on average are "dense"
-  // (run-caching degridder).  Patch slots follow (tile, block) order so that the fold finds the
-  // items of a tile in one contiguous slot range.
+  // `chunk`.  An item's tile id is global: problem * nT^2 + tile.  Items with at least RUN_MIN
+  // visibilities per occupied cell on average are "dense" (run-caching degridder).  Patch slots
+  // follow (global tile, block) order so that the fold finds the items of a tile in one contiguous
+  // slot range.
   const int ntiles = nT * nT;
+  const int gtiles = op->P * ntiles;
   struct Item { int tile, start, count, dense; };
   std::vector<Item> all;
   for (int64_t i = 0; i < M;) {
     const uint32_t k0 = key[perm[i]] >> (2 * log2T);
+    const int b = int(std::upper_bound(offs, offs + op->R + 1, i) - offs) - 1;
+    const int64_t bend = offs[b + 1];
+    const int gt = op->block_prob[b] * ntiles + (int)k0;
     int64_t e = i;
-    const int64_t bend = offs[std::upper_bound(offs, offs + op->R + 1, i) - offs];
     while (e < bend && (key[perm[e]] >> (2 * log2T)) == k0) ++e;
     const int64_t c = e - i, nck = sh::cdiv(c, op->chunk);
     for (int64_t k = 0; k < nck; ++k) {
-      const int64_t a = i + c * k / nck, b = i + c * (k + 1) / nck;
+      const int64_t a = i + c * k / nck, bb = i + c * (k + 1) / nck;
       int64_t cells = 0;
-      for (int64_t q = a; q < b; ++q) cells += (q == a || key[perm[q]] != key[perm[q - 1]]);
-      all.push_back({(int)k0, (int)a, (int)(b - a), (b - a) >= RUN_MIN * cells ? 1 : 0});
+      for (int64_t q = a; q < bb; ++q) cells += (q == a || key[perm[q]] != key[perm[q - 1]]);
+      all.push_back({gt, (int)a, (int)(bb - a), (bb - a) >= RUN_MIN * cells ? 1 : 0});
     }
     i = e;
   }
   std::vector<int> order(all.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return all[x].tile < all[y].tile; });
-  std::vector<int32_t> tile_items(ntiles + 1, 0), per_tile(ntiles, 0), slot_of(all.size());
-  for (size_t s = 0; s < order.size(); ++s) {
-    slot_of[order[s]] = (int32_t)s;
-    per_tile[all[order[s]].tile]++;
+  std::vector<int32_t> tile_items(gtiles + 1, 0), per_tile(gtiles, 0), slot_of(all.size());
+  for (size_t q = 0; q < order.size(); ++q) {
+    slot_of[order[q]] = (int32_t)q;
+    per_tile[all[order[q]].tile]++;
   }
-  for (int t = 0; t < ntiles; ++t) tile_items[t + 1] = tile_items[t] + per_tile[t];
+  for (int t = 0; t < gtiles; ++t) tile_items[t + 1] = tile_items[t] + per_tile[t];
   std::vector<int4> items;
   for (int pass = 0; pass < 2; ++pass)
     for (size_t q = 0; q < all.size(); ++q)
@@ -531,8 +543,8 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   op->chunk_first.assign(op->R + 1, 0);
   for (int b = 0; b < op->R; ++b) {
     op->chunk_first[b] = (int32_t)chunks.size();
-    for (int64_t s = offs[b]; s < offs[b + 1]; s += BALL_CHUNK)
-      chunks.push_back(make_int4(b, (int)s, (int)std::min<int64_t>(s + BALL_CHUNK, offs[b + 1]), 0));
+    for (int64_t q = offs[b]; q < offs[b + 1]; q += BALL_CHUNK)
+      chunks.push_back(make_int4(b, (int)q, (int)std::min<int64_t>(q + BALL_CHUNK, offs[b + 1]), 0));
   }
   op->chunk_first[op->R] = (int32_t)chunks.size();
   op->n_chunks = (int64_t)chunks.size();
@@ -543,6 +555,7 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   SH_TRY(op->tile_items.upload(tile_items));
   SH_TRY(op->chunks.upload(chunks));
   SH_TRY(op->chunk_first_d.upload(op->chunk_first));
+  SH_TRY(op->block_prob_d.upload(op->block_prob));
   SH_TRY(op->partials.alloc(2 * std::max<int64_t>(op->n_chunks, 1)));
   // tables
   std::vector<float> dp(op->n);
@@ -553,8 +566,8 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   SH_TRY(op->tw.upload(tw));
   // scratch
   const int P = op->T + op->J - 1;
-  SH_TRY(op->grid.alloc((size_t)K * K));
-  SH_TRY(op->half.alloc((size_t)op->n * K));
+  SH_TRY(op->grid.alloc((size_t)op->P * K * K));
+  SH_TRY(op->half.alloc((size_t)op->P * op->n * K));
   SH_TRY(op->patches.alloc((size_t)std::max<int64_t>(op->n_items, 1) * P * P));
   SH_TRY(op->vis_tmp.alloc((size_t)M));
   return SH_OK;
@@ -562,20 +575,39 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
 
 extern "C" {
 
-sh_status sh_op_create_tuned(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
-                             const int64_t* block_offsets, int32_t R, int32_t tile, int32_t chunk, sh_op* out) {
+sh_status sh_op_create_batched(const double* uv, const int64_t* M_p, int32_t P, int32_t n, int32_t oversample,
+                               int32_t kernel_width, const int64_t* block_offsets, const int32_t* R_p, int32_t tile,
+                               int32_t chunk, sh_op* out) {
   SH_REQUIRE(out != nullptr, "out is NULL");
   *out = nullptr;
-  SH_REQUIRE(uv != nullptr && block_offsets != nullptr, "uv and block_offsets must be non-NULL");
-  SH_REQUIRE(M >= 1 && M < (int64_t(1) << 31), "M must be in [1, 2^31), got %lld", (long long)M);
+  SH_REQUIRE(uv != nullptr && block_offsets != nullptr && M_p != nullptr && R_p != nullptr, "NULL argument");
+  SH_REQUIRE(P >= 1 && P <= 4096, "P must be in [1, 4096], got %d", P);
+  int64_t M = 0;
+  int64_t R = 0;
+  for (int p = 0; p < P; ++p) {
+    SH_REQUIRE(M_p[p] >= 1, "problem %d has no visibilities", p);
+    SH_REQUIRE(R_p[p] >= 1 && R_p[p] <= M_p[p], "problem %d: R must be in [1, M]", p);
+    M += M_p[p];
+    R += R_p[p];
+  }
+  SH_REQUIRE(M < (int64_t(1) << 31), "total M must be < 2^31, got %lld", (long long)M);
   SH_REQUIRE(sh::is_pow2(n) && n >= 16 && n <= 4096, "n must be a power of two in [16, 4096], got %d", n);
   SH_REQUIRE(oversample == 2 || oversample == 4, "oversample must be 2 or 4, got %d", oversample);
   SH_REQUIRE(kernel_width >= 2 && kernel_width <= 16 && kernel_width % 2 == 0, "J must be even in [2, 16], got %d",
              kernel_width);
-  SH_REQUIRE(R >= 1 && R <= M, "R must be in [1, M], got %d", R);
   SH_REQUIRE(block_offsets[0] == 0 && block_offsets[R] == M, "block offsets must run from 0 to M");
-  for (int i = 0; i < R; ++i)
-    SH_REQUIRE(block_offsets[i + 1] > block_offsets[i], "block offsets must be strictly increasing (block %d)", i);
+  for (int64_t i = 0; i < R; ++i)
+    SH_REQUIRE(block_offsets[i + 1] > block_offsets[i], "block offsets must be strictly increasing (block %lld)",
+               (long long)i);
+  {  // every problem's blocks cover exactly its visibility range
+    int64_t vb = 0, bi = 0;
+    for (int p = 0; p < P; ++p) {
+      SH_REQUIRE(block_offsets[bi] == vb && block_offsets[bi + R_p[p]] == vb + M_p[p],
+                 "blocks of problem %d must cover its visibilities exactly", p);
+      vb += M_p[p];
+      bi += R_p[p];
+    }
+  }
   for (int64_t m = 0; m < 2 * M; ++m)
     SH_REQUIRE(std::isfinite(uv[m]) && uv[m] >= -M_PI && uv[m] < M_PI, "uv[%lld] = %g outside [-pi, pi)",
                (long long)m, uv[m]);
@@ -591,13 +623,14 @@ sh_status sh_op_create_tuned(const double* uv, int64_t M, int32_t n, int32_t ove
     sh::set_error("host allocation failed");
     return SH_ENOMEM;
   }
+  op->P = P;
   op->M = M;
   op->n = n;
   op->alpha = oversample;
   op->K = K;
   op->log2K = sh::ilog2(K);
   op->J = kernel_width;
-  op->R = R;
+  op->R = (int)R;
   op->T = T;
   op->chunk = chunk ? chunk : GRID_CHUNK;
   op->log2T = sh::ilog2(op->T);
@@ -608,6 +641,14 @@ sh_status sh_op_create_tuned(const double* uv, int64_t M, int32_t n, int32_t ove
   for (int t = 0; t < kernel_width; ++t)
     for (int i = 0; i <= KB_DEG; ++i) op->kb.c[t][i] = coef[t * (KB_DEG + 1) + i];
   op->offsets.assign(block_offsets, block_offsets + R + 1);
+  op->vis_off.assign(P + 1, 0);
+  op->block_off.assign(P + 1, 0);
+  op->block_prob.resize(R);
+  for (int p = 0; p < P; ++p) {
+    op->vis_off[p + 1] = op->vis_off[p] + M_p[p];
+    op->block_off[p + 1] = op->block_off[p] + R_p[p];
+    for (int b = op->block_off[p]; b < op->block_off[p + 1]; ++b) op->block_prob[b] = p;
+  }
   sh_status s = op_build(op, uv, block_offsets);
   if (s != SH_OK) {
     delete op;
@@ -615,6 +656,13 @@ sh_status sh_op_create_tuned(const double* uv, int64_t M, int32_t n, int32_t ove
   }
   *out = op;
   return SH_OK;
+}
+
+sh_status sh_op_create_tuned(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
+                             const int64_t* block_offsets, int32_t R, int32_t tile, int32_t chunk, sh_op* out) {
+  SH_REQUIRE(M >= 1 && M < (int64_t(1) << 31), "M must be in [1, 2^31), got %lld", (long long)M);
+  SH_REQUIRE(R >= 1 && R <= M, "R must be in [1, M], got %d", R);
+  return sh_op_create_batched(uv, &M, 1, n, oversample, kernel_width, block_offsets, &R, tile, chunk, out);
 }
 
 sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
@@ -627,7 +675,7 @@ sh_status sh_op_destroy(sh_op op) {
   return SH_OK;
 }
 
-sh_status sh_op_query(sh_op op, int64_t out[8]) {
+sh_status sh_op_query(sh_op op, int64_t out[10]) {
   SH_REQUIRE(op && out, "NULL argument");
   out[0] = op->M;
   out[1] = op->n;
@@ -637,6 +685,8 @@ sh_status sh_op_query(sh_op op, int64_t out[8]) {
   out[5] = op->n_items;
   out[6] = op->T;
   out[7] = op->max_items_per_tile;
+  out[8] = op->P;
+  out[9] = op->n_sparse;
   return SH_OK;
 }
 
@@ -656,22 +706,22 @@ sh_status sh_op_permutation(sh_op op, int64_t* perm_out) {
 
 sh_status sh_phi_fwd(sh_op op, const float* x, float* vis, void* stream) {
   SH_REQUIRE(op && x && vis, "NULL argument");
-  return sh::phi_forward(op, x, (float2*)vis, true, 1.0f, (hipStream_t)stream);
+  return sh::phi_forward(op, x, (float2*)vis, true, nullptr, (hipStream_t)stream);
 }
 
 sh_status sh_phi_adj(sh_op op, const float* vis, float* x, void* stream) {
   SH_REQUIRE(op && x && vis, "NULL argument");
-  return sh::phi_adjoint(op, (const float2*)vis, x, true, 1.0f, (hipStream_t)stream);
+  return sh::phi_adjoint(op, (const float2*)vis, x, true, nullptr, (hipStream_t)stream);
 }
 
 sh_status sh_phi_fwd_internal(sh_op op, const float* x, float* vis, void* stream) {
   SH_REQUIRE(op && x && vis, "NULL argument");
-  return sh::phi_forward(op, x, (float2*)vis, false, 1.0f, (hipStream_t)stream);
+  return sh::phi_forward(op, x, (float2*)vis, false, nullptr, (hipStream_t)stream);
 }
 
 sh_status sh_phi_adj_internal(sh_op op, const float* vis, float* x, void* stream) {
   SH_REQUIRE(op && x && vis, "NULL argument");
-  return sh::phi_adjoint(op, (const float2*)vis, x, false, 1.0f, (hipStream_t)stream);
+  return sh::phi_adjoint(op, (const float2*)vis, x, false, nullptr, (hipStream_t)stream);
 }
 
 sh_status sh_vis_to_internal(sh_op op, const float* user, float* internal, void* stream) {

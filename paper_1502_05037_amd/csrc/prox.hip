@@ -11,7 +11,7 @@
 
 namespace {
 
-constexpr int RB = 512;   // work-groups of the first reduction stage
+constexpr int RB = 512;   // first-stage work-groups of a one-segment reduction
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int tid = threadIdx.x;
@@ -26,93 +26,101 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// partial[b] = sum over a grid-stride slice of a[i]*b[i] (float64)
-__global__ __launch_bounds__(256) void dot_partial(const float* __restrict__ a, const float* __restrict__ b, int64_t N,
+// First stages over segments: grid (gridDim.x, P), blockIdx.y = segment; work-group b of segment p
+// reduces a grid-stride slice of the segment into part[p * gridDim.x + b].
+#define SEGMENT_LOOP(i)                                                                     \
+  const int64_t seg0 = (int64_t)blockIdx.y * per;                                           \
+  for (int64_t i = seg0 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < seg0 + per; i += (int64_t)gridDim.x * 256)
+#define PART_OUT(r) \
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (r)
+
+__global__ __launch_bounds__(256) void dot_partial(const float* __restrict__ a, const float* __restrict__ b, int64_t per,
                                                    double* __restrict__ part) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
-    acc += double(a[i]) * double(b[i]);
+  SEGMENT_LOOP(i) acc += double(a[i]) * double(b[i]);
   const double r = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = r;
+  PART_OUT(r);
 }
 
-// out[0] = sum of part[0..n) (one work-group, fixed tree)
+// out[p] = sum of part[p*n, (p+1)*n) (work-group p, fixed tree)
 __global__ __launch_bounds__(256) void sum_final(const double* __restrict__ part, int n, double* __restrict__ out) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[(int64_t)blockIdx.x * n + i];
   const double r = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[0] = r;
+  if (threadIdx.x == 0) out[blockIdx.x] = r;
 }
 
-__global__ __launch_bounds__(256) void mean_partial(const float* __restrict__ a, int64_t N, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void mean_partial(const float* __restrict__ a, int64_t per, double* __restrict__ part) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) acc += double(a[i]);
+  SEGMENT_LOOP(i) acc += double(a[i]);
   const double r = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = r;
+  PART_OUT(r);
 }
 
-__global__ __launch_bounds__(256) void var_partial(const float* __restrict__ a, int64_t N, const double* __restrict__ sum,
+__global__ __launch_bounds__(256) void var_partial(const float* __restrict__ a, int64_t per, const double* __restrict__ sum,
                                                    double* __restrict__ part) {
   __shared__ double sh[256];
-  const double mean = sum[0] / double(N);
+  const double mean = sum[blockIdx.y] / double(per);
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+  SEGMENT_LOOP(i) {
     const double d = double(a[i]) - mean;
     acc += d * d;
   }
   const double r = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = r;
+  PART_OUT(r);
 }
 
-__global__ __launch_bounds__(256) void maxabs_partial(const float* __restrict__ a, int64_t N, double* __restrict__ part) {
-  __shared__ double sh[256];
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
-    acc = fmax(acc, fabs(double(a[i])));
+__device__ __forceinline__ double block_max(double v, double* sh) {
   const int tid = threadIdx.x;
-  sh[tid] = acc;
+  sh[tid] = v;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (tid < s) sh[tid] = fmax(sh[tid], sh[tid + s]);
     __syncthreads();
   }
-  if (tid == 0) part[blockIdx.x] = sh[0];
+  return sh[0];
+}
+
+__global__ __launch_bounds__(256) void maxabs_partial(const float* __restrict__ a, int64_t per, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  SEGMENT_LOOP(i) acc = fmax(acc, fabs(double(a[i])));
+  const double r = block_max(acc, sh);
+  PART_OUT(r);
 }
 
 __global__ __launch_bounds__(256) void max_final(const double* __restrict__ part, int n, double* __restrict__ out) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc = fmax(acc, part[i]);
-  const int tid = threadIdx.x;
-  sh[tid] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) sh[tid] = fmax(sh[tid], sh[tid + s]);
-    __syncthreads();
-  }
-  if (tid == 0) out[0] = sh[0];
+  for (int i = threadIdx.x; i < n; i += 256) acc = fmax(acc, part[(int64_t)blockIdx.x * n + i]);
+  const double r = block_max(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = r;
 }
 
-__global__ __launch_bounds__(256) void l1w_partial(const float* __restrict__ c, const float* __restrict__ W, int64_t N,
+__global__ __launch_bounds__(256) void l1w_partial(const float* __restrict__ c, const float* __restrict__ W, int64_t per,
                                                    double* __restrict__ part) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
-    acc += fabs(double(c[i]) * (W ? double(W[i]) : 1.0));
+  SEGMENT_LOOP(i) acc += fabs(double(c[i]) * (W ? double(W[i]) : 1.0));
   const double r = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = r;
+  PART_OUT(r);
 }
+#undef SEGMENT_LOOP
+#undef PART_OUT
 
-// weighted soft threshold + dual
-__global__ __launch_bounds__(256) void prox_l1_kernel(int64_t D, const float* __restrict__ s, float* __restrict__ z,
-                                                      const float* __restrict__ W, float gamma, float* __restrict__ v) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= D) return;
+// weighted soft threshold + dual; grid (cdiv(per, 256), P), segment p thresholds at gamma_d[p]
+__global__ __launch_bounds__(256) void prox_l1_kernel(int64_t per, const float* __restrict__ s, float* __restrict__ z,
+                                                      const float* __restrict__ W, const float* __restrict__ gamma_d,
+                                                      float gamma, float* __restrict__ v) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= per) return;
+  const int64_t i = (int64_t)blockIdx.y * per + j;
+  const float g = gamma_d ? gamma_d[blockIdx.y] : gamma;
   const float t = s[i] + z[i];
-  const float tau = gamma * (W ? W[i] : 1.0f);
+  const float tau = g * (W ? W[i] : 1.0f);
   const float m = fabsf(t) - tau;
   const float y = m > 0.f ? copysignf(m, t) : 0.f;
   const float zn = t - y;
@@ -188,54 +196,62 @@ __global__ __launch_bounds__(256) void ball_project(const float2* __restrict__ s
   }
 }
 
-__global__ __launch_bounds__(256) void reweight_kernel(int64_t D, const float* __restrict__ c, double delta,
+__global__ __launch_bounds__(256) void reweight_kernel(int64_t per, const float* __restrict__ c,
+                                                       const double* __restrict__ delta_d, double delta,
                                                        float* __restrict__ W) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < D) W[i] = float(delta / (delta + fabs(double(c[i]))));
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= per) return;
+  const int64_t i = (int64_t)blockIdx.y * per + j;
+  const double dl = delta_d ? delta_d[blockIdx.y] : delta;
+  W[i] = float(dl / (dl + fabs(double(c[i]))));
 }
 
 }  // namespace
 
 namespace sh {
 
-sh_status Reducer::init() {
-  SH_TRY(part.alloc(RB * 2));
+sh_status Reducer::init(int segments) {
+  P = segments;
+  rb = RB / P > 1 ? RB / P : 1;   // about RB work-groups in all
+  SH_TRY(part.alloc(size_t(P) * rb));
   return SH_OK;
 }
 
-sh_status Reducer::dot(const float* a, const float* b, int64_t N, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(dot_partial, dim3(RB), dim3(256), 0, st, a, b, N, part.ptr);
-  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part.ptr, RB, out);
+sh_status Reducer::dot(const float* a, const float* b, int64_t per, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(dot_partial, dim3(rb, P), dim3(256), 0, st, a, b, per, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, out);
   SH_LAUNCHED();
   return SH_OK;
 }
 
-sh_status Reducer::std_dev(const float* a, int64_t N, double* sum_out, double* var_out, hipStream_t st) {
-  hipLaunchKernelGGL(mean_partial, dim3(RB), dim3(256), 0, st, a, N, part.ptr);
-  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part.ptr, RB, sum_out);
-  hipLaunchKernelGGL(var_partial, dim3(RB), dim3(256), 0, st, a, N, sum_out, part.ptr);
-  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part.ptr, RB, var_out);
+sh_status Reducer::std_dev(const float* a, int64_t per, double* sum_out, double* var_out, hipStream_t st) {
+  hipLaunchKernelGGL(mean_partial, dim3(rb, P), dim3(256), 0, st, a, per, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, sum_out);
+  hipLaunchKernelGGL(var_partial, dim3(rb, P), dim3(256), 0, st, a, per, sum_out, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, var_out);
   SH_LAUNCHED();
   return SH_OK;
 }
 
-sh_status Reducer::maxabs(const float* a, int64_t N, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(maxabs_partial, dim3(RB), dim3(256), 0, st, a, N, part.ptr);
-  hipLaunchKernelGGL(max_final, dim3(1), dim3(256), 0, st, part.ptr, RB, out);
+sh_status Reducer::maxabs(const float* a, int64_t per, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(maxabs_partial, dim3(rb, P), dim3(256), 0, st, a, per, part.ptr);
+  hipLaunchKernelGGL(max_final, dim3(P), dim3(256), 0, st, part.ptr, rb, out);
   SH_LAUNCHED();
   return SH_OK;
 }
 
-sh_status Reducer::l1w(const float* c, const float* W, int64_t N, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(l1w_partial, dim3(RB), dim3(256), 0, st, c, W, N, part.ptr);
-  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part.ptr, RB, out);
+sh_status Reducer::l1w(const float* c, const float* W, int64_t per, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(l1w_partial, dim3(rb, P), dim3(256), 0, st, c, W, per, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, out);
   SH_LAUNCHED();
   return SH_OK;
 }
 
-sh_status launch_prox_l1(int64_t D, const float* s, float* z, const float* W, float gamma, float* v, hipStream_t st) {
+sh_status launch_prox_l1(int64_t per, int P, const float* s, float* z, const float* W, const float* gamma_d,
+                         float gamma, float* v, hipStream_t st) {
   ProfScope ps("prox", st);
-  hipLaunchKernelGGL(prox_l1_kernel, dim3((unsigned)cdiv(D, 256)), dim3(256), 0, st, D, s, z, W, gamma, v);
+  hipLaunchKernelGGL(prox_l1_kernel, dim3((unsigned)cdiv(per, 256), P), dim3(256), 0, st, per, s, z, W, gamma_d,
+                     gamma, v);
   SH_LAUNCHED();
   return SH_OK;
 }
@@ -259,8 +275,9 @@ sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* y
   return SH_OK;
 }
 
-sh_status launch_reweight(int64_t D, const float* c, double delta, float* W, hipStream_t st) {
-  hipLaunchKernelGGL(reweight_kernel, dim3((unsigned)cdiv(D, 256)), dim3(256), 0, st, D, c, delta, W);
+sh_status launch_reweight(int64_t per, int P, const float* c, const double* delta_d, double delta, float* W,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(reweight_kernel, dim3((unsigned)cdiv(per, 256), P), dim3(256), 0, st, per, c, delta_d, delta, W);
   SH_LAUNCHED();
   return SH_OK;
 }
@@ -272,7 +289,7 @@ extern "C" {
 sh_status sh_prox_l1(int64_t D, const float* s, float* z, const float* W, float gamma, float* v_out, void* stream) {
   SH_REQUIRE(D >= 1 && s && z && v_out, "invalid argument");
   SH_REQUIRE(std::isfinite(gamma) && gamma >= 0.f, "gamma must be finite and >= 0");
-  return sh::launch_prox_l1(D, s, z, W, gamma, v_out, (hipStream_t)stream);
+  return sh::launch_prox_l1(D, 1, s, z, W, nullptr, gamma, v_out, (hipStream_t)stream);
 }
 
 sh_status sh_prox_pos(int64_t N, const float* s, float* z, float* v_out, void* stream) {
@@ -295,7 +312,7 @@ sh_status sh_prox_ball(sh_op op, const float* s, float* z, const float* yhat, co
 sh_status sh_reweight(int64_t D, const float* c, double delta, float* W_out, void* stream) {
   SH_REQUIRE(D >= 1 && c && W_out, "invalid argument");
   SH_REQUIRE(std::isfinite(delta) && delta > 0, "delta must be finite and > 0");
-  return sh::launch_reweight(D, c, delta, W_out, (hipStream_t)stream);
+  return sh::launch_reweight(D, 1, c, nullptr, delta, W_out, (hipStream_t)stream);
 }
 
 sh_status sh_std(int64_t D, const float* c, double* std_out, void* stream) {

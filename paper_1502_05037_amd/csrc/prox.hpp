@@ -5,20 +5,28 @@
 
 namespace sh {
 
-// Two-stage deterministic float64 reductions; results land in device memory.
+// Two-stage deterministic float64 reductions over P equal segments of length `per` (segment p is
+// a[p*per, (p+1)*per)); segment p's result lands in out[p] (device memory).  The tree depends only on
+// (per, P), so results are reproducible bit for bit.
 struct Reducer {
   DevBuf<double> part;
-  sh_status init();
-  sh_status dot(const float* a, const float* b, int64_t N, double* out, hipStream_t st);
-  sh_status std_dev(const float* a, int64_t N, double* sum_out, double* var_out, hipStream_t st);  // var_out = sum (a-mean)^2
-  sh_status maxabs(const float* a, int64_t N, double* out, hipStream_t st);
-  sh_status l1w(const float* c, const float* W, int64_t N, double* out, hipStream_t st);
+  int P = 1, rb = 512;   // segments, first-stage work-groups per segment
+  sh_status init(int segments = 1);
+  sh_status dot(const float* a, const float* b, int64_t per, double* out, hipStream_t st);
+  // sum_out[p] = sum of segment p, var_out[p] = sum of its squared deviations from its mean
+  sh_status std_dev(const float* a, int64_t per, double* sum_out, double* var_out, hipStream_t st);
+  sh_status maxabs(const float* a, int64_t per, double* out, hipStream_t st);
+  sh_status l1w(const float* c, const float* W, int64_t per, double* out, hipStream_t st);
 };
 
-sh_status launch_prox_l1(int64_t D, const float* s, float* z, const float* W, float gamma, float* v, hipStream_t st);
+// Elementwise proximal steps over P segments of length `per`; segment p uses gamma[p] / delta[p]
+// (device arrays) or, if those are NULL, the scalar.
+sh_status launch_prox_l1(int64_t per, int P, const float* s, float* z, const float* W, const float* gamma_d,
+                         float gamma, float* v, hipStream_t st);
 sh_status launch_prox_pos(int64_t N, const float* s, float* z, float* v, hipStream_t st);
 sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
                            double* resid, float2* v, bool sub_s, hipStream_t st);
-sh_status launch_reweight(int64_t D, const float* c, double delta, float* W, hipStream_t st);
+sh_status launch_reweight(int64_t per, int P, const float* c, const double* delta_d, double delta, float* W,
+                          hipStream_t st);
 
 }  // namespace sh

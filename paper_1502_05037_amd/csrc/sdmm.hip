@@ -14,6 +14,7 @@
 // reuses s_phi = Phi_hat x_{n-1} from the previous iteration, so one iteration costs
 // (cg_iters + 1) applications each of Phi and Phi^dagger.  CG scalars stay on the device.
 // Block norms, dot products, the stopping test and the reweighting statistics are float64.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <memory>
@@ -25,6 +26,7 @@ extern "C" sh_status sh_psi_fwd(sh_psi psi, const float* coeffs, float* x, void*
 extern "C" sh_status sh_psi_adj(sh_psi psi, const float* x, float* coeffs, void* stream);
 extern "C" sh_status sh_psi_planes(sh_psi psi, int32_t* q_out);
 int psi_side(sh_psi psi);
+int psi_batch(sh_psi psi);
 
 namespace {
 
@@ -33,17 +35,30 @@ __global__ void fill_kernel(float* a, int64_t N, float v) {
   if (i < N) a[i] = v;
 }
 
-__global__ void scale_kernel(const float* __restrict__ a, float* __restrict__ b, int64_t N, const double* __restrict__ nrm2) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const double n2 = nrm2[0];
-  const float s = n2 > 0 ? float(1.0 / sqrt(n2)) : 0.f;
-  if (i < N) b[i] = a[i] * s;
+// Per-problem kernels run on grid (cdiv(per, 256), P): element j of segment p = blockIdx.y.
+#define SEG_INDEX(per)                                      \
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; \
+  if (j >= (per)) return;                                   \
+  const int p = blockIdx.y;                                 \
+  const int64_t i = (int64_t)p * (per) + j;
+
+// b = a / sqrt(nrm2[p]) per segment
+__global__ void scale_kernel(const float* __restrict__ a, float* __restrict__ b, int64_t per,
+                             const double* __restrict__ nrm2) {
+  SEG_INDEX(per)
+  const double n2 = nrm2[p];
+  const float sc = n2 > 0 ? float(1.0 / sqrt(n2)) : 0.f;
+  b[i] = a[i] * sc;
 }
 
-__global__ void gather_scale(const float2* __restrict__ src, const uint32_t* __restrict__ idx, float2* __restrict__ dst,
-                             int64_t M, float s) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < M) {
+// yhat (internal order) = y[perm] / nu of the block's problem; one work-group per reduction chunk
+__global__ __launch_bounds__(256) void gather_scale(const float2* __restrict__ src, const uint32_t* __restrict__ idx,
+                                                    float2* __restrict__ dst, const int4* __restrict__ chunks,
+                                                    const int32_t* __restrict__ block_prob,
+                                                    const float* __restrict__ inv_nu) {
+  const int4 c = chunks[blockIdx.x];
+  const float s = inv_nu[block_prob[c.x]];
+  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
     const float2 v = src[idx[i]];
     dst[i] = make_float2(v.x * s, v.y * s);
   }
@@ -68,27 +83,26 @@ __global__ void cg_ap(const float* __restrict__ p, float* __restrict__ Ap, int64
   if (i < N) Ap[i] = 2.f * p[i] + Ap[i];
 }
 
-// alpha = rs / pAp; x += alpha p; r -= alpha Ap
-__global__ void cg_update(float* __restrict__ x, float* __restrict__ r, const float* __restrict__ p,
-                          const float* __restrict__ Ap, int64_t N, const double* __restrict__ rs,
+// per problem: alpha = rs / pAp; x += alpha p; r -= alpha Ap
+__global__ void cg_update(float* __restrict__ x, float* __restrict__ r, const float* __restrict__ pv,
+                          const float* __restrict__ Ap, int64_t per, const double* __restrict__ rs,
                           const double* __restrict__ pAp) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const double d = pAp[0];
-  const float alpha = d > 0 ? float(rs[0] / d) : 0.f;
-  if (i < N) {
-    x[i] = fmaf(alpha, p[i], x[i]);
-    r[i] = fmaf(-alpha, Ap[i], r[i]);
-  }
+  SEG_INDEX(per)
+  const double d = pAp[p];
+  const float alpha = d > 0 ? float(rs[p] / d) : 0.f;
+  x[i] = fmaf(alpha, pv[i], x[i]);
+  r[i] = fmaf(-alpha, Ap[i], r[i]);
 }
 
-// beta = rs_new / rs; p = r + beta p
-__global__ void cg_dir(const float* __restrict__ r, float* __restrict__ p, int64_t N, const double* __restrict__ rs,
+// per problem: beta = rs_new / rs; p = r + beta p
+__global__ void cg_dir(const float* __restrict__ r, float* __restrict__ pv, int64_t per, const double* __restrict__ rs,
                        const double* __restrict__ rs_new) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const double d = rs[0];
-  const float beta = d > 0 ? float(rs_new[0] / d) : 0.f;
-  if (i < N) p[i] = fmaf(beta, p[i], r[i]);
+  SEG_INDEX(per)
+  const double d = rs[p];
+  const float beta = d > 0 ? float(rs_new[p] / d) : 0.f;
+  pv[i] = fmaf(beta, pv[i], r[i]);
 }
+#undef SEG_INDEX
 
 __global__ void diff_kernel(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ c, int64_t N) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -101,13 +115,17 @@ struct Work {
   sh::DevBuf<float> x, xprev, r, p, Ap, t1, t2, vpos, zpos;
   sh::DevBuf<float> spsi, zpsi, vpsi, W;
   sh::DevBuf<float2> yhat, sphi, zphi, vphi, vtmp;
-  sh::DevBuf<double> sc, eps_hat, rho, resid;
+  sh::DevBuf<double> sc, eps_hat, rho, resid, delta;
+  sh::DevBuf<float> inv_nu, gamma;
   sh::Reducer red;
 };
 
-// Power iteration on Re(Phi^H Phi) (scale 1) from x0; returns sqrt of the Rayleigh quotient.
+// Power iteration on Re(Phi^H Phi) (scale 1) from x0, for the P problems of the plan at once (each
+// normalised and tested on its own); nu[p] = sqrt of problem p's Rayleigh quotient.  Stops when
+// every problem's estimate changed by <= tol relative, or after `iters` steps.
 sh_status power_norm(sh_op op, const float* x0, int iters, double tol, double* nu, hipStream_t st) {
-  const int64_t N = int64_t(op->n) * op->n;
+  const int P = op->P;
+  const int64_t per = int64_t(op->n) * op->n, N = per * P;
   sh::DevBuf<float> x, y;
   sh::DevBuf<float2> v;
   sh::DevBuf<double> sc;
@@ -115,30 +133,31 @@ sh_status power_norm(sh_op op, const float* x0, int iters, double tol, double* n
   SH_TRY(x.alloc(N));
   SH_TRY(y.alloc(N));
   SH_TRY(v.alloc(op->M));
-  SH_TRY(sc.alloc(4));
-  SH_TRY(red.init());
-  SH_TRY(red.dot(x0, x0, N, sc.ptr, st));
-  hipLaunchKernelGGL(scale_kernel, dim3(nblk(N)), dim3(256), 0, st, x0, x.ptr, N, sc.ptr);
-  double lam = 0.0;
+  SH_TRY(sc.alloc(3 * P));
+  SH_TRY(red.init(P));
+  SH_TRY(red.dot(x0, x0, per, sc.ptr, st));
+  hipLaunchKernelGGL(scale_kernel, dim3(nblk(per), P), dim3(256), 0, st, x0, x.ptr, per, sc.ptr);
+  std::vector<double> lam(P, 0.0), h(2 * P);
   for (int it = 0; it < iters; ++it) {
-    SH_TRY(sh::phi_forward(op, x.ptr, v.ptr, false, 1.f, st));
-    SH_TRY(sh::phi_adjoint(op, v.ptr, y.ptr, false, 1.f, st));
-    SH_TRY(red.dot(x.ptr, y.ptr, N, sc.ptr + 1, st));
-    SH_TRY(red.dot(y.ptr, y.ptr, N, sc.ptr + 2, st));
-    hipLaunchKernelGGL(scale_kernel, dim3(nblk(N)), dim3(256), 0, st, y.ptr, x.ptr, N, sc.ptr + 2);
-    double h[2];
-    SH_HIP(hipMemcpyAsync(h, sc.ptr + 1, sizeof(h), hipMemcpyDeviceToHost, st));
+    SH_TRY(sh::phi_forward(op, x.ptr, v.ptr, false, nullptr, st));
+    SH_TRY(sh::phi_adjoint(op, v.ptr, y.ptr, false, nullptr, st));
+    SH_TRY(red.dot(x.ptr, y.ptr, per, sc.ptr + P, st));
+    SH_TRY(red.dot(y.ptr, y.ptr, per, sc.ptr + 2 * P, st));
+    hipLaunchKernelGGL(scale_kernel, dim3(nblk(per), P), dim3(256), 0, st, y.ptr, x.ptr, per, sc.ptr + 2 * P);
+    SH_HIP(hipMemcpyAsync(h.data(), sc.ptr + P, 2 * P * sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));
-    if (!std::isfinite(h[0]) || !std::isfinite(h[1])) {
-      sh::set_error("non-finite value in power iteration");
-      return SH_ENONFINITE;
+    bool done = true;
+    for (int p = 0; p < P; ++p) {
+      if (!std::isfinite(h[p]) || !std::isfinite(h[P + p])) {
+        sh::set_error("non-finite value in power iteration (problem %d)", p);
+        return SH_ENONFINITE;
+      }
+      done = done && lam[p] > 0 && std::fabs(h[p] - lam[p]) <= tol * h[p];
+      lam[p] = h[p];
     }
-    const double lam_new = h[0];
-    const bool done = lam > 0 && std::fabs(lam_new - lam) <= tol * lam_new;
-    lam = lam_new;
     if (done) break;
   }
-  *nu = std::sqrt(std::max(lam, 0.0));
+  for (int p = 0; p < P; ++p) nu[p] = std::sqrt(std::max(lam[p], 0.0));
   return SH_OK;
 }
 
@@ -158,6 +177,7 @@ void sh_sdmm_default_params(sh_sdmm_params* p) {
   p->cg_iters = 8;
   p->passes = 1;
   p->check_every = 10;
+  p->graph = 1;
 }
 
 sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream) {
@@ -173,82 +193,116 @@ struct sh_sdmm_s {
   sh_psi psi = nullptr;
   sh_sdmm_params prm{};
   Work w;
-  int64_t N = 0, M = 0, D = 0;
+  int P = 1;
+  int64_t per = 0, Dper = 0;       // pixels and coefficients of one problem
+  int64_t N = 0, M = 0, D = 0;     // totals over the P problems
   int R = 0, kcg = 0;
-  double nu = 0, gamma = 0, delta = 0;
-  float inv_nu = 1.f;
-  std::vector<double> eh;          // eps / nu (host)
+  std::vector<double> nu, gamma, delta;   // per problem
+  std::vector<double> eh;          // eps / nu per block (host)
   const float* Wp = nullptr;       // weights of the current pass (NULL = identity)
   int iters_total = 0;
   double *s_rs = nullptr, *s_pap = nullptr, *s_misc = nullptr;
+  // Replay of one captured iteration (hipGraph) on a session-owned stream.
+  hipStream_t gs = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const float* g_Wp = nullptr;     // the weights pointer baked into gexec
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  ~sh_sdmm_s() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gs) {
+      (void)hipStreamSynchronize(gs);
+      (void)hipStreamDestroy(gs);
+    }
+  }
 };
 
 namespace {
 
+// s_misc layout: [0, P) dx^2, [P, 2P) x^2, [2P, 3P) scratch, [3P, 4P) objective, [4P, 5P) scratch
+enum { MISC_DX = 0, MISC_X = 1, MISC_TMP = 2, MISC_OBJ = 3, MISC_TMP2 = 4, MISC_N = 5 };
+
 sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* W0, const float* x0, hipStream_t st) {
   sh_op op = s->op;
-  const int R = s->R;
+  const int R = s->R, P = s->P;
   const int64_t N = s->N, M = s->M, D = s->D;
   const int kcg = s->kcg;
   Work& w = s->w;
   for (auto* b : {&w.x, &w.xprev, &w.r, &w.p, &w.Ap, &w.t1, &w.t2, &w.vpos, &w.zpos}) SH_TRY(b->alloc(N));
   for (auto* b : {&w.spsi, &w.zpsi, &w.vpsi, &w.W}) SH_TRY(b->alloc(D));
   for (auto* b : {&w.yhat, &w.sphi, &w.zphi, &w.vphi, &w.vtmp}) SH_TRY(b->alloc(M));
-  SH_TRY(w.sc.alloc(2 * kcg + 16));
+  const int nsc = (2 * kcg + 1 + MISC_N) * P;
+  SH_TRY(w.sc.alloc(nsc));
   SH_TRY(w.eps_hat.alloc(R));
   SH_TRY(w.rho.alloc(R));
   SH_TRY(w.resid.alloc(R));
-  SH_TRY(w.red.init());
+  SH_TRY(w.delta.alloc(P));
+  SH_TRY(w.inv_nu.alloc(P));
+  SH_TRY(w.gamma.alloc(P));
+  SH_TRY(w.red.init(P));
   double* sc = w.sc.ptr;
-  s->s_rs = sc;                  // rs_k, k = 0..kcg
-  s->s_pap = sc + kcg + 1;       // pAp_k, k = 0..kcg-1
-  s->s_misc = sc + 2 * kcg + 2;  // [0] dx^2, [1] x^2, [2] scratch, [3] objective, [4] scratch
+  s->s_rs = sc;                        // rs_k of problem p at [k*P + p], k = 0..kcg
+  s->s_pap = sc + (kcg + 1) * P;       // pAp_k at [k*P + p], k = 0..kcg-1
+  s->s_misc = sc + (2 * kcg + 1) * P;  // MISC_* blocks of P
   double* s_misc = s->s_misc;
   SH_HIP(hipMemsetAsync(w.resid.ptr, 0, R * sizeof(double), st));
-  SH_HIP(hipMemsetAsync(w.sc.ptr, 0, (2 * kcg + 16) * sizeof(double), st));
+  SH_HIP(hipMemsetAsync(w.sc.ptr, 0, nsc * sizeof(double), st));
 
   // non-finite data check (float64 sum of squares)
-  SH_TRY(w.red.dot(y, y, 2 * M, s_misc + 2, st));
+  {
+    sh::Reducer r1;
+    SH_TRY(r1.init(1));
+    SH_TRY(r1.dot(y, y, 2 * M, s_misc + MISC_TMP * P, st));
+  }
   double ysq = 0;
-  SH_HIP(hipMemcpyAsync(&ysq, s_misc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipMemcpyAsync(&ysq, s_misc + MISC_TMP * P, sizeof(double), hipMemcpyDeviceToHost, st));
   SH_HIP(hipStreamSynchronize(st));
   if (!std::isfinite(ysq)) {
     sh::set_error("visibilities contain non-finite values");
     return SH_ENONFINITE;
   }
-  // normalisation nu
-  double nu = s->prm.nu;
-  if (!(nu > 0)) {
+  // normalisation nu per problem
+  s->nu.assign(P, s->prm.nu);
+  if (!(s->prm.nu > 0)) {
     hipLaunchKernelGGL(fill_kernel, dim3(nblk(N)), dim3(256), 0, st, w.t1.ptr, N, 1.f);
-    SH_TRY(power_norm(op, w.t1.ptr, 200, 1e-12, &nu, st));
+    SH_TRY(power_norm(op, w.t1.ptr, 200, 1e-12, s->nu.data(), st));
   }
-  SH_REQUIRE(nu > 0 && std::isfinite(nu), "operator norm must be positive");
-  s->nu = nu;
-  s->inv_nu = float(1.0 / nu);
-  hipLaunchKernelGGL(gather_scale, dim3(nblk(M)), dim3(256), 0, st, (const float2*)y, op->perm.ptr, w.yhat.ptr, M,
-                     s->inv_nu);
+  std::vector<float> inv(P);
+  for (int p = 0; p < P; ++p) {
+    SH_REQUIRE(s->nu[p] > 0 && std::isfinite(s->nu[p]), "operator norm of problem %d must be positive", p);
+    inv[p] = float(1.0 / s->nu[p]);
+  }
+  SH_HIP(hipMemcpy(w.inv_nu.ptr, inv.data(), P * sizeof(float), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(gather_scale, dim3((unsigned)op->n_chunks), dim3(256), 0, st, (const float2*)y, op->perm.ptr,
+                     w.yhat.ptr, op->chunks.ptr, op->block_prob_d.ptr, w.inv_nu.ptr);
+  SH_LAUNCHED();
   s->eh.resize(R);
-  for (int i = 0; i < R; ++i) s->eh[i] = eps[i] / nu;
+  for (int i = 0; i < R; ++i) s->eh[i] = eps[i] / s->nu[op->block_prob[i]];
   SH_HIP(hipMemcpyAsync(w.eps_hat.ptr, s->eh.data(), R * sizeof(double), hipMemcpyHostToDevice, st));
-  // gamma = 1e-3 max |Psi^dagger Phi^dagger y| / nu^2 unless given
-  double gamma = s->prm.gamma;
-  if (!(gamma > 0)) {
-    SH_TRY(sh::phi_adjoint(op, (const float2*)y, w.t1.ptr, true, 1.f, st));
+  // gamma = 1e-3 max |Psi^dagger Phi^dagger y| / nu^2 per problem unless given
+  s->gamma.assign(P, s->prm.gamma);
+  if (!(s->prm.gamma > 0)) {
+    SH_TRY(sh::phi_adjoint(op, (const float2*)y, w.t1.ptr, true, nullptr, st));
     SH_TRY(sh_psi_adj(s->psi, w.t1.ptr, w.spsi.ptr, st));
-    SH_TRY(w.red.maxabs(w.spsi.ptr, D, s_misc + 2, st));
-    double mx = 0;
-    SH_HIP(hipMemcpyAsync(&mx, s_misc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    SH_TRY(w.red.maxabs(w.spsi.ptr, s->Dper, s_misc + MISC_TMP * P, st));
+    std::vector<double> mx(P);
+    SH_HIP(hipMemcpyAsync(mx.data(), s_misc + MISC_TMP * P, P * sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));
-    gamma = 1e-3 * mx / (nu * nu);
+    for (int p = 0; p < P; ++p) s->gamma[p] = 1e-3 * mx[p] / (s->nu[p] * s->nu[p]);
   }
-  SH_REQUIRE(gamma > 0 && std::isfinite(gamma), "gamma must be positive (is y zero?)");
-  s->gamma = gamma;
+  std::vector<float> gf(P);
+  for (int p = 0; p < P; ++p) {
+    SH_REQUIRE(s->gamma[p] > 0 && std::isfinite(s->gamma[p]), "gamma of problem %d must be positive (is y zero?)", p);
+    gf[p] = float(s->gamma[p]);
+  }
+  SH_HIP(hipMemcpy(w.gamma.ptr, gf.data(), P * sizeof(float), hipMemcpyHostToDevice));
   // weights of the first pass
   if (W0) {
     SH_HIP(hipMemcpyAsync(w.W.ptr, W0, D * sizeof(float), hipMemcpyDeviceToDevice, st));
     s->Wp = w.W.ptr;
   }
-  s->delta = s->prm.rw_delta0 > 0 && W0 ? s->prm.rw_delta0 : 0.0;
+  s->delta.assign(P, s->prm.rw_delta0 > 0 && W0 ? s->prm.rw_delta0 : 0.0);
   // initial state: zero, or y_psi = Psi^dagger x0, y_phi = Phi_hat x0, y_+ = x0, z = 0
   SH_HIP(hipMemsetAsync(w.zpsi.ptr, 0, D * sizeof(float), st));
   SH_HIP(hipMemsetAsync(w.zphi.ptr, 0, M * sizeof(float2), st));
@@ -258,7 +312,7 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     SH_HIP(hipMemcpyAsync(w.x.ptr, x0, N * sizeof(float), hipMemcpyDeviceToDevice, st));
     SH_HIP(hipMemcpyAsync(w.vpos.ptr, x0, N * sizeof(float), hipMemcpyDeviceToDevice, st));
     SH_TRY(sh_psi_adj(s->psi, x0, w.vpsi.ptr, st));
-    SH_TRY(sh::phi_forward(op, x0, w.sphi.ptr, false, s->inv_nu, st));
+    SH_TRY(sh::phi_forward(op, x0, w.sphi.ptr, false, w.inv_nu.ptr, st));
   } else {
     SH_HIP(hipMemsetAsync(w.x.ptr, 0, N * sizeof(float), st));
     SH_HIP(hipMemsetAsync(w.vpos.ptr, 0, N * sizeof(float), st));
@@ -269,91 +323,163 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   return SH_OK;
 }
 
-// One SDMM iteration, enqueued on `st` with no host synchronisation.
+// One SDMM iteration of all P problems, enqueued on `st` with no host synchronisation, no memset
+// and no allocation (so that it can be captured into a graph).
 sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   sh_op op = s->op;
   Work& w = s->w;
-  const int64_t N = s->N, D = s->D;
+  const int P = s->P;
+  const int64_t N = s->N, per = s->per;
   const unsigned gN = nblk(N);
-  const float inv_nu = s->inv_nu;
+  const dim3 gP(nblk(per), P);
+  const float* inv_nu = w.inv_nu.ptr;
   double *s_rs = s->s_rs, *s_pap = s->s_pap, *s_misc = s->s_misc;
   // ---- x-update by CG from x_{n-1}
   SH_TRY(sh_psi_fwd(s->psi, w.vpsi.ptr, w.t1.ptr, st));
   SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.t2.ptr, false, inv_nu, st));
   hipLaunchKernelGGL(cg_init, dim3(gN), dim3(256), 0, st, w.t1.ptr, w.t2.ptr, w.vpos.ptr, w.x.ptr, w.r.ptr, w.p.ptr,
                      w.xprev.ptr, N);
-  SH_TRY(w.red.dot(w.r.ptr, w.r.ptr, N, s_rs, st));
+  SH_TRY(w.red.dot(w.r.ptr, w.r.ptr, per, s_rs, st));
   for (int k = 0; k < s->kcg; ++k) {
     SH_TRY(sh::phi_forward(op, w.p.ptr, w.vtmp.ptr, false, inv_nu, st));
     SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.Ap.ptr, false, inv_nu, st));
     hipLaunchKernelGGL(cg_ap, dim3(gN), dim3(256), 0, st, w.p.ptr, w.Ap.ptr, N);
-    SH_TRY(w.red.dot(w.p.ptr, w.Ap.ptr, N, s_pap + k, st));
-    hipLaunchKernelGGL(cg_update, dim3(gN), dim3(256), 0, st, w.x.ptr, w.r.ptr, w.p.ptr, w.Ap.ptr, N, s_rs + k,
-                       s_pap + k);
+    SH_TRY(w.red.dot(w.p.ptr, w.Ap.ptr, per, s_pap + k * P, st));
+    hipLaunchKernelGGL(cg_update, gP, dim3(256), 0, st, w.x.ptr, w.r.ptr, w.p.ptr, w.Ap.ptr, per, s_rs + k * P,
+                       s_pap + k * P);
     if (k + 1 < s->kcg) {
-      SH_TRY(w.red.dot(w.r.ptr, w.r.ptr, N, s_rs + k + 1, st));
-      hipLaunchKernelGGL(cg_dir, dim3(gN), dim3(256), 0, st, w.r.ptr, w.p.ptr, N, s_rs + k, s_rs + k + 1);
+      SH_TRY(w.red.dot(w.r.ptr, w.r.ptr, per, s_rs + (k + 1) * P, st));
+      hipLaunchKernelGGL(cg_dir, gP, dim3(256), 0, st, w.r.ptr, w.p.ptr, per, s_rs + k * P, s_rs + (k + 1) * P);
     }
   }
   SH_LAUNCHED();
   // ---- relative change
   hipLaunchKernelGGL(diff_kernel, dim3(gN), dim3(256), 0, st, w.x.ptr, w.xprev.ptr, w.t1.ptr, N);
-  SH_TRY(w.red.dot(w.t1.ptr, w.t1.ptr, N, s_misc, st));
-  SH_TRY(w.red.dot(w.x.ptr, w.x.ptr, N, s_misc + 1, st));
+  SH_TRY(w.red.dot(w.t1.ptr, w.t1.ptr, per, s_misc + MISC_DX * P, st));
+  SH_TRY(w.red.dot(w.x.ptr, w.x.ptr, per, s_misc + MISC_X * P, st));
   // ---- splits
   SH_TRY(sh_psi_adj(s->psi, w.x.ptr, w.spsi.ptr, st));
-  SH_TRY(sh::launch_prox_l1(D, w.spsi.ptr, w.zpsi.ptr, s->Wp, float(s->gamma), w.vpsi.ptr, st));
+  SH_TRY(sh::launch_prox_l1(s->Dper, P, w.spsi.ptr, w.zpsi.ptr, s->Wp, w.gamma.ptr, 0.f, w.vpsi.ptr, st));
   SH_TRY(sh::phi_forward(op, w.x.ptr, w.sphi.ptr, false, inv_nu, st));
   SH_TRY(sh::launch_prox_ball(op, w.sphi.ptr, w.zphi.ptr, w.yhat.ptr, w.eps_hat.ptr, w.rho.ptr, w.resid.ptr,
                               w.vphi.ptr, true, st));
   SH_TRY(sh::launch_prox_pos(N, w.x.ptr, w.zpos.ptr, w.vpos.ptr, st));
-  s->iters_total += 1;
   return SH_OK;
 }
 
-// Reads the stopping quantities of the last iteration (synchronises): rel change, residuals (hat units).
-sh_status sdmm_read(sh_sdmm s, double* rel, std::vector<double>& hres, hipStream_t st) {
-  double h[2];
-  SH_HIP(hipMemcpyAsync(h, s->s_misc, sizeof(h), hipMemcpyDeviceToHost, st));
+// Captures one iteration into an executable graph on the session stream (again whenever the
+// weights pointer, the only launch argument that changes between passes, differs).
+sh_status sdmm_graph(sh_sdmm s) {
+  if (s->gexec && s->g_Wp == s->Wp) return SH_OK;
+  if (!s->gs) {
+    SH_HIP(hipStreamCreateWithFlags(&s->gs, hipStreamNonBlocking));
+    SH_HIP(hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming));
+    SH_HIP(hipEventCreateWithFlags(&s->ev_out, hipEventDisableTiming));
+  }
+  if (s->gexec) {
+    SH_HIP(hipStreamSynchronize(s->gs));
+    SH_HIP(hipGraphExecDestroy(s->gexec));
+    s->gexec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  SH_HIP(hipStreamBeginCapture(s->gs, hipStreamCaptureModeThreadLocal));
+  const sh_status st = sdmm_step(s, s->gs);
+  const hipError_t e = hipStreamEndCapture(s->gs, &g);
+  if (st != SH_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) {
+    sh::set_error("graph capture of the SDMM iteration failed: %s", hipGetErrorString(e));
+    return SH_EDEVICE;
+  }
+  const hipError_t ei = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    s->gexec = nullptr;
+    sh::set_error("graph instantiation failed: %s", hipGetErrorString(ei));
+    return SH_EDEVICE;
+  }
+  s->g_Wp = s->Wp;
+  return SH_OK;
+}
+
+// Enqueue `iters` iterations on `st`: replayed graphs (ordered after and before the caller's stream
+// by events) or, with graphs off or kernel timing on, plain launches.
+sh_status sdmm_run(sh_sdmm s, int iters, hipStream_t st) {
+  if (iters <= 0) return SH_OK;
+  if (!s->prm.graph || sh::profiling_on()) {
+    for (int i = 0; i < iters; ++i) SH_TRY(sdmm_step(s, st));
+  } else {
+    SH_TRY(sdmm_graph(s));
+    SH_HIP(hipEventRecord(s->ev_in, st));
+    SH_HIP(hipStreamWaitEvent(s->gs, s->ev_in, 0));
+    for (int i = 0; i < iters; ++i) SH_HIP(hipGraphLaunch(s->gexec, s->gs));
+    SH_HIP(hipEventRecord(s->ev_out, s->gs));
+    SH_HIP(hipStreamWaitEvent(st, s->ev_out, 0));
+  }
+  s->iters_total += iters;
+  return SH_OK;
+}
+
+// Reads the stopping quantities of the last iteration (synchronises): per-problem relative change,
+// per-block residuals (hat units).
+sh_status sdmm_read(sh_sdmm s, std::vector<double>& rel, std::vector<double>& hres, hipStream_t st) {
+  const int P = s->P;
+  std::vector<double> h(2 * P);
+  SH_HIP(hipMemcpyAsync(h.data(), s->s_misc, 2 * P * sizeof(double), hipMemcpyDeviceToHost, st));
   hres.resize(s->R);
   SH_HIP(hipMemcpyAsync(hres.data(), s->w.resid.ptr, s->R * sizeof(double), hipMemcpyDeviceToHost, st));
   SH_HIP(hipStreamSynchronize(st));
-  if (!std::isfinite(h[0]) || !std::isfinite(h[1])) {
-    sh::set_error("non-finite iterate after %d iterations", s->iters_total);
-    return SH_ENONFINITE;
+  rel.resize(P);
+  for (int p = 0; p < P; ++p) {
+    const double dx = h[MISC_DX * P + p], xx = h[MISC_X * P + p];
+    if (!std::isfinite(dx) || !std::isfinite(xx)) {
+      sh::set_error("non-finite iterate in problem %d after %d iterations", p, s->iters_total);
+      return SH_ENONFINITE;
+    }
+    rel[p] = xx > 0 ? std::sqrt(dx / xx) : (dx == 0 ? 0.0 : INFINITY);
   }
-  *rel = h[1] > 0 ? std::sqrt(h[0] / h[1]) : (h[0] == 0 ? 0.0 : INFINITY);
   return SH_OK;
 }
 
-// Reweighting after a pass: delta_1 = std(Psi^dagger x) (float64), then delta <- beta delta.
+// Reweighting after a pass: delta_1 = std(Psi^dagger x) per problem (float64), then delta <- beta delta.
 sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st) {
   Work& w = s->w;
-  if (!(s->delta > 0)) {
-    // sum of the coefficients in s_misc[2], sum of squared deviations in s_misc[4]
-    SH_TRY(w.red.std_dev(w.spsi.ptr, s->D, s->s_misc + 2, s->s_misc + 4, st));
-    double var_sum = 0;
-    SH_HIP(hipMemcpyAsync(&var_sum, s->s_misc + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+  const int P = s->P;
+  if (!(s->delta[0] > 0)) {
+    double* sum = s->s_misc + MISC_TMP * P;
+    double* var = s->s_misc + MISC_TMP2 * P;
+    SH_TRY(w.red.std_dev(w.spsi.ptr, s->Dper, sum, var, st));
+    std::vector<double> v(P);
+    SH_HIP(hipMemcpyAsync(v.data(), var, P * sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));
-    s->delta = std::sqrt(var_sum / double(s->D));
+    for (int p = 0; p < P; ++p) s->delta[p] = std::sqrt(v[p] / double(s->Dper));
   } else {
-    s->delta *= s->prm.rw_beta;
+    for (int p = 0; p < P; ++p) s->delta[p] *= s->prm.rw_beta;
   }
-  if (!(s->delta > 0) || !std::isfinite(s->delta)) {
-    sh::set_error("reweighting delta is %g (zero image?)", s->delta);
-    return s->delta == 0 ? SH_EINVAL : SH_ENONFINITE;
-  }
-  return sh::launch_reweight(s->D, w.spsi.ptr, s->delta, W_dst, st);
+  for (int p = 0; p < P; ++p)
+    if (!(s->delta[p] > 0) || !std::isfinite(s->delta[p])) {
+      sh::set_error("reweighting delta of problem %d is %g (zero image?)", p, s->delta[p]);
+      return s->delta[p] == 0 ? SH_EINVAL : SH_ENONFINITE;
+    }
+  SH_HIP(hipMemcpyAsync(w.delta.ptr, s->delta.data(), P * sizeof(double), hipMemcpyHostToDevice, st));
+  SH_TRY(sh::launch_reweight(s->Dper, P, w.spsi.ptr, w.delta.ptr, 0.0, W_dst, st));
+  SH_HIP(hipStreamSynchronize(st));   // the host copy of delta is read by the enqueued copy
+  return SH_OK;
 }
 
 sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps, const sh_sdmm_params* prm) {
   SH_REQUIRE(op && psi && y && eps && prm, "NULL argument");
   SH_REQUIRE(psi_side(psi) == op->n, "psi and op image sides differ");
+  SH_REQUIRE(psi_batch(psi) == op->P, "psi batch (%d) must equal the number of problems of op (%d)", psi_batch(psi),
+             op->P);
   SH_REQUIRE(prm->max_iter >= 1 && prm->cg_iters >= 1 && prm->cg_iters <= 64 && prm->passes >= 1 &&
                  prm->check_every >= 1,
              "max_iter, passes, check_every >= 1 and cg_iters in [1, 64] required");
   SH_REQUIRE(prm->tol_rel >= 0 && prm->eps_slack >= 0 && prm->rw_beta > 0 && std::isfinite(prm->rw_beta),
              "tol_rel, eps_slack >= 0 and rw_beta > 0 required");
+  SH_REQUIRE(prm->graph == 0 || prm->graph == 1, "graph must be 0 or 1");
   for (int i = 0; i < op->R; ++i) {
     if (!std::isfinite(eps[i])) {
       sh::set_error("eps[%d] is not finite", i);
@@ -383,9 +509,12 @@ sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps
   s->prm = *params;
   int32_t q = 0;
   sh_psi_planes(psi, &q);
-  s->N = int64_t(op->n) * op->n;
+  s->P = op->P;
+  s->per = int64_t(op->n) * op->n;
+  s->Dper = int64_t(q) * s->per;
+  s->N = s->per * s->P;
   s->M = op->M;
-  s->D = int64_t(q) * s->N;
+  s->D = s->Dper * s->P;
   s->R = op->R;
   s->kcg = params->cg_iters;
   sh_status st = sdmm_setup(s, y, eps, W, x0, (hipStream_t)stream);
@@ -400,20 +529,19 @@ sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps
 
 sh_status sh_sdmm_iterate(sh_sdmm s, int32_t iters, void* stream) {
   SH_REQUIRE(s && iters >= 0, "invalid argument");
-  for (int i = 0; i < iters; ++i) SH_TRY(sdmm_step(s, (hipStream_t)stream));
-  return SH_OK;
+  return sdmm_run(s, iters, (hipStream_t)stream);
 }
 
 sh_status sh_sdmm_result(sh_sdmm s, float* x_out, double* block_resid, double* rel_change, void* stream) {
   SH_REQUIRE(s, "NULL session");
   hipStream_t st = (hipStream_t)stream;
   if (x_out) SH_HIP(hipMemcpyAsync(x_out, s->w.x.ptr, s->N * sizeof(float), hipMemcpyDeviceToDevice, st));
-  double rel = 0;
-  std::vector<double> hres;
-  SH_TRY(sdmm_read(s, &rel, hres, st));
+  std::vector<double> rel, hres;
+  SH_TRY(sdmm_read(s, rel, hres, st));
   if (block_resid)
-    for (int i = 0; i < s->R; ++i) block_resid[i] = hres[i] * s->nu;
-  if (rel_change) *rel_change = rel;
+    for (int i = 0; i < s->R; ++i) block_resid[i] = hres[i] * s->nu[s->op->block_prob[i]];
+  if (rel_change)
+    for (int p = 0; p < s->P; ++p) rel_change[p] = rel[p];
   return SH_OK;
 }
 
@@ -431,52 +559,89 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
   SH_TRY(sh_sdmm_create(op, psi, y, eps, W0, x0, prm, &s, stream));
   std::unique_ptr<sh_sdmm_s> guard(s);
   hipStream_t st = (hipStream_t)stream;
-  sh_sdmm_info inf{};
-  inf.gamma = s->gamma;
-  inf.nu = s->nu;
-  std::vector<double> hres;
-  double rel = INFINITY;
-  bool converged = false;
-  int it_last = 0;
+  const int P = s->P;
+  const int64_t per = s->per;
+  std::vector<double> rel(P, INFINITY), hres;
+  std::vector<int> conv(P, 0), it_conv(P, 0);
+  // In the last pass a problem that meets the stopping test is final at that iteration: its image,
+  // residuals and relative change are taken then, while the batch iterates on for the others.
+  std::vector<int> taken(P, 0);
+  std::vector<double> rel_out(P, INFINITY), res_out(s->R, 0.0);
+  int it_last = 0, iters_total = 0, passes_done = 0;
   for (int pass = 0; pass < prm->passes; ++pass) {
-    converged = false;
+    const bool last = pass + 1 == prm->passes;
+    std::fill(conv.begin(), conv.end(), 0);
     int it = 0;
     while (it < prm->max_iter) {
-      SH_TRY(sdmm_step(s, st));
-      ++it;
-      if (prm->tol_rel > 0 && (it % prm->check_every == 0 || it == prm->max_iter)) {
-        SH_TRY(sdmm_read(s, &rel, hres, st));
-        bool feas = true;
-        for (int i = 0; i < s->R; ++i) feas = feas && hres[i] <= s->eh[i] * (1.0 + prm->eps_slack);
-        if (rel <= prm->tol_rel && feas) {
-          converged = true;
-          break;
+      // without a stopping test, the whole pass is enqueued at once
+      const int chunk = prm->tol_rel > 0 ? std::min(prm->check_every, prm->max_iter - it) : prm->max_iter - it;
+      SH_TRY(sdmm_run(s, chunk, st));
+      it += chunk;
+      if (prm->tol_rel > 0) {
+        SH_TRY(sdmm_read(s, rel, hres, st));
+        bool all = true;
+        for (int p = 0; p < P; ++p) {
+          if (!conv[p]) {
+            bool ok = rel[p] <= prm->tol_rel;
+            for (int i = op->block_off[p]; ok && i < op->block_off[p + 1]; ++i)
+              ok = hres[i] <= s->eh[i] * (1.0 + prm->eps_slack);
+            if (ok) {
+              conv[p] = 1;
+              it_conv[p] = it;
+              if (last) {
+                SH_HIP(hipMemcpyAsync(x_out + p * per, s->w.x.ptr + p * per, per * sizeof(float),
+                                      hipMemcpyDeviceToDevice, st));
+                taken[p] = 1;
+                rel_out[p] = rel[p];
+                for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] * s->nu[p];
+              }
+            }
+          }
+          all = all && conv[p];
         }
+        if (all) break;
       }
     }
     it_last = it;
-    inf.iters_total += it;
-    inf.passes_done = pass + 1;
-    // objective with this pass's weights; spsi holds Psi^dagger x_n
-    if (pass + 1 == prm->passes) SH_TRY(s->w.red.l1w(s->w.spsi.ptr, s->Wp, s->D, s->s_misc + 3, st));
-    // reweight for the next pass (or for W_out after the last one)
-    if (pass + 1 < prm->passes) {
+    iters_total += it;
+    passes_done = pass + 1;
+    if (!last) {  // reweight for the next pass from Psi^dagger x_n (in spsi)
       SH_TRY(sdmm_reweight(s, s->w.W.ptr, st));
       s->Wp = s->w.W.ptr;
-    } else if (W_out) {
-      SH_TRY(sdmm_reweight(s, W_out, st));
     }
   }
-  double obj = 0;
-  SH_HIP(hipMemcpyAsync(&obj, s->s_misc + 3, sizeof(double), hipMemcpyDeviceToHost, st));
-  SH_TRY(sh_sdmm_result(s, x_out, block_resid, &rel, stream));
-  inf.converged = converged ? 1 : 0;
-  inf.iters_last = it_last;
-  inf.rel_change = rel;
-  inf.objective = obj;
-  inf.delta = s->delta;
-  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-  if (info) *info = inf;
+  // the problems not taken at their stopping iteration end with the current iterate
+  SH_TRY(sdmm_read(s, rel, hres, st));
+  for (int p = 0; p < P; ++p) {
+    if (taken[p]) continue;
+    SH_HIP(hipMemcpyAsync(x_out + p * per, s->w.x.ptr + p * per, per * sizeof(float), hipMemcpyDeviceToDevice, st));
+    rel_out[p] = rel[p];
+    for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] * s->nu[p];
+  }
+  // objective with the last pass's weights and W_out, both from Psi^dagger of the returned images
+  SH_TRY(sh_psi_adj(s->psi, x_out, s->w.spsi.ptr, st));
+  SH_TRY(s->w.red.l1w(s->w.spsi.ptr, s->Wp, s->Dper, s->s_misc + MISC_OBJ * P, st));
+  if (W_out) SH_TRY(sdmm_reweight(s, W_out, st));
+  std::vector<double> obj(P);
+  SH_HIP(hipMemcpyAsync(obj.data(), s->s_misc + MISC_OBJ * P, P * sizeof(double), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipStreamSynchronize(st));
+  if (block_resid) std::copy(res_out.begin(), res_out.end(), block_resid);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (info)
+    for (int p = 0; p < P; ++p) {
+      sh_sdmm_info& inf = info[p];
+      inf = sh_sdmm_info{};
+      inf.iters_total = iters_total;
+      inf.passes_done = passes_done;
+      inf.converged = conv[p];
+      inf.iters_last = conv[p] ? it_conv[p] : it_last;
+      inf.rel_change = rel_out[p];
+      inf.objective = obj[p];
+      inf.gamma = s->gamma[p];
+      inf.nu = s->nu[p];
+      inf.delta = s->delta[p];
+      inf.seconds = secs;
+    }
   return SH_OK;
 }
 

@@ -39,7 +39,7 @@ class SarahipError(RuntimeError):
 class SdmmParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("nu", C.c_double), ("tol_rel", C.c_double), ("eps_slack", C.c_double),
                 ("rw_beta", C.c_double), ("rw_delta0", C.c_double), ("max_iter", C.c_int32),
-                ("cg_iters", C.c_int32), ("passes", C.c_int32), ("check_every", C.c_int32)]
+                ("cg_iters", C.c_int32), ("passes", C.c_int32), ("check_every", C.c_int32), ("graph", C.c_int32)]
 
 
 class SdmmInfo(C.Structure):
@@ -54,11 +54,14 @@ class SdmmInfo(C.Structure):
 _vp, _i64, _i32, _u32, _f32, _f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_float, C.c_double
 _P64 = C.POINTER(C.c_double)
 _PI64 = C.POINTER(C.c_int64)
+_PI32 = C.POINTER(C.c_int32)
 _SIGS = {
     "sh_last_error": (C.c_char_p, []),
     "sh_version": (C.c_char_p, []),
     "sh_op_create": (C.c_int, [_P64, _i64, _i32, _i32, _i32, _PI64, _i32, C.POINTER(_vp)]),
     "sh_op_create_tuned": (C.c_int, [_P64, _i64, _i32, _i32, _i32, _PI64, _i32, _i32, _i32, C.POINTER(_vp)]),
+    "sh_op_create_batched": (C.c_int, [_P64, _PI64, _i32, _i32, _i32, _i32, _PI64, _PI32, _i32, _i32,
+                                       C.POINTER(_vp)]),
     "sh_op_destroy": (C.c_int, [_vp]),
     "sh_op_query": (C.c_int, [_vp, _PI64]),
     "sh_op_block_offsets": (C.c_int, [_vp, _PI64]),
@@ -71,6 +74,7 @@ _SIGS = {
     "sh_vis_to_user": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sh_op_norm": (C.c_int, [_vp, _vp, _i32, _f64, _P64, _vp]),
     "sh_psi_create": (C.c_int, [_i32, _i32, _u32, C.POINTER(_vp)]),
+    "sh_psi_create_batched": (C.c_int, [_i32, _i32, _u32, _i32, C.POINTER(_vp)]),
     "sh_psi_destroy": (C.c_int, [_vp]),
     "sh_psi_planes": (C.c_int, [_vp, C.POINTER(_i32)]),
     "sh_daubechies": (C.c_int, [_i32, _P64]),
@@ -153,14 +157,34 @@ def op_create_tuned(uv: np.ndarray, n: int, oversample: int, kernel_width: int, 
     return h.value
 
 
+def op_create_batched(uv: np.ndarray, M_p, n: int, oversample: int, kernel_width: int, block_offsets, R_p,
+                      tile: int = 0, chunk: int = 0) -> int:
+    """One plan for P problems: uv and block_offsets concatenate the problems (see the C header)."""
+    uv = _f64(uv)
+    if uv.ndim != 2 or uv.shape[1] != 2:
+        raise ValueError("uv must be (M, 2)")
+    mp = np.ascontiguousarray(M_p, dtype=np.int64)
+    rp = np.ascontiguousarray(R_p, dtype=np.int32)
+    if mp.shape != rp.shape or mp.ndim != 1:
+        raise ValueError("M_p and R_p must be 1-D of equal length")
+    off = np.ascontiguousarray(block_offsets, dtype=np.int64)
+    if len(off) != int(rp.sum()) + 1 or uv.shape[0] != int(mp.sum()):
+        raise ValueError("block_offsets / uv do not match M_p / R_p")
+    h = _vp()
+    _check(lib.sh_op_create_batched(uv.ctypes.data_as(_P64), mp.ctypes.data_as(_PI64), len(mp), n, oversample,
+                                    kernel_width, off.ctypes.data_as(_PI64), rp.ctypes.data_as(_PI32), tile, chunk,
+                                    C.byref(h)), "op_create_batched")
+    return h.value
+
+
 def op_destroy(op: int) -> None:
     _check(lib.sh_op_destroy(op), "op_destroy")
 
 
 def op_query(op: int) -> dict:
-    out = np.zeros(8, dtype=np.int64)
+    out = np.zeros(10, dtype=np.int64)
     _check(lib.sh_op_query(op, out.ctypes.data_as(_PI64)), "op_query")
-    keys = ("M", "n", "K", "J", "R", "n_items", "tile", "max_items_per_tile")
+    keys = ("M", "n", "K", "J", "R", "n_items", "tile", "max_items_per_tile", "P", "n_sparse")
     return dict(zip(keys, (int(v) for v in out)))
 
 
@@ -202,10 +226,12 @@ def vis_to_user(op, internal, user, stream=None):
     _check(lib.sh_vis_to_user(op, _ptr(internal), _ptr(user), _stream(stream)), "vis_to_user")
 
 
-def op_norm(op, x0, iters: int = 200, tol: float = 1e-12, stream=None) -> float:
-    nu = C.c_double()
-    _check(lib.sh_op_norm(op, _ptr(x0), iters, tol, C.byref(nu), _stream(stream)), "op_norm")
-    return nu.value
+def op_norm(op, x0, iters: int = 200, tol: float = 1e-12, stream=None):
+    """||Phi||: a float for a one-problem plan, a float64 array of P values for a batched one."""
+    P = op_query(op)["P"]
+    nu = np.zeros(P, dtype=np.float64)
+    _check(lib.sh_op_norm(op, _ptr(x0), iters, tol, nu.ctypes.data_as(_P64), _stream(stream)), "op_norm")
+    return float(nu[0]) if P == 1 else nu
 
 
 # ---- SARA dictionary ------------------------------------------------------------------------
@@ -213,6 +239,12 @@ def op_norm(op, x0, iters: int = 200, tol: float = 1e-12, stream=None) -> float:
 def psi_create(n: int, levels: int = 4, basis_mask: int = SARA_MASK) -> int:
     h = _vp()
     _check(lib.sh_psi_create(n, levels, basis_mask, C.byref(h)), "psi_create")
+    return h.value
+
+
+def psi_create_batched(n: int, levels: int, basis_mask: int, batch: int) -> int:
+    h = _vp()
+    _check(lib.sh_psi_create_batched(n, levels, basis_mask, batch, C.byref(h)), "psi_create_batched")
     return h.value
 
 
@@ -274,15 +306,18 @@ def sdmm_default_params() -> SdmmParams:
 
 
 def sdmm_solve(op, psi, y, eps, W, x0, params: SdmmParams, x_out, W_out=None, stream=None):
-    """Returns (info dict, block residuals ||y_i - Phi_i x|| as float64 numpy)."""
+    """Returns (info, block residuals ||y_i - Phi_i x|| as float64 numpy); info is a dict for a
+    one-problem plan and a list of P dicts for a batched one."""
     eps = _f64(eps)
     R = len(eps)
+    P = op_query(op)["P"]
     resid = np.zeros(R, dtype=np.float64)
-    info = SdmmInfo()
+    info = (SdmmInfo * P)()
     _check(lib.sh_sdmm_solve(op, psi, _ptr(y), eps.ctypes.data_as(_P64), _ptr(W), _ptr(x0), C.byref(params),
-                             _ptr(x_out), _ptr(W_out), resid.ctypes.data_as(_P64), C.byref(info),
-                             _stream(stream)), "sdmm_solve")
-    return info.as_dict(), resid
+                             _ptr(x_out), _ptr(W_out), resid.ctypes.data_as(_P64),
+                             C.cast(info, C.POINTER(SdmmInfo)), _stream(stream)), "sdmm_solve")
+    dicts = [i.as_dict() for i in info]
+    return (dicts[0] if P == 1 else dicts), resid
 
 
 def sdmm_create(op, psi, y, eps, W, x0, params: SdmmParams, stream=None) -> int:
@@ -297,13 +332,14 @@ def sdmm_iterate(s: int, iters: int, stream=None) -> None:
     _check(lib.sh_sdmm_iterate(s, iters, _stream(stream)), "sdmm_iterate")
 
 
-def sdmm_result(s: int, x_out=None, R: int = 0, stream=None):
-    """Returns (block residuals as float64 numpy of length R, relative change)."""
+def sdmm_result(s: int, x_out=None, R: int = 0, stream=None, P: int = 1):
+    """Returns (block residuals as float64 numpy of length R, relative change: a float, or P
+    values for a batched session)."""
     resid = np.zeros(max(R, 1), dtype=np.float64)
-    rel = C.c_double()
-    _check(lib.sh_sdmm_result(s, _ptr(x_out), resid.ctypes.data_as(_P64) if R else None, C.byref(rel),
+    rel = np.zeros(P, dtype=np.float64)
+    _check(lib.sh_sdmm_result(s, _ptr(x_out), resid.ctypes.data_as(_P64) if R else None, rel.ctypes.data_as(_P64),
                               _stream(stream)), "sdmm_result")
-    return resid[:R], rel.value
+    return resid[:R], (float(rel[0]) if P == 1 else rel)
 
 
 def sdmm_destroy(s: int) -> None:

@@ -88,3 +88,32 @@ def test_library_shares_torchs_hip_runtime():
     hips = {h for h in hips if "libamdhip64" in h}
     assert len(hips) == 1, hips
     assert os.path.dirname(torch.__file__) in next(iter(hips))
+
+
+def test_op_create_batched_rejects_invalid_arguments():
+    uv = np.zeros((6, 2))
+    cases = (
+        dict(M_p=[3, 3], block_offsets=[0, 2, 4, 6], R_p=[2, 1]),     # block 1 straddles problems 0 and 1
+        dict(M_p=[3, 3], block_offsets=[0, 3, 6], R_p=[1, 2]),        # R_p does not match the offsets
+        dict(M_p=[4, 3], block_offsets=[0, 4, 7], R_p=[1, 1]),        # uv holds 6 points, M_p sums to 7
+        dict(M_p=[6, 0], block_offsets=[0, 6, 6], R_p=[1, 1]),        # empty problem
+    )
+    for c in cases:
+        with pytest.raises((sh.SarahipError, ValueError)) as e:
+            sh.op_create_batched(uv, c["M_p"], 16, 2, 6, c["block_offsets"], c["R_p"])
+        if isinstance(e.value, sh.SarahipError):
+            assert e.value.status == -1
+    # the C entry point validates what the binding does not
+    with pytest.raises(sh.SarahipError) as e:
+        M_p = np.array([3, 3], dtype=np.int64)
+        R_p = np.array([2, 1], dtype=np.int32)
+        off = np.array([0, 2, 4, 6], dtype=np.int64)
+        uv64 = np.zeros((6, 2))
+        h = sh._vp()
+        sh._check(sh.lib.sh_op_create_batched(uv64.ctypes.data_as(sh._P64), M_p.ctypes.data_as(sh._PI64), 2, 16, 2,
+                                              6, off.ctypes.data_as(sh._PI64), R_p.ctypes.data_as(sh._PI32), 0, 0,
+                                              sh.C.byref(h)), "op_create_batched")
+    assert e.value.status == -1 and "cover" in str(e.value)
+    with pytest.raises(sh.SarahipError) as e:
+        sh.psi_create_batched(16, 4, sh.SARA_MASK, 0)
+    assert e.value.status == -1

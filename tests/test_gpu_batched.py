@@ -1,0 +1,221 @@
+"""GPU tests of batched plans: P independent problems in one operator, dictionary and SDMM solve.
+
+A batched plan applies each problem's own Phi to each problem's own image.  Its gridding work items,
+patch order and FFT arithmetic are those of the problem's own single plan, so the operator results
+equal the single-problem results bit for bit; the solve differs from P separate solves only in the
+partition of its float64 reductions and is checked against the FP64 oracle per problem.  Graph
+replay of the iteration is checked bitwise against plain launches.
+"""
+import numpy as np
+import pytest
+
+from oracle import measurement, sdmm, wavelets
+from tests import helpers
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# (m, R) per problem: ragged sizes, one single-block problem, one with five blocks
+SHAPES = [(700, 2), (1500, 4), (300, 1), (1100, 3), (2048, 5)]
+
+
+@pytest.fixture(scope="module")
+def sh():
+    from paper_1502_05037_amd import sarahip
+    return sarahip
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
+
+
+def _problems(n=32, J=6, shapes=SHAPES, cfg=40):
+    return [helpers.build(cfg, n, m, R, J, coverage="gaussian" if k % 2 else "radial", prob=k)
+            for k, (m, R) in enumerate(shapes)]
+
+
+def _concat(pbs):
+    uv = np.concatenate([pb.uv for pb in pbs])
+    M_p = [len(pb.uv) for pb in pbs]
+    R_p = [len(pb.offsets) - 1 for pb in pbs]
+    offs = [0]
+    base = 0
+    for pb in pbs:
+        offs.extend(int(base + o) for o in pb.offsets[1:])
+        base += len(pb.uv)
+    return uv, M_p, R_p, np.array(offs, dtype=np.int64)
+
+
+def _params(sh, **kw):
+    p = sh.sdmm_default_params()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_batched_operator_equals_single_plans(sh):
+    pbs = _problems()
+    n, P = pbs[0].n, len(pbs)
+    uv, M_p, R_p, offs = _concat(pbs)
+    opb = sh.op_create_batched(uv, M_p, n, 2, pbs[0].J, offs, R_p)
+    singles = [sh.op_create(pb.uv, n, 2, pb.J, pb.offsets) for pb in pbs]
+    try:
+        q = sh.op_query(opb)
+        assert q["P"] == P and q["M"] == sum(M_p) and q["R"] == sum(R_p)
+        g = np.random.default_rng(7)
+        xs = g.standard_normal((P, n, n)).astype(np.float32)
+        vs = (g.standard_normal(sum(M_p)) + 1j * g.standard_normal(sum(M_p))).astype(np.complex64)
+        vb = torch.empty(sum(M_p), dtype=torch.complex64, device="cuda")
+        xb = torch.empty((P, n, n), device="cuda")
+        sh.phi_fwd(opb, _dev(xs), vb)
+        sh.phi_adj(opb, _dev(vs, torch.complex64), xb)
+        torch.cuda.synchronize()
+        vb, xb = vb.cpu().numpy(), xb.cpu().numpy()
+        base = 0
+        for p, (pb, op) in enumerate(zip(pbs, singles)):
+            m = M_p[p]
+            v1 = torch.empty(m, dtype=torch.complex64, device="cuda")
+            x1 = torch.empty((n, n), device="cuda")
+            sh.phi_fwd(op, _dev(xs[p]), v1)
+            sh.phi_adj(op, _dev(vs[base:base + m], torch.complex64), x1)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(vb[base:base + m], v1.cpu().numpy())
+            np.testing.assert_array_equal(xb[p], x1.cpu().numpy())
+            # and against the FP64 oracle of this problem alone
+            assert helpers.rel(vb[base:base + m], pb.op.fwd(xs[p].astype(np.float64))) <= 1e-5
+            assert helpers.rel(xb[p], pb.op.adj(vs[base:base + m].astype(np.complex128))) <= 1e-5
+            base += m
+    finally:
+        for op in singles:
+            sh.op_destroy(op)
+        sh.op_destroy(opb)
+
+
+def test_batched_psi_equals_single(sh):
+    n, P, q_levels = 64, 3, 4
+    psib = sh.psi_create_batched(n, q_levels, sh.SARA_MASK, P)
+    psi1 = sh.psi_create(n, q_levels, sh.SARA_MASK)
+    try:
+        q = sh.psi_planes(psib)
+        g = np.random.default_rng(3)
+        xs = g.standard_normal((P, n, n)).astype(np.float32)
+        cs = g.standard_normal((P, q, n, n)).astype(np.float32)
+        cb = torch.empty((P, q, n, n), device="cuda")
+        xb = torch.empty((P, n, n), device="cuda")
+        sh.psi_adj(psib, _dev(xs), cb)
+        sh.psi_fwd(psib, _dev(cs), xb)
+        ref = wavelets.SARA(n, q_levels, 0x1FF)
+        for p in range(P):
+            c1 = torch.empty((q, n, n), device="cuda")
+            x1 = torch.empty((n, n), device="cuda")
+            sh.psi_adj(psi1, _dev(xs[p]), c1)
+            sh.psi_fwd(psi1, _dev(cs[p]), x1)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(cb[p].cpu().numpy(), c1.cpu().numpy())
+            np.testing.assert_array_equal(xb[p].cpu().numpy(), x1.cpu().numpy())
+            assert helpers.rel(cb[p].cpu().numpy(), ref.adj(xs[p].astype(np.float64))) <= 1e-5
+    finally:
+        sh.psi_destroy(psi1)
+        sh.psi_destroy(psib)
+
+
+def test_batched_op_norm(sh):
+    pbs = _problems(shapes=SHAPES[:3])
+    n = pbs[0].n
+    uv, M_p, R_p, offs = _concat(pbs)
+    opb = sh.op_create_batched(uv, M_p, n, 2, pbs[0].J, offs, R_p)
+    try:
+        nu = sh.op_norm(opb, torch.ones((len(pbs), n, n), device="cuda"), iters=500, tol=1e-10)
+        for p, pb in enumerate(pbs):
+            ref = measurement.op_norm(pb.op, np.ones((n, n)), max_iter=500, tol=1e-12)
+            assert nu[p] == pytest.approx(ref, rel=1e-4)
+    finally:
+        sh.op_destroy(opb)
+
+
+def _batched_solve(sh, pbs, prm, levels=4, want_W=False):
+    n, P = pbs[0].n, len(pbs)
+    uv, M_p, R_p, offs = _concat(pbs)
+    op = sh.op_create_batched(uv, M_p, n, 2, pbs[0].J, offs, R_p)
+    psi = sh.psi_create_batched(n, levels, sh.SARA_MASK, P)
+    try:
+        q = sh.psi_planes(psi)
+        y = _dev(np.concatenate([pb.y for pb in pbs]), torch.complex64)
+        eps = np.concatenate([pb.eps for pb in pbs])
+        x = torch.empty((P, n, n), device="cuda")
+        Wo = torch.empty((P, q, n, n), device="cuda") if want_W else None
+        infos, resid = sh.sdmm_solve(op, psi, y, eps, None, None, prm, x, Wo)
+        torch.cuda.synchronize()
+        return x.cpu().numpy().astype(np.float64), infos, resid, (None if Wo is None else Wo.cpu().numpy())
+    finally:
+        sh.psi_destroy(psi)
+        sh.op_destroy(op)
+
+
+def test_batched_sdmm_fixed_schedule_matches_oracle(sh):
+    """Three reweighted passes of every problem at its own nu and gamma (resolved by the library)
+    against the oracle run at the nu and gamma the library reports."""
+    pbs = _problems(shapes=SHAPES[:4])
+    x, infos, resid, Wo = _batched_solve(sh, pbs, _params(sh, max_iter=40, cg_iters=8, passes=3), want_W=True)
+    base = 0
+    for p, pb in enumerate(pbs):
+        psi = wavelets.SARA(pb.n, 4, 0x1FF)
+        nu_ref = measurement.op_norm(pb.op, np.ones((pb.n, pb.n)), max_iter=200, tol=1e-12)
+        gamma_ref = sdmm.default_gamma(pb.op, psi, pb.y, nu_ref)
+        assert infos[p]["nu"] == pytest.approx(nu_ref, rel=1e-4)
+        assert infos[p]["gamma"] == pytest.approx(gamma_ref, rel=1e-4)
+        prm = sdmm.Params(gamma=infos[p]["gamma"], nu=infos[p]["nu"], max_iter=40, cg_iters=8, passes=3)
+        x_ref, _, oinfos, _ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, prm)
+        err = helpers.rel(x[p], x_ref)
+        print(f"problem {p}: image error vs oracle {err:.3e}")
+        assert err <= 1e-4
+        R = len(pb.eps)
+        np.testing.assert_allclose(resid[base:base + R], oinfos[-1].block_resid, rtol=1e-4)
+        assert infos[p]["objective"] == pytest.approx(oinfos[-1].objective, rel=1e-4)
+        assert infos[p]["passes_done"] == 3 and infos[p]["iters_total"] == 120
+        base += R
+
+
+def test_batched_run_to_tolerance_is_feasible(sh):
+    pbs = _problems(shapes=SHAPES, cfg=41)
+    x, infos, resid, _ = _batched_solve(sh, pbs, _params(sh, max_iter=3000, tol_rel=1e-4, check_every=5))
+    for p, pb in enumerate(pbs):
+        assert infos[p]["converged"] == 1, p
+        assert infos[p]["iters_last"] <= infos[p]["iters_total"]
+        assert infos[p]["rel_change"] <= 1e-4
+        v = pb.op.fwd(x[p])
+        for i in range(len(pb.eps)):
+            lo, hi = pb.offsets[i], pb.offsets[i + 1]
+            r = np.linalg.norm(pb.y[lo:hi] - v[lo:hi])
+            assert r <= pb.eps[i] * (1 + 1e-4), (p, i, r, pb.eps[i])
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_graph_replay_equals_plain_launches(sh, batched):
+    """The captured iteration replays the same kernels with the same arguments: bitwise equal
+    images, also across the re-capture that follows a reweighting."""
+    pbs = _problems(shapes=SHAPES[:3] if batched else SHAPES[1:2], cfg=42)
+    outs = []
+    for graph in (0, 1):
+        x, infos, resid, _ = _batched_solve(sh, pbs, _params(sh, max_iter=25, cg_iters=6, passes=2, graph=graph))
+        outs.append((x, resid))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_batched_argument_errors(sh):
+    pbs = _problems(shapes=SHAPES[:2])
+    n = pbs[0].n
+    uv, M_p, R_p, offs = _concat(pbs)
+    op = sh.op_create_batched(uv, M_p, n, 2, pbs[0].J, offs, R_p)
+    psi1 = sh.psi_create(n, 4)
+    try:
+        y = _dev(np.concatenate([pb.y for pb in pbs]), torch.complex64)
+        eps = np.concatenate([pb.eps for pb in pbs])
+        x = torch.empty((2, n, n), device="cuda")
+        with pytest.raises(sh.SarahipError) as e:     # dictionary batch 1 against a plan of 2 problems
+            sh.sdmm_solve(op, psi1, y, eps, None, None, _params(sh), x)
+        assert e.value.status == -1
+    finally:
+        sh.psi_destroy(psi1)
+        sh.op_destroy(op)
