@@ -87,6 +87,32 @@ sh_status sh_op_create_batched(const double* uv, const int64_t* M_p, int32_t P, 
                                int32_t kernel_width, const int64_t* block_offsets, const int32_t* R_p,
                                int32_t tile, int32_t chunk, sh_op* out);
 
+/* Autotuned plan (batched form; P = 1 for one problem).  The kernel width J is the smallest even
+ * width whose aliasing estimate (sh_kb_alias_error) is <= accuracy, e.g. 1e-5; the gridding tile
+ * side and item cap are then chosen by timing `reps` Phi + Phi^dagger pairs of candidate plans on
+ * `stream` (tile sides 8, 16, 32, then item caps 1024 and 16384 for the fastest tile).  The choice
+ * is cached for the process under a hash of the inputs; a repeated call only re-plans.  result
+ * (host) receives the choice and its timing.  Synchronous; allocates and frees candidate plans.
+ * Errors as sh_op_create_batched, plus SH_EINVAL for accuracy outside (0, 1) or unreachable. */
+typedef struct {
+  double accuracy;     /* the target given */
+  double alias_error;  /* estimate for the chosen J */
+  double ms_pair;      /* best measured Phi + Phi^dagger time (ms) */
+  int32_t J;           /* chosen kernel width */
+  int32_t tile;        /* chosen tile side */
+  int32_t chunk;       /* chosen most visibilities per work item */
+  int32_t candidates;  /* plans timed by this call (0 when cached) */
+  int32_t cached;      /* 1 if the tiling came from the process cache */
+} sh_tune_result;
+sh_status sh_op_autotune(const double* uv, const int64_t* M_p, int32_t P, int32_t n, int32_t oversample,
+                         double accuracy, const int64_t* block_offsets, const int32_t* R_p, int32_t reps,
+                         sh_tune_result* result, sh_op* out, void* stream);
+/* Aliasing estimate of the J-wide Kaiser-Bessel interpolation on an alpha-times oversampled grid:
+ * the RMS over image frequencies of sqrt(sum_{l != 0} psi_hat(xi + l)^2) / psi_hat(xi), times
+ * sqrt(2) for two axes -- the expected relative error of Phi against the exact sum for a white
+ * image.  Host only. */
+sh_status sh_kb_alias_error(int32_t kernel_width, int32_t oversample, double* err_out);
+
 /* Query plan sizes: out[0]=M, out[1]=n, out[2]=grid side K, out[3]=J, out[4]=R,
  * out[5]=number of gridding work items, out[6]=tile side, out[7]=max items per tile,
  * out[8]=number of problems P, out[9]=work items of the sparse (one thread per visibility) class. */

@@ -51,6 +51,14 @@ class SdmmInfo(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("accuracy", C.c_double), ("alias_error", C.c_double), ("ms_pair", C.c_double), ("J", C.c_int32),
+                ("tile", C.c_int32), ("chunk", C.c_int32), ("candidates", C.c_int32), ("cached", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _vp, _i64, _i32, _u32, _f32, _f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_float, C.c_double
 _P64 = C.POINTER(C.c_double)
 _PI64 = C.POINTER(C.c_int64)
@@ -62,6 +70,9 @@ _SIGS = {
     "sh_op_create_tuned": (C.c_int, [_P64, _i64, _i32, _i32, _i32, _PI64, _i32, _i32, _i32, C.POINTER(_vp)]),
     "sh_op_create_batched": (C.c_int, [_P64, _PI64, _i32, _i32, _i32, _i32, _PI64, _PI32, _i32, _i32,
                                        C.POINTER(_vp)]),
+    "sh_op_autotune": (C.c_int, [_P64, _PI64, _i32, _i32, _i32, _f64, _PI64, _PI32, _i32, C.POINTER(TuneResult),
+                                 C.POINTER(_vp), _vp]),
+    "sh_kb_alias_error": (C.c_int, [_i32, _i32, _P64]),
     "sh_op_destroy": (C.c_int, [_vp]),
     "sh_op_query": (C.c_int, [_vp, _PI64]),
     "sh_op_block_offsets": (C.c_int, [_vp, _PI64]),
@@ -175,6 +186,29 @@ def op_create_batched(uv: np.ndarray, M_p, n: int, oversample: int, kernel_width
                                     kernel_width, off.ctypes.data_as(_PI64), rp.ctypes.data_as(_PI32), tile, chunk,
                                     C.byref(h)), "op_create_batched")
     return h.value
+
+
+def op_autotune(uv: np.ndarray, M_p, n: int, oversample: int, accuracy: float, block_offsets, R_p, reps: int = 3,
+                stream=None):
+    """Returns (plan handle, dict of the tuner's choice); arguments as op_create_batched."""
+    uv = _f64(uv)
+    mp = np.ascontiguousarray(M_p, dtype=np.int64)
+    rp = np.ascontiguousarray(R_p, dtype=np.int32)
+    off = np.ascontiguousarray(block_offsets, dtype=np.int64)
+    if uv.ndim != 2 or uv.shape[1] != 2 or uv.shape[0] != int(mp.sum()) or len(off) != int(rp.sum()) + 1:
+        raise ValueError("uv / block_offsets do not match M_p / R_p")
+    res = TuneResult()
+    h = _vp()
+    _check(lib.sh_op_autotune(uv.ctypes.data_as(_P64), mp.ctypes.data_as(_PI64), len(mp), n, oversample, accuracy,
+                              off.ctypes.data_as(_PI64), rp.ctypes.data_as(_PI32), reps, C.byref(res), C.byref(h),
+                              _stream(stream)), "op_autotune")
+    return h.value, res.as_dict()
+
+
+def kb_alias_error(kernel_width: int, oversample: int = 2) -> float:
+    e = C.c_double()
+    _check(lib.sh_kb_alias_error(kernel_width, oversample, C.byref(e)), "kb_alias_error")
+    return e.value
 
 
 def op_destroy(op: int) -> None:
