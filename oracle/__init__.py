@@ -14,4 +14,5 @@ prox         Soft threshold, l2-ball projection, positive-orthant projection.
 sdmm         SDMM on problem (3), conjugate-gradient x-update, SARA reweighting,
              KKT residuals.
 problem      Noise scaling, per-block noise bounds, dirty image.
+unet         The warm-start U-Net: layers, forward, gradients, Adam, bfloat16 emulation.
 """
