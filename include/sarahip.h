@@ -261,6 +261,46 @@ sh_status sh_sdmm_result(sh_sdmm s, float* x_out, double* block_resid, double* r
 sh_status sh_sdmm_destroy(sh_sdmm s);
 
 /* ---------------------------------------------------------------------------
+ * Learned warm start: a U-Net mapping the normalised dirty image to a first
+ * image estimate x0 (and, through Psi^dagger x0, first weights W) for the SDMM
+ * solve above, which keeps its constraints and stopping test.  Not part of the
+ * paper's method; it only changes where the iterations start.
+ *
+ * Architecture (levels L, base channels c, c_l = c 2^(l-1)): encoder level l =
+ * two 3x3 zero-padded convolutions + ReLU (levels >= 2 after a 2x2 max-pool);
+ * decoder level l = L-1..1: 2x2 stride-2 transposed convolution c_{l+1} -> c_l,
+ * concat [upsampled, encoder level l], two 3x3 convolutions + ReLU; head = 1x1
+ * convolution to one channel + ReLU.  Loss: mean squared error over pixels.
+ * Parameters are one flat float32 array: for each layer in the order enc1a,
+ * enc1b, ..., encLb, up(L-1)t, up(L-1)a, up(L-1)b, ..., up1b, head, the weight
+ * then the bias; conv weights [cout][cin][3][3], transposed-conv weights
+ * [cin][cout][2][2], head [1][c][1][1].
+ * Arithmetic: bfloat16 operands (weights, activations, layer gradients) in
+ * MFMA products with float32 accumulation; float32 master weights, gradients
+ * and Adam state.
+ * Images: device float32, B x H x W, H and W divisible by 2^(L-1).
+ * ------------------------------------------------------------------------- */
+typedef struct sh_unet_s* sh_unet;
+/* base: multiple of 16 in [16, 128]; levels 1..6.  Parameters start at zero.  Synchronous. */
+sh_status sh_unet_create(int32_t base, int32_t levels, sh_unet* out);
+sh_status sh_unet_destroy(sh_unet u);
+sh_status sh_unet_num_params(sh_unet u, int64_t* n_out);
+/* Copy n host float32 parameters in (resets the Adam state) or out.  Synchronous.  SH_ENONFINITE on
+ * a non-finite parameter. */
+sh_status sh_unet_set_params(sh_unet u, const float* host, int64_t n);
+sh_status sh_unet_get_params(sh_unet u, float* host, int64_t n);
+/* y = network(x), both device float32 B x H x W.  Async. */
+sh_status sh_unet_forward(sh_unet u, const float* x, int32_t B, int32_t H, int32_t W, float* y, void* stream);
+/* Loss mean((network(x) - target)^2) (host) and, if grads_host is not NULL, its gradient with
+ * respect to every parameter (host, flat layout).  Synchronous. */
+sh_status sh_unet_loss_grad(sh_unet u, const float* x, const float* target, int32_t B, int32_t H, int32_t W,
+                            double* loss_out, float* grads_host, void* stream);
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the loss of the batch;
+ * loss_out (host, may be NULL: then the call is async) receives the loss before the step. */
+sh_status sh_unet_train_step(sh_unet u, const float* x, const float* target, int32_t B, int32_t H, int32_t W,
+                             float lr, double* loss_out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (HIP events around the gridding/degridding launches).
  * ------------------------------------------------------------------------- */
 /* Enable (1) or disable (0) event timing; enabling clears the counters. */

@@ -1,0 +1,901 @@
+// Learned warm start: a U-Net that maps the normalised dirty image to a first image estimate, with
+// its training (forward, backward, Adam) on the GPU.
+//
+// Architecture (levels L, base channels c, c_l = c 2^(l-1)): encoder level l = two 3x3 convolutions
+// (zero padding) + ReLU, levels 2..L preceded by a 2x2 max-pool; decoder level l = L-1..1: 2x2
+// stride-2 transposed convolution c_{l+1} -> c_l, channel concat [upsampled, encoder output], two
+// 3x3 convolutions + ReLU; head = 1x1 convolution to one channel + ReLU.  Loss: mean squared error.
+//
+// Number formats: fp32 master weights, gradients and Adam moments; bfloat16 weights, activations
+// and incoming layer gradients as the operands of every matrix product; fp32 accumulation.
+//
+// Every convolution is a matrix product on the MFMA units: activations are NHWC (channels
+// contiguous), a 3x3 convolution is im2col (K = 9 Cin, ordered (ky, kx, ci), zero-padded to a
+// multiple of 16) times the weight matrix, and all products use one kernel of the "NT" form
+// C[m][n] = sum_k A[m][k] B[n][k] with both operands contiguous along k (v_mfma_f32_16x16x16_bf16,
+// 64 x 64 tiles per work-group of four waves, k staged through LDS 32 at a time, optional split-K
+// with a fixed-order reduction).  Weight gradients contract over pixels, so their operands are
+// transposed first (pixels padded to a multiple of 16); a row of ones appended to the second
+// operand yields the bias gradient in the same product.  Results are deterministic.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ uint16_t f2bf(float f) {   // nearest, ties to even (finite inputs)
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+inline unsigned nb(int64_t n, int t = 256) { return (unsigned)sh::cdiv(n, t); }
+inline int64_t rup(int64_t v, int64_t m) { return sh::cdiv(v, m) * m; }
+
+// ---------------------------------------------------------------------------------------------
+// GEMM: C[m][n] = sum_{k in split z} A[m*lda + k] B[n*ldb + k] (+ bias[n]) (relu), bf16 operands.
+// K is a multiple of 16.  Outputs: fp32 C (+ z*M*ldc for split partials) and/or bf16 Cb.
+// ---------------------------------------------------------------------------------------------
+constexpr int GBM = 64, GBN = 64, GBK = 32, GLD = GBK + 8;
+
+__global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, int lda, const uint16_t* __restrict__ B,
+                                               int ldb, int M, int N, int K, int kchunk,
+                                               const float* __restrict__ bias, int relu, float* __restrict__ C,
+                                               int ldc, uint16_t* __restrict__ Cb, int ldcb) {
+  __shared__ uint16_t As[GBM][GLD];
+  __shared__ uint16_t Bs[GBN][GLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 2, lc = (tid & 3) * 8;   // staging: row lr, 8 k-values from lc
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
+    {
+      const int k = k0 + lc;
+      uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+      if (m0 + lr < M && k < ke) va = *(const uint4*)(A + (int64_t)(m0 + lr) * lda + k);
+      if (n0 + lr < N && k < ke) vb = *(const uint4*)(B + (int64_t)(n0 + lr) * ldb + k);
+      *(uint4*)&As[lr][lc] = va;
+      *(uint4*)&Bs[lr][lc] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 16) {
+      const int ko = kk + 4 * (lane >> 4);
+      bf16x4 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = *(const bf16x4*)&As[wm * 32 + i * 16 + (lane & 15)][ko];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = *(const bf16x4*)&Bs[wn * 32 + j * 16 + (lane & 15)][ko];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D[i][j] of a 16x16 block: lane holds rows 4*(lane/16) + r, column lane%16
+  if (C) C += (int64_t)blockIdx.z * M * ldc;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+      if (n >= N) continue;
+      const float bv = bias ? bias[n] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        if (m >= M) continue;
+        float v = acc[i][j][r] + bv;
+        if (relu) v = fmaxf(v, 0.f);
+        if (C) C[(int64_t)m * ldc + n] = v;
+        if (Cb) Cb[(int64_t)m * ldcb + n] = f2bf(v);
+      }
+    }
+}
+
+// out[i] = sum_z part[z*n + i], fixed order
+__global__ void sum_splits(const float* __restrict__ part, int S, int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < S; ++z) s += part[z * n + i];
+  out[i] = s;
+}
+
+// ---- layout kernels ----------------------------------------------------------------------------
+
+__global__ void f32_to_bf16(const float* __restrict__ in, uint16_t* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = f2bf(in[i]);
+}
+
+// col[p][k] for p < B*H*W, k < Kp: k = (ky*3 + kx)*C + c < 9C takes x at (y+ky-1, x+kx-1) (zero outside
+// the image), k >= 9C is zero.  x: NHWC with row stride ldx (channels at offset 0).  One thread per
+// 8 consecutive k.
+__global__ void im2col3(const uint16_t* __restrict__ x, int ldx, int B, int H, int W, int C, int Kp,
+                        uint16_t* __restrict__ col) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int g8 = Kp / 8;
+  const int64_t P = (int64_t)B * H * W;
+  if (t >= P * g8) return;
+  const int64_t p = t / g8;
+  const int k0 = int(t - p * g8) * 8;
+  const int b = int(p / ((int64_t)H * W));
+  const int rem = int(p - (int64_t)b * H * W);
+  const int yy = rem / W, xx = rem - yy * W;
+  uint16_t* dst = col + p * Kp + k0;
+  if ((C & 7) == 0) {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (k0 < 9 * C) {
+      const int tap = k0 / C, c = k0 - tap * C;
+      const int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
+      if (sy >= 0 && sy < H && sx >= 0 && sx < W)
+        v = *(const uint4*)(x + ((int64_t)(b * H + sy) * W + sx) * ldx + c);
+    }
+    *(uint4*)dst = v;
+  } else {
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + e;
+      uint16_t v = 0;
+      if (k < 9 * C) {
+        const int tap = k / C, c = k - tap * C;
+        const int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
+        if (sy >= 0 && sy < H && sx >= 0 && sx < W) v = x[((int64_t)(b * H + sy) * W + sx) * ldx + c];
+      }
+      dst[e] = v;
+    }
+  }
+}
+
+// out[c][r] = in[r*ld + c] (r < R) or 0 (R <= r < Rp), c < C; with ones_row, out[C][r] = (r < R).
+__global__ __launch_bounds__(256) void transpose_pad(const uint16_t* __restrict__ in, int64_t R, int C, int ld,
+                                                     uint16_t* __restrict__ out, int64_t Rp, int ones_row) {
+  __shared__ uint16_t tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t r = r0 + q;
+    const int c = c0 + tx;
+    tile[q][tx] = (r < R && c < C) ? in[r * ld + c] : (uint16_t)0;
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {
+    const int c = c0 + q;
+    const int64_t r = r0 + tx;
+    if (c < C && r < Rp) out[(int64_t)c * Rp + r] = tile[tx][q];
+  }
+  if (ones_row && blockIdx.y == 0 && ty == 0) {
+    const int64_t r = r0 + tx;
+    if (r < Rp) out[(int64_t)C * Rp + r] = r < R ? (uint16_t)0x3F80 : (uint16_t)0;   // bf16 1.0
+  }
+}
+
+// 2x2 max-pool, NHWC; idx = row-major index of the first maximum of the window
+__global__ void pool_fwd(const uint16_t* __restrict__ x, int B, int H, int W, int C, uint16_t* __restrict__ y,
+                         uint8_t* __restrict__ idx) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int h = H / 2, w = W / 2;
+  if (t >= (int64_t)B * h * w * C) return;
+  const int c = int(t % C);
+  const int64_t po = t / C;
+  const int b = int(po / ((int64_t)h * w));
+  const int rem = int(po - (int64_t)b * h * w);
+  const int oy = rem / w, ox = rem - oy * w;
+  float best = -INFINITY;
+  int bi = 0;
+  uint16_t bv = 0;
+  for (int q = 0; q < 4; ++q) {
+    const uint16_t v = x[((int64_t)(b * H + 2 * oy + q / 2) * W + 2 * ox + q % 2) * C + c];
+    const float f = bf2f(v);
+    if (f > best) {
+      best = f;
+      bi = q;
+      bv = v;
+    }
+  }
+  y[t] = bv;
+  idx[t] = (uint8_t)bi;
+}
+
+// gradient of the pool: g_in (B, H, W, C) fp32 from g_out (B, H/2, W/2, C) fp32
+__global__ void pool_bwd(const float* __restrict__ gout, const uint8_t* __restrict__ idx, int B, int H, int W, int C,
+                         float* __restrict__ gin) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int h = H / 2, w = W / 2;
+  if (t >= (int64_t)B * h * w * C) return;
+  const int c = int(t % C);
+  const int64_t po = t / C;
+  const int b = int(po / ((int64_t)h * w));
+  const int rem = int(po - (int64_t)b * h * w);
+  const int oy = rem / w, ox = rem - oy * w;
+  const int bi = idx[t];
+  const float g = gout[t];
+  for (int q = 0; q < 4; ++q)
+    gin[((int64_t)(b * H + 2 * oy + q / 2) * W + 2 * ox + q % 2) * C + c] = q == bi ? g : 0.f;
+}
+
+// transposed-conv output: Y[p_in][(dy*2+dx)*Co + co] (fp32) + bias -> dst (2h x 2w, row stride ld), bf16
+__global__ void tconv_scatter(const float* __restrict__ Y, const float* __restrict__ bias, int B, int h, int w, int Co,
+                              uint16_t* __restrict__ dst, int ld) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)B * h * w * 4 * Co) return;
+  const int n = int(t % (4 * Co));
+  const int64_t p = t / (4 * Co);
+  const int q = n / Co, co = n - q * Co;
+  const int b = int(p / ((int64_t)h * w));
+  const int rem = int(p - (int64_t)b * h * w);
+  const int y = rem / w, x = rem - y * w;
+  const int64_t po = (int64_t)(b * 2 * h + 2 * y + q / 2) * (2 * w) + 2 * x + q % 2;
+  dst[po * ld + co] = f2bf(Y[t] + bias[co]);
+}
+
+// transposed-conv backward: gG[p_in][(dy*2+dx)*Co + co] = bf16(g[(2y+dy, 2x+dx)][co]) (g fp32, row stride ld)
+__global__ void tconv_gather(const float* __restrict__ g, int ld, int B, int h, int w, int Co, uint16_t* __restrict__ gG) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)B * h * w * 4 * Co) return;
+  const int n = int(t % (4 * Co));
+  const int64_t p = t / (4 * Co);
+  const int q = n / Co, co = n - q * Co;
+  const int b = int(p / ((int64_t)h * w));
+  const int rem = int(p - (int64_t)b * h * w);
+  const int y = rem / w, x = rem - y * w;
+  const int64_t po = (int64_t)(b * 2 * h + 2 * y + q / 2) * (2 * w) + 2 * x + q % 2;
+  gG[t] = f2bf(g[po * ld + co]);
+}
+
+// copy C channels: dst[p*ldd + off + c] = src[p*lds + c]
+__global__ void copy_channels(const uint16_t* __restrict__ src, int lds, uint16_t* __restrict__ dst, int ldd, int off,
+                              int64_t P, int C) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= P * C) return;
+  const int64_t p = t / C;
+  const int c = int(t - p * C);
+  dst[p * ldd + off + c] = src[p * lds + c];
+}
+
+// gm[p][c] = bf16((g[p*ldg + c] (+ g2[p*ldg2 + c])) * (act[p][c] > 0))
+__global__ void relu_mask_grad(const float* __restrict__ g, int ldg, const float* __restrict__ g2, int ldg2,
+                               const uint16_t* __restrict__ act, int64_t P, int C, uint16_t* __restrict__ gm) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= P * C) return;
+  const int64_t p = t / C;
+  const int c = int(t - p * C);
+  float v = g[p * ldg + c];
+  if (g2) v += g2[p * ldg2 + c];
+  gm[t] = bf2f(act[t]) > 0.f ? f2bf(v) : (uint16_t)0;
+}
+
+// head: y = relu(z); per-work-group float64 partials of (y - t)^2; g = bf16(2 (y - t) / cnt * (z > 0))
+__global__ __launch_bounds__(256) void mse_loss(const float* __restrict__ z, const float* __restrict__ tgt, int64_t P,
+                                                float* __restrict__ y, uint16_t* __restrict__ g,
+                                                double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  const float inv = 2.0f / float(P);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
+    const float zv = z[i], yv = fmaxf(zv, 0.f), d = yv - tgt[i];
+    if (y) y[i] = yv;
+    if (g) g[i] = zv > 0.f ? f2bf(d * inv) : (uint16_t)0;
+    acc += double(d) * double(d);
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void sum_part_f64(const double* __restrict__ part, int n, int64_t P, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  out[0] = s / double(P);
+}
+
+// head input gradient: da[p][c] = g[p] * w[c] (bf16 operands, exact in fp32)
+__global__ void head_dx(const uint16_t* __restrict__ g, const uint16_t* __restrict__ w, int64_t P, int C,
+                        float* __restrict__ da) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= P * C) return;
+  const int64_t p = t / C;
+  const int c = int(t - p * C);
+  da[t] = bf2f(g[p]) * bf2f(w[c]);
+}
+
+// Adam on flat fp32 arrays
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                            float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// ---- weight operands from the fp32 master (oracle layouts: conv W[co][ci][ky][kx], tconv W[ci][co][dy][dx])
+
+// conv forward operand wf[co][(ky*3+kx)*Ci + ci] (Kp columns) and backward-data operand
+// wd[ci][(a*3+b)*Co + co] = W[co][ci][2-a][2-b] (Kpd columns); zero padding
+__global__ void prep_conv(const float* __restrict__ W, int Co, int Ci, int Kp, int Kpd, uint16_t* __restrict__ wf,
+                          uint16_t* __restrict__ wd) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t nf = (int64_t)Co * Kp, nd = (int64_t)Ci * Kpd;
+  if (t < nf) {
+    const int co = int(t / Kp), k = int(t - (int64_t)co * Kp);
+    uint16_t v = 0;
+    if (k < 9 * Ci) {
+      const int tap = k / Ci, ci = k - tap * Ci;
+      v = f2bf(W[((int64_t)co * Ci + ci) * 9 + tap]);
+    }
+    wf[t] = v;
+  } else if (t < nf + nd) {
+    const int64_t u = t - nf;
+    const int ci = int(u / Kpd), k = int(u - (int64_t)ci * Kpd);
+    uint16_t v = 0;
+    if (k < 9 * Co) {
+      const int tap = k / Co, co = k - tap * Co;
+      v = f2bf(W[((int64_t)co * Ci + ci) * 9 + (8 - tap)]);
+    }
+    wd[u] = v;
+  }
+}
+
+// transposed conv: forward operand wt[(dy*2+dx)*Co + co][ci], backward-data operand wtd[ci][(dy*2+dx)*Co + co]
+__global__ void prep_tconv(const float* __restrict__ W, int Ci, int Co, uint16_t* __restrict__ wt,
+                           uint16_t* __restrict__ wtd) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)Ci * Co * 4;
+  if (t >= n) return;
+  const int q = int(t & 3);
+  const int64_t r = t >> 2;
+  const int co = int(r % Co), ci = int(r / Co);
+  const uint16_t v = f2bf(W[t]);   // W[ci][co][dy][dx], q = dy*2 + dx
+  wt[((int64_t)q * Co + co) * Ci + ci] = v;
+  wtd[(int64_t)ci * 4 * Co + q * Co + co] = v;
+}
+
+// conv gradient scatter: dWg[co][(ky*3+kx)*Ci + ci] -> dW[co][ci][ky][kx]; dWg[co][Kp] -> db[co]
+__global__ void scatter_conv_grad(const float* __restrict__ dWg, int Co, int Ci, int Kp, float* __restrict__ dW,
+                                  float* __restrict__ db) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)Co * Ci * 9;
+  if (t < n) {
+    const int tap = int(t % 9);
+    const int64_t r = t / 9;
+    const int ci = int(r % Ci), co = int(r / Ci);
+    dW[t] = dWg[(int64_t)co * (Kp + 1) + tap * Ci + ci];
+  } else if (t < n + Co) {
+    const int co = int(t - n);
+    db[co] = dWg[(int64_t)co * (Kp + 1) + Kp];
+  }
+}
+
+// transposed-conv gradient scatter: dWg[(q*Co + co)][ci] (ld Ci+1) -> dW[ci][co][q]; db[co] = sum_q dWg[q*Co+co][Ci]
+__global__ void scatter_tconv_grad(const float* __restrict__ dWg, int Ci, int Co, float* __restrict__ dW,
+                                   float* __restrict__ db) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)Ci * Co * 4;
+  if (t < n) {
+    const int q = int(t & 3);
+    const int64_t r = t >> 2;
+    const int co = int(r % Co), ci = int(r / Co);
+    dW[t] = dWg[((int64_t)q * Co + co) * (Ci + 1) + ci];
+  } else if (t < n + Co) {
+    const int co = int(t - n);
+    float s = 0.f;
+    for (int q = 0; q < 4; ++q) s += dWg[((int64_t)q * Co + co) * (Ci + 1) + Ci];
+    db[co] = s;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------------------------------
+
+namespace {
+
+enum Kind { CONV3 = 0, TCONV = 1, HEAD = 2 };
+
+struct Layer {
+  int kind, cin, cout;
+  int64_t w_off, b_off;    // offsets into the flat fp32 parameter array
+  int64_t op_f, op_d;      // offsets of the bf16 forward / backward-data operands
+  int Kp, Kpd;             // padded contraction lengths (conv3)
+};
+
+struct Acts {              // activations of one (B, H, W), allocated on first use
+  int B = 0, H = 0, W = 0;
+  std::vector<sh::DevBuf<uint16_t>> enc;    // 2 per level: a, b outputs (P_l x c_l)
+  std::vector<sh::DevBuf<uint16_t>> pooled; // level l >= 2 input (P_l x c_{l-1})
+  std::vector<sh::DevBuf<uint8_t>> pidx;
+  std::vector<sh::DevBuf<uint16_t>> cat;    // decoder level l: [tconv out, enc_l b] (P_l x 2c_l)
+  std::vector<sh::DevBuf<uint16_t>> dec;    // 2 per decoder level
+  sh::DevBuf<uint16_t> x0;                  // input, bf16
+  sh::DevBuf<float> z;                      // head pre-activation
+  // scratch
+  sh::DevBuf<uint16_t> col, colT, gT, gm, gG;
+  sh::DevBuf<float> f32a, gA, gB, gC, part;
+  std::vector<sh::DevBuf<float>> skipg;     // decoder level l: gradient at the skip half of its concat
+  sh::DevBuf<double> lpart, loss;
+  sh::DevBuf<uint16_t> gbf;                 // head gradient
+};
+
+}  // namespace
+
+struct sh_unet_s {
+  int base = 0, levels = 0;
+  std::vector<Layer> layers;
+  int64_t nparams = 0, nops = 0;
+  sh::DevBuf<float> params, grads, m, v;
+  sh::DevBuf<uint16_t> ops;
+  int64_t t = 0;           // Adam steps taken
+  std::unique_ptr<Acts> ap;  // activations and scratch of the last (B, H, W)
+  sh::DevBuf<float> dwg;     // weight-gradient product (sized at creation)
+};
+
+namespace {
+
+int64_t P_of(const sh_unet_s* u, int l) { return (int64_t)u->ap->B * (u->ap->H >> l) * (u->ap->W >> l); }  // level l+1
+
+sh_status ensure_acts(sh_unet u, int B, int H, int W) {
+  if (u->ap && u->ap->B == B && u->ap->H == H && u->ap->W == W) return SH_OK;
+  u->ap.reset();
+  u->ap.reset(new (std::nothrow) Acts());
+  if (!u->ap) {
+    sh::set_error("host allocation failed");
+    return SH_ENOMEM;
+  }
+  Acts& a = *u->ap;
+  a.B = B;
+  a.H = H;
+  a.W = W;
+  const int L = u->levels;
+  a.enc.resize(2 * L);
+  a.pooled.resize(L);
+  a.pidx.resize(L);
+  a.cat.resize(L);
+  a.dec.resize(2 * L);
+  int64_t maxcol = 0, maxf = 0, maxT = 0, maxpart = 0;
+  for (int l = 0; l < L; ++l) {
+    const int64_t P = P_of(u, l);
+    const int c = u->base << l;
+    SH_TRY(a.enc[2 * l].alloc(P * c));
+    SH_TRY(a.enc[2 * l + 1].alloc(P * c));
+    if (l > 0) {
+      SH_TRY(a.pooled[l].alloc(P * (c / 2)));
+      SH_TRY(a.pidx[l].alloc(P * (c / 2)));
+    }
+    if (l < L - 1) {
+      SH_TRY(a.cat[l].alloc(P * 2 * c));
+      SH_TRY(a.dec[2 * l].alloc(P * c));
+      SH_TRY(a.dec[2 * l + 1].alloc(P * c));
+    }
+    const int64_t Pp = rup(P, 16);
+    const int cin_max = l == 0 ? 2 * c : 2 * c;   // decoder convs read 2c channels
+    const int64_t Kp = rup(9 * std::max(cin_max, 1), 16), Kpd = rup(9 * 2 * c, 16);
+    maxcol = std::max(maxcol, P * std::max(Kp, Kpd));
+    maxT = std::max(maxT, (Kp + 1) * Pp);
+    maxf = std::max(maxf, P * 4 * c);          // fp32 layer gradients / tconv outputs (<= 4c per pixel)
+    maxpart = std::max(maxpart, (int64_t)8 * 1024 * 1024);
+  }
+  const int64_t P1 = P_of(u, 0);
+  SH_TRY(a.x0.alloc(P1));
+  SH_TRY(a.z.alloc(P1));
+  SH_TRY(a.gbf.alloc(P1));
+  SH_TRY(a.col.alloc(maxcol));
+  SH_TRY(a.colT.alloc(maxT));
+  SH_TRY(a.gT.alloc(maxT));
+  SH_TRY(a.gm.alloc(maxf));
+  SH_TRY(a.gG.alloc(maxf));
+  SH_TRY(a.f32a.alloc(maxf));
+  SH_TRY(a.gA.alloc(maxf));
+  SH_TRY(a.gB.alloc(maxf));
+  SH_TRY(a.gC.alloc(maxf));
+  a.skipg.resize(L);
+  for (int l = 0; l < L - 1; ++l) SH_TRY(a.skipg[l].alloc(P_of(u, l) * (u->base << l)));
+  SH_TRY(a.part.alloc(maxpart));
+  SH_TRY(a.lpart.alloc(512));
+  SH_TRY(a.loss.alloc(1));
+  return SH_OK;
+}
+
+// C (M x N, fp32 and/or bf16) = A (M x K) . B (N x K)^T; K % 16 == 0.  Split-K over pixels for the
+// weight gradients, reduced in fixed order through `part`.
+sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M, int N, int64_t K,
+               const float* bias, bool relu, float* C, int ldc, uint16_t* Cb, int ldcb, bool allow_split,
+               hipStream_t st) {
+  SH_REQUIRE(K % 16 == 0 && K > 0, "internal: GEMM K = %lld not a multiple of 16", (long long)K);
+  SH_REQUIRE(M < (int64_t(1) << 31) / GBM, "internal: GEMM M too large");
+  const unsigned gx = (unsigned)sh::cdiv(N, GBN), gy = (unsigned)sh::cdiv(M, GBM);
+  int S = 1;
+  if (allow_split) {
+    const int64_t tiles = (int64_t)gx * gy;
+    S = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(tiles, 1), K / 256));
+    while (S > 1 && (int64_t)S * M * N > u->ap->part.count) --S;
+  }
+  const int64_t kchunk = rup(sh::cdiv(K, S), GBK);
+  S = (int)sh::cdiv(K, kchunk);
+  if (S == 1) {
+    hipLaunchKernelGGL(gemm_nt, dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K, (int)kchunk, bias,
+                       relu ? 1 : 0, C, ldc, Cb, ldcb);
+  } else {
+    SH_REQUIRE(C && !Cb && !bias && !relu && ldc == N, "internal: split GEMM writes plain fp32");
+    hipLaunchKernelGGL(gemm_nt, dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K, (int)kchunk,
+                       nullptr, 0, u->ap->part.ptr, N, nullptr, 0);
+    hipLaunchKernelGGL(sum_splits, dim3(nb(M * N)), dim3(256), 0, st, u->ap->part.ptr, S, M * N, C);
+  }
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status prep_weights(sh_unet u, hipStream_t st) {
+  for (const Layer& ly : u->layers) {
+    const float* W = u->params.ptr + ly.w_off;
+    uint16_t* of = u->ops.ptr + ly.op_f;
+    uint16_t* od = u->ops.ptr + ly.op_d;
+    if (ly.kind == CONV3) {
+      const int64_t n = (int64_t)ly.cout * ly.Kp + (int64_t)ly.cin * ly.Kpd;
+      hipLaunchKernelGGL(prep_conv, dim3(nb(n)), dim3(256), 0, st, W, ly.cout, ly.cin, ly.Kp, ly.Kpd, of, od);
+    } else if (ly.kind == TCONV) {
+      hipLaunchKernelGGL(prep_tconv, dim3(nb((int64_t)ly.cin * ly.cout * 4)), dim3(256), 0, st, W, ly.cin, ly.cout, of,
+                         od);
+    } else {
+      hipLaunchKernelGGL(f32_to_bf16, dim3(nb(ly.cin)), dim3(256), 0, st, W, of, (int64_t)ly.cin);
+    }
+  }
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+// conv3 forward: out (P x Co, bf16) = relu(im2col(in) . wf^T + b)
+sh_status conv_fwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, int B, int H, int W, uint16_t* out,
+                   hipStream_t st) {
+  const int64_t P = (int64_t)B * H * W;
+  hipLaunchKernelGGL(im2col3, dim3(nb(P * (ly.Kp / 8))), dim3(256), 0, st, in, ldin, B, H, W, ly.cin, ly.Kp,
+                     u->ap->col.ptr);
+  return gemm(u, u->ap->col.ptr, ly.Kp, u->ops.ptr + ly.op_f, ly.Kp, P, ly.cout, ly.Kp, u->params.ptr + ly.b_off, true,
+              nullptr, 0, out, ly.cout, false, st);
+}
+
+// conv3 backward.  gin (+ gin2, strided) is the fp32 gradient at the layer's post-ReLU output `out`.
+// Writes the weight and bias gradients and, if dx is set, the fp32 gradient at the input.
+sh_status conv_bwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, const uint16_t* out, const float* gin,
+                   int ldg, const float* gin2, int ldg2, int B, int H, int W, float* dx, hipStream_t st) {
+  Acts& a = *u->ap;
+  const int64_t P = (int64_t)B * H * W, Pp = rup(P, 16);
+  hipLaunchKernelGGL(relu_mask_grad, dim3(nb(P * ly.cout)), dim3(256), 0, st, gin, ldg, gin2, ldg2, out, P, ly.cout,
+                     a.gm.ptr);
+  // weight gradient: gm^T (Co x Pp) . [col^T; 1] ((Kp+1) x Pp)^T
+  hipLaunchKernelGGL(im2col3, dim3(nb(P * (ly.Kp / 8))), dim3(256), 0, st, in, ldin, B, H, W, ly.cin, ly.Kp, a.col.ptr);
+  hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(Pp, 32), (unsigned)sh::cdiv(ly.Kp, 32)), dim3(256), 0, st,
+                     a.col.ptr, P, ly.Kp, ly.Kp, a.colT.ptr, Pp, 1);
+  hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(Pp, 32), (unsigned)sh::cdiv(ly.cout, 32)), dim3(256), 0,
+                     st, a.gm.ptr, P, ly.cout, ly.cout, a.gT.ptr, Pp, 0);
+  SH_TRY(gemm(u, a.gT.ptr, (int)Pp, a.colT.ptr, (int)Pp, ly.cout, ly.Kp + 1, Pp, nullptr, false, u->dwg.ptr, ly.Kp + 1,
+              nullptr, 0, true, st));
+  const int64_t ns = (int64_t)ly.cout * ly.cin * 9 + ly.cout;
+  hipLaunchKernelGGL(scatter_conv_grad, dim3(nb(ns)), dim3(256), 0, st, u->dwg.ptr, ly.cout, ly.cin, ly.Kp,
+                     u->grads.ptr + ly.w_off, u->grads.ptr + ly.b_off);
+  SH_LAUNCHED();
+  if (!dx) return SH_OK;
+  // input gradient: im2col(gm) . wd^T
+  hipLaunchKernelGGL(im2col3, dim3(nb(P * (ly.Kpd / 8))), dim3(256), 0, st, a.gm.ptr, ly.cout, B, H, W, ly.cout, ly.Kpd,
+                     a.col.ptr);
+  return gemm(u, a.col.ptr, ly.Kpd, u->ops.ptr + ly.op_d, ly.Kpd, P, ly.cin, ly.Kpd, nullptr, false, dx, ly.cin,
+              nullptr, 0, false, st);
+}
+
+// Forward pass over B images of H x W (input x fp32 device), keeping every activation.
+sh_status net_forward(sh_unet u, const float* x, int B, int H, int W, hipStream_t st) {
+  SH_TRY(ensure_acts(u, B, H, W));
+  SH_TRY(prep_weights(u, st));
+  Acts& a = *u->ap;
+  const int L = u->levels;
+  const int64_t P1 = (int64_t)B * H * W;
+  hipLaunchKernelGGL(f32_to_bf16, dim3(nb(P1)), dim3(256), 0, st, x, a.x0.ptr, P1);
+  const uint16_t* cur = a.x0.ptr;
+  int ldc = 1;
+  int li = 0;
+  for (int l = 0; l < L; ++l) {
+    const int h = H >> l, w = W >> l, c = u->base << l;
+    if (l > 0) {
+      const int pc = c / 2;
+      hipLaunchKernelGGL(pool_fwd, dim3(nb((int64_t)B * h * w * pc)), dim3(256), 0, st, a.enc[2 * l - 1].ptr, B, 2 * h,
+                         2 * w, pc, a.pooled[l].ptr, a.pidx[l].ptr);
+      cur = a.pooled[l].ptr;
+      ldc = pc;
+    }
+    SH_TRY(conv_fwd(u, u->layers[li++], cur, ldc, B, h, w, a.enc[2 * l].ptr, st));
+    SH_TRY(conv_fwd(u, u->layers[li++], a.enc[2 * l].ptr, c, B, h, w, a.enc[2 * l + 1].ptr, st));
+    cur = a.enc[2 * l + 1].ptr;
+    ldc = c;
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const int h = H >> l, w = W >> l, c = u->base << l;
+    const int64_t Pin = (int64_t)B * (h / 2) * (w / 2), P = (int64_t)B * h * w;
+    const Layer& tl = u->layers[li++];
+    SH_TRY(gemm(u, cur, ldc, u->ops.ptr + tl.op_f, tl.cin, Pin, 4 * c, tl.cin, nullptr, false, a.f32a.ptr, 4 * c,
+                nullptr, 0, false, st));
+    hipLaunchKernelGGL(tconv_scatter, dim3(nb(Pin * 4 * c)), dim3(256), 0, st, a.f32a.ptr, u->params.ptr + tl.b_off, B,
+                       h / 2, w / 2, c, a.cat[l].ptr, 2 * c);
+    hipLaunchKernelGGL(copy_channels, dim3(nb(P * c)), dim3(256), 0, st, a.enc[2 * l + 1].ptr, c, a.cat[l].ptr, 2 * c,
+                       c, P, c);
+    SH_TRY(conv_fwd(u, u->layers[li++], a.cat[l].ptr, 2 * c, B, h, w, a.dec[2 * l].ptr, st));
+    SH_TRY(conv_fwd(u, u->layers[li++], a.dec[2 * l].ptr, c, B, h, w, a.dec[2 * l + 1].ptr, st));
+    cur = a.dec[2 * l + 1].ptr;
+    ldc = c;
+  }
+  const Layer& hd = u->layers[li];
+  return gemm(u, cur, ldc, u->ops.ptr + hd.op_f, hd.cin, P1, 1, hd.cin, u->params.ptr + hd.b_off, false, a.z.ptr, 1,
+              nullptr, 0, false, st);
+}
+
+// fp32 strided copy: dst[p*C + c] = src[p*lds + off + c]
+__global__ void copy_f32_channels(const float* __restrict__ src, int lds, int off, float* __restrict__ dst, int64_t P,
+                                  int C) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= P * C) return;
+  const int64_t p = t / C;
+  const int c = int(t - p * C);
+  dst[t] = src[p * lds + off + c];
+}
+
+// Backward pass after net_forward (every parameter gradient into u->grads); target fp32 device.
+// The loss lands in a.loss (device) and relu(z) in y_out if given.
+sh_status net_backward(sh_unet u, const float* target, float* y_out, hipStream_t st) {
+  Acts& a = *u->ap;
+  const int B = a.B, H = a.H, W = a.W, L = u->levels;
+  const int64_t P1 = (int64_t)B * H * W, P1p = rup(P1, 16);
+  const int nblocks = 256;
+  hipLaunchKernelGGL(mse_loss, dim3(nblocks), dim3(256), 0, st, a.z.ptr, target, P1, y_out, a.gbf.ptr, a.lpart.ptr);
+  hipLaunchKernelGGL(sum_part_f64, dim3(1), dim3(64), 0, st, a.lpart.ptr, nblocks, P1, a.loss.ptr);
+  const int nl = (int)u->layers.size();
+  // head: dW = g^T . [a^T; 1]^T, da = g w
+  const Layer& hd = u->layers[nl - 1];
+  const uint16_t* hin = L > 1 ? a.dec[1].ptr : a.enc[1].ptr;
+  const int c1 = u->base;
+  hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(P1p, 32), 1), dim3(256), 0, st, a.gbf.ptr, P1, 1, 1,
+                     a.gT.ptr, P1p, 0);
+  hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(P1p, 32), (unsigned)sh::cdiv(c1, 32)), dim3(256), 0, st,
+                     hin, P1, c1, c1, a.colT.ptr, P1p, 1);
+  SH_TRY(gemm(u, a.gT.ptr, (int)P1p, a.colT.ptr, (int)P1p, 1, c1 + 1, P1p, nullptr, false, u->dwg.ptr, c1 + 1, nullptr,
+              0, true, st));
+  hipLaunchKernelGGL(copy_f32_channels, dim3(1), dim3(256), 0, st, u->dwg.ptr, c1 + 1, 0, u->grads.ptr + hd.w_off,
+                     (int64_t)1, c1);
+  hipLaunchKernelGGL(copy_f32_channels, dim3(1), dim3(256), 0, st, u->dwg.ptr, c1 + 1, c1, u->grads.ptr + hd.b_off,
+                     (int64_t)1, 1);
+  hipLaunchKernelGGL(head_dx, dim3(nb(P1 * c1)), dim3(256), 0, st, a.gbf.ptr, u->ops.ptr + hd.op_f, P1, c1, a.gA.ptr);
+  SH_LAUNCHED();
+  // decoder, level 1 first; gA holds the gradient at the current level's last output
+  int li = nl - 2;
+  for (int l = 0; l < L - 1; ++l) {
+    const int h = H >> l, w = W >> l, c = u->base << l;
+    const int64_t P = (int64_t)B * h * w, Pin = (int64_t)B * (h / 2) * (w / 2), Pinp = rup(Pin, 16);
+    const Layer& lb = u->layers[li--];
+    const Layer& la = u->layers[li--];
+    const Layer& tl = u->layers[li--];
+    SH_TRY(conv_bwd(u, lb, a.dec[2 * l].ptr, c, a.dec[2 * l + 1].ptr, a.gA.ptr, c, nullptr, 0, B, h, w, a.gB.ptr, st));
+    SH_TRY(conv_bwd(u, la, a.cat[l].ptr, 2 * c, a.dec[2 * l].ptr, a.gB.ptr, c, nullptr, 0, B, h, w, a.gC.ptr, st));
+    // gC = gradient at [upsampled, skip]; the skip half waits for encoder level l
+    hipLaunchKernelGGL(copy_f32_channels, dim3(nb(P * c)), dim3(256), 0, st, a.gC.ptr, 2 * c, c, a.skipg[l].ptr, P, c);
+    // transposed convolution from the upsampled half
+    const int cin = tl.cin;
+    const uint16_t* tin = l + 1 < L - 1 ? a.dec[2 * (l + 1) + 1].ptr : a.enc[2 * (l + 1) + 1].ptr;
+    hipLaunchKernelGGL(tconv_gather, dim3(nb(Pin * 4 * c)), dim3(256), 0, st, a.gC.ptr, 2 * c, B, h / 2, w / 2, c,
+                       a.gG.ptr);
+    hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(Pinp, 32), (unsigned)sh::cdiv(4 * c, 32)), dim3(256), 0,
+                       st, a.gG.ptr, Pin, 4 * c, 4 * c, a.gT.ptr, Pinp, 0);
+    hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(Pinp, 32), (unsigned)sh::cdiv(cin, 32)), dim3(256), 0,
+                       st, tin, Pin, cin, cin, a.colT.ptr, Pinp, 1);
+    SH_TRY(gemm(u, a.gT.ptr, (int)Pinp, a.colT.ptr, (int)Pinp, 4 * c, cin + 1, Pinp, nullptr, false, u->dwg.ptr, cin + 1,
+                nullptr, 0, true, st));
+    hipLaunchKernelGGL(scatter_tconv_grad, dim3(nb((int64_t)cin * c * 4 + c)), dim3(256), 0, st, u->dwg.ptr, cin, c,
+                       u->grads.ptr + tl.w_off, u->grads.ptr + tl.b_off);
+    SH_LAUNCHED();
+    SH_TRY(gemm(u, a.gG.ptr, 4 * c, u->ops.ptr + tl.op_d, 4 * c, Pin, cin, 4 * c, nullptr, false, a.gA.ptr, cin,
+                nullptr, 0, false, st));
+  }
+  // encoder, bottleneck first
+  for (int l = L - 1; l >= 0; --l) {
+    const int h = H >> l, w = W >> l, c = u->base << l;
+    const Layer& lb = u->layers[2 * l + 1];
+    const Layer& la = u->layers[2 * l];
+    const float* skip = l < L - 1 ? a.skipg[l].ptr : nullptr;
+    SH_TRY(conv_bwd(u, lb, a.enc[2 * l].ptr, c, a.enc[2 * l + 1].ptr, a.gA.ptr, c, skip, c, B, h, w, a.gB.ptr, st));
+    const uint16_t* in = l > 0 ? a.pooled[l].ptr : a.x0.ptr;
+    const int ldin = l > 0 ? c / 2 : 1;
+    SH_TRY(conv_bwd(u, la, in, ldin, a.enc[2 * l].ptr, a.gB.ptr, c, nullptr, 0, B, h, w, l > 0 ? a.gC.ptr : nullptr,
+                    st));
+    if (l > 0) {
+      const int pc = c / 2;
+      hipLaunchKernelGGL(pool_bwd, dim3(nb((int64_t)B * h * w * pc)), dim3(256), 0, st, a.gC.ptr, a.pidx[l].ptr, B,
+                         2 * h, 2 * w, pc, a.gA.ptr);
+      SH_LAUNCHED();
+    }
+  }
+  return SH_OK;
+}
+
+sh_status check_shape(sh_unet u, const float* x, int B, int H, int W) {
+  SH_REQUIRE(u && x, "NULL argument");
+  const int m = 1 << (u->levels - 1);
+  SH_REQUIRE(B >= 1 && H >= m && W >= m && H % m == 0 && W % m == 0,
+             "B >= 1 and H, W divisible by 2^(levels-1) = %d required (got %d x %d x %d)", m, B, H, W);
+  SH_REQUIRE((int64_t)B * H * W <= (int64_t(1) << 26), "B*H*W must be <= 2^26");
+  return SH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sh_status sh_unet_create(int32_t base, int32_t levels, sh_unet* out) {
+  SH_REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  SH_REQUIRE(base >= 16 && base <= 128 && base % 16 == 0, "base channels must be a multiple of 16 in [16, 128]");
+  SH_REQUIRE(levels >= 1 && levels <= 6, "levels must be in [1, 6]");
+  std::unique_ptr<sh_unet_s> u(new (std::nothrow) sh_unet_s());
+  if (!u) {
+    sh::set_error("host allocation failed");
+    return SH_ENOMEM;
+  }
+  u->base = base;
+  u->levels = levels;
+  int64_t off = 0, oo = 0, dwg = 0;
+  auto add = [&](int kind, int cin, int cout) {
+    Layer ly{kind, cin, cout, 0, 0, 0, 0, 0, 0};
+    const int64_t nw = kind == CONV3 ? (int64_t)cout * cin * 9 : kind == TCONV ? (int64_t)cin * cout * 4 : cin;
+    ly.w_off = off;
+    ly.b_off = off + nw;
+    off += nw + cout;
+    if (kind == CONV3) {
+      ly.Kp = (int)rup(9 * cin, 16);
+      ly.Kpd = (int)rup(9 * cout, 16);
+      ly.op_f = oo;
+      ly.op_d = oo + (int64_t)cout * ly.Kp;
+      oo += (int64_t)cout * ly.Kp + (int64_t)cin * ly.Kpd;
+      dwg = std::max<int64_t>(dwg, (int64_t)cout * (ly.Kp + 1));
+    } else if (kind == TCONV) {
+      ly.op_f = oo;
+      ly.op_d = oo + (int64_t)cin * cout * 4;
+      oo += (int64_t)cin * cout * 8;
+      dwg = std::max<int64_t>(dwg, (int64_t)4 * cout * (cin + 1));
+    } else {
+      ly.op_f = ly.op_d = oo;
+      oo += rup(cin, 16);
+      dwg = std::max<int64_t>(dwg, cin + 1);
+    }
+    u->layers.push_back(ly);
+  };
+  for (int l = 0; l < levels; ++l) {
+    const int c = base << l;
+    add(CONV3, l == 0 ? 1 : c / 2, c);
+    add(CONV3, c, c);
+  }
+  for (int l = levels - 2; l >= 0; --l) {
+    const int c = base << l;
+    add(TCONV, 2 * c, c);
+    add(CONV3, 2 * c, c);
+    add(CONV3, c, c);
+  }
+  add(HEAD, base, 1);
+  u->nparams = off;
+  u->nops = oo;
+  SH_TRY(u->params.alloc(off));
+  SH_TRY(u->grads.alloc(off));
+  SH_TRY(u->m.alloc(off));
+  SH_TRY(u->v.alloc(off));
+  SH_TRY(u->ops.alloc(oo));
+  SH_TRY(u->dwg.alloc(dwg));
+  SH_HIP(hipMemset(u->params.ptr, 0, off * sizeof(float)));
+  SH_HIP(hipMemset(u->grads.ptr, 0, off * sizeof(float)));
+  SH_HIP(hipMemset(u->m.ptr, 0, off * sizeof(float)));
+  SH_HIP(hipMemset(u->v.ptr, 0, off * sizeof(float)));
+  SH_HIP(hipMemset(u->ops.ptr, 0, oo * sizeof(uint16_t)));
+  *out = u.release();
+  return SH_OK;
+}
+
+sh_status sh_unet_destroy(sh_unet u) {
+  delete u;
+  return SH_OK;
+}
+
+sh_status sh_unet_num_params(sh_unet u, int64_t* n_out) {
+  SH_REQUIRE(u && n_out, "NULL argument");
+  *n_out = u->nparams;
+  return SH_OK;
+}
+
+sh_status sh_unet_set_params(sh_unet u, const float* host, int64_t n) {
+  SH_REQUIRE(u && host, "NULL argument");
+  SH_REQUIRE(n == u->nparams, "expected %lld parameters, got %lld", (long long)u->nparams, (long long)n);
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(host[i])) {
+      sh::set_error("parameter %lld is not finite", (long long)i);
+      return SH_ENONFINITE;
+    }
+  SH_HIP(hipMemcpy(u->params.ptr, host, n * sizeof(float), hipMemcpyHostToDevice));
+  SH_HIP(hipMemset(u->m.ptr, 0, n * sizeof(float)));
+  SH_HIP(hipMemset(u->v.ptr, 0, n * sizeof(float)));
+  u->t = 0;
+  return SH_OK;
+}
+
+sh_status sh_unet_get_params(sh_unet u, float* host, int64_t n) {
+  SH_REQUIRE(u && host, "NULL argument");
+  SH_REQUIRE(n == u->nparams, "expected %lld parameters, got %lld", (long long)u->nparams, (long long)n);
+  SH_HIP(hipMemcpy(host, u->params.ptr, n * sizeof(float), hipMemcpyDeviceToHost));
+  return SH_OK;
+}
+
+sh_status sh_unet_forward(sh_unet u, const float* x, int32_t B, int32_t H, int32_t W, float* y, void* stream) {
+  SH_TRY(check_shape(u, x, B, H, W));
+  SH_REQUIRE(y, "y is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  SH_TRY(net_forward(u, x, B, H, W, st));
+  hipLaunchKernelGGL(mse_loss, dim3(64), dim3(256), 0, st, u->ap->z.ptr, u->ap->z.ptr, (int64_t)B * H * W, y, nullptr,
+                     u->ap->lpart.ptr);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status sh_unet_loss_grad(sh_unet u, const float* x, const float* target, int32_t B, int32_t H, int32_t W,
+                            double* loss_out, float* grads_host, void* stream) {
+  SH_TRY(check_shape(u, x, B, H, W));
+  SH_REQUIRE(target && loss_out, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  SH_TRY(net_forward(u, x, B, H, W, st));
+  SH_TRY(net_backward(u, target, nullptr, st));
+  SH_HIP(hipMemcpyAsync(loss_out, u->ap->loss.ptr, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (grads_host)
+    SH_HIP(hipMemcpyAsync(grads_host, u->grads.ptr, u->nparams * sizeof(float), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipStreamSynchronize(st));
+  return SH_OK;
+}
+
+sh_status sh_unet_train_step(sh_unet u, const float* x, const float* target, int32_t B, int32_t H, int32_t W,
+                             float lr, double* loss_out, void* stream) {
+  SH_TRY(check_shape(u, x, B, H, W));
+  SH_REQUIRE(target, "target is NULL");
+  SH_REQUIRE(std::isfinite(lr) && lr > 0.f, "lr must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  SH_TRY(net_forward(u, x, B, H, W, st));
+  SH_TRY(net_backward(u, target, nullptr, st));
+  u->t += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  hipLaunchKernelGGL(adam_kernel, dim3(nb(u->nparams)), dim3(256), 0, st, u->params.ptr, u->grads.ptr, u->m.ptr,
+                     u->v.ptr, u->nparams, lr, (float)b1, (float)b2, 1e-8f, (float)(1.0 - std::pow(b1, (double)u->t)),
+                     (float)(1.0 - std::pow(b2, (double)u->t)));
+  SH_LAUNCHED();
+  if (loss_out) {
+    SH_HIP(hipMemcpyAsync(loss_out, u->ap->loss.ptr, sizeof(double), hipMemcpyDeviceToHost, st));
+    SH_HIP(hipStreamSynchronize(st));
+  }
+  return SH_OK;
+}
+
+}  // extern "C"

@@ -103,6 +103,14 @@ _SIGS = {
     "sh_sdmm_iterate": (C.c_int, [_vp, _i32, _vp]),
     "sh_sdmm_result": (C.c_int, [_vp, _vp, _P64, _P64, _vp]),
     "sh_sdmm_destroy": (C.c_int, [_vp]),
+    "sh_unet_create": (C.c_int, [_i32, _i32, C.POINTER(_vp)]),
+    "sh_unet_destroy": (C.c_int, [_vp]),
+    "sh_unet_num_params": (C.c_int, [_vp, _PI64]),
+    "sh_unet_set_params": (C.c_int, [_vp, C.POINTER(C.c_float), _i64]),
+    "sh_unet_get_params": (C.c_int, [_vp, C.POINTER(C.c_float), _i64]),
+    "sh_unet_forward": (C.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
+    "sh_unet_loss_grad": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _P64, C.POINTER(C.c_float), _vp]),
+    "sh_unet_train_step": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _f32, _P64, _vp]),
     "sh_profile_enable": (C.c_int, [_i32]),
     "sh_profile_read": (C.c_int, [C.c_char_p, _PI64, _P64]),
 }
@@ -378,6 +386,69 @@ def sdmm_result(s: int, x_out=None, R: int = 0, stream=None, P: int = 1):
 
 def sdmm_destroy(s: int) -> None:
     _check(lib.sh_sdmm_destroy(s), "sdmm_destroy")
+
+
+# ---- learned warm start ---------------------------------------------------------------------
+
+_PF32 = C.POINTER(C.c_float)
+
+
+def unet_create(base: int = 32, levels: int = 4) -> int:
+    h = _vp()
+    _check(lib.sh_unet_create(base, levels, C.byref(h)), "unet_create")
+    return h.value
+
+
+def unet_destroy(u: int) -> None:
+    _check(lib.sh_unet_destroy(u), "unet_destroy")
+
+
+def unet_num_params(u: int) -> int:
+    n = C.c_int64()
+    _check(lib.sh_unet_num_params(u, C.byref(n)), "unet_num_params")
+    return n.value
+
+
+def unet_set_params(u: int, flat: np.ndarray) -> None:
+    a = np.ascontiguousarray(flat, dtype=np.float32)
+    _check(lib.sh_unet_set_params(u, a.ctypes.data_as(_PF32), a.size), "unet_set_params")
+
+
+def unet_get_params(u: int) -> np.ndarray:
+    a = np.zeros(unet_num_params(u), dtype=np.float32)
+    _check(lib.sh_unet_get_params(u, a.ctypes.data_as(_PF32), a.size), "unet_get_params")
+    return a
+
+
+def _bhw(x):
+    if x.dim() == 2:
+        return 1, x.shape[0], x.shape[1]
+    if x.dim() == 3:
+        return x.shape[0], x.shape[1], x.shape[2]
+    raise ValueError("images must be (H, W) or (B, H, W)")
+
+
+def unet_forward(u: int, x, y, stream=None) -> None:
+    B, H, W = _bhw(x)
+    _check(lib.sh_unet_forward(u, _ptr(x), B, H, W, _ptr(y), _stream(stream)), "unet_forward")
+
+
+def unet_loss_grad(u: int, x, target, want_grads: bool = True, stream=None):
+    """Returns (loss, flat float32 gradient or None)."""
+    B, H, W = _bhw(x)
+    loss = C.c_double()
+    g = np.zeros(unet_num_params(u), dtype=np.float32) if want_grads else None
+    _check(lib.sh_unet_loss_grad(u, _ptr(x), _ptr(target), B, H, W, C.byref(loss),
+                                 g.ctypes.data_as(_PF32) if want_grads else None, _stream(stream)), "unet_loss_grad")
+    return loss.value, g
+
+
+def unet_train_step(u: int, x, target, lr: float, want_loss: bool = True, stream=None):
+    B, H, W = _bhw(x)
+    loss = C.c_double()
+    _check(lib.sh_unet_train_step(u, _ptr(x), _ptr(target), B, H, W, lr, C.byref(loss) if want_loss else None,
+                                  _stream(stream)), "unet_train_step")
+    return loss.value if want_loss else None
 
 
 # ---- timing ---------------------------------------------------------------------------------
