@@ -79,6 +79,29 @@ def cpu_baseline(wl, sample=1_000_000):
                       f"visibilities (every {stride}th), n={wl['n']}, J={wl['J']}: {dt:.2f} s"}
 
 
+def warm_measure(sh, op, psi, y, eps, prm, n, dev, x_plain, x_true):
+    """Warm-started solve of the same problem (trained U-Net + first weights from its output), timed
+    from the call to the return like the plain one.  Empty when no trained weights are present."""
+    import torch
+    from paper_1502_05037_amd import warmstart
+    if not os.path.exists(warmstart.WEIGHTS):
+        log("[bench] no trained warm-start weights: warm start not measured")
+        return {}
+    ws = warmstart.WarmStart.load()
+    try:
+        xw = torch.empty((1, n, n), device=dev)
+        log("[bench] warm-started SDMM to the same tolerance ...")
+        info, res, secs = warmstart.warm_solve(ws, op, psi, y, eps, prm, n, dev, xw)
+    finally:
+        ws.close()
+    xw = xw.reshape(n, n)
+    return {"warm_seconds": round(secs, 3), "warm_iters": info["iters_total"], "warm_passes": info["passes_done"],
+            "warm_converged_last_pass": info["converged"], "warm_max_resid_over_eps": float(np.max(res / eps)),
+            "warm_error_vs_true_sky": float(torch.linalg.vector_norm(xw - x_true) / torch.linalg.vector_norm(x_true)),
+            "warm_vs_plain_image_rel_diff": float(torch.linalg.vector_norm(xw - x_plain.reshape(n, n))
+                                                  / torch.linalg.vector_norm(x_plain))}
+
+
 def batched_workload(P=32, n=256, cfg=4):
     """32 independent 256 x 256 problems (frequency channels): M_p log-uniform in [1e5, 1e6], R_p uniform
     in 2..16 uneven blocks, Gaussian-density uv coverage, 20 point sources + blobs each, 30 dB SNR."""
@@ -313,7 +336,9 @@ def main():
         tol = {"plain_seconds": round(time.perf_counter() - t0, 3), "plain_iters": info["iters_total"],
                "passes": info["passes_done"], "converged_last_pass": info["converged"],
                "max_resid_over_eps": float(np.max(res / eps)), "tol_rel": 1e-4,
+               "plain_error_vs_true_sky": float(torch.linalg.vector_norm(x - x_true) / torch.linalg.vector_norm(x_true)),
                "warm_seconds": None, "warm_iters": None}
+        tol.update(warm_measure(sh, op, psi, y, eps, p2, n, dev, x, x_true))
         log(f"[bench] time-to-tol {tol}")
 
     if a.copy_mb:

@@ -206,10 +206,13 @@ typedef struct {
   int32_t check_every; /* host reads the stopping flags every this many iterations (>= 1) */
   int32_t graph;       /* 1: capture one iteration as a HIP graph and replay it; 0: plain launches.
                           Same arithmetic either way; kernel timing (sh_profile_enable) forces 0 */
+  int32_t w_from_x0;   /* 1 (needs x0, W NULL): first-pass weights from the warm start by the
+                          reweighting rule, delta_1 = std(Psi^dagger x0) per problem and
+                          W = delta_1 / (delta_1 + |Psi^dagger x0|), as if x0 ended a pass */
 } sh_sdmm_params;
 
 /* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
- * max_iter 300, cg_iters 8, passes 1, check_every 10, graph 1.  With a batched plan, a given
+ * max_iter 300, cg_iters 8, passes 1, check_every 10, graph 1, w_from_x0 0.  With a batched plan, a given
  * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 
@@ -299,6 +302,18 @@ sh_status sh_unet_loss_grad(sh_unet u, const float* x, const float* target, int3
  * loss_out (host, may be NULL: then the call is async) receives the loss before the step. */
 sh_status sh_unet_train_step(sh_unet u, const float* x, const float* target, int32_t B, int32_t H, int32_t W,
                              float lr, double* loss_out, void* stream);
+
+/* Warm start of a solve with plan op (P problems, image side n): x0_out (device P x n x n) =
+ * s U(d / s) per problem, with d = Phi^dagger y / (Phi^dagger Phi delta)(centre) the dirty image
+ * in units of the PSF peak (delta = unit image at (n/2, n/2)) and s = RMS(d) (so the network
+ * input has unit RMS).  y: device M complex64,
+ * user order.  Pass x0_out to sh_sdmm_solve with w_from_x0 = 1.  Synchronous (allocates scratch). */
+sh_status sh_warm_start(sh_unet u, sh_op op, const float* y, float* x0_out, void* stream);
+/* The network input alone: d_out (device P x n x n) = d / s and scale_out (device P float32) = s,
+ * with d and s as for sh_warm_start.  Synchronous. */
+sh_status sh_dirty_normalised(sh_op op, const float* y, float* d_out, float* scale_out, void* stream);
+/* x[p] *= scale[p] (invert 0) or x[p] /= scale[p] (invert 1) for P images of N pixels (device).  Async. */
+sh_status sh_scale_images(float* x, const float* scale, int32_t P, int64_t N, int32_t invert, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (HIP events around the gridding/degridding launches).

@@ -178,6 +178,7 @@ void sh_sdmm_default_params(sh_sdmm_params* p) {
   p->passes = 1;
   p->check_every = 10;
   p->graph = 1;
+  p->w_from_x0 = 0;
 }
 
 sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream) {
@@ -222,6 +223,8 @@ namespace {
 
 // s_misc layout: [0, P) dx^2, [P, 2P) x^2, [2P, 3P) scratch, [3P, 4P) objective, [4P, 5P) scratch
 enum { MISC_DX = 0, MISC_X = 1, MISC_TMP = 2, MISC_OBJ = 3, MISC_TMP2 = 4, MISC_N = 5 };
+
+sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st);
 
 sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* W0, const float* x0, hipStream_t st) {
   sh_op op = s->op;
@@ -320,6 +323,12 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     SH_HIP(hipMemsetAsync(w.sphi.ptr, 0, M * sizeof(float2), st));
   }
   SH_HIP(hipMemsetAsync(w.xprev.ptr, 0, N * sizeof(float), st));
+  if (s->prm.w_from_x0) {   // weights of the first pass from Psi^dagger x0 (delta_1 = std per problem)
+    SH_TRY(sh_psi_adj(s->psi, x0, w.spsi.ptr, st));
+    std::fill(s->delta.begin(), s->delta.end(), 0.0);
+    SH_TRY(sdmm_reweight(s, w.W.ptr, st));
+    s->Wp = w.W.ptr;
+  }
   return SH_OK;
 }
 
@@ -480,6 +489,7 @@ sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps,
   SH_REQUIRE(prm->tol_rel >= 0 && prm->eps_slack >= 0 && prm->rw_beta > 0 && std::isfinite(prm->rw_beta),
              "tol_rel, eps_slack >= 0 and rw_beta > 0 required");
   SH_REQUIRE(prm->graph == 0 || prm->graph == 1, "graph must be 0 or 1");
+  SH_REQUIRE(prm->w_from_x0 == 0 || prm->w_from_x0 == 1, "w_from_x0 must be 0 or 1");
   for (int i = 0; i < op->R; ++i) {
     if (!std::isfinite(eps[i])) {
       sh::set_error("eps[%d] is not finite", i);
@@ -499,6 +509,7 @@ sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps
   SH_REQUIRE(out, "out is NULL");
   *out = nullptr;
   SH_TRY(sdmm_validate(op, psi, y, eps, params));
+  SH_REQUIRE(!params->w_from_x0 || (x0 && !W), "w_from_x0 needs x0 and no W");
   sh_sdmm s = new (std::nothrow) sh_sdmm_s();
   if (!s) {
     sh::set_error("host allocation failed");

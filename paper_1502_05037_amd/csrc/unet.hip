@@ -22,7 +22,7 @@
 #include <memory>
 #include <vector>
 
-#include "common.hpp"
+#include "op.hpp"
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -895,6 +895,102 @@ sh_status sh_unet_train_step(sh_unet u, const float* x, const float* target, int
     SH_HIP(hipMemcpyAsync(loss_out, u->ap->loss.ptr, sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));
   }
+  return SH_OK;
+}
+
+}  // extern "C"
+
+// ---- warm start: x0 = s U(d / s), d = Phi^dagger y / PSF peak, s = RMS of d, per problem ----------------
+
+namespace {
+
+__global__ void delta_images(float* __restrict__ d, int n) {   // grid (cdiv(n*n, 256), P)
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)n * n) return;
+  d[(int64_t)blockIdx.y * n * n + i] = i == (int64_t)(n / 2) * n + n / 2 ? 1.f : 0.f;
+}
+
+// per problem (work-group p): peak = psf[p](centre); s = RMS(d_p) / peak; in = d_p / peak / s
+__global__ __launch_bounds__(256) void normalise_dirty(const float* __restrict__ psf, const float* __restrict__ d,
+                                                       int n, float* __restrict__ in, float* __restrict__ scale) {
+  __shared__ double sm[256];
+  const int64_t N = (int64_t)n * n, off = (int64_t)blockIdx.x * N;
+  const float peak = psf[off + (int64_t)(n / 2) * n + n / 2];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += 256) m += double(d[off + i]) * double(d[off + i]);
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+    __syncthreads();
+  }
+  const float sc = fmaxf(float(sqrt(sm[0] / double(N))) / peak, 1e-30f);
+  const float inv = 1.f / (peak * sc);
+  for (int64_t i = threadIdx.x; i < N; i += 256) in[off + i] = d[off + i] * inv;
+  if (threadIdx.x == 0) scale[blockIdx.x] = sc;
+}
+
+__global__ void rescale(float* __restrict__ x, const float* __restrict__ scale, int64_t N) {   // grid (.., P)
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) x[(int64_t)blockIdx.y * N + i] *= scale[blockIdx.y];
+}
+
+__global__ void rescale_inv(float* __restrict__ x, const float* __restrict__ scale, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) x[(int64_t)blockIdx.y * N + i] /= scale[blockIdx.y];
+}
+
+}  // namespace
+
+extern "C" {
+
+sh_status sh_dirty_normalised(sh_op op, const float* y, float* d_out, float* scale_out, void* stream) {
+  SH_REQUIRE(op && y && d_out && scale_out, "NULL argument");
+  const int n = op->n, P = op->P;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t N = (int64_t)n * n;
+  sh::DevBuf<float> d, psf;
+  sh::DevBuf<float2> v;
+  SH_TRY(d.alloc(N * P));
+  SH_TRY(psf.alloc(N * P));
+  SH_TRY(v.alloc(op->M));
+  hipLaunchKernelGGL(delta_images, dim3(nb(N), P), dim3(256), 0, st, d.ptr, n);
+  SH_LAUNCHED();
+  SH_TRY(sh::phi_forward(op, d.ptr, v.ptr, false, nullptr, st));
+  SH_TRY(sh::phi_adjoint(op, v.ptr, psf.ptr, false, nullptr, st));
+  SH_TRY(sh::phi_adjoint(op, (const float2*)y, d.ptr, true, nullptr, st));
+  hipLaunchKernelGGL(normalise_dirty, dim3(P), dim3(256), 0, st, psf.ptr, d.ptr, n, d_out, scale_out);
+  SH_LAUNCHED();
+  SH_HIP(hipStreamSynchronize(st));   // scratch is freed on return
+  return SH_OK;
+}
+
+sh_status sh_scale_images(float* x, const float* scale, int32_t P, int64_t N, int32_t invert, void* stream) {
+  SH_REQUIRE(x && scale && P >= 1 && N >= 1, "invalid argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (invert)
+    hipLaunchKernelGGL(rescale_inv, dim3(nb(N), P), dim3(256), 0, st, x, scale, N);
+  else
+    hipLaunchKernelGGL(rescale, dim3(nb(N), P), dim3(256), 0, st, x, scale, N);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status sh_warm_start(sh_unet u, sh_op op, const float* y, float* x0_out, void* stream) {
+  SH_REQUIRE(u && op && y && x0_out, "NULL argument");
+  const int n = op->n, P = op->P;
+  const int m = 1 << (u->levels - 1);
+  SH_REQUIRE(n % m == 0, "image side %d not divisible by 2^(levels-1) = %d", n, m);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t N = (int64_t)n * n;
+  sh::DevBuf<float> in, sc;
+  SH_TRY(in.alloc(N * P));
+  SH_TRY(sc.alloc(P));
+  SH_TRY(sh_dirty_normalised(op, y, in.ptr, sc.ptr, stream));
+  SH_TRY(sh_unet_forward(u, in.ptr, P, n, n, x0_out, stream));
+  hipLaunchKernelGGL(rescale, dim3(nb(N), P), dim3(256), 0, st, x0_out, sc.ptr, N);
+  SH_LAUNCHED();
+  SH_HIP(hipStreamSynchronize(st));   // scratch is freed on return
   return SH_OK;
 }
 

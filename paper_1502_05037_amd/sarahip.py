@@ -39,7 +39,8 @@ class SarahipError(RuntimeError):
 class SdmmParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("nu", C.c_double), ("tol_rel", C.c_double), ("eps_slack", C.c_double),
                 ("rw_beta", C.c_double), ("rw_delta0", C.c_double), ("max_iter", C.c_int32),
-                ("cg_iters", C.c_int32), ("passes", C.c_int32), ("check_every", C.c_int32), ("graph", C.c_int32)]
+                ("cg_iters", C.c_int32), ("passes", C.c_int32), ("check_every", C.c_int32), ("graph", C.c_int32),
+                ("w_from_x0", C.c_int32)]
 
 
 class SdmmInfo(C.Structure):
@@ -111,6 +112,9 @@ _SIGS = {
     "sh_unet_forward": (C.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
     "sh_unet_loss_grad": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _P64, C.POINTER(C.c_float), _vp]),
     "sh_unet_train_step": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _f32, _P64, _vp]),
+    "sh_warm_start": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "sh_dirty_normalised": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "sh_scale_images": (C.c_int, [_vp, _vp, _i32, _i64, _i32, _vp]),
     "sh_profile_enable": (C.c_int, [_i32]),
     "sh_profile_read": (C.c_int, [C.c_char_p, _PI64, _P64]),
 }
@@ -449,6 +453,20 @@ def unet_train_step(u: int, x, target, lr: float, want_loss: bool = True, stream
     _check(lib.sh_unet_train_step(u, _ptr(x), _ptr(target), B, H, W, lr, C.byref(loss) if want_loss else None,
                                   _stream(stream)), "unet_train_step")
     return loss.value if want_loss else None
+
+
+def warm_start(u: int, op: int, y, x0_out, stream=None) -> None:
+    _check(lib.sh_warm_start(u, op, _ptr(y), _ptr(x0_out), _stream(stream)), "warm_start")
+
+
+def dirty_normalised(op: int, y, d_out, scale_out, stream=None) -> None:
+    _check(lib.sh_dirty_normalised(op, _ptr(y), _ptr(d_out), _ptr(scale_out), _stream(stream)), "dirty_normalised")
+
+
+def scale_images(x, scale, invert: bool = False, stream=None) -> None:
+    P = scale.numel()
+    _check(lib.sh_scale_images(_ptr(x), _ptr(scale), P, x.numel() // P, 1 if invert else 0, _stream(stream)),
+           "scale_images")
 
 
 # ---- timing ---------------------------------------------------------------------------------
