@@ -102,6 +102,58 @@ def warm_measure(sh, op, psi, y, eps, prm, n, dev, x_plain, x_true):
                                                   / torch.linalg.vector_norm(x_plain))}
 
 
+def unet_flops(base=32, levels=4, n=256):
+    """Algorithmic flop of one U-Net forward on an n x n image (2 per multiply-add).  A layer's level
+    follows from its channel count c = base 2^l: side n >> l (input side n >> (l+1) for the
+    transposed convolution, whose cin = 2c)."""
+    from paper_1502_05037_amd.warmstart import layer_list
+    f = 0
+    for kind, cin, cout in layer_list(base, levels):
+        if kind == "conv3":
+            side = n >> ((cout // base).bit_length() - 1)
+            f += 2 * 9 * cin * cout * side * side
+        elif kind == "tconv":
+            side = n >> ((cin // base).bit_length() - 1)
+            f += 2 * 4 * cin * cout * side * side
+        else:
+            f += 2 * cin * cout * n * n
+    return f
+
+
+def unet_bench(sh, dev, reps=10):
+    """U-Net forward and training step (BF16 MFMA products) at 256^2 batch 8 and forward at 1024^2."""
+    import torch
+    from paper_1502_05037_amd.warmstart import he_init
+    u = sh.unet_create(32, 4)
+    out = {}
+    try:
+        sh.unet_set_params(u, he_init(32, 4, 0))
+        for name, B, n, train in (("fwd_256_b8", 8, 256, False), ("train_256_b8", 8, 256, True),
+                                  ("fwd_1024_b1", 1, 1024, False)):
+            g = torch.Generator(device="cpu").manual_seed(7)
+            x = torch.rand((B, n, n), generator=g).to(dev)
+            t = torch.rand((B, n, n), generator=g).to(dev)
+            y = torch.empty_like(x)
+            step = (lambda: sh.unet_train_step(u, x, t, 1e-4, want_loss=False)) if train else \
+                (lambda: sh.unet_forward(u, x, y))
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                step()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            fl = B * unet_flops(n=n) * (3 if train else 1)
+            out[name] = {"ms": round(ms, 3), "gflop": round(fl / 1e9, 1), "tflops": round(fl / ms / 1e9, 1),
+                         "frac_of_bf16_mfma_peak": round(fl / ms / 1e9 / 2500.0, 4)}
+            log(f"[bench] unet {name}: {out[name]}")
+        sh.unet_set_params(u, he_init(32, 4, 0))   # leave no trained state behind
+    finally:
+        sh.unet_destroy(u)
+    return out
+
+
 def batched_workload(P=32, n=256, cfg=4):
     """32 independent 256 x 256 problems (frequency channels): M_p log-uniform in [1e5, 1e6], R_p uniform
     in 2..16 uneven blocks, Gaussian-density uv coverage, 20 point sources + blobs each, 30 dB SNR."""
@@ -216,6 +268,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tol", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-small-problems measurement")
+    ap.add_argument("--no-unet", action="store_true", help="skip the U-Net kernel measurement")
+    ap.add_argument("--only-unet", action="store_true", help="run the U-Net kernel measurement alone")
     ap.add_argument("--m", type=int, default=20_000_000)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run three plain device copies of this many MiB (HBM counter calibration)")
@@ -230,6 +284,9 @@ def main():
     from paper_1502_05037_amd import sarahip as sh
 
     dev = torch.device("cuda:0")
+    if a.only_unet:
+        print(json.dumps({"unet": unet_bench(sh, dev)}), flush=True)
+        return
     wl = setup_workload(m=a.m)
     n, m, R, J = wl["n"], wl["m"], wl["R"], wl["J"]
     t0 = time.time()
@@ -353,6 +410,7 @@ def main():
     sh.op_destroy(op)
     del y, clean, x_true
     batched = None if a.no_batch else batched_bench(sh, dev, a.steps, a.warmup, with_tol=not a.no_tol)
+    unet = None if a.no_unet else unet_bench(sh, dev)
     cpu = None if a.no_cpu else cpu_baseline(wl)
     out = {
         "metric": METRIC, "value": value, "unit": "vis/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -365,7 +423,7 @@ def main():
                  "internal_ms": 1e3 * pair_s, "user_ms": 1e3 * pair_user_s},
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
         "roofline": roof, "cpu_baseline": cpu, "sdmm_time_to_tol": tol, "plan_seconds": round(plan_s, 2),
-        "batched": batched,
+        "batched": batched, "unet": unet,
     }
     print(json.dumps(out), flush=True)
 
