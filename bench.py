@@ -97,6 +97,7 @@ def warm_measure(sh, op, psi, y, eps, prm, n, dev, x_plain, x_true):
     xw = xw.reshape(n, n)
     return {"warm_seconds": round(secs, 3), "warm_iters": info["iters_total"], "warm_passes": info["passes_done"],
             "warm_converged_last_pass": info["converged"], "warm_max_resid_over_eps": float(np.max(res / eps)),
+            "warm_rel_change_at_exit": info["rel_change"],
             "warm_error_vs_true_sky": float(torch.linalg.vector_norm(xw - x_true) / torch.linalg.vector_norm(x_true)),
             "warm_vs_plain_image_rel_diff": float(torch.linalg.vector_norm(xw - x_plain.reshape(n, n))
                                                   / torch.linalg.vector_norm(x_plain))}
@@ -393,6 +394,7 @@ def main():
         tol = {"plain_seconds": round(time.perf_counter() - t0, 3), "plain_iters": info["iters_total"],
                "passes": info["passes_done"], "converged_last_pass": info["converged"],
                "max_resid_over_eps": float(np.max(res / eps)), "tol_rel": 1e-4,
+               "plain_rel_change_at_exit": info["rel_change"],
                "plain_error_vs_true_sky": float(torch.linalg.vector_norm(x - x_true) / torch.linalg.vector_norm(x_true)),
                "warm_seconds": None, "warm_iters": None}
         tol.update(warm_measure(sh, op, psi, y, eps, p2, n, dev, x, x_true))

@@ -273,7 +273,8 @@ sh_status sh_sdmm_destroy(sh_sdmm s);
  * two 3x3 zero-padded convolutions + ReLU (levels >= 2 after a 2x2 max-pool);
  * decoder level l = L-1..1: 2x2 stride-2 transposed convolution c_{l+1} -> c_l,
  * concat [upsampled, encoder level l], two 3x3 convolutions + ReLU; head = 1x1
- * convolution to one channel + ReLU.  Loss: mean squared error over pixels.
+ * convolution to one channel + ReLU.  Loss: mean squared error over pixels between the head's
+ * output before its ReLU and the target (the ReLU applies to predictions only).
  * Parameters are one flat float32 array: for each layer in the order enc1a,
  * enc1b, ..., encLb, up(L-1)t, up(L-1)a, up(L-1)b, ..., up1b, head, the weight
  * then the bias; conv weights [cout][cin][3][3], transposed-conv weights
@@ -294,8 +295,8 @@ sh_status sh_unet_set_params(sh_unet u, const float* host, int64_t n);
 sh_status sh_unet_get_params(sh_unet u, float* host, int64_t n);
 /* y = network(x), both device float32 B x H x W.  Async. */
 sh_status sh_unet_forward(sh_unet u, const float* x, int32_t B, int32_t H, int32_t W, float* y, void* stream);
-/* Loss mean((network(x) - target)^2) (host) and, if grads_host is not NULL, its gradient with
- * respect to every parameter (host, flat layout).  Synchronous. */
+/* Loss mean((z(x) - target)^2), z the head output before its ReLU (host), and, if grads_host is not
+ * NULL, its gradient with respect to every parameter (host, flat layout).  Synchronous. */
 sh_status sh_unet_loss_grad(sh_unet u, const float* x, const float* target, int32_t B, int32_t H, int32_t W,
                             double* loss_out, float* grads_host, void* stream);
 /* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the loss of the batch;

@@ -9,13 +9,14 @@ layers are plain definitions written out in NumPy, NCHW, float64:
           row-major order;
 * tconv   2x2 stride-2 transposed convolution: out[o, 2y+a, 2x+b] = bias[o] + sum_c W[c, o, a, b] x[c, y, x];
 * concat  channel concatenation [upsampled, skip];
-* head    1x1 convolution to one channel, then relu.
+* head    1x1 convolution to one channel; the prediction is relu of it.
 
 Architecture (levels L, base channels c, channels c_l = c 2^(l-1)): encoder level l has two conv3 +
 relu (level 1 from 1 input channel); levels 2..L start with a pool; level L is the bottleneck.
 Decoder level l = L-1..1: tconv c_{l+1} -> c_l, concat with encoder level l's output, two conv3 +
-relu (2 c_l -> c_l -> c_l).  Then the head.  Loss: mean squared error over all pixels.  Training:
-Adam with bias correction.
+relu (2 c_l -> c_l -> c_l).  Then the head.  Loss: mean squared error over all pixels between the head
+output before its relu and the target (the relu applies to predictions only, so the head cannot stop
+passing gradient).  Training: Adam with bias correction.
 
 BF16 emulation (emul=True) rounds, to the nearest bfloat16 with ties to even, exactly the values
 that enter a matrix product on the GPU: the network input, the weights (copies of the float64
@@ -189,14 +190,16 @@ class UNet:
         return np.maximum(z, 0.0), tape
 
     def loss_and_grads(self, params: dict, x, target):
-        """MSE loss over all pixels and its gradient with respect to every parameter."""
+        """Loss mean((z - target)^2) over all pixels, z the head output before its relu, and its
+        gradient with respect to every parameter."""
         r, L = self._r, self.levels
-        y, t = self.forward(params, x)
+        _, t = self.forward(params, x)
         W = t["W"]
-        cnt = y.size
-        loss = float(np.mean((y - target) ** 2))
+        z = t["head_z"]
+        cnt = z.size
+        loss = float(np.mean((z - target) ** 2))
         grads = {}
-        g = r(2.0 * (y - target) / cnt * (t["head_z"] > 0))
+        g = r(2.0 * (z - target) / cnt)
         ga, grads["head.w"], grads["head.b"] = head_grads(t["head_in"], W["head.w"], g)
         skip_g = {}
         for l in range(1, L):

@@ -181,10 +181,12 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   constexpr int PP = P * P;
   constexpr int NQ = (J * J + 63) / 64;   // taps per lane
   __shared__ float2 pat[4][PP];           // one patch copy per wave
-  // per wave, tap-major with a 65-entry pitch: phase A (consecutive lanes) and phase B (8 rows at
-  // stride 65) both stay free of LDS bank conflicts
-  __shared__ float2 aw[4][J][65];         // w1[t1] * scale * v of the wave's current 64 visibilities
-  __shared__ float bw[4][J + 1][65];      // w2[t2]; row J stays 0
+  // per wave, tap-major; row pitches of 66 complex / 68 real entries keep every row 16-byte aligned
+  // for the 128-bit reads of phase B (two visibilities of aw, four of bw per read) while the rows of
+  // different taps land in disjoint LDS banks; phase A (consecutive lanes) is conflict-free too
+  constexpr int AWP = 66, BWP = 68;
+  __shared__ __attribute__((aligned(16))) float2 aw[4][J][AWP];  // w1[t1] * scale * v, current 64 visibilities
+  __shared__ __attribute__((aligned(16))) float bw[4][J + 1][BWP];  // w2[t2]; row J stays 0
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   for (int e = tid; e < 4 * PP; e += 256) (&pat[0][0])[e] = make_float2(0.f, 0.f);
@@ -249,12 +251,22 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
       float2 av[NQ][8];
       float bv[NQ][8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int q = 0; q < NQ; ++q) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          av[q][u] = aw[wave][tr[q]][k + u];
-          bv[q][u] = bw[wave][tc[q]][k + u];
+        for (int u = 0; u < 8; u += 2) {
+          const float4 a2 = *(const float4*)&aw[wave][tr[q]][k + u];
+          av[q][u] = make_float2(a2.x, a2.y);
+          av[q][u + 1] = make_float2(a2.z, a2.w);
         }
+#pragma unroll
+        for (int u = 0; u < 8; u += 4) {
+          const float4 b4 = *(const float4*)&bw[wave][tc[q]][k + u];
+          bv[q][u] = b4.x;
+          bv[q][u + 1] = b4.y;
+          bv[q][u + 2] = b4.z;
+          bv[q][u + 3] = b4.w;
+        }
+      }
       const uint32_t group = uint32_t(starts >> k) & 0xffu;
       if (group == 0) {                     // no run starts here: straight-line accumulation
 #pragma unroll

@@ -4,7 +4,8 @@
 // Architecture (levels L, base channels c, c_l = c 2^(l-1)): encoder level l = two 3x3 convolutions
 // (zero padding) + ReLU, levels 2..L preceded by a 2x2 max-pool; decoder level l = L-1..1: 2x2
 // stride-2 transposed convolution c_{l+1} -> c_l, channel concat [upsampled, encoder output], two
-// 3x3 convolutions + ReLU; head = 1x1 convolution to one channel + ReLU.  Loss: mean squared error.
+// 3x3 convolutions + ReLU; head = 1x1 convolution to one channel + ReLU.  Loss: mean squared error
+// between the head's output before its ReLU and the target (the ReLU applies to predictions).
 //
 // Number formats: fp32 master weights, gradients and Adam moments; bfloat16 weights, activations
 // and incoming layer gradients as the operands of every matrix product; fp32 accumulation.
@@ -280,7 +281,8 @@ __global__ void relu_mask_grad(const float* __restrict__ g, int ldg, const float
   gm[t] = bf2f(act[t]) > 0.f ? f2bf(v) : (uint16_t)0;
 }
 
-// head: y = relu(z); per-work-group float64 partials of (y - t)^2; g = bf16(2 (y - t) / cnt * (z > 0))
+// head: y = relu(z) (the prediction); the loss compares z itself with the target, so the head's relu
+// never blocks the gradient: per-work-group float64 partials of (z - t)^2 and g = bf16(2 (z - t) / cnt)
 __global__ __launch_bounds__(256) void mse_loss(const float* __restrict__ z, const float* __restrict__ tgt, int64_t P,
                                                 float* __restrict__ y, uint16_t* __restrict__ g,
                                                 double* __restrict__ part) {
@@ -288,9 +290,9 @@ __global__ __launch_bounds__(256) void mse_loss(const float* __restrict__ z, con
   double acc = 0.0;
   const float inv = 2.0f / float(P);
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < P; i += (int64_t)gridDim.x * 256) {
-    const float zv = z[i], yv = fmaxf(zv, 0.f), d = yv - tgt[i];
-    if (y) y[i] = yv;
-    if (g) g[i] = zv > 0.f ? f2bf(d * inv) : (uint16_t)0;
+    const float zv = z[i], d = zv - tgt[i];
+    if (y) y[i] = fmaxf(zv, 0.f);
+    if (g) g[i] = f2bf(d * inv);
     acc += double(d) * double(d);
   }
   sh[threadIdx.x] = acc;

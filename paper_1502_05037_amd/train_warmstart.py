@@ -1,15 +1,16 @@
 """Train the warm-start U-Net on pairs (normalised dirty image, plain SARA solution).
 
-Each training problem is a 256 x 256 synthetic sky (Gaussian blobs + 20 point sources) observed at
-M = 655 360 Gaussian-density uv points split into R = 8 uneven blocks, at 30 dB input SNR; the
-plain solver (5 passes of at most 300 iterations, tolerance 1e-4) gives the target.  Problems are
+Training problems are 256 x 256 (R = 8 uneven blocks, 30 dB input SNR) of two kinds: the 256^2
+configuration (Gaussian blobs + 20 point sources, M = 655 360 Gaussian-density uv points) and 256^2
+windows of the 1024^2 configuration's skies under its radial coverage and visibility density (see
+KINDS); the plain solver (5 passes of at most 300 iterations, tolerance 1e-4) gives the target.  Problems are
 generated and solved 32 at a time through one batched plan.  The network input and target are the
 dirty image and the solution, both divided by the dirty image's RMS in PSF-peak units.
 Training: Adam, batch 8, mean squared error.  The weights and a JSON record of the run are written
 next to each other.
 
-Usage: python -m paper_1502_05037_amd.train_warmstart --pairs 448 --epochs 400 --train-seconds 200 \
-           --out paper_1502_05037_amd/weights/unet_b32_l4.npy
+Usage: python -m paper_1502_05037_amd.train_warmstart --pairs 256 --pairs-c3 256 --epochs 400 \
+           --train-seconds 240 --out paper_1502_05037_amd/weights/unet_b32_l4.npy
 """
 from __future__ import annotations
 
@@ -32,21 +33,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_problems(first: int, P: int, n=256, m=655_360, R=8, snr=30.0, cfg=TRAIN_CFG):
+# Two kinds of training problem, both 256 x 256:
+#  "c2": the 256^2 configuration itself (blobs + 20 point sources, dynamic range 1e3, Gaussian-density
+#        coverage, M = 655 360, J = 6);
+#  "c3": a 256 x 256 window of a 1024^2 sky from the 1024^2 configuration (blobs sized for 1024^2,
+#        200 point sources, dynamic range 1e4) under radial-density coverage with that configuration's
+#        visibilities per pixel (2e7 / 1024^2, so M = 1 250 000) and J = 8.  Coverage in radians per pixel
+#        gives the same PSF in pixels at both sizes, so these windows show the network what the 1024^2
+#        problem looks like locally.
+KINDS = {"c2": dict(cfg=TRAIN_CFG, m=655_360, J=6), "c3": dict(cfg=TRAIN_CFG + 1, m=1_250_000, J=8)}
+
+
+def make_problems(first: int, P: int, kind: str = "c2", n=256, R=8, snr=30.0):
+    cfg, m = KINDS[kind]["cfg"], KINDS[kind]["m"]
     uvs, offs, xs, draws, sizes = [], [0], [], [], []
     base = 0
     for k in range(P):
         prob = first + k
-        uv = synth.sort_by_radius(synth.uv_gaussian(m, synth.rng(cfg, prob, synth.UV)))
+        g_uv = synth.rng(cfg, prob, synth.UV)
+        uv = synth.uv_gaussian(m, g_uv) if kind == "c2" else synth.uv_radial(m, g_uv)
+        uv = synth.sort_by_radius(uv)
         sz = synth.block_sizes(m, R, synth.rng(cfg, prob, synth.BLOCKS))
         uvs.append(uv)
         sizes.append(sz)
         offs.extend((base + synth.offsets(sz)[1:]).tolist())
         base += m
-        xs.append(synth.sky(n, 20, 3.0, synth.rng(cfg, prob, synth.SKY)).astype(np.float32))
+        g_sky = synth.rng(cfg, prob, synth.SKY)
+        if kind == "c2":
+            x = synth.sky(n, 20, 3.0, g_sky)
+        else:
+            big = synth.sky(1024, 200, 4.0, g_sky)
+            r0, c0 = g_sky.integers(0, 1024 - n + 1, size=2)
+            x = big[r0:r0 + n, c0:c0 + n]
+            x = x / max(float(x.max()), 1e-12)
+        xs.append(x.astype(np.float32))
         draws.append(synth.complex_normal(m, synth.rng(cfg, prob, synth.NOISE)).astype(np.complex64))
-    return dict(P=P, n=n, m=m, R=R, snr=snr, uv=np.concatenate(uvs), off=np.array(offs, dtype=np.int64),
-                x_true=np.stack(xs), draws=np.concatenate(draws), sizes=sizes)
+    return dict(P=P, n=n, m=m, R=R, snr=snr, J=KINDS[kind]["J"], kind=kind, uv=np.concatenate(uvs),
+                off=np.array(offs, dtype=np.int64), x_true=np.stack(xs), draws=np.concatenate(draws), sizes=sizes)
 
 
 def observe(op, pr, dev):
@@ -73,11 +96,11 @@ def solve_params(passes=5, max_iter=300, tol=1e-4):
     return p
 
 
-def make_pairs(first: int, P: int, dev, J=6):
+def make_pairs(first: int, P: int, dev, kind: str = "c2"):
     """Solve P problems together; returns (inputs, targets) on the device, both P x n x n."""
     import torch
-    pr = make_problems(first, P)
-    n, m, R = pr["n"], pr["m"], pr["R"]
+    pr = make_problems(first, P, kind)
+    n, m, R, J = pr["n"], pr["m"], pr["R"], pr["J"]
     op = sh.op_create_batched(pr["uv"], [m] * P, n, 2, J, pr["off"], [R] * P)
     psi = sh.psi_create_batched(n, 4, sh.SARA_MASK, P)
     try:
@@ -129,7 +152,8 @@ def train(ws_u, inputs, targets, epochs: int, lr: float, batch: int, seed: int, 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--pairs", type=int, default=384)
+    ap.add_argument("--pairs", type=int, default=256, help="pairs of the 256^2 configuration")
+    ap.add_argument("--pairs-c3", type=int, default=256, help="pairs of 256^2 windows of the 1024^2 configuration")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--batch", type=int, default=8)
@@ -144,14 +168,20 @@ def main():
     P = 32
     ins, outs, solve_log = [], [], []
     t0 = time.time()
-    for first in range(0, a.pairs, P):
-        d, x, infos = make_pairs(first, min(P, a.pairs - first), dev)
-        ins.append(d)
-        outs.append(x)
-        solve_log.append({"first": first, "iters_total": infos[0]["iters_total"],
-                          "converged": int(sum(i["converged"] for i in infos))})
-        log(f"[train] pairs {first}..{first + d.shape[0] - 1} solved ({time.time() - t0:.0f} s): {solve_log[-1]}")
+    for kind, count in (("c2", a.pairs), ("c3", a.pairs_c3)):
+        for first in range(0, count, P):
+            d, x, infos = make_pairs(first, min(P, count - first), dev, kind)
+            ins.append(d)
+            outs.append(x)
+            solve_log.append({"kind": kind, "first": first, "iters_total": infos[0]["iters_total"],
+                              "converged": int(sum(i["converged"] for i in infos))})
+            log(f"[train] {kind} pairs {first}..{first + d.shape[0] - 1} solved ({time.time() - t0:.0f} s): "
+                f"{solve_log[-1]}")
     inputs, targets = torch.cat(ins), torch.cat(outs)
+    # validation pairs: the last 10 %, drawn from both kinds
+    perm = torch.as_tensor(np.random.Generator(np.random.PCG64(np.random.SeedSequence([1502, 5037, 11]))).permutation(
+        inputs.shape[0]), device=dev)
+    inputs, targets = inputs.index_select(0, perm).contiguous(), targets.index_select(0, perm).contiguous()
     gen_s = time.time() - t0
     u = sh.unet_create(a.base, a.levels)
     try:
@@ -162,9 +192,12 @@ def main():
         sh.unet_destroy(u)
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     np.save(a.out, w.astype(np.float32), allow_pickle=False)
-    meta = {"base": a.base, "levels": a.levels, "pairs": a.pairs, "val_pairs": max(1, round(0.1 * a.pairs)),
-            "train_problems": f"synth config {TRAIN_CFG}, problems 0..{a.pairs - 1}", "n": 256, "M": 655360,
-            "R": 8, "J": 6, "snr_db": 30, "solver": "5 passes x <= 300 iterations, tol_rel 1e-4",
+    total = a.pairs + a.pairs_c3
+    meta = {"base": a.base, "levels": a.levels, "pairs": total, "val_pairs": max(1, round(0.1 * total)),
+            "train_problems": {"c2": f"synth config {TRAIN_CFG}, problems 0..{a.pairs - 1}, M 655360, J 6, Gaussian uv",
+                               "c3": f"synth config {TRAIN_CFG + 1}, problems 0..{a.pairs_c3 - 1}, 256^2 windows of "
+                                     "1024^2 skies, M 1250000, J 8, radial uv"},
+            "n": 256, "R": 8, "snr_db": 30, "solver": "5 passes x <= 300 iterations, tol_rel 1e-4",
             "lr": a.lr, "batch": a.batch, "epochs_run": len(hist), "steps": steps, "init_seed": a.seed,
             "generation_seconds": round(gen_s, 1), "history": hist, "solves": solve_log,
             "command": "python -m paper_1502_05037_amd.train_warmstart " + " ".join(sys.argv[1:])}

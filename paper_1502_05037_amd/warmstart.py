@@ -39,9 +39,8 @@ def layer_list(base: int, levels: int):
 
 def he_init(base: int, levels: int, seed: int) -> np.ndarray:
     """Gaussian weights with variance 2 / fan-in and zero biases in the flat layout, except the head:
-    weights at a tenth of that scale and bias 0.05, so that the head's ReLU starts open with a small
-    output (a head that starts large is driven below zero everywhere by the first steps and stays
-    there)."""
+    weights at a tenth of that scale and bias 0.05, so that the first predictions are small and
+    positive, like the targets."""
     g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([1502, 5037, 9, seed])))
     flat = []
     for kind, cin, cout in layer_list(base, levels):

@@ -89,6 +89,9 @@ def test_gradients_match_central_differences():
     params, x, t = _tiny()
     net = unet.UNet(2, 4, emul=False)
     loss, grads = net.loss_and_grads(params, x, t)
+    y, tape = net.forward(params, x)
+    assert loss == pytest.approx(float(np.mean((tape["head_z"] - t) ** 2)), rel=1e-15)
+    np.testing.assert_array_equal(y, np.maximum(tape["head_z"], 0.0))
     g = np.random.default_rng(4)
     h = 1e-6
     for name, shape in unet.param_shapes(2, 4):
@@ -102,8 +105,8 @@ def test_gradients_match_central_differences():
             a[k] += h
             b[k] -= h
             p1[name], p2[name] = a.reshape(shape), b.reshape(shape)
-            l1 = float(np.mean((net.forward(p1, x)[0] - t) ** 2))
-            l2 = float(np.mean((net.forward(p2, x)[0] - t) ** 2))
+            l1 = float(np.mean((net.forward(p1, x)[1]["head_z"] - t) ** 2))
+            l2 = float(np.mean((net.forward(p2, x)[1]["head_z"] - t) ** 2))
             fd.append((l1 - l2) / (2 * h))
             an.append(grads[name].ravel()[k])
         fd, an = np.array(fd), np.array(an)
