@@ -193,7 +193,7 @@ sh_status sh_std(int64_t D, const float* c, double* std_out, void* stream);
  * ------------------------------------------------------------------------- */
 
 typedef struct {
-  double gamma;        /* l1 prox step; <= 0: 1e-3 * max|Psi^dagger Phi^dagger y| / nu^2 */
+  double gamma;        /* l1 prox step; <= 0: 1e-4 * max|Psi^dagger Phi^dagger y| / nu^2 */
   double nu;           /* operator norm used to normalise; <= 0: sh_op_norm from x0 = ones */
   double tol_rel;      /* stop when ||x_n - x_{n-1}||/||x_n|| <= tol_rel and all blocks feasible;
                           0 = run max_iter every pass (fixed schedule) */

@@ -20,7 +20,7 @@ the solution set of (3) unchanged and puts the spectrum of Q in [2, 3].
 Readings where the paper is silent (each also listed in the design notes):
 * Q^{-1} by conjugate gradients warm-started at the previous x, either to a
   relative residual of 1e-12 or for a fixed number of steps.
-* gamma = 1e-3 ||Psi^dagger Phi_hat^dagger y_hat||_inf unless given.
+* gamma = 1e-4 ||Psi^dagger Phi_hat^dagger y_hat||_inf unless given.
 * stop when ||x_n - x_{n-1}|| / ||x_n|| <= tol_rel and every block satisfies
   ||y_i - Phi_i x_n|| <= eps_i (1 + eps_slack), or after max_iter iterations;
   tol_rel = 0 runs the fixed schedule.
@@ -127,9 +127,11 @@ class Problem:
         return [(int(o[i]), int(o[i + 1])) for i in range(len(o) - 1)]
 
 
-def default_gamma(op, psi, y, nu) -> float:
-    """gamma = 1e-3 max |Psi^dagger Phi_hat^dagger y_hat| = 1e-3 max |Psi^dagger Phi^dagger y| / nu^2."""
-    return 1e-3 * float(np.max(np.abs(psi.adj(op.adj(np.asarray(y, dtype=np.complex128)))))) / nu ** 2
+def default_gamma(op, psi, y, nu, factor: float = 1e-4) -> float:
+    """gamma = factor max |Psi^dagger Phi_hat^dagger y_hat| = factor max |Psi^dagger Phi^dagger y| / nu^2.
+
+    The minimiser does not depend on gamma, only the path to it does."""
+    return factor * float(np.max(np.abs(psi.adj(op.adj(np.asarray(y, dtype=np.complex128)))))) / nu ** 2
 
 
 def init_state(pb: Problem, x0=None) -> State:

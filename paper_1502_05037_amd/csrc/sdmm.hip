@@ -283,7 +283,8 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   s->eh.resize(R);
   for (int i = 0; i < R; ++i) s->eh[i] = eps[i] / s->nu[op->block_prob[i]];
   SH_HIP(hipMemcpyAsync(w.eps_hat.ptr, s->eh.data(), R * sizeof(double), hipMemcpyHostToDevice, st));
-  // gamma = 1e-3 max |Psi^dagger Phi^dagger y| / nu^2 per problem unless given
+  // gamma = 1e-4 max |Psi^dagger Phi^dagger y| / nu^2 per problem unless given (the minimiser does not
+  // depend on gamma; this step meets the stopping test within a few hundred iterations per pass)
   s->gamma.assign(P, s->prm.gamma);
   if (!(s->prm.gamma > 0)) {
     SH_TRY(sh::phi_adjoint(op, (const float2*)y, w.t1.ptr, true, nullptr, st));
@@ -292,7 +293,7 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     std::vector<double> mx(P);
     SH_HIP(hipMemcpyAsync(mx.data(), s_misc + MISC_TMP * P, P * sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));
-    for (int p = 0; p < P; ++p) s->gamma[p] = 1e-3 * mx[p] / (s->nu[p] * s->nu[p]);
+    for (int p = 0; p < P; ++p) s->gamma[p] = 1e-4 * mx[p] / (s->nu[p] * s->nu[p]);
   }
   std::vector<float> gf(P);
   for (int p = 0; p < P; ++p) {

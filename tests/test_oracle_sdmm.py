@@ -150,7 +150,9 @@ def _brute_force_slsqp(op, psi, y, off, eps, W):
 def _check_against_brute_force(R, levels, mask, m, solver=None):
     op, psi, y, off, eps = _tiny_problem(R=R, m=m, levels=levels, mask=mask)
     nu = measurement.op_norm(op, np.ones((psi.n, psi.n)), max_iter=5000, tol=0.0)
-    gamma = sdmm.default_gamma(op, psi, y, nu)
+    # the minimiser does not depend on gamma; the larger step reaches it within the iteration budget
+    # on these tiny problems
+    gamma = sdmm.default_gamma(op, psi, y, nu, factor=1e-3)
     W = np.ones((psi.q, psi.n, psi.n))
     p = sdmm.Params(gamma=gamma, nu=nu, max_iter=20000, tol_rel=1e-11, eps_slack=1e-9)
     x, _, infos, st = sdmm.sara(op, psi, y, off, eps, p)
@@ -180,7 +182,7 @@ def test_sdmm_matches_brute_force(R):
 def test_kkt_residuals_vanish_at_convergence():
     op, psi, y, off, eps = _tiny_problem(R=2, seed=4)
     nu = measurement.op_norm(op, np.ones((psi.n, psi.n)), max_iter=5000, tol=0.0)
-    gamma = sdmm.default_gamma(op, psi, y, nu)
+    gamma = sdmm.default_gamma(op, psi, y, nu, factor=1e-3)
     pb = sdmm.Problem(op, psi, y, off, eps, nu)
     st = sdmm.init_state(pb)
     p = sdmm.Params(gamma=gamma, nu=nu, max_iter=3000, tol_rel=0.0)
