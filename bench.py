@@ -398,7 +398,26 @@ def main():
                "plain_error_vs_true_sky": float(torch.linalg.vector_norm(x - x_true) / torch.linalg.vector_norm(x_true)),
                "warm_seconds": None, "warm_iters": None}
         tol.update(warm_measure(sh, op, psi, y, eps, p2, n, dev, x, x_true))
+        worst = int(np.argmax(res / eps))
+        tol["worst_block"] = worst
+        tol["max_abs_y_over_sigma_in_worst_block"] = float(
+            torch.abs(y[int(wl["off"][worst]):int(wl["off"][worst + 1])]).max() / sigma)
         log(f"[bench] time-to-tol {tol}")
+        # The feasibility slack of 1e-4 lies below what float32 visibilities resolve in the innermost uv
+        # blocks (|y| reaches ~1e4 sigma there), so the same comparison is repeated with a 1e-3 slack.
+        p3 = sh.sdmm_default_params()
+        p3.nu, p3.tol_rel, p3.passes, p3.max_iter, p3.check_every, p3.eps_slack = nu, 1e-4, 5, 300, 10, 1e-3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info3, res3 = sh.sdmm_solve(op, psi, y, eps, None, None, p3, x)
+        torch.cuda.synchronize()
+        loose = {"eps_slack": 1e-3, "plain_seconds": round(time.perf_counter() - t0, 3),
+                 "plain_iters": info3["iters_total"], "plain_converged_last_pass": info3["converged"],
+                 "plain_max_resid_over_eps": float(np.max(res3 / eps)),
+                 "plain_error_vs_true_sky": float(torch.linalg.vector_norm(x - x_true) / torch.linalg.vector_norm(x_true))}
+        loose.update(warm_measure(sh, op, psi, y, eps, p3, n, dev, x, x_true))
+        tol["slack_1e-3"] = loose
+        log(f"[bench] time-to-tol with a 1e-3 feasibility slack {loose}")
 
     if a.copy_mb:
         src = torch.ones(a.copy_mb << 18, dtype=torch.float32, device=dev)

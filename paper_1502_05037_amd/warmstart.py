@@ -92,10 +92,10 @@ class WarmStart:
         return x0
 
 
-def warm_solve(ws: WarmStart, op, psi, y, eps, params, n: int, dev, x_out):
-    """SDMM from the network's x0, with the first weights taken from x0 by the reweighting rule
-    (one pass fewer than params.passes).  Returns (info, block residuals, seconds including the
-    network)."""
+def warm_solve(ws: WarmStart, op, psi, y, eps, params, n: int, dev, x_out, replace_first_pass: bool = True):
+    """SDMM from the network's x0.  With replace_first_pass the first weights come from x0 by the
+    reweighting rule and the solve runs one pass fewer than params.passes; otherwise x0 only starts
+    the first (unweighted) pass.  Returns (info, block residuals, seconds including the network)."""
     import torch
     P = sh.op_query(op)["P"]
     torch.cuda.synchronize()
@@ -104,8 +104,9 @@ def warm_solve(ws: WarmStart, op, psi, y, eps, params, n: int, dev, x_out):
     prm = sh.SdmmParams()
     for f, _ in sh.SdmmParams._fields_:
         setattr(prm, f, getattr(params, f))
-    prm.passes = max(1, params.passes - 1)
-    prm.w_from_x0 = 1
+    if replace_first_pass:
+        prm.passes = max(1, params.passes - 1)
+        prm.w_from_x0 = 1
     info, resid = sh.sdmm_solve(op, psi, y, eps, None, x0, prm, x_out)
     torch.cuda.synchronize()
     return info, resid, time.perf_counter() - t0
