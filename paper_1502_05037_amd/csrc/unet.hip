@@ -12,9 +12,11 @@
 //
 // Every convolution is a matrix product on the MFMA units: activations are NHWC (channels
 // contiguous), a 3x3 convolution is im2col (K = 9 Cin, ordered (ky, kx, ci), zero-padded to a
-// multiple of 16) times the weight matrix, and all products use one kernel of the "NT" form
+// multiple of 16; gathered inside the product's staging, never stored, except where the weight
+// gradient needs it transposed) times the weight matrix, and all products use one kernel of the "NT" form
 // C[m][n] = sum_k A[m][k] B[n][k] with both operands contiguous along k (v_mfma_f32_16x16x16_bf16,
-// 64 x 64 tiles per work-group of four waves, k staged through LDS 32 at a time, optional split-K
+// 64 x 64 tiles per work-group of four waves, k staged through LDS 64 at a time with the next slab
+// prefetched into registers, optional split-K
 // with a fixed-order reduction).  Weight gradients contract over pixels, so their operands are
 // transposed first (pixels padded to a multiple of 16); a row of ones appended to the second
 // operand yields the bias gradient in the same product.  Results are deterministic.
@@ -44,14 +46,26 @@ inline int64_t rup(int64_t v, int64_t m) { return sh::cdiv(v, m) * m; }
 // GEMM: C[m][n] = sum_{k in split z} A[m*lda + k] B[n*ldb + k] (+ bias[n]) (relu), bf16 operands.
 // K is a multiple of 16.  Outputs: fp32 C (+ z*M*ldc for split partials) and/or bf16 Cb.
 // ---------------------------------------------------------------------------------------------
-constexpr int GBM = 64, GBN = 64, GBK = 32, GLD = GBK + 8;
+constexpr int GBM = 64, GBN = 64, GBK = 64, GLD = GBK + 8;
 
+// The next k-slab is loaded from global memory into registers while the MFMAs work on the current one
+// from LDS (one LDS buffer, two barriers per slab).  Staging: thread t loads row t/4 of the A and B
+// tiles, k-values 16 (t % 4) .. 16 (t % 4) + 15 (two 128-bit loads per operand).
+// Implicit 3x3 im2col of an NHWC bf16 image as the A operand: row m = pixel (b, y, x) of a B x H x W
+// batch, column k = (ky*3 + kx)*C + c < 9C takes the pixel (y+ky-1, x+kx-1), channel c (zero outside
+// the image and for k >= 9C).  x has row stride ldx.
+struct Im2col {
+  const uint16_t* x;
+  int ldx, H, W, C;
+};
+
+template <bool GATHER>
 __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, int lda, const uint16_t* __restrict__ B,
                                                int ldb, int M, int N, int K, int kchunk,
                                                const float* __restrict__ bias, int relu, float* __restrict__ C,
-                                               int ldc, uint16_t* __restrict__ Cb, int ldcb) {
-  __shared__ uint16_t As[GBM][GLD];
-  __shared__ uint16_t Bs[GBN][GLD];
+                                               int ldc, uint16_t* __restrict__ Cb, int ldcb, Im2col g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GLD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
@@ -61,17 +75,59 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 2, lc = (tid & 3) * 8;   // staging: row lr, 8 k-values from lc
+  const int lr = tid >> 2, lc = (tid & 3) * 16;   // tile row lr (0..63), k-values lc .. lc + 15
+  uint4 ra[2], rb[2];
+  // gather mode: the pixel of this thread's A row
+  int gb = 0, gy = 0, gx = 0;
+  if constexpr (GATHER) {
+    const int m = m0 + lr;
+    gb = m / (g.H * g.W);
+    const int rem = m - gb * g.H * g.W;
+    gy = rem / g.W;
+    gx = rem - gy * g.W;
+  }
+  auto gather8 = [&](int k) -> uint4 {   // A[m0 + lr][k .. k+7] of the implicit im2col
+    if ((g.C & 7) == 0) {
+      if (k >= 9 * g.C) return make_uint4(0, 0, 0, 0);
+      const int tap = k / g.C, c = k - tap * g.C;
+      const int sy = gy + tap / 3 - 1, sx = gx + tap % 3 - 1;
+      if (sy < 0 || sy >= g.H || sx < 0 || sx >= g.W) return make_uint4(0, 0, 0, 0);
+      return *(const uint4*)(g.x + ((int64_t)(gb * g.H + sy) * g.W + sx) * g.ldx + c);
+    }
+    uint16_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kq = k + q;
+      v[q] = 0;
+      if (kq < 9 * g.C) {
+        const int tap = kq / g.C, c = kq - tap * g.C;
+        const int sy = gy + tap / 3 - 1, sx = gx + tap % 3 - 1;
+        if (sy >= 0 && sy < g.H && sx >= 0 && sx < g.W) v[q] = g.x[((int64_t)(gb * g.H + sy) * g.W + sx) * g.ldx + c];
+      }
+    }
+    return make_uint4(v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
+                      v[6] | (uint32_t(v[7]) << 16));
+  };
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = k0 + lc + 8 * e;
+      if constexpr (GATHER)
+        ra[e] = (m0 + lr < M && k < ke) ? gather8(k) : make_uint4(0, 0, 0, 0);
+      else
+        ra[e] = (m0 + lr < M && k < ke) ? *(const uint4*)(A + (int64_t)(m0 + lr) * lda + k) : make_uint4(0, 0, 0, 0);
+      rb[e] = (n0 + lr < N && k < ke) ? *(const uint4*)(B + (int64_t)(n0 + lr) * ldb + k) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  if (kb < ke) load(kb);
   for (int k0 = kb; k0 < ke; k0 += GBK) {
-    {
-      const int k = k0 + lc;
-      uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
-      if (m0 + lr < M && k < ke) va = *(const uint4*)(A + (int64_t)(m0 + lr) * lda + k);
-      if (n0 + lr < N && k < ke) vb = *(const uint4*)(B + (int64_t)(n0 + lr) * ldb + k);
-      *(uint4*)&As[lr][lc] = va;
-      *(uint4*)&Bs[lr][lc] = vb;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      *(uint4*)&As[lr][lc + 8 * e] = ra[e];
+      *(uint4*)&Bs[lr][lc + 8 * e] = rb[e];
     }
     __syncthreads();
+    if (k0 + GBK < ke) load(k0 + GBK);   // in flight during the products below
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 16) {
       const int ko = kk + 4 * (lane >> 4);
@@ -528,7 +584,7 @@ sh_status ensure_acts(sh_unet u, int B, int H, int W) {
 // weight gradients, reduced in fixed order through `part`.
 sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M, int N, int64_t K,
                const float* bias, bool relu, float* C, int ldc, uint16_t* Cb, int ldcb, bool allow_split,
-               hipStream_t st) {
+               hipStream_t st, const Im2col* gat = nullptr) {
   SH_REQUIRE(K % 16 == 0 && K > 0, "internal: GEMM K = %lld not a multiple of 16", (long long)K);
   SH_REQUIRE(M < (int64_t(1) << 31) / GBM, "internal: GEMM M too large");
   const unsigned gx = (unsigned)sh::cdiv(N, GBN), gy = (unsigned)sh::cdiv(M, GBM);
@@ -540,13 +596,19 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
   }
   const int64_t kchunk = rup(sh::cdiv(K, S), GBK);
   S = (int)sh::cdiv(K, kchunk);
-  if (S == 1) {
-    hipLaunchKernelGGL(gemm_nt, dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K, (int)kchunk, bias,
-                       relu ? 1 : 0, C, ldc, Cb, ldcb);
+  const Im2col g0{nullptr, 0, 1, 1, 1};
+  if (gat) {
+    SH_REQUIRE(S == 1 && M == (int64_t)u->ap->B * gat->H * gat->W && K == rup(9 * gat->C, 16),
+               "internal: implicit im2col shape");
+    hipLaunchKernelGGL(gemm_nt<true>, dim3(gx, gy, 1), dim3(256), 0, st, nullptr, 0, B, ldb, (int)M, N, (int)K,
+                       (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat);
+  } else if (S == 1) {
+    hipLaunchKernelGGL(gemm_nt<false>, dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
+                       (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0);
   } else {
     SH_REQUIRE(C && !Cb && !bias && !relu && ldc == N, "internal: split GEMM writes plain fp32");
-    hipLaunchKernelGGL(gemm_nt, dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K, (int)kchunk,
-                       nullptr, 0, u->ap->part.ptr, N, nullptr, 0);
+    hipLaunchKernelGGL(gemm_nt<false>, dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
+                       (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0);
     hipLaunchKernelGGL(sum_splits, dim3(nb(M * N)), dim3(256), 0, st, u->ap->part.ptr, S, M * N, C);
   }
   SH_LAUNCHED();
@@ -576,10 +638,9 @@ sh_status prep_weights(sh_unet u, hipStream_t st) {
 sh_status conv_fwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, int B, int H, int W, uint16_t* out,
                    hipStream_t st) {
   const int64_t P = (int64_t)B * H * W;
-  hipLaunchKernelGGL(im2col3, dim3(nb(P * (ly.Kp / 8))), dim3(256), 0, st, in, ldin, B, H, W, ly.cin, ly.Kp,
-                     u->ap->col.ptr);
-  return gemm(u, u->ap->col.ptr, ly.Kp, u->ops.ptr + ly.op_f, ly.Kp, P, ly.cout, ly.Kp, u->params.ptr + ly.b_off, true,
-              nullptr, 0, out, ly.cout, false, st);
+  const Im2col g{in, ldin, H, W, ly.cin};
+  return gemm(u, nullptr, 0, u->ops.ptr + ly.op_f, ly.Kp, P, ly.cout, ly.Kp, u->params.ptr + ly.b_off, true, nullptr, 0,
+              out, ly.cout, false, st, &g);
 }
 
 // conv3 backward.  gin (+ gin2, strided) is the fp32 gradient at the layer's post-ReLU output `out`.
@@ -603,11 +664,10 @@ sh_status conv_bwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, con
                      u->grads.ptr + ly.w_off, u->grads.ptr + ly.b_off);
   SH_LAUNCHED();
   if (!dx) return SH_OK;
-  // input gradient: im2col(gm) . wd^T
-  hipLaunchKernelGGL(im2col3, dim3(nb(P * (ly.Kpd / 8))), dim3(256), 0, st, a.gm.ptr, ly.cout, B, H, W, ly.cout, ly.Kpd,
-                     a.col.ptr);
-  return gemm(u, a.col.ptr, ly.Kpd, u->ops.ptr + ly.op_d, ly.Kpd, P, ly.cin, ly.Kpd, nullptr, false, dx, ly.cin,
-              nullptr, 0, false, st);
+  // input gradient: im2col(gm) . wd^T, im2col implicit
+  const Im2col g{a.gm.ptr, ly.cout, H, W, ly.cout};
+  return gemm(u, nullptr, 0, u->ops.ptr + ly.op_d, ly.Kpd, P, ly.cin, ly.Kpd, nullptr, false, dx, ly.cin, nullptr, 0,
+              false, st, &g);
 }
 
 // Forward pass over B images of H x W (input x fp32 device), keeping every activation.
