@@ -132,3 +132,15 @@ def test_adam_first_step_closed_form():
     # second step with the same gradient: m_hat = g, v_hat = g^2 again
     out2 = opt.step(out, gr)
     np.testing.assert_allclose(out2["w"], out["w"] - 1e-3 * gr["w"] / (np.abs(gr["w"]) + 1e-8), rtol=1e-10)
+
+
+def test_warm_start_layer_layout_matches_oracle():
+    """The flat parameter layout the warm-start module initialises (and the library reads) is the
+    oracle's: same layers, kinds and channel counts in the same order."""
+    from paper_1502_05037_amd import warmstart
+    for base, levels in ((16, 1), (16, 3), (32, 4)):
+        ours = warmstart.layer_list(base, levels)
+        ref = [(kind, cin, cout) for _, kind, cin, cout in unet.layer_specs(base, levels)]
+        assert ours == ref
+        n = sum(int(np.prod(s)) for _, s in unet.param_shapes(base, levels))
+        assert warmstart.he_init(base, levels, 0).size == n
