@@ -394,7 +394,7 @@ def main():
         tol = {"plain_seconds": round(time.perf_counter() - t0, 3), "plain_iters": info["iters_total"],
                "passes": info["passes_done"], "converged_last_pass": info["converged"],
                "max_resid_over_eps": float(np.max(res / eps)), "tol_rel": 1e-4,
-               "plain_rel_change_at_exit": info["rel_change"],
+               "plain_rel_change_at_exit": info["rel_change"], "cg_iters": p2.cg_iters,
                "plain_error_vs_true_sky": float(torch.linalg.vector_norm(x - x_true) / torch.linalg.vector_norm(x_true)),
                "warm_seconds": None, "warm_iters": None}
         tol.update(warm_measure(sh, op, psi, y, eps, p2, n, dev, x, x_true))

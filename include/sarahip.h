@@ -212,7 +212,7 @@ typedef struct {
 } sh_sdmm_params;
 
 /* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
- * max_iter 300, cg_iters 8, passes 1, check_every 10, graph 1, w_from_x0 0.  With a batched plan, a given
+ * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0.  With a batched plan, a given
  * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 

@@ -174,7 +174,7 @@ void sh_sdmm_default_params(sh_sdmm_params* p) {
   p->rw_beta = 0.5;
   p->rw_delta0 = 0.0;
   p->max_iter = 300;
-  p->cg_iters = 8;
+  p->cg_iters = 2;   // warm-started at x_{n-1}: two steps give the iterates of eight (see the design notes)
   p->passes = 1;
   p->check_every = 10;
   p->graph = 1;

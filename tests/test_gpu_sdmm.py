@@ -167,3 +167,16 @@ def test_session_split_equals_single_run(sh):
         sh.op_destroy(op)
     np.testing.assert_array_equal(x2.cpu().numpy(), x1.cpu().numpy())
     np.testing.assert_array_equal(r2, r1)
+
+
+def test_default_two_cg_steps_parity(sh):
+    """The library's default x-update (two warm-started CG steps) against the oracle run with the same
+    two steps, over three reweighted passes."""
+    pb = helpers.build(7, 64, 3000, 3, 6, coverage="radial", prob=5)
+    psi, nu, gamma = _oracle_setup(pb)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=80, cg_iters=2, passes=3)
+    x_ref, *_ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
+    prm = _params(sh, gamma=gamma, nu=nu, max_iter=80, passes=3)
+    assert prm.cg_iters == 2
+    x, info, _, _ = _gpu_solve(sh, pb, prm)
+    assert helpers.rel(x, x_ref) <= 1e-4
