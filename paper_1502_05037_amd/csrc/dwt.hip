@@ -146,14 +146,15 @@ __global__ __launch_bounds__(256) void dwt_synthesis(const float* __restrict__ l
       sb[3][r][c] = plane[(int64_t)(H + kr) * n + H + kc];
     }
     __syncthreads();
-    // columns: y[i][c] = sum_t [i - t even] (h[t] top[k][c] + g[t] bottom[k][c]), k = ((i - t) mod L) / 2
+    // columns: y[i][c] = sum_t [i - t even] (h[t] top[k][c] + g[t] bottom[k][c]), k = ((i - t) mod L) / 2.
+    // Window row r holds subband row (kr0 + r) mod H, so k is window row (i - t)/2 + Lf/2 - 1 (local
+    // i; i0 is even), which lies in [0, kw) for every tap: no modulo in the loop.
     for (int e = tid; e < te * kw; e += 256) {
       const int i = e / kw, c = e - i * kw;
       const int gi = i0 + i;
       float lo = 0.f, hi = 0.f;
       for (int t = (gi & 1); t < Lf; t += 2) {
-        const int k = ((gi - t) % L + L) % L / 2;        // subband row
-        const int r = ((k - kr0) % H + H) % H;           // window row
+        const int r = ((i - t) >> 1) + Lf / 2 - 1;       // window row of subband row ((gi - t) mod L) / 2
         lo = fmaf(pl.h[d][t], sb[0][r][c], lo);
         lo = fmaf(pl.g[d][t], sb[2][r][c], lo);
         hi = fmaf(pl.h[d][t], sb[1][r][c], hi);
@@ -171,8 +172,7 @@ __global__ __launch_bounds__(256) void dwt_synthesis(const float* __restrict__ l
       const int gj = j0 + j;
       float v = 0.f;
       for (int t = (gj & 1); t < Lf; t += 2) {
-        const int k = ((gj - t) % L + L) % L / 2;
-        const int c = ((k - kc0) % H + H) % H;
+        const int c = ((j - t) >> 1) + Lf / 2 - 1;       // window column, as for the rows above
         v = fmaf(pl.h[d][t], ylo[i][c], v);
         v = fmaf(pl.g[d][t], yhi[i][c], v);
       }
