@@ -219,3 +219,49 @@ def test_batched_argument_errors(sh):
     finally:
         sh.psi_destroy(psi1)
         sh.op_destroy(op)
+
+
+@pytest.mark.parametrize("n,levels,mask", [(48, 4, 0x1FF), (32, 1, 0x1), (64, 2, 0x1FE)])
+def test_batched_psi_edge_shapes(sh, n, levels, mask):
+    """Batched dictionary on a side that is not a power of two, a Dirac-only dictionary and a
+    wavelet-only one, against the oracle per image."""
+    P = 3
+    psib = sh.psi_create_batched(n, levels, mask, P)
+    try:
+        q = sh.psi_planes(psib)
+        g = np.random.default_rng(11)
+        xs = g.standard_normal((P, n, n)).astype(np.float32)
+        cs = g.standard_normal((P, q, n, n)).astype(np.float32)
+        cb = torch.empty((P, q, n, n), device="cuda")
+        xb = torch.empty((P, n, n), device="cuda")
+        sh.psi_adj(psib, _dev(xs), cb)
+        sh.psi_fwd(psib, _dev(cs), xb)
+        torch.cuda.synchronize()
+        ref = wavelets.SARA(n, levels, mask)
+        for p in range(P):
+            assert helpers.rel(cb[p].cpu().numpy(), ref.adj(xs[p].astype(np.float64))) <= 1e-5
+            assert helpers.rel(xb[p].cpu().numpy(), ref.fwd(cs[p].astype(np.float64))) <= 1e-5
+    finally:
+        sh.psi_destroy(psib)
+
+
+def test_batched_plan_of_one_problem_equals_single_plan(sh):
+    pb = _problems(shapes=SHAPES[1:2])[0]
+    n = pb.n
+    op1 = sh.op_create(pb.uv, n, 2, pb.J, pb.offsets)
+    opb = sh.op_create_batched(pb.uv, [len(pb.uv)], n, 2, pb.J, pb.offsets, [len(pb.offsets) - 1])
+    try:
+        x = _dev(np.random.default_rng(2).standard_normal((1, n, n)))
+        v1 = torch.empty(len(pb.uv), dtype=torch.complex64, device="cuda")
+        vb = torch.empty_like(v1)
+        sh.phi_fwd(op1, x, v1)
+        sh.phi_fwd(opb, x, vb)
+        a1, ab = torch.empty_like(x), torch.empty_like(x)
+        sh.phi_adj(op1, v1, a1)
+        sh.phi_adj(opb, v1, ab)
+        torch.cuda.synchronize()
+        assert torch.equal(v1, vb) and torch.equal(a1, ab)
+        np.testing.assert_array_equal(sh.op_permutation(op1), sh.op_permutation(opb))
+    finally:
+        sh.op_destroy(opb)
+        sh.op_destroy(op1)
