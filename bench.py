@@ -384,7 +384,7 @@ def main():
     tol = None
     if not a.no_tol:
         p2 = sh.sdmm_default_params()
-        p2.nu, p2.tol_rel, p2.passes, p2.max_iter, p2.check_every = nu, 1e-4, 5, 300, 10
+        p2.nu, p2.tol_rel, p2.passes, p2.max_iter, p2.check_every = nu, 1e-4, 5, 300, 1
         x = torch.empty((n, n), device=dev)
         log("[bench] SDMM to tolerance 1e-4, 5 passes of at most 300 iterations ...")
         torch.cuda.synchronize()
@@ -406,7 +406,7 @@ def main():
         # The feasibility slack of 1e-4 lies below what float32 visibilities resolve in the innermost uv
         # blocks (|y| reaches ~1e4 sigma there), so the same comparison is repeated with a 1e-3 slack.
         p3 = sh.sdmm_default_params()
-        p3.nu, p3.tol_rel, p3.passes, p3.max_iter, p3.check_every, p3.eps_slack = nu, 1e-4, 5, 300, 10, 1e-3
+        p3.nu, p3.tol_rel, p3.passes, p3.max_iter, p3.check_every, p3.eps_slack = nu, 1e-4, 5, 300, 1, 1e-3
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info3, res3 = sh.sdmm_solve(op, psi, y, eps, None, None, p3, x)
