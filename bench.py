@@ -8,7 +8,9 @@ Kaiser-Bessel width J = 8 on a 2x oversampled grid, 30 dB input SNR.
 A timed step is one SDMM iteration of the blocked problem (3): (cg_iters + 1) Phi + Phi^dagger
 pairs, Psi and Psi^dagger, the three fused prox/dual updates with float64 block norms and the
 stopping-test reductions.  `value` is the Phi + Phi^dagger visibility rate inside those steps,
-(cg_iters + 1) * M per step.  The JSON line also carries the bare pair rate, the roofline of the
+(cg_iters + 1) * M per step; every CG product goes through a Phi, Phi^dagger pair here (solver option
+toeplitz = 0).  The solver's default iteration (two CG steps through the Toeplitz form of
+Re(Phi_hat^H Phi_hat)) is timed beside it.  The JSON line also carries the bare pair rate, the roofline of the
 dominant interpolation kernel (HIP events on the library's stream), SDMM time-to-tolerance and the
 FP64 CPU oracle timed on a bounded sample of the same workload.
 
@@ -207,6 +209,7 @@ def batched_bench(sh, dev, steps, warmup, with_tol=True, snr=30.0):
     eps = np.concatenate(eps)
     prm = sh.sdmm_default_params()
     prm.cg_iters = 8
+    prm.toeplitz = 0
     sess = sh.sdmm_create(op, psi, y, eps, None, None, prm)
     try:
         sh.sdmm_iterate(sess, warmup)
@@ -312,6 +315,7 @@ def main():
     prm = sh.sdmm_default_params()
     prm.nu = nu
     prm.cg_iters = 8
+    prm.toeplitz = 0          # every CG product through a Phi, Phi^dagger pair: 9 pairs per step
     sess = sh.sdmm_create(op, psi, y, eps, None, None, prm)
     try:
         sh.sdmm_iterate(sess, a.warmup)
@@ -327,6 +331,24 @@ def main():
     pairs = prm.cg_iters + 1
     value = pairs * m / (dt / a.steps)
     log(f"[bench] SDMM iteration {ms_step:.3f} ms -> {value:.4g} vis/s (rel change {rel:.3g})")
+
+    # ---- the solver's default iteration: 2 CG steps through the Toeplitz form of Re(Phi_hat^H Phi_hat)
+    pd = sh.sdmm_default_params()
+    pd.nu = nu
+    t0 = time.perf_counter()
+    sess = sh.sdmm_create(op, psi, y, eps, None, None, pd)
+    create_s = time.perf_counter() - t0
+    try:
+        sh.sdmm_iterate(sess, a.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sh.sdmm_iterate(sess, a.steps)
+        torch.cuda.synchronize()
+        default_it = {"ms": 1e3 * (time.perf_counter() - t0) / a.steps, "cg_iters": pd.cg_iters,
+                      "toeplitz": pd.toeplitz, "session_create_s": round(create_s, 3)}
+    finally:
+        sh.sdmm_destroy(sess)
+    log(f"[bench] default SDMM iteration {default_it}")
     log(f"[bench] per-kernel timing of {a.steps} Phi+Phi^dagger pairs ...")
 
     # ---- bare Phi + Phi^dagger pairs (internal order) and per-kernel event timing
@@ -359,6 +381,21 @@ def main():
         cnt, ms = sh.profile_read(name)
         kern[name] = {"launches": cnt, "avg_ms": ms / max(cnt, 1)}
     sh.profile_enable(False)
+    # one Toeplitz product (three FFT passes), timed the same way
+    tp = sh.toeplitz_create(op, [1.0 / nu ** 2])
+    try:
+        for _ in range(2):
+            sh.toeplitz_apply(tp, xin, xo)
+        sh.profile_enable(True)
+        for _ in range(a.steps):
+            sh.toeplitz_apply(tp, xin, xo)
+        torch.cuda.synchronize()
+        cnt, ms = sh.profile_read("toeplitz")
+        toep_ms = ms / max(cnt, 1)
+        sh.profile_enable(False)
+    finally:
+        sh.toeplitz_destroy(tp)
+    default_it["toeplitz_product_ms"] = round(toep_ms, 4)
     log(f"[bench] pair {1e3 * pair_s:.3f} ms (internal), {1e3 * pair_user_s:.3f} ms (user order); "
         + ", ".join(f"{k} {v['avg_ms']:.4f} ms" for k, v in kern.items()))
     K = q["K"]
@@ -443,6 +480,7 @@ def main():
         "pair": {"internal_vis_per_s": m / pair_s, "user_order_vis_per_s": m / pair_user_s,
                  "internal_ms": 1e3 * pair_s, "user_ms": 1e3 * pair_user_s},
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
+        "default_iteration": default_it,
         "roofline": roof, "cpu_baseline": cpu, "sdmm_time_to_tol": tol, "plan_seconds": round(plan_s, 2),
         "batched": batched, "unet": unet,
     }

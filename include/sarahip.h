@@ -189,6 +189,27 @@ sh_status sh_reweight(int64_t D, const float* c, double delta, float* W_out, voi
 sh_status sh_std(int64_t D, const float* c, double* std_out, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Real normal operator of the measurement model (measurement-equation
+ * paragraph), the matrix of the x-update (Q in the SDMM paragraph):
+ *   (T x)_p = scale_q Re(Phi^H Phi x)_p = scale_q sum_r k(p - r) x_r,
+ *   k(d) = Re sum_m exp(i u_m . d)   (sum over problem q's visibilities),
+ * a 2D convolution, applied as a circulant on the plan's K x K grid (K >= 2n):
+ * zero-pad, FFT, product with the kernel's spectrum, inverse FFT, crop.  The
+ * kernel comes from four adjoint NUFFTs of modulated unit visibilities, so T
+ * matches the NUFFT pair Phi^dagger Phi to the interpolation's accuracy.
+ * ------------------------------------------------------------------------- */
+typedef struct sh_toep_s* sh_toep;
+/* Build T for every problem of `op` (which must outlive it).  scale: host P float64 > 0, or NULL
+ * (all 1).  Holds P*K*K float32 (spectrum) and P*n*K complex64 (scratch) of device memory; needs
+ * M complex64 + P*n*n + 4*P*K*K float32 more while building.  Synchronous.
+ * Errors: SH_EINVAL (NULL, scale <= 0 or non-finite, K < 2n), SH_ENOMEM, SH_EDEVICE. */
+sh_status sh_toeplitz_create(sh_op op, const double* scale, sh_toep* out, void* stream);
+/* out = T x for P images x (device P*n*n float32 each; out may not alias x).  Uses the plan's FFT
+ * scratch, like sh_phi_fwd/adj: calls on one plan must not overlap.  Async. */
+sh_status sh_toeplitz_apply(sh_toep t, const float* x, float* out, void* stream);
+sh_status sh_toeplitz_destroy(sh_toep t);
+
+/* ---------------------------------------------------------------------------
  * SDMM solve of (3) with SARA reweighting (PURIFY paragraph; SARA paragraph).
  * ------------------------------------------------------------------------- */
 
@@ -209,10 +230,13 @@ typedef struct {
   int32_t w_from_x0;   /* 1 (needs x0, W NULL): first-pass weights from the warm start by the
                           reweighting rule, delta_1 = std(Psi^dagger x0) per problem and
                           W = delta_1 / (delta_1 + |Psi^dagger x0|), as if x0 ended a pass */
+  int32_t toeplitz;    /* 1: the CG steps apply Re(Phi_hat^H Phi_hat) through its Toeplitz embedding
+                          (sh_toeplitz_create, built once per solve); 0: a Phi, Phi^dagger pair.
+                          The right-hand side, the residuals and the stopping test always use Phi */
 } sh_sdmm_params;
 
 /* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
- * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0.  With a batched plan, a given
+ * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0, toeplitz 1.  With a batched plan, a given
  * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 
@@ -321,8 +345,9 @@ sh_status sh_scale_images(float* x, const float* scale, int32_t P, int64_t N, in
  * ------------------------------------------------------------------------- */
 /* Enable (1) or disable (0) event timing; enabling clears the counters. */
 sh_status sh_profile_enable(int32_t on);
-/* Launch count and total milliseconds of kernel `name` ("degrid", "grid", "fold",
- * "fft_rows", "fft_cols") recorded since enabling.  Synchronises the device. */
+/* Launch count and total milliseconds of kernel group `name` ("degrid", "grid", "fold",
+ * "fft_rows", "fft_cols", "dwt", "prox", "cg", "toeplitz") recorded since enabling.
+ * Synchronises the device. */
 sh_status sh_profile_read(const char* name, int64_t* count, double* total_ms);
 
 #ifdef __cplusplus

@@ -20,7 +20,7 @@ void set_error(const char* fmt, ...) {
 const char* last_error() { return g_err; }
 
 namespace {
-const char* kNames[] = {"degrid", "grid", "fold", "fft_rows", "fft_cols", "dwt", "prox", "cg"};
+const char* kNames[] = {"degrid", "grid", "fold", "fft_rows", "fft_cols", "dwt", "prox", "cg", "toeplitz"};
 constexpr int kSlots = sizeof(kNames) / sizeof(kNames[0]);
 struct Pending {
   hipEvent_t a, b;

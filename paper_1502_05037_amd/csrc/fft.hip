@@ -8,12 +8,16 @@
 // over those n rows keeping the n needed columns, fused with the crop, the deapodisation and Re().
 //
 // Each work-group transforms B sequences of length L in LDS with self-sorting (Stockham) radix-8
-// stages and one radix-4 or radix-2 stage; twiddles come from a float64-derived table.
+// stages and one radix-4 or radix-2 stage; twiddles come from a float64-derived table.  The same
+// passes without deapodisation, and an unpruned forward 2D transform of a dense K x K array, serve
+// the Toeplitz form of Phi^dagger Phi.
 #include "op.hpp"
 
 namespace {
 
-enum Mode { ROWS_FWD = 0, COLS_FWD = 1, COLS_ADJ = 2, ROWS_ADJ = 3 };
+// COLS_TOEP: column pass of the Toeplitz normal operator (forward DFT of a pruned column, product with
+// the transposed kernel spectrum, inverse DFT, keep the n needed rows).
+enum Mode { ROWS_FWD = 0, COLS_FWD = 1, COLS_ADJ = 2, ROWS_ADJ = 3, FULL_ROWS = 4, FULL_COLS = 5, COLS_TOEP = 6 };
 
 template <bool INV>
 __device__ __forceinline__ float2 rot_mi(float2 a) {  // multiply by -i (forward) or +i (inverse)
@@ -128,6 +132,13 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
   } else if constexpr (MODE == COLS_ADJ) {
     in = (const float2*)in + prob * gk;
     out = (float2*)out + prob * hk;
+  } else if constexpr (MODE == FULL_ROWS || MODE == FULL_COLS) {
+    in = (const float2*)in + prob * gk;
+    out = (float2*)out + prob * gk;
+  } else if constexpr (MODE == COLS_TOEP) {
+    in = (const float2*)in + prob * hk;
+    out = (float2*)out + prob * hk;
+    deapod += prob * gk;              // here: the problem's kernel spectrum, transposed (column-major)
   } else {
     in = (const float2*)in + prob * hk;
     out = (float*)out + prob * img;
@@ -144,7 +155,7 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
       const float val = x[(size_t)r * n + c] * deapod[r] * deapod[c];
       lds[b * L + ((c - half) & (L - 1))] = make_float2(val, 0.f);
     }
-  } else if constexpr (MODE == COLS_FWD) {
+  } else if constexpr (MODE == COLS_FWD || MODE == COLS_TOEP) {
     const float2* h = (const float2*)in;
     for (int e = tid; e < B * L; e += NT) lds[e] = make_float2(0.f, 0.f);
     __syncthreads();
@@ -152,13 +163,13 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
       const int r = e / B, b = e - r * B;
       lds[b * L + ((r - half) & (L - 1))] = h[(size_t)r * K + seq0 + b];
     }
-  } else if constexpr (MODE == COLS_ADJ) {
+  } else if constexpr (MODE == COLS_ADJ || MODE == FULL_COLS) {
     const float2* g = (const float2*)in;
     for (int e = tid; e < B * L; e += NT) {
       const int r = e / B, b = e - r * B;
       lds[b * L + r] = g[(size_t)r * K + seq0 + b];
     }
-  } else {  // ROWS_ADJ
+  } else {  // ROWS_ADJ, FULL_ROWS
     const float2* h = (const float2*)in;
     for (int e = tid; e < B * L; e += NT) {
       const int b = e / L, c = e - b * L;
@@ -170,6 +181,16 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
   // ---- transform: thread tid works on sequence tid / (L/8) ----
   const int sq = tid / (L / 8), lt = tid % (L / 8);
   fft_lds<L, INV>(lds + sq * L, tw, lt);
+  if constexpr (MODE == COLS_TOEP) {
+    // lds[b L + k] *= Ht[(seq0 + b) K + k]: column seq0 + b of the spectrum, read contiguously
+    for (int e = tid; e < B * L; e += NT) {
+      const float hv = deapod[(size_t)seq0 * K + e];
+      const float2 v = lds[e];
+      lds[e] = make_float2(v.x * hv, v.y * hv);
+    }
+    __syncthreads();
+    fft_lds<L, true>(lds + sq * L, tw, lt);
+  }
 
   // ---- store ----
   if constexpr (MODE == ROWS_FWD) {
@@ -178,13 +199,19 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
       const int b = e / L, k = e - b * L;
       h[(size_t)(seq0 + b) * K + k] = lds[e];
     }
-  } else if constexpr (MODE == COLS_FWD) {
+  } else if constexpr (MODE == COLS_FWD || MODE == FULL_COLS) {
     float2* g = (float2*)out;
     for (int e = tid; e < B * L; e += NT) {
       const int k = e / B, b = e - k * B;
       g[(size_t)k * K + seq0 + b] = lds[b * L + k];
     }
-  } else if constexpr (MODE == COLS_ADJ) {
+  } else if constexpr (MODE == FULL_ROWS) {
+    float2* h = (float2*)out;
+    for (int e = tid; e < B * L; e += NT) {
+      const int b = e / L, k = e - b * L;
+      h[(size_t)(seq0 + b) * K + k] = lds[e];
+    }
+  } else if constexpr (MODE == COLS_ADJ || MODE == COLS_TOEP) {
     float2* h = (float2*)out;
     for (int e = tid; e < B * n; e += NT) {
       const int r = e / B, b = e - r * B;
@@ -264,6 +291,18 @@ sh_status fft_adjoint_2d(sh_op op, const float2* grid, float* x, hipStream_t st)
   }
   ProfScope ps("fft_rows", st);
   return launch_mode<ROWS_ADJ>(op->K, op->n, op->P, op->half.ptr, x, op->tw.ptr, op->deapod.ptr, op->n, st);
+}
+
+sh_status fft_full_2d(sh_op op, float2* buf, float2* tmp, hipStream_t st) {
+  SH_TRY(launch_mode<FULL_ROWS>(op->K, op->K, op->P, buf, tmp, op->tw.ptr, op->ones.ptr, op->n, st));
+  return launch_mode<FULL_COLS>(op->K, op->K, op->P, tmp, buf, op->tw.ptr, op->ones.ptr, op->n, st);
+}
+
+sh_status toeplitz_apply(sh_op op, const float* Ht, const float* x, float2* tq, float* out, hipStream_t st) {
+  ProfScope ps("toeplitz", st);
+  SH_TRY(launch_mode<ROWS_FWD>(op->K, op->n, op->P, x, op->half.ptr, op->tw.ptr, op->ones.ptr, op->n, st));
+  SH_TRY(launch_mode<COLS_TOEP>(op->K, op->K, op->P, op->half.ptr, tq, op->tw.ptr, Ht, op->n, st));
+  return launch_mode<ROWS_ADJ>(op->K, op->n, op->P, tq, out, op->tw.ptr, op->ones.ptr, op->n, st);
 }
 
 }  // namespace sh

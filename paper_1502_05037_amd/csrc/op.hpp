@@ -31,6 +31,7 @@ struct sh_op_s {
   int64_t n_items = 0, n_sparse = 0;
   int max_items_per_tile = 0;
   sh::DevBuf<float> deapod;        // 1 / psi_hat((r - n/2) / K), r < n
+  sh::DevBuf<float> ones;          // n ones (FFT passes without deapodisation; set by the Toeplitz build)
   sh::DevBuf<float2> tw;           // exp(-2 pi i m / K), m < K
   // scratch
   sh::DevBuf<float2> grid;         // P x K x K
@@ -55,5 +56,21 @@ sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, co
 // 2D FFT passes of the NUFFT over all P problems (fft.hip).
 sh_status fft_forward_2d(sh_op op, const float* x, float2* grid, hipStream_t st);   // S, Z, F
 sh_status fft_adjoint_2d(sh_op op, const float2* grid, float* x, hipStream_t st);   // F^H, Z^T, S, Re
+// Unpruned forward 2D DFT of P dense K x K complex arrays, in place in buf (tmp: same size, clobbered).
+sh_status fft_full_2d(sh_op op, float2* buf, float2* tmp, hipStream_t st);
+// out = C * x per problem (linear 2D convolution of the n x n image x with the kernel whose DFT on
+// the K x K grid is Ht, stored transposed: Ht[p][k2][k1]); tq: P x n x K complex scratch.
+sh_status toeplitz_apply(sh_op op, const float* Ht, const float* x, float2* tq, float* out, hipStream_t st);
 
+}  // namespace sh
+
+// Toeplitz form of scale_p Re(Phi^H Phi) for a plan (toeplitz.hip).
+struct sh_toep_s {
+  sh_op op = nullptr;
+  sh::DevBuf<float> Ht;            // P x K x K: kernel spectrum / K^2 * scale_p, transposed
+  sh::DevBuf<float2> tq;           // P x n x K scratch of the column pass
+};
+
+namespace sh {
+sh_status toeplitz_build(sh_op op, const double* scale, sh_toep_s* t, hipStream_t st);
 }  // namespace sh

@@ -11,8 +11,11 @@
 // (blocks contiguous).  v_j = y_j - z_j is kept instead of y_j.  The x-update is conjugate gradients
 // warm-started at x_{n-1} with a fixed number of steps; its initial residual
 //   b - Q x_{n-1} = Psi v_psi + Phi_hat^dagger (v_phi - Phi_hat x_{n-1}) + v_+ - 2 x_{n-1}
-// reuses s_phi = Phi_hat x_{n-1} from the previous iteration, so one iteration costs
-// (cg_iters + 1) applications each of Phi and Phi^dagger.  CG scalars stay on the device.
+// reuses s_phi = Phi_hat x_{n-1} from the previous iteration.  The CG products Re(Phi_hat^H Phi_hat) p
+// go through the Toeplitz embedding of that operator (toeplitz.hip: FFT passes only) or, with the
+// option off, through a Phi, Phi^dagger pair; one iteration then costs one application each of Phi
+// and Phi^dagger plus cg_iters Toeplitz products, or (cg_iters + 1) pairs.  CG scalars stay on the
+// device.
 // Block norms, dot products, the stopping test and the reweighting statistics are float64.
 #include <algorithm>
 #include <chrono>
@@ -118,6 +121,7 @@ struct Work {
   sh::DevBuf<double> sc, eps_hat, rho, resid, delta;
   sh::DevBuf<float> inv_nu, gamma;
   sh::Reducer red;
+  sh_toep_s toep;                  // Re(Phi_hat^H Phi_hat) as a convolution (option toeplitz)
 };
 
 // Power iteration on Re(Phi^H Phi) (scale 1) from x0, for the P problems of the plan at once (each
@@ -179,6 +183,7 @@ void sh_sdmm_default_params(sh_sdmm_params* p) {
   p->check_every = 10;
   p->graph = 1;
   p->w_from_x0 = 0;
+  p->toeplitz = 1;
 }
 
 sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream) {
@@ -277,6 +282,11 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     inv[p] = float(1.0 / s->nu[p]);
   }
   SH_HIP(hipMemcpy(w.inv_nu.ptr, inv.data(), P * sizeof(float), hipMemcpyHostToDevice));
+  if (s->prm.toeplitz) {   // the CG operator Re(Phi_hat^H Phi_hat) = Re(Phi^H Phi) / nu^2 per problem
+    std::vector<double> sc(P);
+    for (int p = 0; p < P; ++p) sc[p] = 1.0 / (s->nu[p] * s->nu[p]);
+    SH_TRY(sh::toeplitz_build(op, sc.data(), &w.toep, st));
+  }
   hipLaunchKernelGGL(gather_scale, dim3((unsigned)op->n_chunks), dim3(256), 0, st, (const float2*)y, op->perm.ptr,
                      w.yhat.ptr, op->chunks.ptr, op->block_prob_d.ptr, w.inv_nu.ptr);
   SH_LAUNCHED();
@@ -351,8 +361,12 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
                      w.xprev.ptr, N);
   SH_TRY(w.red.dot(w.r.ptr, w.r.ptr, per, s_rs, st));
   for (int k = 0; k < s->kcg; ++k) {
-    SH_TRY(sh::phi_forward(op, w.p.ptr, w.vtmp.ptr, false, inv_nu, st));
-    SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.Ap.ptr, false, inv_nu, st));
+    if (s->prm.toeplitz) {
+      SH_TRY(sh::toeplitz_apply(op, w.toep.Ht.ptr, w.p.ptr, w.toep.tq.ptr, w.Ap.ptr, st));
+    } else {
+      SH_TRY(sh::phi_forward(op, w.p.ptr, w.vtmp.ptr, false, inv_nu, st));
+      SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.Ap.ptr, false, inv_nu, st));
+    }
     hipLaunchKernelGGL(cg_ap, dim3(gN), dim3(256), 0, st, w.p.ptr, w.Ap.ptr, N);
     SH_TRY(w.red.dot(w.p.ptr, w.Ap.ptr, per, s_pap + k * P, st));
     hipLaunchKernelGGL(cg_update, gP, dim3(256), 0, st, w.x.ptr, w.r.ptr, w.p.ptr, w.Ap.ptr, per, s_rs + k * P,
@@ -491,6 +505,7 @@ sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps,
              "tol_rel, eps_slack >= 0 and rw_beta > 0 required");
   SH_REQUIRE(prm->graph == 0 || prm->graph == 1, "graph must be 0 or 1");
   SH_REQUIRE(prm->w_from_x0 == 0 || prm->w_from_x0 == 1, "w_from_x0 must be 0 or 1");
+  SH_REQUIRE(prm->toeplitz == 0 || prm->toeplitz == 1, "toeplitz must be 0 or 1");
   for (int i = 0; i < op->R; ++i) {
     if (!std::isfinite(eps[i])) {
       sh::set_error("eps[%d] is not finite", i);

@@ -40,7 +40,7 @@ class SdmmParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("nu", C.c_double), ("tol_rel", C.c_double), ("eps_slack", C.c_double),
                 ("rw_beta", C.c_double), ("rw_delta0", C.c_double), ("max_iter", C.c_int32),
                 ("cg_iters", C.c_int32), ("passes", C.c_int32), ("check_every", C.c_int32), ("graph", C.c_int32),
-                ("w_from_x0", C.c_int32)]
+                ("w_from_x0", C.c_int32), ("toeplitz", C.c_int32)]
 
 
 class SdmmInfo(C.Structure):
@@ -85,6 +85,9 @@ _SIGS = {
     "sh_vis_to_internal": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sh_vis_to_user": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sh_op_norm": (C.c_int, [_vp, _vp, _i32, _f64, _P64, _vp]),
+    "sh_toeplitz_create": (C.c_int, [_vp, _P64, C.POINTER(_vp), _vp]),
+    "sh_toeplitz_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sh_toeplitz_destroy": (C.c_int, [_vp]),
     "sh_psi_create": (C.c_int, [_i32, _i32, _u32, C.POINTER(_vp)]),
     "sh_psi_create_batched": (C.c_int, [_i32, _i32, _u32, _i32, C.POINTER(_vp)]),
     "sh_psi_destroy": (C.c_int, [_vp]),
@@ -270,6 +273,28 @@ def vis_to_internal(op, user, internal, stream=None):
 
 def vis_to_user(op, internal, user, stream=None):
     _check(lib.sh_vis_to_user(op, _ptr(internal), _ptr(user), _stream(stream)), "vis_to_user")
+
+
+def toeplitz_create(op, scale=None, stream=None):
+    """Toeplitz form of scale_p Re(Phi^H Phi) for every problem of op; scale: P floats or None."""
+    h = _vp()
+    if scale is None:
+        sp = None
+    else:
+        sc = np.ascontiguousarray(np.atleast_1d(np.asarray(scale, dtype=np.float64)))
+        if sc.size != op_query(op)["P"]:
+            raise ValueError("scale needs one value per problem")
+        sp = sc.ctypes.data_as(_P64)
+    _check(lib.sh_toeplitz_create(op, sp, C.byref(h), _stream(stream)), "toeplitz_create")
+    return h
+
+
+def toeplitz_apply(t, x, out, stream=None):
+    _check(lib.sh_toeplitz_apply(t, _ptr(x), _ptr(out), _stream(stream)), "toeplitz_apply")
+
+
+def toeplitz_destroy(t):
+    _check(lib.sh_toeplitz_destroy(t), "toeplitz_destroy")
 
 
 def op_norm(op, x0, iters: int = 200, tol: float = 1e-12, stream=None):

@@ -180,3 +180,21 @@ def test_default_two_cg_steps_parity(sh):
     assert prm.cg_iters == 2
     x, info, _, _ = _gpu_solve(sh, pb, prm)
     assert helpers.rel(x, x_ref) <= 1e-4
+
+
+@pytest.mark.parametrize("toeplitz", [0, 1])
+def test_cg_operator_forms_match_oracle(sh, toeplitz):
+    """The CG products through a Phi, Phi^dagger pair (0) or through the Toeplitz embedding of
+    Re(Phi_hat^H Phi_hat) (1), against the oracle (whose CG applies its FP64 NUFFT pair), with eight
+    and with the default two CG steps."""
+    pb = helpers.build(1, 64, 2048, 1, 6)
+    psi, nu, gamma = _oracle_setup(pb)
+    for kcg in (8, 2):
+        p = sdmm.Params(gamma=gamma, nu=nu, max_iter=300, cg_iters=kcg)
+        x_ref, _, infos, _ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
+        x, info, resid, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=300, cg_iters=kcg,
+                                                       toeplitz=toeplitz))
+        err = helpers.rel(x, x_ref)
+        print(f"toeplitz={toeplitz} cg_iters={kcg}: image error vs oracle {err:.3e}")
+        assert err <= 1e-4
+        np.testing.assert_allclose(resid, infos[0].block_resid, rtol=1e-4)
