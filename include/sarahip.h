@@ -198,6 +198,12 @@ sh_status sh_std(int64_t D, const float* c, double* std_out, void* stream);
  * kernel comes from four adjoint NUFFTs of modulated unit visibilities, so T
  * matches the NUFFT pair Phi^dagger Phi to the interpolation's accuracy.
  * ------------------------------------------------------------------------- */
+/* Density estimate of 1 / ||Phi_b|| for every block b of the plan (host R float64): with count_b the
+ * largest number of block b's visibilities in an alpha x alpha window of grid cells (side 2 pi / n in the
+ * uv plane, every cell offset, periodic), ||Phi_b||^2 ~ n^2 count_b and b_out[b] = 1 / (n sqrt(count_b)).
+ * Cells are the plan's float64 cells floor(u K / 2 pi) mod K.  Synchronous.  Errors: SH_EINVAL, SH_ENOMEM. */
+sh_status sh_block_weights(sh_op op, double* b_out, void* stream);
+
 typedef struct sh_toep_s* sh_toep;
 /* Build T for every problem of `op` (which must outlive it).  scale: host P float64 > 0, or NULL
  * (all 1).  Holds P*K*K float32 (spectrum) and P*n*K complex64 (scratch) of device memory; needs
@@ -215,7 +221,8 @@ sh_status sh_toeplitz_destroy(sh_toep t);
 
 typedef struct {
   double gamma;        /* l1 prox step; <= 0: 1e-4 * max|Psi^dagger Phi^dagger y| / nu^2 */
-  double nu;           /* operator norm used to normalise; <= 0: sh_op_norm from x0 = ones */
+  double nu;           /* norm used to normalise (see block_norm); <= 0: power iteration from ones
+                          (at most 200 steps, to a relative change of 1e-6) */
   double tol_rel;      /* stop when ||x_n - x_{n-1}||/||x_n|| <= tol_rel and all blocks feasible;
                           0 = run max_iter every pass (fixed schedule) */
   double eps_slack;    /* feasibility test ||y_i - Phi_i x|| <= eps_i (1 + eps_slack) */
@@ -233,10 +240,15 @@ typedef struct {
   int32_t toeplitz;    /* 1: the CG steps apply Re(Phi_hat^H Phi_hat) through its Toeplitz embedding
                           (sh_toeplitz_create, built once per solve); 0: a Phi, Phi^dagger pair.
                           The right-hand side, the residuals and the stopping test always use Phi */
+  int32_t block_norm;  /* normalisation of the data splits: Phi_hat_b = c_b Phi_b, y_hat_b = c_b y_b,
+                          eps_hat_b = c_b eps_b with c_b = a_b / nu_p (b a block of problem p), where
+                          a_b = 1 (0) or the density estimate of 1 / ||Phi_b|| (1, sh_block_weights),
+                          and nu_p = nu if given, else the norm of problem p's a-weighted operator
+                          sum_b a_b^2 Re(Phi_b^H Phi_b).  Any c_b > 0 keeps the solution set */
 } sh_sdmm_params;
 
 /* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
- * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0, toeplitz 1.  With a batched plan, a given
+ * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0, toeplitz 1, block_norm 1.  With a batched plan, a given
  * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 

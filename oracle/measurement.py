@@ -155,3 +155,45 @@ def op_norm(op, x0: np.ndarray, max_iter: int = 200, tol: float = 1e-12) -> floa
             break
         lam = lam_new
     return float(np.sqrt(lam))
+
+
+def block_density_weights(uv: np.ndarray, n: int, alpha: int, offsets) -> np.ndarray:
+    """Density estimate a_b of 1 / ||Phi_b|| for every block b (weights that normalise the data splits).
+
+    The paper splits the data into blocks (2) and constrains each block separately; scaling block b's
+    constraint by any positive number leaves its ball unchanged.  For an n x n image the largest
+    eigenvalue of Re(Phi_b^H Phi_b) is close to n^2 times the largest number of the block's uv samples
+    in a square of side 2 pi / n (uniform density rho per unit area gives (2 pi)^2 rho).  Counted here
+    on the cells floor(u K / (2 pi)) mod K of the K x K grid, K = alpha n (cell side 2 pi / K), as the
+    largest sum over alpha x alpha cells at any cell offset, periodic in both axes:
+        count_b = max_(r, c) sum_(a, d < alpha) H_b[(r + a) mod K, (c + d) mod K],
+        a_b = 1 / (n sqrt(count_b)).
+    """
+    K = alpha * n
+    uv = np.asarray(uv, dtype=np.float64)
+    cells = np.mod(np.floor(uv * (float(K) / (2.0 * np.pi))).astype(np.int64), K)
+    off = np.asarray(offsets, dtype=np.int64)
+    out = np.empty(len(off) - 1)
+    for b in range(len(off) - 1):
+        H = np.zeros((K, K))
+        np.add.at(H, (cells[off[b]:off[b + 1], 0], cells[off[b]:off[b + 1], 1]), 1.0)
+        win = np.zeros((K, K))
+        for a in range(alpha):
+            for d in range(alpha):
+                win += np.roll(np.roll(H, -a, axis=0), -d, axis=1)
+        out[b] = 1.0 / np.sqrt(float(n) * float(n) * win.max())
+    return out
+
+
+class BlockWeighted:
+    """The operator with block b's rows scaled by a_b: (A x)_m = a_b (Phi x)_m for m in block b."""
+
+    def __init__(self, op, offsets, a):
+        self.op, self.n = op, op.n
+        self.w = np.repeat(np.asarray(a, dtype=np.float64), np.diff(np.asarray(offsets, dtype=np.int64)))
+
+    def fwd(self, x):
+        return self.w * self.op.fwd(x)
+
+    def adj(self, v):
+        return self.op.adj(self.w * np.asarray(v, dtype=np.complex128))

@@ -13,14 +13,19 @@ SDMM keeps one primal/dual pair (y_j, z_j) per term and iterates
     y_j = prox_{gamma g_j}(s_j + z_j),
     z_j = z_j + s_j - y_j.
 Here L = {Psi^dagger, Phi_1..Phi_R, I}; Psi Psi^dagger = I, so
-Q = 2 I + Re(Phi^H Phi).  Everything runs on the normalised operator
-Phi_hat = Phi / nu with nu = ||Phi||, data y/nu and bounds eps/nu, which leaves
-the solution set of (3) unchanged and puts the spectrum of Q in [2, 3].
+Q = 2 I + Re(Phi^H Phi).  Everything runs on normalised splits: block b uses
+Phi_hat_b = c_b Phi_b, data c_b y_b and bound c_b eps_b with c_b = a_b / nu, where
+a_b are block weights (1, or measurement.block_density_weights) and nu is the
+norm of the a-weighted operator.  Any c_b > 0 leaves the solution set of (3)
+unchanged; this choice puts the spectrum of Q in [2, 3].
 
 Readings where the paper is silent (each also listed in the design notes):
 * Q^{-1} by conjugate gradients warm-started at the previous x, either to a
   relative residual of 1e-12 or for a fixed number of steps.
 * gamma = 1e-4 ||Psi^dagger Phi_hat^dagger y_hat||_inf unless given.
+* block weights a_b ~ 1 / ||Phi_b|| (density estimate), so that every block's
+  constraint acts on x with a comparable force; a_b = 1 gives one
+  normalisation for all blocks.
 * stop when ||x_n - x_{n-1}|| / ||x_n|| <= tol_rel and every block satisfies
   ||y_i - Phi_i x_n|| <= eps_i (1 + eps_slack), or after max_iter iterations;
   tol_rel = 0 runs the fixed schedule.
@@ -49,6 +54,7 @@ class Params:
     cg_tol: float = 1e-12
     passes: int = 1
     rw_beta: float = 0.5
+    block_weights: np.ndarray | None = None   # a_b per block; None: 1
 
 
 @dataclass
@@ -103,21 +109,25 @@ def cg(Q, b, x0, iters=None, tol=1e-12, max_iter=500):
 
 
 class Problem:
-    """Normalised problem (3): Phi_hat = Phi/nu, y_hat = y/nu, eps_hat = eps/nu."""
+    """Normalised problem (3): block b uses c_b Phi_b, c_b y_b, c_b eps_b with c_b = a_b / nu."""
 
-    def __init__(self, op, psi, y, offsets, eps, nu):
+    def __init__(self, op, psi, y, offsets, eps, nu, block_weights=None):
         self.op, self.psi = op, psi
         self.nu = float(nu)
-        self.y_hat = np.asarray(y, dtype=np.complex128) / self.nu
         self.offsets = np.asarray(offsets, dtype=np.int64)
-        self.eps_hat = np.asarray(eps, dtype=np.float64) / self.nu
+        R = len(self.offsets) - 1
+        a = np.ones(R) if block_weights is None else np.asarray(block_weights, dtype=np.float64)
+        self.c = a / self.nu                                   # c_b per block
+        self.cv = np.repeat(self.c, np.diff(self.offsets))     # c_b per visibility
+        self.y_hat = self.cv * np.asarray(y, dtype=np.complex128)
+        self.eps_hat = self.c * np.asarray(eps, dtype=np.float64)
         self.n = psi.n
 
     def fwd(self, x):
-        return self.op.fwd(x) / self.nu
+        return self.cv * self.op.fwd(x)
 
     def adj(self, v):
-        return self.op.adj(v) / self.nu
+        return self.op.adj(self.cv * np.asarray(v, dtype=np.complex128))
 
     def Q(self, x):
         return 2.0 * x + self.adj(self.fwd(x))
@@ -127,11 +137,15 @@ class Problem:
         return [(int(o[i]), int(o[i + 1])) for i in range(len(o) - 1)]
 
 
-def default_gamma(op, psi, y, nu, factor: float = 1e-4) -> float:
-    """gamma = factor max |Psi^dagger Phi_hat^dagger y_hat| = factor max |Psi^dagger Phi^dagger y| / nu^2.
+def default_gamma(op, psi, y, nu, factor: float = 1e-4, offsets=None, block_weights=None) -> float:
+    """gamma = factor max |Psi^dagger Phi_hat^dagger y_hat| = factor max |Psi^dagger Phi^dagger (c^2 y)|
+    (c_b = a_b / nu; with a = 1: factor max |Psi^dagger Phi^dagger y| / nu^2).
 
     The minimiser does not depend on gamma, only the path to it does."""
-    return factor * float(np.max(np.abs(psi.adj(op.adj(np.asarray(y, dtype=np.complex128)))))) / nu ** 2
+    y = np.asarray(y, dtype=np.complex128)
+    if block_weights is not None:
+        y = y * np.repeat(np.asarray(block_weights, dtype=np.float64) ** 2, np.diff(np.asarray(offsets)))
+    return factor * float(np.max(np.abs(psi.adj(op.adj(y))))) / nu ** 2
 
 
 def init_state(pb: Problem, x0=None) -> State:
@@ -175,7 +189,7 @@ def sdmm_pass(pb: Problem, W, p: Params, st: State, record=False):
         rel = dx / xn if xn > 0 else (0.0 if dx == 0 else np.inf)
         info.iters = it + 1
         info.rel_change = rel
-        info.block_resid = resid * pb.nu
+        info.block_resid = resid / pb.c
         feasible = bool(np.all(resid <= pb.eps_hat * (1.0 + p.eps_slack)))
         if record:
             info.history.append((rel, resid.copy()))
@@ -197,7 +211,7 @@ def sara(op, psi, y, offsets, eps, p: Params, x0=None, W0=None, delta0=None, rec
     Returns (x, W_last, infos, state).  With x0 the SDMM state is warm-started
     from x0; with W0 the first pass uses W0 (delta0 its delta), else W = I.
     """
-    pb = Problem(op, psi, y, offsets, eps, p.nu)
+    pb = Problem(op, psi, y, offsets, eps, p.nu, p.block_weights)
     st = init_state(pb, x0)
     W = W0
     delta = delta0

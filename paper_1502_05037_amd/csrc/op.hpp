@@ -72,5 +72,11 @@ struct sh_toep_s {
 };
 
 namespace sh {
-sh_status toeplitz_build(sh_op op, const double* scale, sh_toep_s* t, hipStream_t st);
+// T = scale_p sum_b wblk_b^2 Re(Phi_b^H Phi_b) over the blocks b of problem p (scale, wblk: host arrays of P
+// and R values, NULL = all 1).
+sh_status toeplitz_build(sh_op op, const double* scale, const double* wblk, sh_toep_s* t, hipStream_t st);
+// Multiplies problem p's operator by factor[p] (host P values).
+sh_status toeplitz_rescale(sh_toep_s* t, const double* factor, hipStream_t st);
+// Density estimate of 1 / ||Phi_b|| for every block b (blocknorm.hip).
+sh_status block_density_weights(sh_op op, std::vector<double>& b, hipStream_t st);
 }  // namespace sh

@@ -140,15 +140,18 @@ __global__ __launch_bounds__(256) void prox_pos_kernel(int64_t N, const float* _
   v[i] = y - zn;
 }
 
-// per-chunk float64 partial sums of ||s + z - yhat||^2 and ||s - yhat||^2
-__global__ __launch_bounds__(256) void ball_norms(const float2* __restrict__ s, const float2* __restrict__ z,
+// per-chunk float64 partial sums of ||s + z - yhat||^2 and ||s - yhat||^2, s = cb s_in (cb: the block's
+// weight, 1 without cblk)
+__global__ __launch_bounds__(256) void ball_norms(const float2* __restrict__ s_in, const float2* __restrict__ z,
                                                   const float2* __restrict__ yh, const int4* __restrict__ chunks,
-                                                  double* __restrict__ part) {
+                                                  const float* __restrict__ cblk, double* __restrict__ part) {
   __shared__ double sh[256];
   const int4 c = chunks[blockIdx.x];
+  const float cb = cblk ? cblk[c.x] : 1.0f;
   double a = 0.0, b = 0.0;
   for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
-    const float2 sv = s[i], zv = z[i], yv = yh[i];
+    const float2 si = s_in[i], zv = z[i], yv = yh[i];
+    const float2 sv = make_float2(cb * si.x, cb * si.y);
     const double dr = double(sv.x) - double(yv.x), di = double(sv.y) - double(yv.y);
     const double tr = dr + double(zv.x), ti = di + double(zv.y);
     a += tr * tr + ti * ti;
@@ -176,23 +179,27 @@ __global__ void ball_final(const double* __restrict__ part, const int* __restric
   resid[b] = sqrt(c);
 }
 
-// y = yhat + (t - yhat) min(1, eps/rho); z <- t - y; v = y - z (- s if sub_s)
-__global__ __launch_bounds__(256) void ball_project(const float2* __restrict__ s, float2* __restrict__ z,
+// s = cb s_in; y = yhat + (t - yhat) min(1, eps/rho); z <- t - y; v = cb (y - z (- s if sub_s)), the
+// factor cb readying v for the unweighted adjoint
+__global__ __launch_bounds__(256) void ball_project(const float2* __restrict__ s_in, float2* __restrict__ z,
                                                     const float2* __restrict__ yh, const int4* __restrict__ chunks,
                                                     const double* __restrict__ eps, const double* __restrict__ rho,
-                                                    float2* __restrict__ v, int sub_s) {
+                                                    const float* __restrict__ cblk, float2* __restrict__ v, int sub_s) {
   const int4 c = chunks[blockIdx.x];
   const double r = rho[c.x], e = eps[c.x];
+  const float cb = cblk ? cblk[c.x] : 1.0f;
   const bool inside = r <= e;   // inside the ball (boundary included) the projection is the identity
   const float ratio = inside ? 1.0f : float(e / r);
   for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
-    const float2 sv = s[i], zv = z[i], yv = yh[i];
+    const float2 si = s_in[i], zv = z[i], yv = yh[i];
+    const float2 sv = make_float2(cb * si.x, cb * si.y);
     const float tr = sv.x + zv.x, ti = sv.y + zv.y;
     const float yr = inside ? tr : yv.x + (tr - yv.x) * ratio;
     const float yi = inside ? ti : yv.y + (ti - yv.y) * ratio;
     const float zr = tr - yr, zi = ti - yi;
     z[i] = make_float2(zr, zi);
-    v[i] = sub_s ? make_float2(yr - zr - sv.x, yi - zi - sv.y) : make_float2(yr - zr, yi - zi);
+    const float vr = sub_s ? yr - zr - sv.x : yr - zr, vi = sub_s ? yi - zi - sv.y : yi - zi;
+    v[i] = make_float2(cb * vr, cb * vi);
   }
 }
 
@@ -264,13 +271,14 @@ sh_status launch_prox_pos(int64_t N, const float* s, float* z, float* v, hipStre
 }
 
 sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
-                           double* resid, float2* v, bool sub_s, hipStream_t st) {
+                           double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st) {
   ProfScope ps("prox", st);
   const unsigned nc = (unsigned)op->n_chunks;
-  hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, op->partials.ptr);
+  hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr);
   hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
                      op->chunk_first_d.ptr, op->R, rho, resid);
-  hipLaunchKernelGGL(ball_project, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, eps, rho, v, sub_s ? 1 : 0);
+  hipLaunchKernelGGL(ball_project, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, eps, rho, cblk, v,
+                     sub_s ? 1 : 0);
   SH_LAUNCHED();
   return SH_OK;
 }
@@ -304,7 +312,7 @@ sh_status sh_prox_ball(sh_op op, const float* s, float* z, const float* yhat, co
   sh::DevBuf<double> rho;
   SH_TRY(rho.alloc(op->R));
   SH_TRY(sh::launch_prox_ball(op, (const float2*)s, (float2*)z, (const float2*)yhat, eps, rho.ptr, resid_out,
-                              (float2*)v_out, false, st));
+                              (float2*)v_out, false, nullptr, st));
   SH_HIP(hipStreamSynchronize(st));  // rho is freed on return
   return SH_OK;
 }

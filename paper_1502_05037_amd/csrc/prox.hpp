@@ -24,8 +24,10 @@ struct Reducer {
 sh_status launch_prox_l1(int64_t per, int P, const float* s, float* z, const float* W, const float* gamma_d,
                          float gamma, float* v, hipStream_t st);
 sh_status launch_prox_pos(int64_t N, const float* s, float* z, float* v, hipStream_t st);
+// cblk: per-block weights c_b (device R floats) or NULL (1): the split uses c_b s (s = Phi x unweighted)
+// and v is returned multiplied by c_b, ready for the unweighted adjoint.
 sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
-                           double* resid, float2* v, bool sub_s, hipStream_t st);
+                           double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st);
 sh_status launch_reweight(int64_t per, int P, const float* c, const double* delta_d, double delta, float* W,
                           hipStream_t st);
 

@@ -4,8 +4,11 @@
 // as f_0(Psi^dagger x) + sum_i iota_{B_i}(Phi_i x) + iota_+(x).  SDMM keeps (y_j, z_j) per term:
 //   x   = Q^{-1} sum_j L_j^T (y_j - z_j),  Q = Psi Psi^dagger + Phi^dagger Phi + I = 2I + Re(Phi^H Phi)
 //   s_j = L_j x;  y_j = prox(s_j + z_j);  z_j += s_j - y_j.
-// Everything runs on Phi_hat = Phi / nu (nu = ||Phi||), y_hat = y / nu, eps_hat = eps / nu, which
-// keeps the solution set and puts the spectrum of Q in [2, 3].
+// Everything runs on the normalised splits Phi_hat_b = c_b Phi_b, y_hat_b = c_b y_b, eps_hat_b = c_b eps_b
+// with c_b = a_b / nu_p for block b of problem p: a_b = 1 (one normalisation per problem) or the
+// density estimate of 1 / ||Phi_b|| (option block_norm, blocknorm.hip), and nu_p the norm of the
+// a-weighted operator of problem p.  Any c_b > 0 keeps the solution set; this choice puts the
+// spectrum of Q in [2, 3].
 //
 // GPU layout: the state lives in device memory; visibility-space vectors are in internal order
 // (blocks contiguous).  v_j = y_j - z_j is kept instead of y_j.  The x-update is conjugate gradients
@@ -54,15 +57,25 @@ __global__ void scale_kernel(const float* __restrict__ a, float* __restrict__ b,
   b[i] = a[i] * sc;
 }
 
-// yhat (internal order) = y[perm] / nu of the block's problem; one work-group per reduction chunk
+// yhat (internal order) = c_b y[perm] for the block b of each chunk; one work-group per reduction chunk
 __global__ __launch_bounds__(256) void gather_scale(const float2* __restrict__ src, const uint32_t* __restrict__ idx,
                                                     float2* __restrict__ dst, const int4* __restrict__ chunks,
-                                                    const int32_t* __restrict__ block_prob,
-                                                    const float* __restrict__ inv_nu) {
+                                                    const float* __restrict__ cblk) {
   const int4 c = chunks[blockIdx.x];
-  const float s = inv_nu[block_prob[c.x]];
+  const float s = cblk[c.x];
   for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
     const float2 v = src[idx[i]];
+    dst[i] = make_float2(v.x * s, v.y * s);
+  }
+}
+
+// dst = w_b src over the chunks of block b (dst may equal src)
+__global__ __launch_bounds__(256) void scale_chunks(const float2* src, float2* dst, const int4* __restrict__ chunks,
+                                                    const float* __restrict__ w) {
+  const int4 c = chunks[blockIdx.x];
+  const float s = w[c.x];
+  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
+    const float2 v = src[i];
     dst[i] = make_float2(v.x * s, v.y * s);
   }
 }
@@ -119,15 +132,17 @@ struct Work {
   sh::DevBuf<float> spsi, zpsi, vpsi, W;
   sh::DevBuf<float2> yhat, sphi, zphi, vphi, vtmp;
   sh::DevBuf<double> sc, eps_hat, rho, resid, delta;
-  sh::DevBuf<float> inv_nu, gamma;
+  sh::DevBuf<float> cblk, cblk2, gamma;   // c_b and c_b^2 per block, gamma per problem
   sh::Reducer red;
   sh_toep_s toep;                  // Re(Phi_hat^H Phi_hat) as a convolution (option toeplitz)
 };
 
 // Power iteration on Re(Phi^H Phi) (scale 1) from x0, for the P problems of the plan at once (each
 // normalised and tested on its own); nu[p] = sqrt of problem p's Rayleigh quotient.  Stops when
-// every problem's estimate changed by <= tol relative, or after `iters` steps.
-sh_status power_norm(sh_op op, const float* x0, int iters, double tol, double* nu, hipStream_t st) {
+// every problem's estimate changed by <= tol relative, or after `iters` steps.  With w2blk (device,
+// per block) the operator is sum_b w2_b Re(Phi_b^H Phi_b); with toep it is that Toeplitz operator.
+sh_status power_norm(sh_op op, const float* x0, int iters, double tol, double* nu, hipStream_t st,
+                     const float* w2blk = nullptr, const sh_toep_s* toep = nullptr) {
   const int P = op->P;
   const int64_t per = int64_t(op->n) * op->n, N = per * P;
   sh::DevBuf<float> x, y;
@@ -143,8 +158,17 @@ sh_status power_norm(sh_op op, const float* x0, int iters, double tol, double* n
   hipLaunchKernelGGL(scale_kernel, dim3(nblk(per), P), dim3(256), 0, st, x0, x.ptr, per, sc.ptr);
   std::vector<double> lam(P, 0.0), h(2 * P);
   for (int it = 0; it < iters; ++it) {
-    SH_TRY(sh::phi_forward(op, x.ptr, v.ptr, false, nullptr, st));
-    SH_TRY(sh::phi_adjoint(op, v.ptr, y.ptr, false, nullptr, st));
+    if (toep) {
+      SH_TRY(sh::toeplitz_apply(op, toep->Ht.ptr, x.ptr, toep->tq.ptr, y.ptr, st));
+    } else {
+      SH_TRY(sh::phi_forward(op, x.ptr, v.ptr, false, nullptr, st));
+      if (w2blk) {
+        hipLaunchKernelGGL(scale_chunks, dim3((unsigned)op->n_chunks), dim3(256), 0, st, v.ptr, v.ptr, op->chunks.ptr,
+                           w2blk);
+        SH_LAUNCHED();
+      }
+      SH_TRY(sh::phi_adjoint(op, v.ptr, y.ptr, false, nullptr, st));
+    }
     SH_TRY(red.dot(x.ptr, y.ptr, per, sc.ptr + P, st));
     SH_TRY(red.dot(y.ptr, y.ptr, per, sc.ptr + 2 * P, st));
     hipLaunchKernelGGL(scale_kernel, dim3(nblk(per), P), dim3(256), 0, st, y.ptr, x.ptr, per, sc.ptr + 2 * P);
@@ -184,6 +208,7 @@ void sh_sdmm_default_params(sh_sdmm_params* p) {
   p->graph = 1;
   p->w_from_x0 = 0;
   p->toeplitz = 1;
+  p->block_norm = 1;
 }
 
 sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream) {
@@ -204,6 +229,7 @@ struct sh_sdmm_s {
   int64_t N = 0, M = 0, D = 0;     // totals over the P problems
   int R = 0, kcg = 0;
   std::vector<double> nu, gamma, delta;   // per problem
+  std::vector<double> cb;          // c_b per block (host)
   std::vector<double> eh;          // eps / nu per block (host)
   const float* Wp = nullptr;       // weights of the current pass (NULL = identity)
   int iters_total = 0;
@@ -246,7 +272,8 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   SH_TRY(w.rho.alloc(R));
   SH_TRY(w.resid.alloc(R));
   SH_TRY(w.delta.alloc(P));
-  SH_TRY(w.inv_nu.alloc(P));
+  SH_TRY(w.cblk.alloc(R));
+  SH_TRY(w.cblk2.alloc(R));
   SH_TRY(w.gamma.alloc(P));
   SH_TRY(w.red.init(P));
   double* sc = w.sc.ptr;
@@ -270,40 +297,60 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     sh::set_error("visibilities contain non-finite values");
     return SH_ENONFINITE;
   }
-  // normalisation nu per problem
+  // block weights a_b (1, or the density estimate of 1 / ||Phi_b||) and the norm nu_p of each problem's
+  // a-weighted operator; c_b = a_b / nu_p.  In Toeplitz mode the CG operator is built here, with the
+  // weights a_b^2, then rescaled by 1 / nu_p^2.
+  std::vector<double> ab(R, 1.0);
+  if (s->prm.block_norm) SH_TRY(sh::block_density_weights(op, ab, st));
+  std::vector<float> a2(R);
+  for (int i = 0; i < R; ++i) a2[i] = float(ab[i] * ab[i]);
+  SH_HIP(hipMemcpy(w.cblk2.ptr, a2.data(), R * sizeof(float), hipMemcpyHostToDevice));
   s->nu.assign(P, s->prm.nu);
-  if (!(s->prm.nu > 0)) {
-    hipLaunchKernelGGL(fill_kernel, dim3(nblk(N)), dim3(256), 0, st, w.t1.ptr, N, 1.f);
-    SH_TRY(power_norm(op, w.t1.ptr, 200, 1e-12, s->nu.data(), st));
+  const bool need_nu = !(s->prm.nu > 0);
+  if (need_nu) hipLaunchKernelGGL(fill_kernel, dim3(nblk(N)), dim3(256), 0, st, w.t1.ptr, N, 1.f);
+  if (s->prm.toeplitz) {
+    SH_TRY(sh::toeplitz_build(op, nullptr, s->prm.block_norm ? ab.data() : nullptr, &w.toep, st));
+    if (need_nu) SH_TRY(power_norm(op, w.t1.ptr, 200, 1e-6, s->nu.data(), st, nullptr, &w.toep));
+  } else if (need_nu) {
+    SH_TRY(power_norm(op, w.t1.ptr, 200, 1e-6, s->nu.data(), st, s->prm.block_norm ? w.cblk2.ptr : nullptr));
   }
-  std::vector<float> inv(P);
-  for (int p = 0; p < P; ++p) {
+  for (int p = 0; p < P; ++p)
     SH_REQUIRE(s->nu[p] > 0 && std::isfinite(s->nu[p]), "operator norm of problem %d must be positive", p);
-    inv[p] = float(1.0 / s->nu[p]);
+  if (s->prm.toeplitz) {
+    std::vector<double> f(P);
+    for (int p = 0; p < P; ++p) f[p] = 1.0 / (s->nu[p] * s->nu[p]);
+    SH_TRY(sh::toeplitz_rescale(&w.toep, f.data(), st));
   }
-  SH_HIP(hipMemcpy(w.inv_nu.ptr, inv.data(), P * sizeof(float), hipMemcpyHostToDevice));
-  if (s->prm.toeplitz) {   // the CG operator Re(Phi_hat^H Phi_hat) = Re(Phi^H Phi) / nu^2 per problem
-    std::vector<double> sc(P);
-    for (int p = 0; p < P; ++p) sc[p] = 1.0 / (s->nu[p] * s->nu[p]);
-    SH_TRY(sh::toeplitz_build(op, sc.data(), &w.toep, st));
+  s->cb.resize(R);
+  std::vector<float> cf(R), cf2(R);
+  for (int i = 0; i < R; ++i) {
+    s->cb[i] = ab[i] / s->nu[op->block_prob[i]];
+    cf[i] = float(s->cb[i]);
+    cf2[i] = float(s->cb[i] * s->cb[i]);
   }
+  SH_HIP(hipMemcpy(w.cblk.ptr, cf.data(), R * sizeof(float), hipMemcpyHostToDevice));
+  SH_HIP(hipMemcpy(w.cblk2.ptr, cf2.data(), R * sizeof(float), hipMemcpyHostToDevice));
   hipLaunchKernelGGL(gather_scale, dim3((unsigned)op->n_chunks), dim3(256), 0, st, (const float2*)y, op->perm.ptr,
-                     w.yhat.ptr, op->chunks.ptr, op->block_prob_d.ptr, w.inv_nu.ptr);
+                     w.yhat.ptr, op->chunks.ptr, w.cblk.ptr);
   SH_LAUNCHED();
   s->eh.resize(R);
-  for (int i = 0; i < R; ++i) s->eh[i] = eps[i] / s->nu[op->block_prob[i]];
+  for (int i = 0; i < R; ++i) s->eh[i] = eps[i] * s->cb[i];
   SH_HIP(hipMemcpyAsync(w.eps_hat.ptr, s->eh.data(), R * sizeof(double), hipMemcpyHostToDevice, st));
-  // gamma = 1e-4 max |Psi^dagger Phi^dagger y| / nu^2 per problem unless given (the minimiser does not
-  // depend on gamma; this step meets the stopping test within a few hundred iterations per pass)
+  // gamma = 1e-4 max |Psi^dagger Phi_hat^dagger y_hat| per problem unless given (the minimiser does not
+  // depend on gamma; this step meets the stopping test within a few hundred iterations per pass);
+  // Phi_hat^dagger y_hat = Phi^dagger (c yhat)
   s->gamma.assign(P, s->prm.gamma);
   if (!(s->prm.gamma > 0)) {
-    SH_TRY(sh::phi_adjoint(op, (const float2*)y, w.t1.ptr, true, nullptr, st));
+    hipLaunchKernelGGL(scale_chunks, dim3((unsigned)op->n_chunks), dim3(256), 0, st, w.yhat.ptr, w.vtmp.ptr,
+                       op->chunks.ptr, w.cblk.ptr);
+    SH_LAUNCHED();
+    SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.t1.ptr, false, nullptr, st));
     SH_TRY(sh_psi_adj(s->psi, w.t1.ptr, w.spsi.ptr, st));
     SH_TRY(w.red.maxabs(w.spsi.ptr, s->Dper, s_misc + MISC_TMP * P, st));
     std::vector<double> mx(P);
     SH_HIP(hipMemcpyAsync(mx.data(), s_misc + MISC_TMP * P, P * sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));
-    for (int p = 0; p < P; ++p) s->gamma[p] = 1e-4 * mx[p] / (s->nu[p] * s->nu[p]);
+    for (int p = 0; p < P; ++p) s->gamma[p] = 1e-4 * mx[p];
   }
   std::vector<float> gf(P);
   for (int p = 0; p < P; ++p) {
@@ -326,7 +373,7 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     SH_HIP(hipMemcpyAsync(w.x.ptr, x0, N * sizeof(float), hipMemcpyDeviceToDevice, st));
     SH_HIP(hipMemcpyAsync(w.vpos.ptr, x0, N * sizeof(float), hipMemcpyDeviceToDevice, st));
     SH_TRY(sh_psi_adj(s->psi, x0, w.vpsi.ptr, st));
-    SH_TRY(sh::phi_forward(op, x0, w.sphi.ptr, false, w.inv_nu.ptr, st));
+    SH_TRY(sh::phi_forward(op, x0, w.sphi.ptr, false, nullptr, st));   // the ball step applies c_b
   } else {
     SH_HIP(hipMemsetAsync(w.x.ptr, 0, N * sizeof(float), st));
     SH_HIP(hipMemsetAsync(w.vpos.ptr, 0, N * sizeof(float), st));
@@ -352,11 +399,10 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   const int64_t N = s->N, per = s->per;
   const unsigned gN = nblk(N);
   const dim3 gP(nblk(per), P);
-  const float* inv_nu = w.inv_nu.ptr;
   double *s_rs = s->s_rs, *s_pap = s->s_pap, *s_misc = s->s_misc;
   // ---- x-update by CG from x_{n-1}
   SH_TRY(sh_psi_fwd(s->psi, w.vpsi.ptr, w.t1.ptr, st));
-  SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.t2.ptr, false, inv_nu, st));
+  SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.t2.ptr, false, nullptr, st));   // vphi carries c_b
   hipLaunchKernelGGL(cg_init, dim3(gN), dim3(256), 0, st, w.t1.ptr, w.t2.ptr, w.vpos.ptr, w.x.ptr, w.r.ptr, w.p.ptr,
                      w.xprev.ptr, N);
   SH_TRY(w.red.dot(w.r.ptr, w.r.ptr, per, s_rs, st));
@@ -364,8 +410,10 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
     if (s->prm.toeplitz) {
       SH_TRY(sh::toeplitz_apply(op, w.toep.Ht.ptr, w.p.ptr, w.toep.tq.ptr, w.Ap.ptr, st));
     } else {
-      SH_TRY(sh::phi_forward(op, w.p.ptr, w.vtmp.ptr, false, inv_nu, st));
-      SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.Ap.ptr, false, inv_nu, st));
+      SH_TRY(sh::phi_forward(op, w.p.ptr, w.vtmp.ptr, false, nullptr, st));
+      hipLaunchKernelGGL(scale_chunks, dim3((unsigned)op->n_chunks), dim3(256), 0, st, w.vtmp.ptr, w.vtmp.ptr,
+                         op->chunks.ptr, w.cblk2.ptr);
+      SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.Ap.ptr, false, nullptr, st));
     }
     hipLaunchKernelGGL(cg_ap, dim3(gN), dim3(256), 0, st, w.p.ptr, w.Ap.ptr, N);
     SH_TRY(w.red.dot(w.p.ptr, w.Ap.ptr, per, s_pap + k * P, st));
@@ -384,9 +432,9 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   // ---- splits
   SH_TRY(sh_psi_adj(s->psi, w.x.ptr, w.spsi.ptr, st));
   SH_TRY(sh::launch_prox_l1(s->Dper, P, w.spsi.ptr, w.zpsi.ptr, s->Wp, w.gamma.ptr, 0.f, w.vpsi.ptr, st));
-  SH_TRY(sh::phi_forward(op, w.x.ptr, w.sphi.ptr, false, inv_nu, st));
+  SH_TRY(sh::phi_forward(op, w.x.ptr, w.sphi.ptr, false, nullptr, st));
   SH_TRY(sh::launch_prox_ball(op, w.sphi.ptr, w.zphi.ptr, w.yhat.ptr, w.eps_hat.ptr, w.rho.ptr, w.resid.ptr,
-                              w.vphi.ptr, true, st));
+                              w.vphi.ptr, true, w.cblk.ptr, st));
   SH_TRY(sh::launch_prox_pos(N, w.x.ptr, w.zpos.ptr, w.vpos.ptr, st));
   return SH_OK;
 }
@@ -506,6 +554,7 @@ sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps,
   SH_REQUIRE(prm->graph == 0 || prm->graph == 1, "graph must be 0 or 1");
   SH_REQUIRE(prm->w_from_x0 == 0 || prm->w_from_x0 == 1, "w_from_x0 must be 0 or 1");
   SH_REQUIRE(prm->toeplitz == 0 || prm->toeplitz == 1, "toeplitz must be 0 or 1");
+  SH_REQUIRE(prm->block_norm == 0 || prm->block_norm == 1, "block_norm must be 0 or 1");
   for (int i = 0; i < op->R; ++i) {
     if (!std::isfinite(eps[i])) {
       sh::set_error("eps[%d] is not finite", i);
@@ -566,7 +615,7 @@ sh_status sh_sdmm_result(sh_sdmm s, float* x_out, double* block_resid, double* r
   std::vector<double> rel, hres;
   SH_TRY(sdmm_read(s, rel, hres, st));
   if (block_resid)
-    for (int i = 0; i < s->R; ++i) block_resid[i] = hres[i] * s->nu[s->op->block_prob[i]];
+    for (int i = 0; i < s->R; ++i) block_resid[i] = hres[i] / s->cb[i];
   if (rel_change)
     for (int p = 0; p < s->P; ++p) rel_change[p] = rel[p];
   return SH_OK;
@@ -620,7 +669,7 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
                                       hipMemcpyDeviceToDevice, st));
                 taken[p] = 1;
                 rel_out[p] = rel[p];
-                for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] * s->nu[p];
+                for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] / s->cb[i];
               }
             }
           }
@@ -643,7 +692,7 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
     if (taken[p]) continue;
     SH_HIP(hipMemcpyAsync(x_out + p * per, s->w.x.ptr + p * per, per * sizeof(float), hipMemcpyDeviceToDevice, st));
     rel_out[p] = rel[p];
-    for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] * s->nu[p];
+    for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] / s->cb[i];
   }
   // objective with the last pass's weights and W_out, both from Psi^dagger of the returned images
   SH_TRY(sh_psi_adj(s->psi, x_out, s->w.spsi.ptr, st));

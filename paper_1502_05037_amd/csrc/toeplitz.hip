@@ -11,7 +11,9 @@
 //
 // The kernel is computed once per plan with the operator's own adjoint: for a shift c,
 // Re Phi^H w with w_m = exp(i u_m . c) is k(d) over the window d in [c - n/2, c + n/2)^2, and the
-// four shifts c in {-n/2, +n/2}^2 cover d in [-n, n)^2.  u_m is the plan's fixed-point coordinate
+// four shifts c in {-n/2, +n/2}^2 cover d in [-n, n)^2.  With per-block weights a_b the same steps give
+// sum_b a_b^2 Re(Phi_b^H Phi_b) (each visibility's modulated unit value carries a_b^2).  u_m is the plan's
+// fixed-point coordinate
 // (the one the interpolation uses), so the Toeplitz operator agrees with the NUFFT pair to the
 // interpolation's accuracy.  The embedded kernel is symmetric up to rounding; the real part of its
 // DFT is kept (the DFT of its symmetric part).
@@ -22,24 +24,34 @@
 
 namespace {
 
-// w_m = exp(i u_m . c) with u = 2 pi kappa / K, kappa = cell + fraction from the packed coordinate.
-// The phase is reduced mod K in float64 before the sine and cosine; since c is an integer, the
-// wrap of the cell index mod K does not change it.
-__global__ void modulate_kernel(const uint2* __restrict__ coord, float2* __restrict__ w, int64_t M, int log2K,
-                                int c1, int c2) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= M) return;
+// w_m = a_b exp(i u_m . c) with u = 2 pi kappa / K, kappa = cell + fraction from the packed coordinate,
+// a_b the weight of the visibility's block (1 without wblk); one work-group per reduction chunk (chunks
+// never straddle a block).  The phase is reduced mod K in float64 before the sine and cosine; since
+// c is an integer, the wrap of the cell index mod K does not change it.
+__global__ __launch_bounds__(256) void modulate_kernel(const uint2* __restrict__ coord, const int4* __restrict__ chunks,
+                                                       const float* __restrict__ wblk, float2* __restrict__ w,
+                                                       int log2K, int c1, int c2) {
+  const int4 ch = chunks[blockIdx.x];
+  const float a = wblk ? wblk[ch.x] : 1.0f;
   const int F = 32 - log2K;
   const uint32_t fmask = (1u << F) - 1u;
-  const uint2 q = coord[i];
-  const double k1 = double(q.x >> F) + ldexp(double(q.x & fmask), -F);
-  const double k2 = double(q.y >> F) + ldexp(double(q.y & fmask), -F);
   const double K = double(1 << log2K);
-  const double t = k1 * c1 + k2 * c2;
-  const double r = t - K * floor(t / K);
-  double s, c;
-  sincos(2.0 * M_PI * r / K, &s, &c);
-  w[i] = make_float2(float(c), float(s));
+  for (int i = ch.y + threadIdx.x; i < ch.z; i += 256) {
+    const uint2 q = coord[i];
+    const double k1 = double(q.x >> F) + ldexp(double(q.x & fmask), -F);
+    const double k2 = double(q.y >> F) + ldexp(double(q.y & fmask), -F);
+    const double t = k1 * c1 + k2 * c2;
+    const double r = t - K * floor(t / K);
+    double s, c;
+    sincos(2.0 * M_PI * r / K, &s, &c);
+    w[i] = make_float2(a * float(c), a * float(s));
+  }
+}
+
+// Ht[p] *= f[p]
+__global__ void scale_spectrum(float* __restrict__ Ht, int64_t KK, const float* __restrict__ f) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < KK) Ht[(size_t)blockIdx.y * KK + j] *= f[blockIdx.y];
 }
 
 // Window pixel (r, c) holds k(r + o1, c + o2); it goes to C[(r + o1) mod K][(c + o2) mod K].
@@ -71,7 +83,7 @@ __global__ void spectrum_transpose(const float2* __restrict__ spec, float* __res
 
 namespace sh {
 
-sh_status toeplitz_build(sh_op op, const double* scale, sh_toep_s* t, hipStream_t st) {
+sh_status toeplitz_build(sh_op op, const double* scale, const double* wblk, sh_toep_s* t, hipStream_t st) {
   const int n = op->n, K = op->K, P = op->P;
   SH_REQUIRE(K >= 2 * n, "the Toeplitz embedding needs a grid side K >= 2n (K = %d, n = %d)", K, n);
   const int64_t M = op->M, nn = (int64_t)n * n, KK = (int64_t)K * K;
@@ -82,7 +94,15 @@ sh_status toeplitz_build(sh_op op, const double* scale, sh_toep_s* t, hipStream_
     sc[p] = float(v / (double(K) * double(K)));
   }
   sh::DevBuf<float2> w, C, tmp;
-  sh::DevBuf<float> win, scd;
+  sh::DevBuf<float> win, scd, wb;
+  if (wblk) {   // a visibility of block b carries wblk[b]^2: the modulated vector and the adjoint's weight
+    std::vector<float> a(op->R);
+    for (int i = 0; i < op->R; ++i) {
+      SH_REQUIRE(std::isfinite(wblk[i]) && wblk[i] > 0, "block weight %d must be positive and finite", i);
+      a[i] = float(wblk[i] * wblk[i]);
+    }
+    SH_TRY(wb.upload(a));
+  }
   SH_TRY(w.alloc(M));
   SH_TRY(win.alloc(P * nn));
   SH_TRY(C.alloc(P * KK));
@@ -95,8 +115,8 @@ sh_status toeplitz_build(sh_op op, const double* scale, sh_toep_s* t, hipStream_
   for (int s1 = 0; s1 < 2; ++s1)
     for (int s2 = 0; s2 < 2; ++s2) {
       const int c1 = s1 ? n / 2 : -n / 2, c2 = s2 ? n / 2 : -n / 2;
-      hipLaunchKernelGGL(modulate_kernel, dim3((unsigned)cdiv(M, 256)), dim3(256), 0, st, op->coord.ptr, w.ptr, M,
-                         op->log2K, c1, c2);
+      hipLaunchKernelGGL(modulate_kernel, dim3((unsigned)op->n_chunks), dim3(256), 0, st, op->coord.ptr,
+                         op->chunks.ptr, wblk ? wb.ptr : nullptr, w.ptr, op->log2K, c1, c2);
       SH_LAUNCHED();
       SH_TRY(phi_adjoint(op, w.ptr, win.ptr, false, nullptr, st));
       hipLaunchKernelGGL(place_window, dim3((unsigned)cdiv(nn, 256), P), dim3(256), 0, st, win.ptr, C.ptr, n,
@@ -113,6 +133,20 @@ sh_status toeplitz_build(sh_op op, const double* scale, sh_toep_s* t, hipStream_
   return SH_OK;
 }
 
+sh_status toeplitz_rescale(sh_toep_s* t, const double* factor, hipStream_t st) {
+  sh_op op = t->op;
+  const int P = op->P;
+  const int64_t KK = int64_t(op->K) * op->K;
+  std::vector<float> f(P);
+  for (int p = 0; p < P; ++p) f[p] = float(factor[p]);
+  sh::DevBuf<float> fd;
+  SH_TRY(fd.upload(f));
+  hipLaunchKernelGGL(scale_spectrum, dim3((unsigned)cdiv(KK, 256), P), dim3(256), 0, st, t->Ht.ptr, KK, fd.ptr);
+  SH_LAUNCHED();
+  SH_HIP(hipStreamSynchronize(st));   // fd is freed on return
+  return SH_OK;
+}
+
 }  // namespace sh
 
 extern "C" {
@@ -121,7 +155,7 @@ sh_status sh_toeplitz_create(sh_op op, const double* scale, sh_toep* out, void* 
   SH_REQUIRE(op && out, "op and out must be non-NULL");
   *out = nullptr;
   auto t = std::make_unique<sh_toep_s>();
-  SH_TRY(sh::toeplitz_build(op, scale, t.get(), (hipStream_t)stream));
+  SH_TRY(sh::toeplitz_build(op, scale, nullptr, t.get(), (hipStream_t)stream));
   *out = t.release();
   return SH_OK;
 }

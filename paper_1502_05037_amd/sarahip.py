@@ -40,7 +40,7 @@ class SdmmParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("nu", C.c_double), ("tol_rel", C.c_double), ("eps_slack", C.c_double),
                 ("rw_beta", C.c_double), ("rw_delta0", C.c_double), ("max_iter", C.c_int32),
                 ("cg_iters", C.c_int32), ("passes", C.c_int32), ("check_every", C.c_int32), ("graph", C.c_int32),
-                ("w_from_x0", C.c_int32), ("toeplitz", C.c_int32)]
+                ("w_from_x0", C.c_int32), ("toeplitz", C.c_int32), ("block_norm", C.c_int32)]
 
 
 class SdmmInfo(C.Structure):
@@ -85,6 +85,7 @@ _SIGS = {
     "sh_vis_to_internal": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sh_vis_to_user": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sh_op_norm": (C.c_int, [_vp, _vp, _i32, _f64, _P64, _vp]),
+    "sh_block_weights": (C.c_int, [_vp, _P64, _vp]),
     "sh_toeplitz_create": (C.c_int, [_vp, _P64, C.POINTER(_vp), _vp]),
     "sh_toeplitz_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sh_toeplitz_destroy": (C.c_int, [_vp]),
@@ -273,6 +274,13 @@ def vis_to_internal(op, user, internal, stream=None):
 
 def vis_to_user(op, internal, user, stream=None):
     _check(lib.sh_vis_to_user(op, _ptr(internal), _ptr(user), _stream(stream)), "vis_to_user")
+
+
+def block_weights(op, stream=None) -> np.ndarray:
+    """Density estimate of 1 / ||Phi_b|| per block (float64, R values)."""
+    b = np.zeros(op_query(op)["R"], dtype=np.float64)
+    _check(lib.sh_block_weights(op, b.ctypes.data_as(_P64), _stream(stream)), "block_weights")
+    return b
 
 
 def toeplitz_create(op, scale=None, stream=None):

@@ -153,18 +153,21 @@ def _batched_solve(sh, pbs, prm, levels=4, want_W=False):
 
 
 def test_batched_sdmm_fixed_schedule_matches_oracle(sh):
-    """Three reweighted passes of every problem at its own nu and gamma (resolved by the library)
-    against the oracle run at the nu and gamma the library reports."""
+    """Three reweighted passes of every problem at its own block weights, nu and gamma (resolved by the
+    library) against the oracle run at the nu and gamma the library reports."""
     pbs = _problems(shapes=SHAPES[:4])
     x, infos, resid, Wo = _batched_solve(sh, pbs, _params(sh, max_iter=40, cg_iters=8, passes=3), want_W=True)
     base = 0
     for p, pb in enumerate(pbs):
         psi = wavelets.SARA(pb.n, 4, 0x1FF)
-        nu_ref = measurement.op_norm(pb.op, np.ones((pb.n, pb.n)), max_iter=200, tol=1e-12)
-        gamma_ref = sdmm.default_gamma(pb.op, psi, pb.y, nu_ref)
+        a = measurement.block_density_weights(pb.uv, pb.n, 2, pb.offsets)
+        nu_ref = measurement.op_norm(measurement.BlockWeighted(pb.op, pb.offsets, a), np.ones((pb.n, pb.n)),
+                                     max_iter=200, tol=1e-12)
+        gamma_ref = sdmm.default_gamma(pb.op, psi, pb.y, nu_ref, offsets=pb.offsets, block_weights=a)
         assert infos[p]["nu"] == pytest.approx(nu_ref, rel=1e-4)
         assert infos[p]["gamma"] == pytest.approx(gamma_ref, rel=1e-4)
-        prm = sdmm.Params(gamma=infos[p]["gamma"], nu=infos[p]["nu"], max_iter=40, cg_iters=8, passes=3)
+        prm = sdmm.Params(gamma=infos[p]["gamma"], nu=infos[p]["nu"], max_iter=40, cg_iters=8, passes=3,
+                          block_weights=a)
         x_ref, _, oinfos, _ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, prm)
         err = helpers.rel(x[p], x_ref)
         print(f"problem {p}: image error vs oracle {err:.3e}")

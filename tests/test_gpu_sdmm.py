@@ -48,19 +48,25 @@ def _params(sh, **kw):
     return p
 
 
-def _oracle_setup(pb, levels=4, mask=0x1FF):
+def _oracle_setup(pb, levels=4, mask=0x1FF, block_norm=True):
+    """The oracle's normalisation: block weights (the library's default) or one per problem, the norm of
+    the weighted operator and the default gamma."""
     psi = wavelets.SARA(pb.n, levels, mask)
-    nu = measurement.op_norm(pb.op, np.ones((pb.n, pb.n)), max_iter=200, tol=1e-12)
-    gamma = sdmm.default_gamma(pb.op, psi, pb.y, nu)
-    return psi, nu, gamma
+    a = measurement.block_density_weights(pb.uv, pb.n, 2, pb.offsets) if block_norm else None
+    A = pb.op if a is None else measurement.BlockWeighted(pb.op, pb.offsets, a)
+    nu = measurement.op_norm(A, np.ones((pb.n, pb.n)), max_iter=200, tol=1e-12)
+    gamma = sdmm.default_gamma(pb.op, psi, pb.y, nu, offsets=pb.offsets, block_weights=a)
+    return psi, nu, gamma, a
 
 
-def test_config1_fixed_schedule_parity(sh):
+@pytest.mark.parametrize("block_norm", [1, 0])
+def test_config1_fixed_schedule_parity(sh, block_norm):
     pb = helpers.build(1, 64, 2048, 1, 6)
-    psi, nu, gamma = _oracle_setup(pb)
-    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=300, cg_iters=8)
+    psi, nu, gamma, a = _oracle_setup(pb, block_norm=bool(block_norm))
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=300, cg_iters=8, block_weights=a)
     x_ref, _, infos, _ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
-    x, info, resid, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=300, cg_iters=8))
+    x, info, resid, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=300, cg_iters=8,
+                                                   block_norm=block_norm))
     assert info["iters_total"] == 300
     err = helpers.rel(x, x_ref)
     print(f"config-1 image error vs oracle: {err:.3e}")
@@ -71,8 +77,8 @@ def test_config1_fixed_schedule_parity(sh):
 
 def test_reweighted_passes_parity_and_weights(sh):
     pb = helpers.build(2, 32, 1200, 3, 6, coverage="radial", prob=1)
-    psi, nu, gamma = _oracle_setup(pb)
-    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=3)
+    psi, nu, gamma, a = _oracle_setup(pb)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=3, block_weights=a)
     x_ref, W_last, infos, st = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
     x, info, resid, Wo = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=3),
                                     want_W=True)
@@ -80,7 +86,7 @@ def test_reweighted_passes_parity_and_weights(sh):
     assert helpers.rel(x, x_ref) <= 1e-4
     # W_out: the weights a fourth pass would use: delta_3 = beta^2 delta_1 from the final image
     c1 = psi.adj(sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps,
-                           sdmm.Params(gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=1))[0])
+                           sdmm.Params(gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=1, block_weights=a))[0])
     delta = 0.25 * np.std(c1)
     assert info["delta"] == pytest.approx(delta, rel=1e-4)
     W_ref = sdmm.reweight(psi.adj(x_ref), delta)
@@ -89,9 +95,9 @@ def test_reweighted_passes_parity_and_weights(sh):
 
 def test_warm_start_parity(sh):
     pb = helpers.build(3, 32, 900, 2, 8, prob=2)
-    psi, nu, gamma = _oracle_setup(pb)
+    psi, nu, gamma, a = _oracle_setup(pb)
     x0 = 0.9 * pb.x_true
-    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=60, cg_iters=8)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=60, cg_iters=8, block_weights=a)
     x_ref, *_ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p, x0=x0)
     x, info, _, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=60, cg_iters=8), x0=x0)
     assert helpers.rel(x, x_ref) <= 1e-4
@@ -173,8 +179,8 @@ def test_default_two_cg_steps_parity(sh):
     """The library's default x-update (two warm-started CG steps) against the oracle run with the same
     two steps, over three reweighted passes."""
     pb = helpers.build(7, 64, 3000, 3, 6, coverage="radial", prob=5)
-    psi, nu, gamma = _oracle_setup(pb)
-    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=80, cg_iters=2, passes=3)
+    psi, nu, gamma, a = _oracle_setup(pb)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=80, cg_iters=2, passes=3, block_weights=a)
     x_ref, *_ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
     prm = _params(sh, gamma=gamma, nu=nu, max_iter=80, passes=3)
     assert prm.cg_iters == 2
@@ -188,9 +194,9 @@ def test_cg_operator_forms_match_oracle(sh, toeplitz):
     Re(Phi_hat^H Phi_hat) (1), against the oracle (whose CG applies its FP64 NUFFT pair), with eight
     and with the default two CG steps."""
     pb = helpers.build(1, 64, 2048, 1, 6)
-    psi, nu, gamma = _oracle_setup(pb)
+    psi, nu, gamma, a = _oracle_setup(pb)
     for kcg in (8, 2):
-        p = sdmm.Params(gamma=gamma, nu=nu, max_iter=300, cg_iters=kcg)
+        p = sdmm.Params(gamma=gamma, nu=nu, max_iter=300, cg_iters=kcg, block_weights=a)
         x_ref, _, infos, _ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
         x, info, resid, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=300, cg_iters=kcg,
                                                        toeplitz=toeplitz))
