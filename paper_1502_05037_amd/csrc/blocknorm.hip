@@ -32,18 +32,21 @@ __global__ __launch_bounds__(256) void count_cells(const uint2* __restrict__ coo
   }
 }
 
-// mx[g0 + b] = max over cells (r, c) of the alpha x alpha window sum starting at (r, c), periodic
+// mx[g0 + b] = max over cells (r, c) of the alpha x alpha window sum starting at (r, c), periodic; each
+// work-group strides over the cells of block b = g0 + blockIdx.y, then one atomic max per work-group
 __global__ __launch_bounds__(256) void window_max(const uint32_t* __restrict__ counts, int log2K, int alpha, int g0,
                                                   uint32_t* __restrict__ mx) {
   __shared__ uint32_t red[256];
   const int K = 1 << log2K, m = K - 1;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t KK = int64_t(1) << (2 * log2K);
   const uint32_t* h = counts + ((size_t)blockIdx.y << (2 * log2K));
   uint32_t s = 0;
-  if (j < (int64_t(1) << (2 * log2K))) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < KK; j += (int64_t)gridDim.x * 256) {
     const int r = int(j >> log2K), c = int(j & m);
+    uint32_t w = 0;
     for (int a = 0; a < alpha; ++a)
-      for (int d = 0; d < alpha; ++d) s += h[((size_t)((r + a) & m) << log2K) | ((c + d) & m)];
+      for (int d = 0; d < alpha; ++d) w += h[((size_t)((r + a) & m) << log2K) | ((c + d) & m)];
+    s = max(s, w);
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -76,8 +79,8 @@ sh_status block_density_weights(sh_op op, std::vector<double>& b, hipStream_t st
                          op->log2K, counts.ptr);
       SH_LAUNCHED();
     }
-    hipLaunchKernelGGL(window_max, dim3((unsigned)cdiv(KK, 256), unsigned(g1 - g0)), dim3(256), 0, st, counts.ptr,
-                       op->log2K, op->alpha, g0, mx.ptr);
+    hipLaunchKernelGGL(window_max, dim3((unsigned)std::min<int64_t>(cdiv(KK, 256), 256), unsigned(g1 - g0)), dim3(256),
+                       0, st, counts.ptr, op->log2K, op->alpha, g0, mx.ptr);
     SH_LAUNCHED();
   }
   std::vector<uint32_t> h(R);

@@ -39,11 +39,25 @@ constexpr int BALL_CHUNK = 8192;   // visibilities per reduction chunk
 constexpr int RUN_MIN = 6;         // mean visibilities per cell of a dense work item
 constexpr int DEGRID_STAGE = 4096; // outputs a dense degridding work-group stages in LDS (= default chunk)
 
-__device__ __forceinline__ float kb_eval(const float* c, float s) {
-  float acc = c[KB_DEG];
+// All J tap weights at s = 2f - 1.  Tap J-1-t at f is tap t at 1 - f (the window is even), and the tap
+// polynomials are tabulated with that symmetry, so the pair shares its even and odd parts in s:
+// w_t = E(s^2) + s O(s^2), w_(J-1-t) = E(s^2) - s O(s^2) (KB_DEG odd; 2 (KB_DEG - 1) + 2 FMA per pair).
+template <int J>
+__device__ __forceinline__ void kb_weights(const KBCoef& kc, float s, float* w) {
+  static_assert(KB_DEG % 2 == 1, "odd polynomial degree");
+  const float u = s * s;
 #pragma unroll
-  for (int i = KB_DEG - 1; i >= 0; --i) acc = fmaf(acc, s, c[i]);
-  return acc;
+  for (int t = 0; t < J / 2; ++t) {
+    const float* c = kc.c[t];
+    float e = c[KB_DEG - 1], o = c[KB_DEG];
+#pragma unroll
+    for (int i = KB_DEG - 3; i >= 0; i -= 2) {
+      e = fmaf(e, u, c[i]);
+      o = fmaf(o, u, c[i + 1]);
+    }
+    w[t] = fmaf(s, o, e);
+    w[J - 1 - t] = fmaf(-s, o, e);
+  }
 }
 
 // Orders this lane's LDS accesses around a point where lanes of one wave hand data to each other
@@ -67,19 +81,21 @@ __device__ __forceinline__ void item_range(const int4& it, int tid, int& lo, int
 template <int J, int T, bool RUNS>
 __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ grid,
                                                      float2* __restrict__ out, const uint32_t* __restrict__ oidx,
-                                                     const int4* __restrict__ items, int log2K, int log2T,
+                                                     const int4* __restrict__ items,
+                                                     const int32_t* __restrict__ item_block, int log2K, int log2T,
                                                      const float* __restrict__ scales, KBCoef kc) {
   constexpr int P = T + J - 1;
   constexpr int LO = J / 2 - 1;
   __shared__ float2 patch[P * P];
   const int tid = threadIdx.x;
-  const int4 it = items[xcd_block_runs(blockIdx.x, gridDim.x, 16)];
+  const int itx = xcd_block_runs(blockIdx.x, gridDim.x, 16);
+  const int4 it = items[itx];
   const int nT = 1 << (log2K - log2T);
   const int kmask = (1 << log2K) - 1;
   const int prob = it.x >> (2 * (log2K - log2T)), tloc = it.x & ((1 << (2 * (log2K - log2T))) - 1);
   const int a0 = (tloc / nT) * T, b0 = (tloc % nT) * T;
   grid += (size_t)prob << (2 * log2K);
-  const float scale = scales ? scales[prob] : 1.f;
+  const float scale = scales ? scales[item_block[itx]] : 1.f;
   for (int e = tid; e < P * P; e += 256) {
     const int p1 = e / P, p2 = e - p1 * P;
     patch[e] = grid[(size_t)((a0 - LO + p1) & kmask) * (kmask + 1) + ((b0 - LO + p2) & kmask)];
@@ -109,9 +125,9 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
     const int lr = int(c.x >> F) - a0, lc = int(c.y >> F) - b0;
     const float s1 = float(c.x & fmask) * fs - 1.0f;
     const float s2 = float(c.y & fmask) * fs - 1.0f;
-    float w2[J];
-#pragma unroll
-    for (int t = 0; t < J; ++t) w2[t] = kb_eval(kc.c[t], s2);
+    float w1[J], w2[J];
+    kb_weights<J>(kc, s1, w1);
+    kb_weights<J>(kc, s2, w2);
     float ar = 0.f, ai = 0.f;
     if constexpr (RUNS) {
       const int cell = lr * T + lc;
@@ -130,9 +146,8 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
           rr = fmaf(w2[t2], cache[t1][t2].x, rr);
           ri = fmaf(w2[t2], cache[t1][t2].y, ri);
         }
-        const float w1 = kb_eval(kc.c[t1], s1);
-        ar = fmaf(w1, rr, ar);
-        ai = fmaf(w1, ri, ai);
+        ar = fmaf(w1[t1], rr, ar);
+        ai = fmaf(w1[t1], ri, ai);
       }
     } else {
 #pragma unroll
@@ -145,9 +160,8 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
           rr = fmaf(w2[t2], g.x, rr);
           ri = fmaf(w2[t2], g.y, ri);
         }
-        const float w1 = kb_eval(kc.c[t1], s1);
-        ar = fmaf(w1, rr, ar);
-        ai = fmaf(w1, ri, ai);
+        ar = fmaf(w1[t1], rr, ar);
+        ai = fmaf(w1[t1], ri, ai);
       }
     }
     const float2 r = make_float2(ar * scale, ai * scale);
@@ -175,8 +189,8 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
 template <int J, int T>
 __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ vis,
                                                    const uint32_t* __restrict__ vidx, const int4* __restrict__ items,
-                                                   float2* __restrict__ patches, int log2K, int log2T,
-                                                   const float* __restrict__ scales, KBCoef kc) {
+                                                   const int32_t* __restrict__ item_block, float2* __restrict__ patches,
+                                                   int log2K, int log2T, const float* __restrict__ scales, KBCoef kc) {
   constexpr int P = T + J - 1;
   constexpr int PP = P * P;
   constexpr int NQ = (J * J + 63) / 64;   // taps per lane
@@ -191,11 +205,12 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   for (int e = tid; e < 4 * PP; e += 256) (&pat[0][0])[e] = make_float2(0.f, 0.f);
   __syncthreads();
-  const int4 it = items[xcd_block_runs(blockIdx.x, gridDim.x, 16)];
+  const int itx = xcd_block_runs(blockIdx.x, gridDim.x, 16);
+  const int4 it = items[itx];
   const int nT = 1 << (log2K - log2T);
   const int prob = it.x >> (2 * (log2K - log2T)), tloc = it.x & ((1 << (2 * (log2K - log2T))) - 1);
   const int a0 = (tloc / nT) * T, b0 = (tloc % nT) * T;
-  const float scale = scales ? scales[prob] : 1.f;
+  const float scale = scales ? scales[item_block[itx]] : 1.f;
   const int F = 32 - log2K;
   const uint32_t fmask = (F == 32) ? 0xffffffffu : ((1u << F) - 1u);
   const float fs = ldexpf(1.0f, 1 - F);
@@ -233,11 +248,13 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
       const float s1 = float(c.x & fmask) * fs - 1.0f;
       const float s2 = float(c.y & fmask) * fs - 1.0f;
       const float vr = v.x * scale, vi = v.y * scale;
+      float w1[J], w2[J];
+      kb_weights<J>(kc, s1, w1);
+      kb_weights<J>(kc, s2, w2);
 #pragma unroll
       for (int t = 0; t < J; ++t) {
-        const float w1 = kb_eval(kc.c[t], s1);
-        aw[wave][t][lane] = make_float2(w1 * vr, w1 * vi);
-        bw[wave][t][lane] = kb_eval(kc.c[t], s2);
+        aw[wave][t][lane] = make_float2(w1[t] * vr, w1[t] * vi);
+        bw[wave][t][lane] = w2[t];
       }
       cell = lr * P + lc;
     }
@@ -387,10 +404,11 @@ template <int J, int T>
 sh_status launch_degrid_T(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, const float* scales, hipStream_t st) {
   if (op->n_sparse)
     hipLaunchKernelGGL((degrid_kernel<J, T, false>), dim3((unsigned)op->n_sparse), dim3(256), 0, st, op->coord.ptr,
-                       grid, out, oidx, op->items.ptr, op->log2K, op->log2T, scales, op->kb);
+                       grid, out, oidx, op->items.ptr, op->item_block.ptr, op->log2K, op->log2T, scales, op->kb);
   if (op->n_items > op->n_sparse)
     hipLaunchKernelGGL((degrid_kernel<J, T, true>), dim3((unsigned)(op->n_items - op->n_sparse)), dim3(256), 0, st,
-                       op->coord.ptr, grid, out, oidx, op->items.ptr + op->n_sparse, op->log2K, op->log2T, scales,
+                       op->coord.ptr, grid, out, oidx, op->items.ptr + op->n_sparse,
+                       op->item_block.ptr + op->n_sparse, op->log2K, op->log2T, scales,
                        op->kb);
   SH_LAUNCHED();
   return SH_OK;
@@ -412,7 +430,7 @@ sh_status launch_grid_T(sh_op op, const float2* vis, const uint32_t* vidx, const
   {
     sh::ProfScope ps("grid", st);
     hipLaunchKernelGGL((grid_kernel<J, T>), dim3((unsigned)op->n_items), dim3(256), 0, st, op->coord.ptr, vis, vidx,
-                       op->items.ptr, op->patches.ptr, op->log2K, op->log2T, scales, op->kb);
+                       op->items.ptr, op->item_block.ptr, op->patches.ptr, op->log2K, op->log2T, scales, op->kb);
     SH_LAUNCHED();
   }
   sh::ProfScope ps("fold", st);
@@ -515,7 +533,7 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   // slot range.
   const int ntiles = nT * nT;
   const int gtiles = op->P * ntiles;
-  struct Item { int tile, start, count, dense; };
+  struct Item { int tile, start, count, dense, block; };
   std::vector<Item> all;
   for (int64_t i = 0; i < M;) {
     const uint32_t k0 = key[perm[i]] >> (2 * log2T);
@@ -529,7 +547,7 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
       const int64_t a = i + c * k / nck, bb = i + c * (k + 1) / nck;
       int64_t cells = 0;
       for (int64_t q = a; q < bb; ++q) cells += (q == a || key[perm[q]] != key[perm[q - 1]]);
-      all.push_back({gt, (int)a, (int)(bb - a), (bb - a) >= RUN_MIN * cells ? 1 : 0});
+      all.push_back({gt, (int)a, (int)(bb - a), (bb - a) >= RUN_MIN * cells ? 1 : 0, b});
     }
     i = e;
   }
@@ -543,9 +561,13 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   }
   for (int t = 0; t < gtiles; ++t) tile_items[t + 1] = tile_items[t] + per_tile[t];
   std::vector<int4> items;
+  std::vector<int32_t> item_block;
   for (int pass = 0; pass < 2; ++pass)
     for (size_t q = 0; q < all.size(); ++q)
-      if (all[q].dense == pass) items.push_back(make_int4(all[q].tile, all[q].start, all[q].count, slot_of[q]));
+      if (all[q].dense == pass) {
+        items.push_back(make_int4(all[q].tile, all[q].start, all[q].count, slot_of[q]));
+        item_block.push_back(all[q].block);
+      }
   op->n_items = (int64_t)items.size();
   op->n_sparse = 0;
   for (auto& a : all) op->n_sparse += a.dense == 0;
@@ -564,6 +586,7 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   SH_TRY(op->coord.upload(ci));
   SH_TRY(op->perm.upload(perm));
   SH_TRY(op->items.upload(items));
+  SH_TRY(op->item_block.upload(item_block));
   SH_TRY(op->tile_items.upload(tile_items));
   SH_TRY(op->chunks.upload(chunks));
   SH_TRY(op->chunk_first_d.upload(op->chunk_first));

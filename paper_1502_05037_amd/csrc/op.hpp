@@ -27,6 +27,7 @@ struct sh_op_s {
   sh::DevBuf<uint32_t> perm;       // internal index -> user index
   sh::DevBuf<int4> items;          // work items (tile, start, count, patch slot): sparse first, then dense
   // (start/count index internal order)
+  sh::DevBuf<int32_t> item_block;  // data block of each work item (order of `items`)
   sh::DevBuf<int32_t> tile_items;  // CSR over global tiles (problem * nT^2 + tile): patch slots of each tile
   int64_t n_items = 0, n_sparse = 0;
   int max_items_per_tile = 0;
@@ -49,7 +50,7 @@ struct sh_op_s {
 namespace sh {
 
 // Phi / Phi^dagger on internal-order (or user-order, via the permutation) visibilities of all P
-// problems; x holds P images.  Problem p's visibilities are scaled by scales[p] (device, NULL = 1).
+// problems; x holds P images.  Block b's visibilities are scaled by scales[b] (device R floats, NULL = 1).
 sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, const float* scales, hipStream_t st);
 sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, const float* scales, hipStream_t st);
 

@@ -69,17 +69,6 @@ __global__ __launch_bounds__(256) void gather_scale(const float2* __restrict__ s
   }
 }
 
-// dst = w_b src over the chunks of block b (dst may equal src)
-__global__ __launch_bounds__(256) void scale_chunks(const float2* src, float2* dst, const int4* __restrict__ chunks,
-                                                    const float* __restrict__ w) {
-  const int4 c = chunks[blockIdx.x];
-  const float s = w[c.x];
-  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
-    const float2 v = src[i];
-    dst[i] = make_float2(v.x * s, v.y * s);
-  }
-}
-
 // r = a + b + c - 2x; p = r; xprev = x
 __global__ void cg_init(const float* __restrict__ a, const float* __restrict__ b, const float* __restrict__ c,
                         const float* __restrict__ x, float* __restrict__ r, float* __restrict__ p,
@@ -132,17 +121,17 @@ struct Work {
   sh::DevBuf<float> spsi, zpsi, vpsi, W;
   sh::DevBuf<float2> yhat, sphi, zphi, vphi, vtmp;
   sh::DevBuf<double> sc, eps_hat, rho, resid, delta;
-  sh::DevBuf<float> cblk, cblk2, gamma;   // c_b and c_b^2 per block, gamma per problem
+  sh::DevBuf<float> cblk, gamma;   // c_b per block, gamma per problem
   sh::Reducer red;
   sh_toep_s toep;                  // Re(Phi_hat^H Phi_hat) as a convolution (option toeplitz)
 };
 
 // Power iteration on Re(Phi^H Phi) (scale 1) from x0, for the P problems of the plan at once (each
 // normalised and tested on its own); nu[p] = sqrt of problem p's Rayleigh quotient.  Stops when
-// every problem's estimate changed by <= tol relative, or after `iters` steps.  With w2blk (device,
-// per block) the operator is sum_b w2_b Re(Phi_b^H Phi_b); with toep it is that Toeplitz operator.
+// every problem's estimate changed by <= tol relative, or after `iters` steps.  With wblk (device,
+// per block) the operator is sum_b wblk_b^2 Re(Phi_b^H Phi_b); with toep it is that Toeplitz operator.
 sh_status power_norm(sh_op op, const float* x0, int iters, double tol, double* nu, hipStream_t st,
-                     const float* w2blk = nullptr, const sh_toep_s* toep = nullptr) {
+                     const float* wblk = nullptr, const sh_toep_s* toep = nullptr) {
   const int P = op->P;
   const int64_t per = int64_t(op->n) * op->n, N = per * P;
   sh::DevBuf<float> x, y;
@@ -161,13 +150,8 @@ sh_status power_norm(sh_op op, const float* x0, int iters, double tol, double* n
     if (toep) {
       SH_TRY(sh::toeplitz_apply(op, toep->Ht.ptr, x.ptr, toep->tq.ptr, y.ptr, st));
     } else {
-      SH_TRY(sh::phi_forward(op, x.ptr, v.ptr, false, nullptr, st));
-      if (w2blk) {
-        hipLaunchKernelGGL(scale_chunks, dim3((unsigned)op->n_chunks), dim3(256), 0, st, v.ptr, v.ptr, op->chunks.ptr,
-                           w2blk);
-        SH_LAUNCHED();
-      }
-      SH_TRY(sh::phi_adjoint(op, v.ptr, y.ptr, false, nullptr, st));
+      SH_TRY(sh::phi_forward(op, x.ptr, v.ptr, false, wblk, st));
+      SH_TRY(sh::phi_adjoint(op, v.ptr, y.ptr, false, wblk, st));
     }
     SH_TRY(red.dot(x.ptr, y.ptr, per, sc.ptr + P, st));
     SH_TRY(red.dot(y.ptr, y.ptr, per, sc.ptr + 2 * P, st));
@@ -273,7 +257,6 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   SH_TRY(w.resid.alloc(R));
   SH_TRY(w.delta.alloc(P));
   SH_TRY(w.cblk.alloc(R));
-  SH_TRY(w.cblk2.alloc(R));
   SH_TRY(w.gamma.alloc(P));
   SH_TRY(w.red.init(P));
   double* sc = w.sc.ptr;
@@ -302,9 +285,9 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   // weights a_b^2, then rescaled by 1 / nu_p^2.
   std::vector<double> ab(R, 1.0);
   if (s->prm.block_norm) SH_TRY(sh::block_density_weights(op, ab, st));
-  std::vector<float> a2(R);
-  for (int i = 0; i < R; ++i) a2[i] = float(ab[i] * ab[i]);
-  SH_HIP(hipMemcpy(w.cblk2.ptr, a2.data(), R * sizeof(float), hipMemcpyHostToDevice));
+  std::vector<float> af(R);
+  for (int i = 0; i < R; ++i) af[i] = float(ab[i]);
+  SH_HIP(hipMemcpy(w.cblk.ptr, af.data(), R * sizeof(float), hipMemcpyHostToDevice));   // a_b until c_b is known
   s->nu.assign(P, s->prm.nu);
   const bool need_nu = !(s->prm.nu > 0);
   if (need_nu) hipLaunchKernelGGL(fill_kernel, dim3(nblk(N)), dim3(256), 0, st, w.t1.ptr, N, 1.f);
@@ -312,7 +295,7 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     SH_TRY(sh::toeplitz_build(op, nullptr, s->prm.block_norm ? ab.data() : nullptr, &w.toep, st));
     if (need_nu) SH_TRY(power_norm(op, w.t1.ptr, 200, 1e-6, s->nu.data(), st, nullptr, &w.toep));
   } else if (need_nu) {
-    SH_TRY(power_norm(op, w.t1.ptr, 200, 1e-6, s->nu.data(), st, s->prm.block_norm ? w.cblk2.ptr : nullptr));
+    SH_TRY(power_norm(op, w.t1.ptr, 200, 1e-6, s->nu.data(), st, s->prm.block_norm ? w.cblk.ptr : nullptr));
   }
   for (int p = 0; p < P; ++p)
     SH_REQUIRE(s->nu[p] > 0 && std::isfinite(s->nu[p]), "operator norm of problem %d must be positive", p);
@@ -322,14 +305,12 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     SH_TRY(sh::toeplitz_rescale(&w.toep, f.data(), st));
   }
   s->cb.resize(R);
-  std::vector<float> cf(R), cf2(R);
+  std::vector<float> cf(R);
   for (int i = 0; i < R; ++i) {
     s->cb[i] = ab[i] / s->nu[op->block_prob[i]];
     cf[i] = float(s->cb[i]);
-    cf2[i] = float(s->cb[i] * s->cb[i]);
   }
   SH_HIP(hipMemcpy(w.cblk.ptr, cf.data(), R * sizeof(float), hipMemcpyHostToDevice));
-  SH_HIP(hipMemcpy(w.cblk2.ptr, cf2.data(), R * sizeof(float), hipMemcpyHostToDevice));
   hipLaunchKernelGGL(gather_scale, dim3((unsigned)op->n_chunks), dim3(256), 0, st, (const float2*)y, op->perm.ptr,
                      w.yhat.ptr, op->chunks.ptr, w.cblk.ptr);
   SH_LAUNCHED();
@@ -341,10 +322,7 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   // Phi_hat^dagger y_hat = Phi^dagger (c yhat)
   s->gamma.assign(P, s->prm.gamma);
   if (!(s->prm.gamma > 0)) {
-    hipLaunchKernelGGL(scale_chunks, dim3((unsigned)op->n_chunks), dim3(256), 0, st, w.yhat.ptr, w.vtmp.ptr,
-                       op->chunks.ptr, w.cblk.ptr);
-    SH_LAUNCHED();
-    SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.t1.ptr, false, nullptr, st));
+    SH_TRY(sh::phi_adjoint(op, w.yhat.ptr, w.t1.ptr, false, w.cblk.ptr, st));
     SH_TRY(sh_psi_adj(s->psi, w.t1.ptr, w.spsi.ptr, st));
     SH_TRY(w.red.maxabs(w.spsi.ptr, s->Dper, s_misc + MISC_TMP * P, st));
     std::vector<double> mx(P);
@@ -410,10 +388,8 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
     if (s->prm.toeplitz) {
       SH_TRY(sh::toeplitz_apply(op, w.toep.Ht.ptr, w.p.ptr, w.toep.tq.ptr, w.Ap.ptr, st));
     } else {
-      SH_TRY(sh::phi_forward(op, w.p.ptr, w.vtmp.ptr, false, nullptr, st));
-      hipLaunchKernelGGL(scale_chunks, dim3((unsigned)op->n_chunks), dim3(256), 0, st, w.vtmp.ptr, w.vtmp.ptr,
-                         op->chunks.ptr, w.cblk2.ptr);
-      SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.Ap.ptr, false, nullptr, st));
+      SH_TRY(sh::phi_forward(op, w.p.ptr, w.vtmp.ptr, false, w.cblk.ptr, st));
+      SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.Ap.ptr, false, w.cblk.ptr, st));
     }
     hipLaunchKernelGGL(cg_ap, dim3(gN), dim3(256), 0, st, w.p.ptr, w.Ap.ptr, N);
     SH_TRY(w.red.dot(w.p.ptr, w.Ap.ptr, per, s_pap + k * P, st));

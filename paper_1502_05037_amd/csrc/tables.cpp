@@ -84,6 +84,10 @@ void kb_tap_polys(int J, double beta, int deg, float* coef /* J*(deg+1), row t *
     }
     for (int i = 0; i < nn; ++i) coef[t * nn + i] = float(mono[i]);
   }
+  // tap J-1-t at s is tap t at -s (the window is even and the nodes symmetric): make the table say so
+  // exactly, as the kernels evaluate the pair from tap t's coefficients
+  for (int t = 0; t < J / 2; ++t)
+    for (int i = 0; i < nn; ++i) coef[(J - 1 - t) * nn + i] = (i % 2 ? -1.0f : 1.0f) * coef[t * nn + i];
 }
 
 // Daubechies extremal-phase scaling filter db_p by spectral factorisation:
