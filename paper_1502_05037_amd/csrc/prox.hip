@@ -149,14 +149,26 @@ __global__ __launch_bounds__(256) void ball_norms(const float2* __restrict__ s_i
   const int4 c = chunks[blockIdx.x];
   const float cb = cblk ? cblk[c.x] : 1.0f;
   double a = 0.0, b = 0.0;
-  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
-    const float2 si = s_in[i], zv = z[i], yv = yh[i];
+  auto acc = [&](float2 si, float2 zv, float2 yv) {
     const float2 sv = make_float2(cb * si.x, cb * si.y);
     const double dr = double(sv.x) - double(yv.x), di = double(sv.y) - double(yv.y);
     const double tr = dr + double(zv.x), ti = di + double(zv.y);
     a += tr * tr + ti * ti;
     b += dr * dr + di * di;
+  };
+  int i = c.y + threadIdx.x;
+  for (; i + 768 < c.z; i += 1024) {   // twelve loads in flight; the sums keep the order of i
+    float2 sv[4], zv[4], yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sv[u] = s_in[i + 256 * u];
+      zv[u] = z[i + 256 * u];
+      yv[u] = yh[i + 256 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc(sv[u], zv[u], yv[u]);
   }
+  for (; i < c.z; i += 256) acc(s_in[i], z[i], yh[i]);
   const double ra = block_sum(a, sh);
   const double rb = block_sum(b, sh);
   if (threadIdx.x == 0) {
@@ -190,8 +202,7 @@ __global__ __launch_bounds__(256) void ball_project(const float2* __restrict__ s
   const float cb = cblk ? cblk[c.x] : 1.0f;
   const bool inside = r <= e;   // inside the ball (boundary included) the projection is the identity
   const float ratio = inside ? 1.0f : float(e / r);
-  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
-    const float2 si = s_in[i], zv = z[i], yv = yh[i];
+  auto step = [&](int i, float2 si, float2 zv, float2 yv) {
     const float2 sv = make_float2(cb * si.x, cb * si.y);
     const float tr = sv.x + zv.x, ti = sv.y + zv.y;
     const float yr = inside ? tr : yv.x + (tr - yv.x) * ratio;
@@ -200,7 +211,20 @@ __global__ __launch_bounds__(256) void ball_project(const float2* __restrict__ s
     z[i] = make_float2(zr, zi);
     const float vr = sub_s ? yr - zr - sv.x : yr - zr, vi = sub_s ? yi - zi - sv.y : yi - zi;
     v[i] = make_float2(cb * vr, cb * vi);
+  };
+  int i = c.y + threadIdx.x;
+  for (; i + 768 < c.z; i += 1024) {   // twelve loads in flight
+    float2 sv[4], zv[4], yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sv[u] = s_in[i + 256 * u];
+      zv[u] = z[i + 256 * u];
+      yv[u] = yh[i + 256 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) step(i + 256 * u, sv[u], zv[u], yv[u]);
   }
+  for (; i < c.z; i += 256) step(i, s_in[i], z[i], yh[i]);
 }
 
 __global__ __launch_bounds__(256) void reweight_kernel(int64_t per, const float* __restrict__ c,

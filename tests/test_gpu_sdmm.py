@@ -24,9 +24,9 @@ def _dev(a, dtype=torch.float32):
     return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
 
 
-def _gpu_solve(sh, pb, prm, x0=None, W0=None, want_W=False, levels=4, mask=0x1FF):
+def _gpu_solve(sh, pb, prm, x0=None, W0=None, want_W=False, levels=4, mask=0x1FF, alpha=2):
     n = pb.n
-    op = sh.op_create(pb.uv, n, 2, pb.J, pb.offsets)
+    op = sh.op_create(pb.uv, n, alpha, pb.J, pb.offsets)
     psi = sh.psi_create(n, levels, mask)
     try:
         q = sh.psi_planes(psi)
@@ -48,11 +48,11 @@ def _params(sh, **kw):
     return p
 
 
-def _oracle_setup(pb, levels=4, mask=0x1FF, block_norm=True):
+def _oracle_setup(pb, levels=4, mask=0x1FF, block_norm=True, alpha=2):
     """The oracle's normalisation: block weights (the library's default) or one per problem, the norm of
     the weighted operator and the default gamma."""
     psi = wavelets.SARA(pb.n, levels, mask)
-    a = measurement.block_density_weights(pb.uv, pb.n, 2, pb.offsets) if block_norm else None
+    a = measurement.block_density_weights(pb.uv, pb.n, alpha, pb.offsets) if block_norm else None
     A = pb.op if a is None else measurement.BlockWeighted(pb.op, pb.offsets, a)
     nu = measurement.op_norm(A, np.ones((pb.n, pb.n)), max_iter=200, tol=1e-12)
     gamma = sdmm.default_gamma(pb.op, psi, pb.y, nu, offsets=pb.offsets, block_weights=a)
@@ -204,3 +204,18 @@ def test_cg_operator_forms_match_oracle(sh, toeplitz):
         print(f"toeplitz={toeplitz} cg_iters={kcg}: image error vs oracle {err:.3e}")
         assert err <= 1e-4
         np.testing.assert_allclose(resid, infos[0].block_resid, rtol=1e-4)
+
+
+def test_four_times_oversampled_grid_parity(sh):
+    """alpha = 4 (K = 4n): the Toeplitz kernel leaves a band of zeros in its circulant, the block weights
+    count 4 x 4 windows; two reweighted passes with the default two CG steps against the oracle."""
+    pb = helpers.build(8, 32, 1500, 3, 6, coverage="radial", prob=6)
+    pb.op = measurement.NUFFT(pb.uv, pb.n, pb.J, 4)
+    psi, nu, gamma, a = _oracle_setup(pb, alpha=4)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=60, cg_iters=2, passes=2, block_weights=a)
+    x_ref, _, infos, _ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
+    x, info, resid, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=60, passes=2), alpha=4)
+    err = helpers.rel(x, x_ref)
+    print(f"alpha 4: image error vs oracle {err:.3e}")
+    assert err <= 1e-4
+    np.testing.assert_allclose(resid, infos[-1].block_resid, rtol=1e-4)
