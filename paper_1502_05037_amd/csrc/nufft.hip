@@ -18,7 +18,7 @@
 // visibilities that share it.
 //
 // Gridding (atomic-free): one work-group per item owns a private padded patch.  Phase A computes the
-// 2J one-dimensional weights of a batch of visibilities, one thread each, into LDS.  Phase B walks
+// 2J one-dimensional weights of a batch of visibilities, two lanes each (one per axis), into LDS.  Phase B walks
 // the batch wave by wave with one lane per tap (t1, t2): the lane accumulates w1[t1] w2[t2] v in a
 // register while the cell stays the same and adds it into its wave's own LDS copy of the patch when
 // the (wave-uniform) cell changes, so no two lanes ever update the same address.  The wave copies
@@ -178,8 +178,10 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
 
 // Gridding of one work item into a private padded patch, written to patches[item slot].
 // Wave w owns the w-th quarter of the item and its own copy of the patch.  It walks its
-// visibilities in batches of 64.  Phase A (one lane per visibility) writes a1[t1] = w1[t1] * scale * v
-// and w2[t2] to the wave's LDS rows and marks, in a 64-bit ballot, where the cell changes.  Phase B
+// visibilities in batches of NB = 32.  Phase A (lane l for visibility l mod 32; lanes 0-31 the first
+// axis, 32-63 the second) writes a1[t1] = w1[t1] * scale * v and w2[t2] to the wave's LDS rows and marks,
+// in a ballot, where the cell changes; 32-entry rows keep the kernel's LDS at 30 KiB (five work-groups per
+// CU at J = 8, T = 16).  Phase B
 // (one lane per tap (t1, t2)) accumulates w2[t2] * a1[t1] in registers while the cell stays the same;
 // at a cell change the finished run is added into the wave's patch copy with a read-modify-write
 // (64 lanes, 64 distinct addresses, no other wave on this copy) whose write is deferred to the next
@@ -195,11 +197,12 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   constexpr int PP = P * P;
   constexpr int NQ = (J * J + 63) / 64;   // taps per lane
   __shared__ float2 pat[4][PP];           // one patch copy per wave
-  // per wave, tap-major; row pitches of 66 complex / 68 real entries keep every row 16-byte aligned
+  // per wave, tap-major; row pitches of 34 complex / 36 real entries keep every row 16-byte aligned
   // for the 128-bit reads of phase B (two visibilities of aw, four of bw per read) while the rows of
-  // different taps land in disjoint LDS banks; phase A (consecutive lanes) is conflict-free too
-  constexpr int AWP = 66, BWP = 68;
-  __shared__ __attribute__((aligned(16))) float2 aw[4][J][AWP];  // w1[t1] * scale * v, current 64 visibilities
+  // different taps land in disjoint LDS banks (row strides of 68 and 36 words); phase A (consecutive
+  // lanes) is conflict-free too
+  constexpr int NB = 32, AWP = NB + 2, BWP = NB + 4;
+  __shared__ __attribute__((aligned(16))) float2 aw[4][J][AWP];  // w1[t1] * scale * v, current NB visibilities
   __shared__ __attribute__((aligned(16))) float bw[4][J + 1][BWP];  // w2[t2]; row J stays 0
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -227,36 +230,39 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
     acc[q] = pend_val[q] = pend_old[q] = make_float2(0.f, 0.f);
   }
   float2* mypat = pat[wave];
-  bw[wave][J][lane] = 0.f;
+  if (lane < BWP) bw[wave][J][lane] = 0.f;
   int cur = -1, pend = -1;                  // patch offset of tap (0, 0): current run, deferred run
   const int w_lo = it.y + int((int64_t)it.z * wave / 4);
   const int w_hi = it.y + int((int64_t)it.z * (wave + 1) / 4);
-  for (int base = w_lo; base < w_hi; base += 64) {
-    const int nb = min(64, w_hi - base);
+  const int vl = lane & (NB - 1);           // this lane's visibility in the batch
+  const bool ax2 = lane >= NB;              // lanes NB..63 weigh the second axis
+  for (int base = w_lo; base < w_hi; base += NB) {
+    const int nb = min(NB, w_hi - base);
     int cell = -1;
-    if (lane >= nb) {                       // padding entries contribute exactly zero
+    if (vl >= nb) {                         // padding entries contribute exactly zero
+      if (!ax2) {
 #pragma unroll
-      for (int t = 0; t < J; ++t) {
-        aw[wave][t][lane] = make_float2(0.f, 0.f);
-        bw[wave][t][lane] = 0.f;
+        for (int t = 0; t < J; ++t) aw[wave][t][vl] = make_float2(0.f, 0.f);
+      } else {
+#pragma unroll
+        for (int t = 0; t < J; ++t) bw[wave][t][vl] = 0.f;
       }
     } else {                                // phase A
-      const int j = base + lane;
+      const int j = base + vl;
       const uint2 c = coord[j];
-      const float2 v = vis[vidx ? vidx[j] : j];
-      const int lr = int(c.x >> F) - a0, lc = int(c.y >> F) - b0;
-      const float s1 = float(c.x & fmask) * fs - 1.0f;
-      const float s2 = float(c.y & fmask) * fs - 1.0f;
-      const float vr = v.x * scale, vi = v.y * scale;
-      float w1[J], w2[J];
-      kb_weights<J>(kc, s1, w1);
-      kb_weights<J>(kc, s2, w2);
+      const float sv = float((ax2 ? c.y : c.x) & fmask) * fs - 1.0f;
+      float w[J];
+      kb_weights<J>(kc, sv, w);
+      if (!ax2) {
+        const float2 v = vis[vidx ? vidx[j] : j];
+        const float vr = v.x * scale, vi = v.y * scale;
 #pragma unroll
-      for (int t = 0; t < J; ++t) {
-        aw[wave][t][lane] = make_float2(w1[t] * vr, w1[t] * vi);
-        bw[wave][t][lane] = w2[t];
+        for (int t = 0; t < J; ++t) aw[wave][t][vl] = make_float2(w[t] * vr, w[t] * vi);
+      } else {
+#pragma unroll
+        for (int t = 0; t < J; ++t) bw[wave][t][vl] = w[t];
       }
-      cell = lr * P + lc;
+      cell = (int(c.x >> F) - a0) * P + (int(c.y >> F) - b0);
     }
     // run starts of this batch: lane i starts a run if its cell differs from lane i-1's
     // (lane 0 compares with the run carried over from the previous batch)
