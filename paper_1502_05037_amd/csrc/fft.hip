@@ -11,13 +11,18 @@
 // stages and one radix-4 or radix-2 stage; twiddles come from a float64-derived table.  The same
 // passes without deapodisation, and an unpruned forward 2D transform of a dense K x K array, serve
 // the Toeplitz form of Phi^dagger Phi.
+#include <algorithm>
+
 #include "op.hpp"
 
 namespace {
 
 // COLS_TOEP: column pass of the Toeplitz normal operator (forward DFT of a pruned column, product with
-// the transposed kernel spectrum, inverse DFT, keep the n needed rows).
-enum Mode { ROWS_FWD = 0, COLS_FWD = 1, COLS_ADJ = 2, ROWS_ADJ = 3, FULL_ROWS = 4, FULL_COLS = 5, COLS_TOEP = 6 };
+// the transposed kernel spectrum, inverse DFT, keep the n needed rows).  ROWS_ADJ_H: ROWS_ADJ on rows
+// of which only columns 0..K/2 were written, the rest following from Hermitian symmetry.
+enum Mode {
+  ROWS_FWD = 0, COLS_FWD = 1, COLS_ADJ = 2, ROWS_ADJ = 3, FULL_ROWS = 4, FULL_COLS = 5, COLS_TOEP = 6, ROWS_ADJ_H = 7
+};
 
 template <bool INV>
 __device__ __forceinline__ float2 rot_mi(float2 a) {  // multiply by -i (forward) or +i (inverse)
@@ -113,7 +118,7 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
                                                       const float2* __restrict__ tw,
                                                       const float* __restrict__ deapod, int n, int per) {
   extern __shared__ float2 lds[];
-  constexpr bool INV = (MODE == COLS_ADJ || MODE == ROWS_ADJ);
+  constexpr bool INV = (MODE == COLS_ADJ || MODE == ROWS_ADJ || MODE == ROWS_ADJ_H);
   constexpr int NT = B * L / 8;
   const int tid = threadIdx.x;
   const int K = L;                    // grid side
@@ -169,6 +174,18 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
       const int r = e / B, b = e - r * B;
       lds[b * L + r] = g[(size_t)r * K + seq0 + b];
     }
+  } else if constexpr (MODE == ROWS_ADJ_H) {
+    const float2* h = (const float2*)in;
+    for (int e = tid; e < B * L; e += NT) {
+      const int b = e / L, c = e - b * L;
+      const float2* row = h + (size_t)(seq0 + b) * K;
+      if (c <= L / 2) {
+        lds[e] = row[c];
+      } else {
+        const float2 v = row[L - c];
+        lds[e] = make_float2(v.x, -v.y);
+      }
+    }
   } else {  // ROWS_ADJ, FULL_ROWS
     const float2* h = (const float2*)in;
     for (int e = tid; e < B * L; e += NT) {
@@ -217,7 +234,7 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
       const int r = e / B, b = e - r * B;
       h[(size_t)r * K + seq0 + b] = lds[b * L + ((r - half) & (L - 1))];
     }
-  } else {
+  } else {  // ROWS_ADJ, ROWS_ADJ_H
     float* x = (float*)out;
     for (int e = tid; e < B * n; e += NT) {
       const int b = e / n, c = e - b * n;
@@ -233,6 +250,9 @@ sh_status launch_len(int per, int P, const void* in, void* out, const float2* tw
   constexpr int B = (8192 / L) < 1 ? 1 : (8192 / L);
   int b = B > 64 ? 64 : B;
   while (b > per) b >>= 1;  // few sequences (tiny images): shrink the batch
+  // fewer than two work-groups per CU: shrink the batch (down to one wave per work-group) so that more
+  // CUs share the pass
+  while (b > 1 && (b / 2) * L / 8 >= 64 && int64_t(P) * (per / b) < 512) b >>= 1;
   const size_t lds = size_t(b) * L * sizeof(float2);
 #define SH_FFT_CASE(BB)                                                                                  \
   if (b == BB) {                                                                                         \
@@ -298,11 +318,17 @@ sh_status fft_full_2d(sh_op op, float2* buf, float2* tmp, hipStream_t st) {
   return launch_mode<FULL_COLS>(op->K, op->K, op->P, tmp, buf, op->tw.ptr, op->ones.ptr, op->n, st);
 }
 
+// The image is real, so every row of the row pass's output is Hermitian in the column index and so is
+// every row after the column pass (the kernel spectrum is real and even): the column pass runs over
+// columns 0..K/2 only (rounded up to whole work-groups) and the last row pass mirrors the rest.
 sh_status toeplitz_apply(sh_op op, const float* Ht, const float* x, float2* tq, float* out, hipStream_t st) {
   ProfScope ps("toeplitz", st);
-  SH_TRY(launch_mode<ROWS_FWD>(op->K, op->n, op->P, x, op->half.ptr, op->tw.ptr, op->ones.ptr, op->n, st));
-  SH_TRY(launch_mode<COLS_TOEP>(op->K, op->K, op->P, op->half.ptr, tq, op->tw.ptr, Ht, op->n, st));
-  return launch_mode<ROWS_ADJ>(op->K, op->n, op->P, tq, out, op->tw.ptr, op->ones.ptr, op->n, st);
+  const int K = op->K;
+  const int b0 = std::min(8192 / K, 64);                 // the column pass's work-group batch (launch_len)
+  const int cols = std::min<int>(K, int(cdiv(K / 2 + 1, b0) * b0));
+  SH_TRY(launch_mode<ROWS_FWD>(K, op->n, op->P, x, op->half.ptr, op->tw.ptr, op->ones.ptr, op->n, st));
+  SH_TRY(launch_mode<COLS_TOEP>(K, cols, op->P, op->half.ptr, tq, op->tw.ptr, Ht, op->n, st));
+  return launch_mode<ROWS_ADJ_H>(K, op->n, op->P, tq, out, op->tw.ptr, op->ones.ptr, op->n, st);
 }
 
 }  // namespace sh

@@ -34,6 +34,77 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 #define PART_OUT(r) \
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (r)
 
+// Conjugate-gradient steps fused with the dot product that follows them (per segment p = problem):
+// r = a + b + c - 2x, p = r, xprev = x, partial r.r
+__global__ __launch_bounds__(256) void cg_init_rr(const float* __restrict__ a, const float* __restrict__ b,
+                                                  const float* __restrict__ c, const float* __restrict__ x,
+                                                  float* __restrict__ r, float* __restrict__ pv,
+                                                  float* __restrict__ xprev, int64_t per, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  SEGMENT_LOOP(i) {
+    const float xv = x[i];
+    const float rv = a[i] + b[i] + c[i] - 2.f * xv;
+    r[i] = rv;
+    pv[i] = rv;
+    xprev[i] = xv;
+    acc += double(rv) * double(rv);
+  }
+  const double rs = block_sum(acc, sh);
+  PART_OUT(rs);
+}
+
+// Ap = 2p + Ap, partial p.Ap
+__global__ __launch_bounds__(256) void cg_ap_dot(const float* __restrict__ pv, float* __restrict__ Ap, int64_t per,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  SEGMENT_LOOP(i) {
+    const float pi = pv[i];
+    const float a = 2.f * pi + Ap[i];
+    Ap[i] = a;
+    acc += double(pi) * double(a);
+  }
+  const double r = block_sum(acc, sh);
+  PART_OUT(r);
+}
+
+// alpha = rs / pAp; x += alpha p; r -= alpha Ap; partial r.r
+__global__ __launch_bounds__(256) void cg_update_rr(float* __restrict__ x, float* __restrict__ r,
+                                                    const float* __restrict__ pv, const float* __restrict__ Ap,
+                                                    int64_t per, const double* __restrict__ rs,
+                                                    const double* __restrict__ pAp, double* __restrict__ part) {
+  __shared__ double sh[256];
+  const double d = pAp[blockIdx.y];
+  const float alpha = d > 0 ? float(rs[blockIdx.y] / d) : 0.f;
+  double acc = 0.0;
+  SEGMENT_LOOP(i) {
+    x[i] = fmaf(alpha, pv[i], x[i]);
+    const float rv = fmaf(-alpha, Ap[i], r[i]);
+    r[i] = rv;
+    acc += double(rv) * double(rv);
+  }
+  const double rr = block_sum(acc, sh);
+  PART_OUT(rr);
+}
+
+// partials of ||x - xprev||^2 (part) and ||x||^2 (part + P * gridDim.x)
+__global__ __launch_bounds__(256) void change_dots(const float* __restrict__ x, const float* __restrict__ xprev,
+                                                   int64_t per, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double a = 0.0, b = 0.0;
+  SEGMENT_LOOP(i) {
+    const float xv = x[i];
+    const float d = xv - xprev[i];
+    a += double(d) * double(d);
+    b += double(xv) * double(xv);
+  }
+  const double ra = block_sum(a, sh);
+  const double rb = block_sum(b, sh);
+  PART_OUT(ra);
+  if (threadIdx.x == 0) part[(int64_t)gridDim.y * gridDim.x + (int64_t)blockIdx.y * gridDim.x + blockIdx.x] = rb;
+}
+
 __global__ __launch_bounds__(256) void dot_partial(const float* __restrict__ a, const float* __restrict__ b, int64_t per,
                                                    double* __restrict__ part) {
   __shared__ double sh[256];
@@ -244,7 +315,37 @@ namespace sh {
 sh_status Reducer::init(int segments) {
   P = segments;
   rb = RB / P > 1 ? RB / P : 1;   // about RB work-groups in all
-  SH_TRY(part.alloc(size_t(P) * rb));
+  SH_TRY(part.alloc(2 * size_t(P) * rb));
+  return SH_OK;
+}
+
+sh_status Reducer::cg_init(const float* a, const float* b, const float* c, const float* x, float* r, float* p,
+                           float* xprev, int64_t per, double* rs_out, hipStream_t st) {
+  hipLaunchKernelGGL(cg_init_rr, dim3(rb, P), dim3(256), 0, st, a, b, c, x, r, p, xprev, per, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, rs_out);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status Reducer::cg_ap(const float* p, float* Ap, int64_t per, double* pap_out, hipStream_t st) {
+  hipLaunchKernelGGL(cg_ap_dot, dim3(rb, P), dim3(256), 0, st, p, Ap, per, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, pap_out);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status Reducer::cg_update(float* x, float* r, const float* p, const float* Ap, int64_t per, const double* rs,
+                             const double* pap, double* rs_out, hipStream_t st) {
+  hipLaunchKernelGGL(cg_update_rr, dim3(rb, P), dim3(256), 0, st, x, r, p, Ap, per, rs, pap, part.ptr);
+  if (rs_out) hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, rs_out);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status Reducer::change(const float* x, const float* xprev, int64_t per, double* out2, hipStream_t st) {
+  hipLaunchKernelGGL(change_dots, dim3(rb, P), dim3(256), 0, st, x, xprev, per, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(2 * P), dim3(256), 0, st, part.ptr, rb, out2);
+  SH_LAUNCHED();
   return SH_OK;
 }
 

@@ -69,36 +69,6 @@ __global__ __launch_bounds__(256) void gather_scale(const float2* __restrict__ s
   }
 }
 
-// r = a + b + c - 2x; p = r; xprev = x
-__global__ void cg_init(const float* __restrict__ a, const float* __restrict__ b, const float* __restrict__ c,
-                        const float* __restrict__ x, float* __restrict__ r, float* __restrict__ p,
-                        float* __restrict__ xprev, int64_t N) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  const float xv = x[i];
-  const float rv = a[i] + b[i] + c[i] - 2.f * xv;
-  r[i] = rv;
-  p[i] = rv;
-  xprev[i] = xv;
-}
-
-// Ap = 2p + Ap
-__global__ void cg_ap(const float* __restrict__ p, float* __restrict__ Ap, int64_t N) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < N) Ap[i] = 2.f * p[i] + Ap[i];
-}
-
-// per problem: alpha = rs / pAp; x += alpha p; r -= alpha Ap
-__global__ void cg_update(float* __restrict__ x, float* __restrict__ r, const float* __restrict__ pv,
-                          const float* __restrict__ Ap, int64_t per, const double* __restrict__ rs,
-                          const double* __restrict__ pAp) {
-  SEG_INDEX(per)
-  const double d = pAp[p];
-  const float alpha = d > 0 ? float(rs[p] / d) : 0.f;
-  x[i] = fmaf(alpha, pv[i], x[i]);
-  r[i] = fmaf(-alpha, Ap[i], r[i]);
-}
-
 // per problem: beta = rs_new / rs; p = r + beta p
 __global__ void cg_dir(const float* __restrict__ r, float* __restrict__ pv, int64_t per, const double* __restrict__ rs,
                        const double* __restrict__ rs_new) {
@@ -108,11 +78,6 @@ __global__ void cg_dir(const float* __restrict__ r, float* __restrict__ pv, int6
   pv[i] = fmaf(beta, pv[i], r[i]);
 }
 #undef SEG_INDEX
-
-__global__ void diff_kernel(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ c, int64_t N) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < N) c[i] = a[i] - b[i];
-}
 
 inline unsigned nblk(int64_t n) { return (unsigned)sh::cdiv(n, 256); }
 
@@ -375,15 +340,12 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   Work& w = s->w;
   const int P = s->P;
   const int64_t N = s->N, per = s->per;
-  const unsigned gN = nblk(N);
   const dim3 gP(nblk(per), P);
   double *s_rs = s->s_rs, *s_pap = s->s_pap, *s_misc = s->s_misc;
   // ---- x-update by CG from x_{n-1}
   SH_TRY(sh_psi_fwd(s->psi, w.vpsi.ptr, w.t1.ptr, st));
   SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.t2.ptr, false, nullptr, st));   // vphi carries c_b
-  hipLaunchKernelGGL(cg_init, dim3(gN), dim3(256), 0, st, w.t1.ptr, w.t2.ptr, w.vpos.ptr, w.x.ptr, w.r.ptr, w.p.ptr,
-                     w.xprev.ptr, N);
-  SH_TRY(w.red.dot(w.r.ptr, w.r.ptr, per, s_rs, st));
+  SH_TRY(w.red.cg_init(w.t1.ptr, w.t2.ptr, w.vpos.ptr, w.x.ptr, w.r.ptr, w.p.ptr, w.xprev.ptr, per, s_rs, st));
   for (int k = 0; k < s->kcg; ++k) {
     if (s->prm.toeplitz) {
       SH_TRY(sh::toeplitz_apply(op, w.toep.Ht.ptr, w.p.ptr, w.toep.tq.ptr, w.Ap.ptr, st));
@@ -391,20 +353,17 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
       SH_TRY(sh::phi_forward(op, w.p.ptr, w.vtmp.ptr, false, w.cblk.ptr, st));
       SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.Ap.ptr, false, w.cblk.ptr, st));
     }
-    hipLaunchKernelGGL(cg_ap, dim3(gN), dim3(256), 0, st, w.p.ptr, w.Ap.ptr, N);
-    SH_TRY(w.red.dot(w.p.ptr, w.Ap.ptr, per, s_pap + k * P, st));
-    hipLaunchKernelGGL(cg_update, gP, dim3(256), 0, st, w.x.ptr, w.r.ptr, w.p.ptr, w.Ap.ptr, per, s_rs + k * P,
-                       s_pap + k * P);
-    if (k + 1 < s->kcg) {
-      SH_TRY(w.red.dot(w.r.ptr, w.r.ptr, per, s_rs + (k + 1) * P, st));
+    SH_TRY(w.red.cg_ap(w.p.ptr, w.Ap.ptr, per, s_pap + k * P, st));
+    const bool more = k + 1 < s->kcg;
+    SH_TRY(w.red.cg_update(w.x.ptr, w.r.ptr, w.p.ptr, w.Ap.ptr, per, s_rs + k * P, s_pap + k * P,
+                           more ? s_rs + (k + 1) * P : nullptr, st));
+    if (more)
       hipLaunchKernelGGL(cg_dir, gP, dim3(256), 0, st, w.r.ptr, w.p.ptr, per, s_rs + k * P, s_rs + (k + 1) * P);
-    }
   }
   SH_LAUNCHED();
   // ---- relative change
-  hipLaunchKernelGGL(diff_kernel, dim3(gN), dim3(256), 0, st, w.x.ptr, w.xprev.ptr, w.t1.ptr, N);
-  SH_TRY(w.red.dot(w.t1.ptr, w.t1.ptr, per, s_misc + MISC_DX * P, st));
-  SH_TRY(w.red.dot(w.x.ptr, w.x.ptr, per, s_misc + MISC_X * P, st));
+  static_assert(MISC_X == MISC_DX + 1, "change() writes dx^2 then x^2");
+  SH_TRY(w.red.change(w.x.ptr, w.xprev.ptr, per, s_misc + MISC_DX * P, st));
   // ---- splits
   SH_TRY(sh_psi_adj(s->psi, w.x.ptr, w.spsi.ptr, st));
   SH_TRY(sh::launch_prox_l1(s->Dper, P, w.spsi.ptr, w.zpsi.ptr, s->Wp, w.gamma.ptr, 0.f, w.vpsi.ptr, st));
