@@ -220,7 +220,7 @@ sh_status sh_toeplitz_destroy(sh_toep t);
  * ------------------------------------------------------------------------- */
 
 typedef struct {
-  double gamma;        /* l1 prox step; <= 0: 1e-4 * max|Psi^dagger Phi^dagger y| / nu^2 */
+  double gamma;        /* l1 prox step; <= 0: 1e-4 max|Psi^dagger Phi_hat^dagger y_hat| per problem */
   double nu;           /* norm used to normalise (see block_norm); <= 0: power iteration from ones
                           (at most 200 steps, to a relative change of 1e-6) */
   double tol_rel;      /* stop when ||x_n - x_{n-1}||/||x_n|| <= tol_rel and all blocks feasible;
@@ -260,7 +260,7 @@ typedef struct {
   double rel_change;     /* ||x_n - x_{n-1}|| / ||x_n|| at exit */
   double objective;      /* ||W Psi^dagger x||_1 with the last pass's weights */
   double gamma;          /* step actually used */
-  double nu;             /* normalisation actually used */
+  double nu;             /* normalisation actually used (nu_p of block_norm) */
   double delta;          /* reweighting delta of W_out */
   double seconds;        /* wall time inside the call */
 } sh_sdmm_info;

@@ -14,7 +14,8 @@
 // (blocks contiguous).  v_j = y_j - z_j is kept instead of y_j.  The x-update is conjugate gradients
 // warm-started at x_{n-1} with a fixed number of steps; its initial residual
 //   b - Q x_{n-1} = Psi v_psi + Phi_hat^dagger (v_phi - Phi_hat x_{n-1}) + v_+ - 2 x_{n-1}
-// reuses s_phi = Phi_hat x_{n-1} from the previous iteration.  The CG products Re(Phi_hat^H Phi_hat) p
+// reuses s_phi = Phi x_{n-1} from the previous iteration (stored unweighted; the ball step applies c_b,
+// and v_phi leaves it multiplied by c_b for the adjoint).  The CG products Re(Phi_hat^H Phi_hat) p
 // go through the Toeplitz embedding of that operator (toeplitz.hip: FFT passes only) or, with the
 // option off, through a Phi, Phi^dagger pair; one iteration then costs one application each of Phi
 // and Phi^dagger plus cg_iters Toeplitz products, or (cg_iters + 1) pairs.  CG scalars stay on the
@@ -179,7 +180,7 @@ struct sh_sdmm_s {
   int R = 0, kcg = 0;
   std::vector<double> nu, gamma, delta;   // per problem
   std::vector<double> cb;          // c_b per block (host)
-  std::vector<double> eh;          // eps / nu per block (host)
+  std::vector<double> eh;          // eps_hat = c_b eps per block (host)
   const float* Wp = nullptr;       // weights of the current pass (NULL = identity)
   int iters_total = 0;
   double *s_rs = nullptr, *s_pap = nullptr, *s_misc = nullptr;
