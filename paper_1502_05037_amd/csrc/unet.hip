@@ -12,14 +12,15 @@
 //
 // Every convolution is a matrix product on the MFMA units: activations are NHWC (channels
 // contiguous), a 3x3 convolution is im2col (K = 9 Cin, ordered (ky, kx, ci), zero-padded to a
-// multiple of 16; gathered inside the product's staging, never stored, except where the weight
-// gradient needs it transposed) times the weight matrix, and all products use one kernel of the "NT" form
+// multiple of 16; gathered inside the product's staging, never stored) times the weight matrix, and the
+// forward and input-gradient products use one kernel of the "NT" form
 // C[m][n] = sum_k A[m][k] B[n][k] with both operands contiguous along k (v_mfma_f32_16x16x16_bf16,
 // 64 x 64 tiles per work-group of four waves, k staged through LDS 64 at a time with the next slab
 // prefetched into registers, optional split-K
-// with a fixed-order reduction).  Weight gradients contract over pixels, so their operands are
-// transposed first (pixels padded to a multiple of 16); a row of ones appended to the second
-// operand yields the bias gradient in the same product.  Results are deterministic.
+// with a fixed-order reduction).  Weight gradients contract over pixels: their kernel ("TN") reads both
+// operands pixel-major as stored (the im2col again gathered) and transposes them on the way into LDS;
+// a column of ones on the second operand yields the bias gradient in the same product.  Results are
+// deterministic.
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -173,73 +174,133 @@ __global__ void sum_splits(const float* __restrict__ part, int S, int64_t n, flo
   out[i] = s;
 }
 
+// Columns k .. k+7 of the implicit 3x3 im2col row (see Im2col) of the pixel (b, y, x)
+__device__ __forceinline__ uint4 im2col8(const Im2col& g, int b, int y, int x, int k) {
+  if ((g.C & 7) == 0) {
+    if (k >= 9 * g.C) return make_uint4(0, 0, 0, 0);
+    const int tap = k / g.C, c = k - tap * g.C;
+    const int sy = y + tap / 3 - 1, sx = x + tap % 3 - 1;
+    if (sy < 0 || sy >= g.H || sx < 0 || sx >= g.W) return make_uint4(0, 0, 0, 0);
+    return *(const uint4*)(g.x + ((int64_t)(b * g.H + sy) * g.W + sx) * g.ldx + c);
+  }
+  uint16_t v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int kq = k + q;
+    v[q] = 0;
+    if (kq < 9 * g.C) {
+      const int tap = kq / g.C, c = kq - tap * g.C;
+      const int sy = y + tap / 3 - 1, sx = x + tap % 3 - 1;
+      if (sy >= 0 && sy < g.H && sx >= 0 && sx < g.W) v[q] = g.x[((int64_t)(b * g.H + sy) * g.W + sx) * g.ldx + c];
+    }
+  }
+  return make_uint4(v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
+                    v[6] | (uint32_t(v[7]) << 16));
+}
+
+// Weight-gradient products, which contract over pixels: C[m][n] = sum_{p in split z} A[p][m] Bv[p][n], p < P,
+// with both operands read in their stored pixel-major layout and transposed on the way into LDS (the
+// MFMA part is that of gemm_nt).  A: P x M, row stride lda.  Bv[p][n] = B[p][n] (row stride ldb) for
+// n < NB, or the implicit 3x3 im2col of g.x when GATHER; 1 for n == NB when `ones` (the bias gradient);
+// 0 beyond.  NB is a multiple of 8.  Staging: thread t takes pixels 2 (t % 32), 2 (t % 32) + 1 of the
+// slab and the 8 columns 8 (t / 32) .. of each tile, and stores every column's pixel pair as one 32-bit
+// LDS word (a wave's two column groups land in disjoint banks).
+template <bool GATHER>
+__global__ __launch_bounds__(256) void gemm_tn(const uint16_t* __restrict__ A, int lda, int M,
+                                               const uint16_t* __restrict__ B, int ldb, int NB, int ones, int N, int P,
+                                               int kchunk, float* __restrict__ C, int ldc, Im2col g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GLD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int kb = blockIdx.z * kchunk, ke = min(P, kb + kchunk);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int pp = 2 * (tid & 31), cc = 8 * (tid >> 5);
+  const uint4 zero = make_uint4(0, 0, 0, 0);
+  auto row8 = [&](const uint16_t* X, int ld, int p, int c0, int ncol) -> uint4 {   // X[p][c0 .. c0+7]
+    if (c0 + 8 <= ncol && (ld & 7) == 0) return *(const uint4*)(X + (int64_t)p * ld + c0);
+    uint16_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = c0 + q < ncol ? X[(int64_t)p * ld + c0 + q] : (uint16_t)0;
+    return make_uint4(v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
+                      v[6] | (uint32_t(v[7]) << 16));
+  };
+  uint4 ra[2], rb[2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int p = k0 + pp + e;
+      ra[e] = zero;
+      rb[e] = zero;
+      if (p >= ke) continue;
+      if (m0 + cc < M) ra[e] = row8(A, lda, p, m0 + cc, M);
+      const int n = n0 + cc;
+      if (n < NB) {
+        if constexpr (GATHER) {
+          const int b = p / (g.H * g.W), rem = p - b * g.H * g.W;
+          const int y = rem / g.W;
+          rb[e] = im2col8(g, b, y, rem - y * g.W, n);
+        } else {
+          rb[e] = row8(B, ldb, p, n, NB);
+        }
+      } else if (n == NB && ones) {
+        rb[e] = make_uint4(0x3F80u, 0, 0, 0);   // bf16 1.0 in column NB
+      }
+    }
+  };
+  auto half = [](const uint4& v, int j) -> uint32_t {   // 16-bit element j of v
+    const uint32_t w = j < 2 ? v.x : j < 4 ? v.y : j < 6 ? v.z : v.w;
+    return (j & 1) ? (w >> 16) : (w & 0xFFFFu);
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += GBK) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      *(uint32_t*)&As[cc + j][pp] = half(ra[0], j) | (half(ra[1], j) << 16);
+      *(uint32_t*)&Bs[cc + j][pp] = half(rb[0], j) | (half(rb[1], j) << 16);
+    }
+    __syncthreads();
+    if (k0 + GBK < ke) load(k0 + GBK);   // in flight during the products below
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 16) {
+      const int ko = kk + 4 * (lane >> 4);
+      bf16x4 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = *(const bf16x4*)&As[wm * 32 + i * 16 + (lane & 15)][ko];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = *(const bf16x4*)&Bs[wn * 32 + j * 16 + (lane & 15)][ko];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  C += (int64_t)blockIdx.z * M * ldc;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+      if (n >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        if (m < M) C[(int64_t)m * ldc + n] = acc[i][j][r];
+      }
+    }
+}
+
 // ---- layout kernels ----------------------------------------------------------------------------
 
 __global__ void f32_to_bf16(const float* __restrict__ in, uint16_t* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) out[i] = f2bf(in[i]);
-}
-
-// col[p][k] for p < B*H*W, k < Kp: k = (ky*3 + kx)*C + c < 9C takes x at (y+ky-1, x+kx-1) (zero outside
-// the image), k >= 9C is zero.  x: NHWC with row stride ldx (channels at offset 0).  One thread per
-// 8 consecutive k.
-__global__ void im2col3(const uint16_t* __restrict__ x, int ldx, int B, int H, int W, int C, int Kp,
-                        uint16_t* __restrict__ col) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int g8 = Kp / 8;
-  const int64_t P = (int64_t)B * H * W;
-  if (t >= P * g8) return;
-  const int64_t p = t / g8;
-  const int k0 = int(t - p * g8) * 8;
-  const int b = int(p / ((int64_t)H * W));
-  const int rem = int(p - (int64_t)b * H * W);
-  const int yy = rem / W, xx = rem - yy * W;
-  uint16_t* dst = col + p * Kp + k0;
-  if ((C & 7) == 0) {
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (k0 < 9 * C) {
-      const int tap = k0 / C, c = k0 - tap * C;
-      const int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
-      if (sy >= 0 && sy < H && sx >= 0 && sx < W)
-        v = *(const uint4*)(x + ((int64_t)(b * H + sy) * W + sx) * ldx + c);
-    }
-    *(uint4*)dst = v;
-  } else {
-    for (int e = 0; e < 8; ++e) {
-      const int k = k0 + e;
-      uint16_t v = 0;
-      if (k < 9 * C) {
-        const int tap = k / C, c = k - tap * C;
-        const int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
-        if (sy >= 0 && sy < H && sx >= 0 && sx < W) v = x[((int64_t)(b * H + sy) * W + sx) * ldx + c];
-      }
-      dst[e] = v;
-    }
-  }
-}
-
-// out[c][r] = in[r*ld + c] (r < R) or 0 (R <= r < Rp), c < C; with ones_row, out[C][r] = (r < R).
-__global__ __launch_bounds__(256) void transpose_pad(const uint16_t* __restrict__ in, int64_t R, int C, int ld,
-                                                     uint16_t* __restrict__ out, int64_t Rp, int ones_row) {
-  __shared__ uint16_t tile[32][33];
-  const int64_t r0 = (int64_t)blockIdx.x * 32;
-  const int c0 = blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-  for (int q = ty; q < 32; q += 8) {
-    const int64_t r = r0 + q;
-    const int c = c0 + tx;
-    tile[q][tx] = (r < R && c < C) ? in[r * ld + c] : (uint16_t)0;
-  }
-  __syncthreads();
-  for (int q = ty; q < 32; q += 8) {
-    const int c = c0 + q;
-    const int64_t r = r0 + tx;
-    if (c < C && r < Rp) out[(int64_t)c * Rp + r] = tile[tx][q];
-  }
-  if (ones_row && blockIdx.y == 0 && ty == 0) {
-    const int64_t r = r0 + tx;
-    if (r < Rp) out[(int64_t)C * Rp + r] = r < R ? (uint16_t)0x3F80 : (uint16_t)0;   // bf16 1.0
-  }
 }
 
 // 2x2 max-pool, NHWC; idx = row-major index of the first maximum of the window
@@ -494,7 +555,7 @@ struct Acts {              // activations of one (B, H, W), allocated on first u
   sh::DevBuf<uint16_t> x0;                  // input, bf16
   sh::DevBuf<float> z;                      // head pre-activation
   // scratch
-  sh::DevBuf<uint16_t> col, colT, gT, gm, gG;
+  sh::DevBuf<uint16_t> gm, gG;
   sh::DevBuf<float> f32a, gA, gB, gC, part;
   std::vector<sh::DevBuf<float>> skipg;     // decoder level l: gradient at the skip half of its concat
   sh::DevBuf<double> lpart, loss;
@@ -536,7 +597,7 @@ sh_status ensure_acts(sh_unet u, int B, int H, int W) {
   a.pidx.resize(L);
   a.cat.resize(L);
   a.dec.resize(2 * L);
-  int64_t maxcol = 0, maxf = 0, maxT = 0, maxpart = 0;
+  int64_t maxf = 0, maxpart = 0;
   for (int l = 0; l < L; ++l) {
     const int64_t P = P_of(u, l);
     const int c = u->base << l;
@@ -551,11 +612,6 @@ sh_status ensure_acts(sh_unet u, int B, int H, int W) {
       SH_TRY(a.dec[2 * l].alloc(P * c));
       SH_TRY(a.dec[2 * l + 1].alloc(P * c));
     }
-    const int64_t Pp = rup(P, 16);
-    const int cin_max = l == 0 ? 2 * c : 2 * c;   // decoder convs read 2c channels
-    const int64_t Kp = rup(9 * std::max(cin_max, 1), 16), Kpd = rup(9 * 2 * c, 16);
-    maxcol = std::max(maxcol, P * std::max(Kp, Kpd));
-    maxT = std::max(maxT, (Kp + 1) * Pp);
     maxf = std::max(maxf, P * 4 * c);          // fp32 layer gradients / tconv outputs (<= 4c per pixel)
     maxpart = std::max(maxpart, (int64_t)8 * 1024 * 1024);
   }
@@ -563,9 +619,6 @@ sh_status ensure_acts(sh_unet u, int B, int H, int W) {
   SH_TRY(a.x0.alloc(P1));
   SH_TRY(a.z.alloc(P1));
   SH_TRY(a.gbf.alloc(P1));
-  SH_TRY(a.col.alloc(maxcol));
-  SH_TRY(a.colT.alloc(maxT));
-  SH_TRY(a.gT.alloc(maxT));
   SH_TRY(a.gm.alloc(maxf));
   SH_TRY(a.gG.alloc(maxf));
   SH_TRY(a.f32a.alloc(maxf));
@@ -615,6 +668,32 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
   return SH_OK;
 }
 
+// Weight gradient C (M x (NB + ones), fp32, row stride NB + ones) = sum over P pixels of A[p]^T Bv[p]
+// (gemm_tn), split over pixels and reduced in fixed order through `part` when the tile grid is small.
+sh_status gemm_wgrad(sh_unet u, const uint16_t* A, int lda, int M, const uint16_t* B, int ldb, int NB, bool ones,
+                     int64_t P, float* C, hipStream_t st, const Im2col* gat = nullptr) {
+  SH_REQUIRE(NB % 8 == 0 && P > 0 && P < (int64_t(1) << 31), "internal: weight-gradient shape");
+  const int N = NB + (ones ? 1 : 0);
+  const unsigned gx = (unsigned)sh::cdiv(N, GBN), gy = (unsigned)sh::cdiv(M, GBM);
+  const int64_t tiles = (int64_t)gx * gy;
+  int S = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(tiles, 1), P / 256));
+  while (S > 1 && (int64_t)S * M * N > u->ap->part.count) --S;
+  const int64_t kchunk = rup(sh::cdiv(P, S), GBK);
+  S = (int)sh::cdiv(P, kchunk);
+  const Im2col g = gat ? *gat : Im2col{nullptr, 0, 1, 1, 1};
+  float* dst = S == 1 ? C : u->ap->part.ptr;
+  if (gat)
+    hipLaunchKernelGGL(gemm_tn<true>, dim3(gx, gy, S), dim3(256), 0, st, A, lda, M, nullptr, 0, NB, ones ? 1 : 0, N,
+                       (int)P, (int)kchunk, dst, N, g);
+  else
+    hipLaunchKernelGGL(gemm_tn<false>, dim3(gx, gy, S), dim3(256), 0, st, A, lda, M, B, ldb, NB, ones ? 1 : 0, N,
+                       (int)P, (int)kchunk, dst, N, g);
+  if (S > 1) hipLaunchKernelGGL(sum_splits, dim3(nb((int64_t)M * N)), dim3(256), 0, st, u->ap->part.ptr, S,
+                                (int64_t)M * N, C);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
 sh_status prep_weights(sh_unet u, hipStream_t st) {
   for (const Layer& ly : u->layers) {
     const float* W = u->params.ptr + ly.w_off;
@@ -648,17 +727,12 @@ sh_status conv_fwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, int
 sh_status conv_bwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, const uint16_t* out, const float* gin,
                    int ldg, const float* gin2, int ldg2, int B, int H, int W, float* dx, hipStream_t st) {
   Acts& a = *u->ap;
-  const int64_t P = (int64_t)B * H * W, Pp = rup(P, 16);
+  const int64_t P = (int64_t)B * H * W;
   hipLaunchKernelGGL(relu_mask_grad, dim3(nb(P * ly.cout)), dim3(256), 0, st, gin, ldg, gin2, ldg2, out, P, ly.cout,
                      a.gm.ptr);
-  // weight gradient: gm^T (Co x Pp) . [col^T; 1] ((Kp+1) x Pp)^T
-  hipLaunchKernelGGL(im2col3, dim3(nb(P * (ly.Kp / 8))), dim3(256), 0, st, in, ldin, B, H, W, ly.cin, ly.Kp, a.col.ptr);
-  hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(Pp, 32), (unsigned)sh::cdiv(ly.Kp, 32)), dim3(256), 0, st,
-                     a.col.ptr, P, ly.Kp, ly.Kp, a.colT.ptr, Pp, 1);
-  hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(Pp, 32), (unsigned)sh::cdiv(ly.cout, 32)), dim3(256), 0,
-                     st, a.gm.ptr, P, ly.cout, ly.cout, a.gT.ptr, Pp, 0);
-  SH_TRY(gemm(u, a.gT.ptr, (int)Pp, a.colT.ptr, (int)Pp, ly.cout, ly.Kp + 1, Pp, nullptr, false, u->dwg.ptr, ly.Kp + 1,
-              nullptr, 0, true, st));
+  // weight gradient: dWg[co][k] = sum_p gm[p][co] [im2col(in), 1][p][k] (k = Kp: the bias)
+  const Im2col gi{in, ldin, H, W, ly.cin};
+  SH_TRY(gemm_wgrad(u, a.gm.ptr, ly.cout, ly.cout, nullptr, 0, ly.Kp, true, P, u->dwg.ptr, st, &gi));
   const int64_t ns = (int64_t)ly.cout * ly.cin * 9 + ly.cout;
   hipLaunchKernelGGL(scatter_conv_grad, dim3(nb(ns)), dim3(256), 0, st, u->dwg.ptr, ly.cout, ly.cin, ly.Kp,
                      u->grads.ptr + ly.w_off, u->grads.ptr + ly.b_off);
@@ -730,7 +804,7 @@ __global__ void copy_f32_channels(const float* __restrict__ src, int lds, int of
 sh_status net_backward(sh_unet u, const float* target, float* y_out, hipStream_t st) {
   Acts& a = *u->ap;
   const int B = a.B, H = a.H, W = a.W, L = u->levels;
-  const int64_t P1 = (int64_t)B * H * W, P1p = rup(P1, 16);
+  const int64_t P1 = (int64_t)B * H * W;
   const int nblocks = 256;
   hipLaunchKernelGGL(mse_loss, dim3(nblocks), dim3(256), 0, st, a.z.ptr, target, P1, y_out, a.gbf.ptr, a.lpart.ptr);
   hipLaunchKernelGGL(sum_part_f64, dim3(1), dim3(64), 0, st, a.lpart.ptr, nblocks, P1, a.loss.ptr);
@@ -739,12 +813,7 @@ sh_status net_backward(sh_unet u, const float* target, float* y_out, hipStream_t
   const Layer& hd = u->layers[nl - 1];
   const uint16_t* hin = L > 1 ? a.dec[1].ptr : a.enc[1].ptr;
   const int c1 = u->base;
-  hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(P1p, 32), 1), dim3(256), 0, st, a.gbf.ptr, P1, 1, 1,
-                     a.gT.ptr, P1p, 0);
-  hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(P1p, 32), (unsigned)sh::cdiv(c1, 32)), dim3(256), 0, st,
-                     hin, P1, c1, c1, a.colT.ptr, P1p, 1);
-  SH_TRY(gemm(u, a.gT.ptr, (int)P1p, a.colT.ptr, (int)P1p, 1, c1 + 1, P1p, nullptr, false, u->dwg.ptr, c1 + 1, nullptr,
-              0, true, st));
+  SH_TRY(gemm_wgrad(u, a.gbf.ptr, 1, 1, hin, c1, c1, true, P1, u->dwg.ptr, st));
   hipLaunchKernelGGL(copy_f32_channels, dim3(1), dim3(256), 0, st, u->dwg.ptr, c1 + 1, 0, u->grads.ptr + hd.w_off,
                      (int64_t)1, c1);
   hipLaunchKernelGGL(copy_f32_channels, dim3(1), dim3(256), 0, st, u->dwg.ptr, c1 + 1, c1, u->grads.ptr + hd.b_off,
@@ -755,7 +824,7 @@ sh_status net_backward(sh_unet u, const float* target, float* y_out, hipStream_t
   int li = nl - 2;
   for (int l = 0; l < L - 1; ++l) {
     const int h = H >> l, w = W >> l, c = u->base << l;
-    const int64_t P = (int64_t)B * h * w, Pin = (int64_t)B * (h / 2) * (w / 2), Pinp = rup(Pin, 16);
+    const int64_t P = (int64_t)B * h * w, Pin = (int64_t)B * (h / 2) * (w / 2);
     const Layer& lb = u->layers[li--];
     const Layer& la = u->layers[li--];
     const Layer& tl = u->layers[li--];
@@ -768,12 +837,7 @@ sh_status net_backward(sh_unet u, const float* target, float* y_out, hipStream_t
     const uint16_t* tin = l + 1 < L - 1 ? a.dec[2 * (l + 1) + 1].ptr : a.enc[2 * (l + 1) + 1].ptr;
     hipLaunchKernelGGL(tconv_gather, dim3(nb(Pin * 4 * c)), dim3(256), 0, st, a.gC.ptr, 2 * c, B, h / 2, w / 2, c,
                        a.gG.ptr);
-    hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(Pinp, 32), (unsigned)sh::cdiv(4 * c, 32)), dim3(256), 0,
-                       st, a.gG.ptr, Pin, 4 * c, 4 * c, a.gT.ptr, Pinp, 0);
-    hipLaunchKernelGGL(transpose_pad, dim3((unsigned)sh::cdiv(Pinp, 32), (unsigned)sh::cdiv(cin, 32)), dim3(256), 0,
-                       st, tin, Pin, cin, cin, a.colT.ptr, Pinp, 1);
-    SH_TRY(gemm(u, a.gT.ptr, (int)Pinp, a.colT.ptr, (int)Pinp, 4 * c, cin + 1, Pinp, nullptr, false, u->dwg.ptr, cin + 1,
-                nullptr, 0, true, st));
+    SH_TRY(gemm_wgrad(u, a.gG.ptr, 4 * c, 4 * c, tin, cin, cin, true, Pin, u->dwg.ptr, st));
     hipLaunchKernelGGL(scatter_tconv_grad, dim3(nb((int64_t)cin * c * 4 + c)), dim3(256), 0, st, u->dwg.ptr, cin, c,
                        u->grads.ptr + tl.w_off, u->grads.ptr + tl.b_off);
     SH_LAUNCHED();
