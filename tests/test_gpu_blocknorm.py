@@ -56,3 +56,39 @@ def test_block_weights_of_a_batched_plan(sh):
         sh.op_destroy(op)
     ref = np.concatenate([measurement.block_density_weights(c[0], n, 2, c[1]) for c in covs])
     np.testing.assert_array_equal(b, ref)
+
+
+def test_one_visibility_blocks_weights_and_solve(sh):
+    """Blocks of one and two visibilities (a single sample in a window: a_b = 1/n) next to a large block:
+    the weights match the oracle exactly and a short solve with them matches the oracle's."""
+    from oracle import sdmm, wavelets
+    from tests import helpers
+    n, m, J = 32, 600, 6
+    pb = helpers.build(31, n, m, 1, J)
+    pb.offsets = np.array([0, 1, 2, 4, m])
+    sizes = np.diff(pb.offsets)
+    pb.eps = np.sqrt(sizes + 2 * np.sqrt(sizes)) * pb.sigma
+    op = sh.op_create(pb.uv, n, 2, J, pb.offsets)
+    psi = sh.psi_create(n, 4)
+    try:
+        b = sh.block_weights(op)
+        a = measurement.block_density_weights(pb.uv, n, 2, pb.offsets)
+        np.testing.assert_array_equal(b, a)
+        assert b[0] == 1.0 / n and b[1] == 1.0 / n
+        spsi = wavelets.SARA(n, 4, 0x1FF)
+        nu = measurement.op_norm(measurement.BlockWeighted(pb.op, pb.offsets, a), np.ones((n, n)), max_iter=200,
+                                 tol=1e-12)
+        gamma = sdmm.default_gamma(pb.op, spsi, pb.y, nu, offsets=pb.offsets, block_weights=a)
+        x_ref, *_ = sdmm.sara(pb.op, spsi, pb.y, pb.offsets, pb.eps,
+                              sdmm.Params(gamma=gamma, nu=nu, max_iter=60, cg_iters=2, block_weights=a))
+        prm = sh.sdmm_default_params()
+        prm.gamma, prm.nu, prm.max_iter = gamma, nu, 60
+        x = torch.empty((n, n), device="cuda")
+        info, _ = sh.sdmm_solve(op, psi, torch.tensor(pb.y.astype(np.complex64), device="cuda"), pb.eps, None, None,
+                                prm, x)
+        err = helpers.rel(x.cpu().numpy().astype(np.float64), x_ref)
+        print(f"one-visibility blocks: image error vs oracle {err:.2e}")
+        assert err <= 1e-4
+    finally:
+        sh.psi_destroy(psi)
+        sh.op_destroy(op)
