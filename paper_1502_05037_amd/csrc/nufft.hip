@@ -150,7 +150,9 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
         ai = fmaf(w1[t1], ri, ai);
       }
     } else {
-#pragma unroll
+      // two rows at a time: a fully unrolled window keeps all J^2 loads live (155 VGPRs, three waves per
+      // SIMD at J = 8); two rows leave 47 VGPRs and eight waves
+#pragma unroll 2
       for (int t1 = 0; t1 < J; ++t1) {
         const float2* row = patch + (lr + t1) * P + lc;
         float rr = 0.f, ri = 0.f;
