@@ -189,7 +189,10 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
 // (64 lanes, 64 distinct addresses, no other wave on this copy) whose write is deferred to the next
 // change so that the read has landed by then.  The wave's cells are non-decreasing, so no later
 // read needs a deferred value.  (LDS float atomics would avoid the read but measure several times
-// slower here.)  Every sum has a fixed order, so the result is reproducible.
+// slower here.)  Every sum has a fixed order, so the result is reproducible.  Latency: the next batch's
+// coordinates and visibilities are loaded while the current batch is accumulated, and in a full batch
+// phase B reads the LDS rows of its next step before the products of the current one (the LDS budget
+// already caps occupancy at five waves per SIMD, so the extra registers cost none).
 template <int J, int T>
 __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ vis,
                                                    const uint32_t* __restrict__ vidx, const int4* __restrict__ items,
@@ -236,8 +239,19 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   int cur = -1, pend = -1;                  // patch offset of tap (0, 0): current run, deferred run
   const int w_lo = it.y + int((int64_t)it.z * wave / 4);
   const int w_hi = it.y + int((int64_t)it.z * (wave + 1) / 4);
+  static_assert(NB == 32, "phase B's full-batch schedule covers 32 visibilities");
   const int vl = lane & (NB - 1);           // this lane's visibility in the batch
   const bool ax2 = lane >= NB;              // lanes NB..63 weigh the second axis
+  // this lane's coordinate and visibility of the next batch, loaded while the current one is accumulated
+  uint2 cn = make_uint2(0u, 0u);
+  float2 vn = make_float2(0.f, 0.f);
+  auto fetch = [&](int j) {
+    if (j < w_hi) {                         // the visibility first: its index may need a load of its own
+      if (!ax2) vn = vis[vidx ? vidx[j] : j];
+      cn = coord[j];
+    }
+  };
+  fetch(w_lo + vl);
   for (int base = w_lo; base < w_hi; base += NB) {
     const int nb = min(NB, w_hi - base);
     int cell = -1;
@@ -250,13 +264,12 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
         for (int t = 0; t < J; ++t) bw[wave][t][vl] = 0.f;
       }
     } else {                                // phase A
-      const int j = base + vl;
-      const uint2 c = coord[j];
+      const uint2 c = cn;
       const float sv = float((ax2 ? c.y : c.x) & fmask) * fs - 1.0f;
       float w[J];
       kb_weights<J>(kc, sv, w);
       if (!ax2) {
-        const float2 v = vis[vidx ? vidx[j] : j];
+        const float2 v = vn;
         const float vr = v.x * scale, vi = v.y * scale;
 #pragma unroll
         for (int t = 0; t < J; ++t) aw[wave][t][vl] = make_float2(w[t] * vr, w[t] * vi);
@@ -266,42 +279,47 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
       }
       cell = (int(c.x >> F) - a0) * P + (int(c.y >> F) - b0);
     }
+    fetch(base + NB + vl);
     // run starts of this batch: lane i starts a run if its cell differs from lane i-1's
     // (lane 0 compares with the run carried over from the previous batch)
     const int prev = __shfl_up(cell, 1);
     const uint64_t starts = __ballot(lane < nb && cell != (lane == 0 ? cur : prev));
     wave_lds_order();                       // phase A rows visible to every lane
     const int nb8 = (nb + 7) & ~7;          // entries up to nb8 exist (padding is zero)
-    for (int k = 0; k < nb8; k += 8) {      // phase B, eight visibilities per step
-      float2 av[NQ][8];
-      float bv[NQ][8];
+    // phase B, eight visibilities per step; in a full batch the LDS reads of the next step are issued
+    // before the products of the current one (two register sets)
+    float2 av[2][NQ][8];
+    float bv[2][NQ][8];
+    auto stage = [&](int s, int k) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
 #pragma unroll
         for (int u = 0; u < 8; u += 2) {
           const float4 a2 = *(const float4*)&aw[wave][tr[q]][k + u];
-          av[q][u] = make_float2(a2.x, a2.y);
-          av[q][u + 1] = make_float2(a2.z, a2.w);
+          av[s][q][u] = make_float2(a2.x, a2.y);
+          av[s][q][u + 1] = make_float2(a2.z, a2.w);
         }
 #pragma unroll
         for (int u = 0; u < 8; u += 4) {
           const float4 b4 = *(const float4*)&bw[wave][tc[q]][k + u];
-          bv[q][u] = b4.x;
-          bv[q][u + 1] = b4.y;
-          bv[q][u + 2] = b4.z;
-          bv[q][u + 3] = b4.w;
+          bv[s][q][u] = b4.x;
+          bv[s][q][u + 1] = b4.y;
+          bv[s][q][u + 2] = b4.z;
+          bv[s][q][u + 3] = b4.w;
         }
       }
+    };
+    auto step = [&](int s, int k) {
       const uint32_t group = uint32_t(starts >> k) & 0xffu;
       if (group == 0) {                     // no run starts here: straight-line accumulation
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            acc[q].x = fmaf(bv[q][u], av[q][u].x, acc[q].x);
-            acc[q].y = fmaf(bv[q][u], av[q][u].y, acc[q].y);
+            acc[q].x = fmaf(bv[s][q][u], av[s][q][u].x, acc[q].x);
+            acc[q].y = fmaf(bv[s][q][u], av[s][q][u].y, acc[q].y);
           }
-        continue;
+        return;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -326,9 +344,24 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          acc[q].x = fmaf(bv[q][u], av[q][u].x, acc[q].x);
-          acc[q].y = fmaf(bv[q][u], av[q][u].y, acc[q].y);
+          acc[q].x = fmaf(bv[s][q][u], av[s][q][u].x, acc[q].x);
+          acc[q].y = fmaf(bv[s][q][u], av[s][q][u].y, acc[q].y);
         }
+      }
+    };
+    if (nb == NB) {                         // a full batch: the schedule is static
+      stage(0, 0);
+      stage(1, 8);
+      step(0, 0);
+      stage(0, 16);
+      step(1, 8);
+      stage(1, 24);
+      step(0, 16);
+      step(1, 24);
+    } else {                                // the wave's last, partial batch
+      for (int k = 0; k < nb8; k += 8) {
+        stage(0, k);
+        step(0, k);
       }
     }
     wave_lds_order();                       // rows of this batch consumed before the next phase A
@@ -374,37 +407,57 @@ __global__ __launch_bounds__(256) void fold_kernel(const float2* __restrict__ pa
   tile_items += prob * nT * nT;
   grid += (size_t)prob * K * K;
   const int l1 = e / T, l2 = e % T;
+  // neighbour n = 3 (da + 1) + (db + 1).  The first item's value of all nine neighbours is loaded
+  // before any is summed, so those loads are in flight together; the load is issued for every
+  // neighbour (slot 0 of the patch array, which always exists, where the neighbour has no item covering
+  // the cell) and its value is replaced by +0, which leaves the sum unchanged since the sum is never -0.
+  int src[9], n0[9], n1[9];
+  float2 first[9];
+#pragma unroll
+  for (int n = 0; n < 9; ++n) {   // the neighbours' slot ranges (uniform: scalar loads, issued together)
+    const int da = n / 3 - 1, db = n % 3 - 1;
+    const int t2 = ((a + da) & (nT - 1)) * nT + ((b + db) & (nT - 1));   // nT is a power of two
+    n0[n] = tile_items[t2];
+    n1[n] = tile_items[t2 + 1];
+  }
+#pragma unroll
+  for (int n = 0; n < 9; ++n) {
+    const int da = n / 3 - 1, db = n % 3 - 1;
+    const int p1 = l1 - da * T + LO, p2 = l2 - db * T + LO;
+    const bool cover = p1 >= 0 && p1 < P && p2 >= 0 && p2 < P;
+    src[n] = p1 * P + p2;
+    if (!cover) n1[n] = n0[n];                      // no items where the patch does not cover the cell
+    const bool has = n0[n] < n1[n];
+    const float2 v = patches[has ? (size_t)n0[n] * (P * P) + src[n] : 0];
+    // the mask goes through an empty asm so that the compiler does not turn the load back into a
+    // conditional one (which would then be waited for before the next neighbour's load)
+    int m = has ? -1 : 0;
+    asm volatile("" : "+v"(m));
+    first[n] = make_float2(__int_as_float(__float_as_int(v.x) & m), __int_as_float(__float_as_int(v.y) & m));
+  }
   float sr = 0.f, si = 0.f;
 #pragma unroll
-  for (int da = -1; da <= 1; ++da) {
-    const int p1 = l1 - da * T + LO;
-    if (p1 < 0 || p1 >= P) continue;
-    const int a2 = (a + da + nT) % nT;
-#pragma unroll
-    for (int db = -1; db <= 1; ++db) {
-      const int p2 = l2 - db * T + LO;
-      if (p2 < 0 || p2 >= P) continue;
-      const int t2 = a2 * nT + (b + db + nT) % nT;
-      const int i0 = tile_items[t2], i1 = tile_items[t2 + 1];
-      const float2* src = patches + p1 * P + p2;
-      int i = i0;
-      for (; i + 4 <= i1; i += 4) {   // four loads in flight; the sum keeps slot order
-        const float2 v0 = src[(size_t)i * (P * P)], v1 = src[(size_t)(i + 1) * (P * P)];
-        const float2 v2 = src[(size_t)(i + 2) * (P * P)], v3 = src[(size_t)(i + 3) * (P * P)];
-        sr += v0.x;
-        si += v0.y;
-        sr += v1.x;
-        si += v1.y;
-        sr += v2.x;
-        si += v2.y;
-        sr += v3.x;
-        si += v3.y;
-      }
-      for (; i < i1; ++i) {
-        const float2 v = src[(size_t)i * (P * P)];
-        sr += v.x;
-        si += v.y;
-      }
+  for (int n = 0; n < 9; ++n) {   // neighbours in order, each one's items in slot order
+    sr += first[n].x;
+    si += first[n].y;
+    const float2* p = patches + src[n];
+    int i = n0[n] + 1;
+    for (; i + 4 <= n1[n]; i += 4) {   // four loads in flight
+      const float2 v0 = p[(size_t)i * (P * P)], v1 = p[(size_t)(i + 1) * (P * P)];
+      const float2 v2 = p[(size_t)(i + 2) * (P * P)], v3 = p[(size_t)(i + 3) * (P * P)];
+      sr += v0.x;
+      si += v0.y;
+      sr += v1.x;
+      si += v1.y;
+      sr += v2.x;
+      si += v2.y;
+      sr += v3.x;
+      si += v3.y;
+    }
+    for (; i < n1[n]; ++i) {
+      const float2 v = p[(size_t)i * (P * P)];
+      sr += v.x;
+      si += v.y;
     }
   }
   grid[(size_t)(a * T + l1) * K + (b * T + l2)] = make_float2(sr, si);
