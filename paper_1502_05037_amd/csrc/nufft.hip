@@ -190,9 +190,10 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
 // change so that the read has landed by then.  The wave's cells are non-decreasing, so no later
 // read needs a deferred value.  (LDS float atomics would avoid the read but measure several times
 // slower here.)  Every sum has a fixed order, so the result is reproducible.  Latency: the next batch's
-// coordinates and visibilities are loaded while the current batch is accumulated, and in a full batch
-// phase B reads the LDS rows of its next step before the products of the current one (the LDS budget
-// already caps occupancy at five waves per SIMD, so the extra registers cost none).
+// coordinates and visibilities are loaded while the current batch is accumulated, and, where the extra
+// registers cost no occupancy (J <= 8 with a patch large enough that LDS already caps the occupancy at
+// five waves per SIMD, as at J = 8, T = 16), phase B reads the LDS rows of a full batch's next step
+// before the products of the current one.
 template <int J, int T>
 __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ vis,
                                                    const uint32_t* __restrict__ vidx, const int4* __restrict__ items,
@@ -209,6 +210,10 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   constexpr int NB = 32, AWP = NB + 2, BWP = NB + 4;
   __shared__ __attribute__((aligned(16))) float2 aw[4][J][AWP];  // w1[t1] * scale * v, current NB visibilities
   __shared__ __attribute__((aligned(16))) float bw[4][J + 1][BWP];  // w2[t2]; row J stays 0
+  // Phase B reads one step ahead (a second register set: about 30 more VGPRs, five waves per SIMD) only
+  // where LDS already limits the occupancy to five work-groups per CU or fewer and a lane has one tap
+  constexpr int LDS_BYTES = int(sizeof(pat) + sizeof(aw) + sizeof(bw));
+  constexpr bool PIPELINE = NQ == 1 && 160 * 1024 / LDS_BYTES <= 5;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   for (int e = tid; e < 4 * PP; e += 256) (&pat[0][0])[e] = make_float2(0.f, 0.f);
@@ -286,8 +291,8 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
     const uint64_t starts = __ballot(lane < nb && cell != (lane == 0 ? cur : prev));
     wave_lds_order();                       // phase A rows visible to every lane
     const int nb8 = (nb + 7) & ~7;          // entries up to nb8 exist (padding is zero)
-    // phase B, eight visibilities per step; in a full batch the LDS reads of the next step are issued
-    // before the products of the current one (two register sets)
+    // phase B, eight visibilities per step; with PIPELINE, in a full batch the LDS reads of the next step
+    // are issued before the products of the current one (two register sets)
     float2 av[2][NQ][8];
     float bv[2][NQ][8];
     auto stage = [&](int s, int k) {
@@ -349,7 +354,7 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
         }
       }
     };
-    if (nb == NB) {                         // a full batch: the schedule is static
+    if (PIPELINE && nb == NB) {             // a full batch: the schedule is static
       stage(0, 0);
       stage(1, 8);
       step(0, 0);
