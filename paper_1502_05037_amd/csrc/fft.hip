@@ -250,9 +250,16 @@ sh_status launch_len(int per, int P, const void* in, void* out, const float2* tw
   constexpr int B = (8192 / L) < 1 ? 1 : (8192 / L);
   int b = B > 64 ? 64 : B;
   while (b > per) b >>= 1;  // few sequences (tiny images): shrink the batch
-  // fewer than two work-groups per CU: shrink the batch (down to one wave per work-group) so that more
-  // CUs share the pass
-  while (b > 1 && (b / 2) * L / 8 >= 64 && int64_t(P) * (per / b) < 512) b >>= 1;
+  // Shrink the batch (down to one wave per work-group) while the pass has fewer than two work-groups per
+  // CU, so that more CUs share it, and further up to eight per CU, which hides more of each
+  // work-group's load-transform-store latency; a pass that reads or writes columns of a row-major array
+  // stops at four columns (32 contiguous bytes of each row) once it has two work-groups per CU, since
+  // narrower column reads cost more than the extra work-groups gain.
+  constexpr bool STRIDED = MODE == COLS_FWD || MODE == COLS_ADJ || MODE == COLS_TOEP || MODE == FULL_COLS;
+  auto groups = [&](int bb) { return int64_t(P) * (per / bb); };
+  while (b > 1 && (b / 2) * L / 8 >= 64 &&
+         (groups(b) < 512 || (groups(b) < 2048 && (!STRIDED || b / 2 >= 4))))
+    b >>= 1;
   const size_t lds = size_t(b) * L * sizeof(float2);
 #define SH_FFT_CASE(BB)                                                                                  \
   if (b == BB) {                                                                                         \
