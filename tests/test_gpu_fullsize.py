@@ -12,13 +12,15 @@ the oracle's answer is exact for a part of it:
   full plan (every work item, every fold cell); the oracle adjoint of the samples alone is its exact
   image.
 * The adjoint identity <Phi x, v> = <x, Phi^dagger v> with x and v dense over all 2e7 visibilities.
+* The per-block l2-ball projection and dual update over the plan's 64 blocks, element-wise against the
+  oracle's closed form, with the float64 block norms.
 
 Bar: norm-wise relative error <= 1e-5 (as at the small sizes).
 """
 import numpy as np
 import pytest
 
-from oracle import measurement
+from oracle import measurement, prox
 from paper_1502_05037_amd import synth
 from tests import helpers
 
@@ -100,3 +102,34 @@ def test_adjoint_identity_dense(sh, full):
     print(f"<Phi x, v> = {lhs:.6e}, <x, Phi^dagger v> = {rhs:.6e}, |diff| / (|v| |Phi x|) = "
           f"{abs(lhs - rhs) / scale:.2e}", flush=True)
     assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_ball_projection_all_blocks(sh, full):
+    op, off = full["op"], full["off"]
+    g = synth.rng(CFG, 4, 0)
+    cplx = lambda k: (g.normal(size=k) + 1j * g.normal(size=k)).astype(np.complex64)
+    s, z, yh = cplx(M), 0.1 * cplx(M), cplx(M)
+    t64 = s.astype(np.complex128) + z.astype(np.complex128)
+    y64 = yh.astype(np.complex128)
+    # blocks inside, on and outside their balls
+    f = np.resize([0.5, 1.0, 2.0, 0.1, 1.5, 0.9, 1e-3], R)
+    eps = np.array([np.linalg.norm(t64[off[i]:off[i + 1]] - y64[off[i]:off[i + 1]]) * f[i] for i in range(R)])
+    zd = torch.tensor(z, device="cuda")
+    vd = torch.empty(M, dtype=torch.complex64, device="cuda")
+    resid = torch.empty(R, dtype=torch.float64, device="cuda")
+    sh.prox_ball(op, torch.tensor(s, device="cuda"), zd, torch.tensor(yh, device="cuda"),
+                 torch.tensor(eps, dtype=torch.float64, device="cuda"), vd, resid)
+    torch.cuda.synchronize()
+    zg, vg, rg = zd.cpu().numpy(), vd.cpu().numpy(), resid.cpu().numpy()
+    s64 = s.astype(np.complex128)
+    worst_z = worst_v = 0.0
+    for i in range(R):
+        lo, hi = off[i], off[i + 1]
+        y = prox.ball(t64[lo:hi], y64[lo:hi], eps[i])
+        zr = t64[lo:hi] - y
+        worst_z = max(worst_z, float(np.max(np.abs(zg[lo:hi] - zr))))
+        worst_v = max(worst_v, float(np.max(np.abs(vg[lo:hi] - (y - zr)))))
+        assert rg[i] == pytest.approx(np.linalg.norm(s64[lo:hi] - y64[lo:hi]), rel=1e-12)
+    print(f"ball projection over {R} blocks of {M} visibilities: max |dz| {worst_z:.2e}, max |dv| {worst_v:.2e}",
+          flush=True)
+    assert worst_z <= 2e-6 and worst_v <= 4e-6

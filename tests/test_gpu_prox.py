@@ -27,7 +27,8 @@ def _dev(a, dtype=torch.float32):
     return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
 
 
-@pytest.mark.parametrize("D,weighted", [(1, False), (1000, True), (100003, True), (589824, False)])
+@pytest.mark.parametrize("D,weighted", [(1, False), (1000, True), (100003, True), (589824, False),
+                                        (9 * 1024 * 1024, True)])   # the 1024^2 SARA coefficient vector
 def test_prox_l1(sh, D, weighted):
     g = synth.rng(31, D, 0)
     s, z = _f32(g.normal(size=D)), _f32(0.3 * g.normal(size=D))
