@@ -14,6 +14,9 @@ the oracle's answer is exact for a part of it:
 * The adjoint identity <Phi x, v> = <x, Phi^dagger v> with x and v dense over all 2e7 visibilities.
 * The per-block l2-ball projection and dual update over the plan's 64 blocks, element-wise against the
   oracle's closed form, with the float64 block norms.
+* The same sampled checks of Phi and Phi^dagger for the batched workload: 32 problems of 256 x 256 with
+  1e5..1e6 visibilities each (1.15e7 in all) in one plan with the tuner's choice for it (J = 6, tile 16,
+  work items of at most 1024 visibilities).
 
 Bar: norm-wise relative error <= 1e-5 (as at the small sizes).
 """
@@ -133,3 +136,59 @@ def test_ball_projection_all_blocks(sh, full):
     print(f"ball projection over {R} blocks of {M} visibilities: max |dz| {worst_z:.2e}, max |dv| {worst_v:.2e}",
           flush=True)
     assert worst_z <= 2e-6 and worst_v <= 4e-6
+
+
+@pytest.fixture(scope="module")
+def batched(sh):
+    import bench
+    bw = bench.batched_workload()
+    print(f"batched full-size parity: {bw['P']} problems of {bw['n']}^2, M = {int(bw['M_p'].sum())}", flush=True)
+    op = sh.op_create_batched(bw["uv"], bw["M_p"], bw["n"], 2, 6, bw["off"], bw["R_p"], tile=16, chunk=1024)
+    q = sh.op_query(op)
+    assert (q["P"], q["J"], q["tile"]) == (bw["P"], 6, 16)
+    yield bw, op
+    sh.op_destroy(op)
+
+
+def _problem_of(bw, idx):
+    starts = np.concatenate([[0], np.cumsum(bw["M_p"])])
+    return np.searchsorted(starts, idx, side="right") - 1, starts
+
+
+def test_batched_forward_sampled_entries(sh, batched):
+    bw, op = batched
+    Mt, n = int(bw["M_p"].sum()), bw["n"]
+    vis = torch.empty(Mt, dtype=torch.complex64, device="cuda")
+    sh.phi_fwd(op, torch.tensor(bw["x_true"], device="cuda"), vis)
+    torch.cuda.synchronize()
+    idx = np.sort(synth.rng(4, 1, synth.UV).choice(Mt, 4096, replace=False))
+    prob, _ = _problem_of(bw, idx)
+    got = vis.cpu().numpy()[idx].astype(np.complex128)
+    ref = np.empty(len(idx), dtype=np.complex128)
+    for p in np.unique(prob):
+        sel = prob == p
+        ref[sel] = measurement.NUFFT(bw["uv"][idx[sel]], n, 6).fwd(bw["x_true"][p].astype(np.float64))
+    err = helpers.rel(got, ref)
+    print(f"batched Phi: rel error {err:.2e} on {len(idx)} sampled visibilities", flush=True)
+    assert err <= TOL
+
+
+def test_batched_adjoint_of_sampled_visibilities(sh, batched):
+    bw, op = batched
+    Mt, n, P = int(bw["M_p"].sum()), bw["n"], bw["P"]
+    idx = np.sort(synth.rng(4, 2, synth.UV).choice(Mt, 20_000, replace=False))
+    vs = synth.complex_normal(len(idx), synth.rng(4, 2, synth.NOISE)).astype(np.complex64)
+    v = np.zeros(Mt, dtype=np.complex64)
+    v[idx] = vs
+    xa = torch.empty((P, n, n), dtype=torch.float32, device="cuda")
+    sh.phi_adj(op, torch.tensor(v, device="cuda"), xa)
+    torch.cuda.synchronize()
+    got = xa.cpu().numpy().astype(np.float64)
+    prob, _ = _problem_of(bw, idx)
+    ref = np.zeros((P, n, n))
+    for p in np.unique(prob):
+        sel = prob == p
+        ref[p] = measurement.NUFFT(bw["uv"][idx[sel]], n, 6).adj(vs[sel].astype(np.complex128))
+    err = helpers.rel(got, ref)
+    print(f"batched Phi^dagger of {len(idx)} sampled visibilities: rel error {err:.2e}", flush=True)
+    assert err <= TOL
