@@ -15,8 +15,9 @@
 // multiple of 16; gathered inside the product's staging, never stored) times the weight matrix, and the
 // forward and input-gradient products use one kernel of the "NT" form
 // C[m][n] = sum_k A[m][k] B[n][k] with both operands contiguous along k (v_mfma_f32_16x16x16_bf16,
-// 64 x 64 tiles per work-group of four waves, k staged through LDS 64 at a time with the next slab
-// prefetched into registers, optional split-K
+// 64 x 64 tiles per work-group of four waves, or 128 x 32 for products with at most 32 columns so that
+// no half of the tile is padding, k staged through LDS 64 at a time with the next slab prefetched into
+// registers, optional split-K
 // with a fixed-order reduction).  Weight gradients contract over pixels: their kernel ("TN") reads both
 // operands pixel-major as stored (the im2col again gathered) and transposes them on the way into LDS;
 // a column of ones on the second operand yields the bias gradient in the same product.  Results are
@@ -60,40 +61,48 @@ struct Im2col {
   int ldx, H, W, C;
 };
 
-template <bool GATHER>
+template <bool GATHER, int WN>
 __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, int lda, const uint16_t* __restrict__ B,
                                                int ldb, int M, int N, int K, int kchunk,
                                                const float* __restrict__ bias, int relu, float* __restrict__ C,
                                                int ldc, uint16_t* __restrict__ Cb, int ldcb, Im2col g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GLD];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GLD];
+  // tile TM x TN: 64 x 64 (four waves 2 x 2) or, for products with at most 32 columns, 128 x 32 (4 x 1)
+  constexpr int TM = 128 / WN, TN = 32 * WN, AR = TM / 64, BU = TN / 32;
+  __shared__ __attribute__((aligned(16))) uint16_t As[TM][GLD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int wm = wave / WN, wn = wave % WN;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 2, lc = (tid & 3) * 16;   // tile row lr (0..63), k-values lc .. lc + 15
-  uint4 ra[2], rb[2];
-  // gather mode: the pixel of this thread's A row
-  int gb = 0, gy = 0, gx = 0;
-  if constexpr (GATHER) {
-    const int m = m0 + lr;
-    gb = m / (g.H * g.W);
-    const int rem = m - gb * g.H * g.W;
-    gy = rem / g.W;
-    gx = rem - gy * g.W;
+  // A: tile rows lr (+ 64), k-values lc .. lc + 15; B: rows br, k-values bc .. bc + 8 BU - 1
+  const int lr = tid >> 2, lc = (tid & 3) * 16;
+  const int br = BU == 2 ? lr : (tid >> 3), bc = BU == 2 ? lc : (tid & 7) * 8;
+  uint4 ra[AR][2], rb[BU];
+  // gather mode: the pixels of this thread's A rows
+  int gb[AR], gy[AR], gx[AR];
+#pragma unroll
+  for (int r = 0; r < AR; ++r) {
+    gb[r] = gy[r] = gx[r] = 0;
+    if constexpr (GATHER) {
+      const int m = m0 + lr + 64 * r;
+      gb[r] = m / (g.H * g.W);
+      const int rem = m - gb[r] * g.H * g.W;
+      gy[r] = rem / g.W;
+      gx[r] = rem - gy[r] * g.W;
+    }
   }
-  auto gather8 = [&](int k) -> uint4 {   // A[m0 + lr][k .. k+7] of the implicit im2col
+  auto gather8 = [&](int r, int k) -> uint4 {   // A[m0 + lr + 64 r][k .. k+7] of the implicit im2col
     if ((g.C & 7) == 0) {
       if (k >= 9 * g.C) return make_uint4(0, 0, 0, 0);
       const int tap = k / g.C, c = k - tap * g.C;
-      const int sy = gy + tap / 3 - 1, sx = gx + tap % 3 - 1;
+      const int sy = gy[r] + tap / 3 - 1, sx = gx[r] + tap % 3 - 1;
       if (sy < 0 || sy >= g.H || sx < 0 || sx >= g.W) return make_uint4(0, 0, 0, 0);
-      return *(const uint4*)(g.x + ((int64_t)(gb * g.H + sy) * g.W + sx) * g.ldx + c);
+      return *(const uint4*)(g.x + ((int64_t)(gb[r] * g.H + sy) * g.W + sx) * g.ldx + c);
     }
     uint16_t v[8];
 #pragma unroll
@@ -102,8 +111,9 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
       v[q] = 0;
       if (kq < 9 * g.C) {
         const int tap = kq / g.C, c = kq - tap * g.C;
-        const int sy = gy + tap / 3 - 1, sx = gx + tap % 3 - 1;
-        if (sy >= 0 && sy < g.H && sx >= 0 && sx < g.W) v[q] = g.x[((int64_t)(gb * g.H + sy) * g.W + sx) * g.ldx + c];
+        const int sy = gy[r] + tap / 3 - 1, sx = gx[r] + tap % 3 - 1;
+        if (sy >= 0 && sy < g.H && sx >= 0 && sx < g.W)
+          v[q] = g.x[((int64_t)(gb[r] * g.H + sy) * g.W + sx) * g.ldx + c];
       }
     }
     return make_uint4(v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
@@ -111,22 +121,29 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
   };
   auto load = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int k = k0 + lc + 8 * e;
-      if constexpr (GATHER)
-        ra[e] = (m0 + lr < M && k < ke) ? gather8(k) : make_uint4(0, 0, 0, 0);
-      else
-        ra[e] = (m0 + lr < M && k < ke) ? *(const uint4*)(A + (int64_t)(m0 + lr) * lda + k) : make_uint4(0, 0, 0, 0);
-      rb[e] = (n0 + lr < N && k < ke) ? *(const uint4*)(B + (int64_t)(n0 + lr) * ldb + k) : make_uint4(0, 0, 0, 0);
+    for (int r = 0; r < AR; ++r)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int k = k0 + lc + 8 * e, m = m0 + lr + 64 * r;
+        if constexpr (GATHER)
+          ra[r][e] = (m < M && k < ke) ? gather8(r, k) : make_uint4(0, 0, 0, 0);
+        else
+          ra[r][e] = (m < M && k < ke) ? *(const uint4*)(A + (int64_t)m * lda + k) : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+    for (int e = 0; e < BU; ++e) {
+      const int k = k0 + bc + 8 * e;
+      rb[e] = (n0 + br < N && k < ke) ? *(const uint4*)(B + (int64_t)(n0 + br) * ldb + k) : make_uint4(0, 0, 0, 0);
     }
   };
   if (kb < ke) load(kb);
   for (int k0 = kb; k0 < ke; k0 += GBK) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      *(uint4*)&As[lr][lc + 8 * e] = ra[e];
-      *(uint4*)&Bs[lr][lc + 8 * e] = rb[e];
-    }
+    for (int r = 0; r < AR; ++r)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) *(uint4*)&As[lr + 64 * r][lc + 8 * e] = ra[r][e];
+#pragma unroll
+    for (int e = 0; e < BU; ++e) *(uint4*)&Bs[br][bc + 8 * e] = rb[e];
     __syncthreads();
     if (k0 + GBK < ke) load(k0 + GBK);   // in flight during the products below
 #pragma unroll
@@ -639,8 +656,11 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
                const float* bias, bool relu, float* C, int ldc, uint16_t* Cb, int ldcb, bool allow_split,
                hipStream_t st, const Im2col* gat = nullptr) {
   SH_REQUIRE(K % 16 == 0 && K > 0, "internal: GEMM K = %lld not a multiple of 16", (long long)K);
-  SH_REQUIRE(M < (int64_t(1) << 31) / GBM, "internal: GEMM M too large");
-  const unsigned gx = (unsigned)sh::cdiv(N, GBN), gy = (unsigned)sh::cdiv(M, GBM);
+  SH_REQUIRE(M < (int64_t(1) << 31) / 128, "internal: GEMM M too large");
+  // products with at most 32 columns take the 128 x 32 tile, the others 64 x 64
+  const bool narrow = N <= 32;
+  const int TM = narrow ? 128 : 64, TN = narrow ? 32 : 64;
+  const unsigned gx = (unsigned)sh::cdiv(N, TN), gy = (unsigned)sh::cdiv(M, TM);
   int S = 1;
   if (allow_split) {
     const int64_t tiles = (int64_t)gx * gy;
@@ -653,15 +673,27 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
   if (gat) {
     SH_REQUIRE(S == 1 && M == (int64_t)u->ap->B * gat->H * gat->W && K == rup(9 * gat->C, 16),
                "internal: implicit im2col shape");
-    hipLaunchKernelGGL(gemm_nt<true>, dim3(gx, gy, 1), dim3(256), 0, st, nullptr, 0, B, ldb, (int)M, N, (int)K,
-                       (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat);
+    if (narrow)
+      hipLaunchKernelGGL((gemm_nt<true, 1>), dim3(gx, gy, 1), dim3(256), 0, st, nullptr, 0, B, ldb, (int)M, N, (int)K,
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat);
+    else
+      hipLaunchKernelGGL((gemm_nt<true, 2>), dim3(gx, gy, 1), dim3(256), 0, st, nullptr, 0, B, ldb, (int)M, N, (int)K,
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat);
   } else if (S == 1) {
-    hipLaunchKernelGGL(gemm_nt<false>, dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                       (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0);
+    if (narrow)
+      hipLaunchKernelGGL((gemm_nt<false, 1>), dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0);
+    else
+      hipLaunchKernelGGL((gemm_nt<false, 2>), dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0);
   } else {
     SH_REQUIRE(C && !Cb && !bias && !relu && ldc == N, "internal: split GEMM writes plain fp32");
-    hipLaunchKernelGGL(gemm_nt<false>, dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                       (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0);
+    if (narrow)
+      hipLaunchKernelGGL((gemm_nt<false, 1>), dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
+                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0);
+    else
+      hipLaunchKernelGGL((gemm_nt<false, 2>), dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
+                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0);
     hipLaunchKernelGGL(sum_splits, dim3(nb(M * N)), dim3(256), 0, st, u->ap->part.ptr, S, M * N, C);
   }
   SH_LAUNCHED();
