@@ -227,3 +227,47 @@ def test_batched_adjoint_of_sampled_visibilities(sh, batched):
     err = helpers.rel(got, ref)
     print(f"batched Phi^dagger of {len(idx)} sampled visibilities: rel error {err:.2e}", flush=True)
     assert err <= TOL
+
+
+def test_largest_grid_against_direct_dft(sh):
+    """n = 4096, alpha = 2: the largest grid side (8192) and FFT length the library accepts.  Phi at 64
+    sampled visibilities and Phi^dagger of those 64 samples against the oracle's direct DFT (exact
+    discretised measurement equation; the NUFFT's own error at J = 8 is ~2e-7), and the Toeplitz product
+    of a point source against k(d) summed directly."""
+    n, m, J = 4096, 20_000, 8
+    uv = synth.sort_by_radius(synth.uv_radial(m, synth.rng(CFG, 7, synth.UV)))
+    off = synth.offsets(synth.block_sizes(m, 4, synth.rng(CFG, 7, synth.BLOCKS)))
+    x = synth.sky(n, 20, 3.0, synth.rng(CFG, 7, synth.SKY)).astype(np.float32)
+    idx = np.sort(synth.rng(CFG, 8, synth.UV).choice(m, 64, replace=False))
+    vs = synth.complex_normal(len(idx), synth.rng(CFG, 8, synth.NOISE)).astype(np.complex64)
+    v = np.zeros(m, dtype=np.complex64)
+    v[idx] = vs
+    op = sh.op_create(uv, n, 2, J, off)
+    try:
+        assert sh.op_query(op)["K"] == 8192
+        vis = torch.empty(m, dtype=torch.complex64, device="cuda")
+        sh.phi_fwd(op, torch.tensor(x, device="cuda"), vis)
+        xa = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        sh.phi_adj(op, torch.tensor(v, device="cuda"), xa)
+        c = (n // 2 - 700, n // 2 + 1234)
+        delta = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+        delta[c] = 1.0
+        t = sh.toeplitz_create(op)
+        try:
+            tout = torch.empty_like(delta)
+            sh.toeplitz_apply(t, delta, tout)
+            torch.cuda.synchronize()
+        finally:
+            sh.toeplitz_destroy(t)
+    finally:
+        sh.op_destroy(op)
+    dft = measurement.DFT(uv[idx], n)
+    e_fwd = helpers.rel(vis.cpu().numpy()[idx].astype(np.complex128), dft.fwd(x.astype(np.float64)))
+    e_adj = helpers.rel(xa.cpu().numpy().astype(np.float64), dft.adj(vs.astype(np.complex128)))
+    pix = [c, (c[0] + 1, c[1] - 1)] + [tuple(int(q) for q in synth.rng(CFG, 9, synth.SKY).integers(0, n, 2))
+                                       for _ in range(6)]
+    got = np.array([float(tout[p].item()) for p in pix])
+    ref = np.array([np.sum(np.cos(uv @ np.array([p[0] - c[0], p[1] - c[1]], dtype=np.float64))) for p in pix])
+    e_toep = helpers.rel(got, ref)
+    print(f"n = {n}, K = 8192: Phi rel error {e_fwd:.2e}, Phi^dagger {e_adj:.2e}, Toeplitz {e_toep:.2e}", flush=True)
+    assert e_fwd <= TOL and e_adj <= TOL and e_toep <= TOL
