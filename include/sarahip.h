@@ -226,7 +226,8 @@ typedef struct {
   double tol_rel;      /* stop when ||x_n - x_{n-1}||/||x_n|| <= tol_rel and all blocks feasible;
                           0 = run max_iter every pass (fixed schedule) */
   double eps_slack;    /* feasibility test ||y_i - Phi_i x|| <= eps_i (1 + eps_slack) */
-  double rw_beta;      /* delta_{t+1} = rw_beta * delta_t */
+  double rw_beta;      /* delta_{t+1} = rw_beta * delta_t.  Between passes W = delta / (delta + |Psi^dagger x|),
+                          and W = 1 where both are 0 (a pass that ended at x = 0 gives delta = 0) */
   double rw_delta0;    /* > 0: delta of the weights W passed in (warm start); else delta_1 = std */
   int32_t max_iter;    /* SDMM iterations per pass */
   int32_t cg_iters;    /* conjugate-gradient steps per x-update */

@@ -201,8 +201,12 @@ def sdmm_pass(pb: Problem, W, p: Params, st: State, record=False):
 
 
 def reweight(coeffs: np.ndarray, delta: float) -> np.ndarray:
-    """SARA weights w = delta / (delta + |c|), in (0, 1]."""
-    return delta / (delta + np.abs(coeffs))
+    """SARA weights w = delta / (delta + |c|), in [0, 1].  Where delta + |c| = 0 (delta = 0 after a pass
+    whose image has all analysis coefficients zero, at a zero coefficient) the weight is 1, the rule's
+    value at c = 0 for every delta > 0."""
+    c = np.abs(np.asarray(coeffs, dtype=np.float64))
+    den = delta + c
+    return np.where(den > 0, delta / np.where(den > 0, den, 1.0), 1.0)
 
 
 def sara(op, psi, y, offsets, eps, p: Params, x0=None, W0=None, delta0=None, record=False):

@@ -305,7 +305,8 @@ __global__ __launch_bounds__(256) void reweight_kernel(int64_t per, const float*
   if (j >= per) return;
   const int64_t i = (int64_t)blockIdx.y * per + j;
   const double dl = delta_d ? delta_d[blockIdx.y] : delta;
-  W[i] = float(dl / (dl + fabs(double(c[i]))));
+  const double den = dl + fabs(double(c[i]));
+  W[i] = den > 0 ? float(dl / den) : 1.f;   // delta = 0 at a zero coefficient: the rule's value at c = 0
 }
 
 }  // namespace

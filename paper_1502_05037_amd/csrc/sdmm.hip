@@ -179,6 +179,7 @@ struct sh_sdmm_s {
   int64_t N = 0, M = 0, D = 0;     // totals over the P problems
   int R = 0, kcg = 0;
   std::vector<double> nu, gamma, delta;   // per problem
+  bool have_delta = false;                 // delta holds a reweighting delta (given, or from a pass)
   std::vector<double> cb;          // c_b per block (host)
   std::vector<double> eh;          // eps_hat = c_b eps per block (host)
   const float* Wp = nullptr;       // weights of the current pass (NULL = identity)
@@ -307,7 +308,8 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     SH_HIP(hipMemcpyAsync(w.W.ptr, W0, D * sizeof(float), hipMemcpyDeviceToDevice, st));
     s->Wp = w.W.ptr;
   }
-  s->delta.assign(P, s->prm.rw_delta0 > 0 && W0 ? s->prm.rw_delta0 : 0.0);
+  s->have_delta = s->prm.rw_delta0 > 0 && W0;
+  s->delta.assign(P, s->have_delta ? s->prm.rw_delta0 : 0.0);
   // initial state: zero, or y_psi = Psi^dagger x0, y_phi = Phi_hat x0, y_+ = x0, z = 0
   SH_HIP(hipMemsetAsync(w.zpsi.ptr, 0, D * sizeof(float), st));
   SH_HIP(hipMemsetAsync(w.zphi.ptr, 0, M * sizeof(float2), st));
@@ -328,6 +330,7 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   if (s->prm.w_from_x0) {   // weights of the first pass from Psi^dagger x0 (delta_1 = std per problem)
     SH_TRY(sh_psi_adj(s->psi, x0, w.spsi.ptr, st));
     std::fill(s->delta.begin(), s->delta.end(), 0.0);
+    s->have_delta = false;
     SH_TRY(sdmm_reweight(s, w.W.ptr, st));
     s->Wp = w.W.ptr;
   }
@@ -455,7 +458,7 @@ sh_status sdmm_read(sh_sdmm s, std::vector<double>& rel, std::vector<double>& hr
 sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st) {
   Work& w = s->w;
   const int P = s->P;
-  if (!(s->delta[0] > 0)) {
+  if (!s->have_delta) {   // the first reweighting: delta_1 = std of the analysis coefficients
     double* sum = s->s_misc + MISC_TMP * P;
     double* var = s->s_misc + MISC_TMP2 * P;
     SH_TRY(w.red.std_dev(w.spsi.ptr, s->Dper, sum, var, st));
@@ -463,13 +466,15 @@ sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st) {
     SH_HIP(hipMemcpyAsync(v.data(), var, P * sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));
     for (int p = 0; p < P; ++p) s->delta[p] = std::sqrt(v[p] / double(s->Dper));
+    s->have_delta = true;
   } else {
     for (int p = 0; p < P; ++p) s->delta[p] *= s->prm.rw_beta;
   }
+  // delta = 0 (a pass that ended at x = 0) is valid: the weights are then 1 at zero coefficients
   for (int p = 0; p < P; ++p)
-    if (!(s->delta[p] > 0) || !std::isfinite(s->delta[p])) {
-      sh::set_error("reweighting delta of problem %d is %g (zero image?)", p, s->delta[p]);
-      return s->delta[p] == 0 ? SH_EINVAL : SH_ENONFINITE;
+    if (!(s->delta[p] >= 0) || !std::isfinite(s->delta[p])) {
+      sh::set_error("reweighting delta of problem %d is %g", p, s->delta[p]);
+      return SH_ENONFINITE;
     }
   SH_HIP(hipMemcpyAsync(w.delta.ptr, s->delta.data(), P * sizeof(double), hipMemcpyHostToDevice, st));
   SH_TRY(sh::launch_reweight(s->Dper, P, w.spsi.ptr, w.delta.ptr, 0.0, W_dst, st));

@@ -4,6 +4,8 @@ Fixed schedules (tol_rel = 0) with the same nu, gamma and CG step count on both 
 within 1e-4 relative (norm-wise).  Runs to tolerance: every block satisfies
 ||y_i - Phi_i x|| <= eps_i (1 + 1e-4), re-evaluated with the oracle's FP64 operator.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -219,3 +221,16 @@ def test_four_times_oversampled_grid_parity(sh):
     print(f"alpha 4: image error vs oracle {err:.3e}")
     assert err <= 1e-4
     np.testing.assert_allclose(resid, infos[-1].block_resid, rtol=1e-4)
+
+
+def test_covering_eps_gives_the_zero_image(sh):
+    """eps_i >= ||y_i|| in every block, the method's degenerate case: x = 0 is feasible and minimises
+    ||W Psi^dagger x||_1.  Three passes from zero stay exactly at zero, and the weights after a pass
+    that ended at x = 0 (delta = 0) are 1 (the oracle's reading), not 0/0."""
+    pb = helpers.build(3, 32, 900, 2, 8, prob=2)
+    eps = np.array([1.5 * np.linalg.norm(pb.y[pb.offsets[i]:pb.offsets[i + 1]]) for i in range(len(pb.eps))])
+    pb = dataclasses.replace(pb, eps=eps)
+    x, info, resid, W = _gpu_solve(sh, pb, _params(sh, max_iter=40, passes=3, tol_rel=1e-4), want_W=True)
+    assert np.all(x == 0)
+    assert np.all(W == 1.0)
+    assert np.all(np.asarray(resid) <= eps)

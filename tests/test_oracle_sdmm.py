@@ -215,6 +215,26 @@ def test_reweight_invariants():
     assert w[0] == 1.0
     assert np.all((w > 0) & (w <= 1))
     assert w[3] < w[2] < w[1] < w[0]
+    # delta = 0 (a pass that ended at x = 0): the weight of a zero coefficient is the limit of the rule
+    # at c = 0 as delta -> 0+, i.e. 1; a non-zero coefficient gets 0, the rule's own value
+    w0 = sdmm.reweight(np.array([0.0, -0.0, 3.0]), 0.0)
+    assert np.array_equal(w0, [1.0, 1.0, 0.0])
+    assert sdmm.reweight(np.array([0.0]), 1e-300)[0] == 1.0
+
+
+def test_covering_eps_gives_the_zero_image_through_every_pass():
+    """eps_i >= ||y_i|| in every block: x = 0 is feasible and minimises ||W Psi^dagger x||_1 for any
+    W.  From zero SARA stays exactly at zero through all passes (delta = 0 after the first: weights 1,
+    not 0/0)."""
+    op, psi, y, off, _ = _tiny_problem(R=2, seed=6)
+    yb = np.asarray(y)
+    eps = np.array([1.5 * np.linalg.norm(yb[off[i]:off[i + 1]]) for i in range(len(off) - 1)])
+    nu = measurement.op_norm(op, np.ones((psi.n, psi.n)), max_iter=500, tol=0.0)
+    gamma = sdmm.default_gamma(op, psi, y, nu)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=40, passes=3)
+    x, W, infos, _ = sdmm.sara(op, psi, y, off, eps, p)
+    assert np.all(x == 0) and np.all(W == 1.0)
+    assert all(np.all(i.block_resid <= eps) for i in infos)
 
 
 def test_sara_passes_reweight_and_warm_start():
