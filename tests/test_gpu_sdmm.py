@@ -234,3 +234,18 @@ def test_covering_eps_gives_the_zero_image(sh):
     assert np.all(x == 0)
     assert np.all(W == 1.0)
     assert np.all(np.asarray(resid) <= eps)
+
+
+@pytest.mark.parametrize("mask,name", [(0x1, "Dirac only"), (1 << 8, "db8 only"), (0b100000110, "Dirac-free db1+db2+db8")])
+def test_other_analysis_priors_fixed_schedule_parity(sh, mask, name):
+    """The same SDMM with another analysis dictionary than SARA's nine bases (the prior enters only
+    through Psi): two reweighted passes, fixed schedule, against the oracle with the same dictionary."""
+    pb = helpers.build(2, 32, 1200, 3, 6, prob=1)
+    psi, nu, gamma, a = _oracle_setup(pb, mask=mask)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=80, cg_iters=8, passes=2, block_weights=a)
+    x_ref, *_ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
+    x, info, _, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=80, cg_iters=8, passes=2,
+                                               tol_rel=0.0), mask=mask)
+    err = helpers.rel(x, x_ref)
+    print(f"{name} (mask {mask:#x}): image error vs oracle {err:.3e}", flush=True)
+    assert err <= 1e-4
