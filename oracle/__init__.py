@@ -8,7 +8,9 @@ from ``paper_1502_05037_amd.synth``, which draws random numbers only.
 Modules
 -------
 kb           Kaiser-Bessel interpolation kernel and its Fourier transform.
-measurement  The measurement operator: direct DFT, FP64 NUFFT, operator norm.
+measurement  The measurement operator: direct DFT, FP64 NUFFT (numpy, and a variant whose
+             interpolation loops are compiled C for millions of visibilities), operator norm.
+nufft_c.c    Those compiled loops (plain C + OpenMP, float64); cbuild.py builds and loads them.
 wavelets     Daubechies filters, periodic DWT, the SARA dictionary.
 prox         Soft threshold, l2-ball projection, positive-orthant projection.
 sdmm         SDMM on problem (3), conjugate-gradient x-update, SARA reweighting,

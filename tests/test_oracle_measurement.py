@@ -82,12 +82,16 @@ def test_dft_adjoint_identities():
     assert np.vdot(v, op.fwd_complex(xc)) == pytest.approx(np.vdot(op.adj_complex(v), xc), rel=1e-12)
 
 
+NUFFTS = [measurement.NUFFT, measurement.NUFFTCompiled]
+
+
+@pytest.mark.parametrize("cls", NUFFTS)
 @pytest.mark.parametrize("n,m,J,bound", [(64, 2048, 6, 2e-5), (64, 2048, 8, 2e-7), (32, 700, 6, 2e-5)])
-def test_nufft_matches_dft(n, m, J, bound):
+def test_nufft_matches_dft(n, m, J, bound, cls):
     uv = _uv(m, 3)
     x = synth.sky(n, 20, 3.0, synth.rng(99, 3, synth.SKY))
     dft = measurement.DFT(uv, n)
-    nu = measurement.NUFFT(uv, n, J)
+    nu = cls(uv, n, J)
     a, b = nu.fwd(x), dft.fwd(x)
     assert np.linalg.norm(a - b) / np.linalg.norm(b) <= bound
     v = synth.complex_normal(m, synth.rng(99, 3, synth.NOISE))
@@ -105,24 +109,59 @@ def test_nufft_matches_dft_subset_256():
     assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 2e-5
 
 
-def test_nufft_radial_wraparound_edges():
+@pytest.mark.parametrize("cls", NUFFTS)
+def test_nufft_radial_wraparound_edges(cls):
     # points on the grid edge (kappa near -K/2 and +K/2) exercise the modulo taps
     n = 32
     uv = np.array([[-np.pi, -np.pi], [np.nextafter(np.pi, 0), 0.3], [0.0, np.nextafter(np.pi, 0)],
                    [-np.pi + 1e-9, 3.1], [0.0, 0.0], [1e-12, -1e-12]])
     x = synth.sky(n, 5, 3.0, synth.rng(99, 5, synth.SKY))
-    a = measurement.NUFFT(uv, n, 8).fwd(x)
+    a = cls(uv, n, 8).fwd(x)
     b = measurement.DFT(uv, n).fwd(x)
     assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 2e-7
 
 
-def test_nufft_adjoint_dot():
+@pytest.mark.parametrize("cls", NUFFTS)
+def test_nufft_adjoint_dot(cls):
     n, m = 32, 900
     g = synth.rng(99, 6, 0)
-    op = measurement.NUFFT(_uv(m, 6), n, 6)
+    op = cls(_uv(m, 6), n, 6)
     x = g.normal(size=(n, n))
     v = g.normal(size=m) + 1j * g.normal(size=m)
     assert np.vdot(v, op.fwd(x)).real == pytest.approx(np.sum(x * op.adj(v)), rel=1e-12)
+
+
+def test_compiled_bessel_series_matches_library():
+    # the compiled oracle sums I0 from its power series; scipy evaluates it by Chebyshev expansions
+    from oracle import cbuild
+    lib = cbuild.load()
+    xs = np.concatenate([np.linspace(0.0, 40.0, 801), [1e-8, 13.8551, 18.6389]])
+    got = np.array([lib.oracle_bessel_i0(float(x)) for x in xs])
+    np.testing.assert_allclose(got, scipy.special.i0(xs), rtol=1e-14)
+    for J in (6, 8):
+        b = kb.beta(J, 2)
+        t = np.linspace(-J / 2 - 0.5, J / 2 + 0.5, 97)
+        np.testing.assert_allclose([lib.oracle_kb(float(s), J, b) for s in t], kb.psi(t, J, b), rtol=1e-14, atol=1e-300)
+
+
+@pytest.mark.parametrize("J", [6, 8])
+def test_compiled_nufft_equals_numpy_nufft(J):
+    # same definition, two implementations: agreement to rounding, with several threads and with one
+    n, m = 64, 30000
+    uv = synth.uv_radial(m, synth.rng(99, 9, synth.UV))
+    x = synth.sky(n, 20, 3.0, synth.rng(99, 9, synth.SKY))
+    v = synth.complex_normal(m, synth.rng(99, 9, synth.NOISE))
+    ref = measurement.NUFFT(uv, n, J)
+    for threads in (None, 1):
+        op = measurement.NUFFTCompiled(uv, n, J, threads=threads)
+        a, b = op.fwd(x), ref.fwd(x)
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 1e-13
+        a, b = op.adj(v), ref.adj(v)
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 1e-13
+        # a block of the operator is the operator of that block's visibilities
+        sub = op.subset(1000, 4000)
+        full = ref.fwd(x)
+        np.testing.assert_allclose(sub.fwd(x), full[1000:4000], rtol=0, atol=1e-12 * np.abs(full).max())
 
 
 def test_op_norm_matches_eigvalsh():
