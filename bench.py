@@ -9,12 +9,14 @@ A timed step is one SDMM iteration of the blocked problem (3): (cg_iters + 1) Ph
 pairs, Psi and Psi^dagger, the three fused prox/dual updates with float64 block norms and the
 stopping-test reductions.  `value` is the Phi + Phi^dagger visibility rate inside those steps,
 (cg_iters + 1) * M per step; every CG product goes through a Phi, Phi^dagger pair here (solver option
-toeplitz = 0).  The solver's default iteration (two CG steps through the Toeplitz form of
-Re(Phi_hat^H Phi_hat)) is timed beside it.  The JSON line also carries the bare pair rate, the roofline of the
-dominant interpolation kernel (HIP events on the library's stream), SDMM time-to-tolerance and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+toeplitz = 0).  Beside it: HIP-event medians and p10/p90 of the steps, of the solver's default
+iteration (two CG steps through the Toeplitz form of Re(Phi_hat^H Phi_hat)) and of bare pairs; the HBM
+roofline of the dominant interpolation kernel (HIP events on the library's stream); SDMM time to
+tolerance with its convergence record (iterations per pass, objective, KKT residuals, a long fixed
+schedule for comparison, feasibility re-checked with the FP64 oracle's operator); the FP64 CPU oracle
+timed on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu] [--no-tol]
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-tol] [--no-batch] [--no-unet]
 """
 from __future__ import annotations
 
@@ -31,12 +33,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Φ+Φ† visibilities/s and SDMM time-to-tol at 1024², plain vs warm-start, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-# FP32 FMA rate without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
-ALU_PEAK_TFLOPS = 78.6
+# MI355X vector FP32 peak (published, packed FMA) and the FMA rate without packed math
+# (256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz), which is what this build's kernels can issue
+FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def stats(ms):
+    """median, p10, p90 (ms) of a list of event times."""
+    a = np.asarray(ms, dtype=np.float64)
+    return {"median_ms": round(float(np.median(a)), 5), "p10_ms": round(float(np.percentile(a, 10)), 5),
+            "p90_ms": round(float(np.percentile(a, 90)), 5), "n": int(a.size)}
+
+
+def event_times(fn, reps):
+    """Runs fn() reps times on the current stream, each bracketed by a pair of HIP events; the times (ms)."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
 
 
 def setup_workload(n=1024, m=20_000_000, R=64, J=8, n_points=200, dr=4.0, snr=30.0, cfg=3):
@@ -64,21 +88,112 @@ def measured_traffic(kernel_name):
     return d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
 
 
-def cpu_baseline(wl, sample=1_000_000):
-    """FP64 oracle Phi + Phi^dagger on every (M/sample)-th visibility of the workload."""
-    from oracle import measurement
-    stride = max(1, wl["m"] // sample)
-    uv = wl["uv"][::stride][:sample]
-    op = measurement.NUFFT(uv, wl["n"], wl["J"])
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, x_tol=None, y_host=None):
+    """The FP64 oracle timed on this host's cores (and, with x_tol, its FP64 operator re-checking the
+    constraints of the GPU's time-to-tolerance image).
+
+    * single thread: the numpy oracle NUFFT, one Phi + Phi^dagger pair on every 20th visibility (1e6);
+    * all threads: the oracle NUFFT with compiled interpolation loops, one pair on all 2e7 visibilities
+      (taps computed once beforehand, like the GPU plan) -- `value`;
+    * the 64^2 workload (direct DFT, M = 2048): one pair and the whole 300-iteration solve;
+    * the 256^2 workload (655 360 visibilities, J = 6): one pair and one SDMM iteration (2 CG steps);
+    * the 1024^2 solve extrapolated from one oracle SDMM iteration times the GPU's iteration count."""
+    from oracle import measurement, problem, sdmm, wavelets
+    from paper_1502_05037_amd import synth
+    cores = len(os.sched_getaffinity(0))
+    n, J, m = wl["n"], wl["J"], wl["m"]
+    out = {"unit": "vis/s", "kind": "oracle", "cores_available": cores, "cpu_model": cpu_model()}
+    # single thread, numpy, sample of the workload
+    stride = max(1, m // 1_000_000)
+    uv = wl["uv"][::stride][:1_000_000]
+    op1 = measurement.NUFFT(uv, n, J)
     x = wl["x_true"].astype(np.float64)
-    v = wl["draws"][::stride][:sample].astype(np.complex128)
+    v = wl["draws"][::stride][:1_000_000].astype(np.complex128)
     t0 = time.perf_counter()
-    op.fwd(x)
-    op.adj(v)
-    dt = time.perf_counter() - t0
-    return {"value": len(uv) / dt, "unit": "vis/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 Phi+Phi^dagger pair (numpy, single thread) on {len(uv)} of the {wl['m']} "
-                      f"visibilities (every {stride}th), n={wl['n']}, J={wl['J']}: {dt:.2f} s"}
+    op1.fwd(x)
+    op1.adj(v)
+    dt1 = time.perf_counter() - t0
+    out["single_thread"] = {"value": len(uv) / dt1, "threads": 1, "seconds": round(dt1, 2),
+                            "sample": f"numpy FP64 NUFFT pair on {len(uv)} of the {m} visibilities (every {stride}th)"}
+    log(f"[bench] oracle single thread: {len(uv) / dt1:.4g} vis/s")
+    # all threads, compiled interpolation loops, the whole workload
+    t0 = time.perf_counter()
+    opc = measurement.NUFFTCompiled(wl["uv"], n, J, threads=cores)
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    vis = opc.fwd(x)
+    opc.adj(vis)
+    dtc = time.perf_counter() - t0
+    out.update({"value": m / dtc, "cores": cores,
+                "sample": f"one FP64 Phi+Phi^dagger pair over all {m} visibilities, n={n}, J={J}, compiled "
+                          f"interpolation loops on {cores} threads: {dtc:.2f} s (taps: {setup:.1f} s once)"})
+    log(f"[bench] oracle all threads: {m / dtc:.4g} vis/s ({dtc:.2f} s per pair)")
+    if x_tol is not None and y_host is not None:
+        # the constraints of (3) for the GPU's time-to-tolerance image, with the FP64 operator
+        vx = opc.fwd(np.asarray(x_tol, dtype=np.float64))
+        off, eps = wl["off"], wl["eps"]
+        r = np.array([np.linalg.norm(y_host[off[i]:off[i + 1]] - vx[off[i]:off[i + 1]]) for i in range(len(eps))])
+        out["check_time_to_tol"] = {"max_resid_over_eps_fp64": float(np.max(r / eps)),
+                                    "worst_block": int(np.argmax(r / eps))}
+        log(f"[bench] oracle FP64 feasibility of the time-to-tol image: {np.max(r / eps):.7f}")
+    # an oracle SDMM iteration at 1024^2 (2 CG steps, the solver's default), for the extrapolated solve
+    psi = wavelets.SARA(n, 4)
+    pb = sdmm.Problem(opc, psi, vis, wl["off"], wl["eps"], 1.0)
+    st = sdmm.init_state(pb)
+    p = sdmm.Params(gamma=1e-6, nu=1.0, max_iter=1, cg_iters=2)
+    t0 = time.perf_counter()
+    sdmm.sdmm_pass(pb, None, p, st)
+    it3 = time.perf_counter() - t0
+    out["config3_iteration_s"] = round(it3, 2)
+    del opc, vis
+    # 64^2, M = 2048, direct DFT: pair and the 300-iteration solve (one weighted-l1 pass)
+    uv1 = synth.sort_by_radius(synth.uv_gaussian(2048, synth.rng(1, 0, synth.UV)))
+    x1 = synth.sky(64, 20, 3.0, synth.rng(1, 0, synth.SKY))
+    d1 = measurement.DFT(uv1, 64)
+    t0 = time.perf_counter()
+    c1 = d1.fwd(x1)
+    d1.adj(c1)
+    pair1 = time.perf_counter() - t0
+    sig = problem.noise_sigma(c1, 30.0)
+    y1 = problem.add_noise(c1, sig, synth.complex_normal(2048, synth.rng(1, 0, synth.NOISE)))
+    eps1 = problem.eps_blocks(sig, [2048])
+    psi1 = wavelets.SARA(64, 4)
+    t0 = time.perf_counter()
+    nu1 = measurement.op_norm(d1, np.ones((64, 64)))
+    g1 = sdmm.default_gamma(d1, psi1, y1, nu1)
+    sdmm.sara(d1, psi1, y1, [0, 2048], eps1, sdmm.Params(gamma=g1, nu=nu1, max_iter=300, cg_iters=2))
+    solve1 = time.perf_counter() - t0
+    out["config1"] = {"pair_vis_per_s": 2048 / pair1, "solve_300_iterations_s": round(solve1, 2),
+                      "what": "64^2, M=2048, direct-DFT oracle, numpy"}
+    # 256^2, 655 360 visibilities, J = 6
+    m2 = 655_360
+    uv2 = synth.sort_by_radius(synth.uv_gaussian(m2, synth.rng(2, 0, synth.UV)))
+    x2 = synth.sky(256, 20, 3.0, synth.rng(2, 0, synth.SKY))
+    o2 = measurement.NUFFTCompiled(uv2, 256, 6, threads=cores)
+    t0 = time.perf_counter()
+    c2 = o2.fwd(x2)
+    o2.adj(c2)
+    pair2 = time.perf_counter() - t0
+    sz2 = synth.block_sizes(m2, 8, synth.rng(2, 0, synth.BLOCKS))
+    pb2 = sdmm.Problem(o2, wavelets.SARA(256, 4), c2, synth.offsets(sz2), np.ones(8), 1.0)
+    t0 = time.perf_counter()
+    sdmm.sdmm_pass(pb2, None, sdmm.Params(gamma=1e-6, nu=1.0, max_iter=1, cg_iters=2), sdmm.init_state(pb2))
+    it2 = time.perf_counter() - t0
+    out["config2"] = {"pair_vis_per_s": m2 / pair2, "iteration_s": round(it2, 3),
+                      "solve_5x300_extrapolated_s": round(1500 * it2, 1),
+                      "what": "256^2, M=655360, J=6, compiled oracle NUFFT, all threads; solve extrapolated"}
+    log(f"[bench] oracle config1 {out['config1']}, config2 {out['config2']}")
+    return out
 
 
 def warm_measure(sh, op, psi, y, eps, prm, n, dev, x_plain, x_true):
@@ -98,8 +213,10 @@ def warm_measure(sh, op, psi, y, eps, prm, n, dev, x_plain, x_true):
         ws.close()
     xw = xw.reshape(n, n)
     return {"warm_seconds": round(secs, 3), "warm_iters": info["iters_total"], "warm_passes": info["passes_done"],
+            "warm_pass_iters": info["pass_iters"],
             "warm_converged_last_pass": info["converged"], "warm_max_resid_over_eps": float(np.max(res / eps)),
             "warm_rel_change_at_exit": info["rel_change"],
+            "warm_kkt_primal": info["kkt_primal"], "warm_kkt_dual": info["kkt_dual"],
             "warm_error_vs_true_sky": float(torch.linalg.vector_norm(xw - x_true) / torch.linalg.vector_norm(x_true)),
             "warm_vs_plain_image_rel_diff": float(torch.linalg.vector_norm(xw - x_plain.reshape(n, n))
                                                   / torch.linalg.vector_norm(x_plain))}
@@ -123,7 +240,7 @@ def unet_flops(base=32, levels=4, n=256):
     return f
 
 
-def unet_bench(sh, dev, reps=10):
+def unet_bench(sh, dev, reps=20):
     """U-Net forward and training step (BF16 MFMA products) at 256^2 batch 8 and forward at 1024^2."""
     import torch
     from paper_1502_05037_amd.warmstart import he_init
@@ -139,17 +256,14 @@ def unet_bench(sh, dev, reps=10):
             y = torch.empty_like(x)
             step = (lambda: sh.unet_train_step(u, x, t, 1e-4, want_loss=False)) if train else \
                 (lambda: sh.unet_forward(u, x, y))
-            for _ in range(2):
+            for _ in range(3):
                 step()
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                step()
-            torch.cuda.synchronize()
-            ms = 1e3 * (time.perf_counter() - t0) / reps
+            st = stats(event_times(step, reps))
+            ms = st["median_ms"]
             fl = B * unet_flops(n=n) * (3 if train else 1)
-            out[name] = {"ms": round(ms, 3), "gflop": round(fl / 1e9, 1), "tflops": round(fl / ms / 1e9, 1),
-                         "frac_of_bf16_mfma_peak": round(fl / ms / 1e9 / 2500.0, 4)}
+            out[name] = {"ms": ms, "p10_ms": st["p10_ms"], "p90_ms": st["p90_ms"], "gflop": round(fl / 1e9, 1),
+                         "tflops": round(fl / ms / 1e9, 1), "frac_of_bf16_mfma_peak": round(fl / ms / 1e9 / BF16_PEAK_TFLOPS, 4)}
             log(f"[bench] unet {name}: {out[name]}")
         sh.unet_set_params(u, he_init(32, 4, 0))   # leave no trained state behind
     finally:
@@ -213,14 +327,11 @@ def batched_bench(sh, dev, steps, warmup, with_tol=True, snr=30.0):
     sess = sh.sdmm_create(op, psi, y, eps, None, None, prm)
     try:
         sh.sdmm_iterate(sess, warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sh.sdmm_iterate(sess, steps)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
+        st = stats(event_times(lambda: sh.sdmm_iterate(sess, 1), steps))
     finally:
         sh.sdmm_destroy(sess)
-    log(f"[bench] batched SDMM iteration {1e3 * dt:.3f} ms for {P} problems -> {9 * M / dt:.4g} vis/s")
+    dt = st["median_ms"] * 1e-3
+    log(f"[bench] batched SDMM iteration {st} for {P} problems -> {9 * M / dt:.4g} vis/s")
     # the same problems one plan at a time (same tiling and width, graph replay), summed
     seq = 0.0
     for p in range(P):
@@ -232,11 +343,7 @@ def batched_bench(sh, dev, steps, warmup, with_tol=True, snr=30.0):
         s1 = sh.sdmm_create(op1, psi1, y[lo:hi].contiguous(), eps[e0:e0 + int(R_p[p])], None, None, prm)
         try:
             sh.sdmm_iterate(s1, 2)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            sh.sdmm_iterate(s1, steps)
-            torch.cuda.synchronize()
-            seq += (time.perf_counter() - t0) / steps
+            seq += stats(event_times(lambda: sh.sdmm_iterate(s1, 1), max(5, steps // 2)))["median_ms"] * 1e-3
         finally:
             sh.sdmm_destroy(s1)
             sh.psi_destroy(psi1)
@@ -251,29 +358,74 @@ def batched_bench(sh, dev, steps, warmup, with_tol=True, snr=30.0):
         t0 = time.perf_counter()
         infos, res = sh.sdmm_solve(op, psi, y, eps, None, None, p2, x)
         torch.cuda.synchronize()
+        ratio = res / eps
         tol = {"seconds": round(time.perf_counter() - t0, 3), "iters_total": infos[0]["iters_total"],
                "passes": infos[0]["passes_done"], "converged_last_pass": int(sum(i["converged"] for i in infos)),
-               "max_resid_over_eps": float(np.max(res / eps)), "tol_rel": 1e-4}
+               "max_resid_over_eps": float(np.max(ratio)), "blocks_over_1e-4": int(np.sum(ratio > 1 + 1e-4)),
+               "tol_rel": 1e-4, "max_kkt_primal": max(i["kkt_primal"] for i in infos),
+               "max_kkt_dual": max(i["kkt_dual"] for i in infos)}
         log(f"[bench] batched time-to-tol {tol}")
     sh.psi_destroy(psi)
     sh.op_destroy(op)
     return {"workload": f"{P} independent {n}x{n} problems, M_p log-uniform in [1e5, 1e6] (total {M}), "
                         f"R_p uniform in 2..16 (total {int(R_p.sum())}), Gaussian uv, 30 dB, one batched plan",
-            "tune": tune, "tune_seconds": round(tune_s, 2), "ms_per_iteration": 1e3 * dt,
+            "tune": tune, "tune_seconds": round(tune_s, 2), "ms_per_iteration": 1e3 * dt, "iteration": st,
             "vis_per_s": 9 * M / dt, "one_plan_at_a_time_ms_per_iteration": 1e3 * seq,
             "batching_speedup": seq / dt, "time_to_tol": tol}
+
+
+def time_to_tol(sh, op, psi, y, eps, n, dev, x_true, long_iters):
+    """Plain SDMM to tolerance (5 passes of at most 300 iterations, tol 1e-4, feasibility slack 1e-4), its
+    convergence record, a long fixed schedule for comparison, and the warm start."""
+    import torch
+    p2 = sh.sdmm_default_params()
+    p2.tol_rel, p2.passes, p2.max_iter, p2.check_every = 1e-4, 5, 300, 1
+    x = torch.empty((n, n), device=dev)
+    log("[bench] SDMM to tolerance 1e-4, 5 passes of at most 300 iterations ...")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info, res = sh.sdmm_solve(op, psi, y, eps, None, None, p2, x)
+    torch.cuda.synchronize()
+    nx = torch.linalg.vector_norm(x_true)
+    tol = {"plain_seconds": round(time.perf_counter() - t0, 3), "plain_iters": info["iters_total"],
+           "plain_pass_iters": info["pass_iters"], "passes": info["passes_done"],
+           "converged_last_pass": info["converged"], "max_resid_over_eps": float(np.max(res / eps)), "tol_rel": 1e-4,
+           "plain_rel_change_at_exit": info["rel_change"], "plain_objective": info["objective"],
+           "plain_kkt_primal": info["kkt_primal"], "plain_kkt_dual": info["kkt_dual"], "cg_iters": p2.cg_iters,
+           "plain_error_vs_true_sky": float(torch.linalg.vector_norm(x - x_true) / nx),
+           "warm_seconds": None, "warm_iters": None}
+    log(f"[bench] time-to-tol plain: {tol}")
+    # a long fixed schedule (the same 5 passes, long_iters iterations each, no stopping test)
+    if long_iters:
+        pl = sh.sdmm_default_params()
+        pl.tol_rel, pl.passes, pl.max_iter = 0.0, 5, long_iters
+        xl = torch.empty((n, n), device=dev)
+        t0 = time.perf_counter()
+        il, rl = sh.sdmm_solve(op, psi, y, eps, None, None, pl, xl)
+        torch.cuda.synchronize()
+        tol["long_fixed_schedule"] = {
+            "iterations_per_pass": long_iters, "seconds": round(time.perf_counter() - t0, 2),
+            "objective": il["objective"], "kkt_primal": il["kkt_primal"], "kkt_dual": il["kkt_dual"],
+            "max_resid_over_eps": float(np.max(rl / eps)),
+            "error_vs_true_sky": float(torch.linalg.vector_norm(xl - x_true) / nx),
+            "time_to_tol_image_rel_diff": float(torch.linalg.vector_norm(x - xl) / torch.linalg.vector_norm(xl))}
+        log(f"[bench] long fixed schedule: {tol['long_fixed_schedule']}")
+    tol.update(warm_measure(sh, op, psi, y, eps, p2, n, dev, x, x_true))
+    return tol, x
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tol", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-small-problems measurement")
     ap.add_argument("--no-unet", action="store_true", help="skip the U-Net kernel measurement")
     ap.add_argument("--only-unet", action="store_true", help="run the U-Net kernel measurement alone")
+    ap.add_argument("--long-iters", type=int, default=1000,
+                    help="iterations per pass of the long fixed schedule compared with the time-to-tol run (0: skip)")
     ap.add_argument("--m", type=int, default=20_000_000)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run three plain device copies of this many MiB (HBM counter calibration)")
@@ -308,28 +460,33 @@ def main():
     y = clean + (sigma / np.sqrt(2)) * torch.tensor(wl["draws"], device=dev)
     sizes = wl["sizes"].astype(np.float64)
     eps = sigma * np.sqrt(sizes + 2 * np.sqrt(sizes))
-    nu = sh.op_norm(op, torch.ones((n, n), device=dev), iters=100, tol=1e-6)
-    log(f"[bench] sigma={sigma:.4g} nu={nu:.6g}")
+    wl["eps"] = eps
+    log(f"[bench] sigma={sigma:.4g}")
 
-    # ---- timed SDMM iterations
+    # ---- timed SDMM iterations: K steps bracketed by synchronisations, each also between HIP events
     prm = sh.sdmm_default_params()
     prm.cg_iters = 8
     prm.toeplitz = 0          # every CG product through a Phi, Phi^dagger pair: 9 pairs per step
     sess = sh.sdmm_create(op, psi, y, eps, None, None, prm)
     try:
         sh.sdmm_iterate(sess, a.warmup)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sh.sdmm_iterate(sess, a.steps)
+        for e0, e1 in ev:
+            e0.record()
+            sh.sdmm_iterate(sess, 1)
+            e1.record()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        step_stats = stats([e0.elapsed_time(e1) for e0, e1 in ev])
         resid, rel = sh.sdmm_result(sess, None, R)
     finally:
         sh.sdmm_destroy(sess)
     ms_step = 1e3 * dt / a.steps
     pairs = prm.cg_iters + 1
     value = pairs * m / (dt / a.steps)
-    log(f"[bench] SDMM iteration {ms_step:.3f} ms -> {value:.4g} vis/s (rel change {rel:.3g})")
+    log(f"[bench] SDMM iteration {ms_step:.3f} ms -> {value:.4g} vis/s; events {step_stats}")
 
     # ---- the solver's default iteration: 2 CG steps through the Toeplitz form of Re(Phi_hat^H Phi_hat)
     pd = sh.sdmm_default_params()
@@ -338,41 +495,33 @@ def main():
     create_s = time.perf_counter() - t0
     try:
         sh.sdmm_iterate(sess, a.warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sh.sdmm_iterate(sess, a.steps)
-        torch.cuda.synchronize()
-        default_it = {"ms": 1e3 * (time.perf_counter() - t0) / a.steps, "cg_iters": pd.cg_iters,
-                      "toeplitz": pd.toeplitz, "session_create_s": round(create_s, 3)}
+        dst = stats(event_times(lambda: sh.sdmm_iterate(sess, 1), a.steps))
+        default_it = {"ms": dst["median_ms"], "p10_ms": dst["p10_ms"], "p90_ms": dst["p90_ms"],
+                      "cg_iters": pd.cg_iters, "toeplitz": pd.toeplitz, "session_create_s": round(create_s, 3)}
     finally:
         sh.sdmm_destroy(sess)
     log(f"[bench] default SDMM iteration {default_it}")
-    log(f"[bench] per-kernel timing of {a.steps} Phi+Phi^dagger pairs ...")
 
-    # ---- bare Phi + Phi^dagger pairs (internal order) and per-kernel event timing
+    # ---- bare Phi + Phi^dagger pairs (internal and user order) and per-kernel event timing
     xin = torch.rand((n, n), device=dev)
     vis = torch.empty(m, dtype=torch.complex64, device=dev)
     xo = torch.empty((n, n), device=dev)
-    for _ in range(2):
+
+    def pair_int():
         sh.phi_fwd_internal(op, xin, vis)
         sh.phi_adj_internal(op, vis, xo)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        sh.phi_fwd_internal(op, xin, vis)
-        sh.phi_adj_internal(op, vis, xo)
-    torch.cuda.synchronize()
-    pair_s = (time.perf_counter() - t0) / a.steps
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
+
+    def pair_user():
         sh.phi_fwd(op, xin, vis)
         sh.phi_adj(op, vis, xo)
-    torch.cuda.synchronize()
-    pair_user_s = (time.perf_counter() - t0) / a.steps
+
+    for _ in range(3):
+        pair_int()
+    pst = stats(event_times(pair_int, a.steps))
+    pust = stats(event_times(pair_user, a.steps))
     sh.profile_enable(True)
     for _ in range(a.steps):
-        sh.phi_fwd_internal(op, xin, vis)
-        sh.phi_adj_internal(op, vis, xo)
+        pair_int()
     torch.cuda.synchronize()
     kern = {}
     for name in ("degrid", "grid", "fold", "fft_rows", "fft_cols"):
@@ -380,6 +529,7 @@ def main():
         kern[name] = {"launches": cnt, "avg_ms": ms / max(cnt, 1)}
     sh.profile_enable(False)
     # one Toeplitz product (three FFT passes), timed the same way
+    nu = sh.op_norm(op, torch.ones((n, n), device=dev), iters=100, tol=1e-6)
     tp = sh.toeplitz_create(op, [1.0 / nu ** 2])
     try:
         for _ in range(2):
@@ -394,64 +544,41 @@ def main():
     finally:
         sh.toeplitz_destroy(tp)
     default_it["toeplitz_product_ms"] = round(toep_ms, 4)
-    log(f"[bench] pair {1e3 * pair_s:.3f} ms (internal), {1e3 * pair_user_s:.3f} ms (user order); "
+    log(f"[bench] pair {pst} (internal), {pust} (user order); "
         + ", ".join(f"{k} {v['avg_ms']:.4f} ms" for k, v in kern.items()))
+
+    # ---- roofline of the dominant interpolation kernel (HBM-bound by its arithmetic intensity).
+    # Algorithmic bytes of one launch: packed uv (8 B) + one complex64 visibility (8 B) per visibility and
+    # one pass over the complex64 K x K grid.  Algorithmic flop: the separable J x J interpolation,
+    # 2J^2 + 2J multiply-adds (4J^2 + 4J flop) per visibility; the Kaiser-Bessel weight evaluation is
+    # implementation work and not counted.
     K = q["K"]
-    # Roofline of the dominant interpolation kernel.  Algorithmic work per visibility and direction:
-    # 2J one-dimensional Kaiser-Bessel weights (Horner, degree 7: 14 flop each) and the separable
-    # J x J interpolation (4 J^2 + 4 J flop); bytes: packed uv (8 B) + one complex64 visibility (8 B)
-    # per visibility plus one pass over the complex64 K x K grid.
-    flop_per_vis = 2 * J * 14 + 4 * J * J + 4 * J
+    N = n * n
     alg_bytes = 16 * m + 8 * K * K
+    mac_flop = (4 * J * J + 4 * J) * m
+    ridge = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    intensity = mac_flop / alg_bytes
     dom = max(("degrid", "grid"), key=lambda k: kern[k]["avg_ms"])
     t_dom = kern[dom]["avg_ms"] * 1e-3
-    achieved = flop_per_vis * m / t_dom / 1e12
-    roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom),
-            "flop_per_launch": flop_per_vis * m, "avg_launch_ms": round(kern[dom]["avg_ms"], 4),
-            "hbm_alg_bytes_per_launch": alg_bytes,
-            "hbm_achieved_GBs": round(alg_bytes / t_dom / 1e9, 1), "hbm_peak_GBs": HBM_PEAK_GBS,
-            "hbm_frac": round(alg_bytes / t_dom / 1e9 / HBM_PEAK_GBS, 4)}
+    achieved = alg_bytes / t_dom / 1e9
+    pair_bytes = 32 * m + 32 * K * K + 8 * N
+    roof = {"kernel": dom, "bound": "hbm" if intensity < ridge else "alu", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom), "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": round(kern[dom]["avg_ms"], 4),
+            "intensity_flop_per_byte": round(intensity, 2), "ridge_flop_per_byte": round(ridge, 2),
+            "alu_view": {"flop_per_launch": mac_flop, "achieved_TFLOPs": round(mac_flop / t_dom / 1e12, 2),
+                         "frac_of_157.3": round(mac_flop / t_dom / 1e12 / FP32_PEAK_TFLOPS, 4),
+                         "frac_of_78.6_nonpacked": round(mac_flop / t_dom / 1e12 / FP32_NONPACKED_TFLOPS, 4)},
+            "pair": {"alg_bytes": pair_bytes, "median_ms": pst["median_ms"],
+                     "frac": round(pair_bytes / (pst["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "user_order_frac": round(pair_bytes / (pust["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
     if dom == "grid":
         roof["fold_avg_ms"] = round(kern["fold"]["avg_ms"], 4)
+    log(f"[bench] roofline {roof}")
 
-    # ---- SDMM time to tolerance (plain start), 5 passes of at most 300 iterations
-    tol = None
-    if not a.no_tol:
-        p2 = sh.sdmm_default_params()
-        p2.tol_rel, p2.passes, p2.max_iter, p2.check_every = 1e-4, 5, 300, 1
-        x = torch.empty((n, n), device=dev)
-        log("[bench] SDMM to tolerance 1e-4, 5 passes of at most 300 iterations ...")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info, res = sh.sdmm_solve(op, psi, y, eps, None, None, p2, x)
-        torch.cuda.synchronize()
-        tol = {"plain_seconds": round(time.perf_counter() - t0, 3), "plain_iters": info["iters_total"],
-               "passes": info["passes_done"], "converged_last_pass": info["converged"],
-               "max_resid_over_eps": float(np.max(res / eps)), "tol_rel": 1e-4,
-               "plain_rel_change_at_exit": info["rel_change"], "cg_iters": p2.cg_iters,
-               "plain_error_vs_true_sky": float(torch.linalg.vector_norm(x - x_true) / torch.linalg.vector_norm(x_true)),
-               "warm_seconds": None, "warm_iters": None}
-        tol.update(warm_measure(sh, op, psi, y, eps, p2, n, dev, x, x_true))
-        worst = int(np.argmax(res / eps))
-        tol["worst_block"] = worst
-        tol["max_abs_y_over_sigma_in_worst_block"] = float(
-            torch.abs(y[int(wl["off"][worst]):int(wl["off"][worst + 1])]).max() / sigma)
-        log(f"[bench] time-to-tol {tol}")
-        # the same comparison with a 1e-3 feasibility slack
-        p3 = sh.sdmm_default_params()
-        p3.tol_rel, p3.passes, p3.max_iter, p3.check_every, p3.eps_slack = 1e-4, 5, 300, 1, 1e-3
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info3, res3 = sh.sdmm_solve(op, psi, y, eps, None, None, p3, x)
-        torch.cuda.synchronize()
-        loose = {"eps_slack": 1e-3, "plain_seconds": round(time.perf_counter() - t0, 3),
-                 "plain_iters": info3["iters_total"], "plain_converged_last_pass": info3["converged"],
-                 "plain_max_resid_over_eps": float(np.max(res3 / eps)),
-                 "plain_error_vs_true_sky": float(torch.linalg.vector_norm(x - x_true) / torch.linalg.vector_norm(x_true))}
-        loose.update(warm_measure(sh, op, psi, y, eps, p3, n, dev, x, x_true))
-        tol["slack_1e-3"] = loose
-        log(f"[bench] time-to-tol with a 1e-3 feasibility slack {loose}")
+    # ---- SDMM time to tolerance (plain, long fixed schedule, warm start)
+    tol, x_tol = (None, None) if a.no_tol else time_to_tol(sh, op, psi, y, eps, n, dev, x_true, a.long_iters)
 
     if a.copy_mb:
         src = torch.ones(a.copy_mb << 18, dtype=torch.float32, device=dev)
@@ -461,12 +588,18 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copies: 3 x {a.copy_mb} MiB")
 
+    y_host = y.cpu().numpy().astype(np.complex128) if (x_tol is not None and not a.no_cpu) else None
+    xt_host = x_tol.cpu().numpy() if y_host is not None else None
     sh.psi_destroy(psi)
     sh.op_destroy(op)
     del y, clean, x_true
     batched = None if a.no_batch else batched_bench(sh, dev, a.steps, a.warmup, with_tol=not a.no_tol)
     unet = None if a.no_unet else unet_bench(sh, dev)
-    cpu = None if a.no_cpu else cpu_baseline(wl)
+    cpu = None if a.no_cpu else cpu_baseline(wl, xt_host, y_host)
+    if cpu is not None and tol is not None:
+        ct = cpu.get("check_time_to_tol", {})
+        tol["max_resid_over_eps_fp64_oracle"] = ct.get("max_resid_over_eps_fp64")
+        tol["oracle_solve_extrapolated_s"] = round(cpu["config3_iteration_s"] * tol["plain_iters"], 1)
     out = {
         "metric": METRIC, "value": value, "unit": "vis/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -474,8 +607,9 @@ def main():
         "config": {"workload": "SARA/SDMM one SDMM iteration, 1024x1024 sky, M=2e7 radial uv, R=64 uneven "
                                "blocks, KB J=8, alpha=2, 8 CG steps", "n": n, "M": m, "R": R, "J": J,
                    "cg_iters": prm.cg_iters, "global_batch": 1},
-        "pair": {"internal_vis_per_s": m / pair_s, "user_order_vis_per_s": m / pair_user_s,
-                 "internal_ms": 1e3 * pair_s, "user_ms": 1e3 * pair_user_s},
+        "step_events": step_stats,
+        "pair": {"internal_vis_per_s": m / (pst["median_ms"] * 1e-3), "user_order_vis_per_s": m / (pust["median_ms"] * 1e-3),
+                 "internal": pst, "user": pust},
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
         "default_iteration": default_it,
         "roofline": roof, "cpu_baseline": cpu, "sdmm_time_to_tol": tol, "plan_seconds": round(plan_s, 2),

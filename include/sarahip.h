@@ -253,6 +253,8 @@ typedef struct {
  * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 
+#define SH_PASS_RECORD 16   /* passes whose iteration counts sh_sdmm_info records */
+
 typedef struct {
   int32_t iters_total;   /* SDMM iterations over all passes */
   int32_t passes_done;
@@ -264,6 +266,11 @@ typedef struct {
   double nu;             /* normalisation actually used (nu_p of block_norm) */
   double delta;          /* reweighting delta of W_out */
   double seconds;        /* wall time inside the call */
+  double kkt_primal;     /* ||(s_j - y_j)_j|| / ||(s_j)_j|| of the state at exit: split images s_j = L_j x
+                            (L = Psi^dagger, the normalised blocks Phi_hat_i, I) against their proximal points */
+  double kkt_dual;       /* ||sum_j L_j^T z_j|| / max_j ||L_j^T z_j|| of the state at exit (stationarity) */
+  int32_t pass_iters[SH_PASS_RECORD];   /* iterations of each pass (the first SH_PASS_RECORD passes), up to
+                            the stopping iteration of this problem; 0 for passes not run */
 } sh_sdmm_info;
 
 /* Solve SARA/(3).  y: device M complex64, user order.  eps: host R float64 (user
@@ -298,6 +305,11 @@ sh_status sh_sdmm_iterate(sh_sdmm s, int32_t iters, void* stream);
 /* Current image (device P*n*n, may be NULL), block residuals ||y_i - Phi_i x|| (host R, may be
  * NULL) and relative change of the last iteration (host, P values, may be NULL).  Synchronous. */
 sh_status sh_sdmm_result(sh_sdmm s, float* x_out, double* block_resid, double* rel_change, void* stream);
+/* KKT residuals (as in sh_sdmm_info) and objective ||W Psi^dagger x||_1 (current weights) of the session's
+ * current state, one value per problem each (host arrays of P, each may be NULL).  Needs at least one
+ * iteration.  Synchronous.  These measure convergence of (3): at a solution every split image equals its
+ * proximal point and the duals balance (SDMM paragraph). */
+sh_status sh_sdmm_kkt(sh_sdmm s, double* kkt_primal, double* kkt_dual, double* objective, void* stream);
 sh_status sh_sdmm_destroy(sh_sdmm s);
 
 /* ---------------------------------------------------------------------------

@@ -179,8 +179,47 @@ __global__ __launch_bounds__(256) void l1w_partial(const float* __restrict__ c, 
   const double r = block_sum(acc, sh);
   PART_OUT(r);
 }
+// partials of sum (a + fb b + fc c)^2 (b, c may be NULL)
+__global__ __launch_bounds__(256) void comb3_sq_partial(const float* __restrict__ a, const float* __restrict__ b,
+                                                        const float* __restrict__ c, float fb, float fc, int64_t per,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  SEGMENT_LOOP(i) {
+    double t = double(a[i]);
+    if (b) t += double(fb) * double(b[i]);
+    if (c) t += double(fc) * double(c[i]);
+    acc += t * t;
+  }
+  const double r = block_sum(acc, sh);
+  PART_OUT(r);
+}
 #undef SEGMENT_LOOP
 #undef PART_OUT
+
+// Primal residual of the data splits (see sdmm.hip: v = cb (y - z - s_hat), s_hat = cb s):
+// per-chunk float64 partial sums of ||s_hat - y||^2 = ||v / cb + z||^2 and of ||s_hat||^2
+__global__ __launch_bounds__(256) void kkt_vis_partial(const float2* __restrict__ s_in, const float2* __restrict__ z,
+                                                       const float2* __restrict__ v, const int4* __restrict__ chunks,
+                                                       const float* __restrict__ cblk, double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int4 c = chunks[blockIdx.x];
+  const float cb = cblk ? cblk[c.x] : 1.0f;
+  double a = 0.0, b = 0.0;
+  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
+    const float2 vv = v[i], zv = z[i], sv = s_in[i];
+    const double rr = double(vv.x) / cb + double(zv.x), ri = double(vv.y) / cb + double(zv.y);
+    const double sr = double(cb) * double(sv.x), si = double(cb) * double(sv.y);
+    a += rr * rr + ri * ri;
+    b += sr * sr + si * si;
+  }
+  const double ra = block_sum(a, sh);
+  const double rb = block_sum(b, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ra;
+    part[2 * blockIdx.x + 1] = rb;
+  }
+}
 
 // weighted soft threshold + dual; grid (cdiv(per, 256), P), segment p thresholds at gamma_d[p]
 __global__ __launch_bounds__(256) void prox_l1_kernel(int64_t per, const float* __restrict__ s, float* __restrict__ z,
@@ -373,6 +412,14 @@ sh_status Reducer::maxabs(const float* a, int64_t per, double* out, hipStream_t 
   return SH_OK;
 }
 
+sh_status Reducer::comb3_sq(const float* a, const float* b, const float* c, float fb, float fc, int64_t per, double* out,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(comb3_sq_partial, dim3(rb, P), dim3(256), 0, st, a, b, c, fb, fc, per, part.ptr);
+  hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, out);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
 sh_status Reducer::l1w(const float* c, const float* W, int64_t per, double* out, hipStream_t st) {
   hipLaunchKernelGGL(l1w_partial, dim3(rb, P), dim3(256), 0, st, c, W, per, part.ptr);
   hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, out);
@@ -405,6 +452,16 @@ sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* y
                      op->chunk_first_d.ptr, op->R, rho, resid);
   hipLaunchKernelGGL(ball_project, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, eps, rho, cblk, v,
                      sub_s ? 1 : 0);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status launch_kkt_vis(sh_op op, const float2* s, const float2* z, const float2* v, const float* cblk, double* prim_b,
+                         double* scale_b, hipStream_t st) {
+  const unsigned nc = (unsigned)op->n_chunks;
+  hipLaunchKernelGGL(kkt_vis_partial, dim3(nc), dim3(256), 0, st, s, z, v, op->chunks.ptr, cblk, op->partials.ptr);
+  hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
+                     op->chunk_first_d.ptr, op->R, prim_b, scale_b);
   SH_LAUNCHED();
   return SH_OK;
 }

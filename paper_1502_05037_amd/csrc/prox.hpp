@@ -17,6 +17,9 @@ struct Reducer {
   sh_status std_dev(const float* a, int64_t per, double* sum_out, double* var_out, hipStream_t st);
   sh_status maxabs(const float* a, int64_t per, double* out, hipStream_t st);
   sh_status l1w(const float* c, const float* W, int64_t per, double* out, hipStream_t st);
+  // out[p] = sum over segment p of (a + fb b + fc c)^2 (b, c may be NULL)
+  sh_status comb3_sq(const float* a, const float* b, const float* c, float fb, float fc, int64_t per, double* out,
+                     hipStream_t st);
   // Conjugate-gradient steps fused with the reduction that follows them (same trees as dot):
   //   cg_init:   r = a + b + c - 2x, p = r, xprev = x;            rs_out = r.r
   //   cg_ap:     Ap = 2p + Ap;                                   pap_out = p.Ap
@@ -39,6 +42,10 @@ sh_status launch_prox_pos(int64_t N, const float* s, float* z, float* v, hipStre
 // and v is returned multiplied by c_b, ready for the unweighted adjoint.
 sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
                            double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st);
+// Primal residual of the data splits per block: prim_b[b] = ||v_b / c_b + z_b|| (= ||s_hat_b - y_b|| for the
+// solver's v = c (y - z - s_hat)) and scale_b[b] = ||c_b s_b|| (device R doubles each).
+sh_status launch_kkt_vis(sh_op op, const float2* s, const float2* z, const float2* v, const float* cblk, double* prim_b,
+                         double* scale_b, hipStream_t st);
 sh_status launch_reweight(int64_t per, int P, const float* c, const double* delta_d, double delta, float* W,
                           hipStream_t st);
 

@@ -87,6 +87,7 @@ struct Work {
   sh::DevBuf<float> spsi, zpsi, vpsi, W;
   sh::DevBuf<float2> yhat, sphi, zphi, vphi, vtmp;
   sh::DevBuf<double> sc, eps_hat, rho, resid, delta;
+  sh::DevBuf<double> kkt;          // KKT reductions at exit: 8 per problem, then 2 per block
   sh::DevBuf<float> cblk, gamma;   // c_b per block, gamma per problem
   sh::Reducer red;
   sh_toep_s toep;                  // Re(Phi_hat^H Phi_hat) as a convolution (option toeplitz)
@@ -225,6 +226,7 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   SH_TRY(w.delta.alloc(P));
   SH_TRY(w.cblk.alloc(R));
   SH_TRY(w.gamma.alloc(P));
+  SH_TRY(w.kkt.alloc(8 * P + 2 * R));
   SH_TRY(w.red.init(P));
   double* sc = w.sc.ptr;
   s->s_rs = sc;                        // rs_k of problem p at [k*P + p], k = 0..kcg
@@ -482,6 +484,51 @@ sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st) {
   return SH_OK;
 }
 
+// Relative KKT residuals of the current SDMM state (after at least one iteration), per problem:
+//   primal = ||(s_j - y_j)_j|| / ||(s_j)_j||   over the splits j = psi, the data blocks, positivity
+//            (s_j = L_j x the split images, y_j their proximal points; zero at a fixed point),
+//   dual   = ||sum_j L_j^T z_j|| / max_j ||L_j^T z_j||   (stationarity of the Lagrangian).
+// The state keeps v_j = y_j - z_j (data splits: c_b (y - z - s_hat)), so s_j - y_j = s_j - v_j - z_j for
+// psi and positivity and -(v / c_b + z) for the data.  Also the objective ||W Psi^dagger x||_1 with the
+// current weights.  Synchronises.
+sh_status sdmm_kkt(sh_sdmm s, std::vector<double>& prim, std::vector<double>& dual, std::vector<double>& obj,
+                   hipStream_t st) {
+  sh_op op = s->op;
+  Work& w = s->w;
+  const int P = s->P, R = s->R;
+  double* k = w.kkt.ptr;
+  SH_TRY(w.red.comb3_sq(w.spsi.ptr, w.vpsi.ptr, w.zpsi.ptr, -1.f, -1.f, s->Dper, k, st));
+  SH_TRY(w.red.dot(w.spsi.ptr, w.spsi.ptr, s->Dper, k + P, st));
+  SH_TRY(w.red.comb3_sq(w.x.ptr, w.vpos.ptr, w.zpos.ptr, -1.f, -1.f, s->per, k + 2 * P, st));
+  SH_TRY(w.red.dot(w.x.ptr, w.x.ptr, s->per, k + 3 * P, st));
+  SH_TRY(sh::launch_kkt_vis(op, w.sphi.ptr, w.zphi.ptr, w.vphi.ptr, w.cblk.ptr, k + 8 * P, k + 8 * P + R, st));
+  SH_TRY(sh_psi_fwd(s->psi, w.zpsi.ptr, w.t1.ptr, st));                              // Psi z_psi
+  SH_TRY(sh::phi_adjoint(op, w.zphi.ptr, w.t2.ptr, false, w.cblk.ptr, st));          // Phi_hat^dagger z_phi
+  SH_TRY(w.red.dot(w.t1.ptr, w.t1.ptr, s->per, k + 4 * P, st));
+  SH_TRY(w.red.dot(w.t2.ptr, w.t2.ptr, s->per, k + 5 * P, st));
+  SH_TRY(w.red.dot(w.zpos.ptr, w.zpos.ptr, s->per, k + 6 * P, st));
+  SH_TRY(w.red.comb3_sq(w.t1.ptr, w.t2.ptr, w.zpos.ptr, 1.f, 1.f, s->per, k + 7 * P, st));
+  SH_TRY(w.red.l1w(w.spsi.ptr, s->Wp, s->Dper, s->s_misc + MISC_OBJ * P, st));
+  std::vector<double> h(8 * P + 2 * R), o(P);
+  SH_HIP(hipMemcpyAsync(h.data(), k, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipMemcpyAsync(o.data(), s->s_misc + MISC_OBJ * P, P * sizeof(double), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipStreamSynchronize(st));
+  prim.assign(P, 0.0);
+  dual.assign(P, 0.0);
+  obj = o;
+  for (int p = 0; p < P; ++p) {
+    double pr = h[p] + h[2 * P + p], sc = h[P + p] + h[3 * P + p];
+    for (int b = op->block_off[p]; b < op->block_off[p + 1]; ++b) {
+      pr += h[8 * P + b] * h[8 * P + b];
+      sc += h[8 * P + R + b] * h[8 * P + R + b];
+    }
+    prim[p] = sc > 0 ? std::sqrt(pr / sc) : 0.0;
+    const double dm = std::sqrt(std::max(h[4 * P + p], std::max(h[5 * P + p], h[6 * P + p])));
+    dual[p] = dm > 0 ? std::sqrt(h[7 * P + p]) / dm : 0.0;
+  }
+  return SH_OK;
+}
+
 sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps, const sh_sdmm_params* prm) {
   SH_REQUIRE(op && psi && y && eps && prm, "NULL argument");
   SH_REQUIRE(psi_side(psi) == op->n, "psi and op image sides differ");
@@ -562,6 +609,19 @@ sh_status sh_sdmm_result(sh_sdmm s, float* x_out, double* block_resid, double* r
   return SH_OK;
 }
 
+sh_status sh_sdmm_kkt(sh_sdmm s, double* kkt_primal, double* kkt_dual, double* objective, void* stream) {
+  SH_REQUIRE(s, "NULL session");
+  SH_REQUIRE(s->iters_total > 0, "the session has not iterated yet");
+  std::vector<double> pr, du, ob;
+  SH_TRY(sdmm_kkt(s, pr, du, ob, (hipStream_t)stream));
+  for (int p = 0; p < s->P; ++p) {
+    if (kkt_primal) kkt_primal[p] = pr[p];
+    if (kkt_dual) kkt_dual[p] = du[p];
+    if (objective) objective[p] = ob[p];
+  }
+  return SH_OK;
+}
+
 sh_status sh_sdmm_destroy(sh_sdmm s) {
   delete s;
   return SH_OK;
@@ -584,6 +644,7 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
   // residuals and relative change are taken then, while the batch iterates on for the others.
   std::vector<int> taken(P, 0);
   std::vector<double> rel_out(P, INFINITY), res_out(s->R, 0.0);
+  std::vector<std::vector<int>> pass_it(P);   // iterations of each pass, per problem
   int it_last = 0, iters_total = 0, passes_done = 0;
   for (int pass = 0; pass < prm->passes; ++pass) {
     const bool last = pass + 1 == prm->passes;
@@ -622,6 +683,7 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
     it_last = it;
     iters_total += it;
     passes_done = pass + 1;
+    for (int p = 0; p < P; ++p) pass_it[p].push_back(conv[p] ? it_conv[p] : it);
     if (!last) {  // reweight for the next pass from Psi^dagger x_n (in spsi)
       SH_TRY(sdmm_reweight(s, s->w.W.ptr, st));
       s->Wp = s->w.W.ptr;
@@ -635,6 +697,9 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
     rel_out[p] = rel[p];
     for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] / s->cb[i];
   }
+  // KKT residuals of the state at exit (Psi^dagger x_n is still in spsi)
+  std::vector<double> kp, kd, kob;
+  SH_TRY(sdmm_kkt(s, kp, kd, kob, st));
   // objective with the last pass's weights and W_out, both from Psi^dagger of the returned images
   SH_TRY(sh_psi_adj(s->psi, x_out, s->w.spsi.ptr, st));
   SH_TRY(s->w.red.l1w(s->w.spsi.ptr, s->Wp, s->Dper, s->s_misc + MISC_OBJ * P, st));
@@ -658,6 +723,9 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
       inf.nu = s->nu[p];
       inf.delta = s->delta[p];
       inf.seconds = secs;
+      inf.kkt_primal = kp[p];
+      inf.kkt_dual = kd[p];
+      for (int t = 0; t < (int)pass_it[p].size() && t < SH_PASS_RECORD; ++t) inf.pass_iters[t] = pass_it[p][t];
     }
   return SH_OK;
 }

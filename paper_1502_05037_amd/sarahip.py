@@ -27,6 +27,7 @@ lib = C.CDLL(_LIB_PATH)
 
 STATUS = {0: "SH_OK", -1: "SH_EINVAL", -2: "SH_ENOMEM", -3: "SH_EDEVICE", -4: "SH_ENONFINITE", -5: "SH_EUNSUPPORTED"}
 SARA_MASK = 0x1FF
+PASS_RECORD = 16   # SH_PASS_RECORD
 
 
 class SarahipError(RuntimeError):
@@ -46,10 +47,13 @@ class SdmmParams(C.Structure):
 class SdmmInfo(C.Structure):
     _fields_ = [("iters_total", C.c_int32), ("passes_done", C.c_int32), ("converged", C.c_int32),
                 ("iters_last", C.c_int32), ("rel_change", C.c_double), ("objective", C.c_double),
-                ("gamma", C.c_double), ("nu", C.c_double), ("delta", C.c_double), ("seconds", C.c_double)]
+                ("gamma", C.c_double), ("nu", C.c_double), ("delta", C.c_double), ("seconds", C.c_double),
+                ("kkt_primal", C.c_double), ("kkt_dual", C.c_double), ("pass_iters", C.c_int32 * PASS_RECORD)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["pass_iters"] = [int(v) for v in self.pass_iters][:self.passes_done]
+        return d
 
 
 class TuneResult(C.Structure):
@@ -107,6 +111,7 @@ _SIGS = {
     "sh_sdmm_create": (C.c_int, [_vp, _vp, _vp, _P64, _vp, _vp, C.POINTER(SdmmParams), C.POINTER(_vp), _vp]),
     "sh_sdmm_iterate": (C.c_int, [_vp, _i32, _vp]),
     "sh_sdmm_result": (C.c_int, [_vp, _vp, _P64, _P64, _vp]),
+    "sh_sdmm_kkt": (C.c_int, [_vp, _P64, _P64, _P64, _vp]),
     "sh_sdmm_destroy": (C.c_int, [_vp]),
     "sh_unet_create": (C.c_int, [_i32, _i32, C.POINTER(_vp)]),
     "sh_unet_destroy": (C.c_int, [_vp]),
@@ -419,6 +424,15 @@ def sdmm_result(s: int, x_out=None, R: int = 0, stream=None, P: int = 1):
     _check(lib.sh_sdmm_result(s, _ptr(x_out), resid.ctypes.data_as(_P64) if R else None, rel.ctypes.data_as(_P64),
                               _stream(stream)), "sdmm_result")
     return resid[:R], (float(rel[0]) if P == 1 else rel)
+
+
+def sdmm_kkt(s: int, P: int = 1, stream=None):
+    """Returns (kkt_primal, kkt_dual, objective) of the session's current state: floats, or arrays of P
+    values for a batched session."""
+    pr, du, ob = (np.zeros(P, dtype=np.float64) for _ in range(3))
+    _check(lib.sh_sdmm_kkt(s, pr.ctypes.data_as(_P64), du.ctypes.data_as(_P64), ob.ctypes.data_as(_P64),
+                           _stream(stream)), "sdmm_kkt")
+    return (float(pr[0]), float(du[0]), float(ob[0])) if P == 1 else (pr, du, ob)
 
 
 def sdmm_destroy(s: int) -> None:

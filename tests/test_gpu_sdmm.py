@@ -77,6 +77,52 @@ def test_config1_fixed_schedule_parity(sh, block_norm):
     assert info["objective"] == pytest.approx(infos[0].objective, rel=1e-4)
 
 
+def test_kkt_residuals_and_pass_iterations_match_oracle(sh):
+    """The KKT residuals reported at exit (relative primal ||s_j - y_j|| and dual ||sum_j L_j^T z_j||) follow
+    the oracle's definitions on the same state after a fixed schedule; per-pass iteration counts."""
+    pb = helpers.build(2, 32, 1200, 3, 6, coverage="radial", prob=4)
+    psi, nu, gamma, a = _oracle_setup(pb)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=2, block_weights=a)
+    x_ref, W_last, infos, st = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
+    # the oracle's KKT of its state at exit, with the same normalisation
+    prob = sdmm.Problem(pb.op, psi, pb.y, pb.offsets, pb.eps, nu, a)
+    kp, kd = sdmm.kkt(prob, st, None, gamma)
+    x, info, resid, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=40, cg_iters=8, passes=2))
+    print(f"KKT primal {info['kkt_primal']:.4e} vs {kp:.4e}, dual {info['kkt_dual']:.4e} vs {kd:.4e}")
+    assert info["pass_iters"] == [40, 40]
+    assert info["kkt_primal"] == pytest.approx(kp, rel=2e-2)
+    assert info["kkt_dual"] == pytest.approx(kd, rel=2e-2)
+    # with a stopping test the passes record where each stopped
+    x, info, resid, _ = _gpu_solve(sh, pb, _params(sh, max_iter=300, tol_rel=1e-4, check_every=1, passes=3))
+    assert len(info["pass_iters"]) == 3 and sum(info["pass_iters"]) == info["iters_total"]
+    assert info["pass_iters"][-1] == info["iters_last"]
+
+
+def test_session_kkt_matches_solve(sh):
+    pb = helpers.build(2, 32, 1200, 3, 6, coverage="radial", prob=4)
+    psi_o, nu, gamma, a = _oracle_setup(pb)
+    prm = _params(sh, gamma=gamma, nu=nu, max_iter=25, cg_iters=2)
+    op = sh.op_create(pb.uv, pb.n, 2, pb.J, pb.offsets)
+    psi = sh.psi_create(pb.n, 4)
+    try:
+        y = _dev(pb.y, torch.complex64)
+        x = torch.empty((pb.n, pb.n), dtype=torch.float32, device="cuda")
+        info, _ = sh.sdmm_solve(op, psi, y, pb.eps, None, None, prm, x)
+        s = sh.sdmm_create(op, psi, y, pb.eps, None, None, prm)
+        try:
+            with pytest.raises(sh.SarahipError):
+                sh.sdmm_kkt(s)          # no iteration yet
+            sh.sdmm_iterate(s, 25)
+            kp, kd, obj = sh.sdmm_kkt(s)
+        finally:
+            sh.sdmm_destroy(s)
+    finally:
+        sh.psi_destroy(psi)
+        sh.op_destroy(op)
+    assert kp == info["kkt_primal"] and kd == info["kkt_dual"]
+    assert obj == pytest.approx(info["objective"], rel=1e-6)
+
+
 def test_reweighted_passes_parity_and_weights(sh):
     pb = helpers.build(2, 32, 1200, 3, 6, coverage="radial", prob=1)
     psi, nu, gamma, a = _oracle_setup(pb)
