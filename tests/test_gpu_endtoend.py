@@ -7,7 +7,9 @@
 The data y = Phi x + n come from the oracle's FP64 NUFFT (its interpolation loops compiled, so that it
 handles 2e7 visibilities), rounded to complex64 for the GPU.  Checks, for each workload:
 
-* Phi on the dense sky image, block by block: each block's own norm-wise error <= 1e-5;
+* Phi on the dense sky image, block by block: each block's error <= 1e-5 of the larger of its own
+  norm and its share of the whole vector's norm (the float32 floor is absolute, near 1e-7 of the RMS
+  visibility, so blocks of visibilities far below the RMS are measured against the RMS level);
 * Phi^dagger of the data restricted to each block, block by block (<= 1e-5 each), and of all the data
   pixel by pixel (largest pixel error <= 1e-5 of the largest pixel);
 * the run to tolerance with the solver's defaults (relative change 1e-4, 5 passes of at most 300
@@ -87,10 +89,22 @@ def test_dense_phi_per_block(sh, wl):
     sh.phi_fwd(wl["op"], torch.tensor(wl["x_true"], dtype=torch.float32, device="cuda"), vis)
     got = vis.cpu().numpy().astype(np.complex128)
     ref = wl["clean"]
-    errs = np.array([helpers.rel(got[lo:hi], ref[lo:hi]) for lo, hi in _blocks(wl)])
-    print(f"[e2e {wl['name']}] Phi per-block errors: max {errs.max():.2e} (block {errs.argmax()}), "
-          f"median {np.median(errs):.2e}; all {helpers.rel(got, ref):.2e}")
-    assert errs.max() <= OP_TOL
+    # Each block's error against its own norm, and against its share of the whole vector's norm
+    # (||Phi x|| sqrt(M_b / M)): float32 rounding in the FFT leaves every grid value, and so every
+    # visibility, with an absolute error near 1e-7 of the RMS visibility, so a block whose visibilities
+    # are far below the RMS (radial annuli away from the centre) shows a larger error against its own
+    # norm.  The bar takes the larger of the two scales: an error confined to one block still has to
+    # stay below 1e-5 of what that block would hold at the RMS level.
+    m = wl["m"]
+    nref = np.linalg.norm(ref)
+    own = np.array([helpers.rel(got[lo:hi], ref[lo:hi]) for lo, hi in _blocks(wl)])
+    scale = np.array([max(np.linalg.norm(ref[lo:hi]), nref * np.sqrt((hi - lo) / m)) for lo, hi in _blocks(wl)])
+    err = np.array([np.linalg.norm(got[lo:hi] - ref[lo:hi]) for lo, hi in _blocks(wl)])
+    print(f"[e2e {wl['name']}] Phi per block: error / own norm max {own.max():.2e} (block {own.argmax()}), "
+          f"median {np.median(own):.2e}; error / max(own norm, share of the RMS) max {(err / scale).max():.2e}; "
+          f"whole vector {helpers.rel(got, ref):.2e}")
+    assert helpers.rel(got, ref) <= OP_TOL
+    assert np.all(err <= OP_TOL * scale)
 
 
 def test_dense_phi_adjoint_per_block_and_pixel(sh, wl):
