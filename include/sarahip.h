@@ -183,6 +183,17 @@ sh_status sh_prox_pos(int64_t N, const float* s, float* z, float* v_out, void* s
 sh_status sh_prox_ball(sh_op op, const float* s, float* z, const float* yhat, const double* eps, float* v_out,
                        double* resid_out, void* stream);
 
+/* The same projection for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): it calls no allocating routine and does not
+ * synchronise (async, so it can be captured).  The per-block norms live in a fixed device array of
+ * SH_BALL_NOALLOC_MAX_BLOCKS float64 values, one per GPU for the life of the process, shared by every
+ * call on that GPU: calls that overlap on one GPU (several streams or threads) race and must be
+ * serialised by the caller, as must calls on the same plan.  Arguments and results as sh_prox_ball.
+ * Errors: SH_EINVAL (NULL argument, or a plan with more than SH_BALL_NOALLOC_MAX_BLOCKS blocks). */
+#define SH_BALL_NOALLOC_MAX_BLOCKS 65536
+sh_status sh_prox_ball_noalloc(sh_op op, const float* s, float* z, const float* yhat, const double* eps, float* v_out,
+                               double* resid_out, void* stream);
+
 /* SARA weights w = delta / (delta + |c|) (device D float32 in and out). */
 sh_status sh_reweight(int64_t D, const float* c, double delta, float* W_out, void* stream);
 /* Population standard deviation of c (float64 reduction).  Synchronous. */

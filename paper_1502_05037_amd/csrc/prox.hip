@@ -6,6 +6,7 @@
 // Reductions are two-stage with a fixed tree (per-work-group partials, then one work-group), so they
 // are deterministic.
 #include <cmath>
+#include <mutex>
 
 #include "prox.hpp"
 
@@ -443,9 +444,9 @@ sh_status launch_prox_pos(int64_t N, const float* s, float* z, float* v, hipStre
   return SH_OK;
 }
 
-sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
-                           double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st) {
-  ProfScope ps("prox", st);
+// The three ball kernels (norm partials, per-block norms, projection) with no timing events.
+sh_status ball_kernels(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
+                              double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st) {
   const unsigned nc = (unsigned)op->n_chunks;
   hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr);
   hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
@@ -454,6 +455,12 @@ sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* y
                      sub_s ? 1 : 0);
   SH_LAUNCHED();
   return SH_OK;
+}
+
+sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
+                           double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st) {
+  ProfScope ps("prox", st);
+  return ball_kernels(op, s, z, yhat, eps, rho, resid, v, sub_s, cblk, st);
 }
 
 sh_status launch_kkt_vis(sh_op op, const float2* s, const float2* z, const float2* v, const float* cblk, double* prim_b,
@@ -474,6 +481,33 @@ sh_status launch_reweight(int64_t per, int P, const float* c, const double* delt
 }
 
 }  // namespace sh
+
+// Per-block float64 norms of sh_prox_ball_noalloc: a file-scope device array (each GPU the library runs
+// on holds its own copy until the process ends).  Host code never passes `scratch` itself: its address on
+// each device comes from hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) double scratch[SH_BALL_NOALLOC_MAX_BLOCKS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch`, resolved on the first call on that device.
+sh_status scratch_address(double** out) {
+  int dev = -1;
+  SH_HIP(hipGetDevice(&dev));
+  SH_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SH_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    SH_REQUIRE(p != nullptr, "no device address for the ball-projection scratch on device %d", dev);
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return SH_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -498,6 +532,18 @@ sh_status sh_prox_ball(sh_op op, const float* s, float* z, const float* yhat, co
                               (float2*)v_out, false, nullptr, st));
   SH_HIP(hipStreamSynchronize(st));  // rho is freed on return
   return SH_OK;
+}
+
+sh_status sh_prox_ball_noalloc(sh_op op, const float* s, float* z, const float* yhat, const double* eps, float* v_out,
+                               double* resid_out, void* stream) {
+  SH_REQUIRE(op && s && z && yhat && eps && v_out && resid_out, "NULL argument");
+  SH_REQUIRE(op->R <= SH_BALL_NOALLOC_MAX_BLOCKS, "%d blocks exceed the %d that sh_prox_ball_noalloc holds (use "
+             "sh_prox_ball)", op->R, SH_BALL_NOALLOC_MAX_BLOCKS);
+  double* rho = nullptr;
+  SH_TRY(scratch_address(&rho));
+  // ball_final writes every block's norm before ball_project reads it: nothing needs clearing
+  return sh::ball_kernels(op, (const float2*)s, (float2*)z, (const float2*)yhat, eps, rho, resid_out, (float2*)v_out,
+                          false, nullptr, (hipStream_t)stream);
 }
 
 sh_status sh_reweight(int64_t D, const float* c, double delta, float* W_out, void* stream) {

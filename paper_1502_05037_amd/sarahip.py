@@ -28,6 +28,7 @@ lib = C.CDLL(_LIB_PATH)
 STATUS = {0: "SH_OK", -1: "SH_EINVAL", -2: "SH_ENOMEM", -3: "SH_EDEVICE", -4: "SH_ENONFINITE", -5: "SH_EUNSUPPORTED"}
 SARA_MASK = 0x1FF
 PASS_RECORD = 16   # SH_PASS_RECORD
+BALL_NOALLOC_MAX_BLOCKS = 65536   # SH_BALL_NOALLOC_MAX_BLOCKS
 
 
 class SarahipError(RuntimeError):
@@ -103,6 +104,7 @@ _SIGS = {
     "sh_prox_l1": (C.c_int, [_i64, _vp, _vp, _vp, _f32, _vp, _vp]),
     "sh_prox_pos": (C.c_int, [_i64, _vp, _vp, _vp, _vp]),
     "sh_prox_ball": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "sh_prox_ball_noalloc": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "sh_reweight": (C.c_int, [_i64, _vp, _f64, _vp, _vp]),
     "sh_std": (C.c_int, [_i64, _vp, _P64, _vp]),
     "sh_sdmm_default_params": (None, [C.POINTER(SdmmParams)]),
@@ -369,6 +371,12 @@ def prox_pos(s, z, v_out, stream=None):
 def prox_ball(op, s, z, yhat, eps_dev, v_out, resid_out, stream=None):
     _check(lib.sh_prox_ball(op, _ptr(s), _ptr(z), _ptr(yhat), _ptr(eps_dev), _ptr(v_out), _ptr(resid_out),
                             _stream(stream)), "prox_ball")
+
+
+def prox_ball_noalloc(op, s, z, yhat, eps_dev, v_out, resid_out, stream=None):
+    """sh_prox_ball without device allocation or synchronisation (async)."""
+    _check(lib.sh_prox_ball_noalloc(op, _ptr(s), _ptr(z), _ptr(yhat), _ptr(eps_dev), _ptr(v_out), _ptr(resid_out),
+                                    _stream(stream)), "prox_ball_noalloc")
 
 
 def reweight(c, delta: float, W_out, stream=None):
