@@ -257,10 +257,15 @@ typedef struct {
                           a_b = 1 (0) or the density estimate of 1 / ||Phi_b|| (1, sh_block_weights),
                           and nu_p = nu if given, else the norm of problem p's a-weighted operator
                           sum_b a_b^2 Re(Phi_b^H Phi_b).  Any c_b > 0 keeps the solution set */
+  double tol_dual;     /* > 0 (with tol_rel > 0): the stopping test also needs the relative dual residual
+                          ||sum_j L_j^T z_j|| / max_j ||L_j^T z_j|| (sh_sdmm_info.kkt_dual) <= tol_dual,
+                          evaluated at the checks where the relative change and feasibility already
+                          hold; 0 = not tested */
 } sh_sdmm_params;
 
 /* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
- * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0, toeplitz 1, block_norm 1.  With a batched plan, a given
+ * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0, toeplitz 1, block_norm 1,
+ * tol_dual 1e-2.  With a batched plan, a given
  * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 

@@ -28,7 +28,10 @@ Readings where the paper is silent (each also listed in the design notes):
   normalisation for all blocks.
 * stop when ||x_n - x_{n-1}|| / ||x_n|| <= tol_rel and every block satisfies
   ||y_i - Phi_i x_n|| <= eps_i (1 + eps_slack), or after max_iter iterations;
-  tol_rel = 0 runs the fixed schedule.
+  tol_rel = 0 runs the fixed schedule.  Optionally (tol_dual > 0) the relative dual
+  residual ||sum_j L_j^T z_j|| / max_j ||L_j^T z_j|| (the stationarity part of the KKT
+  conditions, see kkt) must also be <= tol_dual.  The test is evaluated every
+  check_every iterations of a pass.
 * SARA reweighting (SARA paragraph: weights near the inverse of the previous
   solution's coefficients): w = delta / (delta + |Psi^dagger x|), delta_1 the
   population standard deviation of Psi^dagger x after pass 1 and
@@ -55,6 +58,8 @@ class Params:
     passes: int = 1
     rw_beta: float = 0.5
     block_weights: np.ndarray | None = None   # a_b per block; None: 1
+    check_every: int = 1          # the stopping test is evaluated every check_every iterations of a pass
+    tol_dual: float = 0.0         # > 0: the test also needs the relative dual residual <= tol_dual
 
 
 @dataclass
@@ -193,9 +198,10 @@ def sdmm_pass(pb: Problem, W, p: Params, st: State, record=False):
         feasible = bool(np.all(resid <= pb.eps_hat * (1.0 + p.eps_slack)))
         if record:
             info.history.append((rel, resid.copy()))
-        if p.tol_rel > 0 and rel <= p.tol_rel and feasible:
-            info.converged = True
-            break
+        if p.tol_rel > 0 and (it + 1) % p.check_every == 0 and rel <= p.tol_rel and feasible:
+            if p.tol_dual <= 0 or kkt(pb, st, W, p.gamma)[1] <= p.tol_dual:
+                info.converged = True
+                break
     info.objective = float(np.sum(np.abs(W * pb.psi.adj(st.x))))
     return st, info
 

@@ -160,6 +160,7 @@ void sh_sdmm_default_params(sh_sdmm_params* p) {
   p->w_from_x0 = 0;
   p->toeplitz = 1;
   p->block_norm = 1;
+  p->tol_dual = 1e-2;
 }
 
 sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream) {
@@ -180,10 +181,10 @@ struct sh_sdmm_s {
   int64_t N = 0, M = 0, D = 0;     // totals over the P problems
   int R = 0, kcg = 0;
   std::vector<double> nu, gamma, delta;   // per problem
-  bool have_delta = false;                 // delta holds a reweighting delta (given, or from a pass)
+  std::vector<char> have_delta;            // per problem: delta holds a reweighting delta (given, or from a pass)
   std::vector<double> cb;          // c_b per block (host)
   std::vector<double> eh;          // eps_hat = c_b eps per block (host)
-  const float* Wp = nullptr;       // weights of the current pass (NULL = identity)
+  const float* Wp = nullptr;       // weights of the current pass (the session's W, 1 where no weights were given)
   int iters_total = 0;
   double *s_rs = nullptr, *s_pap = nullptr, *s_misc = nullptr;
   // Replay of one captured iteration (hipGraph) on a session-owned stream.
@@ -207,7 +208,7 @@ namespace {
 // s_misc layout: [0, P) dx^2, [P, 2P) x^2, [2P, 3P) scratch, [3P, 4P) objective, [4P, 5P) scratch
 enum { MISC_DX = 0, MISC_X = 1, MISC_TMP = 2, MISC_OBJ = 3, MISC_TMP2 = 4, MISC_N = 5 };
 
-sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st);
+sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st, const std::vector<char>* which = nullptr);
 
 sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* W0, const float* x0, hipStream_t st) {
   sh_op op = s->op;
@@ -305,13 +306,19 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     gf[p] = float(s->gamma[p]);
   }
   SH_HIP(hipMemcpy(w.gamma.ptr, gf.data(), P * sizeof(float), hipMemcpyHostToDevice));
-  // weights of the first pass
+  // weights of the first pass: W0, or 1 (identity; gamma * 1 is gamma exactly, so the arithmetic is that of
+  // no weights).  One weight array for all passes and problems keeps the captured iteration valid while
+  // problems of a batch reweight at different times.
   if (W0) {
     SH_HIP(hipMemcpyAsync(w.W.ptr, W0, D * sizeof(float), hipMemcpyDeviceToDevice, st));
-    s->Wp = w.W.ptr;
+  } else {
+    hipLaunchKernelGGL(fill_kernel, dim3(nblk(D)), dim3(256), 0, st, w.W.ptr, D, 1.f);
+    SH_LAUNCHED();
   }
-  s->have_delta = s->prm.rw_delta0 > 0 && W0;
-  s->delta.assign(P, s->have_delta ? s->prm.rw_delta0 : 0.0);
+  s->Wp = w.W.ptr;
+  const bool given = s->prm.rw_delta0 > 0 && W0;
+  s->have_delta.assign(P, given ? 1 : 0);
+  s->delta.assign(P, given ? s->prm.rw_delta0 : 0.0);
   // initial state: zero, or y_psi = Psi^dagger x0, y_phi = Phi_hat x0, y_+ = x0, z = 0
   SH_HIP(hipMemsetAsync(w.zpsi.ptr, 0, D * sizeof(float), st));
   SH_HIP(hipMemsetAsync(w.zphi.ptr, 0, M * sizeof(float2), st));
@@ -332,9 +339,8 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   if (s->prm.w_from_x0) {   // weights of the first pass from Psi^dagger x0 (delta_1 = std per problem)
     SH_TRY(sh_psi_adj(s->psi, x0, w.spsi.ptr, st));
     std::fill(s->delta.begin(), s->delta.end(), 0.0);
-    s->have_delta = false;
+    std::fill(s->have_delta.begin(), s->have_delta.end(), 0);
     SH_TRY(sdmm_reweight(s, w.W.ptr, st));
-    s->Wp = w.W.ptr;
   }
   return SH_OK;
 }
@@ -456,21 +462,34 @@ sh_status sdmm_read(sh_sdmm s, std::vector<double>& rel, std::vector<double>& hr
   return SH_OK;
 }
 
-// Reweighting after a pass: delta_1 = std(Psi^dagger x) per problem (float64), then delta <- beta delta.
-sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st) {
+// Reweighting after a pass, from Psi^dagger x (in spsi): delta_1 = std(Psi^dagger x) per problem (float64) at a
+// problem's first reweighting, then delta <- beta delta.  `which` (per problem, NULL = all) selects the problems
+// whose pass just ended; the others keep their weights and delta.
+sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st, const std::vector<char>* which) {
   Work& w = s->w;
   const int P = s->P;
-  if (!s->have_delta) {   // the first reweighting: delta_1 = std of the analysis coefficients
+  auto sel = [&](int p) { return which == nullptr || (*which)[p] != 0; };
+  bool need_std = false;
+  for (int p = 0; p < P; ++p) need_std = need_std || (sel(p) && !s->have_delta[p]);
+  if (need_std) {   // first reweighting of some problem: delta_1 = std of its analysis coefficients
     double* sum = s->s_misc + MISC_TMP * P;
     double* var = s->s_misc + MISC_TMP2 * P;
     SH_TRY(w.red.std_dev(w.spsi.ptr, s->Dper, sum, var, st));
     std::vector<double> v(P);
     SH_HIP(hipMemcpyAsync(v.data(), var, P * sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));
-    for (int p = 0; p < P; ++p) s->delta[p] = std::sqrt(v[p] / double(s->Dper));
-    s->have_delta = true;
-  } else {
-    for (int p = 0; p < P; ++p) s->delta[p] *= s->prm.rw_beta;
+    for (int p = 0; p < P; ++p)
+      if (sel(p) && !s->have_delta[p]) {
+        s->delta[p] = std::sqrt(v[p] / double(s->Dper));
+        s->have_delta[p] = 2;   // set by this call: not scaled below
+      }
+  }
+  for (int p = 0; p < P; ++p) {
+    if (!sel(p)) continue;
+    if (s->have_delta[p] == 2)
+      s->have_delta[p] = 1;
+    else
+      s->delta[p] *= s->prm.rw_beta;
   }
   // delta = 0 (a pass that ended at x = 0) is valid: the weights are then 1 at zero coefficients
   for (int p = 0; p < P; ++p)
@@ -479,7 +498,14 @@ sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st) {
       return SH_ENONFINITE;
     }
   SH_HIP(hipMemcpyAsync(w.delta.ptr, s->delta.data(), P * sizeof(double), hipMemcpyHostToDevice, st));
-  SH_TRY(sh::launch_reweight(s->Dper, P, w.spsi.ptr, w.delta.ptr, 0.0, W_dst, st));
+  if (which == nullptr) {
+    SH_TRY(sh::launch_reweight(s->Dper, P, w.spsi.ptr, w.delta.ptr, 0.0, W_dst, st));
+  } else {
+    for (int p = 0; p < P; ++p)
+      if (sel(p))
+        SH_TRY(sh::launch_reweight(s->Dper, 1, w.spsi.ptr + p * s->Dper, w.delta.ptr + p, 0.0, W_dst + p * s->Dper,
+                                   st));
+  }
   SH_HIP(hipStreamSynchronize(st));   // the host copy of delta is read by the enqueued copy
   return SH_OK;
 }
@@ -539,6 +565,7 @@ sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps,
              "max_iter, passes, check_every >= 1 and cg_iters in [1, 64] required");
   SH_REQUIRE(prm->tol_rel >= 0 && prm->eps_slack >= 0 && prm->rw_beta > 0 && std::isfinite(prm->rw_beta),
              "tol_rel, eps_slack >= 0 and rw_beta > 0 required");
+  SH_REQUIRE(prm->tol_dual >= 0 && std::isfinite(prm->tol_dual), "tol_dual must be finite and >= 0");
   SH_REQUIRE(prm->graph == 0 || prm->graph == 1, "graph must be 0 or 1");
   SH_REQUIRE(prm->w_from_x0 == 0 || prm->w_from_x0 == 1, "w_from_x0 must be 0 or 1");
   SH_REQUIRE(prm->toeplitz == 0 || prm->toeplitz == 1, "toeplitz must be 0 or 1");
@@ -639,67 +666,90 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
   const int P = s->P;
   const int64_t per = s->per;
   std::vector<double> rel(P, INFINITY), hres;
-  std::vector<int> conv(P, 0), it_conv(P, 0);
-  // In the last pass a problem that meets the stopping test is final at that iteration: its image,
-  // residuals and relative change are taken then, while the batch iterates on for the others.
-  std::vector<int> taken(P, 0);
-  std::vector<double> rel_out(P, INFINITY), res_out(s->R, 0.0);
-  std::vector<std::vector<int>> pass_it(P);   // iterations of each pass, per problem
-  int it_last = 0, iters_total = 0, passes_done = 0;
-  for (int pass = 0; pass < prm->passes; ++pass) {
-    const bool last = pass + 1 == prm->passes;
-    std::fill(conv.begin(), conv.end(), 0);
-    int it = 0;
-    while (it < prm->max_iter) {
-      // without a stopping test, the whole pass is enqueued at once
-      const int chunk = prm->tol_rel > 0 ? std::min(prm->check_every, prm->max_iter - it) : prm->max_iter - it;
-      SH_TRY(sdmm_run(s, chunk, st));
-      it += chunk;
-      if (prm->tol_rel > 0) {
-        SH_TRY(sdmm_read(s, rel, hres, st));
-        bool all = true;
-        for (int p = 0; p < P; ++p) {
-          if (!conv[p]) {
-            bool ok = rel[p] <= prm->tol_rel;
-            for (int i = op->block_off[p]; ok && i < op->block_off[p + 1]; ++i)
-              ok = hres[i] <= s->eh[i] * (1.0 + prm->eps_slack);
-            if (ok) {
-              conv[p] = 1;
-              it_conv[p] = it;
-              if (last) {
-                SH_HIP(hipMemcpyAsync(x_out + p * per, s->w.x.ptr + p * per, per * sizeof(float),
-                                      hipMemcpyDeviceToDevice, st));
-                taken[p] = 1;
-                rel_out[p] = rel[p];
-                for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] / s->cb[i];
-              }
-            }
-          }
-          all = all && conv[p];
-        }
-        if (all) break;
-      }
-    }
-    it_last = it;
-    iters_total += it;
-    passes_done = pass + 1;
-    for (int p = 0; p < P; ++p) pass_it[p].push_back(conv[p] ? it_conv[p] : it);
-    if (!last) {  // reweight for the next pass from Psi^dagger x_n (in spsi)
-      SH_TRY(sdmm_reweight(s, s->w.W.ptr, st));
-      s->Wp = s->w.W.ptr;
-    }
-  }
-  // the problems not taken at their stopping iteration end with the current iterate
-  SH_TRY(sdmm_read(s, rel, hres, st));
-  for (int p = 0; p < P; ++p) {
-    if (taken[p]) continue;
+  // Per problem: its pass, iterations in that pass, iterations of each finished pass, and whether it
+  // is done (its last pass ended).  With a stopping test every problem of a batch moves through its
+  // passes on its own: when its test holds (or its pass reaches max_iter) it is reweighted and starts
+  // its next pass at once, and after its last pass its image, residuals, relative change and KKT
+  // residuals are taken, while the batch iterates on for the others.  So a batched solve returns what
+  // each problem would give alone (when max_iter is a multiple of check_every).  Without a stopping
+  // test all passes have max_iter iterations and every problem reweights together.
+  std::vector<int> pass(P, 0), itp(P, 0), done(P, 0), conv(P, 0);
+  std::vector<std::vector<int>> pass_it(P);
+  std::vector<double> rel_out(P, INFINITY), res_out(s->R, 0.0), kp_out(P, 0.0), kd_out(P, 0.0);
+  auto take = [&](int p, std::vector<double>& kp, std::vector<double>& kd) -> sh_status {
     SH_HIP(hipMemcpyAsync(x_out + p * per, s->w.x.ptr + p * per, per * sizeof(float), hipMemcpyDeviceToDevice, st));
     rel_out[p] = rel[p];
     for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] / s->cb[i];
+    kp_out[p] = kp[p];
+    kd_out[p] = kd[p];
+    done[p] = 1;
+    return SH_OK;
+  };
+  if (prm->tol_rel > 0) {
+    for (;;) {
+      int chunk = prm->check_every;
+      for (int p = 0; p < P; ++p)
+        if (!done[p]) chunk = std::min(chunk, prm->max_iter - itp[p]);
+      SH_TRY(sdmm_run(s, chunk, st));
+      for (int p = 0; p < P; ++p)
+        if (!done[p]) itp[p] += chunk;
+      SH_TRY(sdmm_read(s, rel, hres, st));
+      // relative change and feasibility, then (option tol_dual) the relative dual residual, evaluated only
+      // when some problem passed the first two
+      std::vector<char> ok(P, 0);
+      bool any = false;
+      for (int p = 0; p < P; ++p) {
+        if (done[p]) continue;
+        bool k = rel[p] <= prm->tol_rel;
+        for (int i = op->block_off[p]; k && i < op->block_off[p + 1]; ++i)
+          k = hres[i] <= s->eh[i] * (1.0 + prm->eps_slack);
+        ok[p] = k;
+        any = any || k;
+      }
+      std::vector<double> kp, kd, ko;
+      bool have_kkt = false;
+      if (any && prm->tol_dual > 0) {
+        SH_TRY(sdmm_kkt(s, kp, kd, ko, st));
+        have_kkt = true;
+        for (int p = 0; p < P; ++p) ok[p] = ok[p] && kd[p] <= prm->tol_dual;
+      }
+      std::vector<char> next(P, 0);   // problems whose pass ended and that go on to another pass
+      bool finishing = false;
+      for (int p = 0; p < P; ++p) {
+        if (done[p] || !(ok[p] || itp[p] >= prm->max_iter)) continue;
+        pass_it[p].push_back(itp[p]);
+        if (pass[p] + 1 == prm->passes) {
+          conv[p] = ok[p];
+          finishing = true;
+        } else {
+          next[p] = 1;
+          ++pass[p];
+          itp[p] = 0;
+        }
+      }
+      if (finishing) {
+        if (!have_kkt) SH_TRY(sdmm_kkt(s, kp, kd, ko, st));
+        for (int p = 0; p < P; ++p)
+          if (!done[p] && (int)pass_it[p].size() == prm->passes) SH_TRY(take(p, kp, kd));
+      }
+      bool any_next = false;
+      for (int p = 0; p < P; ++p) any_next = any_next || next[p];
+      if (any_next) SH_TRY(sdmm_reweight(s, s->w.W.ptr, st, &next));   // from Psi^dagger x_n (in spsi)
+      bool all = true;
+      for (int p = 0; p < P; ++p) all = all && done[p];
+      if (all) break;
+    }
+  } else {
+    for (int t = 0; t < prm->passes; ++t) {
+      SH_TRY(sdmm_run(s, prm->max_iter, st));
+      for (int p = 0; p < P; ++p) pass_it[p].push_back(prm->max_iter);
+      if (t + 1 < prm->passes) SH_TRY(sdmm_reweight(s, s->w.W.ptr, st));
+    }
+    SH_TRY(sdmm_read(s, rel, hres, st));
+    std::vector<double> kp, kd, ko;
+    SH_TRY(sdmm_kkt(s, kp, kd, ko, st));
+    for (int p = 0; p < P; ++p) SH_TRY(take(p, kp, kd));
   }
-  // KKT residuals of the state at exit (Psi^dagger x_n is still in spsi)
-  std::vector<double> kp, kd, kob;
-  SH_TRY(sdmm_kkt(s, kp, kd, kob, st));
   // objective with the last pass's weights and W_out, both from Psi^dagger of the returned images
   SH_TRY(sh_psi_adj(s->psi, x_out, s->w.spsi.ptr, st));
   SH_TRY(s->w.red.l1w(s->w.spsi.ptr, s->Wp, s->Dper, s->s_misc + MISC_OBJ * P, st));
@@ -713,18 +763,18 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
     for (int p = 0; p < P; ++p) {
       sh_sdmm_info& inf = info[p];
       inf = sh_sdmm_info{};
-      inf.iters_total = iters_total;
-      inf.passes_done = passes_done;
-      inf.converged = conv[p];
-      inf.iters_last = conv[p] ? it_conv[p] : it_last;
+      for (int v : pass_it[p]) inf.iters_total += v;
+      inf.passes_done = (int)pass_it[p].size();
+      inf.converged = prm->tol_rel > 0 ? conv[p] : 0;
+      inf.iters_last = pass_it[p].empty() ? 0 : pass_it[p].back();
       inf.rel_change = rel_out[p];
       inf.objective = obj[p];
       inf.gamma = s->gamma[p];
       inf.nu = s->nu[p];
       inf.delta = s->delta[p];
       inf.seconds = secs;
-      inf.kkt_primal = kp[p];
-      inf.kkt_dual = kd[p];
+      inf.kkt_primal = kp_out[p];
+      inf.kkt_dual = kd_out[p];
       for (int t = 0; t < (int)pass_it[p].size() && t < SH_PASS_RECORD; ++t) inf.pass_iters[t] = pass_it[p][t];
     }
   return SH_OK;

@@ -268,3 +268,81 @@ def test_batched_plan_of_one_problem_equals_single_plan(sh):
     finally:
         sh.op_destroy(opb)
         sh.op_destroy(op1)
+
+
+def test_batched_problems_move_through_their_passes_alone(sh):
+    """With a stopping test each problem of a batch ends its passes on its own schedule (reweighting
+    when its own test holds): its pass lengths equal those of the same problem solved in a plan of its
+    own, and so does its image."""
+    pbs = _problems(shapes=SHAPES, cfg=43)
+    n = pbs[0].n
+    # a dual-residual bound these small problems reach within the cap, so that passes end at different
+    # iterations in different problems
+    kw = dict(max_iter=300, tol_rel=1e-4, check_every=10, passes=3, tol_dual=0.1)
+    x, infos, resid, _ = _batched_solve(sh, pbs, _params(sh, **kw))
+    assert len({tuple(i["pass_iters"]) for i in infos}) > 1
+    for p, pb in enumerate(pbs):
+        op = sh.op_create(pb.uv, n, 2, pb.J, pb.offsets)
+        psi = sh.psi_create(n, 4)
+        try:
+            x1 = torch.empty((n, n), device="cuda")
+            info1, _ = sh.sdmm_solve(op, psi, _dev(pb.y, torch.complex64), pb.eps, None, None, _params(sh, **kw), x1)
+            torch.cuda.synchronize()
+        finally:
+            sh.psi_destroy(psi)
+            sh.op_destroy(op)
+        print(f"problem {p}: batched passes {infos[p]['pass_iters']}, alone {info1['pass_iters']}")
+        assert infos[p]["pass_iters"] == info1["pass_iters"], p
+        assert infos[p]["converged"] == info1["converged"]
+        assert helpers.rel(x[p], x1.cpu().numpy()) <= 1e-4
+
+
+def test_config4_workload_feasible_at_its_cap(sh):
+    """The 32-problem 256^2 workload (M_p log-uniform in [1e5, 1e6], 2..16 blocks each, Gaussian
+    coverage, 30 dB) solved to tolerance in one batched plan with the defaults (relative change 1e-4,
+    feasibility slack 1e-4, dual residual 1e-2) and 3 passes of at most 1000 iterations -- the cap
+    this workload needs: with 300, two problems whose weakest block has ||y_b|| within 2-3 % of eps_b
+    end their passes unconverged at 1.0001-1.0004 eps_b.  Every problem converges and every block
+    satisfies ||y_i - Phi_i x|| <= eps_i (1 + 1e-4) under the oracle's FP64 operator.  The data come
+    from the oracle's FP64 operator as well."""
+    import bench
+    from oracle import problem as oproblem
+    bw = bench.batched_workload()
+    P, n, M_p, R_p = bw["P"], bw["n"], bw["M_p"], bw["R_p"]
+    vo = np.concatenate([[0], np.cumsum(M_p)])
+    ops, ys, eps = [], [], []
+    print(f"config-4 workload: {P} problems, M = {int(M_p.sum())}; oracle data", flush=True)
+    for p in range(P):
+        lo, hi = int(vo[p]), int(vo[p + 1])
+        o = measurement.NUFFTCompiled(bw["uv"][lo:hi], n, 6)
+        clean = o.fwd(bw["x_true"][p].astype(np.float64))
+        sig = oproblem.noise_sigma(clean, 30.0)
+        ys.append(oproblem.add_noise(clean, sig, bw["draws"][lo:hi].astype(np.complex128)).astype(np.complex64))
+        eps.append(oproblem.eps_blocks(sig, bw["sizes"][p]))
+        ops.append(o)
+    y = np.concatenate(ys)
+    eps = np.concatenate(eps)
+    op = sh.op_create_batched(bw["uv"], M_p, n, 2, 6, bw["off"], R_p, tile=16, chunk=1024)
+    psi = sh.psi_create_batched(n, 4, sh.SARA_MASK, P)
+    try:
+        x = torch.empty((P, n, n), device="cuda")
+        print("config-4 workload: batched solve", flush=True)
+        infos, resid = sh.sdmm_solve(op, psi, _dev(y, torch.complex64), eps, None, None,
+                                     _params(sh, max_iter=1000, tol_rel=1e-4, passes=3), x)
+        xh = x.cpu().numpy()
+    finally:
+        sh.psi_destroy(psi)
+        sh.op_destroy(op)
+    worst, rb = 0.0, 0
+    for p in range(P):
+        assert infos[p]["converged"] == 1, (p, infos[p]["pass_iters"])
+        lo, hi = int(vo[p]), int(vo[p + 1])
+        v = ops[p].fwd(xh[p].astype(np.float64))
+        off = bw["off"][rb:rb + R_p[p] + 1] - lo
+        for i in range(R_p[p]):
+            r = np.linalg.norm(y[lo + off[i]:lo + off[i + 1]].astype(np.complex128) - v[off[i]:off[i + 1]])
+            worst = max(worst, r / eps[rb + i])
+            assert r <= eps[rb + i] * (1 + 1e-4), (p, i, r / eps[rb + i])
+        rb += R_p[p]
+    print(f"config-4 workload: all {P} converged, worst ||y_i - Phi_i x|| / eps_i = {worst:.7f} (FP64 oracle), "
+          f"most iterations {max(i['iters_total'] for i in infos)}")
