@@ -212,8 +212,10 @@ def warm_measure(sh, op, psi, y, eps, prm, n, dev, x_plain, x_true):
     finally:
         ws.close()
     xw = xw.reshape(n, n)
-    return {"warm_seconds": round(secs, 3), "warm_iters": info["iters_total"], "warm_passes": info["passes_done"],
-            "warm_pass_iters": info["pass_iters"],
+    wi = info.get("warm_info", info)   # the warm attempt's own record (the same as info unless it fell back)
+    return {"warm_seconds": round(secs, 3), "warm_path": info["path"], "warm_attempt_pass_iters": wi["pass_iters"],
+            "warm_attempt_converged": wi["converged"],
+            "warm_iters": info["iters_total"], "warm_passes": info["passes_done"], "warm_pass_iters": info["pass_iters"],
             "warm_converged_last_pass": info["converged"], "warm_max_resid_over_eps": float(np.max(res / eps)),
             "warm_rel_change_at_exit": info["rel_change"],
             "warm_kkt_primal": info["kkt_primal"], "warm_kkt_dual": info["kkt_dual"],

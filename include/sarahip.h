@@ -261,11 +261,16 @@ typedef struct {
                           ||sum_j L_j^T z_j|| / max_j ||L_j^T z_j|| (sh_sdmm_info.kkt_dual) <= tol_dual,
                           evaluated at the checks where the relative change and feasibility already
                           hold; 0 = not tested */
+  int32_t z_from_x0;   /* 1 (needs x0): the duals of the warm start also come from x0, from the optimality
+                          conditions of the weighted problem at x0: y_psi = soft(c, gamma W) and
+                          z_psi = c - y_psi for c = Psi^dagger x0, z_+ = 0, and per data block z_i = lambda (y_i - y_hat_i) with y_i the projection
+                          of Phi_hat_i x0 onto the block's ball and one lambda >= 0 per problem minimising
+                          ||Psi z_psi + Phi_hat^dagger z_phi||; 0: zero duals */
 } sh_sdmm_params;
 
 /* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
  * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0, toeplitz 1, block_norm 1,
- * tol_dual 1e-2.  With a batched plan, a given
+ * tol_dual 1e-2, z_from_x0 0.  With a batched plan, a given
  * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 

@@ -165,6 +165,36 @@ def init_state(pb: Problem, x0=None) -> State:
     return State(x, pb.psi.adj(x), np.zeros(D), pb.fwd(x), np.zeros(M, complex), x.copy(), np.zeros((n, n)))
 
 
+def dual_warm_start(pb: Problem, st: State, W, gamma: float) -> State:
+    """Duals for a warm start at x0 = st.x (whose splits hold y_j = L_j x0), from the optimality conditions
+    of the weighted problem at x0 (a reading: the paper starts SDMM from zero):
+    * l1 split: the soft threshold's own split of c = Psi^dagger x0, y_psi = soft(c, gamma W) and
+      z_psi = c - y_psi (the subgradient gamma W sign(c) where |c| exceeds the threshold, c below it);
+    * positivity: z_+ = 0 (x0 >= 0);
+    * data blocks: y_i = the projection of Phi_hat_i x0 onto ball i and z_i = lambda (y_i - y_hat_i), a
+      multiple of the ball's outward normal, with the single lambda >= 0 that minimises the stationarity
+      residual ||Psi z_psi + sum_i Phi_hat_i^dagger z_i||, lambda = max(0, -<Psi z_psi, g> / <g, g>),
+      g = sum_i Phi_hat_i^dagger (y_i - y_hat_i)."""
+    st = st.copy()
+    W = np.ones_like(st.y_psi) if W is None else np.asarray(W, dtype=np.float64)
+    c = pb.psi.adj(st.x)
+    st.y_psi = prox.soft(c, gamma * W)
+    st.z_psi = c - st.y_psi
+    s_phi = pb.fwd(st.x)
+    d = np.empty_like(s_phi)
+    for i, (lo, hi) in enumerate(pb.blocks()):
+        d[lo:hi] = prox.ball(s_phi[lo:hi], pb.y_hat[lo:hi], pb.eps_hat[i]) - pb.y_hat[lo:hi]
+    g = pb.adj(d)
+    h = pb.psi.fwd(st.z_psi)
+    gg = float(np.sum(g * g))
+    lam = max(0.0, -float(np.sum(h * g)) / gg) if gg > 0 else 0.0
+    st.y_phi = pb.y_hat + d
+    st.z_phi = lam * d
+    st.y_pos = np.array(st.x, copy=True)
+    st.z_pos = np.zeros_like(st.x)
+    return st
+
+
 def sdmm_pass(pb: Problem, W, p: Params, st: State, record=False):
     """One weighted-l1 solve of (3) by SDMM, continuing from state `st` (modified copy returned)."""
     st = st.copy()
@@ -215,14 +245,17 @@ def reweight(coeffs: np.ndarray, delta: float) -> np.ndarray:
     return np.where(den > 0, delta / np.where(den > 0, den, 1.0), 1.0)
 
 
-def sara(op, psi, y, offsets, eps, p: Params, x0=None, W0=None, delta0=None, record=False):
+def sara(op, psi, y, offsets, eps, p: Params, x0=None, W0=None, delta0=None, record=False, duals_from_x0=False):
     """SARA: p.passes weighted-l1 solves of (3), reweighting between passes.
 
     Returns (x, W_last, infos, state).  With x0 the SDMM state is warm-started
-    from x0; with W0 the first pass uses W0 (delta0 its delta), else W = I.
+    from x0 (and with duals_from_x0 its duals from :func:`dual_warm_start`); with
+    W0 the first pass uses W0 (delta0 its delta), else W = I.
     """
     pb = Problem(op, psi, y, offsets, eps, p.nu, p.block_weights)
     st = init_state(pb, x0)
+    if duals_from_x0:
+        st = dual_warm_start(pb, st, W0, p.gamma)
     W = W0
     delta = delta0
     infos = []

@@ -457,6 +457,16 @@ sh_status ball_kernels(sh_op op, const float2* s, float2* z, const float2* yhat,
   return SH_OK;
 }
 
+sh_status ball_norms_only(sh_op op, const float2* s, const float2* z, const float2* yhat, const float* cblk, double* rho,
+                          double* resid, hipStream_t st) {
+  const unsigned nc = (unsigned)op->n_chunks;
+  hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr);
+  hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
+                     op->chunk_first_d.ptr, op->R, rho, resid);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
 sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
                            double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st) {
   ProfScope ps("prox", st);

@@ -40,6 +40,9 @@ sh_status launch_prox_l1(int64_t per, int P, const float* s, float* z, const flo
 sh_status launch_prox_pos(int64_t N, const float* s, float* z, float* v, hipStream_t st);
 // cblk: per-block weights c_b (device R floats) or NULL (1): the split uses c_b s (s = Phi x unweighted)
 // and v is returned multiplied by c_b, ready for the unweighted adjoint.
+// Only the block norms of the ball step: rho_b = ||c_b s_b + z_b - yhat_b||, resid_b = ||c_b s_b - yhat_b||.
+sh_status ball_norms_only(sh_op op, const float2* s, const float2* z, const float2* yhat, const float* cblk, double* rho,
+                          double* resid, hipStream_t st);
 // The same without timing events (sh_prox_ball_noalloc).
 sh_status ball_kernels(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
                        double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st);

@@ -78,7 +78,50 @@ __global__ void cg_dir(const float* __restrict__ r, float* __restrict__ pv, int6
   const float beta = d > 0 ? float(rs_new[p] / d) : 0.f;
   pv[i] = fmaf(beta, pv[i], r[i]);
 }
+// Dual warm start of the l1 split at s = Psi^dagger x0: the soft threshold's own split of s,
+// y = soft(s, gamma_p W), z = s - y (= s clipped to [-gamma_p W, gamma_p W], the subgradient gamma W sign(s)
+// where |s| exceeds the threshold); v = y - z.
+__global__ void dual_l1_init(const float* __restrict__ sv, const float* __restrict__ W, const float* __restrict__ gamma,
+                             float* __restrict__ z, float* __restrict__ v, int64_t per) {
+  SEG_INDEX(per)
+  const float c = sv[i];
+  const float tau = gamma[p] * W[i];
+  const float m = fabsf(c) - tau;
+  const float y = m > 0.f ? copysignf(m, c) : 0.f;
+  const float zz = c - y;
+  z[i] = zz;
+  v[i] = y - zz;
+}
 #undef SEG_INDEX
+
+// Data splits at the warm start, per reduction chunk (one block each): s_hat = c_b s, y = the projection of
+// s_hat onto block b's ball, z = lambda_p (y - yhat) (a multiple of the ball's outward normal at y, as at
+// a fixed point), v = c_b (y - z - s_hat).  With mode 0 only u = c_b (y - yhat) is written (to v), the
+// vector whose adjoint fixes lambda.
+__global__ __launch_bounds__(256) void dual_ball_init(const float2* __restrict__ s_in, const float2* __restrict__ yh,
+                                                      const int4* __restrict__ chunks, const float* __restrict__ cblk,
+                                                      const double* __restrict__ eps, const double* __restrict__ rho,
+                                                      const int* __restrict__ block_prob,
+                                                      const double* __restrict__ lambda, float2* __restrict__ z,
+                                                      float2* __restrict__ v, int mode) {
+  const int4 c = chunks[blockIdx.x];
+  const float cb = cblk[c.x];
+  const double r = rho[c.x], e = eps[c.x];
+  const float ratio = r <= e ? 1.0f : float(e / r);
+  const float lam = mode ? float(lambda[block_prob[c.x]]) : 0.f;
+  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
+    const float2 si = s_in[i], yv = yh[i];
+    const float sr = cb * si.x, sim = cb * si.y;
+    const float dr = (sr - yv.x) * ratio, di = (sim - yv.y) * ratio;   // y - yhat
+    if (!mode) {
+      v[i] = make_float2(cb * dr, cb * di);
+    } else {
+      const float zr = lam * dr, zi = lam * di;
+      z[i] = make_float2(zr, zi);
+      v[i] = make_float2(cb * (yv.x + dr - zr - sr), cb * (yv.y + di - zi - sim));
+    }
+  }
+}
 
 inline unsigned nblk(int64_t n) { return (unsigned)sh::cdiv(n, 256); }
 
@@ -161,6 +204,7 @@ void sh_sdmm_default_params(sh_sdmm_params* p) {
   p->toeplitz = 1;
   p->block_norm = 1;
   p->tol_dual = 1e-2;
+  p->z_from_x0 = 0;
 }
 
 sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream) {
@@ -181,6 +225,7 @@ struct sh_sdmm_s {
   int64_t N = 0, M = 0, D = 0;     // totals over the P problems
   int R = 0, kcg = 0;
   std::vector<double> nu, gamma, delta;   // per problem
+  std::vector<double> lambda0;             // per problem: the data-dual scale of a dual warm start
   std::vector<char> have_delta;            // per problem: delta holds a reweighting delta (given, or from a pass)
   std::vector<double> cb;          // c_b per block (host)
   std::vector<double> eh;          // eps_hat = c_b eps per block (host)
@@ -209,6 +254,51 @@ namespace {
 enum { MISC_DX = 0, MISC_X = 1, MISC_TMP = 2, MISC_OBJ = 3, MISC_TMP2 = 4, MISC_N = 5 };
 
 sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st, const std::vector<char>* which = nullptr);
+
+// Duals of a warm start from x0, taken from the optimality conditions of the weighted problem at x0 (the
+// primal splits already hold y_j = L_j x0):
+//   l1 split:   y_psi = soft(Psi^dagger x0, gamma W), z_psi = Psi^dagger x0 - y_psi (the subgradient
+//               gamma W sign(.) where a coefficient exceeds its threshold, the coefficient itself below);
+//   positivity: z_+ = 0 (x0 >= 0);
+//   data:       y_i = the projection of Phi_hat_i x0 onto ball i, z_i = lambda (y_i - yhat_i) along the balls'
+//               outward normals, with one lambda >= 0 per problem chosen so that the stationarity residual
+//               ||Psi z_psi + Phi_hat^dagger z_phi|| is smallest: lambda = max(0, -<Psi z_psi, g> / <g, g>),
+//               g = Phi_hat^dagger (y - yhat).
+// From a zero dual the iteration would first have to rebuild all of them.
+sh_status sdmm_dual_warm_start(sh_sdmm s, hipStream_t st) {
+  sh_op op = s->op;
+  Work& w = s->w;
+  const int P = s->P;
+  const int64_t per = s->per;
+  // l1 split (vpsi holds Psi^dagger x0)
+  SH_HIP(hipMemcpyAsync(w.spsi.ptr, w.vpsi.ptr, s->D * sizeof(float), hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(dual_l1_init, dim3(nblk(s->Dper), P), dim3(256), 0, st, w.spsi.ptr, w.W.ptr, w.gamma.ptr,
+                     w.zpsi.ptr, w.vpsi.ptr, s->Dper);
+  SH_LAUNCHED();
+  SH_TRY(sh_psi_fwd(s->psi, w.zpsi.ptr, w.t1.ptr, st));                        // Psi z_psi
+  // data splits: block norms ||c s - yhat|| (zero dual) give each block's projection
+  SH_HIP(hipMemsetAsync(w.zphi.ptr, 0, s->M * sizeof(float2), st));
+  SH_TRY(sh::ball_norms_only(op, w.sphi.ptr, w.zphi.ptr, w.yhat.ptr, w.cblk.ptr, w.rho.ptr, w.kkt.ptr + 8 * P, st));
+  const unsigned nc = (unsigned)op->n_chunks;
+  hipLaunchKernelGGL(dual_ball_init, dim3(nc), dim3(256), 0, st, w.sphi.ptr, w.yhat.ptr, op->chunks.ptr, w.cblk.ptr,
+                     w.eps_hat.ptr, w.rho.ptr, op->block_prob_d.ptr, (const double*)nullptr, w.zphi.ptr, w.vtmp.ptr, 0);
+  SH_LAUNCHED();
+  SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.t2.ptr, false, nullptr, st));        // g = Phi_hat^dagger (y - yhat)
+  double* k = w.kkt.ptr;
+  SH_TRY(w.red.dot(w.t1.ptr, w.t2.ptr, per, k, st));
+  SH_TRY(w.red.dot(w.t2.ptr, w.t2.ptr, per, k + P, st));
+  std::vector<double> h(2 * P), lam(P);
+  SH_HIP(hipMemcpyAsync(h.data(), k, 2 * P * sizeof(double), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipStreamSynchronize(st));
+  for (int p = 0; p < P; ++p) lam[p] = h[P + p] > 0 ? std::max(0.0, -h[p] / h[P + p]) : 0.0;
+  s->lambda0 = lam;
+  SH_HIP(hipMemcpyAsync(k, lam.data(), P * sizeof(double), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(dual_ball_init, dim3(nc), dim3(256), 0, st, w.sphi.ptr, w.yhat.ptr, op->chunks.ptr, w.cblk.ptr,
+                     w.eps_hat.ptr, w.rho.ptr, op->block_prob_d.ptr, (const double*)k, w.zphi.ptr, w.vphi.ptr, 1);
+  SH_LAUNCHED();
+  SH_HIP(hipStreamSynchronize(st));   // lam (host) is read by the enqueued copy
+  return SH_OK;
+}
 
 sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* W0, const float* x0, hipStream_t st) {
   sh_op op = s->op;
@@ -341,6 +431,9 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     std::fill(s->delta.begin(), s->delta.end(), 0.0);
     std::fill(s->have_delta.begin(), s->have_delta.end(), 0);
     SH_TRY(sdmm_reweight(s, w.W.ptr, st));
+  }
+  if (s->prm.z_from_x0) {   // duals from the optimality conditions at x0 (see sdmm_dual_warm_start)
+    SH_TRY(sdmm_dual_warm_start(s, st));
   }
   return SH_OK;
 }
@@ -568,6 +661,7 @@ sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps,
   SH_REQUIRE(prm->tol_dual >= 0 && std::isfinite(prm->tol_dual), "tol_dual must be finite and >= 0");
   SH_REQUIRE(prm->graph == 0 || prm->graph == 1, "graph must be 0 or 1");
   SH_REQUIRE(prm->w_from_x0 == 0 || prm->w_from_x0 == 1, "w_from_x0 must be 0 or 1");
+  SH_REQUIRE(prm->z_from_x0 == 0 || prm->z_from_x0 == 1, "z_from_x0 must be 0 or 1");
   SH_REQUIRE(prm->toeplitz == 0 || prm->toeplitz == 1, "toeplitz must be 0 or 1");
   SH_REQUIRE(prm->block_norm == 0 || prm->block_norm == 1, "block_norm must be 0 or 1");
   for (int i = 0; i < op->R; ++i) {
@@ -590,6 +684,7 @@ sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps
   *out = nullptr;
   SH_TRY(sdmm_validate(op, psi, y, eps, params));
   SH_REQUIRE(!params->w_from_x0 || (x0 && !W), "w_from_x0 needs x0 and no W");
+  SH_REQUIRE(!params->z_from_x0 || x0, "z_from_x0 needs x0");
   sh_sdmm s = new (std::nothrow) sh_sdmm_s();
   if (!s) {
     sh::set_error("host allocation failed");

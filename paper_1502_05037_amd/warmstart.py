@@ -4,8 +4,10 @@ The network sees the dirty image Phi^dagger y divided by the PSF peak ((Phi^dagg
 so that a unit point source gives a unit peak) and scaled to unit RMS; it predicts the solution
 of the plain solver in the same units.  The prediction x0 then starts SDMM together with the weights
 W0 = delta / (delta + |Psi^dagger x0|), delta = std(Psi^dagger x0): the network stands in for the
-first weighted-l1 pass, so a warm solve runs one pass fewer.  The constraints and the stopping test
-of the solve are unchanged, so the network only changes how many iterations are needed.
+first weighted-l1 pass, so a warm solve runs one pass fewer; the SDMM duals start from the
+optimality conditions at x0.  The constraints and the stopping test of the solve are unchanged, so
+the network only changes how many iterations are needed, and the plain solve from zero is the
+fallback when the warm-started one does not meet the test.
 
 Every step runs in libsarahip (operator, dictionary, solver, U-Net kernels); this module only
 arranges the calls.  Training pairs come from the plain batched solver on synthetic skies.
@@ -92,10 +94,17 @@ class WarmStart:
         return x0
 
 
-def warm_solve(ws: WarmStart, op, psi, y, eps, params, n: int, dev, x_out, replace_first_pass: bool = True):
+def warm_solve(ws: WarmStart, op, psi, y, eps, params, n: int, dev, x_out, replace_first_pass: bool = True,
+               duals: bool = True, fallback: bool = True):
     """SDMM from the network's x0.  With replace_first_pass the first weights come from x0 by the
     reweighting rule and the solve runs one pass fewer than params.passes; otherwise x0 only starts
-    the first (unweighted) pass.  Returns (info, block residuals, seconds including the network)."""
+    the first (unweighted) pass.  With duals the SDMM duals also start from x0 (z_from_x0).
+
+    The plain solve from zero stays the fallback: if the warm-started solve ends without meeting its
+    stopping test in its last pass, or with a block outside eps_i (1 + eps_slack), the plain solve with
+    `params` runs from zero and its image is returned.  Returns (info, block residuals, seconds including
+    the network and any fallback); info["path"] is "warm" or "plain fallback" (info["warm_info"] then
+    holds the warm attempt's record)."""
     import torch
     P = sh.op_query(op)["P"]
     torch.cuda.synchronize()
@@ -107,6 +116,18 @@ def warm_solve(ws: WarmStart, op, psi, y, eps, params, n: int, dev, x_out, repla
     if replace_first_pass:
         prm.passes = max(1, params.passes - 1)
         prm.w_from_x0 = 1
+    prm.z_from_x0 = 1 if duals else 0
     info, resid = sh.sdmm_solve(op, psi, y, eps, None, x0, prm, x_out)
+    infos = info if isinstance(info, list) else [info]
+    ok = all(i["converged"] == 1 for i in infos) and bool(np.all(resid <= np.asarray(eps) * (1.0 + params.eps_slack)))
+    if fallback and not ok:
+        warm = info
+        info, resid = sh.sdmm_solve(op, psi, y, eps, None, None, params, x_out)
+        for i in (info if isinstance(info, list) else [info]):
+            i["path"] = "plain fallback"
+            i["warm_info"] = warm
+    else:
+        for i in infos:
+            i["path"] = "warm"
     torch.cuda.synchronize()
     return info, resid, time.perf_counter() - t0

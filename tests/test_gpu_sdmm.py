@@ -176,6 +176,27 @@ def test_warm_start_parity(sh):
     assert helpers.rel(x, x_ref) <= 1e-4
 
 
+def test_dual_warm_start_parity(sh):
+    """A warm start whose weights (from x0 by the reweighting rule) and duals (from the optimality
+    conditions at x0) both come from x0: the same fixed schedule as the oracle's dual_warm_start."""
+    pb = helpers.build(3, 32, 900, 2, 8, prob=2)
+    psi, nu, gamma, a = _oracle_setup(pb)
+    x0 = 0.9 * pb.x_true
+    c0 = psi.adj(x0)
+    d0 = float(np.std(c0))
+    W0 = sdmm.reweight(c0, d0)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=60, cg_iters=8, block_weights=a, passes=2)
+    x_ref, *_ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p, x0=x0, W0=W0, delta0=d0, duals_from_x0=True)
+    x_plain_ref, *_ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p, x0=x0, W0=W0, delta0=d0)
+    x, info, _, _ = _gpu_solve(sh, pb, _params(sh, gamma=gamma, nu=nu, max_iter=60, cg_iters=8, passes=2, w_from_x0=1,
+                                               z_from_x0=1), x0=x0)
+    err = helpers.rel(x, x_ref)
+    print(f"dual warm start: image error vs oracle {err:.2e} (the zero-dual warm start differs by "
+          f"{helpers.rel(x_plain_ref, x_ref):.2e})")
+    assert err <= 1e-4
+    assert helpers.rel(x_plain_ref, x_ref) > 10 * err
+
+
 def test_run_to_tolerance_is_feasible(sh):
     pb = helpers.build(4, 64, 4096, 4, 6, prob=3)
     prm = _params(sh, max_iter=3000, tol_rel=1e-4, check_every=1, passes=2)

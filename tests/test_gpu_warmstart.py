@@ -62,11 +62,12 @@ def test_what_the_trained_network_gains_on_held_out_problems(sh, ws_mod):
     """On held-out 256^2 problems of both training kinds: the network's first image is closer to the
     plain solver's solution than the dirty image in PSF-peak units (what the data alone give) and
     than the zero start, and within twice the error of the best multiple of the dirty image (a
-    rescaling that needs the solution); the warm-started solve then meets the same stopping test with
-    every constraint satisfied (checked with the oracle's FP64 operator).
-    Iteration counts and errors against the true sky are printed, not asserted: with the default step
-    the plain solve itself stops within a few hundred iterations, and a warm start then saves little
-    (see the design notes)."""
+    rescaling that needs the solution).  The warm-started solve then runs with the plain solve's own
+    stopping test (relative change 1e-4, feasibility slack 1e-4, dual residual 1e-2, 5 passes of at
+    most 300 iterations, the network standing in for the first); whichever path produced the image
+    (warm, or the plain fallback when the warm run does not meet the test), every constraint holds
+    within eps_i (1 + 1e-4) under the oracle's FP64 operator.  Iterations and times are printed, not
+    asserted: the network does not save iterations under this test (measured in the design notes)."""
     from paper_1502_05037_amd import train_warmstart as tw
     dev = torch.device("cuda:0")
     ws = ws_mod.WarmStart.load()
@@ -79,7 +80,6 @@ def test_what_the_trained_network_gains_on_held_out_problems(sh, ws_mod):
             try:
                 y, eps = tw.observe(op, pr, dev)
                 prm = tw.solve_params()
-                prm.eps_slack = 1e-3
                 x_plain = torch.empty((1, n, n), device=dev)
                 info_p, _ = sh.sdmm_solve(op, psi, y, eps, None, None, prm, x_plain)
                 x0 = ws.predict(op, y, n, 1, dev)
@@ -100,16 +100,61 @@ def test_what_the_trained_network_gains_on_held_out_problems(sh, ws_mod):
                 x_warm = torch.empty((1, n, n), device=dev)
                 info_w, res_w, secs = ws_mod.warm_solve(ws, op, psi, y, eps, prm, n, dev, x_warm)
                 xt = pr["x_true"][0].astype(np.float64)
-                print(f"{kind}: iterations plain {info_p['iters_total']}, warm {info_w['iters_total']}; error vs "
-                      f"true sky plain {helpers.rel(xs, xt):.4f}, warm {helpers.rel(x_warm.cpu().numpy()[0], xt):.4f}")
-                assert info_w["converged"] == 1
-                v = measurement.NUFFT(pr["uv"], n, pr["J"]).fwd(x_warm.cpu().numpy()[0].astype(np.float64))
+                wi = info_w.get("warm_info", info_w)
+                print(f"{kind}: plain {info_p['pass_iters']} (converged {info_p['converged']}); warm "
+                      f"{wi['pass_iters']} (converged {wi['converged']}), image from the {info_w['path']} path; "
+                      f"error vs true sky plain {helpers.rel(xs, xt):.4f}, returned {helpers.rel(x_warm.cpu().numpy()[0], xt):.4f}")
+                assert info_w["path"] in ("warm", "plain fallback")
+                if info_w["path"] == "warm":
+                    assert info_w["converged"] == 1
+                v = measurement.NUFFTCompiled(pr["uv"], n, pr["J"]).fwd(x_warm.cpu().numpy()[0].astype(np.float64))
                 yy = y.cpu().numpy().astype(np.complex128)
                 for i in range(R):
                     lo, hi = pr["off"][i], pr["off"][i + 1]
-                    assert np.linalg.norm(yy[lo:hi] - v[lo:hi]) <= eps[i] * (1 + 1.1e-3)
+                    assert np.linalg.norm(yy[lo:hi] - v[lo:hi]) <= eps[i] * (1 + 1e-4)
             finally:
                 sh.psi_destroy(psi)
                 sh.op_destroy(op)
     finally:
         ws.close()
+
+
+def test_warm_start_falls_back_to_the_plain_solve(sh, ws_mod):
+    """A warm start that cannot meet the stopping test (a network scaled so that x0 is far too bright, and
+    passes too short to recover) hands over to the plain solve from zero: the returned image is the plain
+    solve's, bit for bit, and the record says which path produced it."""
+    from paper_1502_05037_amd import train_warmstart as tw
+    dev = torch.device("cuda:0")
+    flat = np.load(ws_mod.WEIGHTS, allow_pickle=False).copy()
+    ws = ws_mod.WarmStart(flat)
+    try:
+        # scale the head: the prediction becomes 50 times the network's image
+        meta_layers = ws_mod.layer_list(32, 4)
+        size = 0
+        for kind, cin, cout in meta_layers[:-1]:
+            k = 9 if kind == "conv3" else (4 if kind == "tconv" else 1)
+            size += cin * cout * k + cout
+        flat[size:] *= 50.0
+        sh.unet_set_params(ws.u, flat)
+        pr = tw.make_problems(10 ** 6 + 2, 1, "c2")
+        n = pr["n"]
+        op = sh.op_create(pr["uv"], n, 2, pr["J"], pr["off"])
+        psi = sh.psi_create(n, 4)
+        try:
+            y, eps = tw.observe(op, pr, dev)
+            prm = tw.solve_params(passes=2, max_iter=20)
+            x_w = torch.empty((1, n, n), device=dev)
+            info_w, res_w, _ = ws_mod.warm_solve(ws, op, psi, y, eps, prm, n, dev, x_w)
+            x_p = torch.empty((1, n, n), device=dev)
+            info_p, res_p = sh.sdmm_solve(op, psi, y, eps, None, None, prm, x_p)
+            torch.cuda.synchronize()
+        finally:
+            sh.psi_destroy(psi)
+            sh.op_destroy(op)
+    finally:
+        ws.close()
+    print(f"warm attempt {info_w.get('warm_info', {}).get('pass_iters')} -> {info_w['path']}")
+    assert info_w["path"] == "plain fallback"
+    assert info_w["warm_info"]["converged"] == 0
+    assert torch.equal(x_w, x_p)
+    np.testing.assert_array_equal(res_w, res_p)
