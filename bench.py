@@ -429,6 +429,30 @@ def time_to_tol(sh, op, psi, y, eps, n, dev, x_true, long_iters):
             "time_to_tol_image_rel_diff": float(torch.linalg.vector_norm(x - xl) / torch.linalg.vector_norm(xl)),
             "without_dual_test_image_rel_diff": float(torch.linalg.vector_norm(x0 - xl) / torch.linalg.vector_norm(xl))}
         log(f"[bench] long fixed schedule: {tol['long_fixed_schedule']}")
+    # block-subset iterations (a random fraction of the 64 blocks per iteration), same stopping test
+    tol["block_subset"] = []
+    for frac in (0.5, 0.25):
+        pf = sh.sdmm_default_params()
+        pf.tol_rel, pf.passes, pf.max_iter, pf.block_fraction, pf.block_seed = 1e-4, 5, 300, frac, 1
+        xs = torch.empty((n, n), device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        isub, rsub = sh.sdmm_solve(op, psi, y, eps, None, None, pf, xs)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        sess = sh.sdmm_create(op, psi, y, eps, None, None, pf)
+        try:
+            sh.sdmm_iterate(sess, 3)
+            it_ms = stats(event_times(lambda: sh.sdmm_iterate(sess, 1), 20))
+        finally:
+            sh.sdmm_destroy(sess)
+        tol["block_subset"].append({
+            "block_fraction": frac, "seconds": round(secs, 3), "pass_iters": isub["pass_iters"],
+            "iters": isub["iters_total"], "converged": isub["converged"], "kkt_dual": isub["kkt_dual"],
+            "max_resid_over_eps": float(np.max(rsub / eps)), "iteration_ms": it_ms["median_ms"],
+            "error_vs_true_sky": float(torch.linalg.vector_norm(xs - x_true) / nx),
+            "image_rel_diff_vs_full": float(torch.linalg.vector_norm(xs - x) / torch.linalg.vector_norm(x))})
+        log(f"[bench] block-subset SDMM {tol['block_subset'][-1]}")
     tol.update(warm_measure(sh, op, psi, y, eps, p2, n, dev, x, x_true))
     return tol, x
 

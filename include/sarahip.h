@@ -266,11 +266,21 @@ typedef struct {
                           z_psi = c - y_psi for c = Psi^dagger x0, z_+ = 0, and per data block z_i = lambda (y_i - y_hat_i) with y_i the projection
                           of Phi_hat_i x0 onto the block's ball and one lambda >= 0 per problem minimising
                           ||Psi z_psi + Phi_hat^dagger z_phi||; 0: zero duals */
+  double block_fraction; /* < 1: block-subset iterations (SDMM paragraph: iterations that use only a subset
+                          of the data blocks y_i): in iteration k (counted from the session's start) block b
+                          takes part when u(k R + b) < block_fraction, u(c) the c-th output of the SplitMix64
+                          sequence seeded with block_seed taken to [0, 1) by its top 53 bits; only those
+                          blocks are degridded, projected and gridded (their change to Phi_hat^T (y - z)),
+                          the others keep their split variables.  The x-update still uses every block
+                          (its right-hand side holds Phi_hat^T (y - z) as a running image, its matrix the
+                          Toeplitz product).  The stopping test evaluates every block's residual at x_n.
+                          Needs toeplitz = 1 and z_from_x0 = 0.  1 = every block every iteration */
+  uint64_t block_seed;
 } sh_sdmm_params;
 
 /* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
  * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0, toeplitz 1, block_norm 1,
- * tol_dual 1e-2, z_from_x0 0.  With a batched plan, a given
+ * tol_dual 1e-2, z_from_x0 0, block_fraction 1, block_seed 0.  With a batched plan, a given
  * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 

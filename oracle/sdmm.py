@@ -32,6 +32,9 @@ Readings where the paper is silent (each also listed in the design notes):
   residual ||sum_j L_j^T z_j|| / max_j ||L_j^T z_j|| (the stationarity part of the KKT
   conditions, see kkt) must also be <= tol_dual.  The test is evaluated every
   check_every iterations of a pass.
+* block-subset iterations (the SDMM paragraph's stochastic variant, a reading):
+  in iteration k only the data blocks selected by block_selected update their
+  split variables; the x-update uses every block's current (y_i, z_i).
 * SARA reweighting (SARA paragraph: weights near the inverse of the previous
   solution's coefficients): w = delta / (delta + |Psi^dagger x|), delta_1 the
   population standard deviation of Psi^dagger x after pass 1 and
@@ -60,6 +63,8 @@ class Params:
     block_weights: np.ndarray | None = None   # a_b per block; None: 1
     check_every: int = 1          # the stopping test is evaluated every check_every iterations of a pass
     tol_dual: float = 0.0         # > 0: the test also needs the relative dual residual <= tol_dual
+    block_fraction: float = 1.0   # < 1: block-subset iterations (see block_selected)
+    block_seed: int = 0
 
 
 @dataclass
@@ -71,9 +76,10 @@ class State:
     z_phi: np.ndarray
     y_pos: np.ndarray
     z_pos: np.ndarray
+    k: int = 0                    # SDMM iterations run from this state's start (draws the block subsets)
 
     def copy(self) -> "State":
-        return State(*(np.array(getattr(self, f), copy=True) for f in self.__dataclass_fields__))
+        return State(*(np.array(getattr(self, f), copy=True) for f in list(self.__dataclass_fields__)[:-1]), k=self.k)
 
 
 @dataclass
@@ -84,6 +90,25 @@ class Info:
     block_resid: np.ndarray = field(default_factory=lambda: np.zeros(0))  # ||y_i - Phi_i x||, user units
     objective: float = 0.0
     history: list = field(default_factory=list)
+
+
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, c: int) -> int:
+    """The c-th output (counted from 0) of the SplitMix64 sequence seeded with `seed` (Steele, Lea &
+    Flood 2014): state_c = seed + (c + 1) * 0x9E3779B97F4A7C15 mod 2^64, then two xor-shift-multiply
+    rounds and a final xor-shift."""
+    z = (seed + (c + 1) * 0x9E3779B97F4A7C15) & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def block_selected(seed: int, k: int, R: int, fraction: float) -> np.ndarray:
+    """Blocks of iteration k in block-subset SDMM (the SDMM paragraph: iterations that use only a subset of the
+    data blocks y_i): block b takes part when u = (top 53 bits of splitmix64(seed, k R + b)) / 2^53 < fraction."""
+    return np.array([(splitmix64(seed, k * R + b) >> 11) * 2.0 ** -53 < fraction for b in range(R)], dtype=bool)
 
 
 def cg(Q, b, x0, iters=None, tol=1e-12, max_iter=500):
@@ -202,6 +227,11 @@ def sdmm_pass(pb: Problem, W, p: Params, st: State, record=False):
     info = Info()
     blocks = pb.blocks()
     for it in range(p.max_iter):
+        if p.block_fraction < 1.0:
+            sel = block_selected(p.block_seed, st.k, len(blocks), p.block_fraction)
+        else:
+            sel = np.ones(len(blocks), dtype=bool)
+        st.k += 1
         b = pb.psi.fwd(st.y_psi - st.z_psi) + pb.adj(st.y_phi - st.z_phi) + (st.y_pos - st.z_pos)
         x_prev = st.x
         x = cg(pb.Q, b, x_prev, iters=p.cg_iters, tol=p.cg_tol)
@@ -211,11 +241,13 @@ def sdmm_pass(pb: Problem, W, p: Params, st: State, record=False):
         st.z_psi = st.z_psi + s_psi - st.y_psi
         resid = np.empty(len(blocks))
         for i, (lo, hi) in enumerate(blocks):
+            resid[i] = np.linalg.norm(s_phi[lo:hi] - pb.y_hat[lo:hi])
+            if not sel[i]:          # a block left out of this iteration keeps its split variables
+                continue
             t = s_phi[lo:hi] + st.z_phi[lo:hi]
             yi = prox.ball(t, pb.y_hat[lo:hi], pb.eps_hat[i])
             st.z_phi[lo:hi] = st.z_phi[lo:hi] + s_phi[lo:hi] - yi
             st.y_phi[lo:hi] = yi
-            resid[i] = np.linalg.norm(s_phi[lo:hi] - pb.y_hat[lo:hi])
         st.y_pos = prox.positive(x + st.z_pos)
         st.z_pos = st.z_pos + x - st.y_pos
         st.x = x

@@ -83,12 +83,14 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
                                                      float2* __restrict__ out, const uint32_t* __restrict__ oidx,
                                                      const int4* __restrict__ items,
                                                      const int32_t* __restrict__ item_block, int log2K, int log2T,
-                                                     const float* __restrict__ scales, KBCoef kc) {
+                                                     const float* __restrict__ scales, KBCoef kc,
+                                                     const int32_t* __restrict__ bmask) {
   constexpr int P = T + J - 1;
   constexpr int LO = J / 2 - 1;
   __shared__ float2 patch[P * P];
   const int tid = threadIdx.x;
   const int itx = xcd_block_runs(blockIdx.x, gridDim.x, 16);
+  if (bmask && !bmask[item_block[itx]]) return;   // block not selected this iteration: its outputs are kept
   const int4 it = items[itx];
   const int nT = 1 << (log2K - log2T);
   const int kmask = (1 << log2K) - 1;
@@ -198,7 +200,8 @@ template <int J, int T>
 __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ vis,
                                                    const uint32_t* __restrict__ vidx, const int4* __restrict__ items,
                                                    const int32_t* __restrict__ item_block, float2* __restrict__ patches,
-                                                   int log2K, int log2T, const float* __restrict__ scales, KBCoef kc) {
+                                                   int log2K, int log2T, const float* __restrict__ scales, KBCoef kc,
+                                                   const int32_t* __restrict__ bmask) {
   constexpr int P = T + J - 1;
   constexpr int PP = P * P;
   constexpr int NQ = (J * J + 63) / 64;   // taps per lane
@@ -219,7 +222,8 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   for (int e = tid; e < 4 * PP; e += 256) (&pat[0][0])[e] = make_float2(0.f, 0.f);
   __syncthreads();
   const int itx = xcd_block_runs(blockIdx.x, gridDim.x, 16);
-  const int4 it = items[itx];
+  int4 it = items[itx];
+  if (bmask && !bmask[item_block[itx]]) it.z = 0;   // block not selected: a zero patch, no visibility read
   const int nT = 1 << (log2K - log2T);
   const int prob = it.x >> (2 * (log2K - log2T)), tloc = it.x & ((1 << (2 * (log2K - log2T))) - 1);
   const int a0 = (tloc / nT) * T, b0 = (tloc % nT) * T;
@@ -481,36 +485,39 @@ __global__ void scatter_kernel(const float2* __restrict__ src, const uint32_t* _
 }
 
 template <int J, int T>
-sh_status launch_degrid_T(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, const float* scales, hipStream_t st) {
+sh_status launch_degrid_T(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, const float* scales,
+                          const int32_t* bmask, hipStream_t st) {
   if (op->n_sparse)
     hipLaunchKernelGGL((degrid_kernel<J, T, false>), dim3((unsigned)op->n_sparse), dim3(256), 0, st, op->coord.ptr,
-                       grid, out, oidx, op->items.ptr, op->item_block.ptr, op->log2K, op->log2T, scales, op->kb);
+                       grid, out, oidx, op->items.ptr, op->item_block.ptr, op->log2K, op->log2T, scales, op->kb, bmask);
   if (op->n_items > op->n_sparse)
     hipLaunchKernelGGL((degrid_kernel<J, T, true>), dim3((unsigned)(op->n_items - op->n_sparse)), dim3(256), 0, st,
                        op->coord.ptr, grid, out, oidx, op->items.ptr + op->n_sparse,
                        op->item_block.ptr + op->n_sparse, op->log2K, op->log2T, scales,
-                       op->kb);
+                       op->kb, bmask);
   SH_LAUNCHED();
   return SH_OK;
 }
 
 template <int J>
-sh_status launch_degrid(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, const float* scales, hipStream_t st) {
+sh_status launch_degrid(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, const float* scales,
+                        const int32_t* bmask, hipStream_t st) {
   switch (op->T) {
-    case 8: return launch_degrid_T<J, 8>(op, grid, out, oidx, scales, st);
-    case 16: return launch_degrid_T<J, 16>(op, grid, out, oidx, scales, st);
-    case 32: return launch_degrid_T<J, 32>(op, grid, out, oidx, scales, st);
+    case 8: return launch_degrid_T<J, 8>(op, grid, out, oidx, scales, bmask, st);
+    case 16: return launch_degrid_T<J, 16>(op, grid, out, oidx, scales, bmask, st);
+    case 32: return launch_degrid_T<J, 32>(op, grid, out, oidx, scales, bmask, st);
   }
   sh::set_error("unsupported tile %d", op->T);
   return SH_EUNSUPPORTED;
 }
 
 template <int J, int T>
-sh_status launch_grid_T(sh_op op, const float2* vis, const uint32_t* vidx, const float* scales, hipStream_t st) {
+sh_status launch_grid_T(sh_op op, const float2* vis, const uint32_t* vidx, const float* scales, const int32_t* bmask,
+                        hipStream_t st) {
   {
     sh::ProfScope ps("grid", st);
     hipLaunchKernelGGL((grid_kernel<J, T>), dim3((unsigned)op->n_items), dim3(256), 0, st, op->coord.ptr, vis, vidx,
-                       op->items.ptr, op->item_block.ptr, op->patches.ptr, op->log2K, op->log2T, scales, op->kb);
+                       op->items.ptr, op->item_block.ptr, op->patches.ptr, op->log2K, op->log2T, scales, op->kb, bmask);
     SH_LAUNCHED();
   }
   sh::ProfScope ps("fold", st);
@@ -522,11 +529,12 @@ sh_status launch_grid_T(sh_op op, const float2* vis, const uint32_t* vidx, const
 }
 
 template <int J>
-sh_status launch_grid(sh_op op, const float2* vis, const uint32_t* vidx, const float* scales, hipStream_t st) {
+sh_status launch_grid(sh_op op, const float2* vis, const uint32_t* vidx, const float* scales, const int32_t* bmask,
+                      hipStream_t st) {
   switch (op->T) {
-    case 8: return launch_grid_T<J, 8>(op, vis, vidx, scales, st);
-    case 16: return launch_grid_T<J, 16>(op, vis, vidx, scales, st);
-    case 32: return launch_grid_T<J, 32>(op, vis, vidx, scales, st);
+    case 8: return launch_grid_T<J, 8>(op, vis, vidx, scales, bmask, st);
+    case 16: return launch_grid_T<J, 16>(op, vis, vidx, scales, bmask, st);
+    case 32: return launch_grid_T<J, 32>(op, vis, vidx, scales, bmask, st);
   }
   sh::set_error("unsupported tile %d", op->T);
   return SH_EUNSUPPORTED;
@@ -536,13 +544,14 @@ sh_status launch_grid(sh_op op, const float2* vis, const uint32_t* vidx, const f
 
 namespace sh {
 
-sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, const float* scales, hipStream_t st) {
+sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, const float* scales, hipStream_t st,
+                      const int32_t* bmask) {
   SH_TRY(fft_forward_2d(op, x, op->grid.ptr, st));
   ProfScope ps("degrid", st);
   const uint32_t* oi = user_order ? op->perm.ptr : nullptr;
   switch (op->J) {
 #define SH_J(JJ) \
-  case JJ: return launch_degrid<JJ>(op, op->grid.ptr, vis, oi, scales, st);
+  case JJ: return launch_degrid<JJ>(op, op->grid.ptr, vis, oi, scales, bmask, st);
     SH_J(2) SH_J(4) SH_J(6) SH_J(8) SH_J(10) SH_J(12) SH_J(14) SH_J(16)
 #undef SH_J
   }
@@ -550,12 +559,13 @@ sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, co
   return SH_EUNSUPPORTED;
 }
 
-sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, const float* scales, hipStream_t st) {
+sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, const float* scales, hipStream_t st,
+                      const int32_t* bmask) {
   const uint32_t* vi = user_order ? op->perm.ptr : nullptr;
   sh_status s = SH_EUNSUPPORTED;
   switch (op->J) {
 #define SH_J(JJ) \
-  case JJ: s = launch_grid<JJ>(op, vis, vi, scales, st); break;
+  case JJ: s = launch_grid<JJ>(op, vis, vi, scales, bmask, st); break;
     SH_J(2) SH_J(4) SH_J(6) SH_J(8) SH_J(10) SH_J(12) SH_J(14) SH_J(16)
 #undef SH_J
   }

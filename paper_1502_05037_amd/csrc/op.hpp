@@ -51,8 +51,12 @@ namespace sh {
 
 // Phi / Phi^dagger on internal-order (or user-order, via the permutation) visibilities of all P
 // problems; x holds P images.  Block b's visibilities are scaled by scales[b] (device R floats, NULL = 1).
-sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, const float* scales, hipStream_t st);
-sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, const float* scales, hipStream_t st);
+// With bmask (device R ints, NULL = all) only blocks b with bmask[b] != 0 take part: Phi leaves the other
+// blocks' visibilities as they were, Phi^dagger reads only the selected blocks' visibilities.
+sh_status phi_forward(sh_op op, const float* x, float2* vis, bool user_order, const float* scales, hipStream_t st,
+                      const int32_t* bmask = nullptr);
+sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, const float* scales, hipStream_t st,
+                      const int32_t* bmask = nullptr);
 
 // 2D FFT passes of the NUFFT over all P problems (fft.hip).
 sh_status fft_forward_2d(sh_op op, const float* x, float2* grid, hipStream_t st);   // S, Z, F

@@ -202,15 +202,21 @@ __global__ __launch_bounds__(256) void comb3_sq_partial(const float* __restrict_
 // per-chunk float64 partial sums of ||s_hat - y||^2 = ||v / cb + z||^2 and of ||s_hat||^2
 __global__ __launch_bounds__(256) void kkt_vis_partial(const float2* __restrict__ s_in, const float2* __restrict__ z,
                                                        const float2* __restrict__ v, const int4* __restrict__ chunks,
-                                                       const float* __restrict__ cblk, double* __restrict__ part) {
+                                                       const float* __restrict__ cblk, double* __restrict__ part,
+                                                       int sub_s) {
   __shared__ double sh[256];
   const int4 c = chunks[blockIdx.x];
   const float cb = cblk ? cblk[c.x] : 1.0f;
   double a = 0.0, b = 0.0;
   for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
     const float2 vv = v[i], zv = z[i], sv = s_in[i];
-    const double rr = double(vv.x) / cb + double(zv.x), ri = double(vv.y) / cb + double(zv.y);
     const double sr = double(cb) * double(sv.x), si = double(cb) * double(sv.y);
+    // s_hat - y: -(v / cb + z) when v = cb (y - z - s_hat); s_hat - v / cb - z when v = cb (y - z)
+    double rr = double(vv.x) / cb + double(zv.x), ri = double(vv.y) / cb + double(zv.y);
+    if (!sub_s) {
+      rr -= sr;
+      ri -= si;
+    }
     a += rr * rr + ri * ri;
     b += sr * sr + si * si;
   }
@@ -255,9 +261,11 @@ __global__ __launch_bounds__(256) void prox_pos_kernel(int64_t N, const float* _
 // weight, 1 without cblk)
 __global__ __launch_bounds__(256) void ball_norms(const float2* __restrict__ s_in, const float2* __restrict__ z,
                                                   const float2* __restrict__ yh, const int4* __restrict__ chunks,
-                                                  const float* __restrict__ cblk, double* __restrict__ part) {
+                                                  const float* __restrict__ cblk, double* __restrict__ part,
+                                                  const int32_t* __restrict__ bmask) {
   __shared__ double sh[256];
   const int4 c = chunks[blockIdx.x];
+  if (bmask && !bmask[c.x]) return;   // block not selected: its partials (and norms) are not used
   const float cb = cblk ? cblk[c.x] : 1.0f;
   double a = 0.0, b = 0.0;
   auto acc = [&](float2 si, float2 zv, float2 yv) {
@@ -336,6 +344,34 @@ __global__ __launch_bounds__(256) void ball_project(const float2* __restrict__ s
     for (int u = 0; u < 4; ++u) step(i + 256 * u, sv[u], zv[u], yv[u]);
   }
   for (; i < c.z; i += 256) step(i, s_in[i], z[i], yh[i]);
+}
+
+// The ball step of the selected blocks of a block-subset iteration (blocks with bmask[b] = 0 are left as
+// they are): s = cb s_in; y = yhat + (t - yhat) min(1, eps/rho) with t = s + z; z <- t - y;
+// v = cb (y - z) (no -s: the x-update of these iterations takes Phi_hat^T Phi_hat x from its own product)
+// and dv = v_new - v_old, the change the running image Phi_hat^T v needs.
+__global__ __launch_bounds__(256) void ball_project_delta(const float2* __restrict__ s_in, float2* __restrict__ z,
+                                                          const float2* __restrict__ yh, const int4* __restrict__ chunks,
+                                                          const double* __restrict__ eps, const double* __restrict__ rho,
+                                                          const float* __restrict__ cblk, const int32_t* __restrict__ bmask,
+                                                          float2* __restrict__ v, float2* __restrict__ dv) {
+  const int4 c = chunks[blockIdx.x];
+  if (!bmask[c.x]) return;
+  const double r = rho[c.x], e = eps[c.x];
+  const float cb = cblk ? cblk[c.x] : 1.0f;
+  const bool inside = r <= e;
+  const float ratio = inside ? 1.0f : float(e / r);
+  for (int i = c.y + threadIdx.x; i < c.z; i += 256) {
+    const float2 si = s_in[i], zv = z[i], yv = yh[i], vo = v[i];
+    const float tr = cb * si.x + zv.x, ti = cb * si.y + zv.y;
+    const float yr = inside ? tr : yv.x + (tr - yv.x) * ratio;
+    const float yi = inside ? ti : yv.y + (ti - yv.y) * ratio;
+    const float zr = tr - yr, zi = ti - yi;
+    z[i] = make_float2(zr, zi);
+    const float vr = cb * (yr - zr), vi = cb * (yi - zi);
+    v[i] = make_float2(vr, vi);
+    dv[i] = make_float2(vr - vo.x, vi - vo.y);
+  }
 }
 
 __global__ __launch_bounds__(256) void reweight_kernel(int64_t per, const float* __restrict__ c,
@@ -448,7 +484,8 @@ sh_status launch_prox_pos(int64_t N, const float* s, float* z, float* v, hipStre
 sh_status ball_kernels(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
                               double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st) {
   const unsigned nc = (unsigned)op->n_chunks;
-  hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr);
+  hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr,
+                     (const int32_t*)nullptr);
   hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
                      op->chunk_first_d.ptr, op->R, rho, resid);
   hipLaunchKernelGGL(ball_project, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, eps, rho, cblk, v,
@@ -460,7 +497,8 @@ sh_status ball_kernels(sh_op op, const float2* s, float2* z, const float2* yhat,
 sh_status ball_norms_only(sh_op op, const float2* s, const float2* z, const float2* yhat, const float* cblk, double* rho,
                           double* resid, hipStream_t st) {
   const unsigned nc = (unsigned)op->n_chunks;
-  hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr);
+  hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr,
+                     (const int32_t*)nullptr);
   hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
                      op->chunk_first_d.ptr, op->R, rho, resid);
   SH_LAUNCHED();
@@ -474,11 +512,26 @@ sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* y
 }
 
 sh_status launch_kkt_vis(sh_op op, const float2* s, const float2* z, const float2* v, const float* cblk, double* prim_b,
-                         double* scale_b, hipStream_t st) {
+                         double* scale_b, hipStream_t st, bool sub_s) {
   const unsigned nc = (unsigned)op->n_chunks;
-  hipLaunchKernelGGL(kkt_vis_partial, dim3(nc), dim3(256), 0, st, s, z, v, op->chunks.ptr, cblk, op->partials.ptr);
+  hipLaunchKernelGGL(kkt_vis_partial, dim3(nc), dim3(256), 0, st, s, z, v, op->chunks.ptr, cblk, op->partials.ptr,
+                     sub_s ? 1 : 0);
   hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
                      op->chunk_first_d.ptr, op->R, prim_b, scale_b);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status launch_prox_ball_subset(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps,
+                                 double* rho, double* resid, float2* v, float2* dv, const float* cblk,
+                                 const int32_t* bmask, hipStream_t st) {
+  ProfScope ps("prox", st);
+  const unsigned nc = (unsigned)op->n_chunks;
+  hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr, bmask);
+  hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
+                     op->chunk_first_d.ptr, op->R, rho, resid);
+  hipLaunchKernelGGL(ball_project_delta, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, eps, rho, cblk, bmask,
+                     v, dv);
   SH_LAUNCHED();
   return SH_OK;
 }

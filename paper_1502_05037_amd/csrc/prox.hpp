@@ -48,10 +48,16 @@ sh_status ball_kernels(sh_op op, const float2* s, float2* z, const float2* yhat,
                        double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st);
 sh_status launch_prox_ball(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps, double* rho,
                            double* resid, float2* v, bool sub_s, const float* cblk, hipStream_t st);
-// Primal residual of the data splits per block: prim_b[b] = ||v_b / c_b + z_b|| (= ||s_hat_b - y_b|| for the
-// solver's v = c (y - z - s_hat)) and scale_b[b] = ||c_b s_b|| (device R doubles each).
+// Primal residual of the data splits per block: prim_b[b] = ||s_hat_b - y_b||, from v = c (y - z - s_hat)
+// (sub_s) or v = c (y - z), and scale_b[b] = ||c_b s_b|| (device R doubles each).
 sh_status launch_kkt_vis(sh_op op, const float2* s, const float2* z, const float2* v, const float* cblk, double* prim_b,
-                         double* scale_b, hipStream_t st);
+                         double* scale_b, hipStream_t st, bool sub_s = true);
+// Block-subset ball step: only blocks with bmask[b] != 0 are projected; v = c_b (y - z) and dv = v_new - v_old
+// for those blocks (the other blocks' z, v and dv are left as they are).  resid/rho of unselected blocks are
+// stale.
+sh_status launch_prox_ball_subset(sh_op op, const float2* s, float2* z, const float2* yhat, const double* eps,
+                                 double* rho, double* resid, float2* v, float2* dv, const float* cblk,
+                                 const int32_t* bmask, hipStream_t st);
 sh_status launch_reweight(int64_t per, int P, const float* c, const double* delta_d, double delta, float* W,
                           hipStream_t st);
 

@@ -123,6 +123,48 @@ __global__ __launch_bounds__(256) void dual_ball_init(const float2* __restrict__
   }
 }
 
+// Block-subset iterations: block b takes part in iteration k when u(k R + b) < fraction, u(c) the c-th output
+// (from 0) of the SplitMix64 sequence seeded with `seed` (Steele, Lea & Flood 2014), taken to [0, 1) by its top
+// 53 bits.  One work-group; the iteration counter lives on the device and advances here, so that a captured
+// iteration draws a new subset at every replay.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(1024) void block_mask_kernel(uint64_t seed, unsigned long long* __restrict__ ctr, int R,
+                                                          double fraction, int32_t* __restrict__ mask) {
+  const unsigned long long k = *ctr;
+  for (int b = threadIdx.x; b < R; b += blockDim.x) {
+    const uint64_t z = splitmix64_at(seed, (uint64_t)k * (uint64_t)R + (uint64_t)b);
+    mask[b] = double(z >> 11) * 0x1.0p-53 < fraction ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *ctr = k + 1;
+}
+
+// c = a - b (images)
+__global__ void sub_kernel(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ c, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) c[i] = a[i] - b[i];
+}
+
+// a += b (images)
+__global__ void add_kernel(float* __restrict__ a, const float* __restrict__ b, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) a[i] += b[i];
+}
+
+// v = c_b^2 s per chunk (the data splits' v = c_b (y - z) at a warm start y = c_b Phi x0, z = 0)
+__global__ __launch_bounds__(256) void scale2_chunks(const float2* __restrict__ sv, float2* __restrict__ v,
+                                                     const int4* __restrict__ chunks, const float* __restrict__ cblk) {
+  const int4 c = chunks[blockIdx.x];
+  const float q = cblk[c.x] * cblk[c.x];
+  for (int i = c.y + threadIdx.x; i < c.z; i += 256) v[i] = make_float2(q * sv[i].x, q * sv[i].y);
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)sh::cdiv(n, 256); }
 
 struct Work {
@@ -132,6 +174,10 @@ struct Work {
   sh::DevBuf<double> sc, eps_hat, rho, resid, delta;
   sh::DevBuf<double> kkt;          // KKT reductions at exit: 8 per problem, then 2 per block
   sh::DevBuf<float> cblk, gamma;   // c_b per block, gamma per problem
+  // block-subset iterations: the selected blocks, the iteration counter, the running image Phi_hat^T v_phi
+  sh::DevBuf<int32_t> bmask;
+  sh::DevBuf<unsigned long long> ctr;
+  sh::DevBuf<float> bphi;
   sh::Reducer red;
   sh_toep_s toep;                  // Re(Phi_hat^H Phi_hat) as a convolution (option toeplitz)
 };
@@ -205,6 +251,8 @@ void sh_sdmm_default_params(sh_sdmm_params* p) {
   p->block_norm = 1;
   p->tol_dual = 1e-2;
   p->z_from_x0 = 0;
+  p->block_fraction = 1.0;
+  p->block_seed = 0;
 }
 
 sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream) {
@@ -226,6 +274,7 @@ struct sh_sdmm_s {
   int R = 0, kcg = 0;
   std::vector<double> nu, gamma, delta;   // per problem
   std::vector<double> lambda0;             // per problem: the data-dual scale of a dual warm start
+  bool stoch = false;                      // block-subset iterations (block_fraction < 1)
   std::vector<char> have_delta;            // per problem: delta holds a reweighting delta (given, or from a pass)
   std::vector<double> cb;          // c_b per block (host)
   std::vector<double> eh;          // eps_hat = c_b eps per block (host)
@@ -319,6 +368,12 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   SH_TRY(w.gamma.alloc(P));
   SH_TRY(w.kkt.alloc(8 * P + 2 * R));
   SH_TRY(w.red.init(P));
+  if (s->stoch) {
+    SH_TRY(w.bmask.alloc(R));
+    SH_TRY(w.ctr.alloc(1));
+    SH_TRY(w.bphi.alloc(N));
+    SH_HIP(hipMemsetAsync(w.ctr.ptr, 0, sizeof(unsigned long long), st));
+  }
   double* sc = w.sc.ptr;
   s->s_rs = sc;                        // rs_k of problem p at [k*P + p], k = 0..kcg
   s->s_pap = sc + (kcg + 1) * P;       // pAp_k at [k*P + p], k = 0..kcg-1
@@ -432,6 +487,16 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     std::fill(s->have_delta.begin(), s->have_delta.end(), 0);
     SH_TRY(sdmm_reweight(s, w.W.ptr, st));
   }
+  if (s->stoch) {   // block-subset iterations keep v_phi = c (y - z) and the image Phi_hat^T v_phi
+    if (x0) {
+      hipLaunchKernelGGL(scale2_chunks, dim3((unsigned)op->n_chunks), dim3(256), 0, st, w.sphi.ptr, w.vphi.ptr,
+                         op->chunks.ptr, w.cblk.ptr);
+      SH_LAUNCHED();
+      SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.bphi.ptr, false, nullptr, st));
+    } else {
+      SH_HIP(hipMemsetAsync(w.bphi.ptr, 0, N * sizeof(float), st));
+    }
+  }
   if (s->prm.z_from_x0) {   // duals from the optimality conditions at x0 (see sdmm_dual_warm_start)
     SH_TRY(sdmm_dual_warm_start(s, st));
   }
@@ -449,7 +514,16 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   double *s_rs = s->s_rs, *s_pap = s->s_pap, *s_misc = s->s_misc;
   // ---- x-update by CG from x_{n-1}
   SH_TRY(sh_psi_fwd(s->psi, w.vpsi.ptr, w.t1.ptr, st));
-  SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.t2.ptr, false, nullptr, st));   // vphi carries c_b
+  if (s->stoch) {
+    // this iteration's blocks; b - Q x_{n-1} from the running image Phi_hat^T v_phi and a Toeplitz product
+    hipLaunchKernelGGL(block_mask_kernel, dim3(1), dim3(1024), 0, st, (uint64_t)s->prm.block_seed, w.ctr.ptr, s->R,
+                       s->prm.block_fraction, w.bmask.ptr);
+    SH_TRY(sh::toeplitz_apply(op, w.toep.Ht.ptr, w.x.ptr, w.toep.tq.ptr, w.Ap.ptr, st));
+    hipLaunchKernelGGL(sub_kernel, dim3(nblk(N)), dim3(256), 0, st, w.bphi.ptr, w.Ap.ptr, w.t2.ptr, N);
+    SH_LAUNCHED();
+  } else {
+    SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.t2.ptr, false, nullptr, st));   // vphi carries c_b
+  }
   SH_TRY(w.red.cg_init(w.t1.ptr, w.t2.ptr, w.vpos.ptr, w.x.ptr, w.r.ptr, w.p.ptr, w.xprev.ptr, per, s_rs, st));
   for (int k = 0; k < s->kcg; ++k) {
     if (s->prm.toeplitz) {
@@ -472,9 +546,18 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   // ---- splits
   SH_TRY(sh_psi_adj(s->psi, w.x.ptr, w.spsi.ptr, st));
   SH_TRY(sh::launch_prox_l1(s->Dper, P, w.spsi.ptr, w.zpsi.ptr, s->Wp, w.gamma.ptr, 0.f, w.vpsi.ptr, st));
-  SH_TRY(sh::phi_forward(op, w.x.ptr, w.sphi.ptr, false, nullptr, st));
-  SH_TRY(sh::launch_prox_ball(op, w.sphi.ptr, w.zphi.ptr, w.yhat.ptr, w.eps_hat.ptr, w.rho.ptr, w.resid.ptr,
-                              w.vphi.ptr, true, w.cblk.ptr, st));
+  if (s->stoch) {   // the selected blocks only: their images, ball steps and change of Phi_hat^T v_phi
+    SH_TRY(sh::phi_forward(op, w.x.ptr, w.sphi.ptr, false, nullptr, st, w.bmask.ptr));
+    SH_TRY(sh::launch_prox_ball_subset(op, w.sphi.ptr, w.zphi.ptr, w.yhat.ptr, w.eps_hat.ptr, w.rho.ptr, w.resid.ptr,
+                                       w.vphi.ptr, w.vtmp.ptr, w.cblk.ptr, w.bmask.ptr, st));
+    SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.t2.ptr, false, nullptr, st, w.bmask.ptr));
+    hipLaunchKernelGGL(add_kernel, dim3(nblk(N)), dim3(256), 0, st, w.bphi.ptr, w.t2.ptr, N);
+    SH_LAUNCHED();
+  } else {
+    SH_TRY(sh::phi_forward(op, w.x.ptr, w.sphi.ptr, false, nullptr, st));
+    SH_TRY(sh::launch_prox_ball(op, w.sphi.ptr, w.zphi.ptr, w.yhat.ptr, w.eps_hat.ptr, w.rho.ptr, w.resid.ptr,
+                                w.vphi.ptr, true, w.cblk.ptr, st));
+  }
   SH_TRY(sh::launch_prox_pos(N, w.x.ptr, w.zpos.ptr, w.vpos.ptr, st));
   return SH_OK;
 }
@@ -538,6 +621,12 @@ sh_status sdmm_run(sh_sdmm s, int iters, hipStream_t st) {
 // per-block residuals (hat units).
 sh_status sdmm_read(sh_sdmm s, std::vector<double>& rel, std::vector<double>& hres, hipStream_t st) {
   const int P = s->P;
+  if (s->stoch) {   // the iterations refresh only their blocks' residuals: evaluate all of them at x_n
+    Work& w = s->w;
+    SH_TRY(sh::phi_forward(s->op, w.x.ptr, w.vtmp.ptr, false, nullptr, st));
+    SH_TRY(sh::ball_norms_only(s->op, w.vtmp.ptr, w.zphi.ptr, w.yhat.ptr, w.cblk.ptr, w.kkt.ptr + 8 * P, w.resid.ptr,
+                               st));
+  }
   std::vector<double> h(2 * P);
   SH_HIP(hipMemcpyAsync(h.data(), s->s_misc, 2 * P * sizeof(double), hipMemcpyDeviceToHost, st));
   hres.resize(s->R);
@@ -620,7 +709,12 @@ sh_status sdmm_kkt(sh_sdmm s, std::vector<double>& prim, std::vector<double>& du
   SH_TRY(w.red.dot(w.spsi.ptr, w.spsi.ptr, s->Dper, k + P, st));
   SH_TRY(w.red.comb3_sq(w.x.ptr, w.vpos.ptr, w.zpos.ptr, -1.f, -1.f, s->per, k + 2 * P, st));
   SH_TRY(w.red.dot(w.x.ptr, w.x.ptr, s->per, k + 3 * P, st));
-  SH_TRY(sh::launch_kkt_vis(op, w.sphi.ptr, w.zphi.ptr, w.vphi.ptr, w.cblk.ptr, k + 8 * P, k + 8 * P + R, st));
+  if (s->stoch) {   // split images of every block at x_n; v_phi = c (y - z)
+    SH_TRY(sh::phi_forward(op, w.x.ptr, w.vtmp.ptr, false, nullptr, st));
+    SH_TRY(sh::launch_kkt_vis(op, w.vtmp.ptr, w.zphi.ptr, w.vphi.ptr, w.cblk.ptr, k + 8 * P, k + 8 * P + R, st, false));
+  } else {
+    SH_TRY(sh::launch_kkt_vis(op, w.sphi.ptr, w.zphi.ptr, w.vphi.ptr, w.cblk.ptr, k + 8 * P, k + 8 * P + R, st));
+  }
   SH_TRY(sh_psi_fwd(s->psi, w.zpsi.ptr, w.t1.ptr, st));                              // Psi z_psi
   SH_TRY(sh::phi_adjoint(op, w.zphi.ptr, w.t2.ptr, false, w.cblk.ptr, st));          // Phi_hat^dagger z_phi
   SH_TRY(w.red.dot(w.t1.ptr, w.t1.ptr, s->per, k + 4 * P, st));
@@ -662,6 +756,9 @@ sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps,
   SH_REQUIRE(prm->graph == 0 || prm->graph == 1, "graph must be 0 or 1");
   SH_REQUIRE(prm->w_from_x0 == 0 || prm->w_from_x0 == 1, "w_from_x0 must be 0 or 1");
   SH_REQUIRE(prm->z_from_x0 == 0 || prm->z_from_x0 == 1, "z_from_x0 must be 0 or 1");
+  SH_REQUIRE(prm->block_fraction > 0 && prm->block_fraction <= 1, "block_fraction must be in (0, 1]");
+  SH_REQUIRE(prm->block_fraction == 1 || (prm->toeplitz == 1 && prm->z_from_x0 == 0),
+             "block-subset iterations (block_fraction < 1) need toeplitz = 1 and z_from_x0 = 0");
   SH_REQUIRE(prm->toeplitz == 0 || prm->toeplitz == 1, "toeplitz must be 0 or 1");
   SH_REQUIRE(prm->block_norm == 0 || prm->block_norm == 1, "block_norm must be 0 or 1");
   for (int i = 0; i < op->R; ++i) {
@@ -703,6 +800,7 @@ sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps
   s->D = s->Dper * s->P;
   s->R = op->R;
   s->kcg = params->cg_iters;
+  s->stoch = params->block_fraction < 1.0;
   sh_status st = sdmm_setup(s, y, eps, W, x0, (hipStream_t)stream);
   if (st == SH_OK) st = hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? SH_OK : SH_EDEVICE;
   if (st != SH_OK) {

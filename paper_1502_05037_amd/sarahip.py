@@ -43,7 +43,8 @@ class SdmmParams(C.Structure):
                 ("rw_beta", C.c_double), ("rw_delta0", C.c_double), ("max_iter", C.c_int32),
                 ("cg_iters", C.c_int32), ("passes", C.c_int32), ("check_every", C.c_int32), ("graph", C.c_int32),
                 ("w_from_x0", C.c_int32), ("toeplitz", C.c_int32), ("block_norm", C.c_int32),
-                ("tol_dual", C.c_double), ("z_from_x0", C.c_int32)]
+                ("tol_dual", C.c_double), ("z_from_x0", C.c_int32), ("block_fraction", C.c_double),
+                ("block_seed", C.c_uint64)]
 
 
 class SdmmInfo(C.Structure):

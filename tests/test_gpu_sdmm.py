@@ -197,6 +197,40 @@ def test_dual_warm_start_parity(sh):
     assert helpers.rel(x_plain_ref, x_ref) > 10 * err
 
 
+def test_block_subset_iterations_fixed_schedule_parity(sh):
+    """Block-subset SDMM (a random half of the six data blocks per iteration, drawn by the same counter-based
+    generator on both sides): two reweighted passes of a fixed schedule match the oracle's, and differ from
+    the full iteration."""
+    pb = helpers.build(2, 32, 2400, 6, 6, prob=3)
+    psi, nu, gamma, a = _oracle_setup(pb)
+    kw = dict(gamma=gamma, nu=nu, max_iter=40, cg_iters=2, passes=2)
+    p = sdmm.Params(block_weights=a, block_fraction=0.5, block_seed=11, **kw)
+    x_ref, *_ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, p)
+    x_full, *_ = sdmm.sara(pb.op, psi, pb.y, pb.offsets, pb.eps, sdmm.Params(block_weights=a, **kw))
+    x, info, resid, _ = _gpu_solve(sh, pb, _params(sh, block_fraction=0.5, block_seed=11, **kw))
+    err = helpers.rel(x, x_ref)
+    print(f"block-subset SDMM: image error vs oracle {err:.2e}; full iteration differs by {helpers.rel(x_full, x_ref):.2e}")
+    assert err <= 1e-4
+    assert helpers.rel(x_full, x_ref) > 100 * err
+
+
+def test_block_subset_run_to_tolerance_is_feasible(sh):
+    pb = helpers.build(4, 64, 4096, 8, 6, prob=4)
+    prm = _params(sh, max_iter=3000, tol_rel=1e-4, passes=2, block_fraction=0.25, block_seed=5)
+    x, info, resid, _ = _gpu_solve(sh, pb, prm)
+    print(f"block-subset run to tolerance: passes {info['pass_iters']}, dual residual {info['kkt_dual']:.2e}")
+    assert info["converged"] == 1
+    v = pb.op.fwd(x)
+    for i in range(len(pb.eps)):
+        lo, hi = pb.offsets[i], pb.offsets[i + 1]
+        r = np.linalg.norm(pb.y[lo:hi] - v[lo:hi])
+        assert r <= pb.eps[i] * (1 + 1e-4), (i, r, pb.eps[i])
+    np.testing.assert_allclose(resid, [np.linalg.norm(pb.y[pb.offsets[i]:pb.offsets[i + 1]] - v[pb.offsets[i]:pb.offsets[i + 1]])
+                                       for i in range(len(pb.eps))], rtol=1e-5)
+    with pytest.raises(sh.SarahipError):
+        _gpu_solve(sh, pb, _params(sh, max_iter=10, block_fraction=0.5, toeplitz=0))
+
+
 def test_run_to_tolerance_is_feasible(sh):
     pb = helpers.build(4, 64, 4096, 4, 6, prob=3)
     prm = _params(sh, max_iter=3000, tol_rel=1e-4, check_every=1, passes=2)

@@ -135,3 +135,23 @@ def test_daubechies_minimum_phase(p):
         for _ in range(p):
             qr, _ = np.polydiv(qr, [1.0, 1.0])
         assert np.min(np.abs(np.roots(qr))) > 1.1
+
+
+# ---------------------------------------------------------------------------
+# block-subset iterations
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_reference_outputs():
+    # the first outputs of SplitMix64 seeded with 0, as published with the generator
+    assert [sdmm.splitmix64(0, c) for c in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_block_subset_selection_frequency():
+    R, K, f = 16, 400, 0.3
+    sel = np.array([sdmm.block_selected(5, k, R, f) for k in range(K)])
+    n = sel.size
+    assert abs(sel.mean() - f) <= 4 * np.sqrt(f * (1 - f) / n)
+    # every block is drawn at the same rate, and iterations differ
+    assert np.all(np.abs(sel.mean(axis=0) - f) <= 5 * np.sqrt(f * (1 - f) / K))
+    assert len({tuple(r) for r in sel}) > K // 2
+    assert np.all(sdmm.block_selected(5, 3, R, 1.0)) and not np.any(sdmm.block_selected(5, 3, R, 0.0))

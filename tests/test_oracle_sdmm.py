@@ -277,3 +277,31 @@ def test_dirty_image_psf_peak_is_m_for_dft():
     op = measurement.DFT(synth.uv_gaussian(m, synth.rng(96, 8, synth.UV)), n)
     v = synth.complex_normal(m, synth.rng(96, 8, synth.NOISE))
     np.testing.assert_allclose(problem.dirty_image(op, v), op.adj(v) / m, rtol=1e-12)
+
+
+def test_block_subset_sdmm_full_fraction_is_plain_sdmm():
+    op, psi, y, off, eps = _tiny_problem(R=3, seed=7)
+    nu = measurement.op_norm(op, np.ones((psi.n, psi.n)))
+    gamma = sdmm.default_gamma(op, psi, y, nu)
+    a = sdmm.sara(op, psi, y, off, eps, sdmm.Params(gamma=gamma, nu=nu, max_iter=30, cg_iters=2))[0]
+    b = sdmm.sara(op, psi, y, off, eps, sdmm.Params(gamma=gamma, nu=nu, max_iter=30, cg_iters=2, block_fraction=1.0,
+                                                   block_seed=9))[0]
+    np.testing.assert_array_equal(a, b)
+
+
+def test_block_subset_sdmm_reaches_the_same_minimiser():
+    """Updating a random half of the data blocks per iteration leaves the fixed point of SDMM unchanged: the
+    block-subset run reaches the minimiser of (3) that the full iteration reaches (same objective and image,
+    every constraint met)."""
+    op, psi, y, off, eps = _tiny_problem(R=4, seed=8, m=160)
+    nu = measurement.op_norm(op, np.ones((psi.n, psi.n)), max_iter=5000, tol=0.0)
+    gamma = sdmm.default_gamma(op, psi, y, nu, factor=1e-3)
+    full = sdmm.Params(gamma=gamma, nu=nu, max_iter=20000, tol_rel=1e-11, eps_slack=1e-9)
+    half = sdmm.Params(gamma=gamma, nu=nu, max_iter=40000, tol_rel=1e-11, eps_slack=1e-9, block_fraction=0.5,
+                       block_seed=3)
+    xf, _, inf_f, _ = sdmm.sara(op, psi, y, off, eps, full)
+    xh, _, inf_h, _ = sdmm.sara(op, psi, y, off, eps, half)
+    assert inf_h[0].converged
+    assert inf_h[0].objective == pytest.approx(inf_f[0].objective, rel=1e-5)
+    assert np.linalg.norm(xh - xf) / np.linalg.norm(xf) <= 1e-3
+    assert np.all(inf_h[0].block_resid <= eps * (1 + 1e-6))
