@@ -312,3 +312,119 @@ def kkt(pb: Problem, st: State, W, gamma: float):
     dual = np.linalg.norm(sum(parts))
     scale_d = max(np.linalg.norm(q) for q in parts)
     return prim / scale_p, dual / scale_d if scale_d > 0 else 0.0
+
+
+# ---------------------------------------------------------------------------------------------------
+# Synthesis prior (the SDMM paragraph: the same solver handles other sparsity priors)
+# ---------------------------------------------------------------------------------------------------
+#
+# min ||W alpha||_1 over alpha in R^D subject to ||y_i - Phi_i Psi alpha||_2 <= eps_i for every block and
+# Psi alpha >= 0: the image is synthesised from its coefficients, x = Psi alpha.  As a sum of functions of
+# linear maps of alpha, f_0(alpha) + sum_i iota_{B_i}(Phi_hat_i Psi alpha) + iota_+(Psi alpha), with
+# L = {I, Phi_hat_1 Psi .. Phi_hat_R Psi, Psi} and Q = I + Psi^dagger (I + Re(Phi_hat^H Phi_hat)) Psi (spectrum
+# in [1, 3]: Psi Psi^dagger = I, so Psi^dagger A Psi has the eigenvalues of A restricted to range(Psi^dagger)
+# and 0).  The splits, proximal maps and dual updates are those of the analysis form.
+
+
+@dataclass
+class SynthState:
+    alpha: np.ndarray
+    y_l1: np.ndarray
+    z_l1: np.ndarray
+    y_phi: np.ndarray
+    z_phi: np.ndarray
+    y_pos: np.ndarray
+    z_pos: np.ndarray
+
+    def copy(self) -> "SynthState":
+        return SynthState(*(np.array(getattr(self, f), copy=True) for f in self.__dataclass_fields__))
+
+
+def synth_init_state(pb: Problem, x0=None) -> SynthState:
+    """Zero start, or from an image x0: alpha = Psi^dagger x0 (so Psi alpha = x0), y_j = L_j alpha, z = 0."""
+    D = pb.psi.adj(np.zeros((pb.n, pb.n))).shape
+    M = len(pb.y_hat)
+    if x0 is None:
+        z = np.zeros(D)
+        return SynthState(z, z.copy(), z.copy(), np.zeros(M, complex), np.zeros(M, complex),
+                          np.zeros((pb.n, pb.n)), np.zeros((pb.n, pb.n)))
+    a = pb.psi.adj(np.asarray(x0, dtype=np.float64))
+    x = pb.psi.fwd(a)
+    return SynthState(a, a.copy(), np.zeros(D), pb.fwd(x), np.zeros(M, complex), x, np.zeros((pb.n, pb.n)))
+
+
+def synth_pass(pb: Problem, W, p: Params, st: SynthState, record=False):
+    """One weighted-l1 solve of the synthesis problem by SDMM, continuing from `st`."""
+    st = st.copy()
+    psi = pb.psi
+    W = np.ones_like(st.alpha) if W is None else np.asarray(W, dtype=np.float64)
+    info = Info()
+    blocks = pb.blocks()
+
+    def Q(a):
+        xa = psi.fwd(a)
+        return a + psi.adj(xa + pb.adj(pb.fwd(xa)))
+
+    x_prev = psi.fwd(st.alpha)
+    for it in range(p.max_iter):
+        b = (st.y_l1 - st.z_l1) + psi.adj(pb.adj(st.y_phi - st.z_phi) + (st.y_pos - st.z_pos))
+        alpha = cg(Q, b, st.alpha, iters=p.cg_iters, tol=p.cg_tol)
+        x = psi.fwd(alpha)
+        s_phi = pb.fwd(x)
+        st.y_l1 = prox.soft(alpha + st.z_l1, p.gamma * W)
+        st.z_l1 = st.z_l1 + alpha - st.y_l1
+        resid = np.empty(len(blocks))
+        for i, (lo, hi) in enumerate(blocks):
+            resid[i] = np.linalg.norm(s_phi[lo:hi] - pb.y_hat[lo:hi])
+            t = s_phi[lo:hi] + st.z_phi[lo:hi]
+            yi = prox.ball(t, pb.y_hat[lo:hi], pb.eps_hat[i])
+            st.z_phi[lo:hi] = st.z_phi[lo:hi] + s_phi[lo:hi] - yi
+            st.y_phi[lo:hi] = yi
+        st.y_pos = prox.positive(x + st.z_pos)
+        st.z_pos = st.z_pos + x - st.y_pos
+        st.alpha = alpha
+        dx = float(np.linalg.norm(x - x_prev))
+        xn = float(np.linalg.norm(x))
+        rel = dx / xn if xn > 0 else (0.0 if dx == 0 else np.inf)
+        x_prev = x
+        info.iters = it + 1
+        info.rel_change = rel
+        info.block_resid = resid / pb.c
+        feasible = bool(np.all(resid <= pb.eps_hat * (1.0 + p.eps_slack)))
+        if p.tol_rel > 0 and (it + 1) % p.check_every == 0 and rel <= p.tol_rel and feasible:
+            if p.tol_dual <= 0 or synth_kkt(pb, st, W, p.gamma)[1] <= p.tol_dual:
+                info.converged = True
+                break
+    info.objective = float(np.sum(np.abs(W * st.alpha)))
+    return st, info
+
+
+def sara_synthesis(op, psi, y, offsets, eps, p: Params, x0=None, W0=None, delta0=None):
+    """The SARA loop on the synthesis prior: passes of synth_pass, reweighting w = delta / (delta + |alpha|)
+    between them (delta_1 = std(alpha) after pass 1, delta_{t+1} = beta delta_t).  Returns (x = Psi alpha,
+    W_last, infos, state)."""
+    pb = Problem(op, psi, y, offsets, eps, p.nu, p.block_weights)
+    st = synth_init_state(pb, x0)
+    W, delta, infos = W0, delta0, []
+    for t in range(p.passes):
+        st, info = synth_pass(pb, W, p, st)
+        infos.append(info)
+        if t < p.passes - 1:
+            delta = float(np.std(st.alpha)) if delta is None else p.rw_beta * delta
+            W = reweight(st.alpha, delta)
+    return psi.fwd(st.alpha), W, infos, st
+
+
+def synth_kkt(pb: Problem, st: SynthState, W, gamma: float):
+    """Relative KKT residuals of the synthesis state: primal ||s_j - y_j|| over the splits, dual
+    ||z_l1 + Psi^dagger (Phi_hat^dagger z_phi + z_+)|| against the largest of its terms."""
+    psi = pb.psi
+    x = psi.fwd(st.alpha)
+    s_phi = pb.fwd(x)
+    prim = np.sqrt(np.sum((st.alpha - st.y_l1) ** 2) + np.sum(np.abs(s_phi - st.y_phi) ** 2)
+                   + np.sum((x - st.y_pos) ** 2))
+    scale_p = np.sqrt(np.sum(st.alpha ** 2) + np.sum(np.abs(s_phi) ** 2) + np.sum(x ** 2))
+    parts = [st.z_l1, psi.adj(pb.adj(st.z_phi)), psi.adj(st.z_pos)]
+    dual = np.linalg.norm(sum(parts))
+    scale_d = max(np.linalg.norm(q) for q in parts)
+    return prim / scale_p, dual / scale_d if scale_d > 0 else 0.0

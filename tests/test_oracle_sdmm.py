@@ -305,3 +305,62 @@ def test_block_subset_sdmm_reaches_the_same_minimiser():
     assert inf_h[0].objective == pytest.approx(inf_f[0].objective, rel=1e-5)
     assert np.linalg.norm(xh - xf) / np.linalg.norm(xf) <= 1e-3
     assert np.all(inf_h[0].block_resid <= eps * (1 + 1e-6))
+
+
+# ---------------------------------------------------------------------------------------------------
+# synthesis prior
+# ---------------------------------------------------------------------------------------------------
+
+def test_synthesis_with_dirac_dictionary_is_the_analysis_problem():
+    """With Psi = I (Dirac only) the synthesis and analysis problems and their SDMM iterations coincide."""
+    op, psi, y, off, eps = _tiny_problem(R=2, seed=9, mask=0b1)
+    nu = measurement.op_norm(op, np.ones((psi.n, psi.n)))
+    gamma = sdmm.default_gamma(op, psi, y, nu)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=60, passes=2)
+    xa, Wa, ia, _ = sdmm.sara(op, psi, y, off, eps, p)
+    xs, Ws, is_, _ = sdmm.sara_synthesis(op, psi, y, off, eps, p)
+    np.testing.assert_allclose(xs, xa, rtol=0, atol=1e-10 * np.abs(xa).max())
+    np.testing.assert_allclose(Ws, Wa, rtol=1e-9)
+
+
+def _brute_force_synthesis(op, psi, y, off, eps):
+    """min sum t over (alpha, t): -t <= alpha <= t, Psi alpha >= 0, ||y_i - Phi_i Psi alpha||^2 <= eps_i^2 (SLSQP)."""
+    n = psi.n
+    N, D = n * n, psi.D
+    S = np.stack([psi.fwd(e.reshape(psi.q, n, n)).ravel() for e in np.eye(D)], axis=1)   # Psi, N x D
+    F = np.stack([op.fwd(e.reshape(n, n)) for e in np.eye(N)], axis=1) @ S               # Phi Psi, M x D
+    I_D = np.eye(D)
+    cons = [{"type": "ineq", "fun": lambda z: np.concatenate([z[D:] - z[:D], z[D:] + z[:D]]),
+             "jac": lambda z: np.block([[-I_D, I_D], [I_D, I_D]])},
+            {"type": "ineq", "fun": lambda z: S @ z[:D], "jac": lambda z: np.hstack([S, np.zeros((N, D))])}]
+    for i in range(len(eps)):
+        Fi, yi = F[off[i]:off[i + 1]], y[off[i]:off[i + 1]]
+        cons.append({"type": "ineq",
+                     "fun": lambda z, Fi=Fi, yi=yi, e=eps[i]: np.array([e ** 2 - np.sum(np.abs(yi - Fi @ z[:D]) ** 2)]),
+                     "jac": lambda z, Fi=Fi, yi=yi: np.concatenate([2 * (Fi.conj().T @ (yi - Fi @ z[:D])).real,
+                                                                    np.zeros(D)])[None, :]})
+    c = np.concatenate([np.zeros(D), np.ones(D)])
+    a0 = psi.adj(np.full((n, n), 0.1)).ravel()
+    z0 = np.concatenate([a0, np.abs(a0) + 1.0])
+    res = scipy.optimize.minimize(lambda z: c @ z, z0, jac=lambda z: c, method="SLSQP", constraints=cons,
+                                  options={"maxiter": 3000, "ftol": 1e-14})
+    return (S @ res.x[:D]).reshape(n, n), float(np.sum(np.abs(res.x[:D])))
+
+
+def test_synthesis_sdmm_matches_brute_force():
+    # Dirac + db2 + db4 at two levels on an 8 x 8 image: 192 coefficients
+    op, psi, y, off, eps = _tiny_problem(R=2, m=96, levels=2, mask=0b10101, seed=10)
+    nu = measurement.op_norm(op, np.ones((psi.n, psi.n)), max_iter=5000, tol=0.0)
+    # the minimiser does not depend on gamma; this step reaches it within the budget on this problem
+    gamma = sdmm.default_gamma(op, psi, y, nu, factor=1e-2)
+    p = sdmm.Params(gamma=gamma, nu=nu, max_iter=20000, tol_rel=1e-11, eps_slack=1e-9)
+    x, _, infos, st = sdmm.sara_synthesis(op, psi, y, off, eps, p)
+    assert infos[0].converged
+    x_bf, obj_bf = _brute_force_synthesis(op, psi, y, off, eps)
+    assert infos[0].objective == pytest.approx(obj_bf, rel=2e-5)
+    assert np.all(infos[0].block_resid <= eps * (1 + 1e-6))
+    assert np.min(x) >= -1e-6 * np.max(x)
+    assert np.linalg.norm(x - x_bf) / np.linalg.norm(x_bf) <= 1e-3
+    pb = sdmm.Problem(op, psi, y, off, eps, nu)
+    prim, dual = sdmm.synth_kkt(pb, st, None, gamma)
+    assert prim <= 1e-8 and dual <= 1e-5
