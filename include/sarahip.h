@@ -276,11 +276,18 @@ typedef struct {
                           Toeplitz product).  The stopping test evaluates every block's residual at x_n.
                           Needs toeplitz = 1 and z_from_x0 = 0.  1 = every block every iteration */
   uint64_t block_seed;
+  int32_t synthesis;   /* 1: the synthesis prior (SDMM paragraph: the solver handles various sparsity priors):
+                          min ||W alpha||_1 over coefficients alpha (D = q n^2) subject to the same blocked
+                          constraints on x = Psi alpha and x >= 0; the image returned is Psi alpha and the
+                          weights follow alpha.  SDMM splits L = {I, Phi_hat Psi, Psi}, CG on alpha with
+                          Q = I + Psi^dagger (I + Re(Phi_hat^H Phi_hat)) Psi through the Toeplitz product.
+                          A warm start x0 starts from alpha = Psi^dagger x0.  Needs toeplitz = 1,
+                          z_from_x0 = 0 and block_fraction = 1.  0: the analysis prior ||W Psi^dagger x||_1 */
 } sh_sdmm_params;
 
 /* Defaults: gamma -1, nu -1, tol_rel 0, eps_slack 1e-4, rw_beta 0.5, rw_delta0 0,
  * max_iter 300, cg_iters 2, passes 1, check_every 10, graph 1, w_from_x0 0, toeplitz 1, block_norm 1,
- * tol_dual 1e-2, z_from_x0 0, block_fraction 1, block_seed 0.  With a batched plan, a given
+ * tol_dual 1e-2, z_from_x0 0, block_fraction 1, block_seed 0, synthesis 0.  With a batched plan, a given
  * gamma or nu applies to every problem; otherwise each problem gets its own. */
 void sh_sdmm_default_params(sh_sdmm_params* p);
 
@@ -292,7 +299,7 @@ typedef struct {
   int32_t converged;     /* last pass met the stopping test (not an error when 0) */
   int32_t iters_last;    /* iterations of the last pass */
   double rel_change;     /* ||x_n - x_{n-1}|| / ||x_n|| at exit */
-  double objective;      /* ||W Psi^dagger x||_1 with the last pass's weights */
+  double objective;      /* ||W Psi^dagger x||_1 (synthesis: ||W alpha||_1) with the last pass's weights */
   double gamma;          /* step actually used */
   double nu;             /* normalisation actually used (nu_p of block_norm) */
   double delta;          /* reweighting delta of W_out */

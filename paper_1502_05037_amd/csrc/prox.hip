@@ -36,16 +36,17 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (r)
 
 // Conjugate-gradient steps fused with the dot product that follows them (per segment p = problem):
-// r = a + b + c - 2x, p = r, xprev = x, partial r.r
+// r = a + b + c - xc x (c may be NULL), p = r, xprev = x, partial r.r
 __global__ __launch_bounds__(256) void cg_init_rr(const float* __restrict__ a, const float* __restrict__ b,
                                                   const float* __restrict__ c, const float* __restrict__ x,
                                                   float* __restrict__ r, float* __restrict__ pv,
-                                                  float* __restrict__ xprev, int64_t per, double* __restrict__ part) {
+                                                  float* __restrict__ xprev, int64_t per, double* __restrict__ part,
+                                                  float xc) {
   __shared__ double sh[256];
   double acc = 0.0;
   SEGMENT_LOOP(i) {
     const float xv = x[i];
-    const float rv = a[i] + b[i] + c[i] - 2.f * xv;
+    const float rv = a[i] + b[i] + (c ? c[i] : 0.f) - xc * xv;
     r[i] = rv;
     pv[i] = rv;
     xprev[i] = xv;
@@ -55,14 +56,14 @@ __global__ __launch_bounds__(256) void cg_init_rr(const float* __restrict__ a, c
   PART_OUT(rs);
 }
 
-// Ap = 2p + Ap, partial p.Ap
+// Ap = pc p + Ap, partial p.Ap
 __global__ __launch_bounds__(256) void cg_ap_dot(const float* __restrict__ pv, float* __restrict__ Ap, int64_t per,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part, float pc) {
   __shared__ double sh[256];
   double acc = 0.0;
   SEGMENT_LOOP(i) {
     const float pi = pv[i];
-    const float a = 2.f * pi + Ap[i];
+    const float a = pc * pi + Ap[i];
     Ap[i] = a;
     acc += double(pi) * double(a);
   }
@@ -397,15 +398,15 @@ sh_status Reducer::init(int segments) {
 }
 
 sh_status Reducer::cg_init(const float* a, const float* b, const float* c, const float* x, float* r, float* p,
-                           float* xprev, int64_t per, double* rs_out, hipStream_t st) {
-  hipLaunchKernelGGL(cg_init_rr, dim3(rb, P), dim3(256), 0, st, a, b, c, x, r, p, xprev, per, part.ptr);
+                           float* xprev, int64_t per, double* rs_out, hipStream_t st, float xc) {
+  hipLaunchKernelGGL(cg_init_rr, dim3(rb, P), dim3(256), 0, st, a, b, c, x, r, p, xprev, per, part.ptr, xc);
   hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, rs_out);
   SH_LAUNCHED();
   return SH_OK;
 }
 
-sh_status Reducer::cg_ap(const float* p, float* Ap, int64_t per, double* pap_out, hipStream_t st) {
-  hipLaunchKernelGGL(cg_ap_dot, dim3(rb, P), dim3(256), 0, st, p, Ap, per, part.ptr);
+sh_status Reducer::cg_ap(const float* p, float* Ap, int64_t per, double* pap_out, hipStream_t st, float pc) {
+  hipLaunchKernelGGL(cg_ap_dot, dim3(rb, P), dim3(256), 0, st, p, Ap, per, part.ptr, pc);
   hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, pap_out);
   SH_LAUNCHED();
   return SH_OK;

@@ -21,13 +21,13 @@ struct Reducer {
   sh_status comb3_sq(const float* a, const float* b, const float* c, float fb, float fc, int64_t per, double* out,
                      hipStream_t st);
   // Conjugate-gradient steps fused with the reduction that follows them (same trees as dot):
-  //   cg_init:   r = a + b + c - 2x, p = r, xprev = x;            rs_out = r.r
-  //   cg_ap:     Ap = 2p + Ap;                                   pap_out = p.Ap
+  //   cg_init:   r = a + b + c - xc x (c may be NULL), p = r, xprev = x;  rs_out = r.r
+  //   cg_ap:     Ap = pc p + Ap;                                 pap_out = p.Ap
   //   cg_update: x += alpha p, r -= alpha Ap, alpha = rs / pap;  rs_out = r.r (NULL: not reduced)
   //   change:    out2[0..P) = ||x - xprev||^2, out2[P..2P) = ||x||^2
   sh_status cg_init(const float* a, const float* b, const float* c, const float* x, float* r, float* p, float* xprev,
-                    int64_t per, double* rs_out, hipStream_t st);
-  sh_status cg_ap(const float* p, float* Ap, int64_t per, double* pap_out, hipStream_t st);
+                    int64_t per, double* rs_out, hipStream_t st, float xc = 2.f);
+  sh_status cg_ap(const float* p, float* Ap, int64_t per, double* pap_out, hipStream_t st, float pc = 2.f);
   sh_status cg_update(float* x, float* r, const float* p, const float* Ap, int64_t per, const double* rs,
                       const double* pap, double* rs_out, hipStream_t st);
   sh_status change(const float* x, const float* xprev, int64_t per, double* out2, hipStream_t st);

@@ -145,6 +145,18 @@ __global__ __launch_bounds__(1024) void block_mask_kernel(uint64_t seed, unsigne
   if (threadIdx.x == 0) *ctr = k + 1;
 }
 
+// out = a + b - c (images)
+__global__ void comb_kernel(float* __restrict__ out, const float* __restrict__ a, const float* __restrict__ b,
+                            const float* __restrict__ c, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) out[i] = a[i] + b[i] - c[i];
+}
+
+__global__ void copy_kernel(float* __restrict__ dst, const float* __restrict__ src, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) dst[i] = src[i];
+}
+
 // c = a - b (images)
 __global__ void sub_kernel(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ c, int64_t N) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -178,6 +190,9 @@ struct Work {
   sh::DevBuf<int32_t> bmask;
   sh::DevBuf<unsigned long long> ctr;
   sh::DevBuf<float> bphi;
+  // synthesis prior: the coefficients alpha (x = Psi alpha), the CG vectors in coefficient space, and the
+  // coefficients taken with each problem's returned image
+  sh::DevBuf<float> alpha, ar, ap, aAp, alpha_out;
   sh::Reducer red;
   sh_toep_s toep;                  // Re(Phi_hat^H Phi_hat) as a convolution (option toeplitz)
 };
@@ -253,6 +268,7 @@ void sh_sdmm_default_params(sh_sdmm_params* p) {
   p->z_from_x0 = 0;
   p->block_fraction = 1.0;
   p->block_seed = 0;
+  p->synthesis = 0;
 }
 
 sh_status sh_op_norm(sh_op op, const float* x0, int32_t iters, double tol, double* nu_out, void* stream) {
@@ -275,6 +291,7 @@ struct sh_sdmm_s {
   std::vector<double> nu, gamma, delta;   // per problem
   std::vector<double> lambda0;             // per problem: the data-dual scale of a dual warm start
   bool stoch = false;                      // block-subset iterations (block_fraction < 1)
+  bool synth = false;                      // synthesis prior: the unknowns are the coefficients alpha
   std::vector<char> have_delta;            // per problem: delta holds a reweighting delta (given, or from a pass)
   std::vector<double> cb;          // c_b per block (host)
   std::vector<double> eh;          // eps_hat = c_b eps per block (host)
@@ -302,7 +319,8 @@ namespace {
 // s_misc layout: [0, P) dx^2, [P, 2P) x^2, [2P, 3P) scratch, [3P, 4P) objective, [4P, 5P) scratch
 enum { MISC_DX = 0, MISC_X = 1, MISC_TMP = 2, MISC_OBJ = 3, MISC_TMP2 = 4, MISC_N = 5 };
 
-sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st, const std::vector<char>* which = nullptr);
+sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st, const std::vector<char>* which = nullptr,
+                        const float* coeffs = nullptr);
 
 // Duals of a warm start from x0, taken from the optimality conditions of the weighted problem at x0 (the
 // primal splits already hold y_j = L_j x0):
@@ -368,6 +386,8 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   SH_TRY(w.gamma.alloc(P));
   SH_TRY(w.kkt.alloc(8 * P + 2 * R));
   SH_TRY(w.red.init(P));
+  if (s->synth)
+    for (auto* b : {&w.alpha, &w.ar, &w.ap, &w.aAp, &w.alpha_out}) SH_TRY(b->alloc(D));
   if (s->stoch) {
     SH_TRY(w.bmask.alloc(R));
     SH_TRY(w.ctr.alloc(1));
@@ -481,11 +501,21 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     SH_HIP(hipMemsetAsync(w.sphi.ptr, 0, M * sizeof(float2), st));
   }
   SH_HIP(hipMemsetAsync(w.xprev.ptr, 0, N * sizeof(float), st));
+  if (s->synth) {   // unknowns alpha: zero, or alpha = Psi^dagger x0 (in vpsi) with x = Psi alpha, y_l1 = alpha
+    if (x0) {
+      SH_HIP(hipMemcpyAsync(w.alpha.ptr, w.vpsi.ptr, D * sizeof(float), hipMemcpyDeviceToDevice, st));
+      SH_TRY(sh_psi_fwd(s->psi, w.alpha.ptr, w.x.ptr, st));
+      SH_HIP(hipMemcpyAsync(w.vpos.ptr, w.x.ptr, N * sizeof(float), hipMemcpyDeviceToDevice, st));
+      SH_TRY(sh::phi_forward(op, w.x.ptr, w.sphi.ptr, false, nullptr, st));
+    } else {
+      SH_HIP(hipMemsetAsync(w.alpha.ptr, 0, D * sizeof(float), st));
+    }
+  }
   if (s->prm.w_from_x0) {   // weights of the first pass from Psi^dagger x0 (delta_1 = std per problem)
-    SH_TRY(sh_psi_adj(s->psi, x0, w.spsi.ptr, st));
+    SH_TRY(sh_psi_adj(s->psi, x0, w.spsi.ptr, st));   // (= alpha_0 of the synthesis form)
     std::fill(s->delta.begin(), s->delta.end(), 0.0);
     std::fill(s->have_delta.begin(), s->have_delta.end(), 0);
-    SH_TRY(sdmm_reweight(s, w.W.ptr, st));
+    SH_TRY(sdmm_reweight(s, w.W.ptr, st, nullptr, w.spsi.ptr));
   }
   if (s->stoch) {   // block-subset iterations keep v_phi = c (y - z) and the image Phi_hat^T v_phi
     if (x0) {
@@ -503,6 +533,50 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
   return SH_OK;
 }
 
+// One SDMM iteration on the synthesis prior: min ||W alpha||_1 subject to the balls on Phi_hat Psi alpha and
+// Psi alpha >= 0, L = {I, Phi_hat Psi, Psi}, Q = I + Psi^dagger (I + Re(Phi_hat^H Phi_hat)) Psi.  CG runs on the
+// coefficients from alpha_{n-1}; its initial residual
+//   b - Q alpha_{n-1} = v_l1 + Psi^dagger (Phi^dagger v_phi + v_+ - x_{n-1}) - alpha_{n-1}
+// reuses s_phi = Phi x_{n-1} through v_phi (as in the analysis form), and every product Q p is
+// p + Psi^dagger ((I + T) Psi p) with the Toeplitz product T.  Then x_n = Psi alpha_n feeds the data and
+// positivity splits, alpha_n the l1 split.
+sh_status sdmm_step_synthesis(sh_sdmm s, hipStream_t st) {
+  sh_op op = s->op;
+  Work& w = s->w;
+  const int P = s->P;
+  const int64_t N = s->N, per = s->per, Dp = s->Dper;
+  const dim3 gD(nblk(Dp), P);
+  double *s_rs = s->s_rs, *s_pap = s->s_pap, *s_misc = s->s_misc;
+  SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.t2.ptr, false, nullptr, st));   // vphi carries c_b and -s_hat
+  hipLaunchKernelGGL(comb_kernel, dim3(nblk(N)), dim3(256), 0, st, w.t1.ptr, w.t2.ptr, w.vpos.ptr, w.x.ptr, N);
+  hipLaunchKernelGGL(copy_kernel, dim3(nblk(N)), dim3(256), 0, st, w.xprev.ptr, w.x.ptr, N);
+  SH_LAUNCHED();
+  SH_TRY(sh_psi_adj(s->psi, w.t1.ptr, w.aAp.ptr, st));
+  // (spsi, unused by this form's iteration, receives alpha_{n-1})
+  SH_TRY(w.red.cg_init(w.vpsi.ptr, w.aAp.ptr, nullptr, w.alpha.ptr, w.ar.ptr, w.ap.ptr, w.spsi.ptr, Dp, s_rs, st, 1.f));
+  for (int k = 0; k < s->kcg; ++k) {
+    SH_TRY(sh_psi_fwd(s->psi, w.ap.ptr, w.t1.ptr, st));                                       // Psi p
+    SH_TRY(sh::toeplitz_apply(op, w.toep.Ht.ptr, w.t1.ptr, w.toep.tq.ptr, w.t2.ptr, st));     // T Psi p
+    hipLaunchKernelGGL(add_kernel, dim3(nblk(N)), dim3(256), 0, st, w.t1.ptr, w.t2.ptr, N);
+    SH_TRY(sh_psi_adj(s->psi, w.t1.ptr, w.aAp.ptr, st));
+    SH_TRY(w.red.cg_ap(w.ap.ptr, w.aAp.ptr, Dp, s_pap + k * P, st, 1.f));                    // p + Psi^T (I + T) Psi p
+    const bool more = k + 1 < s->kcg;
+    SH_TRY(w.red.cg_update(w.alpha.ptr, w.ar.ptr, w.ap.ptr, w.aAp.ptr, Dp, s_rs + k * P, s_pap + k * P,
+                           more ? s_rs + (k + 1) * P : nullptr, st));
+    if (more)
+      hipLaunchKernelGGL(cg_dir, gD, dim3(256), 0, st, w.ar.ptr, w.ap.ptr, Dp, s_rs + k * P, s_rs + (k + 1) * P);
+  }
+  SH_LAUNCHED();
+  SH_TRY(sh_psi_fwd(s->psi, w.alpha.ptr, w.x.ptr, st));                                       // x_n = Psi alpha_n
+  SH_TRY(w.red.change(w.x.ptr, w.xprev.ptr, per, s_misc + MISC_DX * P, st));
+  SH_TRY(sh::launch_prox_l1(Dp, P, w.alpha.ptr, w.zpsi.ptr, s->Wp, w.gamma.ptr, 0.f, w.vpsi.ptr, st));
+  SH_TRY(sh::phi_forward(op, w.x.ptr, w.sphi.ptr, false, nullptr, st));
+  SH_TRY(sh::launch_prox_ball(op, w.sphi.ptr, w.zphi.ptr, w.yhat.ptr, w.eps_hat.ptr, w.rho.ptr, w.resid.ptr,
+                              w.vphi.ptr, true, w.cblk.ptr, st));
+  SH_TRY(sh::launch_prox_pos(N, w.x.ptr, w.zpos.ptr, w.vpos.ptr, st));
+  return SH_OK;
+}
+
 // One SDMM iteration of all P problems, enqueued on `st` with no host synchronisation, no memset
 // and no allocation (so that it can be captured into a graph).
 sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
@@ -512,6 +586,7 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   const int64_t N = s->N, per = s->per;
   const dim3 gP(nblk(per), P);
   double *s_rs = s->s_rs, *s_pap = s->s_pap, *s_misc = s->s_misc;
+  if (s->synth) return sdmm_step_synthesis(s, st);
   // ---- x-update by CG from x_{n-1}
   SH_TRY(sh_psi_fwd(s->psi, w.vpsi.ptr, w.t1.ptr, st));
   if (s->stoch) {
@@ -647,16 +722,18 @@ sh_status sdmm_read(sh_sdmm s, std::vector<double>& rel, std::vector<double>& hr
 // Reweighting after a pass, from Psi^dagger x (in spsi): delta_1 = std(Psi^dagger x) per problem (float64) at a
 // problem's first reweighting, then delta <- beta delta.  `which` (per problem, NULL = all) selects the problems
 // whose pass just ended; the others keep their weights and delta.
-sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st, const std::vector<char>* which) {
+sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st, const std::vector<char>* which, const float* coeffs) {
   Work& w = s->w;
   const int P = s->P;
+  // the coefficients the weights follow: Psi^dagger x (analysis, in spsi) or alpha (synthesis)
+  const float* cf = coeffs ? coeffs : (s->synth ? w.alpha.ptr : w.spsi.ptr);
   auto sel = [&](int p) { return which == nullptr || (*which)[p] != 0; };
   bool need_std = false;
   for (int p = 0; p < P; ++p) need_std = need_std || (sel(p) && !s->have_delta[p]);
   if (need_std) {   // first reweighting of some problem: delta_1 = std of its analysis coefficients
     double* sum = s->s_misc + MISC_TMP * P;
     double* var = s->s_misc + MISC_TMP2 * P;
-    SH_TRY(w.red.std_dev(w.spsi.ptr, s->Dper, sum, var, st));
+    SH_TRY(w.red.std_dev(cf, s->Dper, sum, var, st));
     std::vector<double> v(P);
     SH_HIP(hipMemcpyAsync(v.data(), var, P * sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));
@@ -681,14 +758,56 @@ sh_status sdmm_reweight(sh_sdmm s, float* W_dst, hipStream_t st, const std::vect
     }
   SH_HIP(hipMemcpyAsync(w.delta.ptr, s->delta.data(), P * sizeof(double), hipMemcpyHostToDevice, st));
   if (which == nullptr) {
-    SH_TRY(sh::launch_reweight(s->Dper, P, w.spsi.ptr, w.delta.ptr, 0.0, W_dst, st));
+    SH_TRY(sh::launch_reweight(s->Dper, P, cf, w.delta.ptr, 0.0, W_dst, st));
   } else {
     for (int p = 0; p < P; ++p)
       if (sel(p))
-        SH_TRY(sh::launch_reweight(s->Dper, 1, w.spsi.ptr + p * s->Dper, w.delta.ptr + p, 0.0, W_dst + p * s->Dper,
-                                   st));
+        SH_TRY(sh::launch_reweight(s->Dper, 1, cf + p * s->Dper, w.delta.ptr + p, 0.0, W_dst + p * s->Dper, st));
   }
   SH_HIP(hipStreamSynchronize(st));   // the host copy of delta is read by the enqueued copy
+  return SH_OK;
+}
+
+// The KKT residuals and objective of the synthesis form: splits alpha (l1), Phi_hat x (balls) and x (positivity)
+// with x = Psi alpha; dual stationarity z_l1 + Psi^dagger (Phi_hat^dagger z_phi + z_+) = 0 in coefficient space.
+// Definitions as for the analysis form below; the CG scratch ap, aAp holds the coefficient-space terms.
+sh_status sdmm_kkt_synthesis(sh_sdmm s, std::vector<double>& prim, std::vector<double>& dual, std::vector<double>& obj,
+                             hipStream_t st) {
+  sh_op op = s->op;
+  Work& w = s->w;
+  const int P = s->P, R = s->R;
+  const int64_t Dp = s->Dper;
+  double* k = w.kkt.ptr;
+  SH_TRY(w.red.comb3_sq(w.alpha.ptr, w.vpsi.ptr, w.zpsi.ptr, -1.f, -1.f, Dp, k, st));
+  SH_TRY(w.red.dot(w.alpha.ptr, w.alpha.ptr, Dp, k + P, st));
+  SH_TRY(w.red.comb3_sq(w.x.ptr, w.vpos.ptr, w.zpos.ptr, -1.f, -1.f, s->per, k + 2 * P, st));
+  SH_TRY(w.red.dot(w.x.ptr, w.x.ptr, s->per, k + 3 * P, st));
+  SH_TRY(sh::launch_kkt_vis(op, w.sphi.ptr, w.zphi.ptr, w.vphi.ptr, w.cblk.ptr, k + 8 * P, k + 8 * P + R, st));
+  SH_TRY(sh::phi_adjoint(op, w.zphi.ptr, w.t2.ptr, false, w.cblk.ptr, st));          // Phi_hat^dagger z_phi
+  SH_TRY(sh_psi_adj(s->psi, w.t2.ptr, w.aAp.ptr, st));
+  SH_TRY(sh_psi_adj(s->psi, w.zpos.ptr, w.ap.ptr, st));
+  SH_TRY(w.red.dot(w.zpsi.ptr, w.zpsi.ptr, Dp, k + 4 * P, st));
+  SH_TRY(w.red.dot(w.aAp.ptr, w.aAp.ptr, Dp, k + 5 * P, st));
+  SH_TRY(w.red.dot(w.ap.ptr, w.ap.ptr, Dp, k + 6 * P, st));
+  SH_TRY(w.red.comb3_sq(w.zpsi.ptr, w.aAp.ptr, w.ap.ptr, 1.f, 1.f, Dp, k + 7 * P, st));
+  SH_TRY(w.red.l1w(w.alpha.ptr, s->Wp, Dp, s->s_misc + MISC_OBJ * P, st));
+  std::vector<double> h(8 * P + 2 * R), o(P);
+  SH_HIP(hipMemcpyAsync(h.data(), k, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipMemcpyAsync(o.data(), s->s_misc + MISC_OBJ * P, P * sizeof(double), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipStreamSynchronize(st));
+  prim.assign(P, 0.0);
+  dual.assign(P, 0.0);
+  obj = o;
+  for (int p = 0; p < P; ++p) {
+    double pr = h[p] + h[2 * P + p], sc = h[P + p] + h[3 * P + p];
+    for (int b = op->block_off[p]; b < op->block_off[p + 1]; ++b) {
+      pr += h[8 * P + b] * h[8 * P + b];
+      sc += h[8 * P + R + b] * h[8 * P + R + b];
+    }
+    prim[p] = sc > 0 ? std::sqrt(pr / sc) : 0.0;
+    const double dm = std::sqrt(std::max(h[4 * P + p], std::max(h[5 * P + p], h[6 * P + p])));
+    dual[p] = dm > 0 ? std::sqrt(h[7 * P + p]) / dm : 0.0;
+  }
   return SH_OK;
 }
 
@@ -705,6 +824,7 @@ sh_status sdmm_kkt(sh_sdmm s, std::vector<double>& prim, std::vector<double>& du
   Work& w = s->w;
   const int P = s->P, R = s->R;
   double* k = w.kkt.ptr;
+  if (s->synth) return sdmm_kkt_synthesis(s, prim, dual, obj, st);
   SH_TRY(w.red.comb3_sq(w.spsi.ptr, w.vpsi.ptr, w.zpsi.ptr, -1.f, -1.f, s->Dper, k, st));
   SH_TRY(w.red.dot(w.spsi.ptr, w.spsi.ptr, s->Dper, k + P, st));
   SH_TRY(w.red.comb3_sq(w.x.ptr, w.vpos.ptr, w.zpos.ptr, -1.f, -1.f, s->per, k + 2 * P, st));
@@ -759,6 +879,9 @@ sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps,
   SH_REQUIRE(prm->block_fraction > 0 && prm->block_fraction <= 1, "block_fraction must be in (0, 1]");
   SH_REQUIRE(prm->block_fraction == 1 || (prm->toeplitz == 1 && prm->z_from_x0 == 0),
              "block-subset iterations (block_fraction < 1) need toeplitz = 1 and z_from_x0 = 0");
+  SH_REQUIRE(prm->synthesis == 0 || prm->synthesis == 1, "synthesis must be 0 or 1");
+  SH_REQUIRE(prm->synthesis == 0 || (prm->toeplitz == 1 && prm->z_from_x0 == 0 && prm->block_fraction == 1),
+             "the synthesis prior needs toeplitz = 1, z_from_x0 = 0 and block_fraction = 1");
   SH_REQUIRE(prm->toeplitz == 0 || prm->toeplitz == 1, "toeplitz must be 0 or 1");
   SH_REQUIRE(prm->block_norm == 0 || prm->block_norm == 1, "block_norm must be 0 or 1");
   for (int i = 0; i < op->R; ++i) {
@@ -801,6 +924,7 @@ sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps
   s->R = op->R;
   s->kcg = params->cg_iters;
   s->stoch = params->block_fraction < 1.0;
+  s->synth = params->synthesis != 0;
   sh_status st = sdmm_setup(s, y, eps, W, x0, (hipStream_t)stream);
   if (st == SH_OK) st = hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? SH_OK : SH_EDEVICE;
   if (st != SH_OK) {
@@ -871,6 +995,9 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
   std::vector<double> rel_out(P, INFINITY), res_out(s->R, 0.0), kp_out(P, 0.0), kd_out(P, 0.0);
   auto take = [&](int p, std::vector<double>& kp, std::vector<double>& kd) -> sh_status {
     SH_HIP(hipMemcpyAsync(x_out + p * per, s->w.x.ptr + p * per, per * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (s->synth)
+      SH_HIP(hipMemcpyAsync(s->w.alpha_out.ptr + p * s->Dper, s->w.alpha.ptr + p * s->Dper, s->Dper * sizeof(float),
+                            hipMemcpyDeviceToDevice, st));
     rel_out[p] = rel[p];
     for (int i = op->block_off[p]; i < op->block_off[p + 1]; ++i) res_out[i] = hres[i] / s->cb[i];
     kp_out[p] = kp[p];
@@ -943,10 +1070,15 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
     SH_TRY(sdmm_kkt(s, kp, kd, ko, st));
     for (int p = 0; p < P; ++p) SH_TRY(take(p, kp, kd));
   }
-  // objective with the last pass's weights and W_out, both from Psi^dagger of the returned images
-  SH_TRY(sh_psi_adj(s->psi, x_out, s->w.spsi.ptr, st));
-  SH_TRY(s->w.red.l1w(s->w.spsi.ptr, s->Wp, s->Dper, s->s_misc + MISC_OBJ * P, st));
-  if (W_out) SH_TRY(sdmm_reweight(s, W_out, st));
+  // objective with the last pass's weights and W_out, both from the returned images' coefficients:
+  // Psi^dagger x (analysis) or the alpha taken with x (synthesis)
+  const float* coeffs = s->w.spsi.ptr;
+  if (s->synth)
+    coeffs = s->w.alpha_out.ptr;
+  else
+    SH_TRY(sh_psi_adj(s->psi, x_out, s->w.spsi.ptr, st));
+  SH_TRY(s->w.red.l1w(coeffs, s->Wp, s->Dper, s->s_misc + MISC_OBJ * P, st));
+  if (W_out) SH_TRY(sdmm_reweight(s, W_out, st, nullptr, coeffs));
   std::vector<double> obj(P);
   SH_HIP(hipMemcpyAsync(obj.data(), s->s_misc + MISC_OBJ * P, P * sizeof(double), hipMemcpyDeviceToHost, st));
   SH_HIP(hipStreamSynchronize(st));

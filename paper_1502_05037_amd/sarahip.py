@@ -44,7 +44,7 @@ class SdmmParams(C.Structure):
                 ("cg_iters", C.c_int32), ("passes", C.c_int32), ("check_every", C.c_int32), ("graph", C.c_int32),
                 ("w_from_x0", C.c_int32), ("toeplitz", C.c_int32), ("block_norm", C.c_int32),
                 ("tol_dual", C.c_double), ("z_from_x0", C.c_int32), ("block_fraction", C.c_double),
-                ("block_seed", C.c_uint64)]
+                ("block_seed", C.c_uint64), ("synthesis", C.c_int32)]
 
 
 class SdmmInfo(C.Structure):
