@@ -156,6 +156,14 @@ sh_status sh_psi_create(int32_t n, int32_t levels, uint32_t basis_mask, sh_psi* 
  * coefficients batch x q x n x n, image-major.  Pairs with a batched plan of P = batch problems. */
 sh_status sh_psi_create_batched(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch, sh_psi* out);
 sh_status sh_psi_destroy(sh_psi psi);
+/* The same dictionary on caller-provided device memory (e.g. a torch tensor): its scratch (two LL
+ * ping-pong buffers of batch x wavelet planes x (n/2)^2 float32) is carved from `workspace` (device,
+ * 256-byte aligned, at least sh_psi_workspace_bytes bytes, owned by the caller, and to outlive the
+ * handle).  The library then allocates no device memory for the handle.  Errors: SH_EINVAL (size,
+ * alignment, arguments as sh_psi_create_batched). */
+sh_status sh_psi_workspace_bytes(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch, size_t* bytes);
+sh_status sh_psi_create_ws(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch, void* workspace,
+                           size_t bytes, sh_psi* out);
 /* Number of planes q (D = q*n*n coefficients). */
 sh_status sh_psi_planes(sh_psi psi, int32_t* q_out);
 /* The float64 scaling filter of db_p (2p taps) as used by the library (host). */
@@ -221,6 +229,14 @@ typedef struct sh_toep_s* sh_toep;
  * M complex64 + P*n*n + 4*P*K*K float32 more while building.  Synchronous.
  * Errors: SH_EINVAL (NULL, scale <= 0 or non-finite, K < 2n), SH_ENOMEM, SH_EDEVICE. */
 sh_status sh_toeplitz_create(sh_op op, const double* scale, sh_toep* out, void* stream);
+/* The same operator on caller-provided device memory: its spectrum and scratch, and the build's
+ * temporaries, are carved from `workspace` (device, 256-byte aligned, at least
+ * sh_toeplitz_workspace_bytes, owned by the caller and to outlive the handle); the library allocates
+ * no device memory for it.  Errors as sh_toeplitz_create, plus SH_EINVAL for a small or unaligned
+ * workspace. */
+sh_status sh_toeplitz_workspace_bytes(sh_op op, size_t* bytes);
+sh_status sh_toeplitz_create_ws(sh_op op, const double* scale, void* workspace, size_t bytes, sh_toep* out,
+                                void* stream);
 /* out = T x for P images x (device P*n*n float32 each; out may not alias x).  Uses the plan's FFT
  * scratch, like sh_phi_fwd/adj: calls on one plan must not overlap.  Async. */
 sh_status sh_toeplitz_apply(sh_toep t, const float* x, float* out, void* stream);
@@ -328,6 +344,19 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
                         const float* x0, const sh_sdmm_params* params, float* x_out, float* W_out,
                         double* block_resid, sh_sdmm_info* info, void* stream);
 
+/* Device memory of a solve or session with plan op, dictionary psi and these parameters: the solver state
+ * (for M visibilities, N pixels and D coefficients about 40 M + 36 N + 16 D bytes, more with the Toeplitz
+ * spectrum, the synthesis prior or block-subset iterations) plus the largest of the set-up's temporaries
+ * (block-weight counters, the Toeplitz build, the power iteration).  Host only. */
+sh_status sh_workspace_bytes(sh_op op, sh_psi psi, const sh_sdmm_params* params, size_t* bytes);
+/* sh_sdmm_solve with every device allocation of the solve carved from `workspace` (device, 256-byte aligned,
+ * at least sh_workspace_bytes bytes, owned by the caller): all device memory can then come from the caller
+ * (e.g. torch).  Results are those of sh_sdmm_solve, bit for bit.  Errors as sh_sdmm_solve, plus SH_EINVAL
+ * for a small or unaligned workspace. */
+sh_status sh_sdmm_solve_ws(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W,
+                           const float* x0, const sh_sdmm_params* params, float* x_out, float* W_out,
+                           double* block_resid, sh_sdmm_info* info, void* workspace, size_t bytes, void* stream);
+
 /* Session form of the same solver, for callers that drive the iterations themselves
  * (benchmarks, checkpointed runs).  sh_sdmm_create validates as sh_sdmm_solve, copies the data
  * to device (internal order, normalised by nu), resolves nu and gamma, sets the zero or warm
@@ -336,6 +365,10 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
 typedef struct sh_sdmm_s* sh_sdmm;
 sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W,
                          const float* x0, const sh_sdmm_params* params, sh_sdmm* out, void* stream);
+/* The session on a caller's workspace (as sh_sdmm_solve_ws); the workspace must outlive the session. */
+sh_status sh_sdmm_create_ws(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W,
+                            const float* x0, const sh_sdmm_params* params, void* workspace, size_t bytes,
+                            sh_sdmm* out, void* stream);
 /* Enqueue exactly `iters` SDMM iterations of the current weighted-l1 pass (no stopping test, no
  * reweighting, no host synchronisation).  Splitting a run into several calls gives the same
  * iterates as one call.  Async. */

@@ -19,6 +19,11 @@ void set_error(const char* fmt, ...) {
 
 const char* last_error() { return g_err; }
 
+Arena*& arena_slot() {
+  static thread_local Arena* a = nullptr;
+  return a;
+}
+
 namespace {
 const char* kNames[] = {"degrid", "grid", "fold", "fft_rows", "fft_cols", "dwt", "prox", "cg", "toeplitz"};
 constexpr int kSlots = sizeof(kNames) / sizeof(kNames[0]);

@@ -49,38 +49,99 @@ const char* last_error();
     }                                  \
   } while (0)
 
-// Owning device allocation (hipMalloc / hipFree).
+// Caller-provided device memory (a workspace) handed out as a stack: each allocation is carved, 256-byte
+// aligned, at the top; a release marks its block free and the top falls back over every free block at the
+// top, so that scoped temporaries are reused in order.  The owner of the arena must outlive every buffer
+// taken from it.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, top = 0, peak = 0;
+  struct Blk {
+    size_t off;
+    bool freed;
+  };
+  std::vector<Blk> blocks;
+  static constexpr size_t kAlign = 256;
+  static size_t round(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+  void* take(size_t bytes) {
+    const size_t b = round(bytes);
+    if (top + b > size) return nullptr;
+    void* p = base + top;
+    blocks.push_back({top, false});
+    top += b;
+    peak = top > peak ? top : peak;
+    return p;
+  }
+  void give(void* p) {
+    const size_t off = size_t(static_cast<char*>(p) - base);
+    for (auto& b : blocks)
+      if (b.off == off) b.freed = true;
+    while (!blocks.empty() && blocks.back().freed) {
+      top = blocks.back().off;
+      blocks.pop_back();
+    }
+  }
+};
+// The arena that DevBuf allocations of this thread take their memory from (NULL: hipMalloc).
+Arena*& arena_slot();
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena* a) : prev(arena_slot()) { arena_slot() = a; }
+  ~ArenaScope() { arena_slot() = prev; }
+};
+
+// Owning device allocation: hipMalloc / hipFree, or a block of the thread's current arena.
 template <typename T>
 struct DevBuf {
   T* ptr = nullptr;
   size_t count = 0;
+  Arena* arena = nullptr;   // where ptr came from (NULL: hipMalloc)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), count(o.count) {
+  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), count(o.count), arena(o.arena) {
     o.ptr = nullptr;
     o.count = 0;
+    o.arena = nullptr;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       ptr = o.ptr;
       count = o.count;
+      arena = o.arena;
       o.ptr = nullptr;
       o.count = 0;
+      o.arena = nullptr;
     }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+      if (arena)
+        arena->give(ptr);
+      else
+        (void)hipFree(ptr);
+    }
     ptr = nullptr;
     count = 0;
+    arena = nullptr;
   }
   sh_status alloc(size_t n) {
     release();
     if (n == 0) return SH_OK;
-    SH_HIP(hipMalloc((void**)&ptr, n * sizeof(T)));
+    if (Arena* a = arena_slot()) {
+      ptr = static_cast<T*>(a->take(n * sizeof(T)));
+      if (!ptr) {
+        ::sh::set_error("workspace of %zu bytes exhausted (%zu in use, %zu more requested)", a->size, a->top,
+                        Arena::round(n * sizeof(T)));
+        return SH_ENOMEM;
+      }
+      arena = a;
+    } else {
+      SH_HIP(hipMalloc((void**)&ptr, n * sizeof(T)));
+    }
     count = n;
     return SH_OK;
   }

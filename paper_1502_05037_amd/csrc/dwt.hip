@@ -30,6 +30,7 @@ struct sh_psi_s {
   uint32_t mask = 0;
   float scale = 1.f;
   DwtPlanes pl{};
+  sh::Arena arena;                // a caller's workspace (sh_psi_create_ws); declared before the buffers
   sh::DevBuf<float> tmpA, tmpB;   // batch x nplanes x (n/2)^2 LL ping-pong
 };
 
@@ -215,7 +216,45 @@ sh_status sh_daubechies(int32_t p, double* h_out) {
   return SH_OK;
 }
 
+static int wavelet_planes(uint32_t basis_mask) {
+  int k = 0;
+  for (int b = 1; b < 9; ++b) k += (basis_mask >> b) & 1;
+  return k;
+}
+
+static size_t psi_ws_bytes(int32_t n, uint32_t basis_mask, int32_t batch) {
+  const size_t half = size_t(n / 2) * (n / 2) * wavelet_planes(basis_mask) * batch * sizeof(float);
+  return half ? 2 * sh::Arena::round(half) : 0;
+}
+
+static sh_status psi_create(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch, void* workspace,
+                            size_t bytes, sh_psi* out);
+
+extern "C" sh_status sh_psi_workspace_bytes(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch,
+                                            size_t* bytes) {
+  SH_REQUIRE(bytes, "bytes is NULL");
+  SH_REQUIRE(batch >= 1 && batch <= 4096 && n >= 2 && basis_mask != 0 && (basis_mask >> 9) == 0 && levels >= 1,
+             "invalid dictionary");
+  *bytes = psi_ws_bytes(n, basis_mask, batch);
+  return SH_OK;
+}
+
+extern "C" sh_status sh_psi_create_ws(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch, void* workspace,
+                                      size_t bytes, sh_psi* out) {
+  SH_REQUIRE(workspace || psi_ws_bytes(n, basis_mask, batch) == 0, "workspace is NULL");
+  SH_REQUIRE(reinterpret_cast<uintptr_t>(workspace) % sh::Arena::kAlign == 0, "workspace must be %zu-byte aligned",
+             sh::Arena::kAlign);
+  SH_REQUIRE(bytes >= psi_ws_bytes(n, basis_mask, batch), "workspace of %zu bytes is smaller than the %zu needed",
+             bytes, psi_ws_bytes(n, basis_mask, batch));
+  return psi_create(n, levels, basis_mask, batch, workspace, bytes, out);
+}
+
 sh_status sh_psi_create_batched(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch, sh_psi* out) {
+  return psi_create(n, levels, basis_mask, batch, nullptr, 0, out);
+}
+
+static sh_status psi_create(int32_t n, int32_t levels, uint32_t basis_mask, int32_t batch, void* workspace,
+                            size_t bytes, sh_psi* out) {
   SH_REQUIRE(out, "out is NULL");
   *out = nullptr;
   SH_REQUIRE(batch >= 1 && batch <= 4096, "batch must be in [1, 4096]");
@@ -253,6 +292,9 @@ sh_status sh_psi_create_batched(int32_t n, int32_t levels, uint32_t basis_mask, 
   psi->scale = float(1.0 / std::sqrt(double(plane)));
   if (psi->pl.nplanes > 0) {
     const size_t half = size_t(n / 2) * (n / 2) * psi->pl.nplanes * batch;
+    psi->arena.base = static_cast<char*>(workspace);
+    psi->arena.size = bytes;
+    sh::ArenaScope scope(workspace ? &psi->arena : nullptr);
     sh_status s = psi->tmpA.alloc(half);
     if (s == SH_OK) s = psi->tmpB.alloc(half);
     if (s != SH_OK) {

@@ -71,6 +71,7 @@ sh_status toeplitz_apply(sh_op op, const float* Ht, const float* x, float2* tq, 
 
 // Toeplitz form of scale_p Re(Phi^H Phi) for a plan (toeplitz.hip).
 struct sh_toep_s {
+  sh::Arena arena;                 // a caller's workspace (sh_toeplitz_create_ws); declared first, freed last
   sh_op op = nullptr;
   sh::DevBuf<float> Ht;            // P x K x K: kernel spectrum / K^2 * scale_p, transposed
   sh::DevBuf<float2> tq;           // P x n x K scratch of the column pass

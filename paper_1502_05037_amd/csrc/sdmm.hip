@@ -283,6 +283,7 @@ struct sh_sdmm_s {
   sh_op op = nullptr;
   sh_psi psi = nullptr;
   sh_sdmm_params prm{};
+  sh::Arena arena;                 // a caller's workspace (sh_sdmm_create_ws); declared before w, freed after it
   Work w;
   int P = 1;
   int64_t per = 0, Dper = 0;       // pixels and coefficients of one problem
@@ -898,8 +899,38 @@ sh_status sdmm_validate(sh_op op, sh_psi psi, const float* y, const double* eps,
 
 extern "C" {
 
-sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W, const float* x0,
-                         const sh_sdmm_params* params, sh_sdmm* out, void* stream) {
+}  // extern "C"
+
+namespace {
+
+size_t al(size_t b) { return sh::Arena::round(b); }
+
+// Device bytes of a solver session (every allocation of its set-up, in the arena's stack order): the
+// session's arrays, then the largest of the set-up's passing temporaries (the finiteness check's reducer,
+// the block-weight counters, the Toeplitz build, the power iteration, the spectrum rescaling).
+size_t sdmm_ws_bytes(sh_op op, int q, const sh_sdmm_params* prm) {
+  const size_t P = op->P, per = size_t(op->n) * op->n, N = per * P, D = size_t(q) * per * P, M = op->M, R = op->R;
+  const size_t K = op->K, KK = K * K, n = op->n, kcg = prm->cg_iters;
+  const size_t rb = 512 / P > 1 ? 512 / P : 1;
+  size_t pers = 9 * al(4 * N) + 4 * al(4 * D) + 5 * al(8 * M) + al(8 * (2 * kcg + 1 + MISC_N) * P) + 3 * al(8 * R) +
+                al(8 * P) + al(8 * (8 * P + 2 * R)) + al(4 * R) + al(4 * P) + al(8 * 2 * P * rb);
+  if (prm->synthesis) pers += 5 * al(4 * D);
+  if (prm->block_fraction < 1) pers += al(4 * R) + al(8) + al(4 * N);
+  if (prm->toeplitz) pers += al(4 * P * KK) + al(8 * P * n * K);
+  size_t tmp = al(8 * 2 * 512);   // the finiteness check's one-segment reducer
+  if (prm->block_norm) {
+    const size_t G = std::max<size_t>(1, std::min<size_t>(R, (size_t(1) << 26) / KK));
+    tmp = std::max(tmp, al(4 * G * KK) + al(4 * R));
+  }
+  if (prm->toeplitz)
+    tmp = std::max(tmp, (prm->block_norm ? al(4 * R) : 0) + al(8 * M) + al(4 * P * n * n) + 2 * al(8 * P * KK) +
+                            al(4 * P));
+  if (!(prm->nu > 0)) tmp = std::max(tmp, 2 * al(4 * N) + al(8 * M) + al(8 * 3 * P) + al(8 * 2 * P * rb));
+  return pers + tmp;
+}
+
+sh_status sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W, const float* x0,
+                      const sh_sdmm_params* params, void* workspace, size_t ws_bytes, sh_sdmm* out, void* stream) {
   SH_REQUIRE(out, "out is NULL");
   *out = nullptr;
   SH_TRY(sdmm_validate(op, psi, y, eps, params));
@@ -925,7 +956,13 @@ sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps
   s->kcg = params->cg_iters;
   s->stoch = params->block_fraction < 1.0;
   s->synth = params->synthesis != 0;
-  sh_status st = sdmm_setup(s, y, eps, W, x0, (hipStream_t)stream);
+  sh_status st;
+  {
+    s->arena.base = static_cast<char*>(workspace);
+    s->arena.size = ws_bytes;
+    sh::ArenaScope scope(workspace ? &s->arena : nullptr);
+    st = sdmm_setup(s, y, eps, W, x0, (hipStream_t)stream);
+  }
   if (st == SH_OK) st = hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? SH_OK : SH_EDEVICE;
   if (st != SH_OK) {
     delete s;
@@ -933,6 +970,42 @@ sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps
   }
   *out = s;
   return SH_OK;
+}
+
+sh_status check_ws(sh_op op, sh_psi psi, const sh_sdmm_params* params, void* workspace, size_t bytes) {
+  SH_REQUIRE(op && psi && params && workspace, "NULL argument");
+  SH_REQUIRE(reinterpret_cast<uintptr_t>(workspace) % sh::Arena::kAlign == 0, "workspace must be %zu-byte aligned",
+             sh::Arena::kAlign);
+  int32_t q = 0;
+  sh_psi_planes(psi, &q);
+  const size_t need = sdmm_ws_bytes(op, q, params);
+  SH_REQUIRE(bytes >= need, "workspace of %zu bytes is smaller than the %zu needed", bytes, need);
+  return SH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sh_status sh_workspace_bytes(sh_op op, sh_psi psi, const sh_sdmm_params* params, size_t* bytes) {
+  SH_REQUIRE(op && psi && params && bytes, "NULL argument");
+  int32_t q = 0;
+  sh_psi_planes(psi, &q);
+  *bytes = sdmm_ws_bytes(op, q, params);
+  return SH_OK;
+}
+
+sh_status sh_sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W, const float* x0,
+                         const sh_sdmm_params* params, sh_sdmm* out, void* stream) {
+  return sdmm_create(op, psi, y, eps, W, x0, params, nullptr, 0, out, stream);
+}
+
+sh_status sh_sdmm_create_ws(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W, const float* x0,
+                            const sh_sdmm_params* params, void* workspace, size_t bytes, sh_sdmm* out, void* stream) {
+  SH_REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  SH_TRY(check_ws(op, psi, params, workspace, bytes));
+  return sdmm_create(op, psi, y, eps, W, x0, params, workspace, bytes, out, stream);
 }
 
 sh_status sh_sdmm_iterate(sh_sdmm s, int32_t iters, void* stream) {
@@ -971,13 +1044,17 @@ sh_status sh_sdmm_destroy(sh_sdmm s) {
   return SH_OK;
 }
 
-sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W0, const float* x0,
-                        const sh_sdmm_params* prm, float* x_out, float* W_out, double* block_resid,
-                        sh_sdmm_info* info, void* stream) {
+}  // extern "C"
+
+namespace {
+
+sh_status sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W0, const float* x0,
+                     const sh_sdmm_params* prm, float* x_out, float* W_out, double* block_resid, sh_sdmm_info* info,
+                     void* workspace, size_t ws_bytes, void* stream) {
   const auto t_start = std::chrono::steady_clock::now();
   SH_REQUIRE(x_out, "x_out is NULL");
   sh_sdmm s = nullptr;
-  SH_TRY(sh_sdmm_create(op, psi, y, eps, W0, x0, prm, &s, stream));
+  SH_TRY(sdmm_create(op, psi, y, eps, W0, x0, prm, workspace, ws_bytes, &s, stream));
   std::unique_ptr<sh_sdmm_s> guard(s);
   hipStream_t st = (hipStream_t)stream;
   const int P = s->P;
@@ -1103,6 +1180,23 @@ sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps,
       for (int t = 0; t < (int)pass_it[p].size() && t < SH_PASS_RECORD; ++t) inf.pass_iters[t] = pass_it[p][t];
     }
   return SH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sh_status sh_sdmm_solve(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W0, const float* x0,
+                        const sh_sdmm_params* prm, float* x_out, float* W_out, double* block_resid,
+                        sh_sdmm_info* info, void* stream) {
+  return sdmm_solve(op, psi, y, eps, W0, x0, prm, x_out, W_out, block_resid, info, nullptr, 0, stream);
+}
+
+sh_status sh_sdmm_solve_ws(sh_op op, sh_psi psi, const float* y, const double* eps, const float* W0, const float* x0,
+                           const sh_sdmm_params* prm, float* x_out, float* W_out, double* block_resid,
+                           sh_sdmm_info* info, void* workspace, size_t bytes, void* stream) {
+  SH_TRY(check_ws(op, psi, prm, workspace, bytes));
+  return sdmm_solve(op, psi, y, eps, W0, x0, prm, x_out, W_out, block_resid, info, workspace, bytes, stream);
 }
 
 }  // extern "C"

@@ -93,6 +93,14 @@ sh_status toeplitz_build(sh_op op, const double* scale, const double* wblk, sh_t
     SH_REQUIRE(std::isfinite(v) && v > 0, "scale[%d] must be positive and finite, got %g", p, v);
     sc[p] = float(v / (double(K) * double(K)));
   }
+  // the operator's own arrays first, the build's temporaries after them (so that a workspace arena can
+  // take the temporaries back when they are released)
+  SH_TRY(t->Ht.alloc(P * KK));
+  SH_TRY(t->tq.alloc((int64_t)P * n * K));
+  if (!op->ones.ptr) {   // the FFT passes' unit weights belong to the plan: never from a caller's workspace
+    sh::ArenaScope none(nullptr);
+    SH_TRY(op->ones.upload(std::vector<float>(n, 1.0f)));
+  }
   sh::DevBuf<float2> w, C, tmp;
   sh::DevBuf<float> win, scd, wb;
   if (wblk) {   // a visibility of block b carries wblk[b]^2: the modulated vector and the adjoint's weight
@@ -108,9 +116,6 @@ sh_status toeplitz_build(sh_op op, const double* scale, const double* wblk, sh_t
   SH_TRY(C.alloc(P * KK));
   SH_TRY(tmp.alloc(P * KK));
   SH_TRY(scd.upload(sc));
-  SH_TRY(t->Ht.alloc(P * KK));
-  SH_TRY(t->tq.alloc((int64_t)P * n * K));
-  if (!op->ones.ptr) SH_TRY(op->ones.upload(std::vector<float>(n, 1.0f)));   // the FFT passes' unit weights
   SH_HIP(hipMemsetAsync(C.ptr, 0, P * KK * sizeof(float2), st));
   for (int s1 = 0; s1 < 2; ++s1)
     for (int s2 = 0; s2 < 2; ++s2) {
@@ -156,6 +161,38 @@ sh_status sh_toeplitz_create(sh_op op, const double* scale, sh_toep* out, void* 
   *out = nullptr;
   auto t = std::make_unique<sh_toep_s>();
   SH_TRY(sh::toeplitz_build(op, scale, nullptr, t.get(), (hipStream_t)stream));
+  *out = t.release();
+  return SH_OK;
+}
+
+static size_t toeplitz_ws_bytes(sh_op op) {
+  using sh::Arena;
+  const size_t P = op->P, n = op->n, K = op->K, KK = K * K, M = op->M;
+  return Arena::round(4 * P * KK) + Arena::round(8 * P * n * K)                       // spectrum, scratch
+         + Arena::round(8 * M) + Arena::round(4 * P * n * n) + 2 * Arena::round(8 * P * KK) + Arena::round(4 * P);
+}
+
+sh_status sh_toeplitz_workspace_bytes(sh_op op, size_t* bytes) {
+  SH_REQUIRE(op && bytes, "NULL argument");
+  *bytes = toeplitz_ws_bytes(op);
+  return SH_OK;
+}
+
+sh_status sh_toeplitz_create_ws(sh_op op, const double* scale, void* workspace, size_t bytes, sh_toep* out,
+                                void* stream) {
+  SH_REQUIRE(op && out && workspace, "op, workspace and out must be non-NULL");
+  SH_REQUIRE(reinterpret_cast<uintptr_t>(workspace) % sh::Arena::kAlign == 0, "workspace must be %zu-byte aligned",
+             sh::Arena::kAlign);
+  SH_REQUIRE(bytes >= toeplitz_ws_bytes(op), "workspace of %zu bytes is smaller than the %zu needed", bytes,
+             toeplitz_ws_bytes(op));
+  *out = nullptr;
+  auto t = std::make_unique<sh_toep_s>();
+  t->arena.base = static_cast<char*>(workspace);
+  t->arena.size = bytes;
+  {
+    sh::ArenaScope scope(&t->arena);
+    SH_TRY(sh::toeplitz_build(op, scale, nullptr, t.get(), (hipStream_t)stream));
+  }
   *out = t.release();
   return SH_OK;
 }

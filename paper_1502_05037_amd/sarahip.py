@@ -110,6 +110,15 @@ _SIGS = {
     "sh_reweight": (C.c_int, [_i64, _vp, _f64, _vp, _vp]),
     "sh_std": (C.c_int, [_i64, _vp, _P64, _vp]),
     "sh_sdmm_default_params": (None, [C.POINTER(SdmmParams)]),
+    "sh_workspace_bytes": (C.c_int, [_vp, _vp, C.POINTER(SdmmParams), C.POINTER(C.c_size_t)]),
+    "sh_sdmm_solve_ws": (C.c_int, [_vp, _vp, _vp, _P64, _vp, _vp, C.POINTER(SdmmParams), _vp, _vp, _P64,
+                                   C.POINTER(SdmmInfo), _vp, C.c_size_t, _vp]),
+    "sh_sdmm_create_ws": (C.c_int, [_vp, _vp, _vp, _P64, _vp, _vp, C.POINTER(SdmmParams), _vp, C.c_size_t,
+                                    C.POINTER(_vp), _vp]),
+    "sh_psi_workspace_bytes": (C.c_int, [_i32, _i32, _u32, _i32, C.POINTER(C.c_size_t)]),
+    "sh_psi_create_ws": (C.c_int, [_i32, _i32, _u32, _i32, _vp, C.c_size_t, C.POINTER(_vp)]),
+    "sh_toeplitz_workspace_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
+    "sh_toeplitz_create_ws": (C.c_int, [_vp, _P64, _vp, C.c_size_t, C.POINTER(_vp), _vp]),
     "sh_sdmm_solve": (C.c_int, [_vp, _vp, _vp, _P64, _vp, _vp, C.POINTER(SdmmParams), _vp, _vp, _P64,
                                 C.POINTER(SdmmInfo), _vp]),
     "sh_sdmm_create": (C.c_int, [_vp, _vp, _vp, _P64, _vp, _vp, C.POINTER(SdmmParams), C.POINTER(_vp), _vp]),
@@ -306,6 +315,23 @@ def toeplitz_create(op, scale=None, stream=None):
     return h
 
 
+def toeplitz_workspace_bytes(op) -> int:
+    b = C.c_size_t()
+    _check(lib.sh_toeplitz_workspace_bytes(op, C.byref(b)), "toeplitz_workspace_bytes")
+    return b.value
+
+
+def toeplitz_create_ws(op, workspace, scale=None, stream=None):
+    h = _vp()
+    sp = None
+    if scale is not None:
+        sc = np.ascontiguousarray(np.atleast_1d(np.asarray(scale, dtype=np.float64)))
+        sp = sc.ctypes.data_as(_P64)
+    _check(lib.sh_toeplitz_create_ws(op, sp, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                     C.byref(h), _stream(stream)), "toeplitz_create_ws")
+    return h
+
+
 def toeplitz_apply(t, x, out, stream=None):
     _check(lib.sh_toeplitz_apply(t, _ptr(x), _ptr(out), _stream(stream)), "toeplitz_apply")
 
@@ -333,6 +359,19 @@ def psi_create(n: int, levels: int = 4, basis_mask: int = SARA_MASK) -> int:
 def psi_create_batched(n: int, levels: int, basis_mask: int, batch: int) -> int:
     h = _vp()
     _check(lib.sh_psi_create_batched(n, levels, basis_mask, batch, C.byref(h)), "psi_create_batched")
+    return h.value
+
+
+def psi_workspace_bytes(n: int, levels: int, basis_mask: int, batch: int = 1) -> int:
+    b = C.c_size_t()
+    _check(lib.sh_psi_workspace_bytes(n, levels, basis_mask, batch, C.byref(b)), "psi_workspace_bytes")
+    return b.value
+
+
+def psi_create_ws(n: int, levels: int, basis_mask: int, batch: int, workspace) -> int:
+    h = _vp()
+    _check(lib.sh_psi_create_ws(n, levels, basis_mask, batch, _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), C.byref(h)), "psi_create_ws")
     return h.value
 
 
@@ -412,6 +451,35 @@ def sdmm_solve(op, psi, y, eps, W, x0, params: SdmmParams, x_out, W_out=None, st
                              C.cast(info, C.POINTER(SdmmInfo)), _stream(stream)), "sdmm_solve")
     dicts = [i.as_dict() for i in info]
     return (dicts[0] if P == 1 else dicts), resid
+
+
+def workspace_bytes(op, psi, params: SdmmParams) -> int:
+    b = C.c_size_t()
+    _check(lib.sh_workspace_bytes(op, psi, C.byref(params), C.byref(b)), "workspace_bytes")
+    return b.value
+
+
+def sdmm_solve_ws(op, psi, y, eps, W, x0, params: SdmmParams, x_out, workspace, W_out=None, stream=None):
+    """sdmm_solve with the device memory of the solve taken from `workspace` (a uint8 device tensor)."""
+    eps = _f64(eps)
+    P = op_query(op)["P"]
+    resid = np.zeros(len(eps), dtype=np.float64)
+    info = (SdmmInfo * P)()
+    _check(lib.sh_sdmm_solve_ws(op, psi, _ptr(y), eps.ctypes.data_as(_P64), _ptr(W), _ptr(x0), C.byref(params),
+                                _ptr(x_out), _ptr(W_out), resid.ctypes.data_as(_P64), C.cast(info, C.POINTER(SdmmInfo)),
+                                _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)),
+           "sdmm_solve_ws")
+    dicts = [i.as_dict() for i in info]
+    return (dicts[0] if P == 1 else dicts), resid
+
+
+def sdmm_create_ws(op, psi, y, eps, W, x0, params: SdmmParams, workspace, stream=None) -> int:
+    eps = _f64(eps)
+    h = _vp()
+    _check(lib.sh_sdmm_create_ws(op, psi, _ptr(y), eps.ctypes.data_as(_P64), _ptr(W), _ptr(x0), C.byref(params),
+                                 _ptr(workspace), workspace.numel() * workspace.element_size(), C.byref(h),
+                                 _stream(stream)), "sdmm_create_ws")
+    return h.value
 
 
 def sdmm_create(op, psi, y, eps, W, x0, params: SdmmParams, stream=None) -> int:
