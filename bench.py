@@ -83,7 +83,8 @@ def measured_traffic(kernel_name):
         src = open(os.path.join(ROOT, d["source"]), "rb").read()
     except (OSError, ValueError, KeyError):
         return None
-    if d.get("kernel", "").split("<")[0] != kernel_name + "_kernel" or hashlib.sha256(src).hexdigest() != d["source_sha256"]:
+    names = {"grid": ("grid_kernel", "grid_mfma_kernel"), "degrid": ("degrid_kernel",)}.get(kernel_name, ())
+    if d.get("kernel", "").split("<")[0] not in names or hashlib.sha256(src).hexdigest() != d["source_sha256"]:
         return None
     return d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
 

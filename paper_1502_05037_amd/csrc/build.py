@@ -24,6 +24,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-
          "-Wno-unused-result", "-Wno-unused-variable",
          # packed FP32 math off for every device function
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# per-source additions: the gridder keeps its matrix-core accumulators in ordinary VGPRs (the sums are read
+# and reset by vector instructions at every change of cell, which AGPRs would turn into copies)
+EXTRA = {"nufft.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:
@@ -36,7 +39,7 @@ def hipcc() -> str:
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"]
-    cmd = [hipcc(), *lang, *FLAGS, "-c", os.path.join(HERE, src), "-o", obj]
+    cmd = [hipcc(), *lang, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(HERE, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -17,14 +17,17 @@
 // cell) a thread keeps the J x J taps of its current cell in registers across the run of
 // visibilities that share it.
 //
-// Gridding (atomic-free): one work-group per item owns a private padded patch.  Phase A computes the
-// 2J one-dimensional weights of a batch of visibilities, two lanes each (one per axis), into LDS.  Phase B walks
-// the batch wave by wave with one lane per tap (t1, t2): the lane accumulates w1[t1] w2[t2] v in a
-// register while the cell stays the same and adds it into its wave's own LDS copy of the patch when
-// the (wave-uniform) cell changes, so no two lanes ever update the same address.  The wave copies
-// are summed in a fixed order and the patch is written to the item's own slot; the fold kernel then
-// forms each grid cell as the sum, in a fixed order, of the patches that cover it.  Every sum has a
-// fixed order, so the adjoint is bitwise reproducible.
+// Gridding (atomic-free): one work-group per item owns a private padded patch, written to the item's own
+// slot; the fold kernel then forms each grid cell as the sum, in a fixed order, of the patches that cover
+// it.  Every sum has a fixed order, so the adjoint is bitwise reproducible.
+//  * J = 8 (grid_mfma_kernel): the outer products w1 w2^T v of a run of visibilities in one cell accumulate
+//    on the matrix cores (v_mfma_f32_4x4x1_16b_f32, full fp32), two visibilities per instruction; each
+//    half-wave is a stream over its share of the item with its own copy of the rows of the patch it touches.
+//  * other J (grid_kernel): phase A computes the 2J one-dimensional weights of a batch of visibilities, two
+//    lanes each (one per axis), into LDS.  Phase B walks the batch wave by wave with one lane per tap
+//    (t1, t2): the lane accumulates w1[t1] w2[t2] v in a register while the cell stays the same and adds it
+//    into its wave's own LDS copy of the patch when the (wave-uniform) cell changes, so no two lanes ever
+//    update the same address.  The wave copies are summed in a fixed order.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -38,6 +41,10 @@ constexpr int GRID_CHUNK = 4096;   // default visibilities per work item
 constexpr int BALL_CHUNK = 8192;   // visibilities per reduction chunk
 constexpr int RUN_MIN = 6;         // mean visibilities per cell of a dense work item
 constexpr int DEGRID_STAGE = 4096; // outputs a dense degridding work-group stages in LDS (= default chunk)
+
+// The J = 8 gridder: waves per work-group (two streams each).  Two keep a work-group's LDS near 18 KB, so
+// that the registers (five waves per SIMD), not LDS, bound the occupancy.
+constexpr int grid_mfma_waves(int) { return 2; }
 
 // All J tap weights at s = 2f - 1.  Tap J-1-t at f is tap t at 1 - f (the window is even), and the tap
 // polynomials are tabulated with that symmetry, so the pair shares its even and odd parts in s:
@@ -397,6 +404,198 @@ __global__ __launch_bounds__(256) void grid_kernel(const uint2* __restrict__ coo
   }
 }
 
+// Gridding with J = 8 on the matrix cores.  v_mfma_f32_4x4x1_16b_f32 forms sixteen independent 4 x 4
+// outer products a b^T and adds them to its accumulator: block k takes a[i] from lane 4k + i and b[j] from
+// lane 4k + j, and leaves entry (i, j) in accumulator register i of lane 4k + j.  One visibility's 8 x 8 taps,
+// real and imaginary part, are eight such blocks: block (r, tb, ub) holds taps t1 = 4 tb + i, t2 = 4 ub + j
+// of part r, with a = w1[t1] Re/Im(v) and b = w2[t2].  One instruction therefore grids two visibilities, one
+// per half-wave, and each half-wave is an independent stream over its share of the item.
+//
+// Phase A: each lane computes both axes' weights of one visibility of its stream and stages a (real and
+// imaginary rows) and b in LDS, tap-major, so that phase B reads four consecutive visibilities' operands
+// with one 128-bit load.  Phase B: while a stream stays in one cell its blocks accumulate in the matrix
+// registers; when the cell changes, each of the stream's lanes writes its four sums, added to the values it
+// read from the stream's own copy of the patch when the run started, back to the copy, reads the values under
+// the next run and restarts from zero (LDS float atomics would serialise over the lanes).  No other lane
+// touches those addresses and one wave's LDS operations execute in order, so every entry of a copy is a sum
+// in a fixed order; the copies are summed in a fixed order at the end, and the adjoint stays bitwise
+// reproducible.
+template <int T, int NWV>
+__global__ __launch_bounds__(64 * NWV) void grid_mfma_kernel(const uint2* __restrict__ coord,
+                                                             const float2* __restrict__ vis,
+                                                             const uint32_t* __restrict__ vidx,
+                                                             const int4* __restrict__ items,
+                                                             const int32_t* __restrict__ item_block,
+                                                             const int4* __restrict__ item_rows,
+                                                             float2* __restrict__ patches, int log2K, int log2T,
+                                                             const float* __restrict__ scales, KBCoef kc,
+                                                             const int32_t* __restrict__ bmask) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int J = 8, P = T + J - 1, PP = P * P;
+  constexpr int NS = 2 * NWV;             // streams per work-group
+  // Each stream's copy of the patch covers only the cell rows its visibilities occupy plus J - 1 (its stream
+  // is a contiguous run of the item, sorted by row, so the rows of all streams add up to at most
+  // T + NS - 1; an empty stream still gets one row): rows of pitch PR in a pool of RMAX rows, a real and
+  // an imaginary plane PL words apart.  PR = 2 (mod 8) and PL = 16 (mod 32) put the 32 addresses one
+  // write-back instruction of a stream touches (offsets i + 4 ub + 4 tb PR + r PL) in 32 different banks.
+  constexpr int PR = ((P + 5) / 8) * 8 + 2;
+  constexpr int RMAX = T + NS - 1 + NS * (J - 1);
+  constexpr int PL = ((RMAX * PR + 15) / 32) * 32 + 16;
+  constexpr int NB = 16;                  // visibilities per stream and batch (two lanes each in phase A)
+  constexpr int SP = NB + 4;              // staging row pitch: rows 4 words apart, 16-byte aligned
+  static_assert(PR >= P && PL >= RMAX * PR && NS <= 8, "copy layout");
+  __shared__ __attribute__((aligned(16))) float cp[2 * PL];
+  // staged per stream and batch: rows a real, a imaginary, b (J each)
+  __shared__ __attribute__((aligned(16))) float stg[NWV][2][3 * J][SP];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int h = lane >> 5, ax = (lane >> 4) & 1, jl = lane & 15;   // phase A: visibility jl, axis ax
+  const int itx = xcd_block_runs(blockIdx.x, gridDim.x, 16);
+  int4 it = items[itx];
+  const int4 ir = item_rows[itx];
+  if (bmask && !bmask[item_block[itx]]) it.z = 0;   // block not selected: a zero patch, no visibility read
+  // the streams' first rows and pool rows (uniform): stream k's rows start at row base[k] of the pool
+  int first[NS], base[NS + 1];
+  base[0] = 0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    first[k] = ((k < 4 ? ir.x : ir.y) >> (8 * (k & 3))) & 255;
+    base[k + 1] = base[k] + (((k < 4 ? ir.z : ir.w) >> (8 * (k & 3))) & 255) + J - 1;
+  }
+  const int s = wave * 2 + h;             // this lane's stream
+  const int lo = it.y + int((int64_t)it.z * s / NS), hi = it.y + int((int64_t)it.z * (s + 1) / NS);
+  const int nbatch = (it.z + NS * NB - 1) / (NS * NB);   // batches of the longest stream
+  // Loads are unconditional (past the stream's end they read the item's first entry, which always exists,
+  // and the value is discarded where it is used), so that nothing waits for them before they are used.
+  uint2 cn;
+  float2 vn;
+  auto fetch = [&](int b) {
+    const int j = lo + b * NB + jl;
+    const int jj = j < hi ? j : it.y;
+    vn = vis[vidx ? vidx[jj] : jj];
+    cn = coord[jj];
+  };
+  fetch(0);                                 // in flight while the pool is cleared
+  {
+    const int n4 = (base[NS] * PR + 3) / 4;   // every stream's rows
+    float4* c0 = reinterpret_cast<float4*>(cp);
+    float4* c1 = reinterpret_cast<float4*>(cp + PL);
+    for (int e = tid; e < n4; e += 64 * NWV) {
+      c0[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      c1[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  __syncthreads();
+  const int nT = 1 << (log2K - log2T);
+  const int tloc = it.x & ((1 << (2 * (log2K - log2T))) - 1);
+  const int a0 = (tloc / nT) * T, b0 = (tloc % nT) * T;
+  const float scale = scales ? scales[item_block[itx]] : 1.f;
+  const int F = 32 - log2K;
+  const uint32_t fmask = (F == 32) ? 0xffffffffu : ((1u << F) - 1u);
+  const float fs = ldexpf(1.0f, 1 - F);
+  int myfirst = 0, mybase = 0;             // this lane's stream (static indices: no indexed registers)
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    if (k == s) myfirst = first[k];
+    if (k < s) mybase = base[k + 1];
+  }
+  // phase B roles: block (r, tb, ub) of this half, row/column i4
+  const int bl = (lane >> 2) & 7, r = bl >> 2, tb = (bl >> 1) & 1, ub = bl & 1, i4 = lane & 3;
+  const float* arow = &stg[wave][h][r * J + tb * 4 + i4][0];
+  const float* brow = &stg[wave][h][2 * J + ub * 4 + i4][0];
+  float* const mycp = cp + r * PL + (mybase + tb * 4) * PR + ub * 4 + i4;
+  float* wcol = &stg[wave][h][0][jl];     // phase A: this lane's column
+  // The current run of this lane's stream: this lane's first copy address under it, its sums so far (matrix
+  // accumulators) and the copy's values under it, read when the run started.  A stream starts at cell
+  // offset 0 with zero sums and zero values read, which is what the cleared copy holds there, so its first
+  // write-back needs no special case.
+  float* cur = mycp;
+  int curv = 0;                             // cell offset of the current run (first-axis lanes of phase A)
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  float old[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < nbatch; ++b) {
+    const bool valid = lo + b * NB + jl < hi;
+    // past the stream's end: weight 0 (coordinate 0 keeps the weights finite)
+    const uint2 c = valid ? cn : make_uint2(0u, 0u);
+    const float2 v = valid ? vn : make_float2(0.f, 0.f);
+    fetch(b + 1);                           // the next batch's loads stay in flight through this one
+    // this lane's axis: J weights; the first axis's lanes scale them by the visibility (a, real and imaginary
+    // rows), the second axis's lanes store them as they are (b)
+    float w[J];
+    kb_weights<J>(kc, float((ax ? c.y : c.x) & fmask) * fs - 1.0f, w);
+    const int cell = valid ? (int(c.x >> F) - a0 - myfirst) * PR + (int(c.y >> F) - b0) : -1;
+    if (!ax) {
+      const float vr = v.x * scale, vi = v.y * scale;
+#pragma unroll
+      for (int t = 0; t < J; ++t) {
+        wcol[t * SP] = w[t] * vr;
+        wcol[(J + t) * SP] = w[t] * vi;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < J; ++t) wcol[(2 * J + t) * SP] = w[t];
+    }
+    const int left = __shfl(cell, lane - 1);
+    const int prev = jl == 0 ? curv : left;
+    // bit 32 h + j: stream h starts a run at its visibility j (the first axis's lanes decide)
+    const uint64_t starts = __ballot(!ax && valid && cell != prev);
+    const uint32_t any = uint32_t(starts) | uint32_t(starts >> 32);
+    // the cell of the stream's last visibility of this batch, for the next batch's first comparison (when
+    // that visibility is past the stream's end, so are all later ones, and the value is never used)
+    curv = __shfl(cell, (lane & 32) + NB - 1);
+    wave_lds_order();                       // staged rows visible to every lane
+    // every operand of the batch in registers (128-bit reads), so that the steps never wait for LDS except for
+    // the values under a new run
+    float av[NB], bv[NB];
+#pragma unroll
+    for (int g = 0; g < NB / 4; ++g) {
+      const float4 a4 = *(const float4*)(arow + 4 * g), b4 = *(const float4*)(brow + 4 * g);
+      av[4 * g] = a4.x, av[4 * g + 1] = a4.y, av[4 * g + 2] = a4.z, av[4 * g + 3] = a4.w;
+      bv[4 * g] = b4.x, bv[4 * g + 1] = b4.y, bv[4 * g + 2] = b4.z, bv[4 * g + 3] = b4.w;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      // (most steps continue a run: the write-back is laid out away from the straight-line path, so that
+      // those steps do not branch)
+      if (__builtin_expect((any >> j) & 1, 0)) {   // a stream of this wave starts a run here
+        const uint64_t sel = (((starts >> j) & 1) ? 0x00000000ffffffffull : 0ull) |
+                             (((starts >> (32 + j)) & 1) ? 0xffffffff00000000ull : 0ull);
+        if (__builtin_amdgcn_inverse_ballot_w64(sel)) {   // the lanes of the streams that start a run
+          // write the finished run back (its sums plus the values read when it started), then read the
+          // values under the new run and restart from zero
+#pragma unroll
+          for (int q = 0; q < 4; ++q) cur[q * PR] = old[q] + acc[q];
+          wave_lds_order();                 // the new run's window may overlap: read after the write
+          cur = mycp + (h ? __builtin_amdgcn_readlane(cell, 32 + j) : __builtin_amdgcn_readlane(cell, j));
+#pragma unroll
+          for (int q = 0; q < 4; ++q) old[q] = cur[q * PR];
+          acc = f4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      acc = __builtin_amdgcn_mfma_f32_4x4x1f32(av[j], bv[j], acc, 0, 0, 0);
+    }
+    wave_lds_order();                       // staged rows consumed before the next phase A
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cur[q * PR] = old[q] + acc[q];
+  __syncthreads();
+  float2* dst = patches + (size_t)it.w * PP;
+  for (int e = tid; e < PP; e += 64 * NWV) {
+    const int pr = e / P, pc = e - pr * P;
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {        // the streams whose rows cover this one, in stream order
+      const int d = pr - first[k];
+      if (d >= 0 && d < base[k + 1] - base[k]) {
+        const int o = (base[k] + d) * PR + pc;
+        re += cp[o];
+        im += cp[PL + o];
+      }
+    }
+    dst[e] = make_float2(re, im);
+  }
+}
+
 // Each grid cell = sum over the tiles whose padded patch covers it (3 x 3 neighbourhood, fixed order)
 // of that tile's item patches (slot order).  One work-group per group of 256 cells of a tile.
 template <int J, int T>
@@ -516,8 +715,16 @@ sh_status launch_grid_T(sh_op op, const float2* vis, const uint32_t* vidx, const
                         hipStream_t st) {
   {
     sh::ProfScope ps("grid", st);
-    hipLaunchKernelGGL((grid_kernel<J, T>), dim3((unsigned)op->n_items), dim3(256), 0, st, op->coord.ptr, vis, vidx,
-                       op->items.ptr, op->item_block.ptr, op->patches.ptr, op->log2K, op->log2T, scales, op->kb, bmask);
+    if constexpr (J == 8) {
+      constexpr int NWV = grid_mfma_waves(T);
+      hipLaunchKernelGGL((grid_mfma_kernel<T, NWV>), dim3((unsigned)op->n_items), dim3(64 * NWV), 0, st,
+                         op->coord.ptr, vis, vidx, op->items.ptr, op->item_block.ptr, op->item_rows.ptr,
+                         op->patches.ptr, op->log2K, op->log2T, scales, op->kb, bmask);
+    } else {
+      hipLaunchKernelGGL((grid_kernel<J, T>), dim3((unsigned)op->n_items), dim3(256), 0, st, op->coord.ptr, vis,
+                         vidx, op->items.ptr, op->item_block.ptr, op->patches.ptr, op->log2K, op->log2T, scales,
+                         op->kb, bmask);
+    }
     SH_LAUNCHED();
   }
   sh::ProfScope ps("fold", st);
@@ -658,6 +865,28 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
         items.push_back(make_int4(all[q].tile, all[q].start, all[q].count, slot_of[q]));
         item_block.push_back(all[q].block);
       }
+  // J = 8 gridder: the cell rows of each stream of each item (the kernel splits an item into 2 W streams of
+  // near-equal length, W its waves per work-group, exactly as below)
+  std::vector<int4> item_rows;
+  if (op->J == 8) {
+    const int ns = 2 * grid_mfma_waves(op->T);
+    item_rows.resize(items.size());
+    for (size_t q = 0; q < items.size(); ++q) {
+      const int64_t a = items[q].y, c = items[q].z;
+      uint32_t f[2] = {0u, 0u}, r[2] = {0u, 0u};
+      for (int k = 0; k < ns; ++k) {
+        const int64_t lo = a + c * k / ns, hi = a + c * (k + 1) / ns;
+        uint32_t first = 0, rows = 1;      // an empty stream still owns one row
+        if (hi > lo) {
+          first = (key[perm[lo]] >> log2T) & uint32_t(op->T - 1);
+          rows = ((key[perm[hi - 1]] >> log2T) & uint32_t(op->T - 1)) - first + 1;
+        }
+        f[k / 4] |= first << (8 * (k % 4));
+        r[k / 4] |= rows << (8 * (k % 4));
+      }
+      item_rows[q] = make_int4((int)f[0], (int)f[1], (int)r[0], (int)r[1]);
+    }
+  }
   op->n_items = (int64_t)items.size();
   op->n_sparse = 0;
   for (auto& a : all) op->n_sparse += a.dense == 0;
@@ -677,6 +906,7 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   SH_TRY(op->perm.upload(perm));
   SH_TRY(op->items.upload(items));
   SH_TRY(op->item_block.upload(item_block));
+  if (!item_rows.empty()) SH_TRY(op->item_rows.upload(item_rows));
   SH_TRY(op->tile_items.upload(tile_items));
   SH_TRY(op->chunks.upload(chunks));
   SH_TRY(op->chunk_first_d.upload(op->chunk_first));

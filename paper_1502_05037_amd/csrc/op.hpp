@@ -28,6 +28,9 @@ struct sh_op_s {
   sh::DevBuf<int4> items;          // work items (tile, start, count, patch slot): sparse first, then dense
   // (start/count index internal order)
   sh::DevBuf<int32_t> item_block;  // data block of each work item (order of `items`)
+  // J = 8 gridder: per work item, the first cell row (tile-relative; bytes of x, y) and the number of cell
+  // rows (bytes of z, w) of each of the streams the item is split into
+  sh::DevBuf<int4> item_rows;
   sh::DevBuf<int32_t> tile_items;  // CSR over global tiles (problem * nT^2 + tile): patch slots of each tile
   int64_t n_items = 0, n_sparse = 0;
   int max_items_per_tile = 0;

@@ -66,8 +66,9 @@ def test_phi_parity(sh, n, m, J, R, cov):
     assert helpers.rel(xa, ref.adj(v)) <= TOL
 
 
-def test_internal_order_and_permutation(sh):
-    n, m, J, R = 64, 5000, 6, 4
+@pytest.mark.parametrize("J", [6, 8])
+def test_internal_order_and_permutation(sh, J):
+    n, m, R = 64, 5000, 4
     uv = synth.sort_by_radius(synth.uv_radial(m, synth.rng(12, 0, synth.UV)))
     off = synth.offsets(synth.block_sizes(m, R, synth.rng(12, 0, synth.BLOCKS)))
     x, v = _inputs(n, m, 3)
@@ -154,8 +155,9 @@ def test_op_norm_matches_oracle(sh):
     assert nu == pytest.approx(ref, rel=1e-5)
 
 
-def test_determinism_two_runs(sh):
-    n, m, J = 64, 8000, 6
+@pytest.mark.parametrize("J", [6, 8])
+def test_determinism_two_runs(sh, J):
+    n, m = 64, 8000
     uv = synth.uv_radial(m, synth.rng(16, 0, synth.UV))
     x, v = _inputs(n, m, 6)
     a = _fwd_adj(sh, uv, n, J, [0, m], x, v)
@@ -184,3 +186,54 @@ def test_phi_parity_tuned_tiling(sh, tile, chunk):
         sh.op_destroy(op)
     assert helpers.rel(vis.cpu().numpy(), ref.fwd(x)) <= TOL
     assert helpers.rel(xa.cpu().numpy(), ref.adj(v)) <= TOL
+
+
+def _cells_uv(K, cells, frac):
+    """uv of visibilities at grid cells: kappa = cell + fraction in [0, K), uv = 2 pi kappa / K in [0, 2 pi)."""
+    kappa = np.asarray(cells, dtype=np.float64) + np.asarray(frac)
+    return kappa * (2.0 * np.pi / K)
+
+
+@pytest.mark.parametrize("tile,chunk", [(0, 0), (8, 0), (32, 0), (16, 64)])
+def test_gridding_j8_runs_streams_batches(sh, tile, chunk):
+    """Gridding with J = 8, whose work items split into independent streams that accumulate runs of one
+    cell and add each finished run into their own patch copy: one cell holding 5000 visibilities (a run
+    longer than a batch, crossing every stream of its items), a tile with one visibility per cell (runs of
+    one), a tile with three visibilities (fewer than a work item has streams), a tile with 257 (one past a
+    full batch of every stream), and Gaussian-density visibilities elsewhere (tiles of 16 cells for the
+    description; each tiling and a small chunk are run).  The adjoint of random data against the oracle
+    pixel by pixel, and the forward map."""
+    n, J = 64, 8
+    K = 2 * n
+    g = synth.rng(18, tile + chunk, synth.UV)
+    one = _cells_uv(K, np.tile([[10, 20]], (5000, 1)), g.random((5000, 2)))
+    grid16 = np.stack(np.meshgrid(np.arange(16), np.arange(16), indexing="ij"), -1).reshape(-1, 2)
+    singles = _cells_uv(K, grid16 + [32, 16], g.random((256, 2)))             # every cell of tile (2, 1)
+    three = _cells_uv(K, [[33, 34], [33, 35], [46, 40]], g.random((3, 2)))   # tile (2, 2)
+    many = _cells_uv(K, [16, 32] + g.integers(0, 16, (257, 2)), g.random((257, 2)))   # tile (1, 2)
+    rest = synth.uv_gaussian(4000, g)
+    rc = np.floor(np.mod(rest, 2 * np.pi) * (K / (2 * np.pi))).astype(int) // 16
+    keep = ~(((rc[:, 0] == 2) & (rc[:, 1] == 1)) | ((rc[:, 0] == 2) & (rc[:, 1] == 2)) | ((rc[:, 0] == 1) & (rc[:, 1] == 2)))
+    uv = np.concatenate([one, singles, three, many, rest[keep]])
+    uv = np.where(uv >= np.pi, uv - 2 * np.pi, uv)
+    m = len(uv)
+    off = [0, 2600, 5600, m]                                                # blocks split the one-cell run
+    x, v = _inputs(n, m, 40 + tile)
+    ref = measurement.NUFFT(uv, n, J)
+    op = sh.op_create_tuned(uv, n, 2, J, off, tile=tile, chunk=chunk)
+    try:
+        vis = torch.empty(m, dtype=torch.complex64, device="cuda")
+        sh.phi_fwd(op, _dev(x, torch.float32), vis)
+        xa = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        sh.phi_adj(op, _dev(v, torch.complex64), xa)
+        torch.cuda.synchronize()
+        q = sh.op_query(op)
+    finally:
+        sh.op_destroy(op)
+    got, want = xa.cpu().numpy().astype(np.float64), ref.adj(v)
+    pix = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    print(f"J=8 gridding tile {q['tile']} chunk {chunk}: {q['n_items']} items, adjoint error {helpers.rel(got, want):.2e}, "
+          f"largest pixel error / largest pixel {pix:.2e}", flush=True)
+    assert helpers.rel(got, want) <= TOL
+    assert pix <= TOL
+    assert helpers.rel(vis.cpu().numpy(), ref.fwd(x)) <= TOL

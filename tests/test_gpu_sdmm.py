@@ -197,11 +197,12 @@ def test_dual_warm_start_parity(sh):
     assert helpers.rel(x_plain_ref, x_ref) > 10 * err
 
 
-def test_block_subset_iterations_fixed_schedule_parity(sh):
+@pytest.mark.parametrize("J", [6, 8])
+def test_block_subset_iterations_fixed_schedule_parity(sh, J):
     """Block-subset SDMM (a random half of the six data blocks per iteration, drawn by the same counter-based
     generator on both sides): two reweighted passes of a fixed schedule match the oracle's, and differ from
     the full iteration."""
-    pb = helpers.build(2, 32, 2400, 6, 6, prob=3)
+    pb = helpers.build(2, 32, 2400, 6, J, prob=3)
     psi, nu, gamma, a = _oracle_setup(pb)
     kw = dict(gamma=gamma, nu=nu, max_iter=40, cg_iters=2, passes=2)
     p = sdmm.Params(block_weights=a, block_fraction=0.5, block_seed=11, **kw)
