@@ -14,7 +14,7 @@
 // contiguous), a 3x3 convolution is im2col (K = 9 Cin, ordered (ky, kx, ci), zero-padded to a
 // multiple of 16; gathered inside the product's staging, never stored) times the weight matrix, and the
 // forward and input-gradient products use one kernel of the "NT" form
-// C[m][n] = sum_k A[m][k] B[n][k] with both operands contiguous along k (v_mfma_f32_16x16x16_bf16,
+// C[m][n] = sum_k A[m][k] B[n][k] with both operands contiguous along k (v_mfma_f32_16x16x32_bf16,
 // 64 x 64 tiles per work-group of four waves, or 128 x 32 for products with at most 32 columns so that
 // no half of the tile is padding, k staged through LDS 64 at a time with the next slab prefetched into
 // registers, optional split-K
@@ -29,7 +29,7 @@
 
 #include "op.hpp"
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -147,17 +147,17 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
     __syncthreads();
     if (k0 + GBK < ke) load(k0 + GBK);   // in flight during the products below
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 16) {
-      const int ko = kk + 4 * (lane >> 4);
-      bf16x4 a[2], b[2];
+    for (int kk = 0; kk < GBK; kk += 32) {
+      const int ko = kk + 8 * (lane >> 4);
+      bf16x8 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = *(const bf16x4*)&As[wm * 32 + i * 16 + (lane & 15)][ko];
+      for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[wm * 32 + i * 16 + (lane & 15)][ko];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = *(const bf16x4*)&Bs[wn * 32 + j * 16 + (lane & 15)][ko];
+      for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)&Bs[wn * 32 + j * 16 + (lane & 15)][ko];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -284,17 +284,17 @@ __global__ __launch_bounds__(256) void gemm_tn(const uint16_t* __restrict__ A, i
     __syncthreads();
     if (k0 + GBK < ke) load(k0 + GBK);   // in flight during the products below
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 16) {
-      const int ko = kk + 4 * (lane >> 4);
-      bf16x4 a[2], b[2];
+    for (int kk = 0; kk < GBK; kk += 32) {
+      const int ko = kk + 8 * (lane >> 4);
+      bf16x8 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = *(const bf16x4*)&As[wm * 32 + i * 16 + (lane & 15)][ko];
+      for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[wm * 32 + i * 16 + (lane & 15)][ko];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = *(const bf16x4*)&Bs[wn * 32 + j * 16 + (lane & 15)][ko];
+      for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)&Bs[wn * 32 + j * 16 + (lane & 15)][ko];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
