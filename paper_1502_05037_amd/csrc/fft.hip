@@ -64,13 +64,6 @@ __device__ __forceinline__ void dft(float2* v) {
   }
 }
 
-// LDS layout of a sequence: element i at pad(i) = i + i / 8 (one spare slot after every eight), and
-// sequences seq_stride(L) = L + L / 8 + 1 elements apart.  The Stockham writes of the first two radix-8 stages
-// (stride 8, and runs of 8 jumping by 64) and the column-wise loads and stores (stride of one sequence) then
-// spread each group of 16 lanes over all the banks instead of two.
-__device__ __forceinline__ int pad(int i) { return i + (i >> 3); }
-__host__ __device__ constexpr int seq_stride(int L) { return L + L / 8 + 1; }
-
 // One Stockham stage of radix R over a length-L sequence in LDS (all threads of the sequence).
 template <int L, int R, bool INV>
 __device__ __forceinline__ void stage(float2* buf, const float2* __restrict__ tw, int Ns, int lt, int tpt) {
@@ -81,7 +74,7 @@ __device__ __forceinline__ void stage(float2* buf, const float2* __restrict__ tw
   for (int q = 0; q < PER; ++q) {
     const int j = lt + q * tpt;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[q][r] = buf[pad(j + r * NB)];
+    for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * NB];
   }
   __syncthreads();
 #pragma unroll
@@ -98,7 +91,7 @@ __device__ __forceinline__ void stage(float2* buf, const float2* __restrict__ tw
     dft<R, INV>(v[q]);
     const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[pad(base + r * Ns)] = v[q][r];
+    for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q][r];
   }
   __syncthreads();
 }
@@ -127,7 +120,6 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
   extern __shared__ float2 lds[];
   constexpr bool INV = (MODE == COLS_ADJ || MODE == ROWS_ADJ || MODE == ROWS_ADJ_H);
   constexpr int NT = B * L / 8;
-  constexpr int SL = seq_stride(L);
   const int tid = threadIdx.x;
   const int K = L;                    // grid side
   // `per` sequences per problem (n rows or K columns); B divides per, so a block stays in one problem
@@ -160,27 +152,27 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
   // ---- load ----
   if constexpr (MODE == ROWS_FWD) {
     const float* x = (const float*)in;
-    for (int e = tid; e < B * SL; e += NT) lds[e] = make_float2(0.f, 0.f);
+    for (int e = tid; e < B * L; e += NT) lds[e] = make_float2(0.f, 0.f);
     __syncthreads();
     for (int e = tid; e < B * n; e += NT) {
       const int b = e / n, c = e - b * n;
       const int r = seq0 + b;
       const float val = x[(size_t)r * n + c] * deapod[r] * deapod[c];
-      lds[b * SL + pad((c - half) & (L - 1))] = make_float2(val, 0.f);
+      lds[b * L + ((c - half) & (L - 1))] = make_float2(val, 0.f);
     }
   } else if constexpr (MODE == COLS_FWD || MODE == COLS_TOEP) {
     const float2* h = (const float2*)in;
-    for (int e = tid; e < B * SL; e += NT) lds[e] = make_float2(0.f, 0.f);
+    for (int e = tid; e < B * L; e += NT) lds[e] = make_float2(0.f, 0.f);
     __syncthreads();
     for (int e = tid; e < B * n; e += NT) {
       const int r = e / B, b = e - r * B;
-      lds[b * SL + pad((r - half) & (L - 1))] = h[(size_t)r * K + seq0 + b];
+      lds[b * L + ((r - half) & (L - 1))] = h[(size_t)r * K + seq0 + b];
     }
   } else if constexpr (MODE == COLS_ADJ || MODE == FULL_COLS) {
     const float2* g = (const float2*)in;
     for (int e = tid; e < B * L; e += NT) {
       const int r = e / B, b = e - r * B;
-      lds[b * SL + pad(r)] = g[(size_t)r * K + seq0 + b];
+      lds[b * L + r] = g[(size_t)r * K + seq0 + b];
     }
   } else if constexpr (MODE == ROWS_ADJ_H) {
     const float2* h = (const float2*)in;
@@ -188,34 +180,33 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
       const int b = e / L, c = e - b * L;
       const float2* row = h + (size_t)(seq0 + b) * K;
       if (c <= L / 2) {
-        lds[b * SL + pad(c)] = row[c];
+        lds[e] = row[c];
       } else {
         const float2 v = row[L - c];
-        lds[b * SL + pad(c)] = make_float2(v.x, -v.y);
+        lds[e] = make_float2(v.x, -v.y);
       }
     }
   } else {  // ROWS_ADJ, FULL_ROWS
     const float2* h = (const float2*)in;
     for (int e = tid; e < B * L; e += NT) {
       const int b = e / L, c = e - b * L;
-      lds[b * SL + pad(c)] = h[(size_t)(seq0 + b) * K + c];
+      lds[e] = h[(size_t)(seq0 + b) * K + c];
     }
   }
   __syncthreads();
 
   // ---- transform: thread tid works on sequence tid / (L/8) ----
   const int sq = tid / (L / 8), lt = tid % (L / 8);
-  fft_lds<L, INV>(lds + sq * SL, tw, lt);
+  fft_lds<L, INV>(lds + sq * L, tw, lt);
   if constexpr (MODE == COLS_TOEP) {
-    // element k of sequence b *= Ht[(seq0 + b) K + k]: column seq0 + b of the spectrum, read contiguously
+    // lds[b L + k] *= Ht[(seq0 + b) K + k]: column seq0 + b of the spectrum, read contiguously
     for (int e = tid; e < B * L; e += NT) {
       const float hv = deapod[(size_t)seq0 * K + e];
-      const int b = e / L, k = e - b * L;
-      const float2 v = lds[b * SL + pad(k)];
-      lds[b * SL + pad(k)] = make_float2(v.x * hv, v.y * hv);
+      const float2 v = lds[e];
+      lds[e] = make_float2(v.x * hv, v.y * hv);
     }
     __syncthreads();
-    fft_lds<L, true>(lds + sq * SL, tw, lt);
+    fft_lds<L, true>(lds + sq * L, tw, lt);
   }
 
   // ---- store ----
@@ -223,32 +214,32 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
     float2* h = (float2*)out;
     for (int e = tid; e < B * L; e += NT) {
       const int b = e / L, k = e - b * L;
-      h[(size_t)(seq0 + b) * K + k] = lds[b * SL + pad(k)];
+      h[(size_t)(seq0 + b) * K + k] = lds[e];
     }
   } else if constexpr (MODE == COLS_FWD || MODE == FULL_COLS) {
     float2* g = (float2*)out;
     for (int e = tid; e < B * L; e += NT) {
       const int k = e / B, b = e - k * B;
-      g[(size_t)k * K + seq0 + b] = lds[b * SL + pad(k)];
+      g[(size_t)k * K + seq0 + b] = lds[b * L + k];
     }
   } else if constexpr (MODE == FULL_ROWS) {
     float2* h = (float2*)out;
     for (int e = tid; e < B * L; e += NT) {
       const int b = e / L, k = e - b * L;
-      h[(size_t)(seq0 + b) * K + k] = lds[b * SL + pad(k)];
+      h[(size_t)(seq0 + b) * K + k] = lds[e];
     }
   } else if constexpr (MODE == COLS_ADJ || MODE == COLS_TOEP) {
     float2* h = (float2*)out;
     for (int e = tid; e < B * n; e += NT) {
       const int r = e / B, b = e - r * B;
-      h[(size_t)r * K + seq0 + b] = lds[b * SL + pad((r - half) & (L - 1))];
+      h[(size_t)r * K + seq0 + b] = lds[b * L + ((r - half) & (L - 1))];
     }
   } else {  // ROWS_ADJ, ROWS_ADJ_H
     float* x = (float*)out;
     for (int e = tid; e < B * n; e += NT) {
       const int b = e / n, c = e - b * n;
       const int r = seq0 + b;
-      x[(size_t)r * n + c] = lds[b * SL + pad((c - half) & (L - 1))].x * deapod[r] * deapod[c];
+      x[(size_t)r * n + c] = lds[b * L + ((c - half) & (L - 1))].x * deapod[r] * deapod[c];
     }
   }
 }
@@ -269,7 +260,7 @@ sh_status launch_len(int per, int P, const void* in, void* out, const float2* tw
   while (b > 1 && (b / 2) * L / 8 >= 64 &&
          (groups(b) < 512 || (groups(b) < 2048 && (!STRIDED || b / 2 >= 4))))
     b >>= 1;
-  const size_t lds = size_t(b) * seq_stride(L) * sizeof(float2);
+  const size_t lds = size_t(b) * L * sizeof(float2);
 #define SH_FFT_CASE(BB)                                                                                  \
   if (b == BB) {                                                                                         \
     hipLaunchKernelGGL((fft_pass<L, BB, MODE>), dim3(P * (per / BB)), dim3(BB * L / 8), lds, st, in, out, \
