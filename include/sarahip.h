@@ -51,6 +51,11 @@ typedef struct sh_psi_s* sh_psi;  /* SARA dictionary: filter taps, level scratch
 
 /* Message for the last non-OK status on this thread (never NULL). */
 const char* sh_last_error(void);
+/* Device memory the library holds (live_bytes; a caller's workspaces are not counted) and the cap on it
+ * (cap_bytes: the environment variable SH_MAX_DEVICE_BYTES, a positive byte count, read at every allocation;
+ * -1 = none).  An allocation that would take the library past the cap fails with SH_ENOMEM.  Either
+ * pointer may be NULL (not both). */
+sh_status sh_device_bytes(int64_t* live_bytes, int64_t* cap_bytes);
 
 /* Library version string. */
 const char* sh_version(void);
@@ -73,6 +78,12 @@ sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversampl
  * side alpha*n must hold at least 3 tiles.  Results agree with sh_op_create to rounding. */
 sh_status sh_op_create_tuned(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
                              const int64_t* block_offsets, int32_t R, int32_t tile, int32_t chunk, sh_op* out);
+/* sh_op_create_tuned with the plan's uploads on the caller's stream (hipStream_t, NULL = the null stream):
+ * each upload is enqueued on it and waited for before the call returns, so the host arrays may go at once.
+ * Synchronous with respect to that stream.  Errors as sh_op_create_tuned. */
+sh_status sh_op_create_stream(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
+                              const int64_t* block_offsets, int32_t R, int32_t tile, int32_t chunk, void* stream,
+                              sh_op* out);
 sh_status sh_op_destroy(sh_op op);
 
 /* One plan for P independent problems of the same image side, oversampling and kernel width
@@ -381,6 +392,18 @@ sh_status sh_sdmm_result(sh_sdmm s, float* x_out, double* block_resid, double* r
  * iteration.  Synchronous.  These measure convergence of (3): at a solution every split image equals its
  * proximal point and the duals balance (SDMM paragraph). */
 sh_status sh_sdmm_kkt(sh_sdmm s, double* kkt_primal, double* kkt_dual, double* objective, void* stream);
+/* Checkpoint and resume of a session (the SDMM paragraph's iteration carried over a restart): the state one
+ * iteration hands to the next — x, the split and dual vectors of the l1, data and positivity terms, the data
+ * images and block residuals, the weights, the coefficients alpha (synthesis prior) and the running image and
+ * iteration counter (block-subset iterations) — after a header with the session's sizes and options.
+ * sh_sdmm_state_bytes gives the size; export copies the state into host memory the caller owns (at least that
+ * many bytes) after the work already enqueued on `stream`; import overwrites a session's state with one
+ * exported from a session created with the same op, psi, data and parameters, after which sh_sdmm_iterate
+ * continues exactly as the exporting session would have (bitwise).  Both synchronise `stream`.
+ * Errors: SH_EINVAL (NULL, buffer too small, or for import: size, header, sizes or options that differ). */
+sh_status sh_sdmm_state_bytes(sh_sdmm s, size_t* bytes);
+sh_status sh_sdmm_state_export(sh_sdmm s, void* host, size_t bytes, void* stream);
+sh_status sh_sdmm_state_import(sh_sdmm s, const void* host, size_t bytes, void* stream);
 sh_status sh_sdmm_destroy(sh_sdmm s);
 
 /* ---------------------------------------------------------------------------

@@ -1,5 +1,7 @@
 // Library-wide C ABI pieces: error strings, version, kernel-timing events.
+#include <atomic>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -23,6 +25,35 @@ Arena*& arena_slot() {
   static thread_local Arena* a = nullptr;
   return a;
 }
+
+hipStream_t& upload_stream() {
+  static thread_local hipStream_t s = nullptr;
+  return s;
+}
+
+namespace {
+std::atomic<int64_t> g_dev_live{0};
+
+int64_t dev_cap() {   // SH_MAX_DEVICE_BYTES, read at every allocation so that it can change at run time
+  const char* e = std::getenv("SH_MAX_DEVICE_BYTES");
+  if (!e || !*e) return -1;
+  char* end = nullptr;
+  const long long v = std::strtoll(e, &end, 10);
+  return (end && *end == '\0' && v > 0) ? int64_t(v) : -1;
+}
+}  // namespace
+
+bool dev_reserve(size_t bytes) {
+  const int64_t cap = dev_cap();
+  const int64_t after = g_dev_live.fetch_add(int64_t(bytes)) + int64_t(bytes);
+  if (cap > 0 && after > cap) {
+    g_dev_live.fetch_sub(int64_t(bytes));
+    return false;
+  }
+  return true;
+}
+
+void dev_unreserve(size_t bytes) { g_dev_live.fetch_sub(int64_t(bytes)); }
 
 namespace {
 const char* kNames[] = {"degrid", "grid", "fold", "fft_rows", "fft_cols", "dwt", "prox", "cg", "toeplitz"};
@@ -85,6 +116,13 @@ extern "C" {
 const char* sh_last_error(void) { return sh::last_error(); }
 
 const char* sh_version(void) { return "sarahip 0.1 (gfx950)"; }
+
+sh_status sh_device_bytes(int64_t* live_bytes, int64_t* cap_bytes) {
+  SH_REQUIRE(live_bytes || cap_bytes, "NULL argument");
+  if (live_bytes) *live_bytes = sh::g_dev_live.load();
+  if (cap_bytes) *cap_bytes = sh::dev_cap();
+  return SH_OK;
+}
 
 sh_status sh_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> g(sh::g_mu);

@@ -90,6 +90,20 @@ struct ArenaScope {
   ~ArenaScope() { arena_slot() = prev; }
 };
 
+// Library-owned device memory: every hipMalloc of DevBuf reserves its bytes here first, and the reservation
+// fails (SH_ENOMEM) when the environment variable SH_MAX_DEVICE_BYTES holds a positive byte count that the live
+// total would exceed.  Caller workspaces are not counted (the library does not allocate them).
+bool dev_reserve(size_t bytes);
+void dev_unreserve(size_t bytes);
+
+// The stream the uploads of this thread's DevBufs go to (NULL: hipMemcpy, synchronous on the null stream).
+hipStream_t& upload_stream();
+struct UploadStreamScope {
+  hipStream_t prev;
+  explicit UploadStreamScope(hipStream_t s) : prev(upload_stream()) { upload_stream() = s; }
+  ~UploadStreamScope() { upload_stream() = prev; }
+};
+
 // Owning device allocation: hipMalloc / hipFree, or a block of the thread's current arena.
 template <typename T>
 struct DevBuf {
@@ -119,10 +133,12 @@ struct DevBuf {
   ~DevBuf() { release(); }
   void release() {
     if (ptr) {
-      if (arena)
+      if (arena) {
         arena->give(ptr);
-      else
+      } else {
         (void)hipFree(ptr);
+        dev_unreserve(count * sizeof(T));
+      }
     }
     ptr = nullptr;
     count = 0;
@@ -140,14 +156,30 @@ struct DevBuf {
       }
       arena = a;
     } else {
-      SH_HIP(hipMalloc((void**)&ptr, n * sizeof(T)));
+      if (!dev_reserve(n * sizeof(T))) {
+        ::sh::set_error("allocating %zu device bytes would exceed SH_MAX_DEVICE_BYTES", n * sizeof(T));
+        return SH_ENOMEM;
+      }
+      const hipError_t e = hipMalloc((void**)&ptr, n * sizeof(T));
+      if (e != hipSuccess) {
+        ptr = nullptr;
+        dev_unreserve(n * sizeof(T));
+        ::sh::set_error("hipMalloc of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? SH_ENOMEM : SH_EDEVICE;
+      }
     }
     count = n;
     return SH_OK;
   }
   sh_status upload(const T* host, size_t n) {
     SH_TRY(alloc(n));
-    if (n) SH_HIP(hipMemcpy(ptr, host, n * sizeof(T), hipMemcpyHostToDevice));
+    if (!n) return SH_OK;
+    if (hipStream_t st = upload_stream()) {   // the caller's stream; the host array may go right after the call
+      SH_HIP(hipMemcpyAsync(ptr, host, n * sizeof(T), hipMemcpyHostToDevice, st));
+      SH_HIP(hipStreamSynchronize(st));
+    } else {
+      SH_HIP(hipMemcpy(ptr, host, n * sizeof(T), hipMemcpyHostToDevice));
+    }
     return SH_OK;
   }
   sh_status upload(const std::vector<T>& v) { return upload(v.data(), v.size()); }

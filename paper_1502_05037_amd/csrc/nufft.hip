@@ -1025,6 +1025,13 @@ sh_status sh_op_create(const double* uv, int64_t M, int32_t n, int32_t oversampl
   return sh_op_create_tuned(uv, M, n, oversample, kernel_width, block_offsets, R, 0, 0, out);
 }
 
+sh_status sh_op_create_stream(const double* uv, int64_t M, int32_t n, int32_t oversample, int32_t kernel_width,
+                              const int64_t* block_offsets, int32_t R, int32_t tile, int32_t chunk, void* stream,
+                              sh_op* out) {
+  sh::UploadStreamScope scope((hipStream_t)stream);
+  return sh_op_create_tuned(uv, M, n, oversample, kernel_width, block_offsets, R, tile, chunk, out);
+}
+
 sh_status sh_op_destroy(sh_op op) {
   delete op;
   return SH_OK;

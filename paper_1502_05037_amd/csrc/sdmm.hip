@@ -23,6 +23,7 @@
 // Block norms, dot products, the stopping test and the reweighting statistics are float64.
 #include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <cmath>
 #include <memory>
 
@@ -972,6 +973,47 @@ sh_status sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps, c
   return SH_OK;
 }
 
+// Checkpoint of a session: the state one iteration carries to the next, in this order: x, v_psi, z_psi,
+// v_phi, z_phi, v_+, z_+, the data images Phi_hat x (kept per block by block-subset iterations), the block
+// residuals, the weights W, then alpha (synthesis prior) and the running image Phi_hat^T v_phi and the
+// iteration counter (block-subset iterations).  The header records the sizes and options it was taken with.
+struct StateHeader {
+  uint64_t magic;
+  int64_t N, M, D, R, P;
+  int32_t stoch, synth, iters_total, version;
+};
+constexpr uint64_t kStateMagic = 0x31545053414d4453ull;   // "SDMASPT1"
+
+struct Part {
+  void* ptr;
+  size_t bytes;
+};
+
+template <typename T>
+Part part(sh::DevBuf<T>& b) { return Part{b.ptr, b.count * sizeof(T)}; }
+
+std::vector<Part> state_parts(sh_sdmm s) {
+  Work& w = s->w;
+  std::vector<Part> v = {part(w.x),    part(w.vpsi), part(w.zpsi), part(w.vphi),  part(w.zphi),
+                         part(w.vpos), part(w.zpos), part(w.sphi), part(w.resid), part(w.W)};
+  if (s->synth) v.push_back(part(w.alpha));
+  if (s->stoch) {
+    v.push_back(part(w.bphi));
+    v.push_back(part(w.ctr));
+  }
+  return v;
+}
+
+StateHeader state_header(sh_sdmm s) {
+  return StateHeader{kStateMagic, s->N, s->M, s->D, s->R, s->P, s->stoch ? 1 : 0, s->synth ? 1 : 0, s->iters_total, 1};
+}
+
+size_t state_bytes(sh_sdmm s) {
+  size_t n = sizeof(StateHeader);
+  for (const Part& q : state_parts(s)) n += q.bytes;
+  return n;
+}
+
 sh_status check_ws(sh_op op, sh_psi psi, const sh_sdmm_params* params, void* workspace, size_t bytes) {
   SH_REQUIRE(op && psi && params && workspace, "NULL argument");
   SH_REQUIRE(reinterpret_cast<uintptr_t>(workspace) % sh::Arena::kAlign == 0, "workspace must be %zu-byte aligned",
@@ -1036,6 +1078,53 @@ sh_status sh_sdmm_kkt(sh_sdmm s, double* kkt_primal, double* kkt_dual, double* o
     if (kkt_dual) kkt_dual[p] = du[p];
     if (objective) objective[p] = ob[p];
   }
+  return SH_OK;
+}
+
+sh_status sh_sdmm_state_bytes(sh_sdmm s, size_t* bytes) {
+  SH_REQUIRE(s && bytes, "NULL argument");
+  *bytes = state_bytes(s);
+  return SH_OK;
+}
+
+sh_status sh_sdmm_state_export(sh_sdmm s, void* host, size_t bytes, void* stream) {
+  SH_REQUIRE(s && host, "NULL argument");
+  const size_t need = state_bytes(s);
+  SH_REQUIRE(bytes >= need, "state buffer of %zu bytes is smaller than the %zu needed", bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  const StateHeader hd = state_header(s);
+  char* p = static_cast<char*>(host);
+  std::memcpy(p, &hd, sizeof hd);
+  size_t off = sizeof hd;
+  for (const Part& q : state_parts(s)) {
+    SH_HIP(hipMemcpyAsync(p + off, q.ptr, q.bytes, hipMemcpyDeviceToHost, st));
+    off += q.bytes;
+  }
+  SH_HIP(hipStreamSynchronize(st));
+  return SH_OK;
+}
+
+sh_status sh_sdmm_state_import(sh_sdmm s, const void* host, size_t bytes, void* stream) {
+  SH_REQUIRE(s && host, "NULL argument");
+  const size_t need = state_bytes(s);
+  SH_REQUIRE(bytes == need, "state of %zu bytes where this session takes %zu", bytes, need);
+  StateHeader hd;
+  std::memcpy(&hd, host, sizeof hd);
+  const StateHeader mine = state_header(s);
+  SH_REQUIRE(hd.magic == kStateMagic && hd.version == mine.version, "not a session state");
+  SH_REQUIRE(hd.N == mine.N && hd.M == mine.M && hd.D == mine.D && hd.R == mine.R && hd.P == mine.P &&
+                 hd.stoch == mine.stoch && hd.synth == mine.synth,
+             "state taken from a session of other sizes or options");
+  SH_REQUIRE(hd.iters_total >= 0, "invalid iteration count in the state");
+  hipStream_t st = (hipStream_t)stream;
+  const char* p = static_cast<const char*>(host);
+  size_t off = sizeof hd;
+  for (const Part& q : state_parts(s)) {
+    SH_HIP(hipMemcpyAsync(q.ptr, p + off, q.bytes, hipMemcpyHostToDevice, st));
+    off += q.bytes;
+  }
+  SH_HIP(hipStreamSynchronize(st));
+  s->iters_total = hd.iters_total;
   return SH_OK;
 }
 

@@ -125,6 +125,11 @@ _SIGS = {
     "sh_sdmm_iterate": (C.c_int, [_vp, _i32, _vp]),
     "sh_sdmm_result": (C.c_int, [_vp, _vp, _P64, _P64, _vp]),
     "sh_sdmm_kkt": (C.c_int, [_vp, _P64, _P64, _P64, _vp]),
+    "sh_sdmm_state_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
+    "sh_sdmm_state_export": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "sh_sdmm_state_import": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "sh_op_create_stream": (C.c_int, [_P64, _i64, _i32, _i32, _i32, _PI64, _i32, _i32, _i32, _vp, C.POINTER(_vp)]),
+    "sh_device_bytes": (C.c_int, [_PI64, _PI64]),
     "sh_sdmm_destroy": (C.c_int, [_vp]),
     "sh_unet_create": (C.c_int, [_i32, _i32, C.POINTER(_vp)]),
     "sh_unet_destroy": (C.c_int, [_vp]),
@@ -200,6 +205,27 @@ def op_create_tuned(uv: np.ndarray, n: int, oversample: int, kernel_width: int, 
     _check(lib.sh_op_create_tuned(uv.ctypes.data_as(_P64), uv.shape[0], n, oversample, kernel_width,
                                   off.ctypes.data_as(_PI64), len(off) - 1, tile, chunk, C.byref(h)), "op_create_tuned")
     return h.value
+
+
+def op_create_stream(uv: np.ndarray, n: int, oversample: int, kernel_width: int, block_offsets, tile: int = 0,
+                     chunk: int = 0, stream=None) -> int:
+    """op_create_tuned with the plan's uploads on `stream` (default: torch's current stream)."""
+    uv = _f64(uv)
+    if uv.ndim != 2 or uv.shape[1] != 2:
+        raise ValueError("uv must be (M, 2)")
+    off = np.ascontiguousarray(block_offsets, dtype=np.int64)
+    h = _vp()
+    _check(lib.sh_op_create_stream(uv.ctypes.data_as(_P64), uv.shape[0], n, oversample, kernel_width,
+                                   off.ctypes.data_as(_PI64), len(off) - 1, tile, chunk, _stream(stream), C.byref(h)),
+           "op_create_stream")
+    return h.value
+
+
+def device_bytes():
+    """(device bytes the library holds, the SH_MAX_DEVICE_BYTES cap or -1)."""
+    live, cap = C.c_int64(), C.c_int64()
+    _check(lib.sh_device_bytes(C.byref(live), C.byref(cap)), "device_bytes")
+    return live.value, cap.value
 
 
 def op_create_batched(uv: np.ndarray, M_p, n: int, oversample: int, kernel_width: int, block_offsets, R_p,
@@ -511,6 +537,21 @@ def sdmm_kkt(s: int, P: int = 1, stream=None):
     _check(lib.sh_sdmm_kkt(s, pr.ctypes.data_as(_P64), du.ctypes.data_as(_P64), ob.ctypes.data_as(_P64),
                            _stream(stream)), "sdmm_kkt")
     return (float(pr[0]), float(du[0]), float(ob[0])) if P == 1 else (pr, du, ob)
+
+
+def sdmm_state_export(s: int, stream=None) -> np.ndarray:
+    """The session's state (checkpoint) as a host byte array."""
+    nb_ = C.c_size_t()
+    _check(lib.sh_sdmm_state_bytes(s, C.byref(nb_)), "sdmm_state_bytes")
+    buf = np.empty(nb_.value, dtype=np.uint8)
+    _check(lib.sh_sdmm_state_export(s, buf.ctypes.data, nb_.value, _stream(stream)), "sdmm_state_export")
+    return buf
+
+
+def sdmm_state_import(s: int, state: np.ndarray, stream=None) -> None:
+    """Overwrites the session's state with one from sdmm_state_export of a like session."""
+    buf = np.ascontiguousarray(state, dtype=np.uint8)
+    _check(lib.sh_sdmm_state_import(s, buf.ctypes.data, buf.nbytes, _stream(stream)), "sdmm_state_import")
 
 
 def sdmm_destroy(s: int) -> None:
