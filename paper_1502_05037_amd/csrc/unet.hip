@@ -96,13 +96,26 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
       gx[r] = rem - gy[r] * g.W;
     }
   }
-  auto gather8 = [&](int r, int k) -> uint4 {   // A[m0 + lr + 64 r][k .. k+7] of the implicit im2col
-    if ((g.C & 7) == 0) {
-      if (k >= 9 * g.C) return make_uint4(0, 0, 0, 0);
-      const int tap = k / g.C, c = k - tap * g.C;
-      const int sy = gy[r] + tap / 3 - 1, sx = gx[r] + tap % 3 - 1;
+  // Channel counts that are multiples of 8: the tap and channel of this thread's k-values lc + 8 e of the next
+  // slab, advanced by GBK per slab (no integer division in the loop; C >= 8, so a slab moves at most GBK / C
+  // taps)
+  const bool fast = GATHER && (g.C & 7) == 0;
+  int ktap[2] = {0, 0}, kch[2] = {0, 0};
+  if (fast)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = kb + lc + 8 * e;
+      ktap[e] = k / g.C;
+      kch[e] = k - ktap[e] * g.C;
+    }
+  auto gather8 = [&](int r, int k, int e) -> uint4 {   // A[m0 + lr + 64 r][k .. k+7] of the implicit im2col
+    if (fast) {
+      const int tap = ktap[e];
+      if (tap >= 9) return make_uint4(0, 0, 0, 0);
+      const int ty = (tap * 11) >> 5, tx = tap - 3 * ty;   // tap / 3, tap % 3 for tap < 9
+      const int sy = gy[r] + ty - 1, sx = gx[r] + tx - 1;
       if (sy < 0 || sy >= g.H || sx < 0 || sx >= g.W) return make_uint4(0, 0, 0, 0);
-      return *(const uint4*)(g.x + ((int64_t)(gb[r] * g.H + sy) * g.W + sx) * g.ldx + c);
+      return *(const uint4*)(g.x + ((int64_t)(gb[r] * g.H + sy) * g.W + sx) * g.ldx + kch[e]);
     }
     uint16_t v[8];
 #pragma unroll
@@ -126,9 +139,18 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
       for (int e = 0; e < 2; ++e) {
         const int k = k0 + lc + 8 * e, m = m0 + lr + 64 * r;
         if constexpr (GATHER)
-          ra[r][e] = (m < M && k < ke) ? gather8(r, k) : make_uint4(0, 0, 0, 0);
+          ra[r][e] = (m < M && k < ke) ? gather8(r, k, e) : make_uint4(0, 0, 0, 0);
         else
           ra[r][e] = (m < M && k < ke) ? *(const uint4*)(A + (int64_t)m * lda + k) : make_uint4(0, 0, 0, 0);
+      }
+    if (fast)   // on to the next slab's k-values
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        kch[e] += GBK;
+        while (kch[e] >= g.C) {
+          kch[e] -= g.C;
+          ++ktap[e];
+        }
       }
 #pragma unroll
     for (int e = 0; e < BU; ++e) {
@@ -248,6 +270,22 @@ __global__ __launch_bounds__(256) void gemm_tn(const uint16_t* __restrict__ A, i
                       v[6] | (uint32_t(v[7]) << 16));
   };
   uint4 ra[2], rb[2];
+  // gather mode: this thread's im2col columns n0 + cc .. + 7 are fixed (their tap and channel when C is a
+  // multiple of 8), and its two pixels k0 + pp + e advance by GBK per slab: their (image, row, column) are
+  // carried from slab to slab instead of divided out each time
+  const bool fast = GATHER && (g.C & 7) == 0;
+  const int ntap = fast ? (n0 + cc) / g.C : 0, nch = fast ? (n0 + cc) - ntap * g.C : 0;
+  const int nty = (ntap * 11) >> 5, ntx = ntap - 3 * nty;   // ntap / 3, ntap % 3 for ntap < 9
+  int pb[2] = {0, 0}, py[2] = {0, 0}, px[2] = {0, 0};
+  if constexpr (GATHER)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int p = kb + pp + e;
+      pb[e] = p / (g.H * g.W);
+      const int rem = p - pb[e] * g.H * g.W;
+      py[e] = rem / g.W;
+      px[e] = rem - py[e] * g.W;
+    }
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -259,9 +297,15 @@ __global__ __launch_bounds__(256) void gemm_tn(const uint16_t* __restrict__ A, i
       const int n = n0 + cc;
       if (n < NB) {
         if constexpr (GATHER) {
-          const int b = p / (g.H * g.W), rem = p - b * g.H * g.W;
-          const int y = rem / g.W;
-          rb[e] = im2col8(g, b, y, rem - y * g.W, n);
+          if (fast) {
+            if (ntap < 9) {
+              const int sy = py[e] + nty - 1, sx = px[e] + ntx - 1;
+              if (sy >= 0 && sy < g.H && sx >= 0 && sx < g.W)
+                rb[e] = *(const uint4*)(g.x + ((int64_t)(pb[e] * g.H + sy) * g.W + sx) * g.ldx + nch);
+            }
+          } else {
+            rb[e] = im2col8(g, pb[e], py[e], px[e], n);
+          }
         } else {
           rb[e] = row8(B, ldb, p, n, NB);
         }
@@ -269,6 +313,18 @@ __global__ __launch_bounds__(256) void gemm_tn(const uint16_t* __restrict__ A, i
         rb[e] = make_uint4(0x3F80u, 0, 0, 0);   // bf16 1.0 in column NB
       }
     }
+    if constexpr (GATHER)   // on to the next slab's pixels
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        px[e] += GBK;
+        while (px[e] >= g.W) {
+          px[e] -= g.W;
+          if (++py[e] == g.H) {
+            py[e] = 0;
+            ++pb[e];
+          }
+        }
+      }
   };
   auto half = [](const uint4& v, int j) -> uint32_t {   // 16-bit element j of v
     const uint32_t w = j < 2 ? v.x : j < 4 ? v.y : j < 6 ? v.z : v.w;
