@@ -39,7 +39,10 @@ namespace {
 
 constexpr int GRID_CHUNK = 4096;   // default visibilities per work item
 constexpr int BALL_CHUNK = 8192;   // visibilities per reduction chunk
-constexpr int RUN_MIN = 6;         // mean visibilities per cell of a dense work item
+// mean visibilities per cell of a dense work item (the register-cached path pays only at the extreme: at 1024^2 /
+// 2e7 radial, 256^2 / 655k and 512^2 / 4e6 the interleaved path alone was 10-25 % faster, at 64^2 / 2e6, about 120
+// per cell, the cached path 2-5 %)
+constexpr int RUN_MIN = 96;
 constexpr int DEGRID_STAGE = 4096; // outputs a dense degridding work-group stages in LDS (= default chunk)
 
 // The J = 8 gridder: waves per work-group (two streams each).  Two keep a work-group's LDS near 18 KB, so
