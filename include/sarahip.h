@@ -126,7 +126,7 @@ sh_status sh_kb_alias_error(int32_t kernel_width, int32_t oversample, double* er
 
 /* Query plan sizes: out[0]=M, out[1]=n, out[2]=grid side K, out[3]=J, out[4]=R,
  * out[5]=number of gridding work items, out[6]=tile side, out[7]=max items per tile,
- * out[8]=number of problems P, out[9]=work items of the sparse (one thread per visibility) class. */
+ * out[8]=number of problems P, out[9]=work items degridded one thread per visibility (all of them). */
 sh_status sh_op_query(sh_op op, int64_t out[10]);
 
 /* Block offsets in internal order (host, R+1 int64).  Internal order permutes

@@ -12,10 +12,9 @@
 // blocks stay contiguous ("internal order": a permutation inside each block).  A work item is a
 // contiguous run of internal order with one (block, tile), cut into chunks of at most GRID_CHUNK.
 //
-// Degridding: one work-group per item stages the tile's padded (T+J-1)^2 grid patch in LDS; each
-// thread interpolates a contiguous sub-range of the item.  In dense items (many visibilities per
-// cell) a thread keeps the J x J taps of its current cell in registers across the run of
-// visibilities that share it.
+// Degridding: one work-group per item stages the tile's padded (T+J-1)^2 grid patch in LDS; its threads
+// take the item's visibilities interleaved (coalesced loads and stores) and read each one's J x J window
+// from LDS.
 //
 // Gridding (atomic-free): one work-group per item owns a private padded patch, written to the item's own
 // slot; the fold kernel then forms each grid cell as the sum, in a fixed order, of the patches that cover
@@ -39,11 +38,6 @@ namespace {
 
 constexpr int GRID_CHUNK = 4096;   // default visibilities per work item
 constexpr int BALL_CHUNK = 8192;   // visibilities per reduction chunk
-// mean visibilities per cell of a dense work item (the register-cached path pays only at the extreme: at 1024^2 /
-// 2e7 radial, 256^2 / 655k and 512^2 / 4e6 the interleaved path alone was 10-25 % faster, at 64^2 / 2e6, about 120
-// per cell, the cached path 2-5 %)
-constexpr int RUN_MIN = 96;
-constexpr int DEGRID_STAGE = 4096; // outputs a dense degridding work-group stages in LDS (= default chunk)
 
 // The J = 8 gridder: waves per work-group (two streams each).  Two keep a work-group's LDS near 18 KB, so
 // that the registers (five waves per SIMD), not LDS, bound the occupancy.
@@ -76,19 +70,9 @@ __device__ __forceinline__ void kb_weights(const KBCoef& kc, float s, float* w) 
 // wavefront-scope fence (a compiler barrier that needs no wait instruction) is enough.
 __device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-// Work items cover one tile's visibilities (gridding order: tile, then cell).  Each of the 256
-// threads of a work-group takes a contiguous sub-range of the item, so the lanes of a wave sit on
-// different cells.  Items whose visibilities pile up in few cells ("dense" items: many per cell) keep
-// the J x J taps of the current cell in registers across the run of visibilities that share it.
-
-__device__ __forceinline__ void item_range(const int4& it, int tid, int& lo, int& hi) {
-  lo = it.y + int((int64_t)it.z * tid / 256);
-  hi = it.y + int((int64_t)it.z * (tid + 1) / 256);
-}
-
 // Degridding of one item: the tile's padded (T+J-1)^2 grid patch is staged in LDS, then
 // V = sum_{t1,t2} w1[t1] w2[t2] X[r0 + t1, c0 + t2] per visibility.
-template <int J, int T, bool RUNS>
+template <int J, int T>
 __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ coord, const float2* __restrict__ grid,
                                                      float2* __restrict__ out, const uint32_t* __restrict__ oidx,
                                                      const int4* __restrict__ items,
@@ -116,23 +100,9 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
   const int F = 32 - log2K;
   const uint32_t fmask = (F == 32) ? 0xffffffffu : ((1u << F) - 1u);
   const float fs = ldexpf(1.0f, 1 - F);
-  // dense items: a contiguous sub-range per thread (runs of one cell); sparse items: interleaved
-  // visibilities so that the coordinate loads and visibility stores coalesce
-  int lo, hi, step;
-  if constexpr (RUNS) {
-    item_range(it, tid, lo, hi);
-    step = 1;
-  } else {
-    lo = it.y + tid;
-    hi = it.y + it.z;
-    step = 256;
-  }
-  float2 cache[RUNS ? J : 1][RUNS ? J : 1];
-  // dense items stage their results in LDS and store them coalesced at the end
-  __shared__ float2 staged[RUNS ? DEGRID_STAGE : 1];
-  const bool stage_out = RUNS && it.z <= DEGRID_STAGE;
-  int cur = -1;
-  for (int j = lo; j < hi; j += step) {
+  // the item's visibilities interleaved over the threads, so that the coordinate loads and visibility stores
+  // coalesce
+  for (int j = it.y + tid; j < it.y + it.z; j += 256) {
     const uint2 c = coord[j];
     const int lr = int(c.x >> F) - a0, lc = int(c.y >> F) - b0;
     const float s1 = float(c.x & fmask) * fs - 1.0f;
@@ -141,52 +111,22 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
     kb_weights<J>(kc, s1, w1);
     kb_weights<J>(kc, s2, w2);
     float ar = 0.f, ai = 0.f;
-    if constexpr (RUNS) {
-      const int cell = lr * T + lc;
-      if (cell != cur) {
-        cur = cell;
-#pragma unroll
-        for (int t1 = 0; t1 < J; ++t1)
-#pragma unroll
-          for (int t2 = 0; t2 < J; ++t2) cache[t1][t2] = patch[(lr + t1) * P + lc + t2];
-      }
-#pragma unroll
-      for (int t1 = 0; t1 < J; ++t1) {
-        float rr = 0.f, ri = 0.f;
-#pragma unroll
-        for (int t2 = 0; t2 < J; ++t2) {
-          rr = fmaf(w2[t2], cache[t1][t2].x, rr);
-          ri = fmaf(w2[t2], cache[t1][t2].y, ri);
-        }
-        ar = fmaf(w1[t1], rr, ar);
-        ai = fmaf(w1[t1], ri, ai);
-      }
-    } else {
-      // two rows at a time: a fully unrolled window keeps all J^2 loads live (155 VGPRs, three waves per
-      // SIMD at J = 8); two rows leave 47 VGPRs and eight waves
+    // two rows at a time: a fully unrolled window keeps all J^2 loads live (155 VGPRs, three waves per SIMD
+    // at J = 8); two rows leave 47 VGPRs and eight waves
 #pragma unroll 2
-      for (int t1 = 0; t1 < J; ++t1) {
-        const float2* row = patch + (lr + t1) * P + lc;
-        float rr = 0.f, ri = 0.f;
+    for (int t1 = 0; t1 < J; ++t1) {
+      const float2* row = patch + (lr + t1) * P + lc;
+      float rr = 0.f, ri = 0.f;
 #pragma unroll
-        for (int t2 = 0; t2 < J; ++t2) {
-          const float2 g = row[t2];
-          rr = fmaf(w2[t2], g.x, rr);
-          ri = fmaf(w2[t2], g.y, ri);
-        }
-        ar = fmaf(w1[t1], rr, ar);
-        ai = fmaf(w1[t1], ri, ai);
+      for (int t2 = 0; t2 < J; ++t2) {
+        const float2 g = row[t2];
+        rr = fmaf(w2[t2], g.x, rr);
+        ri = fmaf(w2[t2], g.y, ri);
       }
+      ar = fmaf(w1[t1], rr, ar);
+      ai = fmaf(w1[t1], ri, ai);
     }
-    const float2 r = make_float2(ar * scale, ai * scale);
-    if (stage_out)
-      staged[j - it.y] = r;
-    else
-      out[oidx ? oidx[j] : j] = r;
-  }
-  if (stage_out) {
-    __syncthreads();
-    for (int e = tid; e < it.z; e += 256) out[oidx ? oidx[it.y + e] : it.y + e] = staged[e];
+    out[oidx ? oidx[j] : j] = make_float2(ar * scale, ai * scale);
   }
 }
 
@@ -689,14 +629,8 @@ __global__ void scatter_kernel(const float2* __restrict__ src, const uint32_t* _
 template <int J, int T>
 sh_status launch_degrid_T(sh_op op, const float2* grid, float2* out, const uint32_t* oidx, const float* scales,
                           const int32_t* bmask, hipStream_t st) {
-  if (op->n_sparse)
-    hipLaunchKernelGGL((degrid_kernel<J, T, false>), dim3((unsigned)op->n_sparse), dim3(256), 0, st, op->coord.ptr,
-                       grid, out, oidx, op->items.ptr, op->item_block.ptr, op->log2K, op->log2T, scales, op->kb, bmask);
-  if (op->n_items > op->n_sparse)
-    hipLaunchKernelGGL((degrid_kernel<J, T, true>), dim3((unsigned)(op->n_items - op->n_sparse)), dim3(256), 0, st,
-                       op->coord.ptr, grid, out, oidx, op->items.ptr + op->n_sparse,
-                       op->item_block.ptr + op->n_sparse, op->log2K, op->log2T, scales,
-                       op->kb, bmask);
+  hipLaunchKernelGGL((degrid_kernel<J, T>), dim3((unsigned)op->n_items), dim3(256), 0, st, op->coord.ptr, grid, out,
+                     oidx, op->items.ptr, op->item_block.ptr, op->log2K, op->log2T, scales, op->kb, bmask);
   SH_LAUNCHED();
   return SH_OK;
 }
@@ -827,13 +761,11 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   std::vector<uint2> ci(M);
   for (int64_t i = 0; i < M; ++i) ci[i] = cu[perm[i]];
   // work items: runs of internal order with one (block, tile), cut into near-equal chunks of at most
-  // `chunk`.  An item's tile id is global: problem * nT^2 + tile.  Items with at least RUN_MIN
-  // visibilities per occupied cell on average are "dense" (run-caching degridder).  Patch slots
-  // follow (global tile, block) order so that the fold finds the items of a tile in one contiguous
-  // slot range.
+  // `chunk`.  An item's tile id is global: problem * nT^2 + tile.  Patch slots follow (global tile,
+  // block) order so that the fold finds the items of a tile in one contiguous slot range.
   const int ntiles = nT * nT;
   const int gtiles = op->P * ntiles;
-  struct Item { int tile, start, count, dense, block; };
+  struct Item { int tile, start, count, block; };
   std::vector<Item> all;
   for (int64_t i = 0; i < M;) {
     const uint32_t k0 = key[perm[i]] >> (2 * log2T);
@@ -845,9 +777,7 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
     const int64_t c = e - i, nck = sh::cdiv(c, op->chunk);
     for (int64_t k = 0; k < nck; ++k) {
       const int64_t a = i + c * k / nck, bb = i + c * (k + 1) / nck;
-      int64_t cells = 0;
-      for (int64_t q = a; q < bb; ++q) cells += (q == a || key[perm[q]] != key[perm[q - 1]]);
-      all.push_back({gt, (int)a, (int)(bb - a), (bb - a) >= RUN_MIN * cells ? 1 : 0, b});
+      all.push_back({gt, (int)a, (int)(bb - a), b});
     }
     i = e;
   }
@@ -862,12 +792,10 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   for (int t = 0; t < gtiles; ++t) tile_items[t + 1] = tile_items[t] + per_tile[t];
   std::vector<int4> items;
   std::vector<int32_t> item_block;
-  for (int pass = 0; pass < 2; ++pass)
-    for (size_t q = 0; q < all.size(); ++q)
-      if (all[q].dense == pass) {
-        items.push_back(make_int4(all[q].tile, all[q].start, all[q].count, slot_of[q]));
-        item_block.push_back(all[q].block);
-      }
+  for (size_t q = 0; q < all.size(); ++q) {
+    items.push_back(make_int4(all[q].tile, all[q].start, all[q].count, slot_of[q]));
+    item_block.push_back(all[q].block);
+  }
   // J = 8 gridder: the cell rows of each stream of each item (the kernel splits an item into 2 W streams of
   // near-equal length, W its waves per work-group, exactly as below)
   std::vector<int4> item_rows;
@@ -891,8 +819,7 @@ static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
     }
   }
   op->n_items = (int64_t)items.size();
-  op->n_sparse = 0;
-  for (auto& a : all) op->n_sparse += a.dense == 0;
+  op->n_sparse = op->n_items;   // every item takes the interleaved degridder
   op->max_items_per_tile = *std::max_element(per_tile.begin(), per_tile.end());
   // reduction chunks (never straddling a block)
   std::vector<int4> chunks;
