@@ -14,16 +14,17 @@ namespace {
 
 constexpr int RB = 512;   // first-stage work-groups of a one-segment reduction
 
+// Sum of v over the work-group, returned to every thread: a butterfly inside each wave (lane 0's result,
+// whose order of additions is fixed), then the waves' sums in wave order.  Two barriers, whatever the size.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[wave] = v;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) sh[tid] += sh[tid + s];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) r += sh[w];
+  __syncthreads();   // sh is free again for the caller's next sum
   return r;
 }
 
@@ -146,15 +147,15 @@ __global__ __launch_bounds__(256) void var_partial(const float* __restrict__ a, 
   PART_OUT(r);
 }
 
+// Maximum of v over the work-group (for thread 0; exact in any order): per wave, then over the waves.
 __device__ __forceinline__ double block_max(double v, double* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) sh[tid] = fmax(sh[tid], sh[tid + s]);
-    __syncthreads();
-  }
-  return sh[0];
+  double r = sh[0];
+  for (int w = 1; w < int(blockDim.x >> 6); ++w) r = fmax(r, sh[w]);
+  return r;
 }
 
 __global__ __launch_bounds__(256) void maxabs_partial(const float* __restrict__ a, int64_t per, double* __restrict__ part) {
