@@ -17,8 +17,8 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsarahip.so")
-SOURCES = ["abi.cpp", "tables.cpp", "nufft.hip", "fft.hip", "toeplitz.hip", "blocknorm.hip", "dwt.hip", "prox.hip",
-           "sdmm.hip", "tune.hip", "unet.hip"]
+SOURCES = ["abi.cpp", "tables.cpp", "plan.cpp", "nufft.hip", "fft.hip", "toeplitz.hip", "blocknorm.hip", "dwt.hip",
+           "prox.hip", "sdmm.hip", "tune.hip", "unet.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          "-Wno-unused-result", "-Wno-unused-variable",

@@ -32,12 +32,12 @@
 #include <numeric>
 
 #include "op.hpp"
+#include "plan.hpp"
 #include "tables.hpp"
 
 namespace {
 
 constexpr int GRID_CHUNK = 4096;   // default visibilities per work item
-constexpr int BALL_CHUNK = 8192;   // visibilities per reduction chunk
 
 // The J = 8 gridder: waves per work-group (two streams each).  Two keep a work-group's LDS near 18 KB, so
 // that the registers (five waves per SIMD), not LDS, bound the occupancy.
@@ -725,120 +725,24 @@ sh_status phi_adjoint(sh_op op, const float2* vis, float* x, bool user_order, co
 
 static sh_status op_build(sh_op op, const double* uv, const int64_t* offs) {
   const int64_t M = op->M;
-  const int K = op->K, F = 32 - op->log2K, log2T = op->log2T, nT = op->nT;
-  const double scale = double(K) / (2.0 * M_PI);
-  std::vector<uint2> cu(M);
-  std::vector<uint32_t> key(M);
-  for (int64_t m = 0; m < M; ++m) {
-    uint32_t q[2];
-    int cell[2];
-    for (int ax = 0; ax < 2; ++ax) {
-      const double kappa = uv[2 * m + ax] * scale;
-      const double base = std::floor(kappa);
-      const double frac = kappa - base;  // exact in float64, in [0, 1)
-      int64_t cl = (int64_t)base % K;
-      if (cl < 0) cl += K;
-      uint64_t fr = (uint64_t)std::floor(std::ldexp(frac, F));
-      if (F < 32 && fr >= (uint64_t(1) << F)) fr = (uint64_t(1) << F) - 1;
-      q[ax] = (uint32_t)(((uint64_t)cl << F) | fr);
-      cell[ax] = (int)cl;
-    }
-    cu[m] = make_uint2(q[0], q[1]);
-    const uint32_t tile = uint32_t((cell[0] >> log2T) * nT + (cell[1] >> log2T));
-    const uint32_t local = uint32_t(((cell[0] & (op->T - 1)) << log2T) | (cell[1] & (op->T - 1)));
-    key[m] = (tile << (2 * log2T)) | local;
-  }
-  // internal order: sort by (tile, cell) inside each block (blocks never straddle problems)
-  std::vector<uint32_t> perm(M);
-  std::vector<uint64_t> kv;
-  for (int b = 0; b < op->R; ++b) {
-    const int64_t lo = offs[b], hi = offs[b + 1];
-    kv.resize(hi - lo);
-    for (int64_t m = lo; m < hi; ++m) kv[m - lo] = (uint64_t(key[m]) << 32) | uint64_t(m - lo);
-    std::sort(kv.begin(), kv.end());
-    for (int64_t m = lo; m < hi; ++m) perm[m] = uint32_t(lo + (kv[m - lo] & 0xffffffffu));
-  }
-  std::vector<uint2> ci(M);
-  for (int64_t i = 0; i < M; ++i) ci[i] = cu[perm[i]];
-  // work items: runs of internal order with one (block, tile), cut into near-equal chunks of at most
-  // `chunk`.  An item's tile id is global: problem * nT^2 + tile.  Patch slots follow (global tile,
-  // block) order so that the fold finds the items of a tile in one contiguous slot range.
-  const int ntiles = nT * nT;
-  const int gtiles = op->P * ntiles;
-  struct Item { int tile, start, count, block; };
-  std::vector<Item> all;
-  for (int64_t i = 0; i < M;) {
-    const uint32_t k0 = key[perm[i]] >> (2 * log2T);
-    const int b = int(std::upper_bound(offs, offs + op->R + 1, i) - offs) - 1;
-    const int64_t bend = offs[b + 1];
-    const int gt = op->block_prob[b] * ntiles + (int)k0;
-    int64_t e = i;
-    while (e < bend && (key[perm[e]] >> (2 * log2T)) == k0) ++e;
-    const int64_t c = e - i, nck = sh::cdiv(c, op->chunk);
-    for (int64_t k = 0; k < nck; ++k) {
-      const int64_t a = i + c * k / nck, bb = i + c * (k + 1) / nck;
-      all.push_back({gt, (int)a, (int)(bb - a), b});
-    }
-    i = e;
-  }
-  std::vector<int> order(all.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return all[x].tile < all[y].tile; });
-  std::vector<int32_t> tile_items(gtiles + 1, 0), per_tile(gtiles, 0), slot_of(all.size());
-  for (size_t q = 0; q < order.size(); ++q) {
-    slot_of[order[q]] = (int32_t)q;
-    per_tile[all[order[q]].tile]++;
-  }
-  for (int t = 0; t < gtiles; ++t) tile_items[t + 1] = tile_items[t] + per_tile[t];
-  std::vector<int4> items;
-  std::vector<int32_t> item_block;
-  for (size_t q = 0; q < all.size(); ++q) {
-    items.push_back(make_int4(all[q].tile, all[q].start, all[q].count, slot_of[q]));
-    item_block.push_back(all[q].block);
-  }
-  // J = 8 gridder: the cell rows of each stream of each item (the kernel splits an item into 2 W streams of
-  // near-equal length, W its waves per work-group, exactly as below)
-  std::vector<int4> item_rows;
-  if (op->J == 8) {
-    const int ns = 2 * grid_mfma_waves(op->T);
-    item_rows.resize(items.size());
-    for (size_t q = 0; q < items.size(); ++q) {
-      const int64_t a = items[q].y, c = items[q].z;
-      uint32_t f[2] = {0u, 0u}, r[2] = {0u, 0u};
-      for (int k = 0; k < ns; ++k) {
-        const int64_t lo = a + c * k / ns, hi = a + c * (k + 1) / ns;
-        uint32_t first = 0, rows = 1;      // an empty stream still owns one row
-        if (hi > lo) {
-          first = (key[perm[lo]] >> log2T) & uint32_t(op->T - 1);
-          rows = ((key[perm[hi - 1]] >> log2T) & uint32_t(op->T - 1)) - first + 1;
-        }
-        f[k / 4] |= first << (8 * (k % 4));
-        r[k / 4] |= rows << (8 * (k % 4));
-      }
-      item_rows[q] = make_int4((int)f[0], (int)f[1], (int)r[0], (int)r[1]);
-    }
-  }
-  op->n_items = (int64_t)items.size();
+  const int K = op->K;
+  sh::PlanShape shape{M, K, op->log2K, op->T, op->log2T, op->nT, op->P, op->R, op->chunk,
+                      op->J == 8 ? 2 * grid_mfma_waves(op->T) : 0};
+  sh::HostPlan h;
+  sh::plan_host(shape, uv, offs, op->block_prob.data(), h);
+  op->n_items = (int64_t)h.items.size();
   op->n_sparse = op->n_items;   // every item takes the interleaved degridder
-  op->max_items_per_tile = *std::max_element(per_tile.begin(), per_tile.end());
-  // reduction chunks (never straddling a block)
-  std::vector<int4> chunks;
-  op->chunk_first.assign(op->R + 1, 0);
-  for (int b = 0; b < op->R; ++b) {
-    op->chunk_first[b] = (int32_t)chunks.size();
-    for (int64_t q = offs[b]; q < offs[b + 1]; q += BALL_CHUNK)
-      chunks.push_back(make_int4(b, (int)q, (int)std::min<int64_t>(q + BALL_CHUNK, offs[b + 1]), 0));
-  }
-  op->chunk_first[op->R] = (int32_t)chunks.size();
-  op->n_chunks = (int64_t)chunks.size();
+  op->max_items_per_tile = h.max_items_per_tile;
+  op->chunk_first = h.chunk_first;
+  op->n_chunks = (int64_t)h.chunks.size();
 
-  SH_TRY(op->coord.upload(ci));
-  SH_TRY(op->perm.upload(perm));
-  SH_TRY(op->items.upload(items));
-  SH_TRY(op->item_block.upload(item_block));
-  if (!item_rows.empty()) SH_TRY(op->item_rows.upload(item_rows));
-  SH_TRY(op->tile_items.upload(tile_items));
-  SH_TRY(op->chunks.upload(chunks));
+  SH_TRY(op->coord.upload(h.coord));
+  SH_TRY(op->perm.upload(h.perm));
+  SH_TRY(op->items.upload(h.items));
+  SH_TRY(op->item_block.upload(h.item_block));
+  if (!h.item_rows.empty()) SH_TRY(op->item_rows.upload(h.item_rows));
+  SH_TRY(op->tile_items.upload(h.tile_items));
+  SH_TRY(op->chunks.upload(h.chunks));
   SH_TRY(op->chunk_first_d.upload(op->chunk_first));
   SH_TRY(op->block_prob_d.upload(op->block_prob));
   SH_TRY(op->partials.alloc(2 * std::max<int64_t>(op->n_chunks, 1)));
