@@ -404,6 +404,25 @@ sh_status sh_sdmm_kkt(sh_sdmm s, double* kkt_primal, double* kkt_dual, double* o
 sh_status sh_sdmm_state_bytes(sh_sdmm s, size_t* bytes);
 sh_status sh_sdmm_state_export(sh_sdmm s, void* host, size_t bytes, void* stream);
 sh_status sh_sdmm_state_import(sh_sdmm s, const void* host, size_t bytes, void* stream);
+/* Per-iteration metrics of a session (the quantities the stopping test of the SDMM paragraph and the
+ * constraints of eq. (3) are judged by), kept on the device and read back when the caller chooses.
+ * sh_sdmm_metrics_enable gives the session a ring of `rows` rows (0 switches it off and frees it; at most
+ * 2^20), allocated with hipMalloc, and returns the row width 2P + R in *row_width (may be NULL).  From then on
+ * every iteration, replayed graph or not, appends one row of doubles: [0, P) the relative change
+ * ||x_n - x_(n-1)|| / ||x_n|| of each problem, [P, 2P) its objective ||W Psi^dagger x_n||_1 (||W alpha_n||_1
+ * for the synthesis prior) with the pass's weights, [2P, 2P + R) each block's ||y_i - Phi_i x_n|| / eps_i
+ * (block-subset iterations refresh their selected blocks only; the others repeat their last value, at first
+ * their residual at the starting image).
+ * Recording adds one weighted-l1 reduction and one small kernel per iteration.  enable synchronises the
+ * device.  sh_sdmm_metrics_read copies the rows not yet read, oldest first, at most max_rows of them, into
+ * `host` (caller-owned, max_rows * (2P + R) doubles, row-major) after the work enqueued on `stream`, and
+ * synchronises it; *rows_out is the number copied, *first_iter (may be NULL) the session iteration count
+ * after the first of them (iterations are counted from 1).  When more than `rows` iterations passed since the
+ * last read the oldest were overwritten: the copy then starts at the oldest row still held, which
+ * *first_iter shows.  Errors: SH_EINVAL (NULL, rows out of range, ring off for read), SH_ENOMEM. */
+sh_status sh_sdmm_metrics_enable(sh_sdmm s, int32_t rows, int32_t* row_width);
+sh_status sh_sdmm_metrics_read(sh_sdmm s, double* host, int32_t max_rows, int32_t* rows_out, int64_t* first_iter,
+                               void* stream);
 sh_status sh_sdmm_destroy(sh_sdmm s);
 
 /* ---------------------------------------------------------------------------

@@ -298,11 +298,13 @@ __global__ __launch_bounds__(256) void ball_norms(const float2* __restrict__ s_i
   }
 }
 
-// per block: rho = ||t - yhat||, resid = ||s - yhat|| (chunk partials summed in order)
+// per block: rho = ||t - yhat||, resid = ||s - yhat|| (chunk partials summed in order); with bmask, blocks left
+// out keep the values they hold (their partials were not computed)
 __global__ void ball_final(const double* __restrict__ part, const int* __restrict__ first, int R,
-                           double* __restrict__ rho, double* __restrict__ resid) {
+                           double* __restrict__ rho, double* __restrict__ resid,
+                           const int32_t* __restrict__ bmask) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= R) return;
+  if (b >= R || (bmask && !bmask[b])) return;
   double a = 0.0, c = 0.0;
   for (int k = first[b]; k < first[b + 1]; ++k) {
     a += part[2 * k];
@@ -489,7 +491,7 @@ sh_status ball_kernels(sh_op op, const float2* s, float2* z, const float2* yhat,
   hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr,
                      (const int32_t*)nullptr);
   hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
-                     op->chunk_first_d.ptr, op->R, rho, resid);
+                     op->chunk_first_d.ptr, op->R, rho, resid, (const int32_t*)nullptr);
   hipLaunchKernelGGL(ball_project, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, eps, rho, cblk, v,
                      sub_s ? 1 : 0);
   SH_LAUNCHED();
@@ -502,7 +504,7 @@ sh_status ball_norms_only(sh_op op, const float2* s, const float2* z, const floa
   hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr,
                      (const int32_t*)nullptr);
   hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
-                     op->chunk_first_d.ptr, op->R, rho, resid);
+                     op->chunk_first_d.ptr, op->R, rho, resid, (const int32_t*)nullptr);
   SH_LAUNCHED();
   return SH_OK;
 }
@@ -519,7 +521,7 @@ sh_status launch_kkt_vis(sh_op op, const float2* s, const float2* z, const float
   hipLaunchKernelGGL(kkt_vis_partial, dim3(nc), dim3(256), 0, st, s, z, v, op->chunks.ptr, cblk, op->partials.ptr,
                      sub_s ? 1 : 0);
   hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
-                     op->chunk_first_d.ptr, op->R, prim_b, scale_b);
+                     op->chunk_first_d.ptr, op->R, prim_b, scale_b, (const int32_t*)nullptr);
   SH_LAUNCHED();
   return SH_OK;
 }
@@ -531,7 +533,7 @@ sh_status launch_prox_ball_subset(sh_op op, const float2* s, float2* z, const fl
   const unsigned nc = (unsigned)op->n_chunks;
   hipLaunchKernelGGL(ball_norms, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, cblk, op->partials.ptr, bmask);
   hipLaunchKernelGGL(ball_final, dim3((unsigned)cdiv(op->R, 64)), dim3(64), 0, st, op->partials.ptr,
-                     op->chunk_first_d.ptr, op->R, rho, resid);
+                     op->chunk_first_d.ptr, op->R, rho, resid, bmask);
   hipLaunchKernelGGL(ball_project_delta, dim3(nc), dim3(256), 0, st, s, z, yhat, op->chunks.ptr, eps, rho, cblk, bmask,
                      v, dv);
   SH_LAUNCHED();

@@ -305,6 +305,13 @@ struct sh_sdmm_s {
   hipGraphExec_t gexec = nullptr;
   const float* g_Wp = nullptr;     // the weights pointer baked into gexec
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // Per-iteration metrics ring (sh_sdmm_metrics_enable): ring_rows rows of 2P + R doubles, one written by every
+  // iteration (inside the replayed graph); ring_ctr counts the rows written since the ring was enabled.
+  sh::DevBuf<double> ring;
+  sh::DevBuf<unsigned long long> ring_ctr;
+  int ring_rows = 0;
+  int ring_base = 0;                  // iters_total when the ring was enabled
+  unsigned long long ring_next = 0;   // the first row not yet handed to the caller
   ~sh_sdmm_s() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (ev_in) (void)hipEventDestroy(ev_in);
@@ -528,6 +535,9 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
     } else {
       SH_HIP(hipMemsetAsync(w.bphi.ptr, 0, N * sizeof(float), st));
     }
+    // the iterations refresh the residuals of their selected blocks only: start every block from x0's
+    SH_TRY(sh::ball_norms_only(op, w.sphi.ptr, w.zphi.ptr, w.yhat.ptr, w.cblk.ptr, w.kkt.ptr + 8 * P, w.resid.ptr,
+                               st));
   }
   if (s->prm.z_from_x0) {   // duals from the optimality conditions at x0 (see sdmm_dual_warm_start)
     SH_TRY(sdmm_dual_warm_start(s, st));
@@ -542,6 +552,37 @@ sh_status sdmm_setup(sh_sdmm s, const float* y, const double* eps, const float* 
 // reuses s_phi = Phi x_{n-1} through v_phi (as in the analysis form), and every product Q p is
 // p + Psi^dagger ((I + T) Psi p) with the Toeplitz product T.  Then x_n = Psi alpha_n feeds the data and
 // positivity splits, alpha_n the l1 split.
+// One row of the metrics ring: per problem the relative change ||x_n - x_(n-1)|| / ||x_n|| and the objective
+// ||W Psi^dagger x_n||_1 (||W alpha_n||_1 for the synthesis prior), per block the residual ||y_i - Phi_i x_n||
+// over eps_i (both in the normalised units of eq. (3), whose ratio is the user-unit one).  One work-group; the
+// row counter advances after the row is written.
+__global__ __launch_bounds__(256) void ring_record(const double* __restrict__ misc, const double* __restrict__ resid,
+                                                   const double* __restrict__ eps_hat, double* __restrict__ ring,
+                                                   unsigned long long* __restrict__ ctr, int rows, int P, int R) {
+  const unsigned long long c = ctr[0];
+  double* row = ring + (size_t)(c % (unsigned long long)rows) * (size_t)(2 * P + R);
+  for (int j = threadIdx.x; j < P; j += 256) {
+    const double dx = misc[MISC_DX * P + j], xx = misc[MISC_X * P + j];
+    row[j] = xx > 0 ? sqrt(dx / xx) : (dx == 0 ? 0.0 : INFINITY);
+    row[P + j] = misc[MISC_OBJ * P + j];
+  }
+  for (int b = threadIdx.x; b < R; b += 256) row[2 * P + b] = resid[b] / eps_hat[b];
+  __syncthreads();
+  if (threadIdx.x == 0) ctr[0] = c + 1;
+}
+
+// Appends the iteration's metrics row (nothing while the ring is off).  Block-subset iterations refresh the
+// residuals of their selected blocks only; the others keep their last value.
+sh_status ring_step(sh_sdmm s, hipStream_t st) {
+  if (s->ring_rows <= 0) return SH_OK;
+  Work& w = s->w;
+  SH_TRY(w.red.l1w(s->synth ? w.alpha.ptr : w.spsi.ptr, s->Wp, s->Dper, s->s_misc + MISC_OBJ * s->P, st));
+  hipLaunchKernelGGL(ring_record, dim3(1), dim3(256), 0, st, s->s_misc, w.resid.ptr, w.eps_hat.ptr, s->ring.ptr,
+                     s->ring_ctr.ptr, s->ring_rows, s->P, s->R);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
 sh_status sdmm_step_synthesis(sh_sdmm s, hipStream_t st) {
   sh_op op = s->op;
   Work& w = s->w;
@@ -588,7 +629,10 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   const int64_t N = s->N, per = s->per;
   const dim3 gP(nblk(per), P);
   double *s_rs = s->s_rs, *s_pap = s->s_pap, *s_misc = s->s_misc;
-  if (s->synth) return sdmm_step_synthesis(s, st);
+  if (s->synth) {
+    SH_TRY(sdmm_step_synthesis(s, st));
+    return ring_step(s, st);
+  }
   // ---- x-update by CG from x_{n-1}
   SH_TRY(sh_psi_fwd(s->psi, w.vpsi.ptr, w.t1.ptr, st));
   if (s->stoch) {
@@ -636,7 +680,7 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
                                 w.vphi.ptr, true, w.cblk.ptr, st));
   }
   SH_TRY(sh::launch_prox_pos(N, w.x.ptr, w.zpos.ptr, w.vpos.ptr, st));
-  return SH_OK;
+  return ring_step(s, st);
 }
 
 // Captures one iteration into an executable graph on the session stream (again whenever the
@@ -1125,6 +1169,52 @@ sh_status sh_sdmm_state_import(sh_sdmm s, const void* host, size_t bytes, void* 
   }
   SH_HIP(hipStreamSynchronize(st));
   s->iters_total = hd.iters_total;
+  return SH_OK;
+}
+
+sh_status sh_sdmm_metrics_enable(sh_sdmm s, int32_t rows, int32_t* row_width) {
+  SH_REQUIRE(s != nullptr, "session is NULL");
+  SH_REQUIRE(rows >= 0 && rows <= (1 << 20), "rows must be in [0, 2^20], got %d", rows);
+  SH_HIP(hipDeviceSynchronize());   // no enqueued iteration may still write the old ring
+  if (s->gexec) {                   // the captured iteration carries the ring (or its absence): capture again
+    SH_HIP(hipGraphExecDestroy(s->gexec));
+    s->gexec = nullptr;
+  }
+  s->ring.release();
+  s->ring_ctr.release();
+  s->ring_rows = 0;
+  if (row_width) *row_width = 2 * s->P + s->R;
+  if (rows == 0) return SH_OK;
+  SH_TRY(s->ring.alloc((size_t)rows * (size_t)(2 * s->P + s->R)));
+  const unsigned long long zero = 0;
+  SH_TRY(s->ring_ctr.upload(&zero, 1));
+  s->ring_rows = rows;
+  s->ring_base = s->iters_total;
+  s->ring_next = 0;
+  return SH_OK;
+}
+
+sh_status sh_sdmm_metrics_read(sh_sdmm s, double* host, int32_t max_rows, int32_t* rows_out, int64_t* first_iter,
+                               void* stream) {
+  SH_REQUIRE(s != nullptr && rows_out != nullptr, "NULL argument");
+  SH_REQUIRE(s->ring_rows > 0, "the metrics ring is off (sh_sdmm_metrics_enable)");
+  SH_REQUIRE(max_rows >= 0 && (host != nullptr || max_rows == 0), "max_rows must be >= 0 with a host buffer");
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long c = 0;
+  SH_HIP(hipMemcpyAsync(&c, s->ring_ctr.ptr, sizeof(c), hipMemcpyDeviceToHost, st));
+  SH_HIP(hipStreamSynchronize(st));
+  const unsigned long long G = (unsigned long long)s->ring_rows, W = (unsigned long long)(2 * s->P + s->R);
+  const unsigned long long lo = std::max(s->ring_next, c > G ? c - G : 0ull);   // older rows were overwritten
+  const unsigned long long n = std::min<unsigned long long>(c - lo, (unsigned long long)max_rows);
+  for (unsigned long long k = 0; k < n;) {   // at most two contiguous pieces of the ring
+    const unsigned long long slot = (lo + k) % G, len = std::min(n - k, G - slot);
+    SH_HIP(hipMemcpyAsync(host + k * W, s->ring.ptr + slot * W, len * W * sizeof(double), hipMemcpyDeviceToHost, st));
+    k += len;
+  }
+  SH_HIP(hipStreamSynchronize(st));
+  s->ring_next = lo + n;
+  *rows_out = (int32_t)n;
+  if (first_iter) *first_iter = (int64_t)s->ring_base + (int64_t)lo + 1;
   return SH_OK;
 }
 

@@ -128,6 +128,8 @@ _SIGS = {
     "sh_sdmm_state_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "sh_sdmm_state_export": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "sh_sdmm_state_import": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "sh_sdmm_metrics_enable": (C.c_int, [_vp, _i32, C.POINTER(_i32)]),
+    "sh_sdmm_metrics_read": (C.c_int, [_vp, _P64, _i32, C.POINTER(_i32), _PI64, _vp]),
     "sh_op_create_stream": (C.c_int, [_P64, _i64, _i32, _i32, _i32, _PI64, _i32, _i32, _i32, _vp, C.POINTER(_vp)]),
     "sh_device_bytes": (C.c_int, [_PI64, _PI64]),
     "sh_sdmm_destroy": (C.c_int, [_vp]),
@@ -552,6 +554,26 @@ def sdmm_state_import(s: int, state: np.ndarray, stream=None) -> None:
     """Overwrites the session's state with one from sdmm_state_export of a like session."""
     buf = np.ascontiguousarray(state, dtype=np.uint8)
     _check(lib.sh_sdmm_state_import(s, buf.ctypes.data, buf.nbytes, _stream(stream)), "sdmm_state_import")
+
+
+def sdmm_metrics_enable(s: int, rows: int) -> int:
+    """Gives the session a ring of `rows` per-iteration metric rows (0: off); returns the row width 2P + R."""
+    w = _i32()
+    _check(lib.sh_sdmm_metrics_enable(s, int(rows), C.byref(w)), "sdmm_metrics_enable")
+    return w.value
+
+
+def sdmm_metrics_read(s: int, P: int, R: int, max_rows: int, stream=None) -> dict:
+    """The metric rows not yet read (oldest first, at most max_rows): relative change and objective per problem
+    ((rows, P) arrays), residual over eps per block ((rows, R)), and the iteration count after the first row."""
+    buf = np.zeros((max(int(max_rows), 1), 2 * P + R), dtype=np.float64)
+    n = _i32()
+    first = _i64()
+    _check(lib.sh_sdmm_metrics_read(s, buf.ctypes.data_as(_P64), int(max_rows), C.byref(n), C.byref(first),
+                                    _stream(stream)), "sdmm_metrics_read")
+    rows = buf[:n.value]
+    return {"rel_change": rows[:, :P].copy(), "objective": rows[:, P:2 * P].copy(),
+            "resid_over_eps": rows[:, 2 * P:].copy(), "first_iter": int(first.value), "rows": n.value}
 
 
 def sdmm_destroy(s: int) -> None:
