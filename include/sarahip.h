@@ -102,8 +102,12 @@ sh_status sh_op_create_batched(const double* uv, const int64_t* M_p, int32_t P, 
  * width whose aliasing estimate (sh_kb_alias_error) is <= accuracy, e.g. 1e-5; the gridding tile
  * side and item cap are then chosen by timing `reps` Phi + Phi^dagger pairs of candidate plans on
  * `stream` (tile sides 8, 16, 32, then item caps 1024 and 16384 for the fastest tile).  The choice
- * is cached for the process under a hash of the inputs; a repeated call only re-plans.  result
- * (host) receives the choice and its timing.  Synchronous; allocates and frees candidate plans.
+ * is cached for the process under a hash of the inputs; a repeated call only re-plans.  With the
+ * environment variable SH_TUNE_CACHE naming a file, choices also persist across processes: a choice the
+ * process has not made yet is looked up there first, and each new one is appended as a text line
+ * "sarahip-tune-1 <key> <J> <tile> <chunk> <ms>" (the key starts with the library version; the last
+ * valid line of a key wins; a file that cannot be read or written is ignored).  result (host) receives
+ * the choice and its timing.  Synchronous; allocates and frees candidate plans.
  * Errors as sh_op_create_batched, plus SH_EINVAL for accuracy outside (0, 1) or unreachable. */
 typedef struct {
   double accuracy;     /* the target given */
@@ -113,11 +117,13 @@ typedef struct {
   int32_t tile;        /* chosen tile side */
   int32_t chunk;       /* chosen most visibilities per work item */
   int32_t candidates;  /* plans timed by this call (0 when cached) */
-  int32_t cached;      /* 1 if the tiling came from the process cache */
+  int32_t cached;      /* 0 timed now, 1 from the process cache, 2 from the SH_TUNE_CACHE file */
 } sh_tune_result;
 sh_status sh_op_autotune(const double* uv, const int64_t* M_p, int32_t P, int32_t n, int32_t oversample,
                          double accuracy, const int64_t* block_offsets, const int32_t* R_p, int32_t reps,
                          sh_tune_result* result, sh_op* out, void* stream);
+/* Forgets the process cache of sh_op_autotune (the SH_TUNE_CACHE file is left as it is). */
+sh_status sh_tune_cache_clear(void);
 /* Aliasing estimate of the J-wide Kaiser-Bessel interpolation on an alpha-times oversampled grid:
  * the RMS over image frequencies of sqrt(sum_{l != 0} psi_hat(xi + l)^2) / psi_hat(xi), times
  * sqrt(2) for two axes -- the expected relative error of Phi against the exact sum for a white

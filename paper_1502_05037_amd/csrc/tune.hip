@@ -14,8 +14,14 @@
 // Phi and Phi^dagger in internal order after one untimed application, with HIP events on the
 // caller's stream.  The fastest plan is returned, and the choice is remembered for the process
 // under a key of the sizes and a hash of the uv points and block offsets, so that re-planning the
-// same data skips the timing.
+// same data skips the timing.  With the environment variable SH_TUNE_CACHE naming a file, the choices
+// also persist across processes: a key the process has not seen is looked up in that file, and every
+// new choice is appended to it as one line "sarahip-tune-1 <key> <J> <tile> <chunk> <ms>".  The key
+// starts with the library version, so that another build times again; the last valid line of a key
+// wins; a line that does not parse or names a tiling the plan refuses is skipped.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -23,6 +29,8 @@
 
 #include "op.hpp"
 #include "tables.hpp"
+
+#define SH_TUNE_VERSION "sarahip-0.1-gfx950"
 
 namespace {
 
@@ -68,9 +76,41 @@ std::string cache_key(const double* uv, const int64_t* M_p, int P, int n, int al
   h = fnv(R_p, P * sizeof(int32_t), h);
   h = fnv(offs, (R + 1) * sizeof(int64_t), h);
   h = fnv(uv, 2 * M * sizeof(double), h);
-  char buf[160];
-  std::snprintf(buf, sizeof(buf), "%d/%d/%d/%.6e/%lld/%llx", n, P, alpha, acc, (long long)M, (unsigned long long)h);
+  char buf[200];
+  std::snprintf(buf, sizeof(buf), "%s/%d/%d/%d/%.6e/%lld/%llx", SH_TUNE_VERSION, n, P, alpha, acc, (long long)M,
+                (unsigned long long)h);
   return buf;
+}
+
+constexpr const char* kTuneTag = "sarahip-tune-1";
+
+// The last line of the cache file for `key` with kernel width J and a tiling the planner accepts.
+bool file_lookup(const std::string& key, int J, Choice* out) {
+  const char* path = std::getenv("SH_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512], tag[32], k[256];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    Choice c{};
+    if (std::sscanf(line, "%31s %255s %d %d %d %lf", tag, k, &c.J, &c.tile, &c.chunk, &c.ms) != 6) continue;
+    if (std::strcmp(tag, kTuneTag) != 0 || key != k || c.J != J) continue;
+    if ((c.tile != 8 && c.tile != 16 && c.tile != 32) || c.chunk < 64 || c.chunk > (1 << 20) || !(c.ms > 0)) continue;
+    *out = c;
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void file_append(const std::string& key, const Choice& c) {
+  const char* path = std::getenv("SH_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;   // a cache that cannot be written only costs the next process a tuning
+  std::fprintf(f, "%s %s %d %d %d %.6g\n", kTuneTag, key.c_str(), c.J, c.tile, c.chunk, c.ms);
+  std::fclose(f);
 }
 
 __global__ void fill_ones(float* a, int64_t N) {
@@ -146,6 +186,19 @@ sh_status sh_op_autotune(const double* uv, const int64_t* M_p, int32_t P, int32_
       return sh_op_create_batched(uv, M_p, P, n, oversample, J, block_offsets, R_p, c.tile, c.chunk, out);
     }
   }
+  {
+    Choice c{};
+    if (file_lookup(key, J, &c) &&
+        sh_op_create_batched(uv, M_p, P, n, oversample, J, block_offsets, R_p, c.tile, c.chunk, out) == SH_OK) {
+      std::lock_guard<std::mutex> g(g_mu);
+      g_cache[key] = c;
+      result->tile = c.tile;
+      result->chunk = c.chunk;
+      result->ms_pair = c.ms;
+      result->cached = 2;
+      return SH_OK;
+    }
+  }
   // scratch for timing
   int64_t M = 0;
   for (int p = 0; p < P; ++p) M += M_p[p];
@@ -195,10 +248,17 @@ sh_status sh_op_autotune(const double* uv, const int64_t* M_p, int32_t P, int32_
     std::lock_guard<std::mutex> g(g_mu);
     g_cache[key] = bc;
   }
+  file_append(key, bc);
   result->tile = bc.tile;
   result->chunk = bc.chunk;
   result->ms_pair = bc.ms;
   *out = best;
+  return SH_OK;
+}
+
+sh_status sh_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> g(g_mu);
+  g_cache.clear();
   return SH_OK;
 }
 

@@ -132,6 +132,7 @@ _SIGS = {
     "sh_sdmm_metrics_read": (C.c_int, [_vp, _P64, _i32, C.POINTER(_i32), _PI64, _vp]),
     "sh_op_create_stream": (C.c_int, [_P64, _i64, _i32, _i32, _i32, _PI64, _i32, _i32, _i32, _vp, C.POINTER(_vp)]),
     "sh_device_bytes": (C.c_int, [_PI64, _PI64]),
+    "sh_tune_cache_clear": (C.c_int, []),
     "sh_sdmm_destroy": (C.c_int, [_vp]),
     "sh_unet_create": (C.c_int, [_i32, _i32, C.POINTER(_vp)]),
     "sh_unet_destroy": (C.c_int, [_vp]),
@@ -265,6 +266,11 @@ def op_autotune(uv: np.ndarray, M_p, n: int, oversample: int, accuracy: float, b
                               off.ctypes.data_as(_PI64), rp.ctypes.data_as(_PI32), reps, C.byref(res), C.byref(h),
                               _stream(stream)), "op_autotune")
     return h.value, res.as_dict()
+
+
+def tune_cache_clear() -> None:
+    """Forgets the process cache of op_autotune (a SH_TUNE_CACHE file stays)."""
+    _check(lib.sh_tune_cache_clear(), "tune_cache_clear")
 
 
 def kb_alias_error(kernel_width: int, oversample: int = 2) -> float:

@@ -79,7 +79,8 @@ def test_metrics_follow_the_oracle_history(sh):
 def test_ring_wraps_and_matches_plain_launches(sh, variant):
     pb = helpers.build(80, 64, 3000, 4, 6, prob=2)
     R = len(pb.eps)
-    kw = {"analysis": {}, "block_subset": dict(block_fraction=0.5, block_seed=7), "synthesis": dict(synthesis=1)}[variant]
+    kw = {"analysis": {}, "block_subset": dict(block_fraction=0.5, block_seed=7),
+          "synthesis": dict(synthesis=1)}[variant]
     op = sh.op_create(pb.uv, 64, 2, 6, pb.offsets)
     psi = sh.psi_create(64, 4)
     y = torch.tensor(pb.y, dtype=torch.complex64, device="cuda")

@@ -1,4 +1,4 @@
-"""Autotuner: the kernel-width accuracy estimate (CPU) and the tuned plan (GPU).
+"""Autotuner: the kernel-width accuracy estimate (CPU), the tuned plan and its cache file (GPU).
 
 The estimate is pinned to the oracle: the FP64 oracle NUFFT of a white image, compared with the
 exact sum of the measurement equation (the direct DFT), has the relative error the estimate
@@ -79,3 +79,41 @@ def test_autotuned_plan_meets_target_and_is_cached(sh):
     op3, res3 = sh.op_autotune(uv, M_p, 64, 2, 1e-7, offs, R_p, reps=1)
     sh.op_destroy(op3)
     assert res3["J"] == 8
+
+
+@pytest.mark.gpu
+def test_tuning_persists_in_the_cache_file(sh, tmp_path, monkeypatch):
+    """SH_TUNE_CACHE: the first tuning appends its choice, a process that has not tuned these inputs (here: the
+    process cache forgotten) takes it from the file without timing, a later invalid line of the same key is
+    skipped, and without the variable nothing is written."""
+    pb = helpers.build(52, 64, 2000, 2, 6, coverage="radial")
+    M_p, R_p = [len(pb.uv)], [len(pb.offsets) - 1]
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("SH_TUNE_CACHE", str(path))
+    sh.tune_cache_clear()
+    op, res = sh.op_autotune(pb.uv, M_p, 64, 2, 1e-5, pb.offsets, R_p, reps=1)
+    sh.op_destroy(op)
+    assert res["cached"] == 0 and res["candidates"] >= 3
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    tag, key, J, tile, chunk, ms = lines[0].split()
+    assert tag == "sarahip-tune-1" and key.startswith("sarahip-")
+    assert (int(J), int(tile), int(chunk)) == (res["J"], res["tile"], res["chunk"])
+    with open(path, "a") as f:   # a later line of the same key with a tiling no plan has: skipped
+        f.write(f"{tag} {key} {J} 7 {chunk} {ms}\nnot a cache line\n")
+    sh.tune_cache_clear()
+    op, res2 = sh.op_autotune(pb.uv, M_p, 64, 2, 1e-5, pb.offsets, R_p, reps=1)
+    q = sh.op_query(op)
+    sh.op_destroy(op)
+    assert res2["cached"] == 2 and res2["candidates"] == 0
+    assert (res2["J"], res2["tile"], res2["chunk"]) == (res["J"], res["tile"], res["chunk"])
+    assert q["tile"] == res["tile"]
+    op, res3 = sh.op_autotune(pb.uv, M_p, 64, 2, 1e-5, pb.offsets, R_p, reps=1)   # now in the process cache
+    sh.op_destroy(op)
+    assert res3["cached"] == 1
+    monkeypatch.delenv("SH_TUNE_CACHE")
+    sh.tune_cache_clear()
+    before = path.read_text()
+    op, res4 = sh.op_autotune(pb.uv, M_p, 64, 2, 1e-5, pb.offsets, R_p, reps=1)
+    sh.op_destroy(op)
+    assert res4["cached"] == 0 and path.read_text() == before
