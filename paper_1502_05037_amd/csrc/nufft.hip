@@ -539,13 +539,77 @@ __global__ __launch_bounds__(64 * NWV) void grid_mfma_kernel(const uint2* __rest
   }
 }
 
+// The sum of one cell over the item patches of the neighbour tiles with row offsets DA0..DA1 (n = 3 (da + 1) +
+// (db + 1), in order of n; each tile's items in slot order).  The first item's value of every neighbour is
+// loaded before any is summed, so those loads are in flight together; the load is issued for every neighbour
+// (slot 0 of the patch array, which always exists, where the neighbour has no item covering the cell) and its
+// value is replaced by +0, which leaves the sum unchanged since the sum is never -0.
+template <int J, int T, int DA0, int DA1>
+__device__ __forceinline__ float2 fold_cell(const float2* __restrict__ patches, const int* __restrict__ tile_items,
+                                            int nT, int a, int b, int l1, int l2) {
+  constexpr int P = T + J - 1;
+  constexpr int LO = J / 2 - 1;
+  constexpr int NN = 3 * (DA1 - DA0 + 1);
+  int src[NN], n0[NN], n1[NN];
+  float2 first[NN];
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {   // the neighbours' slot ranges (uniform: scalar loads, issued together)
+    const int da = DA0 + k / 3, db = k % 3 - 1;
+    const int t2 = ((a + da) & (nT - 1)) * nT + ((b + db) & (nT - 1));   // nT is a power of two
+    n0[k] = tile_items[t2];
+    n1[k] = tile_items[t2 + 1];
+  }
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    const int da = DA0 + k / 3, db = k % 3 - 1;
+    const int p1 = l1 - da * T + LO, p2 = l2 - db * T + LO;
+    const bool cover = p1 >= 0 && p1 < P && p2 >= 0 && p2 < P;
+    src[k] = p1 * P + p2;
+    if (!cover) n1[k] = n0[k];                      // no items where the patch does not cover the cell
+    const bool has = n0[k] < n1[k];
+    const float2 v = patches[has ? (size_t)n0[k] * (P * P) + src[k] : 0];
+    // the mask goes through an empty asm so that the compiler does not turn the load back into a
+    // conditional one (which would then be waited for before the next neighbour's load)
+    int m = has ? -1 : 0;
+    asm volatile("" : "+v"(m));
+    first[k] = make_float2(__int_as_float(__float_as_int(v.x) & m), __int_as_float(__float_as_int(v.y) & m));
+  }
+  float sr = 0.f, si = 0.f;
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    sr += first[k].x;
+    si += first[k].y;
+    const float2* p = patches + src[k];
+    int i = n0[k] + 1;
+    for (; i + 4 <= n1[k]; i += 4) {   // four loads in flight
+      const float2 v0 = p[(size_t)i * (P * P)], v1 = p[(size_t)(i + 1) * (P * P)];
+      const float2 v2 = p[(size_t)(i + 2) * (P * P)], v3 = p[(size_t)(i + 3) * (P * P)];
+      sr += v0.x;
+      si += v0.y;
+      sr += v1.x;
+      si += v1.y;
+      sr += v2.x;
+      si += v2.y;
+      sr += v3.x;
+      si += v3.y;
+    }
+    for (; i < n1[k]; ++i) {
+      const float2 v = p[(size_t)i * (P * P)];
+      sr += v.x;
+      si += v.y;
+    }
+  }
+  return make_float2(sr, si);
+}
+
 // Each grid cell = sum over the tiles whose padded patch covers it (3 x 3 neighbourhood, fixed order)
-// of that tile's item patches (slot order).  One work-group per group of 256 cells of a tile.
+// of that tile's item patches (slot order).  One work-group per group of 256 cells of a tile.  A patch reaches
+// J/2 rows into the tile below its own and J/2 - 1 into the one above, so a wave whose cell rows lie clear of
+// both tile edges reads only the neighbours of its own tile row (da = 0); the neighbours it skips would add
+// +0 (no item of theirs covers its cells), so every cell keeps the same sum.
 template <int J, int T>
 __global__ __launch_bounds__(256) void fold_kernel(const float2* __restrict__ patches, const int* __restrict__ tile_items,
                                                    float2* __restrict__ grid, int log2K, int log2T) {
-  constexpr int P = T + J - 1;
-  constexpr int LO = J / 2 - 1;
   constexpr int G = (T * T + 255) / 256;   // work-groups per tile
   const int nT = 1 << (log2K - log2T);
   const int K = 1 << log2K;
@@ -558,60 +622,17 @@ __global__ __launch_bounds__(256) void fold_kernel(const float2* __restrict__ pa
   tile_items += prob * nT * nT;
   grid += (size_t)prob * K * K;
   const int l1 = e / T, l2 = e % T;
-  // neighbour n = 3 (da + 1) + (db + 1).  The first item's value of all nine neighbours is loaded
-  // before any is summed, so those loads are in flight together; the load is issued for every
-  // neighbour (slot 0 of the patch array, which always exists, where the neighbour has no item covering
-  // the cell) and its value is replaced by +0, which leaves the sum unchanged since the sum is never -0.
-  int src[9], n0[9], n1[9];
-  float2 first[9];
-#pragma unroll
-  for (int n = 0; n < 9; ++n) {   // the neighbours' slot ranges (uniform: scalar loads, issued together)
-    const int da = n / 3 - 1, db = n % 3 - 1;
-    const int t2 = ((a + da) & (nT - 1)) * nT + ((b + db) & (nT - 1));   // nT is a power of two
-    n0[n] = tile_items[t2];
-    n1[n] = tile_items[t2 + 1];
-  }
-#pragma unroll
-  for (int n = 0; n < 9; ++n) {
-    const int da = n / 3 - 1, db = n % 3 - 1;
-    const int p1 = l1 - da * T + LO, p2 = l2 - db * T + LO;
-    const bool cover = p1 >= 0 && p1 < P && p2 >= 0 && p2 < P;
-    src[n] = p1 * P + p2;
-    if (!cover) n1[n] = n0[n];                      // no items where the patch does not cover the cell
-    const bool has = n0[n] < n1[n];
-    const float2 v = patches[has ? (size_t)n0[n] * (P * P) + src[n] : 0];
-    // the mask goes through an empty asm so that the compiler does not turn the load back into a
-    // conditional one (which would then be waited for before the next neighbour's load)
-    int m = has ? -1 : 0;
-    asm volatile("" : "+v"(m));
-    first[n] = make_float2(__int_as_float(__float_as_int(v.x) & m), __int_as_float(__float_as_int(v.y) & m));
-  }
-  float sr = 0.f, si = 0.f;
-#pragma unroll
-  for (int n = 0; n < 9; ++n) {   // neighbours in order, each one's items in slot order
-    sr += first[n].x;
-    si += first[n].y;
-    const float2* p = patches + src[n];
-    int i = n0[n] + 1;
-    for (; i + 4 <= n1[n]; i += 4) {   // four loads in flight
-      const float2 v0 = p[(size_t)i * (P * P)], v1 = p[(size_t)(i + 1) * (P * P)];
-      const float2 v2 = p[(size_t)(i + 2) * (P * P)], v3 = p[(size_t)(i + 3) * (P * P)];
-      sr += v0.x;
-      si += v0.y;
-      sr += v1.x;
-      si += v1.y;
-      sr += v2.x;
-      si += v2.y;
-      sr += v3.x;
-      si += v3.y;
-    }
-    for (; i < n1[n]; ++i) {
-      const float2 v = p[(size_t)i * (P * P)];
-      sr += v.x;
-      si += v.y;
-    }
-  }
-  grid[(size_t)(a * T + l1) * K + (b * T + l2)] = make_float2(sr, si);
+  // the wave's first and last cell rows (wave-uniform)
+  const int e0 = e & ~63;
+  const int r0 = e0 / T, r1 = min(e0 + 63, T * T - 1) / T;
+  const bool up = r0 < J / 2;                 // rows reached by the patch of the tile above (da = -1)
+  const bool down = r1 >= T - J / 2 + 1;      // rows reached by the patch of the tile below (da = +1)
+  float2 v;
+  if (up && down) v = fold_cell<J, T, -1, 1>(patches, tile_items, nT, a, b, l1, l2);
+  else if (up) v = fold_cell<J, T, -1, 0>(patches, tile_items, nT, a, b, l1, l2);
+  else if (down) v = fold_cell<J, T, 0, 1>(patches, tile_items, nT, a, b, l1, l2);
+  else v = fold_cell<J, T, 0, 0>(patches, tile_items, nT, a, b, l1, l2);
+  grid[(size_t)(a * T + l1) * K + (b * T + l2)] = v;
 }
 
 __global__ void gather_kernel(const float2* __restrict__ src, const uint32_t* __restrict__ idx, float2* __restrict__ dst,
