@@ -425,7 +425,8 @@ sh_status sh_sdmm_state_import(sh_sdmm s, const void* host, size_t bytes, void* 
  * synchronises it; *rows_out is the number copied, *first_iter (may be NULL) the session iteration count
  * after the first of them (iterations are counted from 1).  When more than `rows` iterations passed since the
  * last read the oldest were overwritten: the copy then starts at the oldest row still held, which
- * *first_iter shows.  Errors: SH_EINVAL (NULL, rows out of range, ring off for read), SH_ENOMEM. */
+ * *first_iter shows.  sh_sdmm_state_import empties the ring and numbers its rows from the imported iteration
+ * count.  Errors: SH_EINVAL (NULL, rows out of range, ring off for read), SH_ENOMEM. */
 sh_status sh_sdmm_metrics_enable(sh_sdmm s, int32_t rows, int32_t* row_width);
 sh_status sh_sdmm_metrics_read(sh_sdmm s, double* host, int32_t max_rows, int32_t* rows_out, int64_t* first_iter,
                                void* stream);

@@ -1167,8 +1167,14 @@ sh_status sh_sdmm_state_import(sh_sdmm s, const void* host, size_t bytes, void* 
     SH_HIP(hipMemcpyAsync(q.ptr, p + off, q.bytes, hipMemcpyHostToDevice, st));
     off += q.bytes;
   }
-  SH_HIP(hipStreamSynchronize(st));
   s->iters_total = hd.iters_total;
+  if (s->ring_rows > 0) {   // the metrics ring starts again, numbered from the imported iteration count
+    const unsigned long long zero = 0;
+    SH_HIP(hipMemcpyAsync(s->ring_ctr.ptr, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+    s->ring_base = s->iters_total;
+    s->ring_next = 0;
+  }
+  SH_HIP(hipStreamSynchronize(st));
   return SH_OK;
 }
 

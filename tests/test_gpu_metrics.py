@@ -5,8 +5,10 @@
   equals the session's own KKT objective and the oracle's ||W Psi^dagger x||_1.
 * Ring mechanics: a 16-row ring read after 10 and after 40 iterations gives rows 1-10, then 25-40 (the oldest
   overwritten), bitwise equal to the rows of a 64-row ring filled by plain launches instead of the replayed
-  graph; the last row agrees with sh_sdmm_result; with the ring switched off a read is refused.  For the
-  analysis prior, block-subset iterations and the synthesis prior.
+  graph; the last row agrees with sh_sdmm_result; a checkpoint imported into a fresh session (whose ring then
+  starts again at the imported iteration count) records the rows the exporting session records next, bit for
+  bit; with the ring switched off a read is refused.  For the analysis prior, block-subset iterations and the
+  synthesis prior.
 """
 import numpy as np
 import pytest
@@ -68,9 +70,9 @@ def test_metrics_follow_the_oracle_history(sh):
     print(f"relative change: iteration 1 {rel_g[0]:.4g} vs {rel_o[0]:.4g}, iteration {iters} {rel_g[-1]:.4g} vs "
           f"{rel_o[-1]:.4g}, worst deviation {dev_rel.max():.2e}; residual/eps worst relative deviation "
           f"{dev_res:.2e}; objective {m['objective'][-1, 0]:.6g} vs oracle {infos[0].objective:.6g}", flush=True)
-    # FP32 iterates: the change between iterates carries their rounding (about 1e-6 of ||x||)
-    assert np.all(dev_rel <= 1e-2)
-    assert dev_res <= 1e-3
+    # FP32 iterates: the change between iterates carries their rounding (measured: 4e-6 and 1e-6 worst)
+    assert np.all(dev_rel <= 1e-4)
+    assert dev_res <= 1e-4
     assert m["objective"][-1, 0] == pytest.approx(obj, rel=1e-12)
     assert m["objective"][-1, 0] == pytest.approx(infos[0].objective, rel=1e-4)
 
@@ -101,6 +103,19 @@ def test_ring_wraps_and_matches_plain_launches(sh, variant):
             sh.sdmm_iterate(b, 40)
             bb = sh.sdmm_metrics_read(b, 1, R, 100)
             resid, rel = sh.sdmm_result(b, None, R)
+            # a checkpoint resumed in a fresh session records the rows the exporting session goes on to record
+            state = sh.sdmm_state_export(b)
+            sh.sdmm_iterate(b, 5)
+            bb2 = sh.sdmm_metrics_read(b, 1, R, 100)
+            c = sh.sdmm_create(op, psi, y, pb.eps, None, None, _params(sh, **base))
+            try:
+                sh.sdmm_metrics_enable(c, 8)
+                sh.sdmm_iterate(c, 3)
+                sh.sdmm_state_import(c, state)
+                sh.sdmm_iterate(c, 5)
+                cc = sh.sdmm_metrics_read(c, 1, R, 100)
+            finally:
+                sh.sdmm_destroy(c)
             sh.sdmm_metrics_enable(a, 0)
             with pytest.raises(sh.SarahipError) as e:
                 sh.sdmm_metrics_read(a, 1, R, 100)
@@ -115,6 +130,9 @@ def test_ring_wraps_and_matches_plain_launches(sh, variant):
     assert (a2["rows"], a2["first_iter"]) == (16, 25)
     assert a3["rows"] == 0
     assert (bb["rows"], bb["first_iter"]) == (40, 1)
+    assert (bb2["rows"], bb2["first_iter"]) == (5, 41) and (cc["rows"], cc["first_iter"]) == (5, 41)
+    for key in ("rel_change", "objective", "resid_over_eps"):
+        np.testing.assert_array_equal(cc[key], bb2[key])
     for key in ("rel_change", "objective", "resid_over_eps"):
         np.testing.assert_array_equal(a1[key], bb[key][:10])
         np.testing.assert_array_equal(a2[key], bb[key][24:])
