@@ -28,6 +28,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// Sum of part[seg * n, (seg + 1) * n), computed by the whole work-group in the order of sum_final below (so
+// that every work-group of a launch, and sum_final, get the same bits), returned to every thread.
+__device__ __forceinline__ double seg_total(const double* __restrict__ part, int n, int seg, double* sh) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[(int64_t)seg * n + i];
+  return block_sum(acc, sh);
+}
+
 // First stages over segments: grid (gridDim.x, P), blockIdx.y = segment; work-group b of segment p
 // reduces a grid-stride slice of the segment into part[p * gridDim.x + b].
 #define SEGMENT_LOOP(i)                                                                     \
@@ -72,13 +80,16 @@ __global__ __launch_bounds__(256) void cg_ap_dot(const float* __restrict__ pv, f
   PART_OUT(r);
 }
 
-// alpha = rs / pAp; x += alpha p; r -= alpha Ap; partial r.r
+// pAp = sum of the p.Ap partials (every work-group; the first of the segment stores it), alpha = rs / pAp;
+// x += alpha p; r -= alpha Ap; partial r.r
 __global__ __launch_bounds__(256) void cg_update_rr(float* __restrict__ x, float* __restrict__ r,
                                                     const float* __restrict__ pv, const float* __restrict__ Ap,
                                                     int64_t per, const double* __restrict__ rs,
-                                                    const double* __restrict__ pAp, double* __restrict__ part) {
+                                                    const double* __restrict__ pap_part, double* __restrict__ pap_out,
+                                                    double* __restrict__ part) {
   __shared__ double sh[256];
-  const double d = pAp[blockIdx.y];
+  const double d = seg_total(pap_part, gridDim.x, blockIdx.y, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) pap_out[blockIdx.y] = d;
   const float alpha = d > 0 ? float(rs[blockIdx.y] / d) : 0.f;
   double acc = 0.0;
   SEGMENT_LOOP(i) {
@@ -89,6 +100,19 @@ __global__ __launch_bounds__(256) void cg_update_rr(float* __restrict__ x, float
   }
   const double rr = block_sum(acc, sh);
   PART_OUT(rr);
+}
+
+// rs_new = sum of the r.r partials (every work-group; the first of the segment stores it), beta = rs_new / rs;
+// p = r + beta p
+__global__ __launch_bounds__(256) void cg_dir_rr(const float* __restrict__ r, float* __restrict__ pv, int64_t per,
+                                                 const double* __restrict__ rs, const double* __restrict__ rr_part,
+                                                 double* __restrict__ rs_out) {
+  __shared__ double sh[256];
+  const double rn = seg_total(rr_part, gridDim.x, blockIdx.y, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) rs_out[blockIdx.y] = rn;
+  const double d = rs[blockIdx.y];
+  const float beta = d > 0 ? float(rn / d) : 0.f;
+  SEGMENT_LOOP(i) pv[i] = fmaf(beta, pv[i], r[i]);
 }
 
 // partials of ||x - xprev||^2 (part) and ||x||^2 (part + P * gridDim.x)
@@ -397,6 +421,7 @@ sh_status Reducer::init(int segments) {
   P = segments;
   rb = RB / P > 1 ? RB / P : 1;   // about RB work-groups in all
   SH_TRY(part.alloc(2 * size_t(P) * rb));
+  SH_TRY(part2.alloc(size_t(P) * rb));
   return SH_OK;
 }
 
@@ -408,17 +433,22 @@ sh_status Reducer::cg_init(const float* a, const float* b, const float* c, const
   return SH_OK;
 }
 
-sh_status Reducer::cg_ap(const float* p, float* Ap, int64_t per, double* pap_out, hipStream_t st, float pc) {
+sh_status Reducer::cg_ap(const float* p, float* Ap, int64_t per, hipStream_t st, float pc) {
   hipLaunchKernelGGL(cg_ap_dot, dim3(rb, P), dim3(256), 0, st, p, Ap, per, part.ptr, pc);
-  hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, pap_out);
   SH_LAUNCHED();
   return SH_OK;
 }
 
 sh_status Reducer::cg_update(float* x, float* r, const float* p, const float* Ap, int64_t per, const double* rs,
-                             const double* pap, double* rs_out, hipStream_t st) {
-  hipLaunchKernelGGL(cg_update_rr, dim3(rb, P), dim3(256), 0, st, x, r, p, Ap, per, rs, pap, part.ptr);
-  if (rs_out) hipLaunchKernelGGL(sum_final, dim3(P), dim3(256), 0, st, part.ptr, rb, rs_out);
+                             double* pap_out, hipStream_t st) {
+  hipLaunchKernelGGL(cg_update_rr, dim3(rb, P), dim3(256), 0, st, x, r, p, Ap, per, rs, part.ptr, pap_out,
+                     part2.ptr);
+  SH_LAUNCHED();
+  return SH_OK;
+}
+
+sh_status Reducer::cg_dir(const float* r, float* p, int64_t per, const double* rs, double* rs_out, hipStream_t st) {
+  hipLaunchKernelGGL(cg_dir_rr, dim3(rb, P), dim3(256), 0, st, r, p, per, rs, part2.ptr, rs_out);
   SH_LAUNCHED();
   return SH_OK;
 }

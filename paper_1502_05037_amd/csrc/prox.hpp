@@ -9,7 +9,7 @@ namespace sh {
 // a[p*per, (p+1)*per)); segment p's result lands in out[p] (device memory).  The tree depends only on
 // (per, P), so results are reproducible bit for bit.
 struct Reducer {
-  DevBuf<double> part;
+  DevBuf<double> part, part2;   // first-stage partials (part2: the r.r partials between cg_update and cg_dir)
   int P = 1, rb = 512;   // segments, first-stage work-groups per segment
   sh_status init(int segments = 1);
   sh_status dot(const float* a, const float* b, int64_t per, double* out, hipStream_t st);
@@ -20,16 +20,20 @@ struct Reducer {
   // out[p] = sum over segment p of (a + fb b + fc c)^2 (b, c may be NULL)
   sh_status comb3_sq(const float* a, const float* b, const float* c, float fb, float fc, int64_t per, double* out,
                      hipStream_t st);
-  // Conjugate-gradient steps fused with the reduction that follows them (same trees as dot):
+  // Conjugate-gradient steps fused with the reductions around them (same trees as dot).  A step is cg_ap,
+  // cg_update, then (unless it is the last) cg_dir; the final sum of a dot product is taken by every
+  // work-group of the kernel that consumes it, not by a launch of its own:
   //   cg_init:   r = a + b + c - xc x (c may be NULL), p = r, xprev = x;  rs_out = r.r
-  //   cg_ap:     Ap = pc p + Ap;                                 pap_out = p.Ap
-  //   cg_update: x += alpha p, r -= alpha Ap, alpha = rs / pap;  rs_out = r.r (NULL: not reduced)
+  //   cg_ap:     Ap = pc p + Ap;  partials of p.Ap
+  //   cg_update: pap_out = p.Ap, alpha = rs / pap, x += alpha p, r -= alpha Ap;  partials of r.r
+  //   cg_dir:    rs_out = r.r, beta = rs_out / rs, p = r + beta p
   //   change:    out2[0..P) = ||x - xprev||^2, out2[P..2P) = ||x||^2
   sh_status cg_init(const float* a, const float* b, const float* c, const float* x, float* r, float* p, float* xprev,
                     int64_t per, double* rs_out, hipStream_t st, float xc = 2.f);
-  sh_status cg_ap(const float* p, float* Ap, int64_t per, double* pap_out, hipStream_t st, float pc = 2.f);
+  sh_status cg_ap(const float* p, float* Ap, int64_t per, hipStream_t st, float pc = 2.f);
   sh_status cg_update(float* x, float* r, const float* p, const float* Ap, int64_t per, const double* rs,
-                      const double* pap, double* rs_out, hipStream_t st);
+                      double* pap_out, hipStream_t st);
+  sh_status cg_dir(const float* r, float* p, int64_t per, const double* rs, double* rs_out, hipStream_t st);
   sh_status change(const float* x, const float* xprev, int64_t per, double* out2, hipStream_t st);
 };
 

@@ -71,14 +71,6 @@ __global__ __launch_bounds__(256) void gather_scale(const float2* __restrict__ s
   }
 }
 
-// per problem: beta = rs_new / rs; p = r + beta p
-__global__ void cg_dir(const float* __restrict__ r, float* __restrict__ pv, int64_t per, const double* __restrict__ rs,
-                       const double* __restrict__ rs_new) {
-  SEG_INDEX(per)
-  const double d = rs[p];
-  const float beta = d > 0 ? float(rs_new[p] / d) : 0.f;
-  pv[i] = fmaf(beta, pv[i], r[i]);
-}
 // Dual warm start of the l1 split at s = Psi^dagger x0: the soft threshold's own split of s,
 // y = soft(s, gamma_p W), z = s - y (= s clipped to [-gamma_p W, gamma_p W], the subgradient gamma W sign(s)
 // where |s| exceeds the threshold); v = y - z.
@@ -588,7 +580,6 @@ sh_status sdmm_step_synthesis(sh_sdmm s, hipStream_t st) {
   Work& w = s->w;
   const int P = s->P;
   const int64_t N = s->N, per = s->per, Dp = s->Dper;
-  const dim3 gD(nblk(Dp), P);
   double *s_rs = s->s_rs, *s_pap = s->s_pap, *s_misc = s->s_misc;
   SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.t2.ptr, false, nullptr, st));   // vphi carries c_b and -s_hat
   hipLaunchKernelGGL(comb_kernel, dim3(nblk(N)), dim3(256), 0, st, w.t1.ptr, w.t2.ptr, w.vpos.ptr, w.x.ptr, N);
@@ -602,12 +593,9 @@ sh_status sdmm_step_synthesis(sh_sdmm s, hipStream_t st) {
     SH_TRY(sh::toeplitz_apply(op, w.toep.Ht.ptr, w.t1.ptr, w.toep.tq.ptr, w.t2.ptr, st));     // T Psi p
     hipLaunchKernelGGL(add_kernel, dim3(nblk(N)), dim3(256), 0, st, w.t1.ptr, w.t2.ptr, N);
     SH_TRY(sh_psi_adj(s->psi, w.t1.ptr, w.aAp.ptr, st));
-    SH_TRY(w.red.cg_ap(w.ap.ptr, w.aAp.ptr, Dp, s_pap + k * P, st, 1.f));                    // p + Psi^T (I + T) Psi p
-    const bool more = k + 1 < s->kcg;
-    SH_TRY(w.red.cg_update(w.alpha.ptr, w.ar.ptr, w.ap.ptr, w.aAp.ptr, Dp, s_rs + k * P, s_pap + k * P,
-                           more ? s_rs + (k + 1) * P : nullptr, st));
-    if (more)
-      hipLaunchKernelGGL(cg_dir, gD, dim3(256), 0, st, w.ar.ptr, w.ap.ptr, Dp, s_rs + k * P, s_rs + (k + 1) * P);
+    SH_TRY(w.red.cg_ap(w.ap.ptr, w.aAp.ptr, Dp, st, 1.f));                                  // p + Psi^T (I + T) Psi p
+    SH_TRY(w.red.cg_update(w.alpha.ptr, w.ar.ptr, w.ap.ptr, w.aAp.ptr, Dp, s_rs + k * P, s_pap + k * P, st));
+    if (k + 1 < s->kcg) SH_TRY(w.red.cg_dir(w.ar.ptr, w.ap.ptr, Dp, s_rs + k * P, s_rs + (k + 1) * P, st));
   }
   SH_LAUNCHED();
   SH_TRY(sh_psi_fwd(s->psi, w.alpha.ptr, w.x.ptr, st));                                       // x_n = Psi alpha_n
@@ -627,7 +615,6 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   Work& w = s->w;
   const int P = s->P;
   const int64_t N = s->N, per = s->per;
-  const dim3 gP(nblk(per), P);
   double *s_rs = s->s_rs, *s_pap = s->s_pap, *s_misc = s->s_misc;
   if (s->synth) {
     SH_TRY(sdmm_step_synthesis(s, st));
@@ -653,12 +640,9 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
       SH_TRY(sh::phi_forward(op, w.p.ptr, w.vtmp.ptr, false, w.cblk.ptr, st));
       SH_TRY(sh::phi_adjoint(op, w.vtmp.ptr, w.Ap.ptr, false, w.cblk.ptr, st));
     }
-    SH_TRY(w.red.cg_ap(w.p.ptr, w.Ap.ptr, per, s_pap + k * P, st));
-    const bool more = k + 1 < s->kcg;
-    SH_TRY(w.red.cg_update(w.x.ptr, w.r.ptr, w.p.ptr, w.Ap.ptr, per, s_rs + k * P, s_pap + k * P,
-                           more ? s_rs + (k + 1) * P : nullptr, st));
-    if (more)
-      hipLaunchKernelGGL(cg_dir, gP, dim3(256), 0, st, w.r.ptr, w.p.ptr, per, s_rs + k * P, s_rs + (k + 1) * P);
+    SH_TRY(w.red.cg_ap(w.p.ptr, w.Ap.ptr, per, st));
+    SH_TRY(w.red.cg_update(w.x.ptr, w.r.ptr, w.p.ptr, w.Ap.ptr, per, s_rs + k * P, s_pap + k * P, st));
+    if (k + 1 < s->kcg) SH_TRY(w.red.cg_dir(w.r.ptr, w.p.ptr, per, s_rs + k * P, s_rs + (k + 1) * P, st));
   }
   SH_LAUNCHED();
   // ---- relative change
@@ -958,11 +942,11 @@ size_t sdmm_ws_bytes(sh_op op, int q, const sh_sdmm_params* prm) {
   const size_t K = op->K, KK = K * K, n = op->n, kcg = prm->cg_iters;
   const size_t rb = 512 / P > 1 ? 512 / P : 1;
   size_t pers = 9 * al(4 * N) + 4 * al(4 * D) + 5 * al(8 * M) + al(8 * (2 * kcg + 1 + MISC_N) * P) + 3 * al(8 * R) +
-                al(8 * P) + al(8 * (8 * P + 2 * R)) + al(4 * R) + al(4 * P) + al(8 * 2 * P * rb);
+                al(8 * P) + al(8 * (8 * P + 2 * R)) + al(4 * R) + al(4 * P) + al(8 * 2 * P * rb) + al(8 * P * rb);
   if (prm->synthesis) pers += 5 * al(4 * D);
   if (prm->block_fraction < 1) pers += al(4 * R) + al(8) + al(4 * N);
   if (prm->toeplitz) pers += al(4 * P * KK) + al(8 * P * n * K);
-  size_t tmp = al(8 * 2 * 512);   // the finiteness check's one-segment reducer
+  size_t tmp = al(8 * 2 * 512) + al(8 * 512);   // the finiteness check's one-segment reducer
   if (prm->block_norm) {
     const size_t G = std::max<size_t>(1, std::min<size_t>(R, (size_t(1) << 26) / KK));
     tmp = std::max(tmp, al(4 * G * KK) + al(4 * R));
@@ -970,7 +954,8 @@ size_t sdmm_ws_bytes(sh_op op, int q, const sh_sdmm_params* prm) {
   if (prm->toeplitz)
     tmp = std::max(tmp, (prm->block_norm ? al(4 * R) : 0) + al(8 * M) + al(4 * P * n * n) + 2 * al(8 * P * KK) +
                             al(4 * P));
-  if (!(prm->nu > 0)) tmp = std::max(tmp, 2 * al(4 * N) + al(8 * M) + al(8 * 3 * P) + al(8 * 2 * P * rb));
+  if (!(prm->nu > 0))
+    tmp = std::max(tmp, 2 * al(4 * N) + al(8 * M) + al(8 * 3 * P) + al(8 * 2 * P * rb) + al(8 * P * rb));
   return pers + tmp;
 }
 
