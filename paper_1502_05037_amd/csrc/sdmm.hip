@@ -297,6 +297,11 @@ struct sh_sdmm_s {
   hipGraphExec_t gexec = nullptr;
   const float* g_Wp = nullptr;     // the weights pointer baked into gexec
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // The dictionary's branch of an iteration (Psi v_psi before CG; Psi^dagger x and the l1 step after it) runs
+  // on a second stream beside the data term's branch (Phi^dagger before CG; Phi x, the ball step and the
+  // positivity step after it): the two touch disjoint buffers and join before their results are used.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // Per-iteration metrics ring (sh_sdmm_metrics_enable): ring_rows rows of 2P + R doubles, one written by every
   // iteration (inside the replayed graph); ring_ctr counts the rows written since the ring was enabled.
   sh::DevBuf<double> ring;
@@ -305,6 +310,12 @@ struct sh_sdmm_s {
   int ring_base = 0;                  // iters_total when the ring was enabled
   unsigned long long ring_next = 0;   // the first row not yet handed to the caller
   ~sh_sdmm_s() {
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
@@ -610,6 +621,19 @@ sh_status sdmm_step_synthesis(sh_sdmm s, hipStream_t st) {
 
 // One SDMM iteration of all P problems, enqueued on `st` with no host synchronisation, no memset
 // and no allocation (so that it can be captured into a graph).
+// The side stream starts after the work enqueued on st so far (fork) / st continues after the side stream's
+// work (join).  Under graph capture these are the captured graph's branch and merge.
+sh_status fork_side(sh_sdmm s, hipStream_t st) {
+  SH_HIP(hipEventRecord(s->ev_fork, st));
+  SH_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+  return SH_OK;
+}
+sh_status join_side(sh_sdmm s, hipStream_t st) {
+  SH_HIP(hipEventRecord(s->ev_join, s->side));
+  SH_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+  return SH_OK;
+}
+
 sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   sh_op op = s->op;
   Work& w = s->w;
@@ -620,8 +644,9 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
     SH_TRY(sdmm_step_synthesis(s, st));
     return ring_step(s, st);
   }
-  // ---- x-update by CG from x_{n-1}
-  SH_TRY(sh_psi_fwd(s->psi, w.vpsi.ptr, w.t1.ptr, st));
+  // ---- x-update by CG from x_{n-1}; its right-hand side's dictionary term on the side stream
+  SH_TRY(fork_side(s, st));
+  SH_TRY(sh_psi_fwd(s->psi, w.vpsi.ptr, w.t1.ptr, s->side));
   if (s->stoch) {
     // this iteration's blocks; b - Q x_{n-1} from the running image Phi_hat^T v_phi and a Toeplitz product
     hipLaunchKernelGGL(block_mask_kernel, dim3(1), dim3(1024), 0, st, (uint64_t)s->prm.block_seed, w.ctr.ptr, s->R,
@@ -632,6 +657,7 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   } else {
     SH_TRY(sh::phi_adjoint(op, w.vphi.ptr, w.t2.ptr, false, nullptr, st));   // vphi carries c_b
   }
+  SH_TRY(join_side(s, st));
   SH_TRY(w.red.cg_init(w.t1.ptr, w.t2.ptr, w.vpos.ptr, w.x.ptr, w.r.ptr, w.p.ptr, w.xprev.ptr, per, s_rs, st));
   for (int k = 0; k < s->kcg; ++k) {
     if (s->prm.toeplitz) {
@@ -648,9 +674,10 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
   // ---- relative change
   static_assert(MISC_X == MISC_DX + 1, "change() writes dx^2 then x^2");
   SH_TRY(w.red.change(w.x.ptr, w.xprev.ptr, per, s_misc + MISC_DX * P, st));
-  // ---- splits
-  SH_TRY(sh_psi_adj(s->psi, w.x.ptr, w.spsi.ptr, st));
-  SH_TRY(sh::launch_prox_l1(s->Dper, P, w.spsi.ptr, w.zpsi.ptr, s->Wp, w.gamma.ptr, 0.f, w.vpsi.ptr, st));
+  // ---- splits: the l1 split on the side stream, the data and positivity splits on st
+  SH_TRY(fork_side(s, st));
+  SH_TRY(sh_psi_adj(s->psi, w.x.ptr, w.spsi.ptr, s->side));
+  SH_TRY(sh::launch_prox_l1(s->Dper, P, w.spsi.ptr, w.zpsi.ptr, s->Wp, w.gamma.ptr, 0.f, w.vpsi.ptr, s->side));
   if (s->stoch) {   // the selected blocks only: their images, ball steps and change of Phi_hat^T v_phi
     SH_TRY(sh::phi_forward(op, w.x.ptr, w.sphi.ptr, false, nullptr, st, w.bmask.ptr));
     SH_TRY(sh::launch_prox_ball_subset(op, w.sphi.ptr, w.zphi.ptr, w.yhat.ptr, w.eps_hat.ptr, w.rho.ptr, w.resid.ptr,
@@ -664,6 +691,7 @@ sh_status sdmm_step(sh_sdmm s, hipStream_t st) {
                                 w.vphi.ptr, true, w.cblk.ptr, st));
   }
   SH_TRY(sh::launch_prox_pos(N, w.x.ptr, w.zpos.ptr, w.vpos.ptr, st));
+  SH_TRY(join_side(s, st));
   return ring_step(s, st);
 }
 
@@ -994,6 +1022,12 @@ sh_status sdmm_create(sh_op op, sh_psi psi, const float* y, const double* eps, c
     st = sdmm_setup(s, y, eps, W, x0, (hipStream_t)stream);
   }
   if (st == SH_OK) st = hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? SH_OK : SH_EDEVICE;
+  if (st == SH_OK && (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess ||
+                      hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                      hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess)) {
+    sh::set_error("creating the session's second stream failed");
+    st = SH_EDEVICE;
+  }
   if (st != SH_OK) {
     delete s;
     return st;
