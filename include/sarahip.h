@@ -452,6 +452,8 @@ sh_status sh_sdmm_destroy(sh_sdmm s);
  * MFMA products with float32 accumulation; float32 master weights, gradients
  * and Adam state.
  * Images: device float32, B x H x W, H and W divisible by 2^(L-1).
+ * A handle keeps its activations and its bfloat16 weight operands (converted again only after the
+ * parameters change): calls on one handle must be ordered, on one stream or by the caller.
  * ------------------------------------------------------------------------- */
 typedef struct sh_unet_s* sh_unet;
 /* base: multiple of 16 in [16, 128]; levels 1..6.  Parameters start at zero.  Synchronous. */

@@ -643,6 +643,7 @@ struct sh_unet_s {
   int64_t nparams = 0, nops = 0;
   sh::DevBuf<float> params, grads, m, v;
   sh::DevBuf<uint16_t> ops;
+  bool ops_current = false;  // ops hold the bfloat16 operands of the current params (enqueued)
   int64_t t = 0;           // Adam steps taken
   std::unique_ptr<Acts> ap;  // activations and scratch of the last (B, H, W)
   sh::DevBuf<float> dwg;     // weight-gradient product (sized at creation)
@@ -782,7 +783,11 @@ sh_status gemm_wgrad(sh_unet u, const uint16_t* A, int lda, int M, const uint16_
   return SH_OK;
 }
 
+// The products' bfloat16 weight operands from the float32 parameters, again only after the parameters changed
+// (set_params, an Adam step): repeated forward passes with the same weights reuse them.  The conversion is
+// enqueued on st, ahead of the products that read it on the same stream.
 sh_status prep_weights(sh_unet u, hipStream_t st) {
+  if (u->ops_current) return SH_OK;
   for (const Layer& ly : u->layers) {
     const float* W = u->params.ptr + ly.w_off;
     uint16_t* of = u->ops.ptr + ly.op_f;
@@ -798,6 +803,7 @@ sh_status prep_weights(sh_unet u, hipStream_t st) {
     }
   }
   SH_LAUNCHED();
+  u->ops_current = true;
   return SH_OK;
 }
 
@@ -1053,6 +1059,7 @@ sh_status sh_unet_set_params(sh_unet u, const float* host, int64_t n) {
       return SH_ENONFINITE;
     }
   SH_HIP(hipMemcpy(u->params.ptr, host, n * sizeof(float), hipMemcpyHostToDevice));
+  u->ops_current = false;
   SH_HIP(hipMemset(u->m.ptr, 0, n * sizeof(float)));
   SH_HIP(hipMemset(u->v.ptr, 0, n * sizeof(float)));
   u->t = 0;
@@ -1105,6 +1112,7 @@ sh_status sh_unet_train_step(sh_unet u, const float* x, const float* target, int
                      u->v.ptr, u->nparams, lr, (float)b1, (float)b2, 1e-8f, (float)(1.0 - std::pow(b1, (double)u->t)),
                      (float)(1.0 - std::pow(b2, (double)u->t)));
   SH_LAUNCHED();
+  u->ops_current = false;
   if (loss_out) {
     SH_HIP(hipMemcpyAsync(loss_out, u->ap->loss.ptr, sizeof(double), hipMemcpyDeviceToHost, st));
     SH_HIP(hipStreamSynchronize(st));

@@ -102,6 +102,42 @@ def test_adam_step_closed_form_and_training_reduces_loss(sh):
         sh.unet_destroy(u)
 
 
+def test_weight_operands_follow_parameter_changes(sh):
+    """The bfloat16 weight operands are converted once per set of parameters: a forward pass after set_params or
+    after a training step uses the new parameters (bit for bit the output of a fresh handle loaded with them),
+    and repeated forward passes with unchanged parameters agree bit for bit."""
+    base, levels, n, B = 16, 3, 32, 2
+    pa, pb = _init(base, levels, 5), _init(base, levels, 6)
+    x, t = _data(B, n, 7)
+    xd, td = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    u, v = sh.unet_create(base, levels), sh.unet_create(base, levels)
+    try:
+        y = torch.empty_like(xd)
+        yref = torch.empty_like(xd)
+
+        def fwd(h, out):
+            sh.unet_forward(h, xd, out)
+            torch.cuda.synchronize()
+            return out.cpu().numpy().copy()
+
+        sh.unet_set_params(u, pa)
+        ya = fwd(u, y)
+        np.testing.assert_array_equal(fwd(u, y), ya)
+        sh.unet_set_params(u, pb)
+        sh.unet_set_params(v, pb)
+        yb = fwd(u, y)
+        np.testing.assert_array_equal(yb, fwd(v, yref))
+        assert not np.array_equal(ya, yb)
+        sh.unet_train_step(u, xd, td, 1e-3)
+        yc = fwd(u, y)
+        sh.unet_set_params(v, sh.unet_get_params(u))
+        np.testing.assert_array_equal(yc, fwd(v, yref))
+        assert not np.array_equal(yb, yc)
+    finally:
+        sh.unet_destroy(u)
+        sh.unet_destroy(v)
+
+
 def test_unet_argument_errors(sh):
     for base, levels in ((8, 4), (24, 4), (16, 0), (16, 7)):
         with pytest.raises(sh.SarahipError) as e:
