@@ -69,24 +69,36 @@ template <int L, int R, bool INV>
 __device__ __forceinline__ void stage(float2* buf, const float2* __restrict__ tw, int Ns, int lt, int tpt) {
   constexpr int NB = L / R;                      // butterflies per sequence
   constexpr int PER = (NB + L / 8 - 1) / (L / 8); // butterflies per thread (tpt = L/8)
-  float2 v[PER][R];
+  float2 v[PER][R], w[PER][R];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = lt + q * tpt;
 #pragma unroll
     for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * NB];
   }
+  // the twiddles do not depend on the sequence: their loads are issued before the barrier, so that they are in
+  // flight with the LDS reads (the first stage, Ns = 1, has none)
+  if (Ns > 1) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int k = (lt + q * tpt) % Ns;
+      const int step = L / (Ns * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[q][r] = tw[r * k * step];
+    }
+  }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = lt + q * tpt;
     const int k = j % Ns;
-    const int step = L / (Ns * R);
+    if (Ns > 1) {
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-      float2 w = tw[r * k * step];
-      if (INV) w.y = -w.y;
-      v[q][r] = cmul(v[q][r], w);
+      for (int r = 1; r < R; ++r) {
+        float2 t = w[q][r];
+        if (INV) t.y = -t.y;
+        v[q][r] = cmul(v[q][r], t);
+      }
     }
     dft<R, INV>(v[q]);
     const int base = (j / Ns) * Ns * R + k;
