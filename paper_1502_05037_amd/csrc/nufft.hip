@@ -448,14 +448,13 @@ __global__ __launch_bounds__(64 * NWV) void grid_mfma_kernel(const uint2* __rest
   const float* brow = &stg[wave][h][2 * J + ub * 4 + i4][0];
   float* const mycp = cp + r * PL + (mybase + tb * 4) * PR + ub * 4 + i4;
   float* wcol = &stg[wave][h][0][jl];     // phase A: this lane's column
-  // The current run of this lane's stream: this lane's first copy address under it, its sums so far (matrix
-  // accumulators) and the copy's values under it, read when the run started.  A stream starts at cell
-  // offset 0 with zero sums and zero values read, which is what the cleared copy holds there, so its first
+  // The current run of this lane's stream: this lane's first copy address under it and the copy's values
+  // under it plus the run's products so far (matrix accumulators, loaded from the copy when the run started).
+  // A stream starts at cell offset 0 with zeros, which is what the cleared copy holds there, so its first
   // write-back needs no special case.
   float* cur = mycp;
   int curv = 0;                             // cell offset of the current run (first-axis lanes of phase A)
   f4 acc = {0.f, 0.f, 0.f, 0.f};
-  float old[4] = {0.f, 0.f, 0.f, 0.f};
   for (int b = 0; b < nbatch; ++b) {
     const bool valid = lo + b * NB + jl < hi;
     // past the stream's end: weight 0 (coordinate 0 keeps the weights finite)
@@ -478,14 +477,19 @@ __global__ __launch_bounds__(64 * NWV) void grid_mfma_kernel(const uint2* __rest
 #pragma unroll
       for (int t = 0; t < J; ++t) wcol[(2 * J + t) * SP] = w[t];
     }
-    const int left = __shfl(cell, lane - 1);
+    // the previous visibility's cell: lane - 1 within each row of 16 lanes (DPP row_shr:1; lane 0 of a row
+    // keeps its own value and takes curv instead)
+    const int left = __builtin_amdgcn_update_dpp(cell, cell, 0x111, 0xf, 0xf, false);
     const int prev = jl == 0 ? curv : left;
     // bit 32 h + j: stream h starts a run at its visibility j (the first axis's lanes decide)
     const uint64_t starts = __ballot(!ax && valid && cell != prev);
     const uint32_t any = uint32_t(starts) | uint32_t(starts >> 32);
     // the cell of the stream's last visibility of this batch, for the next batch's first comparison (when
     // that visibility is past the stream's end, so are all later ones, and the value is never used)
-    curv = __shfl(cell, (lane & 32) + NB - 1);
+    {
+      const int c0 = __builtin_amdgcn_readlane(cell, NB - 1), c1 = __builtin_amdgcn_readlane(cell, 32 + NB - 1);
+      curv = h ? c1 : c0;
+    }
     wave_lds_order();                       // staged rows visible to every lane
     // every operand of the batch in registers (128-bit reads), so that the steps never wait for LDS except for
     // the values under a new run
@@ -503,16 +507,20 @@ __global__ __launch_bounds__(64 * NWV) void grid_mfma_kernel(const uint2* __rest
       if (__builtin_expect((any >> j) & 1, 0)) {   // a stream of this wave starts a run here
         const uint64_t sel = (((starts >> j) & 1) ? 0x00000000ffffffffull : 0ull) |
                              (((starts >> (32 + j)) & 1) ? 0xffffffff00000000ull : 0ull);
+        // the new run's cell offsets of both streams (uniform values, read outside the lane mask)
+        const int n0 = __builtin_amdgcn_readlane(cell, j), n1 = __builtin_amdgcn_readlane(cell, 32 + j);
         if (__builtin_amdgcn_inverse_ballot_w64(sel)) {   // the lanes of the streams that start a run
-          // write the finished run back (its sums plus the values read when it started), then read the
-          // values under the new run and restart from zero
+          // write the finished run back (the copy's values plus its products), then load the values under
+          // the new run into the accumulators: the run's products add to them in order
 #pragma unroll
-          for (int q = 0; q < 4; ++q) cur[q * PR] = old[q] + acc[q];
+          for (int q = 0; q < 4; ++q) cur[q * PR] = acc[q];
           wave_lds_order();                 // the new run's window may overlap: read after the write
-          cur = mycp + (h ? __builtin_amdgcn_readlane(cell, 32 + j) : __builtin_amdgcn_readlane(cell, j));
+          cur = mycp + (h ? n1 : n0);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) old[q] = cur[q * PR];
-          acc = f4{0.f, 0.f, 0.f, 0.f};
+          for (int q = 0; q < 4; ++q) acc[q] = cur[q * PR];
+          // wait here for the LDS reads (lgkmcnt 0, the other counters left alone), so that the steps after the
+          // join do not each wait for every read of the batch
+          __builtin_amdgcn_s_waitcnt(0xC07F);
         }
       }
       acc = __builtin_amdgcn_mfma_f32_4x4x1f32(av[j], bv[j], acc, 0, 0, 0);
@@ -520,7 +528,7 @@ __global__ __launch_bounds__(64 * NWV) void grid_mfma_kernel(const uint2* __rest
     wave_lds_order();                       // staged rows consumed before the next phase A
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) cur[q * PR] = old[q] + acc[q];
+  for (int q = 0; q < 4; ++q) cur[q * PR] = acc[q];
   __syncthreads();
   float2* dst = patches + (size_t)it.w * PP;
   for (int e = tid; e < PP; e += 64 * NWV) {
