@@ -204,6 +204,115 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
     }
 }
 
+// Direct 3x3 convolution of an NHWC bf16 image whose channel count C is a multiple of 32, as a product on the
+// MFMA units: C[p][n] = sum_{c, tap} x[p + tap offset][c] Wop[n][tap*C + c] (+ bias[n]) (relu), the same
+// product as gemm_nt over the implicit im2col (zero outside the image) with the k-sum taken channel chunk by
+// channel chunk and tap by tap inside each chunk.  A work-group owns an 8 x 32 pixel tile of one image and TN
+// (64 or 32) output channels; each of its four waves takes two tile rows (64 pixels) and all TN channels, as
+// 4 x TN/16 blocks of v_mfma_f32_16x16x32_bf16.  Per chunk of 32 channels the 10 x 34 input patch and the nine
+// taps' weight rows are staged in LDS once, and every tap's A operand is the patch read at a constant offset,
+// so no gather arithmetic is repeated per tap and the weights are read once per 256 pixels.  The next chunk is
+// loaded into registers while the current one is multiplied.  The MFMA operand and result layouts are those
+// of gemm_nt.
+template <int TN>
+__global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, int ldx, int H, int W, int Cin,
+                                                const uint16_t* __restrict__ Bw, int ldb, int N, int tiles_x,
+                                                int tiles_img, const float* __restrict__ bias, int relu,
+                                                float* __restrict__ Cout, int ldc, uint16_t* __restrict__ Cb,
+                                                int ldcb) {
+  constexpr int TW = 32, TH = 8, BI = 4, BJ = TN / 16;
+  constexpr int PW = TW + 2, NPIX = (TH + 2) * PW;
+  constexpr int CS = 40;                           // LDS pitch of a pixel or weight row: 32 channels + 8
+  constexpr int NPP = NPIX * 4, NWP = 9 * TN * 4;  // 16-byte pieces of the patch and of the weights
+  constexpr int NA = (NPP + 255) / 256, NB = (NWP + 255) / 256;   // pieces per thread
+  __shared__ __attribute__((aligned(16))) uint16_t Ps[NPIX * CS];
+  __shared__ __attribute__((aligned(16))) uint16_t Ws[9 * TN * CS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bimg = blockIdx.x / tiles_img, t = blockIdx.x - bimg * tiles_img;
+  const int ty0 = (t / tiles_x) * TH, tx0 = (t % tiles_x) * TW;
+  const int n0 = blockIdx.y * TN;
+  f32x4 acc[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // this thread's pieces: source offsets in elements without the chunk's channel offset (-1: zero, -2: none;
+  // the host checks that the offsets fit in 30 bits)
+  int sa[NA], sb[NB];
+#pragma unroll
+  for (int e = 0; e < NA; ++e) {
+    const int pc = tid + 256 * e, pix = pc >> 2, part = pc & 3;
+    const int py = pix / PW, px = pix - py * PW;
+    const int y = ty0 - 1 + py, xx = tx0 - 1 + px;
+    sa[e] = pc >= NPP ? -2 : (y >= 0 && y < H && xx >= 0 && xx < W) ? ((bimg * H + y) * W + xx) * ldx + 8 * part : -1;
+  }
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const int q = tid + 256 * e, part = q & 3, row = q >> 2;   // row = tap * TN + r
+    const int tap = row / TN, r = row - tap * TN;
+    sb[e] = q >= NWP ? -2 : n0 + r < N ? (n0 + r) * ldb + tap * Cin + 8 * part : -1;
+  }
+  uint4 ra[NA], rb[NB];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) ra[e] = sa[e] >= 0 ? *(const uint4*)(x + sa[e] + c0) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) rb[e] = sb[e] >= 0 ? *(const uint4*)(Bw + sb[e] + c0) : make_uint4(0, 0, 0, 0);
+  };
+  // A rows of this lane (block i): tile pixel q = 64 wave + 16 i + lane % 16 (row 2 wave + i / 2), channels
+  // 8 (lane / 16) ..; B rows: output channel 16 j + lane % 16
+  const int abase = ((2 * wave) * PW + (lane & 15)) * CS + 8 * (lane >> 4);
+  const int bbase = (lane & 15) * CS + 8 * (lane >> 4);
+  load(0);
+  for (int c0 = 0; c0 < Cin; c0 += 32) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int pc = tid + 256 * e;
+      if (sa[e] != -2) *(uint4*)&Ps[(pc >> 2) * CS + 8 * (pc & 3)] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int q = tid + 256 * e;
+      if (sb[e] != -2) *(uint4*)&Ws[(q >> 2) * CS + 8 * (q & 3)] = rb[e];
+    }
+    __syncthreads();
+    if (c0 + 32 < Cin) load(c0 + 32);   // in flight during the products below
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int toff = ((tap / 3) * PW + tap % 3) * CS;
+      bf16x8 a[BI], b[BJ];
+#pragma unroll
+      for (int i = 0; i < BI; ++i) a[i] = *(const bf16x8*)&Ps[abase + ((i >> 1) * PW + 16 * (i & 1)) * CS + toff];
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) b[j] = *(const bf16x8*)&Ws[(tap * TN + 16 * j) * CS + bbase];
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D[i][j] of a 16x16 block: lane holds rows 4*(lane/16) + r, column lane%16
+#pragma unroll
+  for (int j = 0; j < BJ; ++j) {
+    const int n = n0 + j * 16 + (lane & 15);
+    if (n >= N) continue;
+    const float bv = bias ? bias[n] : 0.f;
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int y = ty0 + 2 * wave + (i >> 1), xx = tx0 + 16 * (i & 1) + 4 * (lane >> 4) + r;
+        if (y >= H || xx >= W) continue;
+        const int64_t m = (int64_t)(bimg * H + y) * W + xx;
+        float v = acc[i][j][r] + bv;
+        if (relu) v = fmaxf(v, 0.f);
+        if (Cout) Cout[m * ldc + n] = v;
+        if (Cb) Cb[m * ldcb + n] = f2bf(v);
+      }
+  }
+}
+
 // out[i] = sum_z part[z*n + i], fixed order
 __global__ void sum_splits(const float* __restrict__ part, int S, int64_t n, float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -471,6 +580,146 @@ __global__ void relu_mask_grad(const float* __restrict__ g, int ldg, const float
   gm[t] = bf2f(act[t]) > 0.f ? f2bf(v) : (uint16_t)0;
 }
 
+// ---- the layout kernels above, eight channels per thread (channel counts, row strides and channel offsets
+// multiples of 8, 16-byte aligned buffers, fewer than 2^31 groups of eight); each element is computed as above
+__device__ __forceinline__ uint16_t u4_get(const uint4& v, int e) {
+  const uint32_t w = e < 2 ? v.x : e < 4 ? v.y : e < 6 ? v.z : v.w;
+  return (uint16_t)(w >> (16 * (e & 1)));
+}
+__device__ __forceinline__ uint4 u4_pack(const uint16_t* h) {
+  return make_uint4(h[0] | (uint32_t(h[1]) << 16), h[2] | (uint32_t(h[3]) << 16), h[4] | (uint32_t(h[5]) << 16),
+                    h[6] | (uint32_t(h[7]) << 16));
+}
+__device__ __forceinline__ void load8f(const float* p, float* v) {
+  const float4 a = *(const float4*)p, b = *(const float4*)(p + 4);
+  v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+}
+__device__ __forceinline__ void store8f(float* p, const float* v) {
+  *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
+  *(float4*)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+__global__ void pool_fwd8(const uint16_t* __restrict__ x, int B, int H, int W, int C, uint16_t* __restrict__ y,
+                          uint8_t* __restrict__ idx) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int C8 = C >> 3, h = H / 2, w = W / 2;
+  if (t >= B * h * w * C8) return;
+  const int c8 = t % C8, po = t / C8;
+  const int b = po / (h * w), rem = po - b * h * w, oy = rem / w, ox = rem - oy * w;
+  uint4 v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = *(const uint4*)(x + ((int64_t)(b * H + 2 * oy + q / 2) * W + 2 * ox + q % 2) * C + 8 * c8);
+  uint16_t bv[8];
+  uint8_t bi[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    float best = -INFINITY;
+    bi[e] = 0;
+    bv[e] = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint16_t hv = u4_get(v[q], e);
+      const float f = bf2f(hv);
+      if (f > best) {
+        best = f;
+        bi[e] = (uint8_t)q;
+        bv[e] = hv;
+      }
+    }
+  }
+  const int64_t o = (int64_t)po * C + 8 * c8;
+  *(uint4*)(y + o) = u4_pack(bv);
+  *(uint2*)(idx + o) = make_uint2(bi[0] | (bi[1] << 8) | (bi[2] << 16) | (uint32_t(bi[3]) << 24),
+                                  bi[4] | (bi[5] << 8) | (bi[6] << 16) | (uint32_t(bi[7]) << 24));
+}
+
+__global__ void pool_bwd8(const float* __restrict__ gout, const uint8_t* __restrict__ idx, int B, int H, int W, int C,
+                          float* __restrict__ gin) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int C8 = C >> 3, h = H / 2, w = W / 2;
+  if (t >= B * h * w * C8) return;
+  const int c8 = t % C8, po = t / C8;
+  const int b = po / (h * w), rem = po - b * h * w, oy = rem / w, ox = rem - oy * w;
+  const int64_t o = (int64_t)po * C + 8 * c8;
+  float g[8];
+  load8f(gout + o, g);
+  const uint2 ib = *(const uint2*)(idx + o);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float r[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = int(((e < 4 ? ib.x : ib.y) >> (8 * (e & 3))) & 255) == q ? g[e] : 0.f;
+    store8f(gin + ((int64_t)(b * H + 2 * oy + q / 2) * W + 2 * ox + q % 2) * C + 8 * c8, r);
+  }
+}
+
+__global__ void tconv_scatter8(const float* __restrict__ Y, const float* __restrict__ bias, int B, int h, int w, int Co,
+                               uint16_t* __restrict__ dst, int ld) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int N8 = Co / 2;   // groups of eight of the 4 Co columns of a row of Y
+  if (t >= B * h * w * N8) return;
+  const int n = 8 * (t % N8), p = t / N8;
+  const int q = n / Co, co = n - q * Co;
+  const int b = p / (h * w), rem = p - b * h * w, y = rem / w, x = rem - y * w;
+  const int64_t po = (int64_t)(b * 2 * h + 2 * y + q / 2) * (2 * w) + 2 * x + q % 2;
+  float v[8];
+  load8f(Y + 8 * (int64_t)t, v);
+  uint16_t r[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = f2bf(v[e] + bias[co + e]);
+  *(uint4*)(dst + po * ld + co) = u4_pack(r);
+}
+
+__global__ void tconv_gather8(const float* __restrict__ g, int ld, int B, int h, int w, int Co,
+                              uint16_t* __restrict__ gG) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int N8 = Co / 2;
+  if (t >= B * h * w * N8) return;
+  const int n = 8 * (t % N8), p = t / N8;
+  const int q = n / Co, co = n - q * Co;
+  const int b = p / (h * w), rem = p - b * h * w, y = rem / w, x = rem - y * w;
+  const int64_t po = (int64_t)(b * 2 * h + 2 * y + q / 2) * (2 * w) + 2 * x + q % 2;
+  float v[8];
+  load8f(g + po * ld + co, v);
+  uint16_t r[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = f2bf(v[e]);
+  *(uint4*)(gG + 8 * (int64_t)t) = u4_pack(r);
+}
+
+__global__ void copy_channels8(const uint16_t* __restrict__ src, int lds, uint16_t* __restrict__ dst, int ldd, int off,
+                               int P, int C) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int C8 = C >> 3;
+  if (t >= P * C8) return;
+  const int p = t / C8, c = 8 * (t - p * C8);
+  *(uint4*)(dst + (int64_t)p * ldd + off + c) = *(const uint4*)(src + (int64_t)p * lds + c);
+}
+
+__global__ void relu_mask_grad8(const float* __restrict__ g, int ldg, const float* __restrict__ g2, int ldg2,
+                                const uint16_t* __restrict__ act, int P, int C, uint16_t* __restrict__ gm) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int C8 = C >> 3;
+  if (t >= P * C8) return;
+  const int p = t / C8, c = 8 * (t - p * C8);
+  float v[8];
+  load8f(g + (int64_t)p * ldg + c, v);
+  if (g2) {
+    float v2[8];
+    load8f(g2 + (int64_t)p * ldg2 + c, v2);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] += v2[e];
+  }
+  const uint4 a = *(const uint4*)(act + 8 * (int64_t)t);
+  uint16_t r[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = bf2f(u4_get(a, e)) > 0.f ? f2bf(v[e]) : (uint16_t)0;
+  *(uint4*)(gm + 8 * (int64_t)t) = u4_pack(r);
+}
+
+inline bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+inline bool fits8(int64_t groups) { return groups < (int64_t(1) << 31) - 256; }
+
 // head: y = relu(z) (the prediction); the loss compares z itself with the target, so the head's relu
 // never blocks the gradient: per-work-group float64 partials of (z - t)^2 and g = bf16(2 (z - t) / cnt)
 __global__ __launch_bounds__(256) void mse_loss(const float* __restrict__ z, const float* __restrict__ tgt, int64_t P,
@@ -727,7 +976,20 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
   const int64_t kchunk = rup(sh::cdiv(K, S), GBK);
   S = (int)sh::cdiv(K, kchunk);
   const Im2col g0{nullptr, 0, 1, 1, 1};
-  if (gat) {
+  if (gat && gat->C % 32 == 0 && gat->ldx % 8 == 0 && ldb % 8 == 0 && K == 9 * gat->C &&
+      M * gat->ldx < (int64_t(1) << 30) && (int64_t)N * ldb < (int64_t(1) << 30) &&
+      (reinterpret_cast<uintptr_t>(gat->x) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0) {
+    // direct convolution: pixel tiles of one image, output-channel tiles
+    SH_REQUIRE(M == (int64_t)u->ap->B * gat->H * gat->W, "internal: convolution shape");
+    const int tiles_x = (int)sh::cdiv(gat->W, 32), tiles_img = tiles_x * (int)sh::cdiv(gat->H, 8);
+    const dim3 grid((unsigned)(tiles_img * u->ap->B), (unsigned)sh::cdiv(N, TN));
+    if (narrow)
+      hipLaunchKernelGGL((conv3_nt<32>), grid, dim3(256), 0, st, gat->x, gat->ldx, gat->H, gat->W, gat->C, B, ldb, N,
+                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb);
+    else
+      hipLaunchKernelGGL((conv3_nt<64>), grid, dim3(256), 0, st, gat->x, gat->ldx, gat->H, gat->W, gat->C, B, ldb, N,
+                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb);
+  } else if (gat) {
     SH_REQUIRE(S == 1 && M == (int64_t)u->ap->B * gat->H * gat->W && K == rup(9 * gat->C, 16),
                "internal: implicit im2col shape");
     if (narrow)
@@ -822,8 +1084,13 @@ sh_status conv_bwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, con
                    int ldg, const float* gin2, int ldg2, int B, int H, int W, float* dx, hipStream_t st) {
   Acts& a = *u->ap;
   const int64_t P = (int64_t)B * H * W;
-  hipLaunchKernelGGL(relu_mask_grad, dim3(nb(P * ly.cout)), dim3(256), 0, st, gin, ldg, gin2, ldg2, out, P, ly.cout,
-                     a.gm.ptr);
+  if (ly.cout % 8 == 0 && ldg % 4 == 0 && (!gin2 || ldg2 % 4 == 0) && al16(gin) && (!gin2 || al16(gin2)) &&
+      fits8(P * ly.cout / 8))
+    hipLaunchKernelGGL(relu_mask_grad8, dim3(nb(P * ly.cout / 8)), dim3(256), 0, st, gin, ldg, gin2, ldg2, out, (int)P,
+                       ly.cout, a.gm.ptr);
+  else
+    hipLaunchKernelGGL(relu_mask_grad, dim3(nb(P * ly.cout)), dim3(256), 0, st, gin, ldg, gin2, ldg2, out, P, ly.cout,
+                       a.gm.ptr);
   // weight gradient: dWg[co][k] = sum_p gm[p][co] [im2col(in), 1][p][k] (k = Kp: the bias)
   const Im2col gi{in, ldin, H, W, ly.cin};
   SH_TRY(gemm_wgrad(u, a.gm.ptr, ly.cout, ly.cout, nullptr, 0, ly.Kp, true, P, u->dwg.ptr, st, &gi));
@@ -853,8 +1120,12 @@ sh_status net_forward(sh_unet u, const float* x, int B, int H, int W, hipStream_
     const int h = H >> l, w = W >> l, c = u->base << l;
     if (l > 0) {
       const int pc = c / 2;
-      hipLaunchKernelGGL(pool_fwd, dim3(nb((int64_t)B * h * w * pc)), dim3(256), 0, st, a.enc[2 * l - 1].ptr, B, 2 * h,
-                         2 * w, pc, a.pooled[l].ptr, a.pidx[l].ptr);
+      if (pc % 8 == 0 && fits8((int64_t)B * h * w * pc / 8))
+        hipLaunchKernelGGL(pool_fwd8, dim3(nb((int64_t)B * h * w * pc / 8)), dim3(256), 0, st, a.enc[2 * l - 1].ptr, B,
+                           2 * h, 2 * w, pc, a.pooled[l].ptr, a.pidx[l].ptr);
+      else
+        hipLaunchKernelGGL(pool_fwd, dim3(nb((int64_t)B * h * w * pc)), dim3(256), 0, st, a.enc[2 * l - 1].ptr, B,
+                           2 * h, 2 * w, pc, a.pooled[l].ptr, a.pidx[l].ptr);
       cur = a.pooled[l].ptr;
       ldc = pc;
     }
@@ -869,10 +1140,17 @@ sh_status net_forward(sh_unet u, const float* x, int B, int H, int W, hipStream_
     const Layer& tl = u->layers[li++];
     SH_TRY(gemm(u, cur, ldc, u->ops.ptr + tl.op_f, tl.cin, Pin, 4 * c, tl.cin, nullptr, false, a.f32a.ptr, 4 * c,
                 nullptr, 0, false, st));
-    hipLaunchKernelGGL(tconv_scatter, dim3(nb(Pin * 4 * c)), dim3(256), 0, st, a.f32a.ptr, u->params.ptr + tl.b_off, B,
-                       h / 2, w / 2, c, a.cat[l].ptr, 2 * c);
-    hipLaunchKernelGGL(copy_channels, dim3(nb(P * c)), dim3(256), 0, st, a.enc[2 * l + 1].ptr, c, a.cat[l].ptr, 2 * c,
-                       c, P, c);
+    if (c % 8 == 0 && fits8(P * c / 8)) {
+      hipLaunchKernelGGL(tconv_scatter8, dim3(nb(Pin * c / 2)), dim3(256), 0, st, a.f32a.ptr, u->params.ptr + tl.b_off,
+                         B, h / 2, w / 2, c, a.cat[l].ptr, 2 * c);
+      hipLaunchKernelGGL(copy_channels8, dim3(nb(P * c / 8)), dim3(256), 0, st, a.enc[2 * l + 1].ptr, c, a.cat[l].ptr,
+                         2 * c, c, (int)P, c);
+    } else {
+      hipLaunchKernelGGL(tconv_scatter, dim3(nb(Pin * 4 * c)), dim3(256), 0, st, a.f32a.ptr, u->params.ptr + tl.b_off,
+                         B, h / 2, w / 2, c, a.cat[l].ptr, 2 * c);
+      hipLaunchKernelGGL(copy_channels, dim3(nb(P * c)), dim3(256), 0, st, a.enc[2 * l + 1].ptr, c, a.cat[l].ptr,
+                         2 * c, c, P, c);
+    }
     SH_TRY(conv_fwd(u, u->layers[li++], a.cat[l].ptr, 2 * c, B, h, w, a.dec[2 * l].ptr, st));
     SH_TRY(conv_fwd(u, u->layers[li++], a.dec[2 * l].ptr, c, B, h, w, a.dec[2 * l + 1].ptr, st));
     cur = a.dec[2 * l + 1].ptr;
@@ -929,8 +1207,12 @@ sh_status net_backward(sh_unet u, const float* target, float* y_out, hipStream_t
     // transposed convolution from the upsampled half
     const int cin = tl.cin;
     const uint16_t* tin = l + 1 < L - 1 ? a.dec[2 * (l + 1) + 1].ptr : a.enc[2 * (l + 1) + 1].ptr;
-    hipLaunchKernelGGL(tconv_gather, dim3(nb(Pin * 4 * c)), dim3(256), 0, st, a.gC.ptr, 2 * c, B, h / 2, w / 2, c,
-                       a.gG.ptr);
+    if (c % 8 == 0 && fits8(Pin * c / 2))
+      hipLaunchKernelGGL(tconv_gather8, dim3(nb(Pin * c / 2)), dim3(256), 0, st, a.gC.ptr, 2 * c, B, h / 2, w / 2, c,
+                         a.gG.ptr);
+    else
+      hipLaunchKernelGGL(tconv_gather, dim3(nb(Pin * 4 * c)), dim3(256), 0, st, a.gC.ptr, 2 * c, B, h / 2, w / 2, c,
+                         a.gG.ptr);
     SH_TRY(gemm_wgrad(u, a.gG.ptr, 4 * c, 4 * c, tin, cin, cin, true, Pin, u->dwg.ptr, st));
     hipLaunchKernelGGL(scatter_tconv_grad, dim3(nb((int64_t)cin * c * 4 + c)), dim3(256), 0, st, u->dwg.ptr, cin, c,
                        u->grads.ptr + tl.w_off, u->grads.ptr + tl.b_off);
@@ -951,8 +1233,12 @@ sh_status net_backward(sh_unet u, const float* target, float* y_out, hipStream_t
                     st));
     if (l > 0) {
       const int pc = c / 2;
-      hipLaunchKernelGGL(pool_bwd, dim3(nb((int64_t)B * h * w * pc)), dim3(256), 0, st, a.gC.ptr, a.pidx[l].ptr, B,
-                         2 * h, 2 * w, pc, a.gA.ptr);
+      if (pc % 8 == 0 && fits8((int64_t)B * h * w * pc / 8))
+        hipLaunchKernelGGL(pool_bwd8, dim3(nb((int64_t)B * h * w * pc / 8)), dim3(256), 0, st, a.gC.ptr, a.pidx[l].ptr,
+                           B, 2 * h, 2 * w, pc, a.gA.ptr);
+      else
+        hipLaunchKernelGGL(pool_bwd, dim3(nb((int64_t)B * h * w * pc)), dim3(256), 0, st, a.gC.ptr, a.pidx[l].ptr, B,
+                           2 * h, 2 * w, pc, a.gA.ptr);
       SH_LAUNCHED();
     }
   }
