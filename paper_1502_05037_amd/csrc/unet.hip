@@ -717,6 +717,40 @@ __global__ void relu_mask_grad8(const float* __restrict__ g, int ldg, const floa
   *(uint4*)(gm + 8 * (int64_t)t) = u4_pack(r);
 }
 
+// 3x3 convolution of a one-channel bf16 image (the network's first layer): out[p][n] = relu(sum_tap x[p + tap
+// offset] wf[n][tap] + bias[n]) with the taps in order and fp32 sums of the exact bf16 products.  One pixel
+// and all N (a multiple of 8, at most 64) output channels per thread; the weights and biases are staged in LDS
+// once per work-group and read there by every lane at the same address.  bf16 output of row stride ldo.
+__global__ __launch_bounds__(256) void conv3_c1(const uint16_t* __restrict__ x, int ldx, int B, int H, int W,
+                                                const uint16_t* __restrict__ wf, int Kp, int N,
+                                                const float* __restrict__ bias, uint16_t* __restrict__ out, int ldo) {
+  __shared__ float ws[64 * 9], bs[64];
+  for (int e = threadIdx.x; e < N * 9; e += 256) ws[e] = bf2f(wf[(e / 9) * Kp + e % 9]);
+  for (int e = threadIdx.x; e < N; e += 256) bs[e] = bias[e];
+  __syncthreads();
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= B * H * W) return;
+  const int b = p / (H * W), rem = p - b * H * W, y = rem / W, xx = rem - y * W;
+  float xv[9];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int sy = y + tap / 3 - 1, sx = xx + tap % 3 - 1;
+    xv[tap] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? bf2f(x[((int64_t)(b * H + sy) * W + sx) * ldx]) : 0.f;
+  }
+  for (int n0 = 0; n0 < N; n0 += 8) {
+    uint16_t r[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float* wr = ws + (n0 + e) * 9;
+      float acc = 0.f;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) acc = fmaf(xv[tap], wr[tap], acc);
+      r[e] = f2bf(fmaxf(acc + bs[n0 + e], 0.f));
+    }
+    *(uint4*)(out + (int64_t)p * ldo + n0) = u4_pack(r);
+  }
+}
+
 inline bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 inline bool fits8(int64_t groups) { return groups < (int64_t(1) << 31) - 256; }
 
@@ -1073,6 +1107,12 @@ sh_status prep_weights(sh_unet u, hipStream_t st) {
 sh_status conv_fwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, int B, int H, int W, uint16_t* out,
                    hipStream_t st) {
   const int64_t P = (int64_t)B * H * W;
+  if (ly.cin == 1 && ly.cout % 8 == 0 && ly.cout <= 64 && fits8(P) && al16(out)) {   // the first layer
+    hipLaunchKernelGGL(conv3_c1, dim3(nb(P)), dim3(256), 0, st, in, ldin, B, H, W, u->ops.ptr + ly.op_f, ly.Kp,
+                       ly.cout, u->params.ptr + ly.b_off, out, ly.cout);
+    SH_LAUNCHED();
+    return SH_OK;
+  }
   const Im2col g{in, ldin, H, W, ly.cin};
   return gemm(u, nullptr, 0, u->ops.ptr + ly.op_f, ly.Kp, P, ly.cout, ly.Kp, u->params.ptr + ly.b_off, true, nullptr, 0,
               out, ly.cout, false, st, &g);
