@@ -293,6 +293,36 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
     __syncthreads();
   }
   // D[i][j] of a 16x16 block: lane holds rows 4*(lane/16) + r, column lane%16
+  if (!Cout && (N % 8) == 0 && (ldcb % 8) == 0 && (reinterpret_cast<uintptr_t>(Cb) & 15) == 0) {
+    // bf16 output only: the tile goes through LDS (the weight area, free after the last barrier) and leaves in
+    // 16-byte stores, each pixel's channels contiguous
+    constexpr int OP = TN + 8;   // pitch of a pixel's row (elements)
+    static_assert(256 * OP <= 9 * TN * CS, "output tile fits the weight area");
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) {
+      const int n = n0 + j * 16 + (lane & 15);
+      const float bv = (bias && n < N) ? bias[n] : 0.f;
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float v = acc[i][j][r] + bv;
+          if (relu) v = fmaxf(v, 0.f);
+          Ws[(64 * wave + 16 * i + 4 * (lane >> 4) + r) * OP + j * 16 + (lane & 15)] = f2bf(v);
+        }
+    }
+    __syncthreads();
+    constexpr int NG = TN / 8;   // groups of eight channels per pixel
+#pragma unroll
+    for (int e = 0; e < 256 * NG / 256; ++e) {
+      const int g = tid + 256 * e, q = g / NG, c8 = g - q * NG;
+      const int y = ty0 + q / TW, xx = tx0 + q % TW, n = n0 + 8 * c8;
+      if (y >= H || xx >= W || n >= N) continue;
+      const int64_t m = (int64_t)(bimg * H + y) * W + xx;
+      *(uint4*)(Cb + m * ldcb + n) = *(const uint4*)&Ws[q * OP + 8 * c8];
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < BJ; ++j) {
     const int n = n0 + j * 16 + (lane & 15);
