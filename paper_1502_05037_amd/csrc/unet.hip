@@ -60,12 +60,19 @@ struct Im2col {
   const uint16_t* x;
   int ldx, H, W, C;
 };
+// Transposed-convolution output of a product (unused when dst is null): column n = (dy*2+dx)*Co + co of row m =
+// input pixel (b, y, x) of a B x h x w batch goes, plus bias[co], as bf16 to channel co of the output pixel
+// (2y+dy, 2x+dx) of the 2h x 2w image, rows of stride ld (Co and ld multiples of 8, dst 16-byte aligned)
+struct Tconv {
+  uint16_t* dst;
+  int ld, h, w, Co;
+};
 
 template <bool GATHER, int WN>
 __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, int lda, const uint16_t* __restrict__ B,
                                                int ldb, int M, int N, int K, int kchunk,
                                                const float* __restrict__ bias, int relu, float* __restrict__ C,
-                                               int ldc, uint16_t* __restrict__ Cb, int ldcb, Im2col g) {
+                                               int ldc, uint16_t* __restrict__ Cb, int ldcb, Im2col g, Tconv tc) {
   // tile TM x TN: 64 x 64 (four waves 2 x 2) or, for products with at most 32 columns, 128 x 32 (4 x 1)
   constexpr int TM = 128 / WN, TN = 32 * WN, AR = TM / 64, BU = TN / 32;
   __shared__ __attribute__((aligned(16))) uint16_t As[TM][GLD];
@@ -184,6 +191,35 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
     __syncthreads();
   }
   // D[i][j] of a 16x16 block: lane holds rows 4*(lane/16) + r, column lane%16
+  if (tc.dst) {
+    // transposed convolution: the bf16 tile goes through LDS (the A area, free after the last barrier) and
+    // each input pixel's run of eight channels of one output pixel leaves in one 16-byte store
+    constexpr int OP = TN + 8;
+    static_assert(TM * OP <= TM * GLD, "output tile fits the A area");
+    uint16_t* Ot = &As[0][0];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = wn * 32 + j * 16 + (lane & 15), n = n0 + col;
+      const float bv = n < N ? bias[n % tc.Co] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ot[(wm * 32 + i * 16 + 4 * (lane >> 4) + r) * OP + col] = f2bf(acc[i][j][r] + bv);
+    }
+    __syncthreads();
+    constexpr int NG = TN / 8;
+#pragma unroll
+    for (int e = 0; e < TM * NG / 256; ++e) {
+      const int gi = tid + 256 * e, row = gi / NG, c8 = gi - row * NG;
+      const int m = m0 + row, n = n0 + 8 * c8;
+      if (m >= M || n >= N) continue;
+      const int q = n / tc.Co, co = n - q * tc.Co;
+      const int b = m / (tc.h * tc.w), rem = m - b * tc.h * tc.w, y = rem / tc.w, x = rem - y * tc.w;
+      const int64_t po = (int64_t)(b * 2 * tc.h + 2 * y + q / 2) * (2 * tc.w) + 2 * x + q % 2;
+      *(uint4*)(tc.dst + po * tc.ld + co) = *(const uint4*)&Ot[row * OP + 8 * c8];
+    }
+    return;
+  }
   if (C) C += (int64_t)blockIdx.z * M * ldc;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -683,22 +719,6 @@ __global__ void pool_bwd8(const float* __restrict__ gout, const uint8_t* __restr
   }
 }
 
-__global__ void tconv_scatter8(const float* __restrict__ Y, const float* __restrict__ bias, int B, int h, int w, int Co,
-                               uint16_t* __restrict__ dst, int ld) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  const int N8 = Co / 2;   // groups of eight of the 4 Co columns of a row of Y
-  if (t >= B * h * w * N8) return;
-  const int n = 8 * (t % N8), p = t / N8;
-  const int q = n / Co, co = n - q * Co;
-  const int b = p / (h * w), rem = p - b * h * w, y = rem / w, x = rem - y * w;
-  const int64_t po = (int64_t)(b * 2 * h + 2 * y + q / 2) * (2 * w) + 2 * x + q % 2;
-  float v[8];
-  load8f(Y + 8 * (int64_t)t, v);
-  uint16_t r[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) r[e] = f2bf(v[e] + bias[co + e]);
-  *(uint4*)(dst + po * ld + co) = u4_pack(r);
-}
 
 __global__ void tconv_gather8(const float* __restrict__ g, int ld, int B, int h, int w, int Co,
                               uint16_t* __restrict__ gG) {
@@ -1024,7 +1044,7 @@ sh_status ensure_acts(sh_unet u, int B, int H, int W) {
 // weight gradients, reduced in fixed order through `part`.
 sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M, int N, int64_t K,
                const float* bias, bool relu, float* C, int ldc, uint16_t* Cb, int ldcb, bool allow_split,
-               hipStream_t st, const Im2col* gat = nullptr) {
+               hipStream_t st, const Im2col* gat = nullptr, const Tconv* tco = nullptr) {
   SH_REQUIRE(K % 16 == 0 && K > 0, "internal: GEMM K = %lld not a multiple of 16", (long long)K);
   SH_REQUIRE(M < (int64_t(1) << 31) / 128, "internal: GEMM M too large");
   // products with at most 32 columns take the 128 x 32 tile, the others 64 x 64
@@ -1040,6 +1060,11 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
   const int64_t kchunk = rup(sh::cdiv(K, S), GBK);
   S = (int)sh::cdiv(K, kchunk);
   const Im2col g0{nullptr, 0, 1, 1, 1};
+  const Tconv tc0{nullptr, 0, 1, 1, 1}, tc = tco ? *tco : tc0;
+  SH_REQUIRE(!tco || (!gat && S == 1 && !C && !Cb && !relu && bias && tco->dst && tco->Co % 8 == 0 &&
+                      tco->ld % 8 == 0 && (reinterpret_cast<uintptr_t>(tco->dst) & 15) == 0 &&
+                      M == (int64_t)u->ap->B * tco->h * tco->w && N == 4 * tco->Co),
+             "internal: transposed-convolution output");
   if (gat && gat->C % 32 == 0 && gat->ldx % 8 == 0 && ldb % 8 == 0 && K == 9 * gat->C &&
       M * gat->ldx < (int64_t(1) << 30) && (int64_t)N * ldb < (int64_t(1) << 30) &&
       (reinterpret_cast<uintptr_t>(gat->x) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0) {
@@ -1058,25 +1083,25 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
                "internal: implicit im2col shape");
     if (narrow)
       hipLaunchKernelGGL((gemm_nt<true, 1>), dim3(gx, gy, 1), dim3(256), 0, st, nullptr, 0, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat);
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat, tc0);
     else
       hipLaunchKernelGGL((gemm_nt<true, 2>), dim3(gx, gy, 1), dim3(256), 0, st, nullptr, 0, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat);
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat, tc0);
   } else if (S == 1) {
     if (narrow)
       hipLaunchKernelGGL((gemm_nt<false, 1>), dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0);
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0, tc);
     else
       hipLaunchKernelGGL((gemm_nt<false, 2>), dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0);
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0, tc);
   } else {
     SH_REQUIRE(C && !Cb && !bias && !relu && ldc == N, "internal: split GEMM writes plain fp32");
     if (narrow)
       hipLaunchKernelGGL((gemm_nt<false, 1>), dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0);
+                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0, tc0);
     else
       hipLaunchKernelGGL((gemm_nt<false, 2>), dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0);
+                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0, tc0);
     hipLaunchKernelGGL(sum_splits, dim3(nb(M * N)), dim3(256), 0, st, u->ap->part.ptr, S, M * N, C);
   }
   SH_LAUNCHED();
@@ -1208,14 +1233,16 @@ sh_status net_forward(sh_unet u, const float* x, int B, int H, int W, hipStream_
     const int h = H >> l, w = W >> l, c = u->base << l;
     const int64_t Pin = (int64_t)B * (h / 2) * (w / 2), P = (int64_t)B * h * w;
     const Layer& tl = u->layers[li++];
-    SH_TRY(gemm(u, cur, ldc, u->ops.ptr + tl.op_f, tl.cin, Pin, 4 * c, tl.cin, nullptr, false, a.f32a.ptr, 4 * c,
-                nullptr, 0, false, st));
     if (c % 8 == 0 && fits8(P * c / 8)) {
-      hipLaunchKernelGGL(tconv_scatter8, dim3(nb(Pin * c / 2)), dim3(256), 0, st, a.f32a.ptr, u->params.ptr + tl.b_off,
-                         B, h / 2, w / 2, c, a.cat[l].ptr, 2 * c);
+      // the upsampled half of the concatenation straight from the product's epilogue
+      const Tconv tcv{a.cat[l].ptr, 2 * c, h / 2, w / 2, c};
+      SH_TRY(gemm(u, cur, ldc, u->ops.ptr + tl.op_f, tl.cin, Pin, 4 * c, tl.cin, u->params.ptr + tl.b_off, false,
+                  nullptr, 0, nullptr, 0, false, st, nullptr, &tcv));
       hipLaunchKernelGGL(copy_channels8, dim3(nb(P * c / 8)), dim3(256), 0, st, a.enc[2 * l + 1].ptr, c, a.cat[l].ptr,
                          2 * c, c, (int)P, c);
     } else {
+      SH_TRY(gemm(u, cur, ldc, u->ops.ptr + tl.op_f, tl.cin, Pin, 4 * c, tl.cin, nullptr, false, a.f32a.ptr, 4 * c,
+                  nullptr, 0, false, st));
       hipLaunchKernelGGL(tconv_scatter, dim3(nb(Pin * 4 * c)), dim3(256), 0, st, a.f32a.ptr, u->params.ptr + tl.b_off,
                          B, h / 2, w / 2, c, a.cat[l].ptr, 2 * c);
       hipLaunchKernelGGL(copy_channels, dim3(nb(P * c)), dim3(256), 0, st, a.enc[2 * l + 1].ptr, c, a.cat[l].ptr,
