@@ -72,8 +72,9 @@ template <bool GATHER, int WN>
 __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, int lda, const uint16_t* __restrict__ B,
                                                int ldb, int M, int N, int K, int kchunk,
                                                const float* __restrict__ bias, int relu, float* __restrict__ C,
-                                               int ldc, uint16_t* __restrict__ Cb, int ldcb, Im2col g, Tconv tc) {
-  // tile TM x TN: 64 x 64 (four waves 2 x 2) or, for products with at most 32 columns, 128 x 32 (4 x 1)
+                                               int ldc, uint16_t* __restrict__ Cb, int ldcb, Im2col g, Tconv tc,
+                                               uint16_t* __restrict__ Cb2, int ldcb2) {
+  // tile TM x TN (Cb2: optional second bf16 output, row stride ldcb2): 64 x 64 (four waves 2 x 2) or, for products with at most 32 columns, 128 x 32 (4 x 1)
   constexpr int TM = 128 / WN, TN = 32 * WN, AR = TM / 64, BU = TN / 32;
   __shared__ __attribute__((aligned(16))) uint16_t As[TM][GLD];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][GLD];
@@ -236,6 +237,7 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
         if (relu) v = fmaxf(v, 0.f);
         if (C) C[(int64_t)m * ldc + n] = v;
         if (Cb) Cb[(int64_t)m * ldcb + n] = f2bf(v);
+        if (Cb2) Cb2[(int64_t)m * ldcb2 + n] = f2bf(v);
       }
     }
 }
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
                                                 const uint16_t* __restrict__ Bw, int ldb, int N, int tiles_x,
                                                 int tiles_img, const float* __restrict__ bias, int relu,
                                                 float* __restrict__ Cout, int ldc, uint16_t* __restrict__ Cb,
-                                                int ldcb) {
+                                                int ldcb, uint16_t* __restrict__ Cb2, int ldcb2) {
   constexpr int TW = 32, TH = 8, BI = 4, BJ = TN / 16;
   constexpr int PW = TW + 2, NPIX = (TH + 2) * PW;
   constexpr int CS = 40;                           // LDS pitch of a pixel or weight row: 32 channels + 8
@@ -329,7 +331,8 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
     __syncthreads();
   }
   // D[i][j] of a 16x16 block: lane holds rows 4*(lane/16) + r, column lane%16
-  if (!Cout && (N % 8) == 0 && (ldcb % 8) == 0 && (reinterpret_cast<uintptr_t>(Cb) & 15) == 0) {
+  if (!Cout && (N % 8) == 0 && (ldcb % 8) == 0 && (reinterpret_cast<uintptr_t>(Cb) & 15) == 0 &&
+      (!Cb2 || ((ldcb2 % 8) == 0 && (reinterpret_cast<uintptr_t>(Cb2) & 15) == 0))) {
     // bf16 output only: the tile goes through LDS (the weight area, free after the last barrier) and leaves in
     // 16-byte stores, each pixel's channels contiguous
     constexpr int OP = TN + 8;   // pitch of a pixel's row (elements)
@@ -355,7 +358,9 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
       const int y = ty0 + q / TW, xx = tx0 + q % TW, n = n0 + 8 * c8;
       if (y >= H || xx >= W || n >= N) continue;
       const int64_t m = (int64_t)(bimg * H + y) * W + xx;
-      *(uint4*)(Cb + m * ldcb + n) = *(const uint4*)&Ws[q * OP + 8 * c8];
+      const uint4 v = *(const uint4*)&Ws[q * OP + 8 * c8];
+      *(uint4*)(Cb + m * ldcb + n) = v;
+      if (Cb2) *(uint4*)(Cb2 + m * ldcb2 + n) = v;
     }
     return;
   }
@@ -375,6 +380,7 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
         if (relu) v = fmaxf(v, 0.f);
         if (Cout) Cout[m * ldc + n] = v;
         if (Cb) Cb[m * ldcb + n] = f2bf(v);
+        if (Cb2) Cb2[m * ldcb2 + n] = f2bf(v);
       }
   }
 }
@@ -624,15 +630,6 @@ __global__ void tconv_gather(const float* __restrict__ g, int ld, int B, int h, 
   gG[t] = f2bf(g[po * ld + co]);
 }
 
-// copy C channels: dst[p*ldd + off + c] = src[p*lds + c]
-__global__ void copy_channels(const uint16_t* __restrict__ src, int lds, uint16_t* __restrict__ dst, int ldd, int off,
-                              int64_t P, int C) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= P * C) return;
-  const int64_t p = t / C;
-  const int c = int(t - p * C);
-  dst[p * ldd + off + c] = src[p * lds + c];
-}
 
 // gm[p][c] = bf16((g[p*ldg + c] (+ g2[p*ldg2 + c])) * (act[p][c] > 0))
 __global__ void relu_mask_grad(const float* __restrict__ g, int ldg, const float* __restrict__ g2, int ldg2,
@@ -737,14 +734,6 @@ __global__ void tconv_gather8(const float* __restrict__ g, int ld, int B, int h,
   *(uint4*)(gG + 8 * (int64_t)t) = u4_pack(r);
 }
 
-__global__ void copy_channels8(const uint16_t* __restrict__ src, int lds, uint16_t* __restrict__ dst, int ldd, int off,
-                               int P, int C) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  const int C8 = C >> 3;
-  if (t >= P * C8) return;
-  const int p = t / C8, c = 8 * (t - p * C8);
-  *(uint4*)(dst + (int64_t)p * ldd + off + c) = *(const uint4*)(src + (int64_t)p * lds + c);
-}
 
 __global__ void relu_mask_grad8(const float* __restrict__ g, int ldg, const float* __restrict__ g2, int ldg2,
                                 const uint16_t* __restrict__ act, int P, int C, uint16_t* __restrict__ gm) {
@@ -799,6 +788,25 @@ __global__ __launch_bounds__(256) void conv3_c1(const uint16_t* __restrict__ x, 
     }
     *(uint4*)(out + (int64_t)p * ldo + n0) = u4_pack(r);
   }
+}
+
+// The head's 1 x 1 convolution to one channel: z[p] = sum_c a[p][c] w[c] + b, fp32 sums of the exact bf16
+// products in channel order; one pixel per thread, C a multiple of 8 and at most 256, rows of stride lda
+__global__ __launch_bounds__(256) void head_fwd(const uint16_t* __restrict__ a, int lda, int64_t P, int C,
+                                                const uint16_t* __restrict__ w, const float* __restrict__ bias,
+                                                float* __restrict__ z) {
+  __shared__ float ws[256];
+  for (int e = threadIdx.x; e < C; e += 256) ws[e] = bf2f(w[e]);
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  float acc = 0.f;
+  for (int c = 0; c < C; c += 8) {
+    const uint4 v = *(const uint4*)(a + p * lda + c);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc = fmaf(bf2f(u4_get(v, e)), ws[c + e], acc);
+  }
+  z[p] = acc + bias[0];
 }
 
 inline bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -1044,7 +1052,8 @@ sh_status ensure_acts(sh_unet u, int B, int H, int W) {
 // weight gradients, reduced in fixed order through `part`.
 sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M, int N, int64_t K,
                const float* bias, bool relu, float* C, int ldc, uint16_t* Cb, int ldcb, bool allow_split,
-               hipStream_t st, const Im2col* gat = nullptr, const Tconv* tco = nullptr) {
+               hipStream_t st, const Im2col* gat = nullptr, const Tconv* tco = nullptr, uint16_t* Cb2 = nullptr,
+               int ldcb2 = 0) {
   SH_REQUIRE(K % 16 == 0 && K > 0, "internal: GEMM K = %lld not a multiple of 16", (long long)K);
   SH_REQUIRE(M < (int64_t(1) << 31) / 128, "internal: GEMM M too large");
   // products with at most 32 columns take the 128 x 32 tile, the others 64 x 64
@@ -1065,6 +1074,7 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
                       tco->ld % 8 == 0 && (reinterpret_cast<uintptr_t>(tco->dst) & 15) == 0 &&
                       M == (int64_t)u->ap->B * tco->h * tco->w && N == 4 * tco->Co),
              "internal: transposed-convolution output");
+  SH_REQUIRE(!Cb2 || (Cb && S == 1), "internal: second output");
   if (gat && gat->C % 32 == 0 && gat->ldx % 8 == 0 && ldb % 8 == 0 && K == 9 * gat->C &&
       M * gat->ldx < (int64_t(1) << 30) && (int64_t)N * ldb < (int64_t(1) << 30) &&
       (reinterpret_cast<uintptr_t>(gat->x) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0) {
@@ -1074,34 +1084,34 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
     const dim3 grid((unsigned)(tiles_img * u->ap->B), (unsigned)sh::cdiv(N, TN));
     if (narrow)
       hipLaunchKernelGGL((conv3_nt<32>), grid, dim3(256), 0, st, gat->x, gat->ldx, gat->H, gat->W, gat->C, B, ldb, N,
-                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb);
+                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, Cb2, ldcb2);
     else
       hipLaunchKernelGGL((conv3_nt<64>), grid, dim3(256), 0, st, gat->x, gat->ldx, gat->H, gat->W, gat->C, B, ldb, N,
-                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb);
+                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, Cb2, ldcb2);
   } else if (gat) {
     SH_REQUIRE(S == 1 && M == (int64_t)u->ap->B * gat->H * gat->W && K == rup(9 * gat->C, 16),
                "internal: implicit im2col shape");
     if (narrow)
       hipLaunchKernelGGL((gemm_nt<true, 1>), dim3(gx, gy, 1), dim3(256), 0, st, nullptr, 0, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat, tc0);
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat, tc0, Cb2, ldcb2);
     else
       hipLaunchKernelGGL((gemm_nt<true, 2>), dim3(gx, gy, 1), dim3(256), 0, st, nullptr, 0, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat, tc0);
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, *gat, tc0, Cb2, ldcb2);
   } else if (S == 1) {
     if (narrow)
       hipLaunchKernelGGL((gemm_nt<false, 1>), dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0, tc);
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0, tc, Cb2, ldcb2);
     else
       hipLaunchKernelGGL((gemm_nt<false, 2>), dim3(gx, gy, 1), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0, tc);
+                         (int)kchunk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, g0, tc, Cb2, ldcb2);
   } else {
     SH_REQUIRE(C && !Cb && !bias && !relu && ldc == N, "internal: split GEMM writes plain fp32");
     if (narrow)
       hipLaunchKernelGGL((gemm_nt<false, 1>), dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0, tc0);
+                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0, tc0, nullptr, 0);
     else
       hipLaunchKernelGGL((gemm_nt<false, 2>), dim3(gx, gy, S), dim3(256), 0, st, A, lda, B, ldb, (int)M, N, (int)K,
-                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0, tc0);
+                         (int)kchunk, nullptr, 0, u->ap->part.ptr, N, nullptr, 0, g0, tc0, nullptr, 0);
     hipLaunchKernelGGL(sum_splits, dim3(nb(M * N)), dim3(256), 0, st, u->ap->part.ptr, S, M * N, C);
   }
   SH_LAUNCHED();
@@ -1160,9 +1170,9 @@ sh_status prep_weights(sh_unet u, hipStream_t st) {
 
 // conv3 forward: out (P x Co, bf16) = relu(im2col(in) . wf^T + b)
 sh_status conv_fwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, int B, int H, int W, uint16_t* out,
-                   hipStream_t st) {
+                   hipStream_t st, uint16_t* out2 = nullptr, int ld2 = 0) {
   const int64_t P = (int64_t)B * H * W;
-  if (ly.cin == 1 && ly.cout % 8 == 0 && ly.cout <= 64 && fits8(P) && al16(out)) {   // the first layer
+  if (ly.cin == 1 && ly.cout % 8 == 0 && ly.cout <= 64 && fits8(P) && al16(out) && !out2) {   // the first layer
     hipLaunchKernelGGL(conv3_c1, dim3(nb(P)), dim3(256), 0, st, in, ldin, B, H, W, u->ops.ptr + ly.op_f, ly.Kp,
                        ly.cout, u->params.ptr + ly.b_off, out, ly.cout);
     SH_LAUNCHED();
@@ -1170,7 +1180,7 @@ sh_status conv_fwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, int
   }
   const Im2col g{in, ldin, H, W, ly.cin};
   return gemm(u, nullptr, 0, u->ops.ptr + ly.op_f, ly.Kp, P, ly.cout, ly.Kp, u->params.ptr + ly.b_off, true, nullptr, 0,
-              out, ly.cout, false, st, &g);
+              out, ly.cout, false, st, &g, nullptr, out2, ld2);
 }
 
 // conv3 backward.  gin (+ gin2, strided) is the fp32 gradient at the layer's post-ReLU output `out`.
@@ -1225,7 +1235,9 @@ sh_status net_forward(sh_unet u, const float* x, int B, int H, int W, hipStream_
       ldc = pc;
     }
     SH_TRY(conv_fwd(u, u->layers[li++], cur, ldc, B, h, w, a.enc[2 * l].ptr, st));
-    SH_TRY(conv_fwd(u, u->layers[li++], a.enc[2 * l].ptr, c, B, h, w, a.enc[2 * l + 1].ptr, st));
+    // below the bottleneck the output is also the skip half of the decoder's concatenation (channels c..2c-1)
+    uint16_t* skip = l < L - 1 ? a.cat[l].ptr + c : nullptr;
+    SH_TRY(conv_fwd(u, u->layers[li++], a.enc[2 * l].ptr, c, B, h, w, a.enc[2 * l + 1].ptr, st, skip, 2 * c));
     cur = a.enc[2 * l + 1].ptr;
     ldc = c;
   }
@@ -1238,15 +1250,11 @@ sh_status net_forward(sh_unet u, const float* x, int B, int H, int W, hipStream_
       const Tconv tcv{a.cat[l].ptr, 2 * c, h / 2, w / 2, c};
       SH_TRY(gemm(u, cur, ldc, u->ops.ptr + tl.op_f, tl.cin, Pin, 4 * c, tl.cin, u->params.ptr + tl.b_off, false,
                   nullptr, 0, nullptr, 0, false, st, nullptr, &tcv));
-      hipLaunchKernelGGL(copy_channels8, dim3(nb(P * c / 8)), dim3(256), 0, st, a.enc[2 * l + 1].ptr, c, a.cat[l].ptr,
-                         2 * c, c, (int)P, c);
     } else {
       SH_TRY(gemm(u, cur, ldc, u->ops.ptr + tl.op_f, tl.cin, Pin, 4 * c, tl.cin, nullptr, false, a.f32a.ptr, 4 * c,
                   nullptr, 0, false, st));
       hipLaunchKernelGGL(tconv_scatter, dim3(nb(Pin * 4 * c)), dim3(256), 0, st, a.f32a.ptr, u->params.ptr + tl.b_off,
                          B, h / 2, w / 2, c, a.cat[l].ptr, 2 * c);
-      hipLaunchKernelGGL(copy_channels, dim3(nb(P * c)), dim3(256), 0, st, a.enc[2 * l + 1].ptr, c, a.cat[l].ptr,
-                         2 * c, c, P, c);
     }
     SH_TRY(conv_fwd(u, u->layers[li++], a.cat[l].ptr, 2 * c, B, h, w, a.dec[2 * l].ptr, st));
     SH_TRY(conv_fwd(u, u->layers[li++], a.dec[2 * l].ptr, c, B, h, w, a.dec[2 * l + 1].ptr, st));
@@ -1254,6 +1262,12 @@ sh_status net_forward(sh_unet u, const float* x, int B, int H, int W, hipStream_
     ldc = c;
   }
   const Layer& hd = u->layers[li];
+  if (hd.cin % 8 == 0 && hd.cin <= 256 && ldc % 8 == 0 && al16(cur)) {
+    hipLaunchKernelGGL(head_fwd, dim3(nb(P1)), dim3(256), 0, st, cur, ldc, P1, hd.cin, u->ops.ptr + hd.op_f,
+                       u->params.ptr + hd.b_off, a.z.ptr);
+    SH_LAUNCHED();
+    return SH_OK;
+  }
   return gemm(u, cur, ldc, u->ops.ptr + hd.op_f, hd.cin, P1, 1, hd.cin, u->params.ptr + hd.b_off, false, a.z.ptr, 1,
               nullptr, 0, false, st);
 }
