@@ -44,6 +44,16 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint3
 inline unsigned nb(int64_t n, int t = 256) { return (unsigned)sh::cdiv(n, t); }
 inline int64_t rup(int64_t v, int64_t m) { return sh::cdiv(v, m) * m; }
 
+// 16-bit lanes of a 16-byte vector
+__device__ __forceinline__ uint16_t u4_get(const uint4& v, int e) {
+  const uint32_t w = e < 2 ? v.x : e < 4 ? v.y : e < 6 ? v.z : v.w;
+  return (uint16_t)(w >> (16 * (e & 1)));
+}
+__device__ __forceinline__ uint4 u4_pack(const uint16_t* h) {
+  return make_uint4(h[0] | (uint32_t(h[1]) << 16), h[2] | (uint32_t(h[3]) << 16), h[4] | (uint32_t(h[5]) << 16),
+                    h[6] | (uint32_t(h[7]) << 16));
+}
+
 // ---------------------------------------------------------------------------------------------
 // GEMM: C[m][n] = sum_{k in split z} A[m*lda + k] B[n*ldb + k] (+ bias[n]) (relu), bf16 operands.
 // K is a multiple of 16.  Outputs: fp32 C (+ z*M*ldc for split partials) and/or bf16 Cb.
@@ -257,7 +267,8 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
                                                 const uint16_t* __restrict__ Bw, int ldb, int N, int tiles_x,
                                                 int tiles_img, const float* __restrict__ bias, int relu,
                                                 float* __restrict__ Cout, int ldc, uint16_t* __restrict__ Cb,
-                                                int ldcb, uint16_t* __restrict__ Cb2, int ldcb2) {
+                                                int ldcb, uint16_t* __restrict__ Cb2, int ldcb2, int staged,
+                                                uint16_t* __restrict__ Pout, uint8_t* __restrict__ Pidx) {
   constexpr int TW = 32, TH = 8, BI = 4, BJ = TN / 16;
   constexpr int PW = TW + 2, NPIX = (TH + 2) * PW;
   constexpr int CS = 40;                           // LDS pitch of a pixel or weight row: 32 channels + 8
@@ -331,10 +342,11 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
     __syncthreads();
   }
   // D[i][j] of a 16x16 block: lane holds rows 4*(lane/16) + r, column lane%16
-  if (!Cout && (N % 8) == 0 && (ldcb % 8) == 0 && (reinterpret_cast<uintptr_t>(Cb) & 15) == 0 &&
-      (!Cb2 || ((ldcb2 % 8) == 0 && (reinterpret_cast<uintptr_t>(Cb2) & 15) == 0))) {
-    // bf16 output only: the tile goes through LDS (the weight area, free after the last barrier) and leaves in
-    // 16-byte stores, each pixel's channels contiguous
+  if (staged) {
+    // bf16 output only (the host checks N, ldcb, ldcb2 multiples of 8 and 16-byte aligned outputs): the tile goes
+    // through LDS (the weight area, free after the last barrier) and leaves in 16-byte stores, each pixel's
+    // channels contiguous; with Pout, also its 2 x 2 max-pool (first maximum's index in Pidx, as pool_fwd), every
+    // window lying inside the tile (H and W even)
     constexpr int OP = TN + 8;   // pitch of a pixel's row (elements)
     static_assert(256 * OP <= 9 * TN * CS, "output tile fits the weight area");
 #pragma unroll
@@ -361,6 +373,42 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
       const uint4 v = *(const uint4*)&Ws[q * OP + 8 * c8];
       *(uint4*)(Cb + m * ldcb + n) = v;
       if (Cb2) *(uint4*)(Cb2 + m * ldcb2 + n) = v;
+    }
+    if (Pout) {
+      const int h2 = H / 2, w2 = W / 2;
+#pragma unroll
+      for (int e = 0; e < (TH / 2) * (TW / 2) * NG / 256; ++e) {
+        const int g = tid + 256 * e, pq = g / NG, c8 = g - pq * NG;
+        const int py = pq / (TW / 2), px = pq - py * (TW / 2);
+        const int oy = ty0 / 2 + py, ox = tx0 / 2 + px, n = n0 + 8 * c8;
+        if (oy >= h2 || ox >= w2 || n >= N) continue;
+        uint4 v[4];
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          v[qq] = *(const uint4*)&Ws[((2 * py + qq / 2) * TW + 2 * px + qq % 2) * OP + 8 * c8];
+        uint16_t bv[8];
+        uint8_t bi[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          float best = -INFINITY;
+          bi[c] = 0;
+          bv[c] = 0;
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const uint16_t hv = u4_get(v[qq], c);
+            const float f = bf2f(hv);
+            if (f > best) {
+              best = f;
+              bi[c] = (uint8_t)qq;
+              bv[c] = hv;
+            }
+          }
+        }
+        const int64_t o = ((int64_t)(bimg * h2 + oy) * w2 + ox) * N + n;
+        *(uint4*)(Pout + o) = u4_pack(bv);
+        *(uint2*)(Pidx + o) = make_uint2(bi[0] | (bi[1] << 8) | (bi[2] << 16) | (uint32_t(bi[3]) << 24),
+                                         bi[4] | (bi[5] << 8) | (bi[6] << 16) | (uint32_t(bi[7]) << 24));
+      }
     }
     return;
   }
@@ -645,14 +693,6 @@ __global__ void relu_mask_grad(const float* __restrict__ g, int ldg, const float
 
 // ---- the layout kernels above, eight channels per thread (channel counts, row strides and channel offsets
 // multiples of 8, 16-byte aligned buffers, fewer than 2^31 groups of eight); each element is computed as above
-__device__ __forceinline__ uint16_t u4_get(const uint4& v, int e) {
-  const uint32_t w = e < 2 ? v.x : e < 4 ? v.y : e < 6 ? v.z : v.w;
-  return (uint16_t)(w >> (16 * (e & 1)));
-}
-__device__ __forceinline__ uint4 u4_pack(const uint16_t* h) {
-  return make_uint4(h[0] | (uint32_t(h[1]) << 16), h[2] | (uint32_t(h[3]) << 16), h[4] | (uint32_t(h[5]) << 16),
-                    h[6] | (uint32_t(h[7]) << 16));
-}
 __device__ __forceinline__ void load8f(const float* p, float* v) {
   const float4 a = *(const float4*)p, b = *(const float4*)(p + 4);
   v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
@@ -1053,7 +1093,8 @@ sh_status ensure_acts(sh_unet u, int B, int H, int W) {
 sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb, int64_t M, int N, int64_t K,
                const float* bias, bool relu, float* C, int ldc, uint16_t* Cb, int ldcb, bool allow_split,
                hipStream_t st, const Im2col* gat = nullptr, const Tconv* tco = nullptr, uint16_t* Cb2 = nullptr,
-               int ldcb2 = 0) {
+               int ldcb2 = 0, uint16_t* pool_out = nullptr, uint8_t* pool_idx = nullptr, bool* pooled = nullptr) {
+  if (pooled) *pooled = false;
   SH_REQUIRE(K % 16 == 0 && K > 0, "internal: GEMM K = %lld not a multiple of 16", (long long)K);
   SH_REQUIRE(M < (int64_t(1) << 31) / 128, "internal: GEMM M too large");
   // products with at most 32 columns take the 128 x 32 tile, the others 64 x 64
@@ -1082,12 +1123,18 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
     SH_REQUIRE(M == (int64_t)u->ap->B * gat->H * gat->W, "internal: convolution shape");
     const int tiles_x = (int)sh::cdiv(gat->W, 32), tiles_img = tiles_x * (int)sh::cdiv(gat->H, 8);
     const dim3 grid((unsigned)(tiles_img * u->ap->B), (unsigned)sh::cdiv(N, TN));
+    const bool staged = !C && Cb && N % 8 == 0 && ldcb % 8 == 0 && al16(Cb) && (!Cb2 || (ldcb2 % 8 == 0 && al16(Cb2)));
+    const bool pool = staged && pool_out && gat->H % 2 == 0 && gat->W % 2 == 0 && al16(pool_out) &&
+                      (reinterpret_cast<uintptr_t>(pool_idx) & 7) == 0;
+    if (pooled) *pooled = pool;
     if (narrow)
       hipLaunchKernelGGL((conv3_nt<32>), grid, dim3(256), 0, st, gat->x, gat->ldx, gat->H, gat->W, gat->C, B, ldb, N,
-                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, Cb2, ldcb2);
+                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, Cb2, ldcb2, staged ? 1 : 0,
+                         pool ? pool_out : nullptr, pool ? pool_idx : nullptr);
     else
       hipLaunchKernelGGL((conv3_nt<64>), grid, dim3(256), 0, st, gat->x, gat->ldx, gat->H, gat->W, gat->C, B, ldb, N,
-                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, Cb2, ldcb2);
+                         tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, Cb2, ldcb2, staged ? 1 : 0,
+                         pool ? pool_out : nullptr, pool ? pool_idx : nullptr);
   } else if (gat) {
     SH_REQUIRE(S == 1 && M == (int64_t)u->ap->B * gat->H * gat->W && K == rup(9 * gat->C, 16),
                "internal: implicit im2col shape");
@@ -1170,7 +1217,9 @@ sh_status prep_weights(sh_unet u, hipStream_t st) {
 
 // conv3 forward: out (P x Co, bf16) = relu(im2col(in) . wf^T + b)
 sh_status conv_fwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, int B, int H, int W, uint16_t* out,
-                   hipStream_t st, uint16_t* out2 = nullptr, int ld2 = 0) {
+                   hipStream_t st, uint16_t* out2 = nullptr, int ld2 = 0, uint16_t* pool_out = nullptr,
+                   uint8_t* pool_idx = nullptr, bool* pooled = nullptr) {
+  if (pooled) *pooled = false;
   const int64_t P = (int64_t)B * H * W;
   if (ly.cin == 1 && ly.cout % 8 == 0 && ly.cout <= 64 && fits8(P) && al16(out) && !out2) {   // the first layer
     hipLaunchKernelGGL(conv3_c1, dim3(nb(P)), dim3(256), 0, st, in, ldin, B, H, W, u->ops.ptr + ly.op_f, ly.Kp,
@@ -1180,7 +1229,7 @@ sh_status conv_fwd(sh_unet u, const Layer& ly, const uint16_t* in, int ldin, int
   }
   const Im2col g{in, ldin, H, W, ly.cin};
   return gemm(u, nullptr, 0, u->ops.ptr + ly.op_f, ly.Kp, P, ly.cout, ly.Kp, u->params.ptr + ly.b_off, true, nullptr, 0,
-              out, ly.cout, false, st, &g, nullptr, out2, ld2);
+              out, ly.cout, false, st, &g, nullptr, out2, ld2, pool_out, pool_idx, pooled);
 }
 
 // conv3 backward.  gin (+ gin2, strided) is the fp32 gradient at the layer's post-ReLU output `out`.
@@ -1221,23 +1270,28 @@ sh_status net_forward(sh_unet u, const float* x, int B, int H, int W, hipStream_
   const uint16_t* cur = a.x0.ptr;
   int ldc = 1;
   int li = 0;
+  bool pooled = false;   // the previous level's convolution also wrote this level's pooled input
   for (int l = 0; l < L; ++l) {
     const int h = H >> l, w = W >> l, c = u->base << l;
     if (l > 0) {
       const int pc = c / 2;
-      if (pc % 8 == 0 && fits8((int64_t)B * h * w * pc / 8))
-        hipLaunchKernelGGL(pool_fwd8, dim3(nb((int64_t)B * h * w * pc / 8)), dim3(256), 0, st, a.enc[2 * l - 1].ptr, B,
-                           2 * h, 2 * w, pc, a.pooled[l].ptr, a.pidx[l].ptr);
-      else
-        hipLaunchKernelGGL(pool_fwd, dim3(nb((int64_t)B * h * w * pc)), dim3(256), 0, st, a.enc[2 * l - 1].ptr, B,
-                           2 * h, 2 * w, pc, a.pooled[l].ptr, a.pidx[l].ptr);
+      if (!pooled) {
+        if (pc % 8 == 0 && fits8((int64_t)B * h * w * pc / 8))
+          hipLaunchKernelGGL(pool_fwd8, dim3(nb((int64_t)B * h * w * pc / 8)), dim3(256), 0, st, a.enc[2 * l - 1].ptr,
+                             B, 2 * h, 2 * w, pc, a.pooled[l].ptr, a.pidx[l].ptr);
+        else
+          hipLaunchKernelGGL(pool_fwd, dim3(nb((int64_t)B * h * w * pc)), dim3(256), 0, st, a.enc[2 * l - 1].ptr, B,
+                             2 * h, 2 * w, pc, a.pooled[l].ptr, a.pidx[l].ptr);
+      }
       cur = a.pooled[l].ptr;
       ldc = pc;
     }
     SH_TRY(conv_fwd(u, u->layers[li++], cur, ldc, B, h, w, a.enc[2 * l].ptr, st));
     // below the bottleneck the output is also the skip half of the decoder's concatenation (channels c..2c-1)
+    // and the next level's pooled input, when the convolution can form it
     uint16_t* skip = l < L - 1 ? a.cat[l].ptr + c : nullptr;
-    SH_TRY(conv_fwd(u, u->layers[li++], a.enc[2 * l].ptr, c, B, h, w, a.enc[2 * l + 1].ptr, st, skip, 2 * c));
+    SH_TRY(conv_fwd(u, u->layers[li++], a.enc[2 * l].ptr, c, B, h, w, a.enc[2 * l + 1].ptr, st, skip, 2 * c,
+                    l < L - 1 ? a.pooled[l + 1].ptr : nullptr, l < L - 1 ? a.pidx[l + 1].ptr : nullptr, &pooled));
     cur = a.enc[2 * l + 1].ptr;
     ldc = c;
   }
