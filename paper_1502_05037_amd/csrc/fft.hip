@@ -64,9 +64,18 @@ __device__ __forceinline__ void dft(float2* v) {
   }
 }
 
+// LDS slot of element i of a sequence: the low four bits of i are XOR-permuted by bits 4-6 of i and by the
+// sequence's tag sx (bits 2-3), a bijection inside every group of 16 elements (L >= 16).  Without it the first
+// radix-8 stage, whose threads write eight consecutive elements each, puts every second thread of a 16-lane
+// group in the same banks, and the column passes, which load and store their B sequences element by element
+// side by side, put the B sequences' elements in the same banks.
+__device__ __forceinline__ int swz(int i, int sx) { return i ^ ((i >> 4) & 7) ^ sx; }
+template <int L>
+__device__ __forceinline__ int slot(int b, int i) { return b * L + swz(i, (b & 3) << 2); }
+
 // One Stockham stage of radix R over a length-L sequence in LDS (all threads of the sequence).
 template <int L, int R, bool INV>
-__device__ __forceinline__ void stage(float2* buf, const float2* __restrict__ tw, int Ns, int lt, int tpt) {
+__device__ __forceinline__ void stage(float2* buf, const float2* __restrict__ tw, int Ns, int lt, int tpt, int sx) {
   constexpr int NB = L / R;                      // butterflies per sequence
   constexpr int PER = (NB + L / 8 - 1) / (L / 8); // butterflies per thread (tpt = L/8)
   float2 v[PER][R], w[PER][R];
@@ -74,7 +83,7 @@ __device__ __forceinline__ void stage(float2* buf, const float2* __restrict__ tw
   for (int q = 0; q < PER; ++q) {
     const int j = lt + q * tpt;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * NB];
+    for (int r = 0; r < R; ++r) v[q][r] = buf[swz(j + r * NB, sx)];
   }
   // the twiddles do not depend on the sequence: their loads are issued before the barrier, so that they are in
   // flight with the LDS reads (the first stage, Ns = 1, has none)
@@ -103,13 +112,13 @@ __device__ __forceinline__ void stage(float2* buf, const float2* __restrict__ tw
     dft<R, INV>(v[q]);
     const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q][r];
+    for (int r = 0; r < R; ++r) buf[swz(base + r * Ns, sx)] = v[q][r];
   }
   __syncthreads();
 }
 
 template <int L, bool INV>
-__device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw, int lt) {
+__device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw, int lt, int sx) {
   constexpr int TPT = L / 8;
   int Ns = 1;
   constexpr int LOG = __builtin_ctz(L);
@@ -117,11 +126,11 @@ __device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ 
   constexpr int REM = LOG % 3;
 #pragma unroll
   for (int s = 0; s < N8; ++s) {
-    stage<L, 8, INV>(buf, tw, Ns, lt, TPT);
+    stage<L, 8, INV>(buf, tw, Ns, lt, TPT, sx);
     Ns *= 8;
   }
-  if constexpr (REM == 2) stage<L, 4, INV>(buf, tw, Ns, lt, TPT);
-  if constexpr (REM == 1) stage<L, 2, INV>(buf, tw, Ns, lt, TPT);
+  if constexpr (REM == 2) stage<L, 4, INV>(buf, tw, Ns, lt, TPT, sx);
+  if constexpr (REM == 1) stage<L, 2, INV>(buf, tw, Ns, lt, TPT, sx);
 }
 
 // B sequences of length L per work-group, L/8 threads each.
@@ -170,7 +179,7 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
       const int b = e / n, c = e - b * n;
       const int r = seq0 + b;
       const float val = x[(size_t)r * n + c] * deapod[r] * deapod[c];
-      lds[b * L + ((c - half) & (L - 1))] = make_float2(val, 0.f);
+      lds[slot<L>(b, (c - half) & (L - 1))] = make_float2(val, 0.f);
     }
   } else if constexpr (MODE == COLS_FWD || MODE == COLS_TOEP) {
     const float2* h = (const float2*)in;
@@ -178,13 +187,13 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
     __syncthreads();
     for (int e = tid; e < B * n; e += NT) {
       const int r = e / B, b = e - r * B;
-      lds[b * L + ((r - half) & (L - 1))] = h[(size_t)r * K + seq0 + b];
+      lds[slot<L>(b, (r - half) & (L - 1))] = h[(size_t)r * K + seq0 + b];
     }
   } else if constexpr (MODE == COLS_ADJ || MODE == FULL_COLS) {
     const float2* g = (const float2*)in;
     for (int e = tid; e < B * L; e += NT) {
       const int r = e / B, b = e - r * B;
-      lds[b * L + r] = g[(size_t)r * K + seq0 + b];
+      lds[slot<L>(b, r)] = g[(size_t)r * K + seq0 + b];
     }
   } else if constexpr (MODE == ROWS_ADJ_H) {
     const float2* h = (const float2*)in;
@@ -192,33 +201,34 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
       const int b = e / L, c = e - b * L;
       const float2* row = h + (size_t)(seq0 + b) * K;
       if (c <= L / 2) {
-        lds[e] = row[c];
+        lds[slot<L>(b, c)] = row[c];
       } else {
         const float2 v = row[L - c];
-        lds[e] = make_float2(v.x, -v.y);
+        lds[slot<L>(b, c)] = make_float2(v.x, -v.y);
       }
     }
   } else {  // ROWS_ADJ, FULL_ROWS
     const float2* h = (const float2*)in;
     for (int e = tid; e < B * L; e += NT) {
       const int b = e / L, c = e - b * L;
-      lds[e] = h[(size_t)(seq0 + b) * K + c];
+      lds[slot<L>(b, c)] = h[(size_t)(seq0 + b) * K + c];
     }
   }
   __syncthreads();
 
   // ---- transform: thread tid works on sequence tid / (L/8) ----
   const int sq = tid / (L / 8), lt = tid % (L / 8);
-  fft_lds<L, INV>(lds + sq * L, tw, lt);
+  fft_lds<L, INV>(lds + sq * L, tw, lt, (sq & 3) << 2);
   if constexpr (MODE == COLS_TOEP) {
     // lds[b L + k] *= Ht[(seq0 + b) K + k]: column seq0 + b of the spectrum, read contiguously
     for (int e = tid; e < B * L; e += NT) {
       const float hv = deapod[(size_t)seq0 * K + e];
-      const float2 v = lds[e];
-      lds[e] = make_float2(v.x * hv, v.y * hv);
+      const int o = slot<L>(e / L, e % L);
+      const float2 v = lds[o];
+      lds[o] = make_float2(v.x * hv, v.y * hv);
     }
     __syncthreads();
-    fft_lds<L, true>(lds + sq * L, tw, lt);
+    fft_lds<L, true>(lds + sq * L, tw, lt, (sq & 3) << 2);
   }
 
   // ---- store ----
@@ -226,32 +236,32 @@ __global__ __launch_bounds__(B * L / 8) void fft_pass(const void* __restrict__ i
     float2* h = (float2*)out;
     for (int e = tid; e < B * L; e += NT) {
       const int b = e / L, k = e - b * L;
-      h[(size_t)(seq0 + b) * K + k] = lds[e];
+      h[(size_t)(seq0 + b) * K + k] = lds[slot<L>(b, k)];
     }
   } else if constexpr (MODE == COLS_FWD || MODE == FULL_COLS) {
     float2* g = (float2*)out;
     for (int e = tid; e < B * L; e += NT) {
       const int k = e / B, b = e - k * B;
-      g[(size_t)k * K + seq0 + b] = lds[b * L + k];
+      g[(size_t)k * K + seq0 + b] = lds[slot<L>(b, k)];
     }
   } else if constexpr (MODE == FULL_ROWS) {
     float2* h = (float2*)out;
     for (int e = tid; e < B * L; e += NT) {
       const int b = e / L, k = e - b * L;
-      h[(size_t)(seq0 + b) * K + k] = lds[e];
+      h[(size_t)(seq0 + b) * K + k] = lds[slot<L>(b, k)];
     }
   } else if constexpr (MODE == COLS_ADJ || MODE == COLS_TOEP) {
     float2* h = (float2*)out;
     for (int e = tid; e < B * n; e += NT) {
       const int r = e / B, b = e - r * B;
-      h[(size_t)r * K + seq0 + b] = lds[b * L + ((r - half) & (L - 1))];
+      h[(size_t)r * K + seq0 + b] = lds[slot<L>(b, (r - half) & (L - 1))];
     }
   } else {  // ROWS_ADJ, ROWS_ADJ_H
     float* x = (float*)out;
     for (int e = tid; e < B * n; e += NT) {
       const int b = e / n, c = e - b * n;
       const int r = seq0 + b;
-      x[(size_t)r * n + c] = lds[b * L + ((c - half) & (L - 1))].x * deapod[r] * deapod[c];
+      x[(size_t)r * n + c] = lds[slot<L>(b, (c - half) & (L - 1))].x * deapod[r] * deapod[c];
     }
   }
 }
