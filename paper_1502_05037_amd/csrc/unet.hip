@@ -437,8 +437,18 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
 __global__ void sum_splits(const float* __restrict__ part, int S, int64_t n, float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
+  // eight partials loaded together, then added one after another: few outputs and many splits leave each
+  // thread a long chain of loads, and the order of the sum stays z = 0, 1, ..., S-1
   float s = 0.f;
-  for (int z = 0; z < S; ++z) s += part[z * n + i];
+  int z = 0;
+  for (; z + 8 <= S; z += 8) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = part[(z + e) * n + i];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s += v[e];
+  }
+  for (; z < S; ++z) s += part[z * n + i];
   out[i] = s;
 }
 
@@ -1336,6 +1346,16 @@ __global__ void copy_f32_channels(const float* __restrict__ src, int lds, int of
   dst[t] = src[p * lds + off + c];
 }
 
+// the same, four channels per thread (C, lds and off multiples of 4, 16-byte aligned buffers)
+__global__ void copy_f32_channels4(const float* __restrict__ src, int lds, int off, float* __restrict__ dst, int P,
+                                   int C) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int C4 = C >> 2;
+  if (t >= P * C4) return;
+  const int p = t / C4, c = 4 * (t - p * C4);
+  *(float4*)(dst + 4 * (int64_t)t) = *(const float4*)(src + (int64_t)p * lds + off + c);
+}
+
 // Backward pass after net_forward (every parameter gradient into u->grads); target fp32 device.
 // The loss lands in a.loss (device) and relu(z) in y_out if given.
 sh_status net_backward(sh_unet u, const float* target, float* y_out, hipStream_t st) {
@@ -1368,7 +1388,12 @@ sh_status net_backward(sh_unet u, const float* target, float* y_out, hipStream_t
     SH_TRY(conv_bwd(u, lb, a.dec[2 * l].ptr, c, a.dec[2 * l + 1].ptr, a.gA.ptr, c, nullptr, 0, B, h, w, a.gB.ptr, st));
     SH_TRY(conv_bwd(u, la, a.cat[l].ptr, 2 * c, a.dec[2 * l].ptr, a.gB.ptr, c, nullptr, 0, B, h, w, a.gC.ptr, st));
     // gC = gradient at [upsampled, skip]; the skip half waits for encoder level l
-    hipLaunchKernelGGL(copy_f32_channels, dim3(nb(P * c)), dim3(256), 0, st, a.gC.ptr, 2 * c, c, a.skipg[l].ptr, P, c);
+    if (c % 4 == 0 && fits8(P * c / 4))
+      hipLaunchKernelGGL(copy_f32_channels4, dim3(nb(P * c / 4)), dim3(256), 0, st, a.gC.ptr, 2 * c, c,
+                         a.skipg[l].ptr, (int)P, c);
+    else
+      hipLaunchKernelGGL(copy_f32_channels, dim3(nb(P * c)), dim3(256), 0, st, a.gC.ptr, 2 * c, c, a.skipg[l].ptr, P,
+                         c);
     // transposed convolution from the upsampled half
     const int cin = tl.cin;
     const uint16_t* tin = l + 1 < L - 1 ? a.dec[2 * (l + 1) + 1].ptr : a.enc[2 * (l + 1) + 1].ptr;
