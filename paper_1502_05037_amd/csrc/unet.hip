@@ -412,6 +412,37 @@ __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, 
     }
     return;
   }
+  if (Cout && !Cb && !Cb2 && (N % 16) == 0 && (ldc % 4) == 0 && (reinterpret_cast<uintptr_t>(Cout) & 15) == 0) {
+    // fp32 output only (the backward-data products): sixteen channels at a time through LDS (the weight area),
+    // each pixel's sixteen values leaving in four 16-byte stores
+    constexpr int OQ = 20;   // pitch of a pixel's row of sixteen floats
+    static_assert(256 * OQ * 4 <= 9 * TN * CS * 2, "fp32 slice fits the weight area");
+    float* Of = reinterpret_cast<float*>(Ws);
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) {
+      if (j > 0) __syncthreads();   // the previous slice has left
+      const int n = n0 + j * 16 + (lane & 15);
+      const float bv = (bias && n < N) ? bias[n] : 0.f;
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float v = acc[i][j][r] + bv;
+          if (relu) v = fmaxf(v, 0.f);
+          Of[(64 * wave + 16 * i + 4 * (lane >> 4) + r) * OQ + (lane & 15)] = v;
+        }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int g = tid + 256 * e, q = g >> 2, c4 = g & 3;
+        const int y = ty0 + q / TW, xx = tx0 + q % TW, nn = n0 + j * 16 + 4 * c4;
+        if (y >= H || xx >= W || nn >= N) continue;
+        const int64_t m = (int64_t)(bimg * H + y) * W + xx;
+        *(float4*)(Cout + m * ldc + nn) = *(const float4*)&Of[q * OQ + 4 * c4];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < BJ; ++j) {
     const int n = n0 + j * 16 + (lane & 15);
