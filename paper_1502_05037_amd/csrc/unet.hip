@@ -507,6 +507,105 @@ __device__ __forceinline__ uint4 im2col8(const Im2col& g, int b, int y, int x, i
                     v[6] | (uint32_t(v[7]) << 16));
 }
 
+// Direct weight gradient of a 3x3 convolution whose input has a multiple of 32 channels C and whose output has a
+// multiple of 32 channels M: part[z][m][tap*C + c] = sum_p g[p][m] x[p + tap offset][c] (x zero outside the
+// image) and part[z][m][9C] = sum_p g[p][m] (the bias gradient), over the pixels of split z, in the layout of
+// gemm_tn's partials (rows of N = 9C + 1).  A work-group owns 32 output channels (m0), 32 input channels (c0) and
+// all nine taps over the 8 x 32 pixel tiles [t0, t1) of the batch; its four waves take (16-row block, 16-channel
+// half) and the nine taps.  Per tile the gradient tile is transposed into LDS (pixels contiguous: the product
+// contracts over pixels), and for each column shift kx the input patch, shifted by kx, likewise, so that every
+// 16-byte operand read stays aligned; the three row shifts ky are then rows of the same patch.
+__global__ __launch_bounds__(256) void wgrad3(const uint16_t* __restrict__ g, int ldg, const uint16_t* __restrict__ x,
+                                              int ldx, int H, int W, int C, int M, int tiles_x, int tiles_img,
+                                              int ntiles, int tiles_per_split, float* __restrict__ part) {
+  constexpr int TW = 32, TH = 8, GP = 40;   // tile, pitch of a transposed row (32 pixels + 8)
+  __shared__ __attribute__((aligned(16))) uint16_t Gt[32 * TH * GP];         // [m][ty][tx]
+  __shared__ __attribute__((aligned(16))) uint16_t Xt[32 * (TH + 2) * GP];   // [c][py][tx]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rb = wave & 1, ch = wave >> 1;
+  const int c0 = blockIdx.x * 32, m0 = blockIdx.y * 32, z = blockIdx.z;
+  const int N = 9 * C + 1;
+  const int tb = z * tiles_per_split, te = min(ntiles, tb + tiles_per_split);
+  f32x4 acc[9], accb = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+  const bool bias = c0 == 0 && ch == 0;
+  const int am = (rb * 16 + (lane & 15)) * TH * GP + 8 * (lane >> 4);   // + ty * GP
+  const int bc = (ch * 16 + (lane & 15)) * (TH + 2) * GP + 8 * (lane >> 4);   // + py * GP
+  for (int t = tb; t < te; ++t) {
+    const int bimg = t / tiles_img, tl = t - bimg * tiles_img;
+    const int ty0 = (tl / tiles_x) * TH, tx0 = (tl % tiles_x) * TW;
+    bf16x8 a[TH];
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) {
+      __syncthreads();   // the previous round's operands have been read
+      // pieces of two horizontally adjacent pixels and eight channels, written as one 32-bit word per channel;
+      // consecutive lanes take consecutive pixel pairs, so a wave's words are contiguous in each row
+      if (kx == 0) {
+        // gradient tile: 128 pixel pairs x 4 groups of eight channels
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int q = tid + 256 * e, pr = q & 127, part8 = q >> 7;
+          const int ty = pr / (TW / 2), tx = 2 * (pr % (TW / 2)), y = ty0 + ty, xx = tx0 + tx;
+          uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+          const uint16_t* src = g + ((int64_t)(bimg * H + y) * W + xx) * ldg + m0 + 8 * part8;
+          if (y < H && xx < W) v0 = *(const uint4*)src;
+          if (y < H && xx + 1 < W) v1 = *(const uint4*)(src + ldg);
+#pragma unroll
+          for (int e2 = 0; e2 < 8; ++e2)
+            *(uint32_t*)&Gt[((8 * part8 + e2) * TH + ty) * GP + tx] = u4_get(v0, e2) | (uint32_t(u4_get(v1, e2)) << 16);
+        }
+      }
+      // input patch shifted by kx: rows ty0 - 1 .. ty0 + 8, columns tx0 - 1 + kx .. + 31 (160 pairs x 4 groups)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const int q = tid + 256 * e;
+        if (q >= 640) break;
+        const int pr = q % 160, part8 = q / 160;
+        const int py = pr / (TW / 2), tx = 2 * (pr % (TW / 2)), y = ty0 - 1 + py, xx = tx0 - 1 + kx + tx;
+        uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+        const uint16_t* src = x + ((int64_t)(bimg * H + y) * W + xx) * ldx + c0 + 8 * part8;
+        if (y >= 0 && y < H && xx >= 0 && xx < W) v0 = *(const uint4*)src;
+        if (y >= 0 && y < H && xx + 1 >= 0 && xx + 1 < W) v1 = *(const uint4*)(src + ldx);
+#pragma unroll
+        for (int e2 = 0; e2 < 8; ++e2)
+          *(uint32_t*)&Xt[((8 * part8 + e2) * (TH + 2) + py) * GP + tx] = u4_get(v0, e2) | (uint32_t(u4_get(v1, e2)) << 16);
+      }
+      __syncthreads();
+      if (kx == 0) {
+#pragma unroll
+        for (int ty = 0; ty < TH; ++ty) a[ty] = *(const bf16x8*)&Gt[am + ty * GP];
+        if (bias)
+#pragma unroll
+          for (int ty = 0; ty < TH; ++ty) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ty], ones, accb, 0, 0, 0);
+      }
+      bf16x8 b[TH + 2];
+#pragma unroll
+      for (int py = 0; py < TH + 2; ++py) b[py] = *(const bf16x8*)&Xt[bc + py * GP];
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+        for (int ty = 0; ty < TH; ++ty)
+          acc[ky * 3 + kx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ty], b[ty + ky], acc[ky * 3 + kx], 0, 0, 0);
+    }
+  }
+  // D of a 16x16 block: lane holds rows 4*(lane/16) + r, column lane%16
+  float* dst = part + (int64_t)z * M * N;
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + rb * 16 + 4 * (lane >> 4) + r, c = c0 + ch * 16 + (lane & 15);
+      dst[(int64_t)m * N + tap * C + c] = acc[tap][r];
+    }
+  if (bias && (lane & 15) == 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[(int64_t)(m0 + rb * 16 + 4 * (lane >> 4) + r) * N + 9 * C] = accb[r];
+}
+
 // Weight-gradient products, which contract over pixels: C[m][n] = sum_{p in split z} A[p][m] Bv[p][n], p < P,
 // with both operands read in their stored pixel-major layout and transposed on the way into LDS (the
 // MFMA part is that of gemm_nt).  A: P x M, row stride lda.  Bv[p][n] = B[p][n] (row stride ldb) for
@@ -1218,6 +1317,24 @@ sh_status gemm_wgrad(sh_unet u, const uint16_t* A, int lda, int M, const uint16_
   while (S > 1 && (int64_t)S * M * N > u->ap->part.count) --S;
   const int64_t kchunk = rup(sh::cdiv(P, S), GBK);
   S = (int)sh::cdiv(P, kchunk);
+  if (gat && ones && gat->C % 32 == 0 && M % 32 == 0 && NB == 9 * gat->C && lda % 8 == 0 && gat->ldx % 8 == 0 &&
+      al16(A) && al16(gat->x) && P == (int64_t)u->ap->B * gat->H * gat->W) {
+    // direct form: pixel tiles of 8 x 32 split over the work-groups, partials in the same layout
+    const int tiles_x = (int)sh::cdiv(gat->W, 32), tiles_img = tiles_x * (int)sh::cdiv(gat->H, 8);
+    const int ntiles = tiles_img * u->ap->B;
+    const int blocks = (gat->C / 32) * (M / 32);
+    int Sd = (int)std::max<int64_t>(1, std::min<int64_t>(256 / blocks, ntiles));
+    while (Sd > 1 && (int64_t)Sd * M * N > u->ap->part.count) --Sd;
+    const int per = (int)sh::cdiv(ntiles, Sd);
+    Sd = (int)sh::cdiv(ntiles, per);
+    float* dstd = Sd == 1 ? C : u->ap->part.ptr;
+    hipLaunchKernelGGL(wgrad3, dim3(gat->C / 32, M / 32, Sd), dim3(256), 0, st, A, lda, gat->x, gat->ldx, gat->H,
+                       gat->W, gat->C, M, tiles_x, tiles_img, ntiles, per, dstd);
+    if (Sd > 1) hipLaunchKernelGGL(sum_splits, dim3(nb((int64_t)M * N)), dim3(256), 0, st, u->ap->part.ptr, Sd,
+                                   (int64_t)M * N, C);
+    SH_LAUNCHED();
+    return SH_OK;
+  }
   const Im2col g = gat ? *gat : Im2col{nullptr, 0, 1, 1, 1};
   float* dst = S == 1 ? C : u->ap->part.ptr;
   if (gat)
