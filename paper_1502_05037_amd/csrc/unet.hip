@@ -10,18 +10,23 @@
 // Number formats: fp32 master weights, gradients and Adam moments; bfloat16 weights, activations
 // and incoming layer gradients as the operands of every matrix product; fp32 accumulation.
 //
-// Every convolution is a matrix product on the MFMA units: activations are NHWC (channels
-// contiguous), a 3x3 convolution is im2col (K = 9 Cin, ordered (ky, kx, ci), zero-padded to a
-// multiple of 16; gathered inside the product's staging, never stored) times the weight matrix, and the
-// forward and input-gradient products use one kernel of the "NT" form
-// C[m][n] = sum_k A[m][k] B[n][k] with both operands contiguous along k (v_mfma_f32_16x16x32_bf16,
-// 64 x 64 tiles per work-group of four waves, or 128 x 32 for products with at most 32 columns so that
-// no half of the tile is padding, k staged through LDS 64 at a time with the next slab prefetched into
-// registers, optional split-K
-// with a fixed-order reduction).  Weight gradients contract over pixels: their kernel ("TN") reads both
-// operands pixel-major as stored (the im2col again gathered) and transposes them on the way into LDS;
-// a column of ones on the second operand yields the bias gradient in the same product.  Results are
-// deterministic.
+// Every convolution is a matrix product on the MFMA units (v_mfma_f32_16x16x32_bf16), activations NHWC
+// (channels contiguous), a 3x3 convolution the product of im2col (K = 9 Cin, ordered (ky, kx, ci)) with the
+// weight matrix.  Three forms:
+//  * conv3_nt, the direct convolution, for inputs with a multiple of 32 channels (forward and input
+//    gradients): per 32-channel chunk the input patch of an 8 x 32 pixel tile and the nine taps' weights are
+//    staged in LDS once and each tap reads the patch at a constant offset; bf16 results leave through LDS in
+//    16-byte stores, optionally also into a second buffer (the decoder's concatenation) and as the 2 x 2
+//    max-pool of the tile.
+//  * wgrad3, the direct weight gradient for the same layers: the gradient tile and the column-shifted input
+//    patches are transposed into LDS so that the product contracts over pixels.
+//  * gemm_nt / gemm_tn, products with im2col gathered inside the staging (the other layers, the transposed
+//    convolutions, whose epilogue can write the upsampled pixels straight into the concatenation, and their
+//    weight gradients): "NT" C[m][n] = sum_k A[m][k] B[n][k] with both operands contiguous along k (64 x 64
+//    tiles, or 128 x 32 for at most 32 columns, k staged 64 at a time, optional split-K), "TN" contracting over
+//    pixels with both operands transposed on the way into LDS and a column of ones for the bias gradient.
+// The first layer (one input channel) and the 1 x 1 head are direct vector kernels.  Split-K partials are
+// summed in a fixed order; results are deterministic.
 #include <cmath>
 #include <cstring>
 #include <memory>
