@@ -1267,12 +1267,15 @@ sh_status gemm(sh_unet u, const uint16_t* A, int lda, const uint16_t* B, int ldb
     // direct convolution: pixel tiles of one image, output-channel tiles
     SH_REQUIRE(M == (int64_t)u->ap->B * gat->H * gat->W, "internal: convolution shape");
     const int tiles_x = (int)sh::cdiv(gat->W, 32), tiles_img = tiles_x * (int)sh::cdiv(gat->H, 8);
-    const dim3 grid((unsigned)(tiles_img * u->ap->B), (unsigned)sh::cdiv(N, TN));
+    // 32-channel tiles also where 64-channel tiles would leave fewer than two work-groups per CU (the deep
+    // levels' small images): twice the work-groups, and the 32-channel tile's smaller LDS fits three per CU
+    const bool n32 = narrow || (int64_t)tiles_img * u->ap->B * sh::cdiv(N, 64) < 512;
+    const dim3 grid((unsigned)(tiles_img * u->ap->B), (unsigned)sh::cdiv(N, n32 ? 32 : 64));
     const bool staged = !C && Cb && N % 8 == 0 && ldcb % 8 == 0 && al16(Cb) && (!Cb2 || (ldcb2 % 8 == 0 && al16(Cb2)));
     const bool pool = staged && pool_out && gat->H % 2 == 0 && gat->W % 2 == 0 && al16(pool_out) &&
                       (reinterpret_cast<uintptr_t>(pool_idx) & 7) == 0;
     if (pooled) *pooled = pool;
-    if (narrow)
+    if (n32)
       hipLaunchKernelGGL((conv3_nt<32>), grid, dim3(256), 0, st, gat->x, gat->ldx, gat->H, gat->W, gat->C, B, ldb, N,
                          tiles_x, tiles_img, bias, relu ? 1 : 0, C, ldc, Cb, ldcb, Cb2, ldcb2, staged ? 1 : 0,
                          pool ? pool_out : nullptr, pool ? pool_idx : nullptr);
