@@ -111,9 +111,10 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
     kb_weights<J>(kc, s1, w1);
     kb_weights<J>(kc, s2, w2);
     float ar = 0.f, ai = 0.f;
-    // two rows at a time: a fully unrolled window keeps all J^2 loads live (155 VGPRs, three waves per SIMD
-    // at J = 8); two rows leave 47 VGPRs and eight waves
-#pragma unroll 2
+    // the window fully unrolled (the row weights w1[t1] stay in registers with static indices; a loop over
+    // the rows would select them with compare-and-select chains), two rows per scheduling region: left free,
+    // the scheduler hoists all J^2 loads (155 VGPRs, three waves per SIMD at J = 8)
+#pragma unroll
     for (int t1 = 0; t1 < J; ++t1) {
       const float2* row = patch + (lr + t1) * P + lc;
       float rr = 0.f, ri = 0.f;
@@ -125,6 +126,7 @@ __global__ __launch_bounds__(256) void degrid_kernel(const uint2* __restrict__ c
       }
       ar = fmaf(w1[t1], rr, ar);
       ai = fmaf(w1[t1], ri, ai);
+      if (t1 & 1) __asm__ volatile("" : "+v"(ar), "+v"(ai) :: "memory");   // these rows done before the next loads
     }
     out[oidx ? oidx[j] : j] = make_float2(ar * scale, ai * scale);
   }
