@@ -948,8 +948,10 @@ __global__ void relu_mask_grad8(const float* __restrict__ g, int ldg, const floa
 __global__ __launch_bounds__(256) void conv3_c1(const uint16_t* __restrict__ x, int ldx, int B, int H, int W,
                                                 const uint16_t* __restrict__ wf, int Kp, int N,
                                                 const float* __restrict__ bias, uint16_t* __restrict__ out, int ldo) {
-  __shared__ float ws[64 * 9], bs[64];
-  for (int e = threadIdx.x; e < N * 9; e += 256) ws[e] = bf2f(wf[(e / 9) * Kp + e % 9]);
+  // rows of 12 (16-byte aligned: a channel's nine weights in three 16-byte reads, the last three zero)
+  __shared__ __attribute__((aligned(16))) float ws[64 * 12];
+  __shared__ float bs[64];
+  for (int e = threadIdx.x; e < N * 12; e += 256) ws[e] = e % 12 < 9 ? bf2f(wf[(e / 12) * Kp + e % 12]) : 0.f;
   for (int e = threadIdx.x; e < N; e += 256) bs[e] = bias[e];
   __syncthreads();
   const int p = blockIdx.x * 256 + threadIdx.x;
@@ -965,7 +967,7 @@ __global__ __launch_bounds__(256) void conv3_c1(const uint16_t* __restrict__ x, 
     uint16_t r[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const float* wr = ws + (n0 + e) * 9;
+      const float* wr = ws + (n0 + e) * 12;
       float acc = 0.f;
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) acc = fmaf(xv[tap], wr[tap], acc);
