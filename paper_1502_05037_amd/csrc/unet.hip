@@ -266,7 +266,10 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t* __restrict__ A, i
 // taps' weight rows are staged in LDS once, and every tap's A operand is the patch read at a constant offset,
 // so no gather arithmetic is repeated per tap and the weights are read once per 256 pixels.  The next chunk is
 // loaded into registers while the current one is multiplied.  The MFMA operand and result layouts are those
-// of gemm_nt.
+// of gemm_nt.  Outputs: fp32 Cout (row stride ldc) and/or bf16 Cb (ldcb), optionally a second bf16 copy Cb2
+// (ldcb2, e.g. the skip half of a concatenation); with `staged` (bf16 only, host-checked alignment) the tile
+// leaves through LDS in 16-byte stores, and with Pout also as its 2 x 2 max-pool (Pidx: first-maximum index per
+// window and channel, as pool_fwd).
 template <int TN>
 __global__ __launch_bounds__(256) void conv3_nt(const uint16_t* __restrict__ x, int ldx, int H, int W, int Cin,
                                                 const uint16_t* __restrict__ Bw, int ldb, int N, int tiles_x,
